@@ -1,0 +1,368 @@
+/*
+ * kpz_oracle.c -- TEST INFRASTRUCTURE, NOT PRODUCT CODE.
+ *
+ * Plain, slow, obviously-correct CPU oracle for the 2+1-d KPZ octahedron
+ * model (Kelling, Odor, Nagy, Schulz, Heinig, "Comparison of different
+ * parallel implementations of the 2+1-dimensional KPZ model and the
+ * 3-dimensional KMC model", Sec. 2.1 and Sec. 3.1).  Only the tests, the
+ * smoke check and the CPU-baseline leg of the benchmark may load this
+ * library; the GPU path shares no code with it.
+ *
+ * State: two int8 arrays sx[y*L+x], sy[y*L+x] in {-1,+1} holding the
+ * forward slopes sigma_x(x,y) = h(x+1,y)-h(x,y) and sigma_y(x,y) =
+ * h(x,y+1)-h(x,y) on the periodic L x L lattice (Sec. 2.1, the slope
+ * description of the octahedron surface), plus the anchor height h(0,0).
+ *
+ * Update rule (Sec. 2.1, eq. "rule"): a site whose four nearest neighbours
+ * are all one unit higher (a local minimum) is raised by two with
+ * probability p; a site whose four neighbours are all one unit lower (a
+ * local maximum) is lowered by two with probability q.  In slope terms
+ * both moves negate sigma_x(x,y), sigma_x(x-1,y), sigma_y(x,y) and
+ * sigma_y(x,y-1).
+ *
+ * Dynamics provided:
+ *   or_rs_heights_run  random-sequential updates on an int64 height field
+ *   or_rs_slopes_run   the same draws applied to the slope arrays
+ *   or_dd_run          the two-layer decomposition of Sec. 3 / 3.1:
+ *                      dead-border blocks with a random origin every MCS
+ *                      (device layer), single-hit double tiling inside each
+ *                      block (work-group layer)
+ *   or_rs1d_run        the 1+1-d rooftop (ASEP) reduction (Sec. 2.1)
+ * One Monte Carlo step (MCS) is N = L*L update attempts (Sec. 2.2).
+ *
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
+ * random numbers: as easy as 1, 2, 3", SC'11), written out here from its
+ * published definition.  The paper used LCGs / Mersenne Twister and found
+ * the choice immaterial (Sec. 3.1); the counter layout below is this
+ * project's own reading of the unspecified stream structure.
+ *   ctr = (idx_lo, idx_hi, t, tag<<24 | sub),  key = (seed_lo, seed_hi)
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_TAG_ORIGIN 1u
+#define OR_TAG_SET    2u
+#define OR_TAG_SITE   3u
+#define OR_TAG_ACC1   4u
+#define OR_TAG_ACC2   5u
+#define OR_TAG_RS     6u
+#define OR_TAG_RS1D   7u
+
+#define OR_OK       0
+#define OR_EINVAL  -1
+#define OR_ENOMEM  -2
+#define OR_ECHECK  -3
+
+/* ---------------------------------------------------------------- Philox */
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;   /* key schedule: golden-ratio Weyl increments */
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+void or_draw(uint64_t seed, uint32_t tag, uint32_t t, uint64_t idx, uint32_t sub, uint32_t w[4])
+{
+    uint32_t ctr[4] = { (uint32_t)idx, (uint32_t)(idx >> 32), t, (tag << 24) | (sub & 0xFFFFFFu) };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    or_philox4x32_10(ctr, key, w);
+}
+
+/* Acceptance threshold: an attempt with 32-bit uniform u is accepted iff
+ * u < floor(prob * 2^32); prob = 1 gives 2^32 (always), prob = 0 gives 0. */
+static uint64_t threshold(double prob)
+{
+    if (prob >= 1.0) return (uint64_t)1 << 32;
+    if (prob <= 0.0) return 0;
+    return (uint64_t)(prob * 4294967296.0);
+}
+
+/* ------------------------------------------------------------ the rule */
+
+enum { SITE_NONE = 0, SITE_MIN = 1, SITE_MAX = 2 };
+
+static int classify(int L, const int8_t *sx, const int8_t *sy, int x, int y)
+{
+    int xm = (x + L - 1) % L, ym = (y + L - 1) % L;
+    int a = sx[y * L + x];    /* h(x+1,y) - h(x,y)  */
+    int b = sy[y * L + x];    /* h(x,y+1) - h(x,y)  */
+    int c = sx[y * L + xm];   /* h(x,y) - h(x-1,y)  */
+    int d = sy[ym * L + x];   /* h(x,y) - h(x,y-1)  */
+    if (a == 1 && b == 1 && c == -1 && d == -1) return SITE_MIN;
+    if (a == -1 && b == -1 && c == 1 && d == 1) return SITE_MAX;
+    return SITE_NONE;
+}
+
+static void flip(int L, int8_t *sx, int8_t *sy, int x, int y)
+{
+    int xm = (x + L - 1) % L, ym = (y + L - 1) % L;
+    sx[y * L + x] = (int8_t)-sx[y * L + x];
+    sy[y * L + x] = (int8_t)-sy[y * L + x];
+    sx[y * L + xm] = (int8_t)-sx[y * L + xm];
+    sy[ym * L + x] = (int8_t)-sy[ym * L + x];
+}
+
+/* ------------------------------------------------- flat initial state */
+
+/* Flat start (Sec. 2.1): heights h(x,y) = (x+y) mod 2, h(0,0) = 0. */
+int or_flat(int L, int8_t *sx, int8_t *sy)
+{
+    if (L <= 0 || (L & 1)) return OR_EINVAL;
+    for (int y = 0; y < L; ++y)
+        for (int x = 0; x < L; ++x) {
+            int h = (x + y) & 1;
+            int hx = ((x + 1) % L + y) & 1;   /* L even: parity is periodic */
+            int hy = (x + (y + 1) % L) & 1;
+            sx[y * L + x] = (int8_t)(hx - h);
+            sy[y * L + x] = (int8_t)(hy - h);
+        }
+    return OR_OK;
+}
+
+/* ------------------------------------------- random-sequential dynamics */
+
+/* One attempt of MCS t with index a in [0, N): site = floor(w0 * N / 2^32),
+ * uniform u = w1. */
+int or_rs_heights_run(int L, double p, double q, uint64_t seed, uint32_t t0, int n_mcs,
+                      int64_t *h)
+{
+    if (L <= 0 || (L & 1) || n_mcs < 0) return OR_EINVAL;
+    const uint64_t N = (uint64_t)L * (uint64_t)L;
+    const uint64_t P = threshold(p), Q = threshold(q);
+    uint32_t w[4];
+    for (int m = 0; m < n_mcs; ++m) {
+        uint32_t t = t0 + (uint32_t)m;
+        for (uint64_t a = 0; a < N; ++a) {
+            or_draw(seed, OR_TAG_RS, t, a, 0, w);
+            uint64_t site = ((uint64_t)w[0] * N) >> 32;
+            int x = (int)(site % (uint64_t)L), y = (int)(site / (uint64_t)L);
+            int64_t hh = h[site];
+            int64_t hl = h[(uint64_t)y * L + (x + L - 1) % L];
+            int64_t hr = h[(uint64_t)y * L + (x + 1) % L];
+            int64_t hd = h[(uint64_t)((y + L - 1) % L) * L + x];
+            int64_t hu = h[(uint64_t)((y + 1) % L) * L + x];
+            if (hl == hh + 1 && hr == hh + 1 && hd == hh + 1 && hu == hh + 1) {
+                if ((uint64_t)w[1] < P) h[site] = hh + 2;
+            } else if (hl == hh - 1 && hr == hh - 1 && hd == hh - 1 && hu == hh - 1) {
+                if ((uint64_t)w[1] < Q) h[site] = hh - 2;
+            }
+        }
+    }
+    return OR_OK;
+}
+
+int or_rs_slopes_run(int L, double p, double q, uint64_t seed, uint32_t t0, int n_mcs,
+                     int8_t *sx, int8_t *sy, int64_t *h00, int64_t *net)
+{
+    if (L <= 0 || (L & 1) || n_mcs < 0) return OR_EINVAL;
+    const uint64_t N = (uint64_t)L * (uint64_t)L;
+    const uint64_t P = threshold(p), Q = threshold(q);
+    uint32_t w[4];
+    for (int m = 0; m < n_mcs; ++m) {
+        uint32_t t = t0 + (uint32_t)m;
+        for (uint64_t a = 0; a < N; ++a) {
+            or_draw(seed, OR_TAG_RS, t, a, 0, w);
+            uint64_t site = ((uint64_t)w[0] * N) >> 32;
+            int x = (int)(site % (uint64_t)L), y = (int)(site / (uint64_t)L);
+            int kind = classify(L, sx, sy, x, y);
+            int dh = 0;
+            if (kind == SITE_MIN && (uint64_t)w[1] < P) dh = 2;
+            if (kind == SITE_MAX && (uint64_t)w[1] < Q) dh = -2;
+            if (dh) {
+                flip(L, sx, sy, x, y);
+                *net += dh / 2;
+                if (x == 0 && y == 0) *h00 += dh;
+            }
+        }
+    }
+    return OR_OK;
+}
+
+/* ---------------------------------------- decomposed (DB + DT) dynamics */
+
+/*
+ * One MCS t of the two-layer schedule (Sec. 3 and 3.1):
+ *
+ * Device layer, dead border.  Origin (ox, oy) = (floor(w0*Bx/2^32),
+ * floor(w1*By/2^32)) from draw (ORIGIN, t, 0, 0); it moves every MCS.
+ * Block (bx, by), b = by*nbx + bx, covers global sites
+ * ((ox + bx*Bx + lx) mod L, (oy + by*By + ly) mod L), 0 <= lx < Bx,
+ * 0 <= ly < By.  Sites with lx = 0 (when nbx > 1) or ly = 0 (when
+ * nby > 1) are the dead border: they are never updated, but an attempt
+ * that lands there still counts.  With width one on the low side, every
+ * update of a block reads and writes only slopes stored at its own sites.
+ *
+ * Work-group layer, single-hit double tiling.  Tiles Tx x Ty, each bisected
+ * in both directions into four cells of cx x cy = Tx/2 x Ty/2 sites; cell
+ * set s = sx + 2 sy.  A block makes S = Tx*Ty single-hit steps per MCS, so
+ * every site of the block had on average one chance.  In step k the block
+ * draws one set s_k (uniform, with replacement) = bits 2k..2k+1 of w0 of
+ * draw (SET, t, b, 0); every tile then makes one attempt at a site of its
+ * set-s_k cell.  Cells of one set are at least cx+1 (cy+1) sites apart, so
+ * the attempts of a step never touch each other.
+ *
+ * Site inside a 2x2 cell: r in [0,4), rx = r & 1, ry = r >> 1.  Tiles are
+ * numbered in groups of four: with H = nty/4 (or 1 if nty < 4), tile
+ * (tx, ty) of block b is member j = ty / H of group
+ * G = b*(ntx*H) + (ty mod H)*ntx + tx.  Step k of member j takes
+ * r = bits 8j + 2(k mod 4) .. +1 of word k/4 of draw (SITE, t, G, 0).
+ * 1x1 cells (2x2 tiles) draw no site bits.
+ *
+ * Acceptance uniform of member j of group G at step k:
+ * u = A << 24 | (B & 0xFFFFFF), A = byte j of word (k mod 4) of
+ * draw (ACC1, t, G, k/4), B = word j of draw (ACC2, t, G, k).
+ */
+static int dd_validate(int L, int Bx, int By, int Tx, int Ty)
+{
+    if (L <= 0 || (L & 1)) return 0;
+    if (Bx <= 0 || By <= 0 || L % Bx || L % By) return 0;
+    if (!((Tx == 4 && Ty == 4) || (Tx == 2 && Ty == 2))) return 0;
+    if (Bx % Tx || By % Ty) return 0;
+    int nty = By / Ty;
+    if (nty >= 4 && nty % 4) return 0;
+    return 1;
+}
+
+int or_dd_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, int Ty,
+              uint32_t t0, int n_mcs, int8_t *sx, int8_t *sy, int64_t *h00, int64_t *net,
+              int check)
+{
+    if (!dd_validate(L, Bx, By, Tx, Ty) || n_mcs < 0) return OR_EINVAL;
+    const int nbx = L / Bx, nby = L / By;
+    const int ntx = Bx / Tx, nty = By / Ty;
+    const int H = nty >= 4 ? nty / 4 : 1;
+    const uint64_t nq = (uint64_t)ntx * (uint64_t)H;
+    const int cx = Tx / 2, cy = Ty / 2;
+    const int S = Tx * Ty;
+    const int has_site_draw = (cx * cy == 4);
+    const uint64_t P = threshold(p), Q = threshold(q);
+    const uint64_t FULL = (uint64_t)1 << 32;
+    const int nblocks = nbx * nby;
+
+    /* per block: its set word; per group: its four site-draw words */
+    uint32_t *setw = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)nblocks);
+    uint32_t *sitew = (uint32_t *)malloc(sizeof(uint32_t) * 4 * (size_t)nblocks * (size_t)nq);
+    int64_t *stamp = check ? (int64_t *)malloc(sizeof(int64_t) * (size_t)L * (size_t)L) : NULL;
+    if (!setw || !sitew || (check && !stamp)) {
+        free(setw); free(sitew); free(stamp);
+        return OR_ENOMEM;
+    }
+    if (check)
+        for (size_t i = 0; i < (size_t)L * (size_t)L; ++i) stamp[i] = -1;
+    int64_t step_id = 0;
+    int status = OR_OK;
+    uint32_t w[4];
+
+    for (int m = 0; m < n_mcs && status == OR_OK; ++m) {
+        const uint32_t t = t0 + (uint32_t)m;
+        or_draw(seed, OR_TAG_ORIGIN, t, 0, 0, w);
+        const int ox = (int)(((uint64_t)w[0] * (uint64_t)Bx) >> 32);
+        const int oy = (int)(((uint64_t)w[1] * (uint64_t)By) >> 32);
+        for (int b = 0; b < nblocks; ++b) {
+            or_draw(seed, OR_TAG_SET, t, (uint64_t)b, 0, w);
+            setw[b] = w[0];
+            if (has_site_draw)
+                for (uint64_t g = 0; g < nq; ++g) {
+                    or_draw(seed, OR_TAG_SITE, t, (uint64_t)b * nq + g, 0, w);
+                    memcpy(&sitew[4 * ((uint64_t)b * nq + g)], w, sizeof w);
+                }
+        }
+        /* all blocks make step k "at the same time"; blocks are independent,
+           so visiting them one after the other gives the same result */
+        for (int k = 0; k < S && status == OR_OK; ++k, ++step_id) {
+            for (int by = 0; by < nby; ++by)
+                for (int bx = 0; bx < nbx; ++bx) {
+                    const int b = by * nbx + bx;
+                    const int s = (int)((setw[b] >> (2 * k)) & 3u);
+                    const int ssx = s & 1, ssy = s >> 1;
+                    for (int ty = 0; ty < nty; ++ty)
+                        for (int tx = 0; tx < ntx; ++tx) {
+                            const int j = ty / H;
+                            const uint64_t G = (uint64_t)b * nq + (uint64_t)(ty % H) * ntx + tx;
+                            int r = 0;
+                            if (has_site_draw)
+                                r = (int)((sitew[4 * G + (k >> 2)] >> (8 * j + 2 * (k & 3))) & 3u);
+                            const int rx = has_site_draw ? (r & 1) : 0;
+                            const int ry = has_site_draw ? (r >> 1) : 0;
+                            const int lx = tx * Tx + ssx * cx + rx;
+                            const int ly = ty * Ty + ssy * cy + ry;
+                            if ((nbx > 1 && lx == 0) || (nby > 1 && ly == 0)) continue;
+                            const int gx = (ox + bx * Bx + lx) % L;
+                            const int gy = (oy + by * By + ly) % L;
+                            if (check) {
+                                /* no two attempts of one step are equal or neighbours */
+                                const int nx[5] = { gx, (gx + 1) % L, (gx + L - 1) % L, gx, gx };
+                                const int ny[5] = { gy, gy, gy, (gy + 1) % L, (gy + L - 1) % L };
+                                for (int e = 0; e < 5; ++e)
+                                    if (stamp[(size_t)ny[e] * L + nx[e]] == step_id) status = OR_ECHECK;
+                                stamp[(size_t)gy * L + gx] = step_id;
+                            }
+                            const int kind = classify(L, sx, sy, gx, gy);
+                            if (kind == SITE_NONE) continue;
+                            const uint64_t thr = kind == SITE_MIN ? P : Q;
+                            if (thr == 0) continue;
+                            if (thr < FULL) {
+                                uint32_t wa[4], wb[4];
+                                or_draw(seed, OR_TAG_ACC1, t, G, (uint32_t)(k >> 2), wa);
+                                or_draw(seed, OR_TAG_ACC2, t, G, (uint32_t)k, wb);
+                                const uint32_t A = (wa[k & 3] >> (8 * j)) & 0xFFu;
+                                const uint32_t u = (A << 24) | (wb[j] & 0xFFFFFFu);
+                                if ((uint64_t)u >= thr) continue;
+                            }
+                            flip(L, sx, sy, gx, gy);
+                            const int dh = kind == SITE_MIN ? 2 : -2;
+                            *net += dh / 2;
+                            if (gx == 0 && gy == 0) *h00 += dh;
+                        }
+                }
+        }
+    }
+    free(setw); free(sitew); free(stamp);
+    return status;
+}
+
+/* -------------------------------------------- 1+1-d rooftop reduction */
+
+/* Ring of L bonds s[i] = h(i+1) - h(i) in {-1,+1}; site i is a minimum iff
+ * s[i-1] = -1 and s[i] = +1.  Attempt a of MCS t: site floor(w0*L/2^32),
+ * u = w1 of draw (RS1D, t, a, 0). */
+int or_rs1d_run(int L, double p, double q, uint64_t seed, uint32_t t0, int n_mcs,
+                int8_t *s, int64_t *h0, int64_t *net)
+{
+    if (L <= 0 || (L & 1) || n_mcs < 0) return OR_EINVAL;
+    const uint64_t P = threshold(p), Q = threshold(q);
+    uint32_t w[4];
+    for (int m = 0; m < n_mcs; ++m) {
+        uint32_t t = t0 + (uint32_t)m;
+        for (uint64_t a = 0; a < (uint64_t)L; ++a) {
+            or_draw(seed, OR_TAG_RS1D, t, a, 0, w);
+            int i = (int)(((uint64_t)w[0] * (uint64_t)L) >> 32);
+            int im = (i + L - 1) % L;
+            int dh = 0;
+            if (s[im] == -1 && s[i] == 1 && (uint64_t)w[1] < P) dh = 2;
+            else if (s[im] == 1 && s[i] == -1 && (uint64_t)w[1] < Q) dh = -2;
+            if (dh) {
+                s[im] = (int8_t)-s[im];
+                s[i] = (int8_t)-s[i];
+                *net += dh / 2;
+                if (i == 0) *h0 += dh;
+            }
+        }
+    }
+    return OR_OK;
+}
