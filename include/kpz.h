@@ -1,0 +1,144 @@
+/*
+ * kpz.h -- C ABI of the MI355X (gfx950) library for the Monte Carlo sweep of
+ * the 2+1-dimensional KPZ octahedron model.
+ *
+ * Model (Kelling, Odor, Nagy, Schulz, Heinig, "Comparison of different
+ * parallel implementations of the 2+1-dimensional KPZ model and the
+ * 3-dimensional KMC model"):
+ *   - Sec. 2.1: the surface on a periodic L x L lattice is stored as the
+ *     x and y slopes sigma = +-1 of every site; a site whose four neighbours
+ *     are all one unit higher (a local minimum) flips to a local maximum
+ *     with probability p, a local maximum flips back with probability q
+ *     (eq. "rule"); the squared width W^2 = <h^2> - <h>^2 (eq. "Wdef").
+ *   - Sec. 2.2: one Monte Carlo step (MCS) = N = L^2 update attempts.
+ *   - Sec. 3 and 3.1: random-sequential dynamics made parallel by two
+ *     decomposition layers -- dead-border blocks whose origin moves randomly
+ *     (device layer) and single-hit double tiling inside each block
+ *     (work-group layer).
+ *
+ * Data layout ("words"), shared with every caller:
+ *   L*L/16 uint32 words, row-major, L/16 words per row.  Word w of row y
+ *   holds sites x = 16 w + k, k = 0..15: bit 2k is sigma_x(x,y) =
+ *   h(x+1,y) - h(x,y) and bit 2k+1 is sigma_y(x,y) = h(x,y+1) - h(x,y),
+ *   bit value 1 meaning +1.  4 bytes per 16 sites, i.e. L^2/4 bytes.
+ *
+ * Memory ownership: the library never allocates device memory.  The caller
+ * owns the device buffers `words` (L*L/4 bytes) and `workspace`
+ * (kpz_workspace_bytes()); both must stay valid, and must not be touched by
+ * other work on other streams, until kpz_destroy().  The handle itself is a
+ * small host object owned by the library.
+ *
+ * Streams: all device work of a handle is enqueued on the HIP stream given
+ * to kpz_init (a hipStream_t passed as void*; NULL = the default stream).
+ * kpz_init and kpz_sweep only enqueue; kpz_roughness, kpz_get_state and
+ * kpz_set_state synchronise that stream.
+ *
+ * Errors: every entry point returns a kpz_status; nothing throws or aborts
+ * across the ABI.  On KPZ_EHIP the HIP error text is kept in the handle
+ * (kpz_last_error).  A handle is not thread-safe; distinct handles are
+ * independent.
+ */
+#ifndef KPZ_H_
+#define KPZ_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KPZ_OK = 0,
+    KPZ_EINVAL = -1,   /* invalid argument or parameter combination        */
+    KPZ_ESIZE = -2,    /* a caller buffer is smaller than required          */
+    KPZ_EHIP = -3,     /* a HIP runtime call failed (see kpz_last_error)    */
+    KPZ_ESTATE = -4,   /* device state inconsistent (e.g. corrupted words)  */
+    KPZ_ERANGE = -5    /* a result does not fit the output type             */
+} kpz_status;
+
+/* Parameters of one simulation.
+ *   L        linear size; even, a multiple of 16, at least 16.
+ *   p, q     acceptance probabilities of deposition (minimum -> maximum) and
+ *            desorption (maximum -> minimum), 0 <= p, q <= 1 (Sec. 2.1).
+ *            They are applied as integer thresholds floor(p * 2^32)
+ *            (p = 1 -> 2^32) against 32-bit uniforms.
+ *   seed     64-bit Philox4x32-10 key.
+ *   block_x, block_y
+ *            dead-border block shape of the device layer (Sec. 3): powers
+ *            of two dividing L, 16 <= block_x <= 1024, 16 <= block_y,
+ *            block_x * block_y <= 65536.  0 = library default
+ *            (min(L, 256) in each direction).  A direction with a single
+ *            block has no dead border (the block is periodic).
+ *   tile_x, tile_y
+ *            double-tiling tile shape of the work-group layer (Sec. 3.1);
+ *            must be 4 x 4 (four 2 x 2 cells per tile, 16 single-hit steps
+ *            per MCS); 0 = default (4).
+ *   flags    reserved, must be 0.
+ * The shape changes the sequence of updates, so results are reproducible for
+ * identical (L, p, q, seed, block, tile) only. */
+typedef struct {
+    int32_t L;
+    double p;
+    double q;
+    uint64_t seed;
+    int32_t block_x;
+    int32_t block_y;
+    int32_t tile_x;
+    int32_t tile_y;
+    uint32_t flags;
+} kpz_params;
+
+typedef struct kpz_sim kpz_sim;
+
+/* Bytes of device workspace a simulation with these parameters needs.
+ * Returns KPZ_EINVAL for invalid parameters. */
+kpz_status kpz_workspace_bytes(const kpz_params *params, size_t *ws_bytes);
+
+/* Creates a handle and enqueues the flat initial state (Sec. 2.1: heights
+ * h(x,y) = (x + y) mod 2, i.e. even rows 0x33333333 and odd rows
+ * 0xCCCCCCCC) into `d_words`, zeroes the workspace counters and sets the
+ * MCS counter t = 0.  `d_words` / `d_workspace` are device pointers of at
+ * least L*L/4 and kpz_workspace_bytes() bytes (else KPZ_ESIZE); `stream`
+ * is a hipStream_t.  On error *out is set to NULL. */
+kpz_status kpz_init(kpz_sim **out, const kpz_params *params, uint32_t *d_words,
+                    size_t words_bytes, void *d_workspace, size_t workspace_bytes,
+                    void *stream);
+
+/* Enqueues n_mcs Monte Carlo steps t, t+1, ..., t+n_mcs-1 of the decomposed
+ * schedule (Sec. 3 / 3.1): per MCS a new random block origin, then 16
+ * single-hit steps in which every block picks a random set of cells and
+ * every 4 x 4 tile makes one attempt in its cell of that set.  n_mcs >= 0. */
+kpz_status kpz_sweep(kpz_sim *sim, int32_t n_mcs);
+
+/* Exact moments of the current surface (Sec. 2.1, height reconstruction and
+ * eq. "Wdef"): S1 = sum h, S2 = sum h^2 over all N = L^2 sites, with the
+ * absolute heights of the flat start continued by the dynamics (h(0,0) =
+ * 0 at t = 0), and W2 = S2/N - (S1/N)^2, computed as the double nearest to
+ * (N S2 - S1^2) / N^2 from 128-bit integers.  Synchronises the stream.
+ * Any output pointer may be NULL.  KPZ_ERANGE if S1 or S2 does not fit
+ * int64 (W2 is still written); KPZ_ESTATE if the words are not a valid
+ * surface for the recorded number of flips. */
+kpz_status kpz_roughness(kpz_sim *sim, int64_t *S1, int64_t *S2, double *W2);
+
+/* Checkpoint support.  The complete dynamical state is (words, t, net_flips)
+ * where net_flips = #depositions - #desorptions since the flat start (so
+ * S1 = N/2 + 2 net_flips).  get synchronises the stream; set enqueues the
+ * counter reset and makes the next sweep run MCS number t. */
+kpz_status kpz_get_state(kpz_sim *sim, int64_t *t, int64_t *net_flips);
+kpz_status kpz_set_state(kpz_sim *sim, int64_t t, int64_t net_flips);
+
+/* Frees the handle (not the caller's buffers).  NULL is ignored. */
+void kpz_destroy(kpz_sim *sim);
+
+/* Static text for a status code. */
+const char *kpz_status_str(kpz_status status);
+
+/* Text of the last error recorded in the handle ("" if none). */
+const char *kpz_last_error(const kpz_sim *sim);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KPZ_H_ */

@@ -71,7 +71,14 @@ def lib():
                                 c.c_uint32, c.c_int, i8p, i8p, i64p, i64p, c.c_int]
         L.or_rs1d_run.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
                                   c.c_uint32, c.c_int, i8p, i64p, i64p]
-        for f in ("or_flat", "or_rs_heights_run", "or_rs_slopes_run", "or_dd_run", "or_rs1d_run"):
+        L.or_dd_block_mcs.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
+                                      c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint32,
+                                      c.c_int, c.c_int, i8p, i8p, i64p]
+        L.or_dd_origin.argtypes = [c.c_uint64, c.c_uint32, c.c_int, c.c_int,
+                                   c.POINTER(c.c_int), c.POINTER(c.c_int)]
+        L.or_dd_origin.restype = None
+        for f in ("or_flat", "or_rs_heights_run", "or_rs_slopes_run", "or_dd_run", "or_rs1d_run",
+                  "or_dd_block_mcs"):
             getattr(L, f).restype = c.c_int
         _lib = L
     return _lib
@@ -158,6 +165,29 @@ def rs_heights_run(h: np.ndarray, t0: int, n_mcs: int, p: float, q: float, seed:
     h = np.ascontiguousarray(h, np.int64)
     _check(lib().or_rs_heights_run(L, p, q, seed, t0, n_mcs, h), "rs_heights_run")
     return h
+
+
+def dd_origin(seed: int, t: int, block) -> tuple:
+    ox, oy = ctypes.c_int(), ctypes.c_int()
+    lib().or_dd_origin(seed, t, block[0], block[1], ctypes.byref(ox), ctypes.byref(oy))
+    return ox.value, oy.value
+
+
+def dd_block_mcs(L: int, p: float, q: float, seed: int, block, t: int, bx: int, by: int,
+                 bsx: np.ndarray, bsy: np.ndarray) -> int:
+    """One MCS of block (bx, by) on its own slopes (arrays of shape
+    (By, Bx), modified in place); returns the net number of flips."""
+    net = np.zeros(1, np.int64)
+    _check(lib().or_dd_block_mcs(L, p, q, seed, block[0], block[1], 4, 4, t, bx, by, bsx, bsy,
+                                 net), "dd_block_mcs")
+    return int(net[0])
+
+
+def block_region(block, origin, bx: int, by: int, L: int):
+    """Global (rows, cols) index vectors of block (bx, by) for a given origin."""
+    rows = (origin[1] + by * block[1] + np.arange(block[1])) % L
+    cols = (origin[0] + bx * block[0] + np.arange(block[0])) % L
+    return rows, cols
 
 
 def rs1d_run(s: np.ndarray, h0: np.ndarray, net: np.ndarray, t0: int, n_mcs: int,

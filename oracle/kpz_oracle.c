@@ -366,3 +366,81 @@ int or_rs1d_run(int L, double p, double q, uint64_t seed, uint32_t t0, int n_mcs
     }
     return OR_OK;
 }
+
+/* ------------------------------------------- one block, on its own copy */
+
+/*
+ * One MCS t of the decomposed schedule restricted to block (bx, by), run on a
+ * copy of that block's sites: bsx[ly*Bx+lx], bsy[ly*Bx+lx] hold sigma_x,
+ * sigma_y of block-local site (lx, ly), i.e. global site
+ * ((ox + bx*Bx + lx) mod L, (oy + by*By + ly) mod L).  Requires more than one
+ * block along both axes: then the dead border (lx = 0, ly = 0) keeps every
+ * update inside the block's own sites, so this equals the block's part of
+ * or_dd_run.  Same draws and the same step order as or_dd_run.
+ */
+int or_dd_block_mcs(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, int Ty,
+                    uint32_t t, int bx, int by, int8_t *bsx, int8_t *bsy, int64_t *net)
+{
+    if (!dd_validate(L, Bx, By, Tx, Ty)) return OR_EINVAL;
+    const int nbx = L / Bx, nby = L / By;
+    if (nbx < 2 || nby < 2 || bx < 0 || by < 0 || bx >= nbx || by >= nby) return OR_EINVAL;
+    const int ntx = Bx / Tx, nty = By / Ty;
+    const int H = nty >= 4 ? nty / 4 : 1;
+    const uint64_t nq = (uint64_t)ntx * (uint64_t)H;
+    const int cx = Tx / 2, cy = Ty / 2;
+    const int S = Tx * Ty;
+    const int has_site_draw = (cx * cy == 4);
+    const uint64_t P = threshold(p), Q = threshold(q);
+    const uint64_t FULL = (uint64_t)1 << 32;
+    const int b = by * nbx + bx;
+    uint32_t w[4];
+    or_draw(seed, OR_TAG_SET, t, (uint64_t)b, 0, w);
+    const uint32_t setw = w[0];
+    for (int k = 0; k < S; ++k) {
+        const int s = (int)((setw >> (2 * k)) & 3u);
+        const int ssx = s & 1, ssy = s >> 1;
+        for (int ty = 0; ty < nty; ++ty)
+            for (int tx = 0; tx < ntx; ++tx) {
+                const int j = ty / H;
+                const uint64_t G = (uint64_t)b * nq + (uint64_t)(ty % H) * ntx + tx;
+                int r = 0;
+                if (has_site_draw) {
+                    or_draw(seed, OR_TAG_SITE, t, G, 0, w);
+                    r = (int)((w[k >> 2] >> (8 * j + 2 * (k & 3))) & 3u);
+                }
+                const int rx = has_site_draw ? (r & 1) : 0;
+                const int ry = has_site_draw ? (r >> 1) : 0;
+                const int lx = tx * Tx + ssx * cx + rx;
+                const int ly = ty * Ty + ssy * cy + ry;
+                if (lx == 0 || ly == 0) continue;   /* dead border */
+                int8_t *a = &bsx[ly * Bx + lx], *bb = &bsy[ly * Bx + lx];
+                int8_t *c = &bsx[ly * Bx + lx - 1], *d = &bsy[(ly - 1) * Bx + lx];
+                int kind = SITE_NONE;
+                if (*a == 1 && *bb == 1 && *c == -1 && *d == -1) kind = SITE_MIN;
+                if (*a == -1 && *bb == -1 && *c == 1 && *d == 1) kind = SITE_MAX;
+                if (kind == SITE_NONE) continue;
+                const uint64_t thr = kind == SITE_MIN ? P : Q;
+                if (thr == 0) continue;
+                if (thr < FULL) {
+                    uint32_t wa[4], wb[4];
+                    or_draw(seed, OR_TAG_ACC1, t, G, (uint32_t)(k >> 2), wa);
+                    or_draw(seed, OR_TAG_ACC2, t, G, (uint32_t)k, wb);
+                    const uint32_t A = (wa[k & 3] >> (8 * j)) & 0xFFu;
+                    const uint32_t u = (A << 24) | (wb[j] & 0xFFFFFFu);
+                    if ((uint64_t)u >= thr) continue;
+                }
+                *a = (int8_t)-*a; *bb = (int8_t)-*bb; *c = (int8_t)-*c; *d = (int8_t)-*d;
+                *net += kind == SITE_MIN ? 1 : -1;
+            }
+    }
+    return OR_OK;
+}
+
+/* Origin of MCS t: ox = floor(w0 * Bx / 2^32), oy = floor(w1 * By / 2^32). */
+void or_dd_origin(uint64_t seed, uint32_t t, int Bx, int By, int *ox, int *oy)
+{
+    uint32_t w[4];
+    or_draw(seed, OR_TAG_ORIGIN, t, 0, 0, w);
+    *ox = (int)(((uint64_t)w[0] * (uint64_t)Bx) >> 32);
+    *oy = (int)(((uint64_t)w[1] * (uint64_t)By) >> 32);
+}

@@ -1,0 +1,81 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/kpz.h declares, and validates its arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def kpz():
+    import paper_1204_5072_amd as k
+    if not os.path.exists(k.LIB_PATH):
+        from paper_1204_5072_amd import build
+        build.build()
+    k.lib()
+    return k
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "kpz.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kpz_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_function(kpz):
+    names = header_functions()
+    assert set(names) == set(kpz.EXPORTED)
+    for n in names:
+        assert hasattr(kpz.lib(), n), n
+
+
+def test_status_strings(kpz):
+    assert kpz.status_str(0) == "ok"
+    for s in (-1, -2, -3, -4, -5):
+        assert kpz.status_str(s) and kpz.status_str(s) != "unknown status"
+    assert kpz.status_str(-99) == "unknown status"
+
+
+@pytest.mark.parametrize("L,block", [(16, None), (64, None), (4096, None), (65536, None),
+                                     (4096, (256, 64)), (48, (16, 16)), (768, (256, 256))])
+def test_workspace_bytes_valid(kpz, L, block):
+    n = kpz.workspace_bytes(kpz.make_params(L, 1.0, 0.0, 1, block))
+    assert n >= 256 + 8 * 1024 + 16 * L
+
+
+@pytest.mark.parametrize("kw", [
+    dict(L=8), dict(L=24), dict(L=0), dict(L=64, p=1.5), dict(L=64, q=-0.1),
+    dict(L=64, block=(48, 16)), dict(L=64, block=(8, 16)), dict(L=64, block=(128, 64)),
+    dict(L=2048, block=(2048, 16)), dict(L=1024, block=(512, 256)),
+    dict(L=64, tile=(8, 8)), dict(L=96, block=(64, 32)),
+])
+def test_invalid_params_rejected(kpz, kw):
+    p = kpz.make_params(**kw)
+    with pytest.raises(kpz.KPZError) as e:
+        kpz.workspace_bytes(p)
+    assert e.value.status == kpz.KPZ_EINVAL
+
+
+def test_init_validates_before_device_work(kpz):
+    L = kpz.lib()
+    h = ctypes.c_void_p(1)
+    bad = kpz.make_params(24)
+    assert L.kpz_init(ctypes.byref(h), ctypes.byref(bad), ctypes.c_void_p(8), 1 << 20,
+                      ctypes.c_void_p(8), 1 << 20, None) == kpz.KPZ_EINVAL
+    assert h.value is None
+    good = kpz.make_params(64)
+    # null device pointers and short buffers are refused
+    assert L.kpz_init(ctypes.byref(h), ctypes.byref(good), None, 1 << 20, ctypes.c_void_p(8),
+                      1 << 20, None) == kpz.KPZ_EINVAL
+    assert L.kpz_init(ctypes.byref(h), ctypes.byref(good), ctypes.c_void_p(8), 64 * 64 // 4 - 4,
+                      ctypes.c_void_p(8), 1 << 20, None) == kpz.KPZ_ESIZE
+    assert L.kpz_init(ctypes.byref(h), ctypes.byref(good), ctypes.c_void_p(8), 64 * 64 // 4,
+                      ctypes.c_void_p(8), 100, None) == kpz.KPZ_ESIZE
+    assert L.kpz_init(None, ctypes.byref(good), ctypes.c_void_p(8), 1 << 20, ctypes.c_void_p(8),
+                      1 << 20, None) == kpz.KPZ_EINVAL
+    assert L.kpz_sweep(None, 1) == kpz.KPZ_EINVAL
+    assert L.kpz_roughness(None, None, None, None) == kpz.KPZ_EINVAL
+    L.kpz_destroy(None)

@@ -1,0 +1,208 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle's
+decomposed schedule, element by element.
+
+Integer state, so the bar is bit-exactness of every packed word and of the
+exact moments S1, S2; W^2 must equal the double the oracle derives from the
+same integers (correctly rounded from 128-bit integers: equal for power-of-two
+L, within one ulp otherwise).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1204_5072_amd as kpz
+    kpz.lib()
+    return kpz
+
+
+def oracle_state(oracle_lib, L, n_mcs, p, q, seed, block):
+    st = oracle_lib.SlopeState(L)
+    st.run_dd(n_mcs, p, q, seed, block=block, tile=(4, 4))
+    return st
+
+
+def assert_moments(oracle_lib, st, m, L):
+    S1, S2 = st.moments()
+    assert (m.S1, m.S2) == (S1, S2)
+    exact = oracle_lib.w2(S1, S2, L * L)
+    if L & (L - 1) == 0:
+        assert m.W2 == exact
+    else:
+        assert math.isclose(m.W2, exact, rel_tol=4e-16, abs_tol=0)
+
+
+def test_init_and_t0_moments(gpu, oracle_lib):
+    for L in (16, 48, 64, 256, 1024):
+        _log(f"init L={L}")
+        sim = gpu.Sim(L)
+        w = sim.words_host()
+        ref = oracle_lib.pack(*[a for a in (oracle_lib.SlopeState(L).sx, oracle_lib.SlopeState(L).sy)])
+        assert np.array_equal(w, ref)
+        m = sim.roughness()
+        assert (m.S1, m.S2, m.W2) == (L * L // 2, L * L // 2, 0.25)
+        assert sim.state() == (0, 0)
+
+
+CASES = [
+    # (L, block, p, q, seed, n_mcs)
+    (16, (16, 16), 1.0, 0.0, 1, 6),          # one block, periodic in both directions, 4 lanes
+    (32, (16, 16), 1.0, 0.0, 2, 6),          # dead borders, 16-wide blocks (one word per row)
+    (64, (64, 64), 1.0, 0.0, 1, 8),          # one 64x64 block (the L = 64 workload shape)
+    (64, (32, 16), 1.0, 0.0, 3, 8),
+    (64, (16, 64), 1.0, 0.0, 4, 8),          # single block along y, dead border along x
+    (64, (64, 16), 0.5, 0.5, 5, 8),          # single block along x
+    (128, (64, 64), 1.0, 0.25, 6, 6),
+    (128, (128, 128), 1.0, 0.0, 7, 6),        # K = 4 quads per lane
+    (256, (256, 256), 1.0, 0.0, 8, 4),        # K = 16 (the large-lattice shape)
+    (256, (128, 128), 1.0, 0.0, 9, 4),
+    (256, (256, 64), 0.7, 0.3, 10, 4),        # K = 4, generic thresholds (ties resolved)
+    (256, (1024 // 4, 32), 0.3, 0.9, 11, 4),
+    (512, (512, 128), 1.0, 0.0, 12, 3),       # 512-wide blocks, K = 16
+    (1024, (1024, 64), 1.0, 0.5, 13, 2),      # 1024-wide blocks
+    (48, (16, 16), 1.0, 0.0, 14, 6),          # non-power-of-two L (ragged word count per row)
+    (96, (32, 32), 0.5, 0.5, 15, 6),
+    (192, (64, 64), 1.0, 0.0, 16, 4),
+    (64, (32, 32), 0.0, 0.0, 17, 3),          # frozen dynamics
+    (64, (32, 32), 0.0, 1.0, 18, 5),          # desorption only
+    (256, (64, 64), 1.0, 0.999999, 19, 3),    # threshold just below 2^32: tie path
+]
+
+
+@pytest.mark.parametrize("L,block,p,q,seed,n", CASES)
+def test_sweep_matches_oracle(gpu, oracle_lib, L, block, p, q, seed, n):
+    _log(f"sweep L={L} block={block} p={p} q={q} seed={seed} n={n}")
+    sim = gpu.Sim(L, p, q, seed, block)
+    st = oracle_lib.SlopeState(L)
+    for t in range(n):
+        sim.sweep(1)
+        st.run_dd(1, p, q, seed, block=block, tile=(4, 4))
+        w = sim.words_host()
+        ref = oracle_lib.pack(st.sx, st.sy)
+        if not np.array_equal(w, ref):
+            bad = np.argwhere(w != ref)
+            pytest.fail(f"words differ after MCS {t}: {len(bad)} words, first at {bad[0]}")
+        m = sim.roughness()
+        assert_moments(oracle_lib, st, m, L)
+        assert sim.state() == (t + 1, int(st.net[0]))
+
+
+def test_l64_full_run_every_mcs(gpu, oracle_lib):
+    """The L = 64, p = 1, q = 0, seed 1 workload: 1000 MCS, moments after
+    every MCS, words compared every 50 MCS."""
+    L, p, q, seed = 64, 1.0, 0.0, 1
+    _log("full L=64 run, 1000 MCS")
+    sim = gpu.Sim(L, p, q, seed)
+    st = oracle_lib.SlopeState(L)
+    for t in range(1000):
+        sim.sweep(1)
+        st.run_dd(1, p, q, seed, block=(64, 64), tile=(4, 4))
+        m = sim.roughness()
+        S1, S2 = st.moments()
+        assert (m.S1, m.S2) == (S1, S2), t
+        if t % 50 == 49:
+            assert np.array_equal(sim.words_host(), oracle_lib.pack(st.sx, st.sy)), t
+
+
+def test_batch_of_mcs_equals_single_steps(gpu):
+    """kpz_sweep(n) == n calls of kpz_sweep(1) (t advances inside)."""
+    a = gpu.Sim(128, 1.0, 0.25, 3, (64, 32))
+    b = gpu.Sim(128, 1.0, 0.25, 3, (64, 32))
+    a.sweep(7)
+    for _ in range(7):
+        b.sweep(1)
+    assert np.array_equal(a.words_host(), b.words_host())
+    assert a.state() == b.state() == (7, b.state()[1])
+
+
+def test_checkpoint_resume(gpu):
+    L = 128
+    ref = gpu.Sim(L, 1.0, 0.5, 9, (64, 64)).sweep(10)
+    a = gpu.Sim(L, 1.0, 0.5, 9, (64, 64)).sweep(4)
+    words, (t, net) = a.words_host().copy(), a.state()
+    b = gpu.Sim(L, 1.0, 0.5, 9, (64, 64))
+    b.load_words(words)
+    b.set_state(t, net)
+    b.sweep(6)
+    assert np.array_equal(b.words_host(), ref.words_host())
+    assert b.roughness() == ref.roughness()
+
+
+def test_l4096_first_mcs(gpu, oracle_lib):
+    """L = 4096 (the 2^24-site workload), default 256 x 256 blocks: words after
+    MCS 1 and 2 for both (p, q) of that workload."""
+    L = 4096
+    for p, q in ((1.0, 0.0), (0.5, 0.5)):
+        _log(f"L=4096 p={p} q={q}")
+        sim = gpu.Sim(L, p, q, 1)
+        st = oracle_lib.SlopeState(L)
+        for t in range(2):
+            sim.sweep(1)
+            st.run_dd(1, p, q, 1, block=(256, 256), tile=(4, 4))
+            assert np.array_equal(sim.words_host(), oracle_lib.pack(st.sx, st.sy)), t
+        assert_moments(oracle_lib, st, sim.roughness(), L)
+
+
+def _block_slopes(oracle_lib, words_rows, cols, L):
+    """Unpack the given global columns from full packed rows."""
+    sx, sy = oracle_lib.unpack(words_rows, L) if words_rows.shape[0] == L else \
+        _unpack_rows(oracle_lib, words_rows, L)
+    return np.ascontiguousarray(sx[:, cols]), np.ascontiguousarray(sy[:, cols])
+
+
+def _unpack_rows(oracle_lib, rows_words, L):
+    n = rows_words.shape[0]
+    w = rows_words.astype(np.uint64)
+    k = np.arange(16, dtype=np.uint64)
+    bx = ((w[:, :, None] >> (2 * k)) & 1).reshape(n, L)
+    by = ((w[:, :, None] >> (2 * k + 1)) & 1).reshape(n, L)
+    return (2 * bx.astype(np.int8) - 1), (2 * by.astype(np.int8) - 1)
+
+
+def test_l65536_sampled_blocks(gpu, oracle_lib):
+    """The 2^32-site workload in the launch configuration the benchmark times
+    (256 x 256 blocks, 16 quads per lane): MCS 2 checked on sampled blocks,
+    including the ones that wrap around the lattice edges, against the
+    oracle's single-block runner; the moments must be consistent."""
+    import torch
+    L, B, p, q, seed = 65536, (256, 256), 1.0, 0.0, 1
+    _log("L=65536 sampled blocks")
+    sim = gpu.Sim(L, p, q, seed, B)
+    sim.sweep(2)
+    t = 2
+    origin = oracle_lib.dd_origin(seed, t, B)
+    nb = L // B[0]
+    samples = [(0, 0), (nb - 1, 0), (0, nb - 1), (nb - 1, nb - 1), (123, 77), (200, 255)]
+    W = L // 16
+    words = sim.words.view(L, W)
+    befores = []
+    for bx, by in samples:
+        rows, cols = oracle_lib.block_region(B, origin, bx, by, L)
+        r = torch.as_tensor(rows, device=sim.words.device)
+        host = words.index_select(0, r).cpu().numpy().view(np.uint32)
+        befores.append(_block_slopes(oracle_lib, host, cols, L))
+    sim.sweep(1)
+    for (bx, by), (bsx, bsy) in zip(samples, befores):
+        rows, cols = oracle_lib.block_region(B, origin, bx, by, L)
+        oracle_lib.dd_block_mcs(L, p, q, seed, B, t, bx, by, bsx, bsy)
+        r = torch.as_tensor(rows, device=sim.words.device)
+        host = words.index_select(0, r).cpu().numpy().view(np.uint32)
+        gsx, gsy = _block_slopes(oracle_lib, host, cols, L)
+        assert np.array_equal(gsx, bsx), (bx, by)
+        assert np.array_equal(gsy, bsy), (bx, by)
+    m = sim.roughness()   # raises KPZ_ESTATE if words and flip count disagree
+    assert m.W2 > 0.25

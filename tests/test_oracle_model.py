@@ -319,3 +319,25 @@ def test_dd_with_acceptance_matches_exact_law(oracle_lib, chain4):
     vals = _mc_w2(oracle_lib, lambda i: oracle_lib.SlopeState(4).run_dd(
         t, p, q, 9000 + i, block=block, tile=tile), 3000, t)
     assert abs(_z(vals, exact)) < 4.0
+
+
+@pytest.mark.parametrize("p,q", [(1.0, 0.0), (0.6, 0.4)])
+def test_block_runner_equals_full_run(oracle_lib, p, q):
+    """One block on its own copy == that block's part of the whole-lattice
+    MCS (blocks of one MCS do not interact)."""
+    L, B, seed = 64, (32, 16), 3
+    st = oracle_lib.SlopeState(L).run_dd(2, p, q, seed, block=B)
+    before = st.copy()
+    t = st.t
+    st.run_dd(1, p, q, seed, block=B)
+    origin = oracle_lib.dd_origin(seed, t, B)
+    total = 0
+    for by in range(L // B[1]):
+        for bx in range(L // B[0]):
+            rows, cols = oracle_lib.block_region(B, origin, bx, by, L)
+            bsx = np.ascontiguousarray(before.sx[np.ix_(rows, cols)])
+            bsy = np.ascontiguousarray(before.sy[np.ix_(rows, cols)])
+            total += oracle_lib.dd_block_mcs(L, p, q, seed, B, t, bx, by, bsx, bsy)
+            assert np.array_equal(bsx, st.sx[np.ix_(rows, cols)])
+            assert np.array_equal(bsy, st.sy[np.ix_(rows, cols)])
+    assert total == int(st.net[0] - before.net[0])
