@@ -67,9 +67,10 @@ typedef enum {
  *   block_x, block_y
  *            dead-border block shape of the device layer (Sec. 3): powers
  *            of two dividing L, 16 <= block_x <= 1024, 16 <= block_y,
- *            block_x * block_y <= 65536.  0 = library default
- *            (min(L, 256) in each direction).  A direction with a single
- *            block has no dead border (the block is periodic).
+ *            block_x * block_y <= 65536.  0 = library default (the
+ *            largest power of two <= 256 dividing L, per direction).  A
+ *            direction with a single block has no dead border (the block is
+ *            periodic).
  *   tile_x, tile_y
  *            double-tiling tile shape of the work-group layer (Sec. 3.1);
  *            must be 4 x 4 (four 2 x 2 cells per tile, 16 single-hit steps

@@ -541,8 +541,11 @@ kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
     const int tx = p->tile_x ? p->tile_x : TILE, ty = p->tile_y ? p->tile_y : TILE;
     if (tx != TILE || ty != TILE) return KPZ_EINVAL;
     const int64_t L = p->L;
-    const int64_t bx = p->block_x ? p->block_x : (L < 256 ? L : 256);
-    const int64_t by = p->block_y ? p->block_y : (L < 256 ? L : 256);
+    // default: the largest power of two <= 256 that divides L (L % 16 == 0)
+    int64_t dflt = 256;
+    while (L % dflt) dflt >>= 1;
+    const int64_t bx = p->block_x ? p->block_x : dflt;
+    const int64_t by = p->block_y ? p->block_y : dflt;
     if (!is_pow2(bx) || !is_pow2(by)) return KPZ_EINVAL;
     if (bx < 16 || by < 16 || bx > 1024 || bx * by > 65536) return KPZ_EINVAL;
     if (L % bx || L % by) return KPZ_EINVAL;
