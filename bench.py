@@ -70,6 +70,84 @@ def cpu_baseline(L, block, p, q, seed, budget_s):
                       f"{dt:.1f} s on {platform.processor() or platform.machine()}"}
 
 
+def log_times(n=64, t_max=10_000):
+    """n log-spaced sampling times ending at t_max: t_k = max(t_{k-1} + 1,
+    round(t_max^(k/(n-1))))."""
+    out = []
+    for k in range(n):
+        t = max((out[-1] + 1) if out else 1, round(t_max ** (k / (n - 1))))
+        out.append(int(t))
+    return out
+
+
+def ensemble_leg(args):
+    """The batched ensemble: 512 lattices, L uniform over {256,...,2048},
+    p = 1, q uniform over {0, 1/4, 1/2}, seeds 1000 + r (job table from numpy
+    default_rng(0)), 10^4 MCS with W^2 at 64 log-spaced times, run as one
+    captured graph of persistent launches; compared with plain single-lattice
+    launches of a subset of the same members, one after another."""
+    import numpy as np
+    import torch
+    import paper_1204_5072_amd as kpz
+    from paper_1204_5072_amd import autotune
+
+    rng = np.random.default_rng(0)
+    n = args.ens_members
+    Ls = rng.choice([256, 512, 1024, 2048], size=n)
+    qs = rng.choice([0.0, 0.25, 0.5], size=n)
+    base = [kpz.make_params(int(L), 1.0, float(q), 1000 + r) for r, (L, q) in enumerate(zip(Ls, qs))]
+    if args.ens_block:
+        block = tuple(args.ens_block)
+        tuned = None
+    else:
+        tuned = autotune.tune_ensemble(base, mcs=2)
+        block = tuned["block"]
+    members = [kpz.make_params(m.L, m.p, m.q, m.seed, block) for m in base]
+    times = log_times(64, args.ens_mcs)
+    ens = kpz.Ensemble(members)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S1, S2, W2 = ens.run(times)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    attempts = float(sum(int(L) ** 2 for L in Ls)) * times[-1]
+    ens.close()
+    # sequential plain launches: a subset of members, each on its own
+    m_seq = min(args.ens_seq_members, n)
+    seq_mcs = 5
+    sims = [kpz.Sim(m.L, m.p, m.q, m.seed, block) for m in members[:m_seq]]
+    for sim in sims:
+        sim.sweep(1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for sim in sims:
+        sim.sweep(seq_mcs)
+    torch.cuda.synchronize()
+    seq_elapsed = time.perf_counter() - t1
+    seq_attempts = float(sum(m.L ** 2 for m in members[:m_seq])) * seq_mcs
+    final = {}
+    for L in (256, 512, 1024, 2048):
+        sel = Ls == L
+        if sel.any():
+            final[str(L)] = float(np.mean(W2[-1][sel]))
+    return {
+        "metric": "site-update attempts/s, batched ensemble",
+        "value": attempts / elapsed,
+        "unit": "attempts/s",
+        "seconds": elapsed,
+        "members": n,
+        "mcs": times[-1],
+        "samples": len(times),
+        "block": list(block),
+        "autotune_ms_per_mcs": ({f"{k[0]}x{k[1]}": v for k, v in tuned["ms_per_mcs"].items()}
+                                if tuned else None),
+        "sequential_plain_launches": {"value": seq_attempts / seq_elapsed, "unit": "attempts/s",
+                                      "members": m_seq, "mcs": seq_mcs},
+        "speedup_vs_sequential": (attempts / elapsed) / (seq_attempts / seq_elapsed),
+        "mean_w2_final_by_L": final,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +161,11 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ens-members", type=int, default=512)
+    ap.add_argument("--ens-mcs", type=int, default=10_000)
+    ap.add_argument("--ens-block", type=int, nargs=2, default=None)
+    ap.add_argument("--ens-seq-members", type=int, default=32)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -168,6 +251,11 @@ def main():
         "w2_last": w2[-1] if w2 else None,
         "t_final": sim.state()[0],
     }
+    sim.close()
+    del sim
+    if not args.no_ensemble:
+        print("bench: ensemble leg", file=sys.stderr, flush=True)
+        line["ensemble"] = ensemble_leg(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(L, block, args.p, args.q, args.seed, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -138,6 +138,65 @@ const char *kpz_status_str(kpz_status status);
 /* Text of the last error recorded in the handle ("" if none). */
 const char *kpz_last_error(const kpz_sim *sim);
 
+/* ------------------------------------------------------------------------
+ * Ensembles: many independent lattices advanced together.
+ *
+ * Ensemble averages of W^2(t) need hundreds of independent realisations.  A
+ * batch holds n members, each a full simulation as above with its own L, p,
+ * q and seed; all members share one block shape (block_x, block_y, resolved
+ * as for a single lattice from the smallest L when 0) and the 4 x 4 tile.
+ * Every member's results are bit-identical to a single-lattice run with the
+ * same parameters and block shape.  One kpz_batch_sweep is one persistent
+ * launch that runs every member's MCS; members do not wait for each other.
+ *
+ * Memory (caller-owned device buffers, sizes from kpz_batch_sizes):
+ * `words` holds the members' packed lattices one after the other (member
+ * r at kpz_batch_word_offset words, 256-byte aligned), each in the single-
+ * lattice layout; `workspace` holds per-member counters, row sums, the
+ * straddling-word buffers and the sample results.
+ */
+typedef struct kpz_batch kpz_batch;
+
+#define KPZ_BATCH_MAX_SAMPLES 128
+
+/* Device bytes of the words buffer and of the workspace for these members
+ * (n >= 1).  KPZ_EINVAL if a member is invalid or the block shapes differ. */
+kpz_status kpz_batch_sizes(const kpz_params *members, int32_t n, size_t *words_bytes,
+                           size_t *workspace_bytes);
+
+/* Creates the batch and enqueues the flat start of every member (t = 0) on
+ * `stream` (a hipStream_t). */
+kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
+                          uint32_t *d_words, size_t words_bytes, void *d_workspace,
+                          size_t workspace_bytes, void *stream);
+
+/* Offset (in uint32 words) of member r's lattice inside the words buffer. */
+kpz_status kpz_batch_word_offset(const kpz_batch *batch, int32_t member, size_t *offset_words);
+
+/* Enqueues n_mcs MCS of every member (one persistent launch). */
+kpz_status kpz_batch_sweep(kpz_batch *batch, int32_t n_mcs);
+
+/* Exact moments of every member (arrays of n; any may be NULL), as
+ * kpz_roughness.  Synchronises the stream. */
+kpz_status kpz_batch_roughness(kpz_batch *batch, int64_t *S1, int64_t *S2, double *W2);
+
+/* Runs the whole sampling schedule as one captured HIP graph: for each of
+ * the n_times strictly increasing MCS counts times[k] (> current t), sweep
+ * every member up to t = times[k] and take its moments.  Outputs are arrays
+ * of n_times * n, sample-major (any may be NULL).  n_times <=
+ * KPZ_BATCH_MAX_SAMPLES.  Synchronises the stream. */
+kpz_status kpz_batch_run(kpz_batch *batch, const int32_t *times, int32_t n_times, int64_t *S1,
+                         int64_t *S2, double *W2);
+
+/* Current MCS count of the batch (all members share it). */
+kpz_status kpz_batch_get_t(const kpz_batch *batch, int64_t *t);
+
+/* Frees the batch handle (not the caller's buffers).  NULL is ignored. */
+void kpz_batch_destroy(kpz_batch *batch);
+
+/* Text of the last error recorded in the batch handle ("" if none). */
+const char *kpz_batch_last_error(const kpz_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

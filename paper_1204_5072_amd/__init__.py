@@ -22,7 +22,11 @@ LIB_PATH = os.path.join(PKG, "libkpz.so")
 KPZ_OK, KPZ_EINVAL, KPZ_ESIZE, KPZ_EHIP, KPZ_ESTATE, KPZ_ERANGE = 0, -1, -2, -3, -4, -5
 
 EXPORTED = ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness", "kpz_get_state",
-            "kpz_set_state", "kpz_destroy", "kpz_status_str", "kpz_last_error")
+            "kpz_set_state", "kpz_destroy", "kpz_status_str", "kpz_last_error",
+            "kpz_batch_sizes", "kpz_batch_init", "kpz_batch_word_offset", "kpz_batch_sweep",
+            "kpz_batch_roughness", "kpz_batch_run", "kpz_batch_get_t", "kpz_batch_destroy",
+            "kpz_batch_last_error")
+BATCH_MAX_SAMPLES = 128
 
 
 class KPZError(RuntimeError):
@@ -66,8 +70,22 @@ def lib() -> ctypes.CDLL:
         L.kpz_status_str.restype = c.c_char_p
         L.kpz_last_error.argtypes = [vp]
         L.kpz_last_error.restype = c.c_char_p
+        P, i64p, f64p = c.POINTER(kpz_params), c.POINTER(c.c_int64), c.POINTER(c.c_double)
+        L.kpz_batch_sizes.argtypes = [P, c.c_int32, c.POINTER(c.c_size_t), c.POINTER(c.c_size_t)]
+        L.kpz_batch_init.argtypes = [c.POINTER(vp), P, c.c_int32, vp, c.c_size_t, vp, c.c_size_t, vp]
+        L.kpz_batch_word_offset.argtypes = [vp, c.c_int32, c.POINTER(c.c_size_t)]
+        L.kpz_batch_sweep.argtypes = [vp, c.c_int32]
+        L.kpz_batch_roughness.argtypes = [vp, i64p, i64p, f64p]
+        L.kpz_batch_run.argtypes = [vp, c.POINTER(c.c_int32), c.c_int32, i64p, i64p, f64p]
+        L.kpz_batch_get_t.argtypes = [vp, i64p]
+        L.kpz_batch_destroy.argtypes = [vp]
+        L.kpz_batch_destroy.restype = None
+        L.kpz_batch_last_error.argtypes = [vp]
+        L.kpz_batch_last_error.restype = c.c_char_p
         for f in ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness",
-                  "kpz_get_state", "kpz_set_state"):
+                  "kpz_get_state", "kpz_set_state", "kpz_batch_sizes", "kpz_batch_init",
+                  "kpz_batch_word_offset", "kpz_batch_sweep", "kpz_batch_roughness",
+                  "kpz_batch_run", "kpz_batch_get_t"):
             getattr(L, f).restype = c.c_int
         _lib = L
     return _lib
@@ -160,6 +178,98 @@ class Sim:
     def close(self) -> None:
         if self._h:
             lib().kpz_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_sizes(members) -> Tuple[int, int]:
+    arr = (kpz_params * len(members))(*members)
+    wb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    st = lib().kpz_batch_sizes(arr, len(members), ctypes.byref(wb), ctypes.byref(sb))
+    if st != KPZ_OK:
+        raise KPZError(st, "kpz_batch_sizes")
+    return wb.value, sb.value
+
+
+class Ensemble:
+    """n independent lattices on one GPU, advanced together by one
+    persistent launch per call.  ``members`` is a list of kpz_params (see
+    make_params); all must resolve to the same block shape."""
+
+    def __init__(self, members, device="cuda", stream=None):
+        import torch
+        self.members = list(members)
+        self.n = len(self.members)
+        self._arr = (kpz_params * self.n)(*self.members)
+        wb, sb = batch_sizes(self.members)
+        self.device = torch.device(device)
+        self.words = torch.empty(wb // 4, dtype=torch.int32, device=self.device)
+        self.workspace = torch.empty(sb, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = ctypes.c_void_p()
+        st = lib().kpz_batch_init(ctypes.byref(self._h), self._arr, self.n,
+                                  ctypes.c_void_p(self.words.data_ptr()), wb,
+                                  ctypes.c_void_p(self.workspace.data_ptr()), sb,
+                                  ctypes.c_void_p(self.stream.cuda_stream))
+        if st != KPZ_OK:
+            raise KPZError(st, "kpz_batch_init")
+
+    def _check(self, st, what):
+        if st != KPZ_OK:
+            raise KPZError(st, what, lib().kpz_batch_last_error(self._h).decode())
+
+    def sweep(self, n_mcs: int = 1) -> "Ensemble":
+        self._check(lib().kpz_batch_sweep(self._h, int(n_mcs)), "kpz_batch_sweep")
+        return self
+
+    def roughness(self):
+        import numpy as np
+        S1 = (ctypes.c_int64 * self.n)()
+        S2 = (ctypes.c_int64 * self.n)()
+        W2 = (ctypes.c_double * self.n)()
+        self._check(lib().kpz_batch_roughness(self._h, S1, S2, W2), "kpz_batch_roughness")
+        return np.array(S1[:], dtype=object), np.array(S2[:], dtype=object), np.array(W2[:])
+
+    def run(self, times):
+        """Sweep to each of the increasing MCS counts in ``times`` and sample
+        the moments there, as one captured HIP graph; returns arrays of shape
+        (len(times), n)."""
+        import numpy as np
+        k = len(times)
+        T = (ctypes.c_int32 * k)(*[int(t) for t in times])
+        S1 = (ctypes.c_int64 * (k * self.n))()
+        S2 = (ctypes.c_int64 * (k * self.n))()
+        W2 = (ctypes.c_double * (k * self.n))()
+        self._check(lib().kpz_batch_run(self._h, T, k, S1, S2, W2), "kpz_batch_run")
+        shape = (k, self.n)
+        return (np.array(S1[:], dtype=np.int64).reshape(shape),
+                np.array(S2[:], dtype=np.int64).reshape(shape),
+                np.array(W2[:]).reshape(shape))
+
+    @property
+    def t(self) -> int:
+        v = ctypes.c_int64()
+        self._check(lib().kpz_batch_get_t(self._h, ctypes.byref(v)), "kpz_batch_get_t")
+        return v.value
+
+    def member_words(self, r: int):
+        """Copy of member r's packed words, numpy uint32 of shape (L, L/16)."""
+        off = ctypes.c_size_t()
+        self._check(lib().kpz_batch_word_offset(self._h, int(r), ctypes.byref(off)),
+                    "kpz_batch_word_offset")
+        L = self.members[r].L
+        self.stream.synchronize()
+        w = self.words[off.value: off.value + L * L // 16]
+        return w.cpu().numpy().view("uint32").reshape(L, L // 16)
+
+    def close(self) -> None:
+        if self._h:
+            lib().kpz_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -1,0 +1,86 @@
+"""Block-shape autotuner for the sweep.
+
+The dead-border block shape (the device layer of the decomposition) is a
+free parameter of the method: any valid shape gives a correct decomposed
+schedule, but the shape changes the sequence of updates, so the chosen shape
+is returned and must be recorded with the results (runs are reproducible for
+identical parameters and shape only).  The tuner times each candidate with
+HIP events on the device and keeps the fastest; the launch shape (threads per
+block) is chosen by the library and does not affect results.
+"""
+from __future__ import annotations
+
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
+
+from . import Ensemble, KPZError, Sim, make_params, workspace_bytes
+
+# Candidate shapes (block_x, block_y): wide blocks keep the HBM rows
+# coalesced; areas from 64x64 to 256x256 keep the dead-border fraction
+# 1/Bx + 1/By at or below about 3 %.
+CANDIDATES: Tuple[Tuple[int, int], ...] = (
+    (256, 256), (512, 128), (1024, 64), (256, 128), (512, 64), (128, 128), (1024, 32),
+    (256, 64), (128, 64), (64, 64),
+)
+
+
+def valid_shapes(L: int, candidates: Iterable[Tuple[int, int]] = CANDIDATES) -> List[Tuple[int, int]]:
+    out = []
+    for bx, by in candidates:
+        if L % bx or L % by:
+            continue
+        try:
+            workspace_bytes(make_params(L, 1.0, 0.0, 1, (bx, by)))
+        except KPZError:
+            continue
+        out.append((bx, by))
+    return out
+
+
+def _time(fn, reps: int) -> float:
+    import torch
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()                      # warm-up (first launch of this kernel variant)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(reps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / reps
+
+
+def tune_lattice(L: int, p: float = 1.0, q: float = 0.0, mcs: int = 2,
+                 candidates: Optional[Sequence[Tuple[int, int]]] = None) -> Dict:
+    """Fastest block shape for one lattice of size L; returns
+    {"block": (bx, by), "ms_per_mcs": {shape: ms}}."""
+    shapes = valid_shapes(L, candidates or CANDIDATES)
+    if not shapes:
+        raise ValueError(f"no valid block shape for L={L}")
+    timings = {}
+    for shape in shapes:
+        sim = Sim(L, p, q, 12345, shape)
+        timings[shape] = _time(lambda: sim.sweep(mcs), 1) / mcs
+        sim.close()
+        del sim
+    best = min(timings, key=timings.get)
+    return {"block": best, "ms_per_mcs": timings}
+
+
+def tune_ensemble(members, mcs: int = 2,
+                  candidates: Optional[Sequence[Tuple[int, int]]] = None) -> Dict:
+    """Fastest common block shape for an ensemble (list of kpz_params with
+    block 0); returns {"block": (bx, by), "ms_per_mcs": {shape: ms}}."""
+    Lmin = min(m.L for m in members)
+    shapes = [s for s in valid_shapes(Lmin, candidates or CANDIDATES)
+              if all(m.L % s[0] == 0 and m.L % s[1] == 0 for m in members)]
+    if not shapes:
+        raise ValueError("no common block shape for the ensemble")
+    timings = {}
+    for shape in shapes:
+        ms = [make_params(m.L, m.p, m.q, m.seed, shape) for m in members]
+        ens = Ensemble(ms)
+        timings[shape] = _time(lambda: ens.sweep(mcs), 1) / mcs
+        ens.close()
+        del ens
+    best = min(timings, key=timings.get)
+    return {"block": best, "ms_per_mcs": timings}

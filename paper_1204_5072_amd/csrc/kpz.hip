@@ -41,9 +41,11 @@
 
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "kpz.h"
 
@@ -53,7 +55,6 @@ constexpr uint32_t TAG_ORIGIN = 1, TAG_SET = 2, TAG_SITE = 3, TAG_ACC1 = 4, TAG_
 constexpr int NSLOTS = 1024;          // flip-counter slots in the workspace
 constexpr int WS_HEADER = 256;        // results area at the start of the workspace
 constexpr int TILE = 4;               // tile edge (sites)
-constexpr int STEPS = TILE * TILE;    // single-hit steps per MCS
 
 // ------------------------------------------------------------------ Philox
 
@@ -126,28 +127,180 @@ __global__ void kpz_fill_counters_kernel(long long *slots, long long first)
 
 struct SweepArgs {
     uint32_t *words;
+    uint32_t *side;              // [2][L][nbx]: straddling-word parts (left edge, right edge)
     unsigned long long *slots;   // NSLOTS flip counters
     uint32_t L, W;               // size, words per row
     uint32_t Bx, By;             // block shape
     uint32_t nbx, nby;           // blocks per direction
     uint32_t ntx, log2ntx;       // tiles per block row
-    uint32_t H;                  // tile rows per quad row (nty / 4)
+    uint32_t H, log2H;           // quad rows per plane (nty / 4)
     uint32_t nq;                 // quads per plane
-    uint32_t nw;                 // aligned words per block row (Bx / 16)
-    uint32_t units;              // load/store units per block
+    uint32_t nw, log2nw;         // aligned words per block row (Bx / 16)
+    uint32_t units;              // load/store units per block (nq / 2)
     uint32_t seed_lo, seed_hi;
     uint32_t t;
+    uint32_t slot_mask;          // flip-counter slots - 1 (power of two)
+    uint32_t acc;                // 1 unless P = 2^32 and Q = 0 (acceptance draws needed)
     uint64_t P, Q;               // acceptance thresholds over 2^32
 };
 
-template <int K, bool ACC>
-__global__ __launch_bounds__(64) void kpz_sweep_kernel(const SweepArgs a)
+// Quad q = tid + TPB i (tid = thread in the block) has tile column
+// qx = q mod ntx and quad row qy = q / ntx.  With NTX (= ntx) known at
+// compile time both tests below fold to constants or a single lane compare.
+template <int TPB, int NTX>
+__device__ __forceinline__ bool quad_left_edge(uint32_t tid, int i, const SweepArgs &a)
 {
-    extern __shared__ uint32_t lds[];
-    const uint32_t lane = threadIdx.x;
-    const uint32_t b = blockIdx.x;
+    if constexpr (NTX >= TPB) return (i % (NTX / TPB)) == 0 && tid == 0;
+    else if constexpr (NTX > 0) return (tid & (NTX - 1)) == 0;
+    else return ((tid + (uint32_t)TPB * i) & (a.ntx - 1)) == 0;
+}
+
+template <int TPB, int NTX>
+__device__ __forceinline__ bool quad_bottom_row(uint32_t tid, int i, const SweepArgs &a)
+{
+    if constexpr (NTX >= TPB) return i < NTX / TPB;
+    else if constexpr (NTX > 0) return i == 0 && tid < (uint32_t)NTX;
+    else return tid + (uint32_t)TPB * i < a.ntx;
+}
+
+// Byte-wise helpers for the acceptance test of four tiles at once.
+__device__ __forceinline__ uint32_t byte_lt(uint32_t A, uint32_t c)
+{
+    // 0x80 in every byte of A that is below c (c in [1, 255]): 9-bit
+    // differences (a | 0x100) - c in 16-bit lanes have bit 8 clear iff a < c
+    const uint32_t cc = c * 0x00010001u;
+    const uint32_t even = ((A & 0x00FF00FFu) | 0x01000100u) - cc;
+    const uint32_t odd = (((A >> 8) & 0x00FF00FFu) | 0x01000100u) - cc;
+    const uint32_t ge = ((even >> 1) & 0x00800080u) | ((odd << 7) & 0x80008000u);
+    return ~ge & 0x80808080u;
+}
+
+__device__ __forceinline__ uint32_t byte_eq(uint32_t A, uint32_t c)
+{
+    // 0x80 in every byte of A equal to c
+    const uint32_t z = A ^ (c * 0x01010101u);
+    return ~(((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z) & 0x80808080u;
+}
+
+__device__ __forceinline__ uint32_t bytes_nonzero(uint32_t F)
+{
+    // F has at most one bit per byte, at position 0, 2, 4 or 6
+    return (F + 0x7F7F7F7Fu) & 0x80808080u;
+}
+
+__device__ __forceinline__ uint32_t expand_bit7(uint32_t m7)
+{
+    const uint32_t m = m7 >> 7;
+    return (m << 8) - m;
+}
+
+struct AccCtx {
+    bool fullP;          // P = 2^32: every minimum is accepted
+    uint32_t tP, tQ;     // top bytes of P and Q
+    uint32_t lowP, lowQ; // low 24 bits of P and Q
+};
+
+// One single-hit attempt in each of the four tiles of a quad.  ca, la, da:
+// LDS indices of the quad's own cells (set s), the cells to the left (set
+// s^1) and the cells below (set s^2).
+template <int SX, int SY, bool ACC>
+__device__ __forceinline__ void quad_update(uint32_t *lds, uint32_t ca, uint32_t la, uint32_t da,
+                                            uint32_t rot, uint32_t D, uint32_t dm, bool lok,
+                                            uint32_t Aw, const AccCtx &ac, uint64_t G, uint32_t k,
+                                            const SweepArgs &a, int &net)
+{
+    const uint32_t c = lds[ca];
+    const uint32_t l = lds[la];
+    const uint32_t d = SY ? lds[da] : rotr(lds[da], rot);
+    // one-hot sigma_x position 2r of each tile's chosen site
+    const uint32_t oh = __builtin_amdgcn_perm(0u, 0x40100401u, D) & ~dm;
+    // neighbour slopes moved onto each site's own bit positions:
+    // sigma_x(x-1,y) at 2r, sigma_y(x,y-1) at 2r+1
+    const uint32_t X = ((c << 2) & 0x44444444u) | ((l >> 2) & 0x11111111u);
+    const uint32_t Y = ((c << 4) & 0xA0A0A0A0u) | ((d >> 4) & 0x0A0A0A0Au);
+    const uint32_t N = X | Y;
+    // minimum: own slopes (+1,+1), incoming slopes (-1,-1)
+    const uint32_t zmin = c & ~N;
+    uint32_t F = zmin & (zmin >> 1) & oh;
+    if (ACC) {
+        // maximum: own slopes (-1,-1), incoming slopes (+1,+1)
+        const uint32_t zmax = N & ~c;
+        const uint32_t Fx = zmax & (zmax >> 1) & oh;
+        const uint32_t mn = bytes_nonzero(F), mx = bytes_nonzero(Fx);
+        const uint32_t accP = ac.fullP ? 0x80808080u : (ac.tP ? byte_lt(Aw, ac.tP) : 0u);
+        const uint32_t accQ = ac.tQ ? byte_lt(Aw, ac.tQ) : 0u;
+        uint32_t keep7 = (mn & accP) | (mx & accQ);
+        const uint32_t tieP = (!ac.fullP && ac.lowP) ? (mn & byte_eq(Aw, ac.tP)) : 0u;
+        const uint32_t tieQ = ac.lowQ ? (mx & byte_eq(Aw, ac.tQ)) : 0u;
+        if (__any((tieP | tieQ) != 0)) {
+            const U4 w2 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t, (TAG_ACC2 << 24) | k,
+                                 a.seed_lo, a.seed_hi);
+            const uint32_t Bw[4] = {w2.x, w2.y, w2.z, w2.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t b24 = Bw[j] & 0xFFFFFFu;
+                if (((tieP >> (8 * j + 7)) & 1u) && b24 < ac.lowP) keep7 |= 0x80u << (8 * j);
+                if (((tieQ >> (8 * j + 7)) & 1u) && b24 < ac.lowQ) keep7 |= 0x80u << (8 * j);
+            }
+        }
+        const uint32_t keep = expand_bit7(keep7);
+        const uint32_t fmin = F & keep, fmax = Fx & keep;
+        net += __builtin_popcount(fmin) - __builtin_popcount(fmax);
+        F = fmin | fmax;
+    } else {
+        net += __builtin_popcount(F);
+    }
+    // flip: own sigma_x, sigma_y; sigma_x of the left site; sigma_y of the lower site
+    const uint32_t mc = F | (F << 1) | ((F >> 2) & 0x11111111u) | ((F >> 3) & 0x0A0A0A0Au);
+    const uint32_t ml = (F & 0x11111111u) << 2;
+    const uint32_t md = (F & 0x05050505u) << 5;
+    lds[ca] = c ^ mc;
+    if (SX || lok) lds[la] = l ^ ml;
+    lds[da] = SY ? (d ^ md) : rotr(d ^ md, (32u - rot) & 31u);
+}
+
+// All quads of this thread for one step with cell set (SX, SY).
+template <int TPB, int K, int NTX, int SX, int SY, bool ACC>
+__device__ __forceinline__ void step_quads(uint32_t *lds, uint32_t tid, uint32_t kr,
+                                           const uint32_t (&sw)[K][4], const uint32_t (&aw)[K][4],
+                                           const AccCtx &ac, uint64_t Gbase, uint32_t k,
+                                           const SweepArgs &a, int &net)
+{
+    constexpr uint32_t S = SX + 2 * SY;
+    const uint32_t ntx = NTX ? (uint32_t)NTX : a.ntx;
+    const uint32_t nq = NTX ? (uint32_t)NTX * a.H : a.nq;
+    const uint32_t pc = S * nq, pl = (S ^ 1u) * nq, pd = (S ^ 2u) * nq;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const uint32_t q = tid + (uint32_t)TPB * i;
+        const bool ledge = SX ? false : quad_left_edge<TPB, NTX>(tid, i, a);
+        const bool bottom = SY ? false : quad_bottom_row<TPB, NTX>(tid, i, a);
+        // left quad (tile tx-1) for sx = 0: q-1, or the wrap-around quad of
+        // a single periodic block, or (dead left edge) the quad itself,
+        // which is then only read
+        const uint32_t lq = SX ? q : (ledge ? (a.nbx == 1 ? q + ntx - 1 : q) : q - 1);
+        // lower quad (tile ty-1) for sy = 0: q - ntx, or for the bottom quad
+        // row the top quad row, one byte down
+        const uint32_t dq = SY ? q : (bottom ? q + (a.H - 1) * ntx : q - ntx);
+        const uint32_t rot = bottom ? 24u : 0u;
+        const uint32_t dm = (ledge && a.nbx > 1 ? 0x11111111u : 0u) |
+                            (bottom && a.nby > 1 ? 0x00000005u : 0u);
+        const bool lok = !ledge || a.nbx == 1;
+        const uint32_t D = (sw[i][0] >> (2 * kr)) & 0x03030303u;
+        quad_update<SX, SY, ACC>(lds, pc + q, pl + lq, pd + dq, rot, D, dm, lok,
+                                 ACC ? aw[i][0] : 0u, ac, Gbase + q, k, a, net);
+    }
+}
+
+// One MCS of dead-border block b (device layer) with the block in LDS.
+template <int TPB, int K, int NTX, bool ACC>
+__device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint32_t *lds)
+{
+    const uint32_t tid = threadIdx.x;
     const uint32_t bx = b % a.nbx, by = b / a.nbx;
-    const uint32_t nq = a.nq;
+    const uint32_t ntx = NTX ? (uint32_t)NTX : a.ntx;
+    const uint32_t nq = NTX ? (uint32_t)NTX * a.H : a.nq;
+    const uint32_t nw = ntx / 4;
 
     // device layer: origin of this MCS, then this block's frame
     const U4 wo = philox(0u, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
@@ -160,14 +313,19 @@ __global__ __launch_bounds__(64) void kpz_sweep_kernel(const SweepArgs a)
     const uint32_t sh2 = 2u * (gx0 & 15u);
     const uint32_t gw0 = gx0 >> 4;
 
-    uint32_t *edge = lds + 4 * nq;   // [2][By]: original first / last aligned word of each row
-
-    // ---- load: HBM row words -> aligned block words -> cells -> quads
-    for (uint32_t u = lane; u < a.units; u += 64) {
-        const uint32_t wx = u % a.nw;
-        const uint32_t rest = u / a.nw;
-        const uint32_t qy = rest % a.H;
-        const uint32_t sy = rest / a.H;
+    // ---- load: HBM row words -> aligned block words -> cells -> quads.
+    // Unit u = (wx, qy, sy): aligned word column wx of the two rows of cell
+    // row sy in the tile rows qy + j H, j = 0..3.  The nw units of one row
+    // group sit in consecutive lanes of one wave (nw divides 64), so the next
+    // word of a row comes from the next lane.
+    constexpr int UIT = (K * TPB / 2 + TPB - 1) / TPB;
+    for (int it = 0; it < UIT; ++it) {
+        const uint32_t u = tid + (uint32_t)TPB * it;
+        const bool uok = u < a.units;
+        const uint32_t wx = u & (nw - 1);
+        const uint32_t rest = u >> a.log2nw;
+        const uint32_t qy = rest & (a.H - 1);
+        const uint32_t sy = rest >> a.log2H;
         uint32_t gw = gw0 + wx;
         if (gw >= a.W) gw -= a.W;
         const uint32_t gw1 = gw + 1 == a.W ? 0 : gw + 1;
@@ -181,140 +339,82 @@ __global__ __launch_bounds__(64) void kpz_sweep_kernel(const SweepArgs a)
                 uint32_t gy = gy0 + r0 + h;
                 if (gy >= a.L) gy -= a.L;
                 const uint32_t *row = a.words + (size_t)gy * a.W;
-                const uint32_t lo = row[gw];
-                const uint32_t hi = sh2 ? row[gw1] : 0u;
+                const uint32_t lo = uok ? row[gw] : 0u;
+                uint32_t hi = __shfl_down(lo, 1, 64);
+                if (uok && wx == nw - 1 && sh2) hi = row[gw1];
                 A[h] = __builtin_amdgcn_alignbit(hi, lo, sh2);
-                if (wx == 0) edge[r0 + h] = A[h];
-                if (wx == a.nw - 1) edge[a.By + r0 + h] = A[h];
             }
             E[j] = (A[0] & 0x0F0F0F0Fu) | ((A[1] & 0x0F0F0F0Fu) << 4);
             O[j] = ((A[0] >> 4) & 0x0F0F0F0Fu) | (A[1] & 0xF0F0F0F0u);
         }
         transpose_bytes(E);
         transpose_bytes(O);
-        const uint32_t q0 = qy * a.ntx + 4 * wx;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            lds[(2 * sy) * nq + q0 + m] = E[m];
-            lds[(2 * sy + 1) * nq + q0 + m] = O[m];
+        if (uok) {
+            const uint32_t q0 = qy * ntx + 4 * wx;
+            *(uint4 *)(lds + (2 * sy) * nq + q0) = make_uint4(E[0], E[1], E[2], E[3]);
+            *(uint4 *)(lds + (2 * sy + 1) * nq + q0) = make_uint4(O[0], O[1], O[2], O[3]);
         }
     }
 
-    // ---- per-quad constants and random words of this MCS
-    uint32_t own[K], lft[K], dwn[K], rl[K], dmx[K], dmy[K], sw[K][4];
-    bool lok[K], valid[K];
+    // ---- site draws of this MCS for this thread's quads
+    const uint64_t Gbase = (uint64_t)b * nq;
+    uint32_t sw[K][4];
+    uint32_t aw[K][4];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        const uint32_t q = lane + 64u * i;
-        valid[i] = q < nq;
-        const uint32_t qx = q & (a.ntx - 1), qy = q >> a.log2ntx;
-        own[i] = q;
-        // left neighbour quad for set sx = 0 (tile tx-1); wraps if one block per row
-        lok[i] = qx > 0 || a.nbx == 1;
-        lft[i] = qx > 0 ? q - 1 : (a.nbx == 1 ? q + a.ntx - 1 : q);
-        // lower neighbour quad for set sy = 0 (tile ty-1): for qy = 0 it is the
-        // last quad row, shifted by one byte
-        dwn[i] = qy > 0 ? q - a.ntx : q + (a.H - 1) * a.ntx;
-        rl[i] = qy > 0 ? 0u : 24u;
-        // dead border: local x = 0 (rx = 0 sites of tiles tx = 0), local y = 0
-        // (ry = 0 sites of tile ty = 0, i.e. byte 0 of quad row 0)
-        dmx[i] = (qx == 0 && a.nbx > 1) ? 0x11111111u : 0u;
-        dmy[i] = (qy == 0 && a.nby > 1) ? 0x00000005u : 0u;
-        const uint64_t G = (uint64_t)b * nq + q;
+        const uint64_t G = Gbase + tid + (uint32_t)TPB * i;
         const U4 s4 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t, TAG_SITE << 24, a.seed_lo,
                              a.seed_hi);
         sw[i][0] = s4.x;
         sw[i][1] = s4.y;
         sw[i][2] = s4.z;
         sw[i][3] = s4.w;
+        aw[i][0] = aw[i][1] = aw[i][2] = aw[i][3] = 0u;
     }
     const uint32_t setw = philox(b, 0u, a.t, TAG_SET << 24, a.seed_lo, a.seed_hi).x;
+    AccCtx ac;
+    ac.fullP = a.P >= (1ull << 32);
+    ac.tP = ac.fullP ? 256u : (uint32_t)(a.P >> 24);
+    ac.tQ = (uint32_t)(a.Q >> 24);
+    ac.lowP = (uint32_t)(a.P & 0xFFFFFFu);
+    ac.lowQ = (uint32_t)(a.Q & 0xFFFFFFu);
+    const bool active = K * TPB == (int)nq || tid < nq;
     int net = 0;
 
     __syncthreads();
 
-    // ---- work-group layer: 16 single-hit steps k = 4 kq + kr; sw[i][0] holds
-    // the site word of the current group of four steps
+    // ---- work-group layer: 16 single-hit steps k = 4 kq + kr
     for (int kq = 0; kq < 4; ++kq) {
-        for (int kr = 0; kr < 4; ++kr) {
-            const int k = 4 * kq + kr;
-            const uint32_t s = (setw >> (2 * k)) & 3u;
-            const bool sx = s & 1u, sy = s >> 1;
-            const uint32_t pc = s * nq, pl = (s ^ 1u) * nq, pd = (s ^ 2u) * nq;
+        if (ACC) {
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                if (K == 1 && !valid[i]) continue;
-                const uint32_t ca = pc + own[i];
-                const uint32_t la = pl + (sx ? own[i] : lft[i]);
-                const uint32_t da = pd + (sy ? own[i] : dwn[i]);
-                const uint32_t rot = sy ? 0u : rl[i];
-                const uint32_t c = lds[ca];
-                const uint32_t l = lds[la];
-                const uint32_t d = rotr(lds[da], rot);
-                // site of each tile's cell: r = 2 ry + rx in byte j
-                const uint32_t D = (sw[i][0] >> (2 * kr)) & 0x03030303u;
-                // one-hot sigma_x position 2r of the chosen site in every byte
-                uint32_t oh = __builtin_amdgcn_perm(0u, 0x40100401u, D);
-                oh &= ~((sx ? 0u : dmx[i]) | (sy ? 0u : dmy[i]));
-                // neighbour slopes moved onto each site's own bit positions:
-                // sigma_x(x-1,y) at 2r, sigma_y(x,y-1) at 2r+1
-                const uint32_t X = ((c << 2) & 0x44444444u) | ((l >> 2) & 0x11111111u);
-                const uint32_t Y = ((c << 4) & 0xA0A0A0A0u) | ((d >> 4) & 0x0A0A0A0Au);
-                const uint32_t N = X | Y;
-                // minimum: own slopes (+1,+1), incoming slopes (-1,-1)
-                const uint32_t zmin = c & ~N;
-                uint32_t F = zmin & (zmin >> 1) & oh;
-                if (ACC) {
-                    // maximum: own slopes (-1,-1), incoming slopes (+1,+1)
-                    const uint32_t zmax = N & ~c;
-                    const uint32_t Fx = zmax & (zmax >> 1) & oh;
-                    uint32_t keep = 0;
-                    if (__any((F | Fx) != 0)) {
-                        const uint64_t G = (uint64_t)b * nq + own[i];
-                        const U4 w1 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t,
-                                             (TAG_ACC1 << 24) | (uint32_t)kq, a.seed_lo,
-                                             a.seed_hi);
-                        const uint32_t Aw = kr == 0 ? w1.x : kr == 1 ? w1.y : kr == 2 ? w1.z : w1.w;
-                        uint32_t tie = 0;
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const bool is_min = (F >> (8 * j)) & 0xFFu;
-                            const bool is_max = (Fx >> (8 * j)) & 0xFFu;
-                            const uint64_t thr = is_min ? a.P : a.Q;
-                            const uint32_t Aj = (Aw >> (8 * j)) & 0xFFu;
-                            const uint32_t t8 = (uint32_t)(thr >> 24);   // 256 for thr = 2^32
-                            if ((is_min || is_max) && thr != 0) {
-                                if (Aj < t8) keep |= 0xFFu << (8 * j);
-                                else if (Aj == t8 && (thr & 0xFFFFFFu)) tie |= 1u << j;
-                            }
-                        }
-                        if (__any(tie != 0)) {
-                            const U4 w2 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t,
-                                                 (TAG_ACC2 << 24) | (uint32_t)k, a.seed_lo,
-                                                 a.seed_hi);
-                            const uint32_t Bw[4] = {w2.x, w2.y, w2.z, w2.w};
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) {
-                                const bool is_min = (F >> (8 * j)) & 0xFFu;
-                                const uint64_t thr = is_min ? a.P : a.Q;
-                                if ((tie >> j) & 1u && (Bw[j] & 0xFFFFFFu) < (uint32_t)(thr & 0xFFFFFFu))
-                                    keep |= 0xFFu << (8 * j);
-                            }
-                        }
-                    }
-                    const uint32_t fmin = F & keep, fmax = Fx & keep;
-                    net += __builtin_popcount(fmin) - __builtin_popcount(fmax);
-                    F = fmin | fmax;
-                } else {
-                    net += __builtin_popcount(F);
+                const uint64_t G = Gbase + tid + (uint32_t)TPB * i;
+                const U4 w1 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t,
+                                     (TAG_ACC1 << 24) | (uint32_t)kq, a.seed_lo, a.seed_hi);
+                aw[i][0] = w1.x;
+                aw[i][1] = w1.y;
+                aw[i][2] = w1.z;
+                aw[i][3] = w1.w;
+            }
+        }
+        for (uint32_t kr = 0; kr < 4; ++kr) {
+            const uint32_t k = 4u * kq + kr;
+            const uint32_t s = (setw >> (2 * k)) & 3u;
+            if (active) {
+                switch (s) {
+                case 0: step_quads<TPB, K, NTX, 0, 0, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
+                case 1: step_quads<TPB, K, NTX, 1, 0, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
+                case 2: step_quads<TPB, K, NTX, 0, 1, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
+                default: step_quads<TPB, K, NTX, 1, 1, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
                 }
-                // flip: own sigma_x, sigma_y; sigma_x of the left site; sigma_y of the lower site
-                const uint32_t mc = F | (F << 1) | ((F >> 2) & 0x11111111u) | ((F >> 3) & 0x0A0A0A0Au);
-                const uint32_t ml = (F & 0x11111111u) << 2;
-                const uint32_t md = (F & 0x05050505u) << 5;
-                lds[ca] = c ^ mc;
-                if (sx || lok[i]) lds[la] = l ^ ml;
-                lds[da] = rotr(d ^ md, (32u - rot) & 31u);
+            }
+            if (ACC) {
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    aw[i][0] = aw[i][1];
+                    aw[i][1] = aw[i][2];
+                    aw[i][2] = aw[i][3];
+                }
             }
             __syncthreads();
         }
@@ -326,25 +426,29 @@ __global__ __launch_bounds__(64) void kpz_sweep_kernel(const SweepArgs a)
         }
     }
 
-    // ---- store: quads -> cells -> aligned block words -> HBM row words
-    for (uint32_t u = lane; u < a.units; u += 64) {
-        const uint32_t wx = u % a.nw;
-        const uint32_t rest = u / a.nw;
-        const uint32_t qy = rest % a.H;
-        const uint32_t sy = rest / a.H;
-        const uint32_t q0 = qy * a.ntx + 4 * wx;
-        uint32_t E[4], O[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            E[m] = lds[(2 * sy) * nq + q0 + m];
-            O[m] = lds[(2 * sy + 1) * nq + q0 + m];
+    // ---- store: quads -> cells -> aligned block words -> HBM row words.
+    // Words wholly inside the block are stored; the block's parts of the two
+    // words it shares with its left and right neighbours go to the side
+    // buffer and are merged by kpz_merge_kernel.
+    for (int it = 0; it < UIT; ++it) {
+        const uint32_t u = tid + (uint32_t)TPB * it;
+        const bool uok = u < a.units;
+        const uint32_t wx = u & (nw - 1);
+        const uint32_t rest = u >> a.log2nw;
+        const uint32_t qy = rest & (a.H - 1);
+        const uint32_t sy = rest >> a.log2H;
+        const uint32_t q0 = qy * ntx + 4 * wx;
+        uint32_t E[4] = {0u, 0u, 0u, 0u}, O[4] = {0u, 0u, 0u, 0u};
+        if (uok) {
+            const uint4 e = *(const uint4 *)(lds + (2 * sy) * nq + q0);
+            const uint4 o = *(const uint4 *)(lds + (2 * sy + 1) * nq + q0);
+            E[0] = e.x; E[1] = e.y; E[2] = e.z; E[3] = e.w;
+            O[0] = o.x; O[1] = o.y; O[2] = o.z; O[3] = o.w;
         }
         transpose_bytes(E);
         transpose_bytes(O);
         uint32_t gw = gw0 + wx;
         if (gw >= a.W) gw -= a.W;
-        uint32_t gwe = gw0 + a.nw;
-        if (gwe >= a.W) gwe -= a.W;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t r0 = 4 * (qy + j * a.H) + 2 * sy;
@@ -356,130 +460,222 @@ __global__ __launch_bounds__(64) void kpz_sweep_kernel(const SweepArgs a)
                 uint32_t gy = gy0 + r0 + h;
                 if (gy >= a.L) gy -= a.L;
                 uint32_t *row = a.words + (size_t)gy * a.W;
-                // aligned word of the left neighbour unit (same row)
                 const uint32_t prev = __shfl_up(A[h], 1, 64);
+                if (!uok) continue;
                 if (sh2 == 0) {
                     row[gw] = A[h];
                 } else {
-                    if (wx == 0) {
-                        const uint32_t delta = (A[h] ^ edge[r0 + h]) << sh2;
-                        if (delta) atomicXor(row + gw, delta);
-                    } else {
-                        row[gw] = __builtin_amdgcn_alignbit(A[h], prev, 32u - sh2);
-                    }
-                    if (wx == a.nw - 1) {
-                        const uint32_t delta = (A[h] ^ edge[a.By + r0 + h]) >> (32u - sh2);
-                        if (delta) atomicXor(row + gwe, delta);
-                    }
+                    if (wx > 0) row[gw] = __builtin_amdgcn_alignbit(A[h], prev, 32u - sh2);
+                    else a.side[(size_t)gy * a.nbx + bx] = A[h] << sh2;
+                    if (wx == nw - 1)
+                        a.side[((size_t)a.L + gy) * a.nbx + bx] = A[h] >> (32u - sh2);
                 }
             }
         }
     }
 
-    // ---- flip counter of this block
+    // ---- flip counter of this block: wave sums, one atomic per wave
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) net += __shfl_xor(net, off, 64);
-    if (lane == 0 && net != 0)
-        atomicAdd(a.slots + (b & (NSLOTS - 1)), (unsigned long long)(long long)net);
+    if ((tid & 63u) == 0 && net != 0)
+        atomicAdd(a.slots + ((b * (TPB / 64) + tid / 64) & a.slot_mask),
+                  (unsigned long long)(long long)net);
+}
+
+template <int TPB, int K, int NTX, bool ACC>
+__global__ __launch_bounds__(TPB) void kpz_sweep_kernel(const SweepArgs a)
+{
+    extern __shared__ uint32_t lds[];
+    sweep_block<TPB, K, NTX, ACC>(a, blockIdx.x, lds);
+}
+
+// Straddling words of MCS a.t: the word at the left edge of block column bx
+// in row gy holds the last sites of block bx-1 (low bits) and the first
+// sites of block bx (high bits); both parts were written to the side buffer.
+__device__ __forceinline__ void merge_straddles(const SweepArgs &a, uint64_t first, uint64_t stride)
+{
+    const U4 wo = philox(0u, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
+    const uint32_t ox = (uint32_t)(((uint64_t)wo.x * a.Bx) >> 32);
+    if ((ox & 15u) == 0) return;
+    const uint64_t n = (uint64_t)a.L * a.nbx;
+    for (uint64_t i = first; i < n; i += stride) {
+        const uint32_t gy = (uint32_t)(i / a.nbx), bx = (uint32_t)(i % a.nbx);
+        uint32_t gw = (ox >> 4) + bx * a.nw;
+        if (gw >= a.W) gw -= a.W;
+        const uint32_t left = a.side[((size_t)a.L + gy) * a.nbx + (bx == 0 ? a.nbx - 1 : bx - 1)];
+        const uint32_t right = a.side[(size_t)gy * a.nbx + bx];
+        a.words[(size_t)gy * a.W + gw] = left | right;
+    }
+}
+
+__global__ void kpz_merge_kernel(const SweepArgs a)
+{
+    merge_straddles(a, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x,
+                    (uint64_t)gridDim.x * blockDim.x);
 }
 
 // ------------------------------------------------------------ roughness
 
 // Per row y: with P(x) = sum_{l<x} sigma_x(l,y) (height relative to the row
 // start), A_y = sum_x P(x) and B_y = sum_x P(x)^2.  One wave per row.
-__global__ __launch_bounds__(256) void kpz_row_moments_kernel(const uint32_t *words, uint32_t L,
-                                                              uint32_t W, long long *rowA,
-                                                              long long *rowB)
+//
+// A word's 16 sigma_x bits are compacted into two bytes of 8 sites; a
+// 256-entry LDS table gives, for 8 sites with local prefix p_k (k = 0..7),
+// d = p_8, a = sum p_k and c = sum p_k^2.  Each lane takes four consecutive
+// words (one 16-byte load); one wave scan per 256 words places the lanes.
+__device__ __forceinline__ uint32_t lut8_entry(uint32_t byte)
 {
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t row = blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (row >= L) return;
-    const uint32_t *rp = words + (size_t)row * W;
+    int p = 0, a = 0, c = 0;
+    for (int i = 0; i < 8; ++i) {
+        a += p;
+        c += p * p;
+        p += ((byte >> i) & 1u) ? 1 : -1;
+    }
+    // d + 8 in bits 0..4, a + 28 in bits 5..10, c in bits 11..18
+    return (uint32_t)(p + 8) | ((uint32_t)(a + 28) << 5) | ((uint32_t)c << 11);
+}
+
+struct WordSums {
+    int d, s1, s2;   // increment, sum of prefixes, sum of squared prefixes (16 sites)
+};
+
+__device__ __forceinline__ WordSums word_sums(uint32_t w, const uint32_t *lut)
+{
+    uint32_t x = w & 0x55555555u;              // sigma_x of site i at bit 2i
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+    x = (x | (x >> 4)) & 0x00FF00FFu;          // sites 0..7 in byte 0, 8..15 in byte 2
+    const uint32_t e0 = lut[x & 0xFFu], e1 = lut[(x >> 16) & 0xFFu];
+    const int d0 = (int)(e0 & 31u) - 8, a0 = (int)((e0 >> 5) & 63u) - 28, c0 = (int)(e0 >> 11);
+    const int d1 = (int)(e1 & 31u) - 8, a1 = (int)((e1 >> 5) & 63u) - 28, c1 = (int)(e1 >> 11);
+    WordSums r;
+    r.d = d0 + d1;
+    r.s1 = a0 + 8 * d0 + a1;
+    r.s2 = c0 + 8 * d0 * d0 + 2 * d0 * a1 + c1;
+    return r;
+}
+
+// Moments of one row (one wave): returns (A_y, B_y) in lane 0.
+__device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, const uint32_t *lut,
+                                            uint32_t lane, long long &A, long long &B)
+{
+    const bool vec = (W & 3u) == 0;
     long long s1 = 0, s2 = 0;
-    int carry = 0;
-    for (uint32_t base = 0; base < W; base += 64) {
-        const uint32_t idx = base + lane;
-        const bool ok = idx < W;
-        const uint32_t w = ok ? rp[idx] : 0u;
-        int cur = 0, p1 = 0, p2 = 0;
-        if (ok) {
+    long long carry = 0;
+    for (uint32_t base = 0; base < W; base += 256) {
+        const uint32_t idx = base + 4 * lane;
+        uint32_t v[4] = {0u, 0u, 0u, 0u};
+        int nv = 0;
+        if (vec) {
+            if (idx < W) {
+                const uint4 q = *(const uint4 *)(rp + idx);
+                v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+                nv = 4;
+            }
+        } else {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                p1 += cur;
-                p2 += cur * cur;
-                cur += ((w >> (2 * k)) & 1u) ? 1 : -1;
+            for (int m = 0; m < 4; ++m)
+                if (idx + m < W) { v[m] = rp[idx + m]; nv = m + 1; }
+        }
+        // this lane's words relative to its own start
+        int o = 0;
+        long long l1 = 0, l2 = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            if (m < nv) {
+                const WordSums ws = word_sums(v[m], lut);
+                l1 += 16 * o + ws.s1;
+                l2 += (long long)(16 * o) * o + 2LL * o * ws.s1 + ws.s2;
+                o += ws.d;
             }
         }
-        // exclusive prefix of the word increments across the wave
-        int incl = cur;
+        // lane offsets within the chunk: exclusive scan of o
+        int incl = o;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            const int v = __shfl_up(incl, off, 64);
-            if ((int)lane >= off) incl += v;
+            const int t = __shfl_up(incl, off, 64);
+            if ((int)lane >= off) incl += t;
         }
-        const int total = __shfl(incl, 63, 64);
-        const long long o = carry + incl - cur;
-        if (ok) {
-            s1 += 16 * o + p1;
-            s2 += 16 * o * o + 2 * o * p1 + p2;
-        }
-        carry += total;
+        const long long c = carry + incl - o;
+        const long long n = 16LL * nv;
+        s1 += n * c + l1;
+        s2 += n * c * c + 2 * c * l1 + l2;
+        carry += __shfl(incl, 63, 64);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         s1 += __shfl_xor(s1, off, 64);
         s2 += __shfl_xor(s2, off, 64);
     }
-    if (lane == 0) {
-        rowA[row] = s1;
-        rowB[row] = s2;
+    A = s1;
+    B = s2;
+}
+
+__global__ __launch_bounds__(256) void kpz_row_moments_kernel(const uint32_t *words, uint32_t L,
+                                                              uint32_t W, long long *rowA,
+                                                              long long *rowB)
+{
+    __shared__ uint32_t lut[256];
+    lut[threadIdx.x] = lut8_entry(threadIdx.x);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint32_t row = blockIdx.x * 4u + (threadIdx.x >> 6); row < L; row += gridDim.x * 4u) {
+        long long A, B;
+        row_moments(words + (size_t)row * W, W, lut, lane, A, B);
+        if (lane == 0) {
+            rowA[row] = A;
+            rowB[row] = B;
+        }
     }
 }
 
-// One work-group of 1024 threads: c_y = sum_{k<y} sigma_y(0,k) (column-0
+// One work-group of NT threads: c_y = sum_{k<y} sigma_y(0,k) (column-0
 // heights), R1 = sum_y (L c_y + A_y), R2 = sum_y (L c_y^2 + 2 c_y A_y + B_y)
 // in 128-bit, and the sum of the flip-counter slots.
-__global__ __launch_bounds__(1024) void kpz_finalize_kernel(const uint32_t *words, uint32_t L,
-                                                            uint32_t W, const long long *rowA,
-                                                            const long long *rowB,
-                                                            const long long *slots,
-                                                            long long *res)
+template <int NT>
+__device__ __forceinline__ void finalize_moments(const uint32_t *words, uint32_t L, uint32_t W,
+                                                 const long long *rowA, const long long *rowB,
+                                                 const long long *slots, uint32_t nslots,
+                                                 long long *res)
 {
-    __shared__ long long sc[1024];
-    __shared__ __int128 r2s[1024];
-    __shared__ long long r1s[1024];
-    __shared__ long long ns[1024];
+    __shared__ long long sc[NT];
+    __shared__ __int128 r2s[NT];
+    __shared__ long long r1s[NT];
+    __shared__ long long ns[NT];
     const uint32_t tid = threadIdx.x;
-    const uint32_t per = (L + 1023) / 1024;
-    const uint32_t y0 = tid * per;
+    const uint32_t per = (L + NT - 1) / NT;
+    const uint32_t y0 = min(L, tid * per);
     const uint32_t y1 = min(L, y0 + per);
     long long loc = 0;
     for (uint32_t y = y0; y < y1; ++y) loc += ((words[(size_t)y * W] >> 1) & 1u) ? 1 : -1;
     sc[tid] = loc;
     __syncthreads();
-    // inclusive Hillis-Steele scan over the 1024 thread sums
-    for (uint32_t off = 1; off < 1024; off <<= 1) {
+    // inclusive Hillis-Steele scan over the thread sums
+    for (uint32_t off = 1; off < NT; off <<= 1) {
         const long long v = tid >= off ? sc[tid - off] : 0;
         __syncthreads();
         sc[tid] += v;
         __syncthreads();
     }
+    // this thread's rows: with |c| <= L/2, |A_y| <= L^2/2 and B_y <= L^3/4
+    // every row's term fits int64 for L <= 2^20; the sum over rows is kept
+    // in 128-bit (additions only)
     long long c = sc[tid] - loc;
     long long r1 = 0;
     __int128 r2 = 0;
     for (uint32_t y = y0; y < y1; ++y) {
         const long long Ay = rowA[y], By = rowB[y];
         r1 += (long long)L * c + Ay;
-        r2 += (__int128)L * c * c + (__int128)2 * c * Ay + By;
+        r2 += (__int128)((long long)L * c * c + 2 * c * Ay + By);
         c += ((words[(size_t)y * W] >> 1) & 1u) ? 1 : -1;
     }
     long long n = 0;
-    for (uint32_t i = tid; i < NSLOTS; i += 1024) n += slots[i];
+    for (uint32_t i = tid; i < nslots; i += NT) n += slots[i];
     r1s[tid] = r1;
     r2s[tid] = r2;
     ns[tid] = n;
     __syncthreads();
-    for (uint32_t off = 512; off > 0; off >>= 1) {
+    for (uint32_t off = NT / 2; off > 0; off >>= 1) {
         if (tid < off) {
             r1s[tid] += r1s[tid + off];
             r2s[tid] += r2s[tid + off];
@@ -494,6 +690,159 @@ __global__ __launch_bounds__(1024) void kpz_finalize_kernel(const uint32_t *word
         res[2] = (long long)(uint64_t)(u2 >> 64);
         res[3] = ns[0];
     }
+}
+
+__global__ __launch_bounds__(1024) void kpz_finalize_kernel(const uint32_t *words, uint32_t L,
+                                                            uint32_t W, const long long *rowA,
+                                                            const long long *rowB,
+                                                            const long long *slots,
+                                                            long long *res)
+{
+    finalize_moments<1024>(words, L, W, rowA, rowB, slots, NSLOTS, res);
+}
+
+// ------------------------------------------------------------ ensemble
+//
+// Many independent lattices ("members", each with its own L, p, q and seed,
+// one common block shape) advance together.  One persistent launch runs
+// `rounds` MCS of every member: work-groups take tickets in the order
+// (round, member, block); the block of member r at round k + 1 waits only
+// until member r's round k is complete, so members never wait for each
+// other.  The work-group that finishes the last block of a member's round
+// merges that member's straddling words and then publishes the round
+// (agent-scope release; the waiting side acquires).
+
+struct MemberRows {
+    const uint32_t *words;
+    long long *rowA, *rowB;
+    const long long *slots;
+    uint32_t L, W;
+};
+
+struct BatchArgs {
+    const SweepArgs *members;    // per member; field t = MCS index at launch start
+    const uint32_t *bprefix;     // [n + 1] prefix sums of blocks per member
+    unsigned int *ctl;           // [0..1] 64-bit ticket counter, [64 + r] blocks done,
+                                 // [64 + n + r] rounds ready
+    uint32_t n;
+    uint32_t per_round;          // blocks of all members per round = bprefix[n]
+    uint32_t rounds;
+};
+
+template <int TPB, int K, int NTX>
+__global__ __launch_bounds__(TPB) void kpz_batch_kernel(const BatchArgs ba)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ unsigned long long s_ticket;
+    __shared__ unsigned int s_last;
+    const uint64_t total = (uint64_t)ba.per_round * ba.rounds;
+    unsigned int *const done = ba.ctl + 64;
+    unsigned int *const ready = ba.ctl + 64 + ba.n;
+    for (;;) {
+        if (threadIdx.x == 0) s_ticket = atomicAdd((unsigned long long *)ba.ctl, 1ull);
+        __syncthreads();
+        const uint64_t ticket = s_ticket;
+        __syncthreads();
+        if (ticket >= total) break;
+        const uint32_t round = __builtin_amdgcn_readfirstlane((uint32_t)(ticket / ba.per_round));
+        const uint32_t rem = __builtin_amdgcn_readfirstlane(
+            (uint32_t)(ticket - (uint64_t)round * ba.per_round));
+        // member r: the last one with bprefix[r] <= rem
+        uint32_t lo = 0, hi = ba.n;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (ba.bprefix[mid] <= rem) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t r = __builtin_amdgcn_readfirstlane(lo);
+        const uint32_t b = rem - ba.bprefix[r];
+        SweepArgs a = ba.members[r];
+        a.t += round;
+        if (round > 0) {
+            if (threadIdx.x == 0)
+                while (__hip_atomic_load(ready + r, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < round)
+                    __builtin_amdgcn_s_sleep(2);
+            __syncthreads();
+            __threadfence();   // every wave orders its loads after the acquire
+        }
+        if (a.acc) sweep_block<TPB, K, NTX, true>(a, b, lds);
+        else sweep_block<TPB, K, NTX, false>(a, b, lds);
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned int nb = ba.bprefix[r + 1] - ba.bprefix[r];
+            const unsigned int old = atomicAdd(done + r, 1u);
+            s_last = (old + 1 == (round + 1) * nb) ? 1u : 0u;
+        }
+        __syncthreads();
+        if (s_last) {
+            __threadfence();   // acquire: the other blocks' side-buffer parts
+            merge_straddles(a, threadIdx.x, TPB);
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0)
+                __hip_atomic_store(ready + r, round + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void kpz_zero_kernel(uint32_t *p, uint64_t n)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__global__ void kpz_batch_reset_kernel(unsigned int *ctl, uint32_t n)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < 64 + 2 * n; i += gridDim.x * blockDim.x)
+        ctl[i] = 0u;
+}
+
+__global__ void kpz_batch_advance_kernel(SweepArgs *members, uint32_t n, uint32_t dt)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        members[i].t += dt;
+}
+
+// Row moments of all members: rows numbered consecutively over the members
+// (rprefix = prefix sums of L), one wave per row.
+__global__ __launch_bounds__(256) void kpz_batch_rows_kernel(const MemberRows *mr,
+                                                             const uint32_t *rprefix, uint32_t n)
+{
+    __shared__ uint32_t lut[256];
+    lut[threadIdx.x] = lut8_entry(threadIdx.x);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t total = rprefix[n];
+    for (uint32_t g = blockIdx.x * 4u + (threadIdx.x >> 6); g < total; g += gridDim.x * 4u) {
+        uint32_t lo = 0, hi = n;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (rprefix[mid] <= g) lo = mid;
+            else hi = mid;
+        }
+        const MemberRows m = mr[lo];
+        const uint32_t row = g - rprefix[lo];
+        long long A, B;
+        row_moments(m.words + (size_t)row * m.W, m.W, lut, lane, A, B);
+        if (lane == 0) {
+            m.rowA[row] = A;
+            m.rowB[row] = B;
+        }
+    }
+}
+
+// One work-group per member; results of sample `k` go to res[(k n + r) 4 ..].
+__global__ __launch_bounds__(256) void kpz_batch_finalize_kernel(const MemberRows *mr, uint32_t n,
+                                                                 uint32_t nslots, long long *res,
+                                                                 uint32_t k)
+{
+    const uint32_t r = blockIdx.x;
+    const MemberRows m = mr[r];
+    finalize_moments<256>(m.words, m.L, m.W, m.rowA, m.rowB, m.slots, nslots,
+                          res + ((size_t)k * n + r) * 4);
 }
 
 }  // namespace
@@ -554,9 +903,12 @@ kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
     return KPZ_OK;
 }
 
-size_t ws_needed(int64_t L)
+size_t ws_needed(int64_t L, int64_t Bx)
 {
-    return (size_t)WS_HEADER + sizeof(long long) * NSLOTS + 2 * sizeof(long long) * (size_t)L;
+    // header, flip-counter slots, two int64 per row (row moments), and the
+    // side buffer of the straddling words: two uint32 per (row, block column)
+    return (size_t)WS_HEADER + sizeof(long long) * NSLOTS + 2 * sizeof(long long) * (size_t)L +
+           2 * sizeof(uint32_t) * (size_t)L * (size_t)(L / Bx);
 }
 
 kpz_status hip_fail(kpz_sim *s, hipError_t e, const char *what)
@@ -569,26 +921,271 @@ long long *ws_res(kpz_sim *s) { return (long long *)s->ws; }
 long long *ws_slots(kpz_sim *s) { return (long long *)(s->ws + WS_HEADER); }
 long long *ws_rowA(kpz_sim *s) { return ws_slots(s) + NSLOTS; }
 long long *ws_rowB(kpz_sim *s) { return ws_rowA(s) + s->prm.L; }
+uint32_t *ws_side(kpz_sim *s) { return (uint32_t *)(ws_rowB(s) + s->prm.L); }
 
-template <int K, bool ACC>
+template <int TPB, int K, int NTX, bool ACC>
 hipError_t launch_sweep_k(const SweepArgs &a, uint32_t nblocks, size_t shmem, hipStream_t st)
 {
-    hipLaunchKernelGGL((kpz_sweep_kernel<K, ACC>), dim3(nblocks), dim3(64), shmem, st, a);
+    hipLaunchKernelGGL((kpz_sweep_kernel<TPB, K, NTX, ACC>), dim3(nblocks), dim3(TPB), shmem, st, a);
     return hipGetLastError();
 }
 
-template <bool ACC>
-hipError_t launch_sweep(const SweepArgs &a, uint32_t K, uint32_t nblocks, size_t shmem,
-                        hipStream_t st)
+// Shape-specialised kernels for the tile-column counts of the common block
+// widths (256, 512, 1024 sites); every other width runs the runtime-width
+// kernel (NTX = 0).
+template <int TPB, int K, bool ACC>
+hipError_t launch_sweep_ntx(const SweepArgs &a, uint32_t nblocks, size_t shmem, hipStream_t st)
 {
+    switch (a.ntx) {
+    case 64: return launch_sweep_k<TPB, K, 64, ACC>(a, nblocks, shmem, st);
+    case 128: return launch_sweep_k<TPB, K, 128, ACC>(a, nblocks, shmem, st);
+    case 256: return launch_sweep_k<TPB, K, 256, ACC>(a, nblocks, shmem, st);
+    default: return launch_sweep_k<TPB, K, 0, ACC>(a, nblocks, shmem, st);
+    }
+}
+
+// tpb threads per block, K = nq / tpb quads per thread (K = 1 with idle
+// lanes for blocks of fewer than 64 quads).
+template <bool ACC>
+hipError_t launch_sweep(const SweepArgs &a, uint32_t tpb, uint32_t K, uint32_t nblocks,
+                        size_t shmem, hipStream_t st)
+{
+    if (tpb == 256) {
+        switch (K) {
+        case 1: return launch_sweep_ntx<256, 1, ACC>(a, nblocks, shmem, st);
+        case 2: return launch_sweep_ntx<256, 2, ACC>(a, nblocks, shmem, st);
+        case 4: return launch_sweep_ntx<256, 4, ACC>(a, nblocks, shmem, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (K) {
-    case 1: return launch_sweep_k<1, ACC>(a, nblocks, shmem, st);
-    case 2: return launch_sweep_k<2, ACC>(a, nblocks, shmem, st);
-    case 4: return launch_sweep_k<4, ACC>(a, nblocks, shmem, st);
-    case 8: return launch_sweep_k<8, ACC>(a, nblocks, shmem, st);
-    case 16: return launch_sweep_k<16, ACC>(a, nblocks, shmem, st);
+    case 1: return launch_sweep_ntx<64, 1, ACC>(a, nblocks, shmem, st);
+    case 2: return launch_sweep_ntx<64, 2, ACC>(a, nblocks, shmem, st);
+    case 4: return launch_sweep_ntx<64, 4, ACC>(a, nblocks, shmem, st);
+    case 8: return launch_sweep_ntx<64, 8, ACC>(a, nblocks, shmem, st);
+    case 16: return launch_sweep_ntx<64, 16, ACC>(a, nblocks, shmem, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+}  // namespace
+
+
+// ------------------------------------------------------------ ensemble host
+
+namespace {
+
+constexpr int BATCH_SLOTS = 64;   // flip-counter slots per member
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct BatchLayout {
+    uint32_t Bx, By;
+    std::vector<size_t> word_off;   // per member, in words
+    size_t words_bytes;
+    size_t off_ctl, off_members, off_bprefix, off_rprefix, off_rows, off_res, off_slots;
+    std::vector<size_t> off_rowA, off_rowB, off_side;
+    size_t ws_bytes;
+};
+
+kpz_status batch_layout(const kpz_params *m, int32_t n, BatchLayout *lay)
+{
+    if (!m || n < 1) return KPZ_EINVAL;
+    int64_t Lmin = INT64_MAX;
+    for (int32_t r = 0; r < n; ++r) Lmin = m[r].L < Lmin ? m[r].L : Lmin;
+    if (Lmin < 16 || Lmin % 16) return KPZ_EINVAL;
+    int64_t dflt = 256;
+    while (Lmin % dflt) dflt >>= 1;
+    int64_t bx = -1, by = -1;
+    for (int32_t r = 0; r < n; ++r) {
+        kpz_params q = m[r];
+        if (!q.block_x) q.block_x = (int32_t)dflt;
+        if (!q.block_y) q.block_y = (int32_t)dflt;
+        uint32_t rbx, rby;
+        const kpz_status st = resolve(&q, &rbx, &rby);
+        if (st != KPZ_OK) return st;
+        if (bx < 0) { bx = rbx; by = rby; }
+        if ((int64_t)rbx != bx || (int64_t)rby != by) return KPZ_EINVAL;
+    }
+    lay->Bx = (uint32_t)bx;
+    lay->By = (uint32_t)by;
+    lay->word_off.resize(n);
+    size_t w = 0;
+    for (int32_t r = 0; r < n; ++r) {
+        lay->word_off[r] = w;
+        w += align256((size_t)m[r].L * m[r].L / 4) / 4;
+    }
+    lay->words_bytes = 4 * w;
+    size_t o = 0;
+    lay->off_ctl = o;      o = align256(o + 4 * (64 + 2 * (size_t)n));
+    lay->off_members = o;  o = align256(o + sizeof(SweepArgs) * (size_t)n);
+    lay->off_bprefix = o;  o = align256(o + 4 * ((size_t)n + 1));
+    lay->off_rprefix = o;  o = align256(o + 4 * ((size_t)n + 1));
+    lay->off_rows = o;     o = align256(o + sizeof(MemberRows) * (size_t)n);
+    lay->off_res = o;      o = align256(o + 4 * sizeof(long long) * (size_t)n * KPZ_BATCH_MAX_SAMPLES);
+    lay->off_slots = o;    o = align256(o + sizeof(long long) * BATCH_SLOTS * (size_t)n);
+    lay->off_rowA.resize(n);
+    lay->off_rowB.resize(n);
+    lay->off_side.resize(n);
+    for (int32_t r = 0; r < n; ++r) {
+        const size_t L = (size_t)m[r].L;
+        lay->off_rowA[r] = o; o = align256(o + 8 * L);
+        lay->off_rowB[r] = o; o = align256(o + 8 * L);
+        lay->off_side[r] = o; o = align256(o + 4 * 2 * L * (L / lay->Bx));
+    }
+    lay->ws_bytes = o;
+    return KPZ_OK;
+}
+
+template <int TPB, int K, int NTX>
+void batch_kernel_ptr(const void **fn)
+{
+    *fn = (const void *)kpz_batch_kernel<TPB, K, NTX>;
+}
+
+}  // namespace
+
+struct kpz_batch {
+    int32_t n;
+    std::vector<kpz_params> prm;
+    BatchLayout lay;
+    uint32_t *words;
+    uint8_t *ws;
+    hipStream_t stream;
+    int64_t t;
+    uint32_t tpb, K, ntx, nq, per_round, grid;
+    size_t shmem;
+    uint32_t total_rows;
+    char err[256];
+};
+
+namespace {
+
+kpz_status batch_fail(kpz_batch *b, hipError_t e, const char *what)
+{
+    if (b) snprintf(b->err, sizeof b->err, "%s: %s", what, hipGetErrorString(e));
+    return KPZ_EHIP;
+}
+
+// Launches the persistent kernel for the batch's shape.
+template <int TPB, int K>
+hipError_t batch_launch_k(kpz_batch *bt, const BatchArgs &ba, hipStream_t st)
+{
+    switch (bt->ntx) {
+    case 64:
+        hipLaunchKernelGGL((kpz_batch_kernel<TPB, K, 64>), dim3(bt->grid), dim3(TPB), bt->shmem, st, ba);
+        break;
+    case 128:
+        hipLaunchKernelGGL((kpz_batch_kernel<TPB, K, 128>), dim3(bt->grid), dim3(TPB), bt->shmem, st, ba);
+        break;
+    case 256:
+        hipLaunchKernelGGL((kpz_batch_kernel<TPB, K, 256>), dim3(bt->grid), dim3(TPB), bt->shmem, st, ba);
+        break;
+    default:
+        hipLaunchKernelGGL((kpz_batch_kernel<TPB, K, 0>), dim3(bt->grid), dim3(TPB), bt->shmem, st, ba);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t batch_launch(kpz_batch *bt, const BatchArgs &ba, hipStream_t st)
+{
+    if (bt->tpb == 256) {
+        switch (bt->K) {
+        case 1: return batch_launch_k<256, 1>(bt, ba, st);
+        case 2: return batch_launch_k<256, 2>(bt, ba, st);
+        case 4: return batch_launch_k<256, 4>(bt, ba, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (bt->K) {
+    case 1: return batch_launch_k<64, 1>(bt, ba, st);
+    case 2: return batch_launch_k<64, 2>(bt, ba, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int TPB, int K>
+const void *batch_fn_k(uint32_t ntx)
+{
+    switch (ntx) {
+    case 64: return (const void *)kpz_batch_kernel<TPB, K, 64>;
+    case 128: return (const void *)kpz_batch_kernel<TPB, K, 128>;
+    case 256: return (const void *)kpz_batch_kernel<TPB, K, 256>;
+    default: return (const void *)kpz_batch_kernel<TPB, K, 0>;
+    }
+}
+
+const void *batch_fn(uint32_t tpb, uint32_t K, uint32_t ntx)
+{
+    if (tpb == 256) return K == 1 ? batch_fn_k<256, 1>(ntx) : K == 2 ? batch_fn_k<256, 2>(ntx)
+                                                                     : batch_fn_k<256, 4>(ntx);
+    return K == 1 ? batch_fn_k<64, 1>(ntx) : batch_fn_k<64, 2>(ntx);
+}
+
+SweepArgs *batch_members(kpz_batch *b) { return (SweepArgs *)(b->ws + b->lay.off_members); }
+unsigned int *batch_ctl(kpz_batch *b) { return (unsigned int *)(b->ws + b->lay.off_ctl); }
+long long *batch_res(kpz_batch *b) { return (long long *)(b->ws + b->lay.off_res); }
+
+// sweep n_mcs on stream st (capturable: kernels only)
+kpz_status batch_sweep_on(kpz_batch *b, int32_t n_mcs, hipStream_t st)
+{
+    if (n_mcs <= 0) return KPZ_OK;
+    hipLaunchKernelGGL(kpz_batch_reset_kernel, dim3(1), dim3(256), 0, st, batch_ctl(b),
+                       (uint32_t)b->n);
+    BatchArgs ba;
+    ba.members = batch_members(b);
+    ba.bprefix = (const uint32_t *)(b->ws + b->lay.off_bprefix);
+    ba.ctl = batch_ctl(b);
+    ba.n = (uint32_t)b->n;
+    ba.per_round = b->per_round;
+    ba.rounds = (uint32_t)n_mcs;
+    hipError_t e = batch_launch(b, ba, st);
+    if (e != hipSuccess) return batch_fail(b, e, "kpz_batch_sweep launch");
+    hipLaunchKernelGGL(kpz_batch_advance_kernel, dim3((b->n + 255) / 256), dim3(256), 0, st,
+                       batch_members(b), (uint32_t)b->n, (uint32_t)n_mcs);
+    e = hipGetLastError();
+    if (e != hipSuccess) return batch_fail(b, e, "kpz_batch_sweep launch");
+    return KPZ_OK;
+}
+
+kpz_status batch_moments_on(kpz_batch *b, uint32_t k, hipStream_t st)
+{
+    const MemberRows *mr = (const MemberRows *)(b->ws + b->lay.off_rows);
+    const uint32_t rgrid = (b->total_rows + 3) / 4 < 8192 ? (b->total_rows + 3) / 4 : 8192;
+    hipLaunchKernelGGL(kpz_batch_rows_kernel, dim3(rgrid), dim3(256), 0, st, mr,
+                       (const uint32_t *)(b->ws + b->lay.off_rprefix), (uint32_t)b->n);
+    hipLaunchKernelGGL(kpz_batch_finalize_kernel, dim3(b->n), dim3(256), 0, st, mr,
+                       (uint32_t)b->n, (uint32_t)BATCH_SLOTS, batch_res(b), k);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return batch_fail(b, e, "kpz_batch moments launch");
+    return KPZ_OK;
+}
+
+// Converts (R1, R2 lo, R2 hi, net) of member r into S1, S2, W2.
+kpz_status convert_moments(const long long *res, int64_t L, int64_t *S1o, int64_t *S2o,
+                           double *W2o, char *err, size_t errn)
+{
+    const __int128 N = (__int128)L * L;
+    const __int128 R1 = res[0];
+    const __int128 R2 = (__int128)(((unsigned __int128)(uint64_t)res[2] << 64) | (uint64_t)res[1]);
+    const __int128 net = res[3];
+    const __int128 S1 = N / 2 + 2 * net;
+    const __int128 num = S1 - R1;
+    if (num % N != 0) {
+        snprintf(err, errn, "height anchor not integral: words and flip count disagree");
+        return KPZ_ESTATE;
+    }
+    const __int128 ha = num / N;
+    const __int128 S2 = R2 + 2 * ha * R1 + N * ha * ha;
+    const __int128 wnum = N * R2 - R1 * R1;
+    if (W2o) *W2o = (double)((long double)wnum / ((long double)N * (long double)N));
+    const __int128 lim = (__int128)INT64_MAX;
+    kpz_status st = KPZ_OK;
+    if (S1 > lim || S1 < -lim - 1 || S2 > lim || S2 < 0) st = KPZ_ERANGE;
+    if (S1o) *S1o = (int64_t)S1;
+    if (S2o) *S2o = (int64_t)S2;
+    return st;
 }
 
 }  // namespace
@@ -616,7 +1213,7 @@ kpz_status kpz_workspace_bytes(const kpz_params *p, size_t *bytes)
     const kpz_status st = resolve(p, &bx, &by);
     if (st != KPZ_OK) return st;
     if (!bytes) return KPZ_EINVAL;
-    *bytes = ws_needed(p->L);
+    *bytes = ws_needed(p->L, bx);
     return KPZ_OK;
 }
 
@@ -630,7 +1227,7 @@ kpz_status kpz_init(kpz_sim **out, const kpz_params *p, uint32_t *d_words, size_
     if (st != KPZ_OK) return st;
     if (!d_words || !d_ws) return KPZ_EINVAL;
     const uint64_t L = (uint64_t)p->L;
-    if (words_bytes < L * L / 4 || ws_bytes < ws_needed(p->L)) return KPZ_ESIZE;
+    if (words_bytes < L * L / 4 || ws_bytes < ws_needed(p->L, bx)) return KPZ_ESIZE;
     kpz_sim *s = new (std::nothrow) kpz_sim();
     if (!s) return KPZ_EINVAL;
     s->prm = *p;
@@ -679,6 +1276,7 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     const uint32_t L = (uint32_t)s->prm.L;
     SweepArgs a;
     a.words = s->words;
+    a.side = ws_side(s);
     a.slots = (unsigned long long *)ws_slots(s);
     a.L = L;
     a.W = L / 16;
@@ -689,22 +1287,38 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     a.ntx = s->Bx / TILE;
     a.log2ntx = (uint32_t)ilog2(a.ntx);
     a.H = s->By / 16;
+    a.log2H = (uint32_t)ilog2(a.H);
     a.nq = a.ntx * a.H;
     a.nw = s->Bx / 16;
+    a.log2nw = (uint32_t)ilog2(a.nw);
     a.units = a.nw * a.H * 2;
     a.seed_lo = (uint32_t)s->prm.seed;
     a.seed_hi = (uint32_t)(s->prm.seed >> 32);
     a.P = s->P;
     a.Q = s->Q;
-    const uint32_t K = a.nq <= 64 ? 1u : a.nq / 64u;
+    a.slot_mask = NSLOTS - 1;
+    a.acc = !(s->P == (1ull << 32) && s->Q == 0);
+    // threads per block: four waves when the block has at least 256 quads
+    // (fewer registers per lane, more waves to hide LDS and HBM latency);
+    // KPZ_THREADS_PER_BLOCK=64 selects one wave per block.  The launch shape
+    // does not change any result.
+    uint32_t tpb = a.nq >= 256 ? 256u : 64u;
+    if (const char *env = getenv("KPZ_THREADS_PER_BLOCK"))
+        if (atoi(env) == 64) tpb = 64u;
+    const uint32_t K = a.nq <= tpb ? 1u : a.nq / tpb;
     const uint32_t nblocks = a.nbx * a.nby;
-    const size_t shmem = sizeof(uint32_t) * (4 * (size_t)a.nq + 2 * (size_t)s->By);
+    const size_t shmem = sizeof(uint32_t) * 4 * (size_t)a.nq;
+    const uint64_t nmerge = (uint64_t)L * a.nbx;
+    const uint32_t mgrid = (uint32_t)((nmerge + 255) / 256 < 8192 ? (nmerge + 255) / 256 : 8192);
     const bool acc = !(s->P == (1ull << 32) && s->Q == 0);
     for (int32_t m = 0; m < n_mcs; ++m) {
         a.t = (uint32_t)(s->t + m);
-        const hipError_t e = acc ? launch_sweep<true>(a, K, nblocks, shmem, s->stream)
-                                 : launch_sweep<false>(a, K, nblocks, shmem, s->stream);
+        hipError_t e = acc ? launch_sweep<true>(a, tpb, K, nblocks, shmem, s->stream)
+                           : launch_sweep<false>(a, tpb, K, nblocks, shmem, s->stream);
         if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep launch");
+        hipLaunchKernelGGL(kpz_merge_kernel, dim3(mgrid), dim3(256), 0, s->stream, a);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep merge launch");
     }
     s->t += n_mcs;
     return KPZ_OK;
@@ -714,8 +1328,9 @@ kpz_status kpz_roughness(kpz_sim *s, int64_t *S1o, int64_t *S2o, double *W2o)
 {
     if (!s) return KPZ_EINVAL;
     const uint32_t L = (uint32_t)s->prm.L, W = L / 16;
-    hipLaunchKernelGGL(kpz_row_moments_kernel, dim3((L + 3) / 4), dim3(256), 0, s->stream,
-                       s->words, L, W, ws_rowA(s), ws_rowB(s));
+    const uint32_t rgrid = (L + 3) / 4 < 4096 ? (L + 3) / 4 : 4096;
+    hipLaunchKernelGGL(kpz_row_moments_kernel, dim3(rgrid), dim3(256), 0, s->stream, s->words, L,
+                       W, ws_rowA(s), ws_rowB(s));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(s, e, "kpz_roughness launch");
     hipLaunchKernelGGL(kpz_finalize_kernel, dim3(1), dim3(1024), 0, s->stream, s->words, L, W,
@@ -778,5 +1393,244 @@ kpz_status kpz_set_state(kpz_sim *s, int64_t t, int64_t net)
 }
 
 void kpz_destroy(kpz_sim *s) { delete s; }
+
+
+kpz_status kpz_batch_sizes(const kpz_params *members, int32_t n, size_t *words_bytes,
+                           size_t *ws_bytes)
+{
+    BatchLayout lay;
+    const kpz_status st = batch_layout(members, n, &lay);
+    if (st != KPZ_OK) return st;
+    if (words_bytes) *words_bytes = lay.words_bytes;
+    if (ws_bytes) *ws_bytes = lay.ws_bytes;
+    return KPZ_OK;
+}
+
+kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n, uint32_t *d_words,
+                          size_t words_bytes, void *d_ws, size_t ws_bytes, void *stream)
+{
+    if (!out) return KPZ_EINVAL;
+    *out = nullptr;
+    BatchLayout lay;
+    kpz_status st = batch_layout(members, n, &lay);
+    if (st != KPZ_OK) return st;
+    if (!d_words || !d_ws) return KPZ_EINVAL;
+    if (words_bytes < lay.words_bytes || ws_bytes < lay.ws_bytes) return KPZ_ESIZE;
+    kpz_batch *b = new (std::nothrow) kpz_batch();
+    if (!b) return KPZ_EINVAL;
+    b->n = n;
+    b->prm.assign(members, members + n);
+    b->lay = lay;
+    b->words = d_words;
+    b->ws = (uint8_t *)d_ws;
+    b->stream = (hipStream_t)stream;
+    b->t = 0;
+    b->err[0] = 0;
+    b->ntx = lay.Bx / TILE;
+    b->nq = b->ntx * (lay.By / 16);
+    b->tpb = b->nq >= 256 ? 256u : 64u;
+    if (const char *env = getenv("KPZ_THREADS_PER_BLOCK"))
+        if (atoi(env) == 64 && b->nq <= 128) b->tpb = 64u;
+    b->K = b->nq <= b->tpb ? 1u : b->nq / b->tpb;
+    if (b->tpb == 256 && b->K > 4) { delete b; return KPZ_EINVAL; }
+    b->shmem = sizeof(uint32_t) * 4 * (size_t)b->nq;
+
+    std::vector<SweepArgs> args(n);
+    std::vector<MemberRows> rows(n);
+    std::vector<uint32_t> bprefix(n + 1, 0), rprefix(n + 1, 0);
+    long long *slots = (long long *)(b->ws + lay.off_slots);
+    for (int32_t r = 0; r < n; ++r) {
+        const kpz_params &p = members[r];
+        const uint32_t L = (uint32_t)p.L;
+        SweepArgs &a = args[r];
+        a.words = d_words + lay.word_off[r];
+        a.side = (uint32_t *)(b->ws + lay.off_side[r]);
+        a.slots = (unsigned long long *)(slots + (size_t)BATCH_SLOTS * r);
+        a.L = L;
+        a.W = L / 16;
+        a.Bx = lay.Bx;
+        a.By = lay.By;
+        a.nbx = L / lay.Bx;
+        a.nby = L / lay.By;
+        a.ntx = lay.Bx / TILE;
+        a.log2ntx = (uint32_t)ilog2(a.ntx);
+        a.H = lay.By / 16;
+        a.log2H = (uint32_t)ilog2(a.H);
+        a.nq = a.ntx * a.H;
+        a.nw = lay.Bx / 16;
+        a.log2nw = (uint32_t)ilog2(a.nw);
+        a.units = a.nw * a.H * 2;
+        a.seed_lo = (uint32_t)p.seed;
+        a.seed_hi = (uint32_t)(p.seed >> 32);
+        a.t = 0;
+        a.slot_mask = BATCH_SLOTS - 1;
+        a.P = threshold(p.p);
+        a.Q = threshold(p.q);
+        a.acc = !(a.P == (1ull << 32) && a.Q == 0);
+        rows[r].words = a.words;
+        rows[r].rowA = (long long *)(b->ws + lay.off_rowA[r]);
+        rows[r].rowB = (long long *)(b->ws + lay.off_rowB[r]);
+        rows[r].slots = slots + (size_t)BATCH_SLOTS * r;
+        rows[r].L = L;
+        rows[r].W = L / 16;
+        bprefix[r + 1] = bprefix[r] + a.nbx * a.nby;
+        rprefix[r + 1] = rprefix[r] + L;
+    }
+    b->per_round = bprefix[n];
+    b->total_rows = rprefix[n];
+    hipError_t e = hipSuccess;
+    auto h2d = [&](size_t off, const void *src, size_t bytes) {
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->ws + off, src, bytes, hipMemcpyHostToDevice, b->stream);
+    };
+    h2d(lay.off_members, args.data(), sizeof(SweepArgs) * n);
+    h2d(lay.off_bprefix, bprefix.data(), 4 * (n + 1));
+    h2d(lay.off_rprefix, rprefix.data(), 4 * (n + 1));
+    h2d(lay.off_rows, rows.data(), sizeof(MemberRows) * n);
+    for (int32_t r = 0; r < n && e == hipSuccess; ++r) {
+        const uint64_t L = (uint64_t)members[r].L;
+        const uint32_t W = (uint32_t)(L / 16);
+        if (W % 4 == 0) {
+            const uint64_t n4 = L * L / 64;
+            const uint32_t blocks = (uint32_t)((n4 + 255) / 256 < 65536 ? (n4 + 255) / 256 : 65536);
+            hipLaunchKernelGGL(kpz_init_kernel, dim3(blocks), dim3(256), 0, b->stream,
+                               (uint4 *)(d_words + lay.word_off[r]), n4, W / 4);
+        } else {
+            hipLaunchKernelGGL(kpz_init_small_kernel, dim3(1), dim3(256), 0, b->stream,
+                               d_words + lay.word_off[r], (uint32_t)(L * L / 16), W);
+        }
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        const uint32_t ns = (uint32_t)BATCH_SLOTS * (uint32_t)n;
+        hipLaunchKernelGGL(kpz_zero_kernel, dim3((2 * ns + 255) / 256), dim3(256), 0, b->stream,
+                           (uint32_t *)slots, (uint64_t)2 * ns);
+        e = hipGetLastError();
+    }
+    // persistent grid: as many work-groups as can be resident
+    int dev = 0, cus = 0, per_cu = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_fn(b->tpb, b->K, b->ntx),
+                                                         (int)b->tpb, b->shmem);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        batch_fail(b, e, "kpz_batch_init");
+        delete b;
+        return KPZ_EHIP;
+    }
+    b->grid = (uint32_t)(cus * (per_cu > 0 ? per_cu : 1));
+    *out = b;
+    return KPZ_OK;
+}
+
+kpz_status kpz_batch_word_offset(const kpz_batch *b, int32_t r, size_t *off)
+{
+    if (!b || !off || r < 0 || r >= b->n) return KPZ_EINVAL;
+    *off = b->lay.word_off[r];
+    return KPZ_OK;
+}
+
+kpz_status kpz_batch_sweep(kpz_batch *b, int32_t n_mcs)
+{
+    if (!b || n_mcs < 0) return KPZ_EINVAL;
+    if (b->t + n_mcs > 0xFFFFFFFFll) return KPZ_ERANGE;
+    const kpz_status st = batch_sweep_on(b, n_mcs, b->stream);
+    if (st == KPZ_OK) b->t += n_mcs;
+    return st;
+}
+
+kpz_status kpz_batch_roughness(kpz_batch *b, int64_t *S1, int64_t *S2, double *W2)
+{
+    if (!b) return KPZ_EINVAL;
+    kpz_status st = batch_moments_on(b, 0, b->stream);
+    if (st != KPZ_OK) return st;
+    std::vector<long long> res(4 * (size_t)b->n);
+    hipError_t e = hipMemcpyAsync(res.data(), batch_res(b), res.size() * sizeof(long long),
+                                  hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return batch_fail(b, e, "kpz_batch_roughness copy");
+    kpz_status worst = KPZ_OK;
+    for (int32_t r = 0; r < b->n; ++r) {
+        const kpz_status s = convert_moments(&res[4 * (size_t)r], b->prm[r].L, S1 ? S1 + r : nullptr,
+                                             S2 ? S2 + r : nullptr, W2 ? W2 + r : nullptr, b->err,
+                                             sizeof b->err);
+        if (s != KPZ_OK && worst == KPZ_OK) worst = s;
+    }
+    return worst;
+}
+
+kpz_status kpz_batch_run(kpz_batch *b, const int32_t *times, int32_t n_times, int64_t *S1,
+                         int64_t *S2, double *W2)
+{
+    if (!b || !times || n_times < 1 || n_times > KPZ_BATCH_MAX_SAMPLES) return KPZ_EINVAL;
+    int64_t prev = b->t;
+    for (int32_t k = 0; k < n_times; ++k) {
+        if (times[k] <= prev) return KPZ_EINVAL;
+        prev = times[k];
+    }
+    if (prev > 0xFFFFFFFFll) return KPZ_ERANGE;
+    // capture the schedule on a private stream, ordered after the caller's stream
+    hipStream_t cs = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_out, hipEventDisableTiming);
+    kpz_status st = KPZ_OK;
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        int64_t t = b->t;
+        for (int32_t k = 0; k < n_times && st == KPZ_OK; ++k) {
+            st = batch_sweep_on(b, (int32_t)(times[k] - t), cs);
+            t = times[k];
+            if (st == KPZ_OK) st = batch_moments_on(b, (uint32_t)k, cs);
+        }
+        const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess && st == KPZ_OK) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess && st == KPZ_OK) e = hipEventRecord(ev_in, b->stream);
+    if (e == hipSuccess && st == KPZ_OK) e = hipStreamWaitEvent(cs, ev_in, 0);
+    if (e == hipSuccess && st == KPZ_OK) e = hipGraphLaunch(exec, cs);
+    if (e == hipSuccess && st == KPZ_OK) e = hipEventRecord(ev_out, cs);
+    if (e == hipSuccess && st == KPZ_OK) e = hipStreamWaitEvent(b->stream, ev_out, 0);
+    std::vector<long long> res(4 * (size_t)b->n * n_times);
+    if (e == hipSuccess && st == KPZ_OK)
+        e = hipMemcpyAsync(res.data(), batch_res(b), res.size() * sizeof(long long),
+                           hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess && st == KPZ_OK) e = hipStreamSynchronize(b->stream);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (st != KPZ_OK) return st;
+    if (e != hipSuccess) return batch_fail(b, e, "kpz_batch_run");
+    b->t = times[n_times - 1];
+    kpz_status worst = KPZ_OK;
+    for (int32_t k = 0; k < n_times; ++k)
+        for (int32_t r = 0; r < b->n; ++r) {
+            const size_t i = (size_t)k * b->n + r;
+            const kpz_status s = convert_moments(&res[4 * i], b->prm[r].L, S1 ? S1 + i : nullptr,
+                                                 S2 ? S2 + i : nullptr, W2 ? W2 + i : nullptr,
+                                                 b->err, sizeof b->err);
+            if (s != KPZ_OK && worst == KPZ_OK) worst = s;
+        }
+    return worst;
+}
+
+kpz_status kpz_batch_get_t(const kpz_batch *b, int64_t *t)
+{
+    if (!b || !t) return KPZ_EINVAL;
+    *t = b->t;
+    return KPZ_OK;
+}
+
+void kpz_batch_destroy(kpz_batch *b) { delete b; }
+
+const char *kpz_batch_last_error(const kpz_batch *b) { return b ? b->err : ""; }
 
 }  // extern "C"

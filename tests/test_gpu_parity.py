@@ -206,3 +206,17 @@ def test_l65536_sampled_blocks(gpu, oracle_lib):
         assert np.array_equal(gsy, bsy), (bx, by)
     m = sim.roughness()   # raises KPZ_ESTATE if words and flip count disagree
     assert m.W2 > 0.25
+
+
+@pytest.mark.parametrize("block,q", [((256, 256), 0.0), ((512, 128), 0.25), ((256, 64), 0.0)])
+def test_launch_shape_does_not_change_results(gpu, monkeypatch, block, q):
+    """One wave per block and four waves per block give identical lattices."""
+    L = 512
+    runs = []
+    for tpb in ("256", "64"):
+        monkeypatch.setenv("KPZ_THREADS_PER_BLOCK", tpb)
+        sim = gpu.Sim(L, 1.0, q, 5, block)
+        sim.sweep(3)
+        runs.append((sim.words_host().copy(), sim.roughness()))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert runs[0][1] == runs[1][1]
