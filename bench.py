@@ -148,6 +148,31 @@ def ensemble_leg(args):
     }
 
 
+def serving_leg(args):
+    """Serving: Poisson stream of jobs (2000 at 50 jobs/s by default), L =
+    2^k with k uniform on 8..13, p = 1, q uniform on [0, 0.5], MCS log-uniform
+    on 10^2..10^4, admitted into a device job pool by HBM budget and run with
+    continuous batching; p50/p99 of arrival -> result latency."""
+    from paper_1204_5072_amd import serve
+    jobs = serve.poisson_jobs(n_jobs=args.serve_jobs, rate=args.serve_rate, seed=0)
+    rep = serve.serve(jobs, hbm_bytes=int(args.serve_hbm_gib * (1 << 30)),
+                      quantum=args.serve_quantum)
+    return {
+        "metric": "job latency p50/p99 (arrival -> result), serving",
+        "p50_ms": rep.latency_p50_ms,
+        "p99_ms": rep.latency_p99_ms,
+        "max_ms": rep.latency_max_ms,
+        "throughput_attempts_per_s": rep.attempts_per_s,
+        "jobs": rep.jobs,
+        "seconds": rep.seconds,
+        "offered_attempts_per_s": rep.attempts / max(j.arrival for j in jobs),
+        "steps": rep.steps,
+        "max_resident_jobs": rep.max_resident,
+        "hbm_budget_gib": args.serve_hbm_gib,
+        "quantum_mcs": args.serve_quantum,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +191,11 @@ def main():
     ap.add_argument("--ens-mcs", type=int, default=10_000)
     ap.add_argument("--ens-block", type=int, nargs=2, default=None)
     ap.add_argument("--ens-seq-members", type=int, default=32)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-hbm-gib", type=float, default=16.0)
+    ap.add_argument("--serve-quantum", type=int, default=64)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -256,6 +286,9 @@ def main():
     if not args.no_ensemble:
         print("bench: ensemble leg", file=sys.stderr, flush=True)
         line["ensemble"] = ensemble_leg(args)
+    if not args.no_serve:
+        print("bench: serving leg", file=sys.stderr, flush=True)
+        line["serving"] = serving_leg(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(L, block, args.p, args.q, args.seed, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -197,6 +197,56 @@ void kpz_batch_destroy(kpz_batch *batch);
 /* Text of the last error recorded in the batch handle ("" if none). */
 const char *kpz_batch_last_error(const kpz_batch *batch);
 
+/* ------------------------------------------------------------------------
+ * Job pool: continuous batching of independent simulation jobs.
+ *
+ * A job is (params, n_mcs): a flat start advanced n_mcs MCS, whose result is
+ * its exact final S1, S2, W^2.  Jobs live in a caller-owned device arena
+ * (the HBM budget); kpz_pool_submit admits a job only if its lattice and
+ * workspace fit into free arena memory and a slot is free.  Each
+ * kpz_pool_step is one persistent launch in which every resident job
+ * advances min(quantum, remaining) MCS; jobs submitted between steps join
+ * the next one, so new work overlaps running work on the device.  A job's
+ * result is bit-identical whatever else runs with it.  All jobs of a pool
+ * share the pool's block shape (block_x, block_y must divide every L).
+ */
+typedef struct kpz_pool kpz_pool;
+
+/* Arena bytes one job occupies while resident. */
+kpz_status kpz_pool_job_bytes(const kpz_params *job, int32_t block_x, int32_t block_y,
+                              size_t *bytes);
+
+/* Arena bytes of the pool's control region (part of the arena). */
+kpz_status kpz_pool_control_bytes(int32_t max_jobs, int32_t max_quantum, size_t *bytes);
+
+/* Creates a pool over the device arena [d_arena, d_arena + arena_bytes)
+ * (caller-owned, 256-byte aligned) for at most max_jobs resident jobs and
+ * steps of at most max_quantum MCS, on `stream` (a hipStream_t). */
+kpz_status kpz_pool_init(kpz_pool **out, void *d_arena, size_t arena_bytes, int32_t max_jobs,
+                         int32_t max_quantum, int32_t block_x, int32_t block_y, void *stream);
+
+/* Admits a job (flat start enqueued) and returns its id; KPZ_ESIZE if it
+ * does not fit into free arena memory or no slot is free right now (it may
+ * fit after running jobs finish); KPZ_EINVAL if it can never run here. */
+kpz_status kpz_pool_submit(kpz_pool *pool, const kpz_params *job, int64_t n_mcs,
+                           int64_t *job_id);
+
+/* One step: every resident job advances min(quantum, remaining) MCS; jobs
+ * that reach their n_mcs are sampled and leave the arena.  *n_active
+ * (may be NULL) = jobs still resident after the step. */
+kpz_status kpz_pool_step(kpz_pool *pool, int32_t quantum, int32_t *n_active);
+
+/* Moves up to max_results finished jobs' results (FIFO) to the arrays;
+ * *n_results = how many.  Any array may be NULL. */
+kpz_status kpz_pool_poll(kpz_pool *pool, int32_t max_results, int64_t *job_ids, int64_t *S1,
+                         int64_t *S2, double *W2, int32_t *n_results);
+
+/* Resident jobs and free arena bytes (largest free extent). */
+kpz_status kpz_pool_stats(const kpz_pool *pool, int32_t *n_active, size_t *largest_free);
+
+void kpz_pool_destroy(kpz_pool *pool);
+const char *kpz_pool_last_error(const kpz_pool *pool);
+
 #ifdef __cplusplus
 }
 #endif

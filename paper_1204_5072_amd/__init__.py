@@ -25,7 +25,10 @@ EXPORTED = ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness", "kp
             "kpz_set_state", "kpz_destroy", "kpz_status_str", "kpz_last_error",
             "kpz_batch_sizes", "kpz_batch_init", "kpz_batch_word_offset", "kpz_batch_sweep",
             "kpz_batch_roughness", "kpz_batch_run", "kpz_batch_get_t", "kpz_batch_destroy",
-            "kpz_batch_last_error")
+            "kpz_batch_last_error",
+            "kpz_pool_job_bytes", "kpz_pool_control_bytes", "kpz_pool_init", "kpz_pool_submit",
+            "kpz_pool_step", "kpz_pool_poll", "kpz_pool_stats", "kpz_pool_destroy",
+            "kpz_pool_last_error")
 BATCH_MAX_SAMPLES = 128
 
 
@@ -82,10 +85,25 @@ def lib() -> ctypes.CDLL:
         L.kpz_batch_destroy.restype = None
         L.kpz_batch_last_error.argtypes = [vp]
         L.kpz_batch_last_error.restype = c.c_char_p
+        szp, i32p = c.POINTER(c.c_size_t), c.POINTER(c.c_int32)
+        L.kpz_pool_job_bytes.argtypes = [P, c.c_int32, c.c_int32, szp]
+        L.kpz_pool_control_bytes.argtypes = [c.c_int32, c.c_int32, szp]
+        L.kpz_pool_init.argtypes = [c.POINTER(vp), vp, c.c_size_t, c.c_int32, c.c_int32, c.c_int32,
+                                    c.c_int32, vp]
+        L.kpz_pool_submit.argtypes = [vp, P, c.c_int64, i64p]
+        L.kpz_pool_step.argtypes = [vp, c.c_int32, i32p]
+        L.kpz_pool_poll.argtypes = [vp, c.c_int32, i64p, i64p, i64p, f64p, i32p]
+        L.kpz_pool_stats.argtypes = [vp, i32p, szp]
+        L.kpz_pool_destroy.argtypes = [vp]
+        L.kpz_pool_destroy.restype = None
+        L.kpz_pool_last_error.argtypes = [vp]
+        L.kpz_pool_last_error.restype = c.c_char_p
         for f in ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness",
                   "kpz_get_state", "kpz_set_state", "kpz_batch_sizes", "kpz_batch_init",
                   "kpz_batch_word_offset", "kpz_batch_sweep", "kpz_batch_roughness",
-                  "kpz_batch_run", "kpz_batch_get_t"):
+                  "kpz_batch_run", "kpz_batch_get_t", "kpz_pool_job_bytes",
+                  "kpz_pool_control_bytes", "kpz_pool_init", "kpz_pool_submit", "kpz_pool_step",
+                  "kpz_pool_poll", "kpz_pool_stats"):
             getattr(L, f).restype = c.c_int
         _lib = L
     return _lib
@@ -270,6 +288,78 @@ class Ensemble:
     def close(self) -> None:
         if self._h:
             lib().kpz_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pool:
+    """Continuous-batching job pool over a device arena of ``hbm_bytes``
+    (the HBM budget).  submit() returns a job id, or None when the job does
+    not fit right now; step() advances every resident job; poll() returns
+    finished jobs' exact moments."""
+
+    def __init__(self, hbm_bytes: int, max_jobs: int = 1024, max_quantum: int = 256,
+                 block: Tuple[int, int] = (256, 256), device="cuda", stream=None):
+        import torch
+        self.block = tuple(block)
+        self.max_quantum = max_quantum
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(hbm_bytes), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = ctypes.c_void_p()
+        st = lib().kpz_pool_init(ctypes.byref(self._h), ctypes.c_void_p(self.arena.data_ptr()),
+                                 self.arena.numel(), max_jobs, max_quantum, self.block[0],
+                                 self.block[1], ctypes.c_void_p(self.stream.cuda_stream))
+        if st != KPZ_OK:
+            raise KPZError(st, "kpz_pool_init")
+
+    def _check(self, st, what):
+        if st != KPZ_OK:
+            raise KPZError(st, what, lib().kpz_pool_last_error(self._h).decode())
+
+    def job_bytes(self, params: kpz_params) -> int:
+        n = ctypes.c_size_t()
+        self._check(lib().kpz_pool_job_bytes(ctypes.byref(params), self.block[0], self.block[1],
+                                             ctypes.byref(n)), "kpz_pool_job_bytes")
+        return n.value
+
+    def submit(self, params: kpz_params, n_mcs: int):
+        jid = ctypes.c_int64()
+        st = lib().kpz_pool_submit(self._h, ctypes.byref(params), int(n_mcs), ctypes.byref(jid))
+        if st == KPZ_ESIZE:
+            return None
+        self._check(st, "kpz_pool_submit")
+        return jid.value
+
+    def step(self, quantum: int) -> int:
+        n = ctypes.c_int32()
+        self._check(lib().kpz_pool_step(self._h, int(quantum), ctypes.byref(n)), "kpz_pool_step")
+        return n.value
+
+    def poll(self, max_results: int = 4096):
+        ids = (ctypes.c_int64 * max_results)()
+        S1 = (ctypes.c_int64 * max_results)()
+        S2 = (ctypes.c_int64 * max_results)()
+        W2 = (ctypes.c_double * max_results)()
+        n = ctypes.c_int32()
+        self._check(lib().kpz_pool_poll(self._h, max_results, ids, S1, S2, W2, ctypes.byref(n)),
+                    "kpz_pool_poll")
+        return [(ids[i], Moments(S1[i], S2[i], W2[i])) for i in range(n.value)]
+
+    def stats(self):
+        n, free = ctypes.c_int32(), ctypes.c_size_t()
+        self._check(lib().kpz_pool_stats(self._h, ctypes.byref(n), ctypes.byref(free)),
+                    "kpz_pool_stats")
+        return n.value, free.value
+
+    def close(self) -> None:
+        if self._h:
+            lib().kpz_pool_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

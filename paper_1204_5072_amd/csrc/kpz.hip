@@ -44,6 +44,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <deque>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -722,6 +725,12 @@ struct MemberRows {
 struct BatchArgs {
     const SweepArgs *members;    // per member; field t = MCS index at launch start
     const uint32_t *bprefix;     // [n + 1] prefix sums of blocks per member
+    // Optional uneven rounds (job pool): members sorted by decreasing rounds,
+    // round k runs members [0, round_members[k]) and its tickets start at
+    // round_start[k] (round_start[rounds] = total).  Null: every member runs
+    // every round.
+    const unsigned long long *round_start;
+    const uint32_t *round_members;
     unsigned int *ctl;           // [0..1] 64-bit ticket counter, [64 + r] blocks done,
                                  // [64 + n + r] rounds ready
     uint32_t n;
@@ -735,7 +744,8 @@ __global__ __launch_bounds__(TPB) void kpz_batch_kernel(const BatchArgs ba)
     extern __shared__ uint32_t lds[];
     __shared__ unsigned long long s_ticket;
     __shared__ unsigned int s_last;
-    const uint64_t total = (uint64_t)ba.per_round * ba.rounds;
+    const uint64_t total = ba.round_start ? ba.round_start[ba.rounds]
+                                          : (uint64_t)ba.per_round * ba.rounds;
     unsigned int *const done = ba.ctl + 64;
     unsigned int *const ready = ba.ctl + 64 + ba.n;
     for (;;) {
@@ -744,11 +754,25 @@ __global__ __launch_bounds__(TPB) void kpz_batch_kernel(const BatchArgs ba)
         const uint64_t ticket = s_ticket;
         __syncthreads();
         if (ticket >= total) break;
-        const uint32_t round = __builtin_amdgcn_readfirstlane((uint32_t)(ticket / ba.per_round));
-        const uint32_t rem = __builtin_amdgcn_readfirstlane(
-            (uint32_t)(ticket - (uint64_t)round * ba.per_round));
+        uint32_t round, rem, nmem;
+        if (ba.round_start) {
+            // round: the last k with round_start[k] <= ticket
+            uint32_t klo = 0, khi = ba.rounds;
+            while (khi - klo > 1) {
+                const uint32_t mid = (klo + khi) >> 1;
+                if (ba.round_start[mid] <= ticket) klo = mid;
+                else khi = mid;
+            }
+            round = __builtin_amdgcn_readfirstlane(klo);
+            rem = __builtin_amdgcn_readfirstlane((uint32_t)(ticket - ba.round_start[round]));
+            nmem = ba.round_members[round];
+        } else {
+            round = __builtin_amdgcn_readfirstlane((uint32_t)(ticket / ba.per_round));
+            rem = __builtin_amdgcn_readfirstlane((uint32_t)(ticket - (uint64_t)round * ba.per_round));
+            nmem = ba.n;
+        }
         // member r: the last one with bprefix[r] <= rem
-        uint32_t lo = 0, hi = ba.n;
+        uint32_t lo = 0, hi = nmem;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
             if (ba.bprefix[mid] <= rem) lo = mid;
@@ -1140,6 +1164,8 @@ kpz_status batch_sweep_on(kpz_batch *b, int32_t n_mcs, hipStream_t st)
     ba.n = (uint32_t)b->n;
     ba.per_round = b->per_round;
     ba.rounds = (uint32_t)n_mcs;
+    ba.round_start = nullptr;
+    ba.round_members = nullptr;
     hipError_t e = batch_launch(b, ba, st);
     if (e != hipSuccess) return batch_fail(b, e, "kpz_batch_sweep launch");
     hipLaunchKernelGGL(kpz_batch_advance_kernel, dim3((b->n + 255) / 256), dim3(256), 0, st,
@@ -1186,6 +1212,153 @@ kpz_status convert_moments(const long long *res, int64_t L, int64_t *S1o, int64_
     if (S1o) *S1o = (int64_t)S1;
     if (S2o) *S2o = (int64_t)S2;
     return st;
+}
+
+}  // namespace
+
+
+// ------------------------------------------------------------ job pool host
+
+namespace {
+
+struct PoolJob {
+    int64_t id;
+    kpz_params prm;
+    int64_t t, n_mcs;
+    size_t off, bytes;        // arena extent
+    size_t off_words, off_slots, off_rowA, off_rowB, off_side;
+};
+
+struct PoolResult {
+    int64_t id, S1, S2;
+    double W2;
+    kpz_status st;
+};
+
+size_t pool_job_bytes_raw(int64_t L, uint32_t Bx)
+{
+    return align256((size_t)L * L / 4) + align256(sizeof(long long) * BATCH_SLOTS) +
+           2 * align256(8 * (size_t)L) + align256(4 * 2 * (size_t)L * (size_t)(L / Bx));
+}
+
+struct PoolCtl {
+    size_t off_ctl, off_members, off_bprefix, off_rstart, off_rmem, off_rows, off_res, bytes;
+};
+
+PoolCtl pool_ctl_layout(int32_t max_jobs, int32_t max_quantum)
+{
+    PoolCtl c;
+    size_t o = 0;
+    c.off_ctl = o;      o = align256(o + 4 * (64 + 2 * (size_t)max_jobs));
+    c.off_members = o;  o = align256(o + sizeof(SweepArgs) * (size_t)max_jobs);
+    c.off_bprefix = o;  o = align256(o + 4 * ((size_t)max_jobs + 1));
+    c.off_rstart = o;   o = align256(o + 8 * ((size_t)max_quantum + 1));
+    c.off_rmem = o;     o = align256(o + 4 * ((size_t)max_quantum + 1));
+    c.off_rows = o;     o = align256(o + sizeof(MemberRows) * (size_t)max_jobs);
+    c.off_res = o;      o = align256(o + 4 * sizeof(long long) * (size_t)max_jobs);
+    c.bytes = o;
+    return c;
+}
+
+}  // namespace
+
+struct kpz_pool {
+    uint8_t *arena;
+    size_t arena_bytes;
+    int32_t max_jobs, max_quantum;
+    uint32_t Bx, By, tpb, K, ntx, nq, grid;
+    size_t shmem;
+    hipStream_t stream;
+    PoolCtl ctl;
+    std::map<size_t, size_t> free_list;   // offset -> bytes (heap part of the arena)
+    std::vector<PoolJob> jobs;            // resident
+    std::deque<PoolResult> done;
+    int64_t next_id;
+    char err[256];
+};
+
+namespace {
+
+bool pool_alloc(kpz_pool *p, size_t bytes, size_t *off)
+{
+    for (auto it = p->free_list.begin(); it != p->free_list.end(); ++it) {
+        if (it->second >= bytes) {
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t roff = it->first + bytes;
+            p->free_list.erase(it);
+            if (rest) p->free_list[roff] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+void pool_free(kpz_pool *p, size_t off, size_t bytes)
+{
+    auto it = p->free_list.emplace(off, bytes).first;
+    // merge with the following and the preceding extents
+    auto nx = std::next(it);
+    if (nx != p->free_list.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        p->free_list.erase(nx);
+    }
+    if (it != p->free_list.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            p->free_list.erase(it);
+        }
+    }
+}
+
+kpz_status pool_fail(kpz_pool *p, hipError_t e, const char *what)
+{
+    if (p) snprintf(p->err, sizeof p->err, "%s: %s", what, hipGetErrorString(e));
+    return KPZ_EHIP;
+}
+
+SweepArgs pool_args(const kpz_pool *p, const PoolJob &j)
+{
+    SweepArgs a;
+    const uint32_t L = (uint32_t)j.prm.L;
+    a.words = (uint32_t *)(p->arena + j.off_words);
+    a.side = (uint32_t *)(p->arena + j.off_side);
+    a.slots = (unsigned long long *)(p->arena + j.off_slots);
+    a.L = L;
+    a.W = L / 16;
+    a.Bx = p->Bx;
+    a.By = p->By;
+    a.nbx = L / p->Bx;
+    a.nby = L / p->By;
+    a.ntx = p->Bx / TILE;
+    a.log2ntx = (uint32_t)ilog2(a.ntx);
+    a.H = p->By / 16;
+    a.log2H = (uint32_t)ilog2(a.H);
+    a.nq = a.ntx * a.H;
+    a.nw = p->Bx / 16;
+    a.log2nw = (uint32_t)ilog2(a.nw);
+    a.units = a.nw * a.H * 2;
+    a.seed_lo = (uint32_t)j.prm.seed;
+    a.seed_hi = (uint32_t)(j.prm.seed >> 32);
+    a.t = (uint32_t)j.t;
+    a.slot_mask = BATCH_SLOTS - 1;
+    a.P = threshold(j.prm.p);
+    a.Q = threshold(j.prm.q);
+    a.acc = !(a.P == (1ull << 32) && a.Q == 0);
+    return a;
+}
+
+// Persistent launch over the members currently in the pool's tables.
+hipError_t pool_launch(kpz_pool *p, const BatchArgs &ba)
+{
+    kpz_batch tmp;
+    tmp.tpb = p->tpb;
+    tmp.K = p->K;
+    tmp.ntx = p->ntx;
+    tmp.grid = p->grid;
+    tmp.shmem = p->shmem;
+    return batch_launch(&tmp, ba, p->stream);
 }
 
 }  // namespace
@@ -1632,5 +1805,280 @@ kpz_status kpz_batch_get_t(const kpz_batch *b, int64_t *t)
 void kpz_batch_destroy(kpz_batch *b) { delete b; }
 
 const char *kpz_batch_last_error(const kpz_batch *b) { return b ? b->err : ""; }
+
+
+kpz_status kpz_pool_job_bytes(const kpz_params *job, int32_t bx, int32_t by, size_t *bytes)
+{
+    if (!job || !bytes) return KPZ_EINVAL;
+    kpz_params q = *job;
+    q.block_x = bx;
+    q.block_y = by;
+    uint32_t rbx, rby;
+    const kpz_status st = resolve(&q, &rbx, &rby);
+    if (st != KPZ_OK) return st;
+    *bytes = pool_job_bytes_raw(job->L, rbx);
+    return KPZ_OK;
+}
+
+kpz_status kpz_pool_control_bytes(int32_t max_jobs, int32_t max_quantum, size_t *bytes)
+{
+    if (max_jobs < 1 || max_quantum < 1 || !bytes) return KPZ_EINVAL;
+    *bytes = pool_ctl_layout(max_jobs, max_quantum).bytes;
+    return KPZ_OK;
+}
+
+kpz_status kpz_pool_init(kpz_pool **out, void *d_arena, size_t arena_bytes, int32_t max_jobs,
+                         int32_t max_quantum, int32_t bx, int32_t by, void *stream)
+{
+    if (!out) return KPZ_EINVAL;
+    *out = nullptr;
+    if (!d_arena || ((uintptr_t)d_arena & 255) || max_jobs < 1 || max_quantum < 1) return KPZ_EINVAL;
+    if (!is_pow2(bx) || !is_pow2(by) || bx < 16 || by < 16 || bx > 1024 || (int64_t)bx * by > 65536)
+        return KPZ_EINVAL;
+    const PoolCtl ctl = pool_ctl_layout(max_jobs, max_quantum);
+    if (arena_bytes < ctl.bytes) return KPZ_ESIZE;
+    kpz_pool *p = new (std::nothrow) kpz_pool();
+    if (!p) return KPZ_EINVAL;
+    p->arena = (uint8_t *)d_arena;
+    p->arena_bytes = arena_bytes;
+    p->max_jobs = max_jobs;
+    p->max_quantum = max_quantum;
+    p->Bx = (uint32_t)bx;
+    p->By = (uint32_t)by;
+    p->ntx = p->Bx / TILE;
+    p->nq = p->ntx * (p->By / 16);
+    p->tpb = p->nq >= 256 ? 256u : 64u;
+    p->K = p->nq <= p->tpb ? 1u : p->nq / p->tpb;
+    p->shmem = sizeof(uint32_t) * 4 * (size_t)p->nq;
+    p->stream = (hipStream_t)stream;
+    p->ctl = ctl;
+    p->next_id = 0;
+    p->err[0] = 0;
+    if ((p->tpb == 256 && p->K > 4) || (p->tpb == 64 && p->K > 2)) {
+        delete p;
+        return KPZ_EINVAL;
+    }
+    if (arena_bytes > ctl.bytes) p->free_list[ctl.bytes] = arena_bytes - ctl.bytes;
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_fn(p->tpb, p->K, p->ntx),
+                                                         (int)p->tpb, p->shmem);
+    if (e != hipSuccess) {
+        pool_fail(p, e, "kpz_pool_init");
+        delete p;
+        return KPZ_EHIP;
+    }
+    p->grid = (uint32_t)(cus * (per_cu > 0 ? per_cu : 1));
+    *out = p;
+    return KPZ_OK;
+}
+
+kpz_status kpz_pool_submit(kpz_pool *p, const kpz_params *job, int64_t n_mcs, int64_t *id)
+{
+    if (!p || !job || n_mcs < 1 || n_mcs > 0xFFFFFFFFll) return KPZ_EINVAL;
+    kpz_params q = *job;
+    q.block_x = (int32_t)p->Bx;
+    q.block_y = (int32_t)p->By;
+    if ((job->block_x && job->block_x != (int32_t)p->Bx) ||
+        (job->block_y && job->block_y != (int32_t)p->By))
+        return KPZ_EINVAL;
+    uint32_t rbx, rby;
+    kpz_status st = resolve(&q, &rbx, &rby);
+    if (st != KPZ_OK) return st;
+    const size_t bytes = pool_job_bytes_raw(q.L, p->Bx);
+    if (bytes > p->arena_bytes - p->ctl.bytes) return KPZ_EINVAL;
+    if ((int32_t)p->jobs.size() >= p->max_jobs) return KPZ_ESIZE;
+    size_t off;
+    if (!pool_alloc(p, bytes, &off)) return KPZ_ESIZE;
+    PoolJob j;
+    j.id = p->next_id++;
+    j.prm = q;
+    j.t = 0;
+    j.n_mcs = n_mcs;
+    j.off = off;
+    j.bytes = bytes;
+    const size_t L = (size_t)q.L;
+    size_t o = off;
+    j.off_words = o; o += align256(L * L / 4);
+    j.off_slots = o; o += align256(sizeof(long long) * BATCH_SLOTS);
+    j.off_rowA = o;  o += align256(8 * L);
+    j.off_rowB = o;  o += align256(8 * L);
+    j.off_side = o;
+    const uint32_t W = (uint32_t)(L / 16);
+    uint32_t *words = (uint32_t *)(p->arena + j.off_words);
+    if (W % 4 == 0) {
+        const uint64_t n4 = (uint64_t)L * L / 64;
+        const uint32_t blocks = (uint32_t)((n4 + 255) / 256 < 65536 ? (n4 + 255) / 256 : 65536);
+        hipLaunchKernelGGL(kpz_init_kernel, dim3(blocks), dim3(256), 0, p->stream, (uint4 *)words, n4,
+                           W / 4);
+    } else {
+        hipLaunchKernelGGL(kpz_init_small_kernel, dim3(1), dim3(256), 0, p->stream, words,
+                           (uint32_t)(L * L / 16), W);
+    }
+    hipLaunchKernelGGL(kpz_zero_kernel, dim3(1), dim3(256), 0, p->stream,
+                       (uint32_t *)(p->arena + j.off_slots), (uint64_t)2 * BATCH_SLOTS);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        pool_free(p, off, bytes);
+        return pool_fail(p, e, "kpz_pool_submit launch");
+    }
+    p->jobs.push_back(j);
+    if (id) *id = j.id;
+    return KPZ_OK;
+}
+
+kpz_status kpz_pool_step(kpz_pool *p, int32_t quantum, int32_t *n_active)
+{
+    if (!p || quantum < 1 || quantum > p->max_quantum) return KPZ_EINVAL;
+    const size_t n = p->jobs.size();
+    if (n == 0) {
+        if (n_active) *n_active = 0;
+        return KPZ_OK;
+    }
+    // members sorted by decreasing rounds this step
+    std::vector<size_t> order(n);
+    for (size_t i = 0; i < n; ++i) order[i] = i;
+    auto rounds_of = [&](size_t i) {
+        const int64_t rem = p->jobs[i].n_mcs - p->jobs[i].t;
+        return (uint32_t)(rem < quantum ? rem : quantum);
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return rounds_of(a) > rounds_of(b); });
+    std::vector<SweepArgs> args(n);
+    std::vector<uint32_t> bprefix(n + 1, 0), rounds(n);
+    for (size_t k = 0; k < n; ++k) {
+        const PoolJob &j = p->jobs[order[k]];
+        args[k] = pool_args(p, j);
+        rounds[k] = rounds_of(order[k]);
+        bprefix[k + 1] = bprefix[k] + args[k].nbx * args[k].nby;
+    }
+    const uint32_t R = rounds[0];
+    std::vector<unsigned long long> rstart(R + 1, 0);
+    std::vector<uint32_t> rmem(R + 1, 0);
+    size_t m = n;
+    for (uint32_t k = 0; k < R; ++k) {
+        while (m > 0 && rounds[m - 1] <= k) --m;   // members with rounds > k: [0, m)
+        rmem[k] = (uint32_t)m;
+        rstart[k + 1] = rstart[k] + bprefix[m];
+    }
+    hipError_t e = hipSuccess;
+    auto h2d = [&](size_t off, const void *src, size_t bytes) {
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(p->arena + off, src, bytes, hipMemcpyHostToDevice, p->stream);
+    };
+    h2d(p->ctl.off_members, args.data(), sizeof(SweepArgs) * n);
+    h2d(p->ctl.off_bprefix, bprefix.data(), 4 * (n + 1));
+    h2d(p->ctl.off_rstart, rstart.data(), 8 * ((size_t)R + 1));
+    h2d(p->ctl.off_rmem, rmem.data(), 4 * ((size_t)R + 1));
+    if (e != hipSuccess) return pool_fail(p, e, "kpz_pool_step copy");
+    hipLaunchKernelGGL(kpz_batch_reset_kernel, dim3(1), dim3(256), 0, p->stream,
+                       (unsigned int *)(p->arena + p->ctl.off_ctl), (uint32_t)n);
+    BatchArgs ba;
+    ba.members = (const SweepArgs *)(p->arena + p->ctl.off_members);
+    ba.bprefix = (const uint32_t *)(p->arena + p->ctl.off_bprefix);
+    ba.round_start = (const unsigned long long *)(p->arena + p->ctl.off_rstart);
+    ba.round_members = (const uint32_t *)(p->arena + p->ctl.off_rmem);
+    ba.ctl = (unsigned int *)(p->arena + p->ctl.off_ctl);
+    ba.n = (uint32_t)n;
+    ba.per_round = bprefix[n];
+    ba.rounds = R;
+    e = pool_launch(p, ba);
+    if (e != hipSuccess) return pool_fail(p, e, "kpz_pool_step launch");
+    for (size_t k = 0; k < n; ++k) p->jobs[order[k]].t += rounds[k];
+    // sample and release the jobs that reached their n_mcs
+    std::vector<size_t> fin;
+    for (size_t i = 0; i < n; ++i)
+        if (p->jobs[i].t >= p->jobs[i].n_mcs) fin.push_back(i);
+    if (!fin.empty()) {
+        std::vector<MemberRows> rows(fin.size());
+        std::vector<uint32_t> rprefix(fin.size() + 1, 0);
+        for (size_t f = 0; f < fin.size(); ++f) {
+            const PoolJob &j = p->jobs[fin[f]];
+            rows[f].words = (const uint32_t *)(p->arena + j.off_words);
+            rows[f].rowA = (long long *)(p->arena + j.off_rowA);
+            rows[f].rowB = (long long *)(p->arena + j.off_rowB);
+            rows[f].slots = (const long long *)(p->arena + j.off_slots);
+            rows[f].L = (uint32_t)j.prm.L;
+            rows[f].W = (uint32_t)(j.prm.L / 16);
+            rprefix[f + 1] = rprefix[f] + (uint32_t)j.prm.L;
+        }
+        h2d(p->ctl.off_rows, rows.data(), sizeof(MemberRows) * fin.size());
+        // the bprefix area is free again once the launch has read it; reuse it
+        // (stream order) for the row prefix of the finished jobs
+        h2d(p->ctl.off_bprefix, rprefix.data(), 4 * (fin.size() + 1));
+        if (e != hipSuccess) return pool_fail(p, e, "kpz_pool_step copy");
+        const uint32_t total_rows = rprefix[fin.size()];
+        const uint32_t rgrid = (total_rows + 3) / 4 < 8192 ? (total_rows + 3) / 4 : 8192;
+        const MemberRows *mr = (const MemberRows *)(p->arena + p->ctl.off_rows);
+        hipLaunchKernelGGL(kpz_batch_rows_kernel, dim3(rgrid), dim3(256), 0, p->stream, mr,
+                           (const uint32_t *)(p->arena + p->ctl.off_bprefix), (uint32_t)fin.size());
+        hipLaunchKernelGGL(kpz_batch_finalize_kernel, dim3((uint32_t)fin.size()), dim3(256), 0,
+                           p->stream, mr, (uint32_t)fin.size(), (uint32_t)BATCH_SLOTS,
+                           (long long *)(p->arena + p->ctl.off_res), 0u);
+        e = hipGetLastError();
+        std::vector<long long> res(4 * fin.size());
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(res.data(), p->arena + p->ctl.off_res, res.size() * sizeof(long long),
+                               hipMemcpyDeviceToHost, p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) return pool_fail(p, e, "kpz_pool_step sample");
+        for (size_t f = 0; f < fin.size(); ++f) {
+            const PoolJob &j = p->jobs[fin[f]];
+            PoolResult r;
+            r.id = j.id;
+            r.st = convert_moments(&res[4 * f], j.prm.L, &r.S1, &r.S2, &r.W2, p->err, sizeof p->err);
+            p->done.push_back(r);
+            pool_free(p, j.off, j.bytes);
+        }
+        std::vector<PoolJob> keep;
+        keep.reserve(n - fin.size());
+        size_t f = 0;
+        for (size_t i = 0; i < n; ++i) {
+            if (f < fin.size() && fin[f] == i) { ++f; continue; }
+            keep.push_back(p->jobs[i]);
+        }
+        p->jobs.swap(keep);
+    }
+    if (n_active) *n_active = (int32_t)p->jobs.size();
+    return KPZ_OK;
+}
+
+kpz_status kpz_pool_poll(kpz_pool *p, int32_t max_results, int64_t *ids, int64_t *S1, int64_t *S2,
+                         double *W2, int32_t *n_results)
+{
+    if (!p || max_results < 0) return KPZ_EINVAL;
+    int32_t k = 0;
+    kpz_status worst = KPZ_OK;
+    while (k < max_results && !p->done.empty()) {
+        const PoolResult &r = p->done.front();
+        if (ids) ids[k] = r.id;
+        if (S1) S1[k] = r.S1;
+        if (S2) S2[k] = r.S2;
+        if (W2) W2[k] = r.W2;
+        if (r.st != KPZ_OK && worst == KPZ_OK) worst = r.st;
+        p->done.pop_front();
+        ++k;
+    }
+    if (n_results) *n_results = k;
+    return worst;
+}
+
+kpz_status kpz_pool_stats(const kpz_pool *p, int32_t *n_active, size_t *largest_free)
+{
+    if (!p) return KPZ_EINVAL;
+    if (n_active) *n_active = (int32_t)p->jobs.size();
+    if (largest_free) {
+        size_t m = 0;
+        for (const auto &kv : p->free_list) m = kv.second > m ? kv.second : m;
+        *largest_free = m;
+    }
+    return KPZ_OK;
+}
+
+void kpz_pool_destroy(kpz_pool *p) { delete p; }
+
+const char *kpz_pool_last_error(const kpz_pool *p) { return p ? p->err : ""; }
 
 }  // extern "C"

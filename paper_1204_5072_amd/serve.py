@@ -1,0 +1,110 @@
+"""Serving loop: simulation jobs arrive over time, are admitted into a
+device job pool by HBM budget, run with continuous batching, and leave with
+their exact final W^2.  Reports p50/p99 job latency (arrival -> result) and
+throughput."""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import Pool, make_params
+
+
+@dataclass
+class Job:
+    arrival: float       # seconds after the start of the run
+    L: int
+    p: float
+    q: float
+    seed: int
+    n_mcs: int
+    jid: Optional[int] = None
+    admitted: Optional[float] = None
+    finished: Optional[float] = None
+    result: object = None
+
+
+def poisson_jobs(n_jobs: int = 2000, rate: float = 50.0, seed: int = 0,
+                 log2L=(8, 13), log10_mcs=(2.0, 4.0), q_max: float = 0.5) -> List[Job]:
+    """Poisson arrivals; L = 2^k with k uniform on the integers of log2L
+    (log-uniform over powers of two); MCS = round(10^U), U uniform on
+    log10_mcs; p = 1, q uniform on [0, q_max]; seed = job number."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=n_jobs)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    ks = rng.integers(log2L[0], log2L[1] + 1, size=n_jobs)
+    mcs = np.round(10.0 ** rng.uniform(log10_mcs[0], log10_mcs[1], size=n_jobs)).astype(int)
+    qs = rng.uniform(0.0, q_max, size=n_jobs)
+    return [Job(float(arrivals[i]), int(2 ** ks[i]), 1.0, float(qs[i]), i, int(mcs[i]))
+            for i in range(n_jobs)]
+
+
+@dataclass
+class ServeReport:
+    jobs: int
+    seconds: float
+    attempts: float
+    latency_p50_ms: float
+    latency_p99_ms: float
+    latency_max_ms: float
+    steps: int
+    max_resident: int
+    extra: Dict = field(default_factory=dict)
+
+    @property
+    def attempts_per_s(self) -> float:
+        return self.attempts / self.seconds
+
+
+def serve(jobs: List[Job], hbm_bytes: int, quantum: int = 64, block=(256, 256),
+          max_jobs: int = 1024, clock=time.perf_counter) -> ServeReport:
+    """Runs the jobs in real time: a job becomes visible at its arrival time,
+    waits FIFO until it fits into the pool, and is done when its result is
+    back on the host."""
+    pool = Pool(hbm_bytes, max_jobs=max_jobs, max_quantum=quantum, block=block)
+    pending = deque(sorted(jobs, key=lambda j: j.arrival))
+    waiting: deque = deque()
+    by_id: Dict[int, Job] = {}
+    t0 = clock()
+    steps = 0
+    resident = 0
+    max_resident = 0
+    done = 0
+    while done < len(jobs):
+        now = clock() - t0
+        while pending and pending[0].arrival <= now:
+            waiting.append(pending.popleft())
+        while waiting:
+            j = waiting[0]
+            jid = pool.submit(make_params(j.L, j.p, j.q, j.seed, block), j.n_mcs)
+            if jid is None:
+                break
+            j.jid, j.admitted = jid, clock() - t0
+            by_id[jid] = j
+            waiting.popleft()
+            resident += 1
+        if resident == 0:
+            # idle until the next arrival
+            if pending:
+                delay = pending[0].arrival - (clock() - t0)
+                if delay > 0:
+                    time.sleep(min(delay, 0.01))
+            continue
+        max_resident = max(max_resident, resident)
+        resident = pool.step(quantum)
+        steps += 1
+        now = clock() - t0
+        for jid, mom in pool.poll():
+            j = by_id.pop(jid)
+            j.finished, j.result = now, mom
+            done += 1
+    seconds = clock() - t0
+    pool.close()
+    lat = np.array([(j.finished - j.arrival) * 1e3 for j in jobs])
+    attempts = float(sum(j.L * j.L * j.n_mcs for j in jobs))
+    return ServeReport(len(jobs), seconds, attempts, float(np.percentile(lat, 50)),
+                       float(np.percentile(lat, 99)), float(lat.max()), steps, max_resident)
