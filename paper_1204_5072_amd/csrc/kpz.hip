@@ -131,6 +131,7 @@ __global__ void kpz_fill_counters_kernel(long long *slots, long long first)
 struct SweepArgs {
     uint32_t *words;
     uint32_t *side;              // [2][L][nbx]: straddling-word parts (left edge, right edge)
+    uint32_t *pairs;             // [nby][nbx]: arrivals at the pair (bx-1, bx), two per MCS
     unsigned long long *slots;   // NSLOTS flip counters
     uint32_t L, W;               // size, words per row
     uint32_t Bx, By;             // block shape
@@ -432,7 +433,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
     // ---- store: quads -> cells -> aligned block words -> HBM row words.
     // Words wholly inside the block are stored; the block's parts of the two
     // words it shares with its left and right neighbours go to the side
-    // buffer and are merged by kpz_merge_kernel.
+    // buffer and are merged below.
     for (int it = 0; it < UIT; ++it) {
         const uint32_t u = tid + (uint32_t)TPB * it;
         const bool uok = u < a.units;
@@ -477,6 +478,42 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
         }
     }
 
+    // ---- the shared words: of the two blocks of a pair (bx-1, bx) the one
+    // that arrives second (odd count) ORs both parts into the lattice
+    if (sh2 != 0) {
+        __shared__ uint32_t s_merge;
+        __threadfence();   // release this block's side-buffer parts
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t m = 1u;   // a single block per row owns both parts itself
+            if (a.nbx > 1) {
+                const uint32_t rowb = by * a.nbx;
+                m = 0u;
+                if (atomicAdd(a.pairs + rowb + bx, 1u) & 1u) m |= 1u;
+                if (atomicAdd(a.pairs + rowb + (bx + 1 == a.nbx ? 0 : bx + 1), 1u) & 1u) m |= 2u;
+            }
+            s_merge = m;
+        }
+        __syncthreads();
+        const uint32_t m = s_merge;
+        if (m) {
+            __threadfence();   // acquire the neighbour's parts
+            const uint32_t bl = bx == 0 ? a.nbx - 1 : bx - 1;
+            const uint32_t br = bx + 1 == a.nbx ? 0 : bx + 1;
+            uint32_t gwe = gw0 + nw;
+            if (gwe >= a.W) gwe -= a.W;
+            for (uint32_t r = tid; r < a.By; r += TPB) {
+                uint32_t gy = gy0 + r;
+                if (gy >= a.L) gy -= a.L;
+                uint32_t *row = a.words + (size_t)gy * a.W;
+                const uint32_t *sl = a.side + (size_t)gy * a.nbx;              // left-edge parts
+                const uint32_t *sr = a.side + ((size_t)a.L + gy) * a.nbx;      // right-edge parts
+                if (m & 1u) row[gw0] = sr[bl] | sl[bx];
+                if (m & 2u) row[gwe] = sr[bx] | sl[br];
+            }
+        }
+    }
+
     // ---- flip counter of this block: wave sums, one atomic per wave
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) net += __shfl_xor(net, off, 64);
@@ -490,31 +527,6 @@ __global__ __launch_bounds__(TPB) void kpz_sweep_kernel(const SweepArgs a)
 {
     extern __shared__ uint32_t lds[];
     sweep_block<TPB, K, NTX, ACC>(a, blockIdx.x, lds);
-}
-
-// Straddling words of MCS a.t: the word at the left edge of block column bx
-// in row gy holds the last sites of block bx-1 (low bits) and the first
-// sites of block bx (high bits); both parts were written to the side buffer.
-__device__ __forceinline__ void merge_straddles(const SweepArgs &a, uint64_t first, uint64_t stride)
-{
-    const U4 wo = philox(0u, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
-    const uint32_t ox = (uint32_t)(((uint64_t)wo.x * a.Bx) >> 32);
-    if ((ox & 15u) == 0) return;
-    const uint64_t n = (uint64_t)a.L * a.nbx;
-    for (uint64_t i = first; i < n; i += stride) {
-        const uint32_t gy = (uint32_t)(i / a.nbx), bx = (uint32_t)(i % a.nbx);
-        uint32_t gw = (ox >> 4) + bx * a.nw;
-        if (gw >= a.W) gw -= a.W;
-        const uint32_t left = a.side[((size_t)a.L + gy) * a.nbx + (bx == 0 ? a.nbx - 1 : bx - 1)];
-        const uint32_t right = a.side[(size_t)gy * a.nbx + bx];
-        a.words[(size_t)gy * a.W + gw] = left | right;
-    }
-}
-
-__global__ void kpz_merge_kernel(const SweepArgs a)
-{
-    merge_straddles(a, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x,
-                    (uint64_t)gridDim.x * blockDim.x);
 }
 
 // ------------------------------------------------------------ roughness
@@ -712,8 +724,7 @@ __global__ __launch_bounds__(1024) void kpz_finalize_kernel(const uint32_t *word
 // (round, member, block); the block of member r at round k + 1 waits only
 // until member r's round k is complete, so members never wait for each
 // other.  The work-group that finishes the last block of a member's round
-// merges that member's straddling words and then publishes the round
-// (agent-scope release; the waiting side acquires).
+// publishes the round (agent-scope release; the waiting side acquires).
 
 struct MemberRows {
     const uint32_t *words;
@@ -743,7 +754,6 @@ __global__ __launch_bounds__(TPB) void kpz_batch_kernel(const BatchArgs ba)
 {
     extern __shared__ uint32_t lds[];
     __shared__ unsigned long long s_ticket;
-    __shared__ unsigned int s_last;
     const uint64_t total = ba.round_start ? ba.round_start[ba.rounds]
                                           : (uint64_t)ba.per_round * ba.rounds;
     unsigned int *const done = ba.ctl + 64;
@@ -791,20 +801,14 @@ __global__ __launch_bounds__(TPB) void kpz_batch_kernel(const BatchArgs ba)
         }
         if (a.acc) sweep_block<TPB, K, NTX, true>(a, b, lds);
         else sweep_block<TPB, K, NTX, false>(a, b, lds);
+        // the block (its merges included) is complete: count it; the last
+        // block of the member's round publishes the round
         __threadfence();
         __syncthreads();
         if (threadIdx.x == 0) {
             const unsigned int nb = ba.bprefix[r + 1] - ba.bprefix[r];
             const unsigned int old = atomicAdd(done + r, 1u);
-            s_last = (old + 1 == (round + 1) * nb) ? 1u : 0u;
-        }
-        __syncthreads();
-        if (s_last) {
-            __threadfence();   // acquire: the other blocks' side-buffer parts
-            merge_straddles(a, threadIdx.x, TPB);
-            __threadfence();
-            __syncthreads();
-            if (threadIdx.x == 0)
+            if (old + 1 == (round + 1) * nb)
                 __hip_atomic_store(ready + r, round + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
@@ -927,12 +931,14 @@ kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
     return KPZ_OK;
 }
 
-size_t ws_needed(int64_t L, int64_t Bx)
+size_t ws_needed(int64_t L, int64_t Bx, int64_t By)
 {
-    // header, flip-counter slots, two int64 per row (row moments), and the
-    // side buffer of the straddling words: two uint32 per (row, block column)
+    // header, flip-counter slots, two int64 per row (row moments), the side
+    // buffer of the straddling words (two uint32 per row and block column)
+    // and one pair counter per block
     return (size_t)WS_HEADER + sizeof(long long) * NSLOTS + 2 * sizeof(long long) * (size_t)L +
-           2 * sizeof(uint32_t) * (size_t)L * (size_t)(L / Bx);
+           2 * sizeof(uint32_t) * (size_t)L * (size_t)(L / Bx) +
+           sizeof(uint32_t) * (size_t)(L / Bx) * (size_t)(L / By);
 }
 
 kpz_status hip_fail(kpz_sim *s, hipError_t e, const char *what)
@@ -946,6 +952,10 @@ long long *ws_slots(kpz_sim *s) { return (long long *)(s->ws + WS_HEADER); }
 long long *ws_rowA(kpz_sim *s) { return ws_slots(s) + NSLOTS; }
 long long *ws_rowB(kpz_sim *s) { return ws_rowA(s) + s->prm.L; }
 uint32_t *ws_side(kpz_sim *s) { return (uint32_t *)(ws_rowB(s) + s->prm.L); }
+uint32_t *ws_pairs(kpz_sim *s)
+{
+    return ws_side(s) + 2 * (size_t)s->prm.L * (size_t)(s->prm.L / s->Bx);
+}
 
 template <int TPB, int K, int NTX, bool ACC>
 hipError_t launch_sweep_k(const SweepArgs &a, uint32_t nblocks, size_t shmem, hipStream_t st)
@@ -1008,7 +1018,7 @@ struct BatchLayout {
     std::vector<size_t> word_off;   // per member, in words
     size_t words_bytes;
     size_t off_ctl, off_members, off_bprefix, off_rprefix, off_rows, off_res, off_slots;
-    std::vector<size_t> off_rowA, off_rowB, off_side;
+    std::vector<size_t> off_rowA, off_rowB, off_side, off_pairs;
     size_t ws_bytes;
 };
 
@@ -1051,11 +1061,13 @@ kpz_status batch_layout(const kpz_params *m, int32_t n, BatchLayout *lay)
     lay->off_rowA.resize(n);
     lay->off_rowB.resize(n);
     lay->off_side.resize(n);
+    lay->off_pairs.resize(n);
     for (int32_t r = 0; r < n; ++r) {
         const size_t L = (size_t)m[r].L;
         lay->off_rowA[r] = o; o = align256(o + 8 * L);
         lay->off_rowB[r] = o; o = align256(o + 8 * L);
         lay->off_side[r] = o; o = align256(o + 4 * 2 * L * (L / lay->Bx));
+        lay->off_pairs[r] = o; o = align256(o + 4 * (L / lay->Bx) * (L / lay->By));
     }
     lay->ws_bytes = o;
     return KPZ_OK;
@@ -1226,7 +1238,7 @@ struct PoolJob {
     kpz_params prm;
     int64_t t, n_mcs;
     size_t off, bytes;        // arena extent
-    size_t off_words, off_slots, off_rowA, off_rowB, off_side;
+    size_t off_words, off_slots, off_rowA, off_rowB, off_side, off_pairs;
 };
 
 struct PoolResult {
@@ -1235,10 +1247,11 @@ struct PoolResult {
     kpz_status st;
 };
 
-size_t pool_job_bytes_raw(int64_t L, uint32_t Bx)
+size_t pool_job_bytes_raw(int64_t L, uint32_t Bx, uint32_t By)
 {
     return align256((size_t)L * L / 4) + align256(sizeof(long long) * BATCH_SLOTS) +
-           2 * align256(8 * (size_t)L) + align256(4 * 2 * (size_t)L * (size_t)(L / Bx));
+           2 * align256(8 * (size_t)L) + align256(4 * 2 * (size_t)L * (size_t)(L / Bx)) +
+           align256(4 * (size_t)(L / Bx) * (size_t)(L / By));
 }
 
 struct PoolCtl {
@@ -1324,6 +1337,7 @@ SweepArgs pool_args(const kpz_pool *p, const PoolJob &j)
     const uint32_t L = (uint32_t)j.prm.L;
     a.words = (uint32_t *)(p->arena + j.off_words);
     a.side = (uint32_t *)(p->arena + j.off_side);
+    a.pairs = (uint32_t *)(p->arena + j.off_pairs);
     a.slots = (unsigned long long *)(p->arena + j.off_slots);
     a.L = L;
     a.W = L / 16;
@@ -1386,7 +1400,7 @@ kpz_status kpz_workspace_bytes(const kpz_params *p, size_t *bytes)
     const kpz_status st = resolve(p, &bx, &by);
     if (st != KPZ_OK) return st;
     if (!bytes) return KPZ_EINVAL;
-    *bytes = ws_needed(p->L, bx);
+    *bytes = ws_needed(p->L, bx, by);
     return KPZ_OK;
 }
 
@@ -1400,7 +1414,7 @@ kpz_status kpz_init(kpz_sim **out, const kpz_params *p, uint32_t *d_words, size_
     if (st != KPZ_OK) return st;
     if (!d_words || !d_ws) return KPZ_EINVAL;
     const uint64_t L = (uint64_t)p->L;
-    if (words_bytes < L * L / 4 || ws_bytes < ws_needed(p->L, bx)) return KPZ_ESIZE;
+    if (words_bytes < L * L / 4 || ws_bytes < ws_needed(p->L, bx, by)) return KPZ_ESIZE;
     kpz_sim *s = new (std::nothrow) kpz_sim();
     if (!s) return KPZ_EINVAL;
     s->prm = *p;
@@ -1430,6 +1444,9 @@ kpz_status kpz_init(kpz_sim **out, const kpz_params *p, uint32_t *d_words, size_
     if (e == hipSuccess) {
         hipLaunchKernelGGL(kpz_fill_counters_kernel, dim3(NSLOTS / 256), dim3(256), 0, s->stream,
                            ws_slots(s), 0LL);
+        const uint64_t npairs = (L / bx) * (L / by);
+        hipLaunchKernelGGL(kpz_zero_kernel, dim3((uint32_t)((npairs + 255) / 256 < 4096 ? (npairs + 255) / 256 : 4096)),
+                           dim3(256), 0, s->stream, ws_pairs(s), npairs);
         e = hipGetLastError();
     }
     if (e != hipSuccess) {
@@ -1450,6 +1467,7 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     SweepArgs a;
     a.words = s->words;
     a.side = ws_side(s);
+    a.pairs = ws_pairs(s);
     a.slots = (unsigned long long *)ws_slots(s);
     a.L = L;
     a.W = L / 16;
@@ -1481,17 +1499,12 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     const uint32_t K = a.nq <= tpb ? 1u : a.nq / tpb;
     const uint32_t nblocks = a.nbx * a.nby;
     const size_t shmem = sizeof(uint32_t) * 4 * (size_t)a.nq;
-    const uint64_t nmerge = (uint64_t)L * a.nbx;
-    const uint32_t mgrid = (uint32_t)((nmerge + 255) / 256 < 8192 ? (nmerge + 255) / 256 : 8192);
     const bool acc = !(s->P == (1ull << 32) && s->Q == 0);
     for (int32_t m = 0; m < n_mcs; ++m) {
         a.t = (uint32_t)(s->t + m);
         hipError_t e = acc ? launch_sweep<true>(a, tpb, K, nblocks, shmem, s->stream)
                            : launch_sweep<false>(a, tpb, K, nblocks, shmem, s->stream);
         if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep launch");
-        hipLaunchKernelGGL(kpz_merge_kernel, dim3(mgrid), dim3(256), 0, s->stream, a);
-        e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep merge launch");
     }
     s->t += n_mcs;
     return KPZ_OK;
@@ -1618,6 +1631,7 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
         SweepArgs &a = args[r];
         a.words = d_words + lay.word_off[r];
         a.side = (uint32_t *)(b->ws + lay.off_side[r]);
+        a.pairs = (uint32_t *)(b->ws + lay.off_pairs[r]);
         a.slots = (unsigned long long *)(slots + (size_t)BATCH_SLOTS * r);
         a.L = L;
         a.W = L / 16;
@@ -1672,6 +1686,9 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
             hipLaunchKernelGGL(kpz_init_small_kernel, dim3(1), dim3(256), 0, b->stream,
                                d_words + lay.word_off[r], (uint32_t)(L * L / 16), W);
         }
+        const uint64_t npairs = (L / lay.Bx) * (L / lay.By);
+        hipLaunchKernelGGL(kpz_zero_kernel, dim3((uint32_t)((npairs + 255) / 256)), dim3(256), 0,
+                           b->stream, (uint32_t *)(b->ws + lay.off_pairs[r]), npairs);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
@@ -1816,7 +1833,7 @@ kpz_status kpz_pool_job_bytes(const kpz_params *job, int32_t bx, int32_t by, siz
     uint32_t rbx, rby;
     const kpz_status st = resolve(&q, &rbx, &rby);
     if (st != KPZ_OK) return st;
-    *bytes = pool_job_bytes_raw(job->L, rbx);
+    *bytes = pool_job_bytes_raw(job->L, rbx, rby);
     return KPZ_OK;
 }
 
@@ -1887,7 +1904,7 @@ kpz_status kpz_pool_submit(kpz_pool *p, const kpz_params *job, int64_t n_mcs, in
     uint32_t rbx, rby;
     kpz_status st = resolve(&q, &rbx, &rby);
     if (st != KPZ_OK) return st;
-    const size_t bytes = pool_job_bytes_raw(q.L, p->Bx);
+    const size_t bytes = pool_job_bytes_raw(q.L, p->Bx, p->By);
     if (bytes > p->arena_bytes - p->ctl.bytes) return KPZ_EINVAL;
     if ((int32_t)p->jobs.size() >= p->max_jobs) return KPZ_ESIZE;
     size_t off;
@@ -1905,7 +1922,8 @@ kpz_status kpz_pool_submit(kpz_pool *p, const kpz_params *job, int64_t n_mcs, in
     j.off_slots = o; o += align256(sizeof(long long) * BATCH_SLOTS);
     j.off_rowA = o;  o += align256(8 * L);
     j.off_rowB = o;  o += align256(8 * L);
-    j.off_side = o;
+    j.off_side = o;  o += align256(4 * 2 * L * (L / p->Bx));
+    j.off_pairs = o;
     const uint32_t W = (uint32_t)(L / 16);
     uint32_t *words = (uint32_t *)(p->arena + j.off_words);
     if (W % 4 == 0) {
@@ -1919,6 +1937,9 @@ kpz_status kpz_pool_submit(kpz_pool *p, const kpz_params *job, int64_t n_mcs, in
     }
     hipLaunchKernelGGL(kpz_zero_kernel, dim3(1), dim3(256), 0, p->stream,
                        (uint32_t *)(p->arena + j.off_slots), (uint64_t)2 * BATCH_SLOTS);
+    const uint64_t npairs = (uint64_t)(L / p->Bx) * (L / p->By);
+    hipLaunchKernelGGL(kpz_zero_kernel, dim3((uint32_t)((npairs + 255) / 256)), dim3(256), 0,
+                       p->stream, (uint32_t *)(p->arena + j.off_pairs), npairs);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         pool_free(p, off, bytes);
