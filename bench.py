@@ -9,8 +9,9 @@ sweep + roughness).  Value = site-update attempts per second over the timed
 steps, with the lattice already resident in HBM.
 
 Prints one JSON line.  Besides the contract fields it carries
-  roofline      the sweep kernel's integer-ALU roofline (HIP events on the
-                sweep's stream give its mean launch time), plus its HBM view
+  roofline      the integer-ALU roofline of one MCS (sweep plus straddling-
+                word merge; HIP events on the sweep's stream give its mean
+                time), plus its HBM view
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload
                 (single blocks of the same lattice, same draws)
 """
@@ -32,8 +33,11 @@ sys.path.insert(0, ROOT)
 # FMAs as 4 flops per lane-cycle).
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Algorithmic cost of one attempt (bytes and integer operations); derivation
-# in the design doc (sweep roofline).
+# Algorithmic cost of one attempt: the packed lattice (2 bits per site) is
+# read once and written once per MCS (0.5 B); the SWAR update of four tiles
+# at once takes 31 32-bit integer operations per step (site draw, one-hot,
+# dead mask, neighbour alignment, minimum test, flip masks, apply, count),
+# 7.75 per attempt, plus 1.25 for the Philox draws: 9 per attempt.
 BYTES_PER_ATTEMPT = 0.5
 OPS_PER_ATTEMPT = 9.0
 
@@ -84,8 +88,9 @@ def ensemble_leg(args):
     """The batched ensemble: 512 lattices, L uniform over {256,...,2048},
     p = 1, q uniform over {0, 1/4, 1/2}, seeds 1000 + r (job table from numpy
     default_rng(0)), 10^4 MCS with W^2 at 64 log-spaced times, run as one
-    captured graph of persistent launches; compared with plain single-lattice
-    launches of a subset of the same members, one after another."""
+    captured graph (per MCS: one launch over every member's blocks and one
+    straddling-word merge); compared with plain single-lattice launches of a
+    subset of the same members, one after another."""
     import numpy as np
     import torch
     import paper_1204_5072_amd as kpz
@@ -102,6 +107,7 @@ def ensemble_leg(args):
     else:
         tuned = autotune.tune_ensemble(base, mcs=2)
         block = tuned["block"]
+        print(f"bench: ensemble block {block} (tuned)", file=sys.stderr, flush=True)
     members = [kpz.make_params(m.L, m.p, m.q, m.seed, block) for m in base]
     times = log_times(64, args.ens_mcs)
     ens = kpz.Ensemble(members)
@@ -111,6 +117,7 @@ def ensemble_leg(args):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     attempts = float(sum(int(L) ** 2 for L in Ls)) * times[-1]
+    print(f"bench: ensemble run {elapsed:.2f} s", file=sys.stderr, flush=True)
     ens.close()
     # sequential plain launches: a subset of members, each on its own
     m_seq = min(args.ens_seq_members, n)
@@ -155,8 +162,12 @@ def serving_leg(args):
     continuous batching; p50/p99 of arrival -> result latency."""
     from paper_1204_5072_amd import serve
     jobs = serve.poisson_jobs(n_jobs=args.serve_jobs, rate=args.serve_rate, seed=0)
+    def progress(done, total, resident):
+        print(f"bench: serving {done}/{total} done, {resident} resident", file=sys.stderr,
+              flush=True)
+
     rep = serve.serve(jobs, hbm_bytes=int(args.serve_hbm_gib * (1 << 30)),
-                      quantum=args.serve_quantum)
+                      quantum=args.serve_quantum, progress=progress)
     return {
         "metric": "job latency p50/p99 (arrival -> result), serving",
         "p50_ms": rep.latency_p50_ms,
@@ -271,7 +282,10 @@ def main():
             "unit": "Tops/s",
             "frac": achieved_tops / VALU_PEAK_TOPS,
             "traffic": None,
-            "kernel": "kpz_sweep_kernel",
+            # one MCS = the sweep launch plus the straddling-word merge launch,
+            # bracketed together by the events (the sum of the two kernels'
+            # average durations in a kernel trace)
+            "kernel": "kpz_sweep_kernel+kpz_merge_kernel",
             "mean_launch_ms": sweep_ms,
             "ops_per_attempt": OPS_PER_ATTEMPT,
             "hbm_achieved_gbs": achieved_gbs,

@@ -122,6 +122,16 @@ kpz_status kpz_sweep(kpz_sim *sim, int32_t n_mcs);
  * surface for the recorded number of flips. */
 kpz_status kpz_roughness(kpz_sim *sim, int64_t *S1, int64_t *S2, double *W2);
 
+/* Height distribution to fourth order (the one-point functions of Sec.
+ * 2.1): exact sums M_k = sum over sites of (h - h(0,0))^k, k = 1..4, as
+ * 128-bit integers in sums[2k-2] (low 64 bits) and sums[2k-1] (high 64
+ * bits, two's complement), and from them, in extended precision, the
+ * variance W2, the skewness m3 / m2^(3/2) and the excess kurtosis
+ * m4 / m2^2 - 3 of the heights (m_k central moments).  Any output may be
+ * NULL.  Synchronises the stream. */
+kpz_status kpz_height_moments(kpz_sim *sim, int64_t sums[8], double *W2, double *skewness,
+                              double *kurtosis);
+
 /* Checkpoint support.  The complete dynamical state is (words, t, net_flips)
  * where net_flips = #depositions - #desorptions since the flat start (so
  * S1 = N/2 + 2 net_flips).  get synchronises the stream; set enqueues the
@@ -146,8 +156,9 @@ const char *kpz_last_error(const kpz_sim *sim);
  * q and seed; all members share one block shape (block_x, block_y, resolved
  * as for a single lattice from the smallest L when 0) and the 4 x 4 tile.
  * Every member's results are bit-identical to a single-lattice run with the
- * same parameters and block shape.  One kpz_batch_sweep is one persistent
- * launch that runs every member's MCS; members do not wait for each other.
+ * same parameters and block shape.  Each MCS of a kpz_batch_sweep is one
+ * launch over the blocks of all members plus one launch that merges their
+ * straddling words (the launch boundary orders one MCS before the next).
  *
  * Memory (caller-owned device buffers, sizes from kpz_batch_sizes):
  * `words` holds the members' packed lattices one after the other (member
@@ -173,7 +184,7 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
 /* Offset (in uint32 words) of member r's lattice inside the words buffer. */
 kpz_status kpz_batch_word_offset(const kpz_batch *batch, int32_t member, size_t *offset_words);
 
-/* Enqueues n_mcs MCS of every member (one persistent launch). */
+/* Enqueues n_mcs MCS of every member (two launches per MCS). */
 kpz_status kpz_batch_sweep(kpz_batch *batch, int32_t n_mcs);
 
 /* Exact moments of every member (arrays of n; any may be NULL), as
@@ -204,9 +215,11 @@ const char *kpz_batch_last_error(const kpz_batch *batch);
  * its exact final S1, S2, W^2.  Jobs live in a caller-owned device arena
  * (the HBM budget); kpz_pool_submit admits a job only if its lattice and
  * workspace fit into free arena memory and a slot is free.  Each
- * kpz_pool_step is one persistent launch in which every resident job
- * advances min(quantum, remaining) MCS; jobs submitted between steps join
- * the next one, so new work overlaps running work on the device.  A job's
+ * kpz_pool_step advances every resident job min(quantum, remaining) MCS
+ * in rounds: round k is one launch over all blocks of the jobs with more
+ * than k MCS left in this step (plus the merge of their straddling words);
+ * jobs submitted between steps join the next one, so new work overlaps
+ * running work on the device.  A job's
  * result is bit-identical whatever else runs with it.  All jobs of a pool
  * share the pool's block shape (block_x, block_y must divide every L).
  */
@@ -216,8 +229,9 @@ typedef struct kpz_pool kpz_pool;
 kpz_status kpz_pool_job_bytes(const kpz_params *job, int32_t block_x, int32_t block_y,
                               size_t *bytes);
 
-/* Arena bytes of the pool's control region (part of the arena). */
-kpz_status kpz_pool_control_bytes(int32_t max_jobs, int32_t max_quantum, size_t *bytes);
+/* Arena bytes of the pool's control region (the first part of the arena;
+ * job lattices and workspaces use the rest). */
+kpz_status kpz_pool_control_bytes(int32_t max_jobs, size_t *bytes);
 
 /* Creates a pool over the device arena [d_arena, d_arena + arena_bytes)
  * (caller-owned, 256-byte aligned) for at most max_jobs resident jobs and

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(PKG, "libkpz.so")
 
 KPZ_OK, KPZ_EINVAL, KPZ_ESIZE, KPZ_EHIP, KPZ_ESTATE, KPZ_ERANGE = 0, -1, -2, -3, -4, -5
 
-EXPORTED = ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness", "kpz_get_state",
+EXPORTED = ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness", "kpz_height_moments",
+            "kpz_get_state",
             "kpz_set_state", "kpz_destroy", "kpz_status_str", "kpz_last_error",
             "kpz_batch_sizes", "kpz_batch_init", "kpz_batch_word_offset", "kpz_batch_sweep",
             "kpz_batch_roughness", "kpz_batch_run", "kpz_batch_get_t", "kpz_batch_destroy",
@@ -65,6 +66,9 @@ def lib() -> ctypes.CDLL:
         L.kpz_sweep.argtypes = [vp, c.c_int32]
         L.kpz_roughness.argtypes = [vp, c.POINTER(c.c_int64), c.POINTER(c.c_int64),
                                     c.POINTER(c.c_double)]
+        L.kpz_height_moments.argtypes = [vp, c.POINTER(c.c_int64), c.POINTER(c.c_double),
+                                         c.POINTER(c.c_double), c.POINTER(c.c_double)]
+        L.kpz_height_moments.restype = c.c_int
         L.kpz_get_state.argtypes = [vp, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
         L.kpz_set_state.argtypes = [vp, c.c_int64, c.c_int64]
         L.kpz_destroy.argtypes = [vp]
@@ -87,7 +91,7 @@ def lib() -> ctypes.CDLL:
         L.kpz_batch_last_error.restype = c.c_char_p
         szp, i32p = c.POINTER(c.c_size_t), c.POINTER(c.c_int32)
         L.kpz_pool_job_bytes.argtypes = [P, c.c_int32, c.c_int32, szp]
-        L.kpz_pool_control_bytes.argtypes = [c.c_int32, c.c_int32, szp]
+        L.kpz_pool_control_bytes.argtypes = [c.c_int32, szp]
         L.kpz_pool_init.argtypes = [c.POINTER(vp), vp, c.c_size_t, c.c_int32, c.c_int32, c.c_int32,
                                     c.c_int32, vp]
         L.kpz_pool_submit.argtypes = [vp, P, c.c_int64, i64p]
@@ -171,6 +175,16 @@ class Sim:
                                         ctypes.byref(W2)), "kpz_roughness")
         return Moments(S1.value, S2.value, W2.value)
 
+    def height_moments(self):
+        """Exact sums M_k = sum (h - h(0,0))^k, k = 1..4 (Python ints), and
+        (W2, skewness, excess kurtosis) of the height distribution."""
+        sums = (ctypes.c_int64 * 8)()
+        w2, sk, ku = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(lib().kpz_height_moments(self._h, sums, ctypes.byref(w2), ctypes.byref(sk),
+                                             ctypes.byref(ku)), "kpz_height_moments")
+        M = [(sums[2 * k + 1] << 64) + (sums[2 * k] & ((1 << 64) - 1)) for k in range(4)]
+        return M, (w2.value, sk.value, ku.value)
+
     def state(self) -> Tuple[int, int]:
         t, net = ctypes.c_int64(), ctypes.c_int64()
         self._check(lib().kpz_get_state(self._h, ctypes.byref(t), ctypes.byref(net)),
@@ -215,8 +229,8 @@ def batch_sizes(members) -> Tuple[int, int]:
 
 
 class Ensemble:
-    """n independent lattices on one GPU, advanced together by one
-    persistent launch per call.  ``members`` is a list of kpz_params (see
+    """n independent lattices on one GPU, advanced together: each MCS is one
+    launch over the blocks of every member (plus the straddling-word merge).  ``members`` is a list of kpz_params (see
     make_params); all must resolve to the same block shape."""
 
     def __init__(self, members, device="cuda", stream=None):
@@ -321,6 +335,15 @@ class Pool:
     def _check(self, st, what):
         if st != KPZ_OK:
             raise KPZError(st, what, lib().kpz_pool_last_error(self._h).decode())
+
+    @staticmethod
+    def control_bytes(max_jobs: int) -> int:
+        """Arena bytes of the control region for ``max_jobs`` resident jobs."""
+        n = ctypes.c_size_t()
+        st = lib().kpz_pool_control_bytes(int(max_jobs), ctypes.byref(n))
+        if st != KPZ_OK:
+            raise KPZError(st, "kpz_pool_control_bytes")
+        return n.value
 
     def job_bytes(self, params: kpz_params) -> int:
         n = ctypes.c_size_t()

@@ -84,3 +84,23 @@ def tune_ensemble(members, mcs: int = 2,
         del ens
     best = min(timings, key=timings.get)
     return {"block": best, "ms_per_mcs": timings}
+
+
+def main(argv=None) -> None:
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="time the sweep for each candidate block shape")
+    ap.add_argument("--L", type=int, default=65536)
+    ap.add_argument("--p", type=float, default=1.0)
+    ap.add_argument("--q", type=float, default=0.0)
+    ap.add_argument("--mcs", type=int, default=5)
+    args = ap.parse_args(argv)
+    res = tune_lattice(args.L, args.p, args.q, args.mcs)
+    rows = {f"{s[0]}x{s[1]}": {"ms_per_mcs": ms, "attempts_per_s": args.L * args.L / ms * 1e3}
+            for s, ms in sorted(res["ms_per_mcs"].items(), key=lambda kv: kv[1])}
+    print(json.dumps({"L": args.L, "p": args.p, "q": args.q, "best": list(res["block"]),
+                      "shapes": rows}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -39,6 +39,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <math.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -131,7 +132,6 @@ __global__ void kpz_fill_counters_kernel(long long *slots, long long first)
 struct SweepArgs {
     uint32_t *words;
     uint32_t *side;              // [2][L][nbx]: straddling-word parts (left edge, right edge)
-    uint32_t *pairs;             // [nby][nbx]: arrivals at the pair (bx-1, bx), two per MCS
     unsigned long long *slots;   // NSLOTS flip counters
     uint32_t L, W;               // size, words per row
     uint32_t Bx, By;             // block shape
@@ -433,7 +433,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
     // ---- store: quads -> cells -> aligned block words -> HBM row words.
     // Words wholly inside the block are stored; the block's parts of the two
     // words it shares with its left and right neighbours go to the side
-    // buffer and are merged below.
+    // buffer and are merged by a separate launch (the kernel boundary makes
+    // both parts visible; a release/acquire between work-groups inside the
+    // launch would write back the whole L2 per block).
     for (int it = 0; it < UIT; ++it) {
         const uint32_t u = tid + (uint32_t)TPB * it;
         const bool uok = u < a.units;
@@ -478,42 +480,6 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
         }
     }
 
-    // ---- the shared words: of the two blocks of a pair (bx-1, bx) the one
-    // that arrives second (odd count) ORs both parts into the lattice
-    if (sh2 != 0) {
-        __shared__ uint32_t s_merge;
-        __threadfence();   // release this block's side-buffer parts
-        __syncthreads();
-        if (tid == 0) {
-            uint32_t m = 1u;   // a single block per row owns both parts itself
-            if (a.nbx > 1) {
-                const uint32_t rowb = by * a.nbx;
-                m = 0u;
-                if (atomicAdd(a.pairs + rowb + bx, 1u) & 1u) m |= 1u;
-                if (atomicAdd(a.pairs + rowb + (bx + 1 == a.nbx ? 0 : bx + 1), 1u) & 1u) m |= 2u;
-            }
-            s_merge = m;
-        }
-        __syncthreads();
-        const uint32_t m = s_merge;
-        if (m) {
-            __threadfence();   // acquire the neighbour's parts
-            const uint32_t bl = bx == 0 ? a.nbx - 1 : bx - 1;
-            const uint32_t br = bx + 1 == a.nbx ? 0 : bx + 1;
-            uint32_t gwe = gw0 + nw;
-            if (gwe >= a.W) gwe -= a.W;
-            for (uint32_t r = tid; r < a.By; r += TPB) {
-                uint32_t gy = gy0 + r;
-                if (gy >= a.L) gy -= a.L;
-                uint32_t *row = a.words + (size_t)gy * a.W;
-                const uint32_t *sl = a.side + (size_t)gy * a.nbx;              // left-edge parts
-                const uint32_t *sr = a.side + ((size_t)a.L + gy) * a.nbx;      // right-edge parts
-                if (m & 1u) row[gw0] = sr[bl] | sl[bx];
-                if (m & 2u) row[gwe] = sr[bx] | sl[br];
-            }
-        }
-    }
-
     // ---- flip counter of this block: wave sums, one atomic per wave
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) net += __shfl_xor(net, off, 64);
@@ -527,6 +493,35 @@ __global__ __launch_bounds__(TPB) void kpz_sweep_kernel(const SweepArgs a)
 {
     extern __shared__ uint32_t lds[];
     sweep_block<TPB, K, NTX, ACC>(a, blockIdx.x, lds);
+}
+
+// Straddling word j = gy * nbx + bx of MCS a.t: the word at the left edge of
+// block column bx in row gy holds the last sites of block bx-1 (low bits) and
+// the first sites of block bx (high bits); both parts are in the side buffer.
+__device__ __forceinline__ void merge_one(const SweepArgs &a, uint32_t ox, uint64_t j)
+{
+    const uint32_t gy = (uint32_t)(j / a.nbx), bx = (uint32_t)(j % a.nbx);
+    uint32_t gw = (ox >> 4) + bx * a.nw;
+    if (gw >= a.W) gw -= a.W;
+    const uint32_t left = a.side[((size_t)a.L + gy) * a.nbx + (bx == 0 ? a.nbx - 1 : bx - 1)];
+    const uint32_t right = a.side[(size_t)gy * a.nbx + bx];
+    a.words[(size_t)gy * a.W + gw] = left | right;
+}
+
+__device__ __forceinline__ uint32_t origin_x(const SweepArgs &a)
+{
+    const U4 wo = philox(0u, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
+    return (uint32_t)(((uint64_t)wo.x * a.Bx) >> 32);
+}
+
+__global__ void kpz_merge_kernel(const SweepArgs a)
+{
+    const uint32_t ox = origin_x(a);
+    if ((ox & 15u) == 0) return;
+    const uint64_t n = (uint64_t)a.L * a.nbx;
+    for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < n;
+         j += (uint64_t)gridDim.x * blockDim.x)
+        merge_one(a, ox, j);
 }
 
 // ------------------------------------------------------------ roughness
@@ -716,15 +711,208 @@ __global__ __launch_bounds__(1024) void kpz_finalize_kernel(const uint32_t *word
     finalize_moments<1024>(words, L, W, rowA, rowB, slots, NSLOTS, res);
 }
 
+
+// ------------------------------------------------ height moments to order 4
+//
+// Exact sums M_k = sum over sites of (h - h(0,0))^k, k = 1..4 (the one-point
+// functions of the height distribution), with the same row scheme as W^2:
+// per 8 sites a table entry (d, sum p, ..., sum p^4) of the local prefix
+// p, combined by binomial shifts sum (c + v)^k = sum_j C(k,j) c^(k-j) S_j.
+
+struct Mom4 {
+    long long n;                  // number of values
+    long long s1;
+    long long s2;
+    __int128 s3, s4;
+};
+
+__device__ __forceinline__ Mom4 mom4_shift(const Mom4 &m, long long c)
+{
+    // moments of (v + c) from those of v
+    Mom4 r;
+    const __int128 C = c, C2 = C * C, C3 = C2 * C, C4 = C3 * C;
+    r.n = m.n;
+    r.s1 = m.s1 + m.n * c;
+    r.s2 = m.s2 + 2 * c * m.s1 + m.n * c * c;
+    r.s3 = m.s3 + 3 * C * m.s2 + 3 * C2 * m.s1 + C3 * m.n;
+    r.s4 = m.s4 + 4 * C * m.s3 + 6 * C2 * m.s2 + 4 * C3 * m.s1 + C4 * m.n;
+    return r;
+}
+
+__device__ __forceinline__ void mom4_add(Mom4 &a, const Mom4 &b)
+{
+    a.n += b.n;
+    a.s1 += b.s1;
+    a.s2 += b.s2;
+    a.s3 += b.s3;
+    a.s4 += b.s4;
+}
+
+// 8 sites: local prefix p_k (k = 0..7) -> d = p_8 and sum p^j, j = 1..4
+// (|sum p| <= 28, sum p^2 <= 140, |sum p^3| <= 784, sum p^4 <= 4676)
+__device__ __forceinline__ uint2 lut8_mom4(uint32_t byte)
+{
+    int p = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
+    for (int i = 0; i < 8; ++i) {
+        a1 += p;
+        a2 += p * p;
+        a3 += p * p * p;
+        a4 += p * p * p * p;
+        p += ((byte >> i) & 1u) ? 1 : -1;
+    }
+    // x: d + 8 (5 bits) | a1 + 28 (6) | a2 (8) ; y: a3 + 1024 (11) | a4 (13)
+    return make_uint2((uint32_t)(p + 8) | ((uint32_t)(a1 + 28) << 5) | ((uint32_t)a2 << 11),
+                      (uint32_t)(a3 + 1024) | ((uint32_t)a4 << 11));
+}
+
+__device__ __forceinline__ Mom4 chunk8(uint2 e, int &d)
+{
+    Mom4 m;
+    d = (int)(e.x & 31u) - 8;
+    m.n = 8;
+    m.s1 = (int)((e.x >> 5) & 63u) - 28;
+    m.s2 = (int)(e.x >> 11);
+    m.s3 = (int)(e.y & 2047u) - 1024;
+    m.s4 = (int)(e.y >> 11);
+    return m;
+}
+
+__device__ void row_mom4(const uint32_t *rp, uint32_t W, const uint2 *lut, uint32_t lane, Mom4 &out)
+{
+    Mom4 tot = {0, 0, 0, 0, 0};
+    long long carry = 0;
+    for (uint32_t base = 0; base < W; base += 64) {
+        const uint32_t idx = base + lane;
+        Mom4 w = {0, 0, 0, 0, 0};
+        int dw = 0;
+        if (idx < W) {
+            uint32_t x = rp[idx] & 0x55555555u;
+            x = (x | (x >> 1)) & 0x33333333u;
+            x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+            x = (x | (x >> 4)) & 0x00FF00FFu;
+            int d0, d1;
+            const Mom4 lo = chunk8(lut[x & 0xFFu], d0);
+            Mom4 hi = chunk8(lut[(x >> 16) & 0xFFu], d1);
+            hi = mom4_shift(hi, d0);
+            w = lo;
+            mom4_add(w, hi);
+            dw = d0 + d1;
+        }
+        int incl = dw;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(incl, off, 64);
+            if ((int)lane >= off) incl += t;
+        }
+        mom4_add(tot, mom4_shift(w, carry + incl - dw));
+        carry += __shfl(incl, 63, 64);
+    }
+    // wave sum
+    for (int off = 32; off > 0; off >>= 1) {
+        tot.n += __shfl_xor(tot.n, off, 64);
+        tot.s1 += __shfl_xor(tot.s1, off, 64);
+        tot.s2 += __shfl_xor(tot.s2, off, 64);
+        long long lo3 = (long long)(uint64_t)(unsigned __int128)tot.s3;
+        long long hi3 = (long long)(uint64_t)((unsigned __int128)tot.s3 >> 64);
+        long long lo4 = (long long)(uint64_t)(unsigned __int128)tot.s4;
+        long long hi4 = (long long)(uint64_t)((unsigned __int128)tot.s4 >> 64);
+        const __int128 o3 = (__int128)(((unsigned __int128)(uint64_t)__shfl_xor(hi3, off, 64) << 64) |
+                                       (uint64_t)__shfl_xor(lo3, off, 64));
+        const __int128 o4 = (__int128)(((unsigned __int128)(uint64_t)__shfl_xor(hi4, off, 64) << 64) |
+                                       (uint64_t)__shfl_xor(lo4, off, 64));
+        tot.s3 += o3;
+        tot.s4 += o4;
+    }
+    out = tot;
+}
+
+// Per row y (relative to the row start): (sum P, sum P^2, sum P^3, sum P^4),
+// 6 int64 per row: s1, s2, s3 lo/hi, s4 lo/hi.
+__global__ __launch_bounds__(256) void kpz_row_mom4_kernel(const uint32_t *words, uint32_t L,
+                                                           uint32_t W, long long *rows6)
+{
+    __shared__ uint2 lut[256];
+    lut[threadIdx.x] = lut8_mom4(threadIdx.x);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint32_t row = blockIdx.x * 4u + (threadIdx.x >> 6); row < L; row += gridDim.x * 4u) {
+        Mom4 m;
+        row_mom4(words + (size_t)row * W, W, lut, lane, m);
+        if (lane == 0) {
+            long long *o = rows6 + 6 * (size_t)row;
+            o[0] = m.s1;
+            o[1] = m.s2;
+            o[2] = (long long)(uint64_t)(unsigned __int128)m.s3;
+            o[3] = (long long)(uint64_t)((unsigned __int128)m.s3 >> 64);
+            o[4] = (long long)(uint64_t)(unsigned __int128)m.s4;
+            o[5] = (long long)(uint64_t)((unsigned __int128)m.s4 >> 64);
+        }
+    }
+}
+
+// One work-group: rows shifted by their column-0 height c_y and summed;
+// res = M1..M4 as (lo, hi) pairs.
+__global__ __launch_bounds__(256) void kpz_mom4_finalize_kernel(const uint32_t *words, uint32_t L,
+                                                                uint32_t W, const long long *rows6,
+                                                                long long *res)
+{
+    constexpr int NT = 256;
+    __shared__ long long sc[NT];
+    __shared__ __int128 acc[4][NT];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t per = (L + NT - 1) / NT;
+    const uint32_t y0 = min(L, tid * per), y1 = min(L, y0 + per);
+    long long loc = 0;
+    for (uint32_t y = y0; y < y1; ++y) loc += ((words[(size_t)y * W] >> 1) & 1u) ? 1 : -1;
+    sc[tid] = loc;
+    __syncthreads();
+    for (uint32_t off = 1; off < NT; off <<= 1) {
+        const long long v = tid >= off ? sc[tid - off] : 0;
+        __syncthreads();
+        sc[tid] += v;
+        __syncthreads();
+    }
+    long long c = sc[tid] - loc;
+    __int128 t1 = 0, t2 = 0, t3 = 0, t4 = 0;
+    for (uint32_t y = y0; y < y1; ++y) {
+        const long long *o = rows6 + 6 * (size_t)y;
+        Mom4 m;
+        m.n = L;
+        m.s1 = o[0];
+        m.s2 = o[1];
+        m.s3 = (__int128)(((unsigned __int128)(uint64_t)o[3] << 64) | (uint64_t)o[2]);
+        m.s4 = (__int128)(((unsigned __int128)(uint64_t)o[5] << 64) | (uint64_t)o[4]);
+        const Mom4 r = mom4_shift(m, c);
+        t1 += r.s1;
+        t2 += r.s2;
+        t3 += r.s3;
+        t4 += r.s4;
+        c += ((words[(size_t)y * W] >> 1) & 1u) ? 1 : -1;
+    }
+    acc[0][tid] = t1;
+    acc[1][tid] = t2;
+    acc[2][tid] = t3;
+    acc[3][tid] = t4;
+    __syncthreads();
+    for (uint32_t off = NT / 2; off > 0; off >>= 1) {
+        if (tid < off)
+            for (int k = 0; k < 4; ++k) acc[k][tid] += acc[k][tid + off];
+        __syncthreads();
+    }
+    if (tid == 0)
+        for (int k = 0; k < 4; ++k) {
+            const unsigned __int128 u = (unsigned __int128)acc[k][0];
+            res[2 * k] = (long long)(uint64_t)u;
+            res[2 * k + 1] = (long long)(uint64_t)(u >> 64);
+        }
+}
+
 // ------------------------------------------------------------ ensemble
 //
 // Many independent lattices ("members", each with its own L, p, q and seed,
-// one common block shape) advance together.  One persistent launch runs
-// `rounds` MCS of every member: work-groups take tickets in the order
-// (round, member, block); the block of member r at round k + 1 waits only
-// until member r's round k is complete, so members never wait for each
-// other.  The work-group that finishes the last block of a member's round
-// publishes the round (agent-scope release; the waiting side acquires).
+// one common block shape) advance together: one launch runs one MCS of
+// every member (all their blocks in one grid), one more merges their
+// straddling words.  Rounds are separated by kernel boundaries, which make
+// each round's words visible to the next at no extra cost.
 
 struct MemberRows {
     const uint32_t *words;
@@ -733,85 +921,49 @@ struct MemberRows {
     uint32_t L, W;
 };
 
-struct BatchArgs {
-    const SweepArgs *members;    // per member; field t = MCS index at launch start
-    const uint32_t *bprefix;     // [n + 1] prefix sums of blocks per member
-    // Optional uneven rounds (job pool): members sorted by decreasing rounds,
-    // round k runs members [0, round_members[k]) and its tickets start at
-    // round_start[k] (round_start[rounds] = total).  Null: every member runs
-    // every round.
-    const unsigned long long *round_start;
-    const uint32_t *round_members;
-    unsigned int *ctl;           // [0..1] 64-bit ticket counter, [64 + r] blocks done,
-                                 // [64 + n + r] rounds ready
-    uint32_t n;
-    uint32_t per_round;          // blocks of all members per round = bprefix[n]
-    uint32_t rounds;
-};
-
+// One round of the ensemble: every block of members [0, nmem) runs MCS
+// t_r + k (t_r = the member's t at the start of the call).  Block g of the
+// grid is block g - bprefix[r] of member r (bprefix = prefix sums of the
+// members' block counts).
 template <int TPB, int K, int NTX>
-__global__ __launch_bounds__(TPB) void kpz_batch_kernel(const BatchArgs ba)
+__global__ __launch_bounds__(TPB) void kpz_batch_round_kernel(const SweepArgs *members,
+                                                              const uint32_t *bprefix,
+                                                              uint32_t nmem, uint32_t k)
 {
     extern __shared__ uint32_t lds[];
-    __shared__ unsigned long long s_ticket;
-    const uint64_t total = ba.round_start ? ba.round_start[ba.rounds]
-                                          : (uint64_t)ba.per_round * ba.rounds;
-    unsigned int *const done = ba.ctl + 64;
-    unsigned int *const ready = ba.ctl + 64 + ba.n;
-    for (;;) {
-        if (threadIdx.x == 0) s_ticket = atomicAdd((unsigned long long *)ba.ctl, 1ull);
-        __syncthreads();
-        const uint64_t ticket = s_ticket;
-        __syncthreads();
-        if (ticket >= total) break;
-        uint32_t round, rem, nmem;
-        if (ba.round_start) {
-            // round: the last k with round_start[k] <= ticket
-            uint32_t klo = 0, khi = ba.rounds;
-            while (khi - klo > 1) {
-                const uint32_t mid = (klo + khi) >> 1;
-                if (ba.round_start[mid] <= ticket) klo = mid;
-                else khi = mid;
-            }
-            round = __builtin_amdgcn_readfirstlane(klo);
-            rem = __builtin_amdgcn_readfirstlane((uint32_t)(ticket - ba.round_start[round]));
-            nmem = ba.round_members[round];
-        } else {
-            round = __builtin_amdgcn_readfirstlane((uint32_t)(ticket / ba.per_round));
-            rem = __builtin_amdgcn_readfirstlane((uint32_t)(ticket - (uint64_t)round * ba.per_round));
-            nmem = ba.n;
-        }
-        // member r: the last one with bprefix[r] <= rem
+    const uint32_t g = blockIdx.x;
+    uint32_t lo = 0, hi = nmem;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (bprefix[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    const uint32_t r = __builtin_amdgcn_readfirstlane(lo);
+    SweepArgs a = members[r];
+    a.t += k;
+    const uint32_t b = g - bprefix[r];
+    if (a.acc) sweep_block<TPB, K, NTX, true>(a, b, lds);
+    else sweep_block<TPB, K, NTX, false>(a, b, lds);
+}
+
+// Straddling words of members [0, nmem) after round k; sprefix = prefix
+// sums of L_r * nbx_r.
+__global__ void kpz_batch_merge_kernel(const SweepArgs *members, const unsigned long long *sprefix,
+                                       uint32_t nmem, uint32_t k)
+{
+    const uint64_t total = sprefix[nmem];
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t lo = 0, hi = nmem;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (ba.bprefix[mid] <= rem) lo = mid;
+            if (sprefix[mid] <= i) lo = mid;
             else hi = mid;
         }
-        const uint32_t r = __builtin_amdgcn_readfirstlane(lo);
-        const uint32_t b = rem - ba.bprefix[r];
-        SweepArgs a = ba.members[r];
-        a.t += round;
-        if (round > 0) {
-            if (threadIdx.x == 0)
-                while (__hip_atomic_load(ready + r, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < round)
-                    __builtin_amdgcn_s_sleep(2);
-            __syncthreads();
-            __threadfence();   // every wave orders its loads after the acquire
-        }
-        if (a.acc) sweep_block<TPB, K, NTX, true>(a, b, lds);
-        else sweep_block<TPB, K, NTX, false>(a, b, lds);
-        // the block (its merges included) is complete: count it; the last
-        // block of the member's round publishes the round
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const unsigned int nb = ba.bprefix[r + 1] - ba.bprefix[r];
-            const unsigned int old = atomicAdd(done + r, 1u);
-            if (old + 1 == (round + 1) * nb)
-                __hip_atomic_store(ready + r, round + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __syncthreads();
+        SweepArgs a = members[lo];
+        a.t += k;
+        const uint32_t ox = origin_x(a);
+        if ((ox & 15u) != 0) merge_one(a, ox, i - sprefix[lo]);
     }
 }
 
@@ -820,12 +972,6 @@ __global__ void kpz_zero_kernel(uint32_t *p, uint64_t n)
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = 0u;
-}
-
-__global__ void kpz_batch_reset_kernel(unsigned int *ctl, uint32_t n)
-{
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < 64 + 2 * n; i += gridDim.x * blockDim.x)
-        ctl[i] = 0u;
 }
 
 __global__ void kpz_batch_advance_kernel(SweepArgs *members, uint32_t n, uint32_t dt)
@@ -933,12 +1079,12 @@ kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
 
 size_t ws_needed(int64_t L, int64_t Bx, int64_t By)
 {
-    // header, flip-counter slots, two int64 per row (row moments), the side
-    // buffer of the straddling words (two uint32 per row and block column)
-    // and one pair counter per block
-    return (size_t)WS_HEADER + sizeof(long long) * NSLOTS + 2 * sizeof(long long) * (size_t)L +
-           2 * sizeof(uint32_t) * (size_t)L * (size_t)(L / Bx) +
-           sizeof(uint32_t) * (size_t)(L / Bx) * (size_t)(L / By);
+    // header, flip-counter slots, six int64 per row (row moments: two for
+    // W^2, six for the fourth-order moments) and the side buffer of the
+    // straddling words (two uint32 per row and block column)
+    (void)By;
+    return (size_t)WS_HEADER + sizeof(long long) * NSLOTS + 6 * sizeof(long long) * (size_t)L +
+           2 * sizeof(uint32_t) * (size_t)L * (size_t)(L / Bx);
 }
 
 kpz_status hip_fail(kpz_sim *s, hipError_t e, const char *what)
@@ -951,11 +1097,7 @@ long long *ws_res(kpz_sim *s) { return (long long *)s->ws; }
 long long *ws_slots(kpz_sim *s) { return (long long *)(s->ws + WS_HEADER); }
 long long *ws_rowA(kpz_sim *s) { return ws_slots(s) + NSLOTS; }
 long long *ws_rowB(kpz_sim *s) { return ws_rowA(s) + s->prm.L; }
-uint32_t *ws_side(kpz_sim *s) { return (uint32_t *)(ws_rowB(s) + s->prm.L); }
-uint32_t *ws_pairs(kpz_sim *s)
-{
-    return ws_side(s) + 2 * (size_t)s->prm.L * (size_t)(s->prm.L / s->Bx);
-}
+uint32_t *ws_side(kpz_sim *s) { return (uint32_t *)(ws_rowA(s) + 6 * (size_t)s->prm.L); }
 
 template <int TPB, int K, int NTX, bool ACC>
 hipError_t launch_sweep_k(const SweepArgs &a, uint32_t nblocks, size_t shmem, hipStream_t st)
@@ -1017,8 +1159,8 @@ struct BatchLayout {
     uint32_t Bx, By;
     std::vector<size_t> word_off;   // per member, in words
     size_t words_bytes;
-    size_t off_ctl, off_members, off_bprefix, off_rprefix, off_rows, off_res, off_slots;
-    std::vector<size_t> off_rowA, off_rowB, off_side, off_pairs;
+    size_t off_members, off_bprefix, off_sprefix, off_rprefix, off_rows, off_res, off_slots;
+    std::vector<size_t> off_rowA, off_rowB, off_side;
     size_t ws_bytes;
 };
 
@@ -1051,9 +1193,9 @@ kpz_status batch_layout(const kpz_params *m, int32_t n, BatchLayout *lay)
     }
     lay->words_bytes = 4 * w;
     size_t o = 0;
-    lay->off_ctl = o;      o = align256(o + 4 * (64 + 2 * (size_t)n));
     lay->off_members = o;  o = align256(o + sizeof(SweepArgs) * (size_t)n);
     lay->off_bprefix = o;  o = align256(o + 4 * ((size_t)n + 1));
+    lay->off_sprefix = o;  o = align256(o + 8 * ((size_t)n + 1));
     lay->off_rprefix = o;  o = align256(o + 4 * ((size_t)n + 1));
     lay->off_rows = o;     o = align256(o + sizeof(MemberRows) * (size_t)n);
     lay->off_res = o;      o = align256(o + 4 * sizeof(long long) * (size_t)n * KPZ_BATCH_MAX_SAMPLES);
@@ -1061,22 +1203,76 @@ kpz_status batch_layout(const kpz_params *m, int32_t n, BatchLayout *lay)
     lay->off_rowA.resize(n);
     lay->off_rowB.resize(n);
     lay->off_side.resize(n);
-    lay->off_pairs.resize(n);
     for (int32_t r = 0; r < n; ++r) {
         const size_t L = (size_t)m[r].L;
         lay->off_rowA[r] = o; o = align256(o + 8 * L);
         lay->off_rowB[r] = o; o = align256(o + 8 * L);
         lay->off_side[r] = o; o = align256(o + 4 * 2 * L * (L / lay->Bx));
-        lay->off_pairs[r] = o; o = align256(o + 4 * (L / lay->Bx) * (L / lay->By));
     }
     lay->ws_bytes = o;
     return KPZ_OK;
 }
 
-template <int TPB, int K, int NTX>
-void batch_kernel_ptr(const void **fn)
+// Kernel shape shared by every member of an ensemble or pool.
+struct RoundShape {
+    uint32_t tpb, K, ntx;
+    size_t shmem;
+};
+
+bool round_shape(uint32_t Bx, uint32_t By, RoundShape *rs)
 {
-    *fn = (const void *)kpz_batch_kernel<TPB, K, NTX>;
+    rs->ntx = Bx / TILE;
+    const uint32_t nq = rs->ntx * (By / 16);
+    rs->tpb = nq >= 256 ? 256u : 64u;
+    rs->K = nq <= rs->tpb ? 1u : nq / rs->tpb;
+    rs->shmem = sizeof(uint32_t) * 4 * (size_t)nq;
+    return (rs->tpb == 256 && rs->K <= 4) || (rs->tpb == 64 && rs->K <= 2);
+}
+
+template <int TPB, int K>
+void round_launch_k(const RoundShape &rs, uint32_t grid, hipStream_t st, const SweepArgs *members,
+                    const uint32_t *bprefix, uint32_t nmem, uint32_t k)
+{
+    switch (rs.ntx) {
+    case 64:
+        hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 64>), dim3(grid), dim3(TPB), rs.shmem,
+                           st, members, bprefix, nmem, k);
+        break;
+    case 128:
+        hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 128>), dim3(grid), dim3(TPB), rs.shmem,
+                           st, members, bprefix, nmem, k);
+        break;
+    case 256:
+        hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 256>), dim3(grid), dim3(TPB), rs.shmem,
+                           st, members, bprefix, nmem, k);
+        break;
+    default:
+        hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 0>), dim3(grid), dim3(TPB), rs.shmem,
+                           st, members, bprefix, nmem, k);
+        break;
+    }
+}
+
+// One round (MCS k of the call) of members [0, nmem) plus the merge of
+// their straddling words.  grid = bprefix[nmem], mwords = sprefix[nmem].
+hipError_t round_launch(const RoundShape &rs, uint32_t grid, uint64_t mwords, hipStream_t st,
+                        const SweepArgs *members, const uint32_t *bprefix,
+                        const unsigned long long *sprefix, uint32_t nmem, uint32_t k)
+{
+    if (rs.tpb == 256) {
+        if (rs.K == 1) round_launch_k<256, 1>(rs, grid, st, members, bprefix, nmem, k);
+        else if (rs.K == 2) round_launch_k<256, 2>(rs, grid, st, members, bprefix, nmem, k);
+        else round_launch_k<256, 4>(rs, grid, st, members, bprefix, nmem, k);
+    } else {
+        if (rs.K == 1) round_launch_k<64, 1>(rs, grid, st, members, bprefix, nmem, k);
+        else round_launch_k<64, 2>(rs, grid, st, members, bprefix, nmem, k);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint32_t mgrid = (uint32_t)((mwords + 255) / 256 < 8192 ? (mwords + 255) / 256 : 8192);
+    hipLaunchKernelGGL(kpz_batch_merge_kernel, dim3(mgrid), dim3(256), 0, st, members, sprefix,
+                       nmem, k);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -1089,8 +1285,9 @@ struct kpz_batch {
     uint8_t *ws;
     hipStream_t stream;
     int64_t t;
-    uint32_t tpb, K, ntx, nq, per_round, grid;
-    size_t shmem;
+    RoundShape rs;
+    uint32_t per_round;
+    uint64_t merge_words;
     uint32_t total_rows;
     char err[256];
 };
@@ -1103,86 +1300,23 @@ kpz_status batch_fail(kpz_batch *b, hipError_t e, const char *what)
     return KPZ_EHIP;
 }
 
-// Launches the persistent kernel for the batch's shape.
-template <int TPB, int K>
-hipError_t batch_launch_k(kpz_batch *bt, const BatchArgs &ba, hipStream_t st)
-{
-    switch (bt->ntx) {
-    case 64:
-        hipLaunchKernelGGL((kpz_batch_kernel<TPB, K, 64>), dim3(bt->grid), dim3(TPB), bt->shmem, st, ba);
-        break;
-    case 128:
-        hipLaunchKernelGGL((kpz_batch_kernel<TPB, K, 128>), dim3(bt->grid), dim3(TPB), bt->shmem, st, ba);
-        break;
-    case 256:
-        hipLaunchKernelGGL((kpz_batch_kernel<TPB, K, 256>), dim3(bt->grid), dim3(TPB), bt->shmem, st, ba);
-        break;
-    default:
-        hipLaunchKernelGGL((kpz_batch_kernel<TPB, K, 0>), dim3(bt->grid), dim3(TPB), bt->shmem, st, ba);
-        break;
-    }
-    return hipGetLastError();
-}
-
-hipError_t batch_launch(kpz_batch *bt, const BatchArgs &ba, hipStream_t st)
-{
-    if (bt->tpb == 256) {
-        switch (bt->K) {
-        case 1: return batch_launch_k<256, 1>(bt, ba, st);
-        case 2: return batch_launch_k<256, 2>(bt, ba, st);
-        case 4: return batch_launch_k<256, 4>(bt, ba, st);
-        default: return hipErrorInvalidValue;
-        }
-    }
-    switch (bt->K) {
-    case 1: return batch_launch_k<64, 1>(bt, ba, st);
-    case 2: return batch_launch_k<64, 2>(bt, ba, st);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <int TPB, int K>
-const void *batch_fn_k(uint32_t ntx)
-{
-    switch (ntx) {
-    case 64: return (const void *)kpz_batch_kernel<TPB, K, 64>;
-    case 128: return (const void *)kpz_batch_kernel<TPB, K, 128>;
-    case 256: return (const void *)kpz_batch_kernel<TPB, K, 256>;
-    default: return (const void *)kpz_batch_kernel<TPB, K, 0>;
-    }
-}
-
-const void *batch_fn(uint32_t tpb, uint32_t K, uint32_t ntx)
-{
-    if (tpb == 256) return K == 1 ? batch_fn_k<256, 1>(ntx) : K == 2 ? batch_fn_k<256, 2>(ntx)
-                                                                     : batch_fn_k<256, 4>(ntx);
-    return K == 1 ? batch_fn_k<64, 1>(ntx) : batch_fn_k<64, 2>(ntx);
-}
-
 SweepArgs *batch_members(kpz_batch *b) { return (SweepArgs *)(b->ws + b->lay.off_members); }
-unsigned int *batch_ctl(kpz_batch *b) { return (unsigned int *)(b->ws + b->lay.off_ctl); }
 long long *batch_res(kpz_batch *b) { return (long long *)(b->ws + b->lay.off_res); }
 
-// sweep n_mcs on stream st (capturable: kernels only)
+// sweep n_mcs on stream st (kernels only: capturable)
 kpz_status batch_sweep_on(kpz_batch *b, int32_t n_mcs, hipStream_t st)
 {
     if (n_mcs <= 0) return KPZ_OK;
-    hipLaunchKernelGGL(kpz_batch_reset_kernel, dim3(1), dim3(256), 0, st, batch_ctl(b),
-                       (uint32_t)b->n);
-    BatchArgs ba;
-    ba.members = batch_members(b);
-    ba.bprefix = (const uint32_t *)(b->ws + b->lay.off_bprefix);
-    ba.ctl = batch_ctl(b);
-    ba.n = (uint32_t)b->n;
-    ba.per_round = b->per_round;
-    ba.rounds = (uint32_t)n_mcs;
-    ba.round_start = nullptr;
-    ba.round_members = nullptr;
-    hipError_t e = batch_launch(b, ba, st);
-    if (e != hipSuccess) return batch_fail(b, e, "kpz_batch_sweep launch");
+    const uint32_t *bp = (const uint32_t *)(b->ws + b->lay.off_bprefix);
+    const unsigned long long *sp = (const unsigned long long *)(b->ws + b->lay.off_sprefix);
+    for (int32_t k = 0; k < n_mcs; ++k) {
+        const hipError_t e = round_launch(b->rs, b->per_round, b->merge_words, st, batch_members(b),
+                                          bp, sp, (uint32_t)b->n, (uint32_t)k);
+        if (e != hipSuccess) return batch_fail(b, e, "kpz_batch_sweep launch");
+    }
     hipLaunchKernelGGL(kpz_batch_advance_kernel, dim3((b->n + 255) / 256), dim3(256), 0, st,
                        batch_members(b), (uint32_t)b->n, (uint32_t)n_mcs);
-    e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return batch_fail(b, e, "kpz_batch_sweep launch");
     return KPZ_OK;
 }
@@ -1238,7 +1372,7 @@ struct PoolJob {
     kpz_params prm;
     int64_t t, n_mcs;
     size_t off, bytes;        // arena extent
-    size_t off_words, off_slots, off_rowA, off_rowB, off_side, off_pairs;
+    size_t off_words, off_slots, off_rowA, off_rowB, off_side;
 };
 
 struct PoolResult {
@@ -1250,23 +1384,21 @@ struct PoolResult {
 size_t pool_job_bytes_raw(int64_t L, uint32_t Bx, uint32_t By)
 {
     return align256((size_t)L * L / 4) + align256(sizeof(long long) * BATCH_SLOTS) +
-           2 * align256(8 * (size_t)L) + align256(4 * 2 * (size_t)L * (size_t)(L / Bx)) +
-           align256(4 * (size_t)(L / Bx) * (size_t)(L / By));
+           2 * align256(8 * (size_t)L) + align256(4 * 2 * (size_t)L * (size_t)(L / Bx));
 }
 
 struct PoolCtl {
-    size_t off_ctl, off_members, off_bprefix, off_rstart, off_rmem, off_rows, off_res, bytes;
+    size_t off_members, off_bprefix, off_sprefix, off_rprefix, off_rows, off_res, bytes;
 };
 
-PoolCtl pool_ctl_layout(int32_t max_jobs, int32_t max_quantum)
+PoolCtl pool_ctl_layout(int32_t max_jobs)
 {
     PoolCtl c;
     size_t o = 0;
-    c.off_ctl = o;      o = align256(o + 4 * (64 + 2 * (size_t)max_jobs));
     c.off_members = o;  o = align256(o + sizeof(SweepArgs) * (size_t)max_jobs);
     c.off_bprefix = o;  o = align256(o + 4 * ((size_t)max_jobs + 1));
-    c.off_rstart = o;   o = align256(o + 8 * ((size_t)max_quantum + 1));
-    c.off_rmem = o;     o = align256(o + 4 * ((size_t)max_quantum + 1));
+    c.off_sprefix = o;  o = align256(o + 8 * ((size_t)max_jobs + 1));
+    c.off_rprefix = o;  o = align256(o + 4 * ((size_t)max_jobs + 1));
     c.off_rows = o;     o = align256(o + sizeof(MemberRows) * (size_t)max_jobs);
     c.off_res = o;      o = align256(o + 4 * sizeof(long long) * (size_t)max_jobs);
     c.bytes = o;
@@ -1279,8 +1411,8 @@ struct kpz_pool {
     uint8_t *arena;
     size_t arena_bytes;
     int32_t max_jobs, max_quantum;
-    uint32_t Bx, By, tpb, K, ntx, nq, grid;
-    size_t shmem;
+    uint32_t Bx, By;
+    RoundShape rs;
     hipStream_t stream;
     PoolCtl ctl;
     std::map<size_t, size_t> free_list;   // offset -> bytes (heap part of the arena)
@@ -1337,7 +1469,6 @@ SweepArgs pool_args(const kpz_pool *p, const PoolJob &j)
     const uint32_t L = (uint32_t)j.prm.L;
     a.words = (uint32_t *)(p->arena + j.off_words);
     a.side = (uint32_t *)(p->arena + j.off_side);
-    a.pairs = (uint32_t *)(p->arena + j.off_pairs);
     a.slots = (unsigned long long *)(p->arena + j.off_slots);
     a.L = L;
     a.W = L / 16;
@@ -1361,18 +1492,6 @@ SweepArgs pool_args(const kpz_pool *p, const PoolJob &j)
     a.Q = threshold(j.prm.q);
     a.acc = !(a.P == (1ull << 32) && a.Q == 0);
     return a;
-}
-
-// Persistent launch over the members currently in the pool's tables.
-hipError_t pool_launch(kpz_pool *p, const BatchArgs &ba)
-{
-    kpz_batch tmp;
-    tmp.tpb = p->tpb;
-    tmp.K = p->K;
-    tmp.ntx = p->ntx;
-    tmp.grid = p->grid;
-    tmp.shmem = p->shmem;
-    return batch_launch(&tmp, ba, p->stream);
 }
 
 }  // namespace
@@ -1444,9 +1563,6 @@ kpz_status kpz_init(kpz_sim **out, const kpz_params *p, uint32_t *d_words, size_
     if (e == hipSuccess) {
         hipLaunchKernelGGL(kpz_fill_counters_kernel, dim3(NSLOTS / 256), dim3(256), 0, s->stream,
                            ws_slots(s), 0LL);
-        const uint64_t npairs = (L / bx) * (L / by);
-        hipLaunchKernelGGL(kpz_zero_kernel, dim3((uint32_t)((npairs + 255) / 256 < 4096 ? (npairs + 255) / 256 : 4096)),
-                           dim3(256), 0, s->stream, ws_pairs(s), npairs);
         e = hipGetLastError();
     }
     if (e != hipSuccess) {
@@ -1467,7 +1583,6 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     SweepArgs a;
     a.words = s->words;
     a.side = ws_side(s);
-    a.pairs = ws_pairs(s);
     a.slots = (unsigned long long *)ws_slots(s);
     a.L = L;
     a.W = L / 16;
@@ -1499,12 +1614,16 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     const uint32_t K = a.nq <= tpb ? 1u : a.nq / tpb;
     const uint32_t nblocks = a.nbx * a.nby;
     const size_t shmem = sizeof(uint32_t) * 4 * (size_t)a.nq;
-    const bool acc = !(s->P == (1ull << 32) && s->Q == 0);
+    const uint64_t nstraddle = (uint64_t)L * a.nbx;
+    const uint32_t mgrid = (uint32_t)((nstraddle + 255) / 256 < 8192 ? (nstraddle + 255) / 256 : 8192);
     for (int32_t m = 0; m < n_mcs; ++m) {
         a.t = (uint32_t)(s->t + m);
-        hipError_t e = acc ? launch_sweep<true>(a, tpb, K, nblocks, shmem, s->stream)
-                           : launch_sweep<false>(a, tpb, K, nblocks, shmem, s->stream);
+        hipError_t e = a.acc ? launch_sweep<true>(a, tpb, K, nblocks, shmem, s->stream)
+                             : launch_sweep<false>(a, tpb, K, nblocks, shmem, s->stream);
         if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep launch");
+        hipLaunchKernelGGL(kpz_merge_kernel, dim3(mgrid), dim3(256), 0, s->stream, a);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep merge launch");
     }
     s->t += n_mcs;
     return KPZ_OK;
@@ -1548,6 +1667,42 @@ kpz_status kpz_roughness(kpz_sim *s, int64_t *S1o, int64_t *S2o, double *W2o)
     if (S1o) *S1o = (int64_t)S1;
     if (S2o) *S2o = (int64_t)S2;
     return st;
+}
+
+kpz_status kpz_height_moments(kpz_sim *s, int64_t sums[8], double *W2, double *skewness,
+                              double *kurtosis)
+{
+    if (!s) return KPZ_EINVAL;
+    const uint32_t L = (uint32_t)s->prm.L, W = L / 16;
+    long long *rows6 = ws_rowA(s);   // 6 int64 per row
+    const uint32_t rgrid = (L + 3) / 4 < 4096 ? (L + 3) / 4 : 4096;
+    hipLaunchKernelGGL(kpz_row_mom4_kernel, dim3(rgrid), dim3(256), 0, s->stream, s->words, L, W,
+                       rows6);
+    hipLaunchKernelGGL(kpz_mom4_finalize_kernel, dim3(1), dim3(256), 0, s->stream, s->words, L, W,
+                       (const long long *)rows6, ws_res(s) + 4);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(s, e, "kpz_height_moments launch");
+    long long res[8];
+    e = hipMemcpyAsync(res, ws_res(s) + 4, sizeof res, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "kpz_height_moments copy");
+    if (sums)
+        for (int k = 0; k < 8; ++k) sums[k] = res[k];
+    __int128 M[4];
+    for (int k = 0; k < 4; ++k)
+        M[k] = (__int128)(((unsigned __int128)(uint64_t)res[2 * k + 1] << 64) | (uint64_t)res[2 * k]);
+    // central moments (shift invariant) in extended precision
+    const long double N = (long double)L * (long double)L;
+    const long double mu = (long double)M[0] / N;
+    const long double e2 = (long double)M[1] / N, e3 = (long double)M[2] / N,
+                      e4 = (long double)M[3] / N;
+    const long double m2 = e2 - mu * mu;
+    const long double m3 = e3 - 3 * mu * e2 + 2 * mu * mu * mu;
+    const long double m4 = e4 - 4 * mu * e3 + 6 * mu * mu * e2 - 3 * mu * mu * mu * mu;
+    if (W2) *W2 = (double)m2;
+    if (skewness) *skewness = m2 > 0 ? (double)(m3 / powl(m2, 1.5L)) : 0.0;
+    if (kurtosis) *kurtosis = m2 > 0 ? (double)(m4 / (m2 * m2) - 3) : 0.0;
+    return KPZ_OK;
 }
 
 kpz_status kpz_get_state(kpz_sim *s, int64_t *t, int64_t *net)
@@ -1612,18 +1767,12 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
     b->stream = (hipStream_t)stream;
     b->t = 0;
     b->err[0] = 0;
-    b->ntx = lay.Bx / TILE;
-    b->nq = b->ntx * (lay.By / 16);
-    b->tpb = b->nq >= 256 ? 256u : 64u;
-    if (const char *env = getenv("KPZ_THREADS_PER_BLOCK"))
-        if (atoi(env) == 64 && b->nq <= 128) b->tpb = 64u;
-    b->K = b->nq <= b->tpb ? 1u : b->nq / b->tpb;
-    if (b->tpb == 256 && b->K > 4) { delete b; return KPZ_EINVAL; }
-    b->shmem = sizeof(uint32_t) * 4 * (size_t)b->nq;
+    if (!round_shape(lay.Bx, lay.By, &b->rs)) { delete b; return KPZ_EINVAL; }
 
     std::vector<SweepArgs> args(n);
     std::vector<MemberRows> rows(n);
     std::vector<uint32_t> bprefix(n + 1, 0), rprefix(n + 1, 0);
+    std::vector<unsigned long long> sprefix(n + 1, 0);
     long long *slots = (long long *)(b->ws + lay.off_slots);
     for (int32_t r = 0; r < n; ++r) {
         const kpz_params &p = members[r];
@@ -1631,7 +1780,6 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
         SweepArgs &a = args[r];
         a.words = d_words + lay.word_off[r];
         a.side = (uint32_t *)(b->ws + lay.off_side[r]);
-        a.pairs = (uint32_t *)(b->ws + lay.off_pairs[r]);
         a.slots = (unsigned long long *)(slots + (size_t)BATCH_SLOTS * r);
         a.L = L;
         a.W = L / 16;
@@ -1661,9 +1809,11 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
         rows[r].L = L;
         rows[r].W = L / 16;
         bprefix[r + 1] = bprefix[r] + a.nbx * a.nby;
+        sprefix[r + 1] = sprefix[r] + (unsigned long long)L * a.nbx;
         rprefix[r + 1] = rprefix[r] + L;
     }
     b->per_round = bprefix[n];
+    b->merge_words = sprefix[n];
     b->total_rows = rprefix[n];
     hipError_t e = hipSuccess;
     auto h2d = [&](size_t off, const void *src, size_t bytes) {
@@ -1672,6 +1822,7 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
     };
     h2d(lay.off_members, args.data(), sizeof(SweepArgs) * n);
     h2d(lay.off_bprefix, bprefix.data(), 4 * (n + 1));
+    h2d(lay.off_sprefix, sprefix.data(), 8 * (n + 1));
     h2d(lay.off_rprefix, rprefix.data(), 4 * (n + 1));
     h2d(lay.off_rows, rows.data(), sizeof(MemberRows) * n);
     for (int32_t r = 0; r < n && e == hipSuccess; ++r) {
@@ -1686,9 +1837,6 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
             hipLaunchKernelGGL(kpz_init_small_kernel, dim3(1), dim3(256), 0, b->stream,
                                d_words + lay.word_off[r], (uint32_t)(L * L / 16), W);
         }
-        const uint64_t npairs = (L / lay.Bx) * (L / lay.By);
-        hipLaunchKernelGGL(kpz_zero_kernel, dim3((uint32_t)((npairs + 255) / 256)), dim3(256), 0,
-                           b->stream, (uint32_t *)(b->ws + lay.off_pairs[r]), npairs);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
@@ -1697,20 +1845,12 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
                            (uint32_t *)slots, (uint64_t)2 * ns);
         e = hipGetLastError();
     }
-    // persistent grid: as many work-groups as can be resident
-    int dev = 0, cus = 0, per_cu = 0;
-    if (e == hipSuccess) e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_fn(b->tpb, b->K, b->ntx),
-                                                         (int)b->tpb, b->shmem);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         batch_fail(b, e, "kpz_batch_init");
         delete b;
         return KPZ_EHIP;
     }
-    b->grid = (uint32_t)(cus * (per_cu > 0 ? per_cu : 1));
     *out = b;
     return KPZ_OK;
 }
@@ -1837,10 +1977,10 @@ kpz_status kpz_pool_job_bytes(const kpz_params *job, int32_t bx, int32_t by, siz
     return KPZ_OK;
 }
 
-kpz_status kpz_pool_control_bytes(int32_t max_jobs, int32_t max_quantum, size_t *bytes)
+kpz_status kpz_pool_control_bytes(int32_t max_jobs, size_t *bytes)
 {
-    if (max_jobs < 1 || max_quantum < 1 || !bytes) return KPZ_EINVAL;
-    *bytes = pool_ctl_layout(max_jobs, max_quantum).bytes;
+    if (max_jobs < 1 || !bytes) return KPZ_EINVAL;
+    *bytes = pool_ctl_layout(max_jobs).bytes;
     return KPZ_OK;
 }
 
@@ -1852,7 +1992,7 @@ kpz_status kpz_pool_init(kpz_pool **out, void *d_arena, size_t arena_bytes, int3
     if (!d_arena || ((uintptr_t)d_arena & 255) || max_jobs < 1 || max_quantum < 1) return KPZ_EINVAL;
     if (!is_pow2(bx) || !is_pow2(by) || bx < 16 || by < 16 || bx > 1024 || (int64_t)bx * by > 65536)
         return KPZ_EINVAL;
-    const PoolCtl ctl = pool_ctl_layout(max_jobs, max_quantum);
+    const PoolCtl ctl = pool_ctl_layout(max_jobs);
     if (arena_bytes < ctl.bytes) return KPZ_ESIZE;
     kpz_pool *p = new (std::nothrow) kpz_pool();
     if (!p) return KPZ_EINVAL;
@@ -1862,32 +2002,15 @@ kpz_status kpz_pool_init(kpz_pool **out, void *d_arena, size_t arena_bytes, int3
     p->max_quantum = max_quantum;
     p->Bx = (uint32_t)bx;
     p->By = (uint32_t)by;
-    p->ntx = p->Bx / TILE;
-    p->nq = p->ntx * (p->By / 16);
-    p->tpb = p->nq >= 256 ? 256u : 64u;
-    p->K = p->nq <= p->tpb ? 1u : p->nq / p->tpb;
-    p->shmem = sizeof(uint32_t) * 4 * (size_t)p->nq;
     p->stream = (hipStream_t)stream;
     p->ctl = ctl;
     p->next_id = 0;
     p->err[0] = 0;
-    if ((p->tpb == 256 && p->K > 4) || (p->tpb == 64 && p->K > 2)) {
+    if (!round_shape(p->Bx, p->By, &p->rs)) {
         delete p;
         return KPZ_EINVAL;
     }
     if (arena_bytes > ctl.bytes) p->free_list[ctl.bytes] = arena_bytes - ctl.bytes;
-    int dev = 0, cus = 0, per_cu = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_fn(p->tpb, p->K, p->ntx),
-                                                         (int)p->tpb, p->shmem);
-    if (e != hipSuccess) {
-        pool_fail(p, e, "kpz_pool_init");
-        delete p;
-        return KPZ_EHIP;
-    }
-    p->grid = (uint32_t)(cus * (per_cu > 0 ? per_cu : 1));
     *out = p;
     return KPZ_OK;
 }
@@ -1922,8 +2045,7 @@ kpz_status kpz_pool_submit(kpz_pool *p, const kpz_params *job, int64_t n_mcs, in
     j.off_slots = o; o += align256(sizeof(long long) * BATCH_SLOTS);
     j.off_rowA = o;  o += align256(8 * L);
     j.off_rowB = o;  o += align256(8 * L);
-    j.off_side = o;  o += align256(4 * 2 * L * (L / p->Bx));
-    j.off_pairs = o;
+    j.off_side = o;
     const uint32_t W = (uint32_t)(L / 16);
     uint32_t *words = (uint32_t *)(p->arena + j.off_words);
     if (W % 4 == 0) {
@@ -1937,9 +2059,6 @@ kpz_status kpz_pool_submit(kpz_pool *p, const kpz_params *job, int64_t n_mcs, in
     }
     hipLaunchKernelGGL(kpz_zero_kernel, dim3(1), dim3(256), 0, p->stream,
                        (uint32_t *)(p->arena + j.off_slots), (uint64_t)2 * BATCH_SLOTS);
-    const uint64_t npairs = (uint64_t)(L / p->Bx) * (L / p->By);
-    hipLaunchKernelGGL(kpz_zero_kernel, dim3((uint32_t)((npairs + 255) / 256)), dim3(256), 0,
-                       p->stream, (uint32_t *)(p->arena + j.off_pairs), npairs);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         pool_free(p, off, bytes);
@@ -1969,20 +2088,13 @@ kpz_status kpz_pool_step(kpz_pool *p, int32_t quantum, int32_t *n_active)
                      [&](size_t a, size_t b) { return rounds_of(a) > rounds_of(b); });
     std::vector<SweepArgs> args(n);
     std::vector<uint32_t> bprefix(n + 1, 0), rounds(n);
+    std::vector<unsigned long long> sprefix(n + 1, 0);
     for (size_t k = 0; k < n; ++k) {
         const PoolJob &j = p->jobs[order[k]];
         args[k] = pool_args(p, j);
         rounds[k] = rounds_of(order[k]);
         bprefix[k + 1] = bprefix[k] + args[k].nbx * args[k].nby;
-    }
-    const uint32_t R = rounds[0];
-    std::vector<unsigned long long> rstart(R + 1, 0);
-    std::vector<uint32_t> rmem(R + 1, 0);
-    size_t m = n;
-    for (uint32_t k = 0; k < R; ++k) {
-        while (m > 0 && rounds[m - 1] <= k) --m;   // members with rounds > k: [0, m)
-        rmem[k] = (uint32_t)m;
-        rstart[k + 1] = rstart[k] + bprefix[m];
+        sprefix[k + 1] = sprefix[k] + (unsigned long long)args[k].L * args[k].nbx;
     }
     hipError_t e = hipSuccess;
     auto h2d = [&](size_t off, const void *src, size_t bytes) {
@@ -1991,22 +2103,20 @@ kpz_status kpz_pool_step(kpz_pool *p, int32_t quantum, int32_t *n_active)
     };
     h2d(p->ctl.off_members, args.data(), sizeof(SweepArgs) * n);
     h2d(p->ctl.off_bprefix, bprefix.data(), 4 * (n + 1));
-    h2d(p->ctl.off_rstart, rstart.data(), 8 * ((size_t)R + 1));
-    h2d(p->ctl.off_rmem, rmem.data(), 4 * ((size_t)R + 1));
+    h2d(p->ctl.off_sprefix, sprefix.data(), 8 * (n + 1));
     if (e != hipSuccess) return pool_fail(p, e, "kpz_pool_step copy");
-    hipLaunchKernelGGL(kpz_batch_reset_kernel, dim3(1), dim3(256), 0, p->stream,
-                       (unsigned int *)(p->arena + p->ctl.off_ctl), (uint32_t)n);
-    BatchArgs ba;
-    ba.members = (const SweepArgs *)(p->arena + p->ctl.off_members);
-    ba.bprefix = (const uint32_t *)(p->arena + p->ctl.off_bprefix);
-    ba.round_start = (const unsigned long long *)(p->arena + p->ctl.off_rstart);
-    ba.round_members = (const uint32_t *)(p->arena + p->ctl.off_rmem);
-    ba.ctl = (unsigned int *)(p->arena + p->ctl.off_ctl);
-    ba.n = (uint32_t)n;
-    ba.per_round = bprefix[n];
-    ba.rounds = R;
-    e = pool_launch(p, ba);
-    if (e != hipSuccess) return pool_fail(p, e, "kpz_pool_step launch");
+    // round k runs the members with more than k rounds this step: a prefix
+    // [0, m) of the sorted table, so its grid is bprefix[m]
+    const SweepArgs *d_members = (const SweepArgs *)(p->arena + p->ctl.off_members);
+    const uint32_t *d_bprefix = (const uint32_t *)(p->arena + p->ctl.off_bprefix);
+    const unsigned long long *d_sprefix = (const unsigned long long *)(p->arena + p->ctl.off_sprefix);
+    size_t m = n;
+    for (uint32_t k = 0; k < rounds[0]; ++k) {
+        while (m > 0 && rounds[m - 1] <= k) --m;
+        e = round_launch(p->rs, bprefix[m], sprefix[m], p->stream, d_members, d_bprefix, d_sprefix,
+                         (uint32_t)m, k);
+        if (e != hipSuccess) return pool_fail(p, e, "kpz_pool_step launch");
+    }
     for (size_t k = 0; k < n; ++k) p->jobs[order[k]].t += rounds[k];
     // sample and release the jobs that reached their n_mcs
     std::vector<size_t> fin;
@@ -2026,15 +2136,13 @@ kpz_status kpz_pool_step(kpz_pool *p, int32_t quantum, int32_t *n_active)
             rprefix[f + 1] = rprefix[f] + (uint32_t)j.prm.L;
         }
         h2d(p->ctl.off_rows, rows.data(), sizeof(MemberRows) * fin.size());
-        // the bprefix area is free again once the launch has read it; reuse it
-        // (stream order) for the row prefix of the finished jobs
-        h2d(p->ctl.off_bprefix, rprefix.data(), 4 * (fin.size() + 1));
+        h2d(p->ctl.off_rprefix, rprefix.data(), 4 * (fin.size() + 1));
         if (e != hipSuccess) return pool_fail(p, e, "kpz_pool_step copy");
         const uint32_t total_rows = rprefix[fin.size()];
         const uint32_t rgrid = (total_rows + 3) / 4 < 8192 ? (total_rows + 3) / 4 : 8192;
         const MemberRows *mr = (const MemberRows *)(p->arena + p->ctl.off_rows);
         hipLaunchKernelGGL(kpz_batch_rows_kernel, dim3(rgrid), dim3(256), 0, p->stream, mr,
-                           (const uint32_t *)(p->arena + p->ctl.off_bprefix), (uint32_t)fin.size());
+                           (const uint32_t *)(p->arena + p->ctl.off_rprefix), (uint32_t)fin.size());
         hipLaunchKernelGGL(kpz_batch_finalize_kernel, dim3((uint32_t)fin.size()), dim3(256), 0,
                            p->stream, mr, (uint32_t)fin.size(), (uint32_t)BATCH_SLOTS,
                            (long long *)(p->arena + p->ctl.off_res), 0u);

@@ -61,10 +61,12 @@ class ServeReport:
 
 
 def serve(jobs: List[Job], hbm_bytes: int, quantum: int = 64, block=(256, 256),
-          max_jobs: int = 1024, clock=time.perf_counter) -> ServeReport:
+          max_jobs: int = 1024, clock=time.perf_counter, progress=None,
+          progress_every_s: float = 10.0) -> ServeReport:
     """Runs the jobs in real time: a job becomes visible at its arrival time,
     waits FIFO until it fits into the pool, and is done when its result is
-    back on the host."""
+    back on the host.  ``progress(done, total, resident)`` is called about
+    every ``progress_every_s`` seconds when given."""
     pool = Pool(hbm_bytes, max_jobs=max_jobs, max_quantum=quantum, block=block)
     pending = deque(sorted(jobs, key=lambda j: j.arrival))
     waiting: deque = deque()
@@ -74,8 +76,12 @@ def serve(jobs: List[Job], hbm_bytes: int, quantum: int = 64, block=(256, 256),
     resident = 0
     max_resident = 0
     done = 0
+    next_report = progress_every_s
     while done < len(jobs):
         now = clock() - t0
+        if progress is not None and now >= next_report:
+            progress(done, len(jobs), resident)
+            next_report = now + progress_every_s
         while pending and pending[0].arrival <= now:
             waiting.append(pending.popleft())
         while waiting:

@@ -1,4 +1,4 @@
-"""Ensemble (batched) path: every member of a persistent multi-lattice launch
+"""Ensemble (batched) path: every member of a multi-lattice launch
 is bit-identical to the single-lattice run with the same parameters and
 block shape (and so to the oracle), with uneven L and different p, q."""
 import numpy as np

@@ -220,3 +220,21 @@ def test_launch_shape_does_not_change_results(gpu, monkeypatch, block, q):
         runs.append((sim.words_host().copy(), sim.roughness()))
     assert np.array_equal(runs[0][0], runs[1][0])
     assert runs[0][1] == runs[1][1]
+
+
+@pytest.mark.parametrize("L,block,p,q,n", [(64, (64, 64), 1.0, 0.0, 20), (256, (64, 64), 1.0, 0.3, 6),
+                                           (192, (64, 64), 0.5, 0.5, 5), (1024, (256, 256), 1.0, 0.0, 3)])
+def test_height_moments_exact(gpu, oracle_lib, L, block, p, q, n):
+    """Fourth-order sums sum (h - h(0,0))^k equal the oracle's exact sums."""
+    sim = gpu.Sim(L, p, q, 7, block)
+    sim.sweep(n)
+    M, (w2, sk, ku) = sim.height_moments()
+    st = oracle_lib.SlopeState(L).run_dd(n, p, q, 7, block=block, tile=(4, 4))
+    rel = st.heights() - int(st.h00[0])
+    ref = [sum(int(v) for v in (rel.astype(object) ** k).ravel()) for k in (1, 2, 3, 4)]
+    assert M == ref
+    N = L * L
+    mu = ref[0] / N
+    m2 = ref[1] / N - mu * mu
+    assert math.isclose(w2, m2, rel_tol=1e-12)
+    assert w2 == pytest.approx(sim.roughness().W2, rel=1e-12)

@@ -58,7 +58,7 @@ def test_pool_admission_by_budget(gpu):
     probe = kpz.Pool(64 << 20, max_jobs=8, max_quantum=8)
     job_bytes = probe.job_bytes(one)
     probe.close()
-    ctl = 1 << 20
+    ctl = kpz.Pool.control_bytes(8)
     pool = kpz.Pool(ctl + job_bytes + job_bytes // 2, max_jobs=8, max_quantum=8)
     a = pool.submit(one, 5)
     assert a is not None
