@@ -184,6 +184,21 @@ def serving_leg(args):
     }
 
 
+def copy_probe(mib: int) -> None:
+    """A plain copy of known size (mib MiB read, mib MiB written per call):
+    hardware byte counters read on it give the scale between the counters'
+    units and bytes."""
+    import torch
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n, "calls": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,7 +222,13 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-hbm-gib", type=float, default=16.0)
     ap.add_argument("--serve-quantum", type=int, default=64)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (3 times) "
+                         "and exit: the known-size reference for HBM byte counters")
     args = ap.parse_args()
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on exactly one GPU (one lattice per device); "
