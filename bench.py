@@ -155,6 +155,45 @@ def ensemble_leg(args):
     }
 
 
+def latency_leg(args):
+    """The small workload: L = 64, p = 1, q = 0, seed 1, one 64 x 64 block
+    (periodic, no dead border), 1000 MCS with the exact moments after every
+    MCS.  Eager: each MCS is sweep(1) + roughness() (which waits for the
+    result); per-MCS latency p50/p99.  Graph: the whole run (1000 sweeps and
+    1000 samples) as one captured graph, through a one-member ensemble."""
+    import numpy as np
+    import torch
+    import paper_1204_5072_amd as kpz
+
+    L, n_mcs = 64, 1000
+    sim = kpz.Sim(L, 1.0, 0.0, 1, (64, 64))
+    sim.sweep(1)
+    sim.roughness()
+    lat = []
+    for _ in range(n_mcs):
+        t0 = time.perf_counter()
+        sim.sweep(1)
+        sim.roughness()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    sim.close()
+    ens = kpz.Ensemble([kpz.make_params(L, 1.0, 0.0, 1, (64, 64))])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, W2 = ens.run(list(range(1, n_mcs + 1)))
+    graph_s = time.perf_counter() - t0
+    ens.close()
+    lat = np.array(lat)
+    return {
+        "metric": "per-MCS latency (sweep + exact W^2 on the host), L=64",
+        "eager_p50_ms": float(np.percentile(lat, 50)),
+        "eager_p99_ms": float(np.percentile(lat, 99)),
+        "graph_run_ms": graph_s * 1e3,
+        "graph_ms_per_mcs": graph_s * 1e3 / n_mcs,
+        "mcs": n_mcs,
+        "w2_final": float(W2[-1, 0]),
+    }
+
+
 def serving_leg(args):
     """Serving: Poisson stream of jobs (2000 at 50 jobs/s by default), L =
     2^k with k uniform on 8..13, p = 1, q uniform on [0, 0.5], MCS log-uniform
@@ -210,6 +249,8 @@ def main():
     ap.add_argument("--p", type=float, default=1.0)
     ap.add_argument("--q", type=float, default=0.0)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--moves", type=int, default=1,
+                    help="dead-border origin moves per MCS (block residency 1/moves MCS)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
@@ -218,6 +259,7 @@ def main():
     ap.add_argument("--ens-block", type=int, nargs=2, default=None)
     ap.add_argument("--ens-seq-members", type=int, default=32)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-hbm-gib", type=float, default=16.0)
@@ -242,7 +284,7 @@ def main():
     block = tuple(args.block)
     print(f"bench: L={L} block={block} p={args.p} q={args.q} seed={args.seed} "
           f"steps={args.steps} warmup={args.warmup} mcs/step={M}", file=sys.stderr, flush=True)
-    sim = kpz.Sim(L, args.p, args.q, args.seed, block)
+    sim = kpz.Sim(L, args.p, args.q, args.seed, block, moves=args.moves)
     stream = sim.stream
     for _ in range(args.warmup):
         sim.sweep(M)
@@ -295,6 +337,7 @@ def main():
                         f"Philox seed {args.seed}, dead-border blocks {block[0]}x{block[1]}, "
                         f"4x4 double tiles; step = {M} MCS + one exact W^2 sample",
             "L": L, "block": list(block), "tile": [4, 4], "mcs_per_step": M,
+            "origin_moves_per_mcs": args.moves,
         },
         "roofline": {
             "bound": "alu",
@@ -321,6 +364,9 @@ def main():
     if not args.no_ensemble:
         print("bench: ensemble leg", file=sys.stderr, flush=True)
         line["ensemble"] = ensemble_leg(args)
+    if not args.no_latency:
+        print("bench: latency leg", file=sys.stderr, flush=True)
+        line["latency"] = latency_leg(args)
     if not args.no_serve:
         print("bench: serving leg", file=sys.stderr, flush=True)
         line["serving"] = serving_leg(args)

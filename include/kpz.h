@@ -75,9 +75,15 @@ typedef enum {
  *            double-tiling tile shape of the work-group layer (Sec. 3.1);
  *            must be 4 x 4 (four 2 x 2 cells per tile, 16 single-hit steps
  *            per MCS); 0 = default (4).
+ *   moves    how often the dead-border origin moves per MCS (Sec. 3: the
+ *            origin is moved randomly "after some time"): 1, 2, 4, 8 or 16;
+ *            0 = default (1).  Each MCS then runs `moves` residencies of
+ *            16 / moves single-hit steps, each with its own random origin
+ *            (block residency 1 / moves MCS; every residency reads and
+ *            writes the whole lattice once).
  *   flags    reserved, must be 0.
- * The shape changes the sequence of updates, so results are reproducible for
- * identical (L, p, q, seed, block, tile) only. */
+ * The shape and `moves` change the sequence of updates, so results are
+ * reproducible for identical (L, p, q, seed, block, tile, moves) only. */
 typedef struct {
     int32_t L;
     double p;
@@ -87,6 +93,7 @@ typedef struct {
     int32_t block_y;
     int32_t tile_x;
     int32_t tile_y;
+    int32_t moves;
     uint32_t flags;
 } kpz_params;
 
@@ -154,7 +161,8 @@ const char *kpz_last_error(const kpz_sim *sim);
  * Ensemble averages of W^2(t) need hundreds of independent realisations.  A
  * batch holds n members, each a full simulation as above with its own L, p,
  * q and seed; all members share one block shape (block_x, block_y, resolved
- * as for a single lattice from the smallest L when 0) and the 4 x 4 tile.
+ * as for a single lattice from the smallest L when 0), the 4 x 4 tile and
+ * `moves`.
  * Every member's results are bit-identical to a single-lattice run with the
  * same parameters and block shape.  Each MCS of a kpz_batch_sweep is one
  * launch over the blocks of all members plus one launch that merges their
@@ -168,7 +176,7 @@ const char *kpz_last_error(const kpz_sim *sim);
  */
 typedef struct kpz_batch kpz_batch;
 
-#define KPZ_BATCH_MAX_SAMPLES 128
+#define KPZ_BATCH_MAX_SAMPLES 1024
 
 /* Device bytes of the words buffer and of the workspace for these members
  * (n >= 1).  KPZ_EINVAL if a member is invalid or the block shapes differ. */
@@ -219,9 +227,10 @@ const char *kpz_batch_last_error(const kpz_batch *batch);
  * in rounds: round k is one launch over all blocks of the jobs with more
  * than k MCS left in this step (plus the merge of their straddling words);
  * jobs submitted between steps join the next one, so new work overlaps
- * running work on the device.  A job's
- * result is bit-identical whatever else runs with it.  All jobs of a pool
- * share the pool's block shape (block_x, block_y must divide every L).
+ * running work on the device.  A job's result is bit-identical whatever
+ * else runs with it.  All jobs of a pool share the pool's block shape
+ * (block_x, block_y must divide every L) and move the origin once per MCS
+ * (moves 0 or 1).
  */
 typedef struct kpz_pool kpz_pool;
 

@@ -67,14 +67,14 @@ def lib():
         L.or_rs_slopes_run.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
                                        c.c_uint32, c.c_int, i8p, i8p, i64p, i64p]
         L.or_dd_run.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
-                                c.c_int, c.c_int, c.c_int, c.c_int,
+                                c.c_int, c.c_int, c.c_int, c.c_int, c.c_int,
                                 c.c_uint32, c.c_int, i8p, i8p, i64p, i64p, c.c_int]
         L.or_rs1d_run.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
                                   c.c_uint32, c.c_int, i8p, i64p, i64p]
         L.or_dd_block_mcs.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
-                                      c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint32,
-                                      c.c_int, c.c_int, i8p, i8p, i64p]
-        L.or_dd_origin.argtypes = [c.c_uint64, c.c_uint32, c.c_int, c.c_int,
+                                      c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint32,
+                                      c.c_int, c.c_int, c.c_int, i8p, i8p, i64p]
+        L.or_dd_origin.argtypes = [c.c_uint64, c.c_uint32, c.c_int, c.c_int, c.c_int,
                                    c.POINTER(c.c_int), c.POINTER(c.c_int)]
         L.or_dd_origin.restype = None
         for f in ("or_flat", "or_rs_heights_run", "or_rs_slopes_run", "or_dd_run", "or_rs1d_run",
@@ -131,11 +131,13 @@ class SlopeState:
 
     # dynamics
     def run_dd(self, n_mcs: int, p: float, q: float, seed: int, block=(None, None),
-               tile=(4, 4), check: bool = False) -> "SlopeState":
+               tile=(4, 4), check: bool = False, moves: int = 1) -> "SlopeState":
+        """n_mcs MCS of the decomposed schedule; ``moves`` = origin moves
+        per MCS (block residency 1/moves MCS)."""
         bx = block[0] or self.L
         by = block[1] or self.L
-        rc = lib().or_dd_run(self.L, p, q, seed, bx, by, tile[0], tile[1], self.t, n_mcs,
-                             self.sx, self.sy, self.h00, self.net, int(check))
+        rc = lib().or_dd_run(self.L, p, q, seed, bx, by, tile[0], tile[1], moves, self.t,
+                             n_mcs, self.sx, self.sy, self.h00, self.net, int(check))
         _check(rc, "dd_run")
         self.t += n_mcs
         return self
@@ -167,19 +169,21 @@ def rs_heights_run(h: np.ndarray, t0: int, n_mcs: int, p: float, q: float, seed:
     return h
 
 
-def dd_origin(seed: int, t: int, block) -> tuple:
+def dd_origin(seed: int, t: int, block, res: int = 0) -> tuple:
+    """Block origin of residency ``res`` of MCS t."""
     ox, oy = ctypes.c_int(), ctypes.c_int()
-    lib().or_dd_origin(seed, t, block[0], block[1], ctypes.byref(ox), ctypes.byref(oy))
+    lib().or_dd_origin(seed, t, res, block[0], block[1], ctypes.byref(ox), ctypes.byref(oy))
     return ox.value, oy.value
 
 
 def dd_block_mcs(L: int, p: float, q: float, seed: int, block, t: int, bx: int, by: int,
-                 bsx: np.ndarray, bsy: np.ndarray) -> int:
-    """One MCS of block (bx, by) on its own slopes (arrays of shape
-    (By, Bx), modified in place); returns the net number of flips."""
+                 bsx: np.ndarray, bsy: np.ndarray, moves: int = 1, res: int = 0) -> int:
+    """Residency ``res`` of MCS t (the whole MCS when moves = 1) of block
+    (bx, by) on its own slopes (arrays of shape (By, Bx), modified in
+    place); returns the net number of flips."""
     net = np.zeros(1, np.int64)
-    _check(lib().or_dd_block_mcs(L, p, q, seed, block[0], block[1], 4, 4, t, bx, by, bsx, bsy,
-                                 net), "dd_block_mcs")
+    _check(lib().or_dd_block_mcs(L, p, q, seed, block[0], block[1], 4, 4, moves, t, res, bx, by,
+                                 bsx, bsy, net), "dd_block_mcs")
     return int(net[0])
 
 

@@ -189,7 +189,11 @@ class SmallChain:
         T1 = sum(self.site_operator(s, p, q) for s in range(self.N)) / self.N
         return np.linalg.matrix_power(T1, self.N)
 
-    def dd_mcs(self, p: float, q: float, block, tile) -> np.ndarray:
+    def dd_mcs(self, p: float, q: float, block, tile, moves: int = 1) -> np.ndarray:
+        """Transition matrix of one MCS of the decomposed schedule: per
+        residency a uniform random origin, then S/moves single-hit steps
+        (each block a uniform set, each tile a uniform site of its cell);
+        the MCS is ``moves`` independent residencies (Sec. 3, 3.1)."""
         L = self.L
         Bx, By = block
         Tx, Ty = tile
@@ -199,6 +203,7 @@ class SmallChain:
         S = Tx * Ty
         ops = {s: self.site_operator(s, p, q) for s in range(self.N)}
         I = np.eye(self.n)
+        assert S % moves == 0
         total = np.zeros((self.n, self.n))
         for oy in range(By):
             for ox in range(Bx):
@@ -228,8 +233,8 @@ class SmallChain:
                                     M = M @ (cell / (cx * cy))
                             bstep += M / 4.0
                         step = step @ bstep
-                total += np.linalg.matrix_power(step, S)
-        return total / (Bx * By)
+                total += np.linalg.matrix_power(step, S // moves)
+        return np.linalg.matrix_power(total / (Bx * By), moves)
 
     def expected_w2(self, T: np.ndarray, times) -> dict:
         pi = np.zeros(self.n)

@@ -226,10 +226,18 @@ int or_rs_slopes_run(int L, double p, double q, uint64_t seed, uint32_t t0, int 
  * Acceptance uniform of member j of group G at step k:
  * u = A << 24 | (B & 0xFFFFFF), A = byte j of word (k mod 4) of
  * draw (ACC1, t, G, k/4), B = word j of draw (ACC2, t, G, k).
+ *
+ * Block residency (Sec. 3: the origin is moved "after some time").  With
+ * `moves` = m > 1 the origin moves m times per MCS: residency i = 0..m-1
+ * of MCS t has its own origin from draw (ORIGIN, t, i, 0) and runs steps
+ * k = i S/m .. (i+1) S/m - 1 in the blocks of that origin, with the set,
+ * site and acceptance draws above taken with sub-counters (SET: i; SITE: i;
+ * ACC1: 4i + k/4; ACC2: 16i + k).  m = 1 is the schedule above.
  */
-static int dd_validate(int L, int Bx, int By, int Tx, int Ty)
+static int dd_validate(int L, int Bx, int By, int Tx, int Ty, int moves)
 {
     if (L <= 0 || (L & 1)) return 0;
+    if (moves < 1 || (moves & (moves - 1)) || (Tx * Ty) % moves) return 0;
     if (Bx <= 0 || By <= 0 || L % Bx || L % By) return 0;
     if (!((Tx == 4 && Ty == 4) || (Tx == 2 && Ty == 2))) return 0;
     if (Bx % Tx || By % Ty) return 0;
@@ -239,10 +247,10 @@ static int dd_validate(int L, int Bx, int By, int Tx, int Ty)
 }
 
 int or_dd_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, int Ty,
-              uint32_t t0, int n_mcs, int8_t *sx, int8_t *sy, int64_t *h00, int64_t *net,
-              int check)
+              int moves, uint32_t t0, int n_mcs, int8_t *sx, int8_t *sy, int64_t *h00,
+              int64_t *net, int check)
 {
-    if (!dd_validate(L, Bx, By, Tx, Ty) || n_mcs < 0) return OR_EINVAL;
+    if (!dd_validate(L, Bx, By, Tx, Ty, moves) || n_mcs < 0) return OR_EINVAL;
     const int nbx = L / Bx, nby = L / By;
     const int ntx = Bx / Tx, nty = By / Ty;
     const int H = nty >= 4 ? nty / 4 : 1;
@@ -268,23 +276,25 @@ int or_dd_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
     int status = OR_OK;
     uint32_t w[4];
 
+    const int per_res = S / moves;
     for (int m = 0; m < n_mcs && status == OR_OK; ++m) {
-        const uint32_t t = t0 + (uint32_t)m;
-        or_draw(seed, OR_TAG_ORIGIN, t, 0, 0, w);
+      const uint32_t t = t0 + (uint32_t)m;
+      for (int res = 0; res < moves && status == OR_OK; ++res) {
+        or_draw(seed, OR_TAG_ORIGIN, t, (uint64_t)res, 0, w);
         const int ox = (int)(((uint64_t)w[0] * (uint64_t)Bx) >> 32);
         const int oy = (int)(((uint64_t)w[1] * (uint64_t)By) >> 32);
         for (int b = 0; b < nblocks; ++b) {
-            or_draw(seed, OR_TAG_SET, t, (uint64_t)b, 0, w);
+            or_draw(seed, OR_TAG_SET, t, (uint64_t)b, (uint32_t)res, w);
             setw[b] = w[0];
             if (has_site_draw)
                 for (uint64_t g = 0; g < nq; ++g) {
-                    or_draw(seed, OR_TAG_SITE, t, (uint64_t)b * nq + g, 0, w);
+                    or_draw(seed, OR_TAG_SITE, t, (uint64_t)b * nq + g, (uint32_t)res, w);
                     memcpy(&sitew[4 * ((uint64_t)b * nq + g)], w, sizeof w);
                 }
         }
         /* all blocks make step k "at the same time"; blocks are independent,
            so visiting them one after the other gives the same result */
-        for (int k = 0; k < S && status == OR_OK; ++k, ++step_id) {
+        for (int k = res * per_res; k < (res + 1) * per_res && status == OR_OK; ++k, ++step_id) {
             for (int by = 0; by < nby; ++by)
                 for (int bx = 0; bx < nbx; ++bx) {
                     const int b = by * nbx + bx;
@@ -318,8 +328,8 @@ int or_dd_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
                             if (thr == 0) continue;
                             if (thr < FULL) {
                                 uint32_t wa[4], wb[4];
-                                or_draw(seed, OR_TAG_ACC1, t, G, (uint32_t)(k >> 2), wa);
-                                or_draw(seed, OR_TAG_ACC2, t, G, (uint32_t)k, wb);
+                                or_draw(seed, OR_TAG_ACC1, t, G, (uint32_t)(4 * res + (k >> 2)), wa);
+                                or_draw(seed, OR_TAG_ACC2, t, G, (uint32_t)(16 * res + k), wb);
                                 const uint32_t A = (wa[k & 3] >> (8 * j)) & 0xFFu;
                                 const uint32_t u = (A << 24) | (wb[j] & 0xFFFFFFu);
                                 if ((uint64_t)u >= thr) continue;
@@ -331,6 +341,7 @@ int or_dd_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
                         }
                 }
         }
+      }
     }
     free(setw); free(sitew); free(stamp);
     return status;
@@ -370,8 +381,9 @@ int or_rs1d_run(int L, double p, double q, uint64_t seed, uint32_t t0, int n_mcs
 /* ------------------------------------------- one block, on its own copy */
 
 /*
- * One MCS t of the decomposed schedule restricted to block (bx, by), run on a
- * copy of that block's sites: bsx[ly*Bx+lx], bsy[ly*Bx+lx] hold sigma_x,
+ * Residency res of MCS t of the decomposed schedule (the whole MCS when
+ * moves = 1) restricted to block (bx, by) of that residency's origin, run on
+ * a copy of that block's sites: bsx[ly*Bx+lx], bsy[ly*Bx+lx] hold sigma_x,
  * sigma_y of block-local site (lx, ly), i.e. global site
  * ((ox + bx*Bx + lx) mod L, (oy + by*By + ly) mod L).  Requires more than one
  * block along both axes: then the dead border (lx = 0, ly = 0) keeps every
@@ -379,9 +391,10 @@ int or_rs1d_run(int L, double p, double q, uint64_t seed, uint32_t t0, int n_mcs
  * or_dd_run.  Same draws and the same step order as or_dd_run.
  */
 int or_dd_block_mcs(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, int Ty,
-                    uint32_t t, int bx, int by, int8_t *bsx, int8_t *bsy, int64_t *net)
+                    int moves, uint32_t t, int res, int bx, int by, int8_t *bsx, int8_t *bsy,
+                    int64_t *net)
 {
-    if (!dd_validate(L, Bx, By, Tx, Ty)) return OR_EINVAL;
+    if (!dd_validate(L, Bx, By, Tx, Ty, moves) || res < 0 || res >= moves) return OR_EINVAL;
     const int nbx = L / Bx, nby = L / By;
     if (nbx < 2 || nby < 2 || bx < 0 || by < 0 || bx >= nbx || by >= nby) return OR_EINVAL;
     const int ntx = Bx / Tx, nty = By / Ty;
@@ -393,10 +406,11 @@ int or_dd_block_mcs(int L, double p, double q, uint64_t seed, int Bx, int By, in
     const uint64_t P = threshold(p), Q = threshold(q);
     const uint64_t FULL = (uint64_t)1 << 32;
     const int b = by * nbx + bx;
+    const int per_res = S / moves;
     uint32_t w[4];
-    or_draw(seed, OR_TAG_SET, t, (uint64_t)b, 0, w);
+    or_draw(seed, OR_TAG_SET, t, (uint64_t)b, (uint32_t)res, w);
     const uint32_t setw = w[0];
-    for (int k = 0; k < S; ++k) {
+    for (int k = res * per_res; k < (res + 1) * per_res; ++k) {
         const int s = (int)((setw >> (2 * k)) & 3u);
         const int ssx = s & 1, ssy = s >> 1;
         for (int ty = 0; ty < nty; ++ty)
@@ -405,7 +419,7 @@ int or_dd_block_mcs(int L, double p, double q, uint64_t seed, int Bx, int By, in
                 const uint64_t G = (uint64_t)b * nq + (uint64_t)(ty % H) * ntx + tx;
                 int r = 0;
                 if (has_site_draw) {
-                    or_draw(seed, OR_TAG_SITE, t, G, 0, w);
+                    or_draw(seed, OR_TAG_SITE, t, G, (uint32_t)res, w);
                     r = (int)((w[k >> 2] >> (8 * j + 2 * (k & 3))) & 3u);
                 }
                 const int rx = has_site_draw ? (r & 1) : 0;
@@ -423,8 +437,8 @@ int or_dd_block_mcs(int L, double p, double q, uint64_t seed, int Bx, int By, in
                 if (thr == 0) continue;
                 if (thr < FULL) {
                     uint32_t wa[4], wb[4];
-                    or_draw(seed, OR_TAG_ACC1, t, G, (uint32_t)(k >> 2), wa);
-                    or_draw(seed, OR_TAG_ACC2, t, G, (uint32_t)k, wb);
+                    or_draw(seed, OR_TAG_ACC1, t, G, (uint32_t)(4 * res + (k >> 2)), wa);
+                    or_draw(seed, OR_TAG_ACC2, t, G, (uint32_t)(16 * res + k), wb);
                     const uint32_t A = (wa[k & 3] >> (8 * j)) & 0xFFu;
                     const uint32_t u = (A << 24) | (wb[j] & 0xFFFFFFu);
                     if ((uint64_t)u >= thr) continue;
@@ -436,11 +450,12 @@ int or_dd_block_mcs(int L, double p, double q, uint64_t seed, int Bx, int By, in
     return OR_OK;
 }
 
-/* Origin of MCS t: ox = floor(w0 * Bx / 2^32), oy = floor(w1 * By / 2^32). */
-void or_dd_origin(uint64_t seed, uint32_t t, int Bx, int By, int *ox, int *oy)
+/* Origin of residency res of MCS t: ox = floor(w0 * Bx / 2^32),
+ * oy = floor(w1 * By / 2^32) of draw (ORIGIN, t, res, 0). */
+void or_dd_origin(uint64_t seed, uint32_t t, int res, int Bx, int By, int *ox, int *oy)
 {
     uint32_t w[4];
-    or_draw(seed, OR_TAG_ORIGIN, t, 0, 0, w);
+    or_draw(seed, OR_TAG_ORIGIN, t, (uint64_t)res, 0, w);
     *ox = (int)(((uint64_t)w[0] * (uint64_t)Bx) >> 32);
     *oy = (int)(((uint64_t)w[1] * (uint64_t)By) >> 32);
 }

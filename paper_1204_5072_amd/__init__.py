@@ -30,7 +30,7 @@ EXPORTED = ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness", "kp
             "kpz_pool_job_bytes", "kpz_pool_control_bytes", "kpz_pool_init", "kpz_pool_submit",
             "kpz_pool_step", "kpz_pool_poll", "kpz_pool_stats", "kpz_pool_destroy",
             "kpz_pool_last_error")
-BATCH_MAX_SAMPLES = 128
+BATCH_MAX_SAMPLES = 1024
 
 
 class KPZError(RuntimeError):
@@ -46,7 +46,8 @@ class kpz_params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("p", ctypes.c_double), ("q", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("block_x", ctypes.c_int32),
                 ("block_y", ctypes.c_int32), ("tile_x", ctypes.c_int32),
-                ("tile_y", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("tile_y", ctypes.c_int32), ("moves", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
 
 
 _lib = None
@@ -118,10 +119,13 @@ def status_str(status: int) -> str:
 
 
 def make_params(L: int, p: float = 1.0, q: float = 0.0, seed: int = 1,
-                block: Optional[Tuple[int, int]] = None, tile: Tuple[int, int] = (4, 4)) -> kpz_params:
+                block: Optional[Tuple[int, int]] = None, tile: Tuple[int, int] = (4, 4),
+                moves: int = 1) -> kpz_params:
+    """Parameters of one lattice; ``moves`` = dead-border origin moves per
+    MCS (block residency 1/moves MCS)."""
     bx, by = block if block else (0, 0)
     return kpz_params(L, float(p), float(q), int(seed), int(bx), int(by), int(tile[0]),
-                      int(tile[1]), 0)
+                      int(tile[1]), int(moves), 0)
 
 
 def workspace_bytes(params: kpz_params) -> int:
@@ -144,9 +148,10 @@ class Sim:
     L*L/16 packed slope words (bit layout in include/kpz.h)."""
 
     def __init__(self, L: int, p: float = 1.0, q: float = 0.0, seed: int = 1,
-                 block: Optional[Tuple[int, int]] = None, device="cuda", stream=None):
+                 block: Optional[Tuple[int, int]] = None, device="cuda", stream=None,
+                 moves: int = 1):
         import torch
-        self.params = make_params(L, p, q, seed, block)
+        self.params = make_params(L, p, q, seed, block, moves=moves)
         self.L = L
         ws = workspace_bytes(self.params)
         self.device = torch.device(device)
@@ -230,8 +235,9 @@ def batch_sizes(members) -> Tuple[int, int]:
 
 class Ensemble:
     """n independent lattices on one GPU, advanced together: each MCS is one
-    launch over the blocks of every member (plus the straddling-word merge).  ``members`` is a list of kpz_params (see
-    make_params); all must resolve to the same block shape."""
+    launch over the blocks of every member (plus the straddling-word merge).
+    ``members`` is a list of kpz_params (see make_params); all must resolve
+    to the same block shape."""
 
     def __init__(self, members, device="cuda", stream=None):
         import torch

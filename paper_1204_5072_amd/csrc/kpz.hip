@@ -143,6 +143,8 @@ struct SweepArgs {
     uint32_t units;              // load/store units per block (nq / 2)
     uint32_t seed_lo, seed_hi;
     uint32_t t;
+    uint32_t res;                // residency of MCS t (origin move), 0 .. moves - 1
+    uint32_t nsteps;             // single-hit steps per residency (16 / moves)
     uint32_t slot_mask;          // flip-counter slots - 1 (power of two)
     uint32_t acc;                // 1 unless P = 2^32 and Q = 0 (acceptance draws needed)
     uint64_t P, Q;               // acceptance thresholds over 2^32
@@ -237,7 +239,8 @@ __device__ __forceinline__ void quad_update(uint32_t *lds, uint32_t ca, uint32_t
         const uint32_t tieP = (!ac.fullP && ac.lowP) ? (mn & byte_eq(Aw, ac.tP)) : 0u;
         const uint32_t tieQ = ac.lowQ ? (mx & byte_eq(Aw, ac.tQ)) : 0u;
         if (__any((tieP | tieQ) != 0)) {
-            const U4 w2 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t, (TAG_ACC2 << 24) | k,
+            const U4 w2 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t,
+                                 (TAG_ACC2 << 24) | (16u * a.res + k),
                                  a.seed_lo, a.seed_hi);
             const uint32_t Bw[4] = {w2.x, w2.y, w2.z, w2.w};
 #pragma unroll
@@ -306,8 +309,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
     const uint32_t nq = NTX ? (uint32_t)NTX * a.H : a.nq;
     const uint32_t nw = ntx / 4;
 
-    // device layer: origin of this MCS, then this block's frame
-    const U4 wo = philox(0u, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
+    // device layer: origin of this residency, then this block's frame
+    const U4 wo = philox(a.res, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
     const uint32_t ox = (uint32_t)(((uint64_t)wo.x * a.Bx) >> 32);
     const uint32_t oy = (uint32_t)(((uint64_t)wo.y * a.By) >> 32);
     uint32_t gx0 = ox + bx * a.Bx;
@@ -367,15 +370,17 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const uint64_t G = Gbase + tid + (uint32_t)TPB * i;
-        const U4 s4 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t, TAG_SITE << 24, a.seed_lo,
-                             a.seed_hi);
+        const U4 s4 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t, (TAG_SITE << 24) | a.res,
+                             a.seed_lo, a.seed_hi);
         sw[i][0] = s4.x;
         sw[i][1] = s4.y;
         sw[i][2] = s4.z;
         sw[i][3] = s4.w;
         aw[i][0] = aw[i][1] = aw[i][2] = aw[i][3] = 0u;
     }
-    const uint32_t setw = philox(b, 0u, a.t, TAG_SET << 24, a.seed_lo, a.seed_hi).x;
+    const uint32_t setw = philox(b, 0u, a.t, (TAG_SET << 24) | a.res, a.seed_lo, a.seed_hi).x;
+    // steps of this residency: [k0, k1) of the MCS's 16
+    const uint32_t k0 = a.res * a.nsteps, k1 = k0 + a.nsteps;
     AccCtx ac;
     ac.fullP = a.P >= (1ull << 32);
     ac.tP = ac.fullP ? 256u : (uint32_t)(a.P >> 24);
@@ -387,14 +392,17 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
 
     __syncthreads();
 
-    // ---- work-group layer: 16 single-hit steps k = 4 kq + kr
+    // ---- work-group layer: single-hit steps k = 4 kq + kr in [k0, k1)
+    // (all 16 when the origin moves once per MCS); the step range is the
+    // same for the whole block, so skipping steps never splits a barrier
     for (int kq = 0; kq < 4; ++kq) {
-        if (ACC) {
+        if (ACC && 4u * kq + 3u >= k0 && 4u * kq < k1) {
 #pragma unroll
             for (int i = 0; i < K; ++i) {
                 const uint64_t G = Gbase + tid + (uint32_t)TPB * i;
                 const U4 w1 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t,
-                                     (TAG_ACC1 << 24) | (uint32_t)kq, a.seed_lo, a.seed_hi);
+                                     (TAG_ACC1 << 24) | (4u * a.res + (uint32_t)kq), a.seed_lo,
+                                     a.seed_hi);
                 aw[i][0] = w1.x;
                 aw[i][1] = w1.y;
                 aw[i][2] = w1.z;
@@ -404,13 +412,16 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
         for (uint32_t kr = 0; kr < 4; ++kr) {
             const uint32_t k = 4u * kq + kr;
             const uint32_t s = (setw >> (2 * k)) & 3u;
-            if (active) {
-                switch (s) {
-                case 0: step_quads<TPB, K, NTX, 0, 0, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
-                case 1: step_quads<TPB, K, NTX, 1, 0, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
-                case 2: step_quads<TPB, K, NTX, 0, 1, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
-                default: step_quads<TPB, K, NTX, 1, 1, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
+            if (k >= k0 && k < k1) {
+                if (active) {
+                    switch (s) {
+                    case 0: step_quads<TPB, K, NTX, 0, 0, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
+                    case 1: step_quads<TPB, K, NTX, 1, 0, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
+                    case 2: step_quads<TPB, K, NTX, 0, 1, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
+                    default: step_quads<TPB, K, NTX, 1, 1, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
+                    }
                 }
+                __syncthreads();
             }
             if (ACC) {
 #pragma unroll
@@ -420,7 +431,6 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
                     aw[i][2] = aw[i][3];
                 }
             }
-            __syncthreads();
         }
 #pragma unroll
         for (int i = 0; i < K; ++i) {
@@ -510,7 +520,7 @@ __device__ __forceinline__ void merge_one(const SweepArgs &a, uint32_t ox, uint6
 
 __device__ __forceinline__ uint32_t origin_x(const SweepArgs &a)
 {
-    const U4 wo = philox(0u, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
+    const U4 wo = philox(a.res, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
     return (uint32_t)(((uint64_t)wo.x * a.Bx) >> 32);
 }
 
@@ -928,7 +938,8 @@ struct MemberRows {
 template <int TPB, int K, int NTX>
 __global__ __launch_bounds__(TPB) void kpz_batch_round_kernel(const SweepArgs *members,
                                                               const uint32_t *bprefix,
-                                                              uint32_t nmem, uint32_t k)
+                                                              uint32_t nmem, uint32_t k,
+                                                              uint32_t res)
 {
     extern __shared__ uint32_t lds[];
     const uint32_t g = blockIdx.x;
@@ -941,15 +952,16 @@ __global__ __launch_bounds__(TPB) void kpz_batch_round_kernel(const SweepArgs *m
     const uint32_t r = __builtin_amdgcn_readfirstlane(lo);
     SweepArgs a = members[r];
     a.t += k;
+    a.res = res;
     const uint32_t b = g - bprefix[r];
     if (a.acc) sweep_block<TPB, K, NTX, true>(a, b, lds);
     else sweep_block<TPB, K, NTX, false>(a, b, lds);
 }
 
-// Straddling words of members [0, nmem) after round k; sprefix = prefix
-// sums of L_r * nbx_r.
+// Straddling words of members [0, nmem) after round (k, res); sprefix =
+// prefix sums of L_r * nbx_r.
 __global__ void kpz_batch_merge_kernel(const SweepArgs *members, const unsigned long long *sprefix,
-                                       uint32_t nmem, uint32_t k)
+                                       uint32_t nmem, uint32_t k, uint32_t res)
 {
     const uint64_t total = sprefix[nmem];
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < total;
@@ -962,6 +974,7 @@ __global__ void kpz_batch_merge_kernel(const SweepArgs *members, const unsigned 
         }
         SweepArgs a = members[lo];
         a.t += k;
+        a.res = res;
         const uint32_t ox = origin_x(a);
         if ((ox & 15u) != 0) merge_one(a, ox, i - sprefix[lo]);
     }
@@ -1061,6 +1074,9 @@ kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
     if (p->L < 16 || (p->L % 16) != 0) return KPZ_EINVAL;
     if (!(p->p >= 0.0 && p->p <= 1.0 && p->q >= 0.0 && p->q <= 1.0)) return KPZ_EINVAL;
     if (p->flags != 0) return KPZ_EINVAL;
+    if (p->moves != 0 && p->moves != 1 && p->moves != 2 && p->moves != 4 && p->moves != 8 &&
+        p->moves != 16)
+        return KPZ_EINVAL;
     const int tx = p->tile_x ? p->tile_x : TILE, ty = p->tile_y ? p->tile_y : TILE;
     if (tx != TILE || ty != TILE) return KPZ_EINVAL;
     const int64_t L = p->L;
@@ -1076,6 +1092,8 @@ kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
     *By = (uint32_t)by;
     return KPZ_OK;
 }
+
+uint32_t moves_of(const kpz_params *p) { return p->moves ? (uint32_t)p->moves : 1u; }
 
 size_t ws_needed(int64_t L, int64_t Bx, int64_t By)
 {
@@ -1157,6 +1175,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct BatchLayout {
     uint32_t Bx, By;
+    uint32_t moves;                 // origin moves per MCS, common to all members
     std::vector<size_t> word_off;   // per member, in words
     size_t words_bytes;
     size_t off_members, off_bprefix, off_sprefix, off_rprefix, off_rows, off_res, off_slots;
@@ -1173,6 +1192,9 @@ kpz_status batch_layout(const kpz_params *m, int32_t n, BatchLayout *lay)
     int64_t dflt = 256;
     while (Lmin % dflt) dflt >>= 1;
     int64_t bx = -1, by = -1;
+    for (int32_t r = 0; r < n; ++r)
+        if (moves_of(&m[r]) != moves_of(&m[0])) return KPZ_EINVAL;
+    lay->moves = moves_of(&m[0]);
     for (int32_t r = 0; r < n; ++r) {
         kpz_params q = m[r];
         if (!q.block_x) q.block_x = (int32_t)dflt;
@@ -1231,47 +1253,49 @@ bool round_shape(uint32_t Bx, uint32_t By, RoundShape *rs)
 
 template <int TPB, int K>
 void round_launch_k(const RoundShape &rs, uint32_t grid, hipStream_t st, const SweepArgs *members,
-                    const uint32_t *bprefix, uint32_t nmem, uint32_t k)
+                    const uint32_t *bprefix, uint32_t nmem, uint32_t k, uint32_t res)
 {
     switch (rs.ntx) {
     case 64:
         hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 64>), dim3(grid), dim3(TPB), rs.shmem,
-                           st, members, bprefix, nmem, k);
+                           st, members, bprefix, nmem, k, res);
         break;
     case 128:
         hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 128>), dim3(grid), dim3(TPB), rs.shmem,
-                           st, members, bprefix, nmem, k);
+                           st, members, bprefix, nmem, k, res);
         break;
     case 256:
         hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 256>), dim3(grid), dim3(TPB), rs.shmem,
-                           st, members, bprefix, nmem, k);
+                           st, members, bprefix, nmem, k, res);
         break;
     default:
         hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 0>), dim3(grid), dim3(TPB), rs.shmem,
-                           st, members, bprefix, nmem, k);
+                           st, members, bprefix, nmem, k, res);
         break;
     }
 }
 
-// One round (MCS k of the call) of members [0, nmem) plus the merge of
-// their straddling words.  grid = bprefix[nmem], mwords = sprefix[nmem].
+// One round (residency res of MCS k of the call) of members [0, nmem) plus
+// the merge of their straddling words.  grid = bprefix[nmem], mwords =
+// sprefix[nmem].
 hipError_t round_launch(const RoundShape &rs, uint32_t grid, uint64_t mwords, hipStream_t st,
                         const SweepArgs *members, const uint32_t *bprefix,
-                        const unsigned long long *sprefix, uint32_t nmem, uint32_t k)
+                        const unsigned long long *sprefix, uint32_t nmem, uint32_t k,
+                        uint32_t res)
 {
     if (rs.tpb == 256) {
-        if (rs.K == 1) round_launch_k<256, 1>(rs, grid, st, members, bprefix, nmem, k);
-        else if (rs.K == 2) round_launch_k<256, 2>(rs, grid, st, members, bprefix, nmem, k);
-        else round_launch_k<256, 4>(rs, grid, st, members, bprefix, nmem, k);
+        if (rs.K == 1) round_launch_k<256, 1>(rs, grid, st, members, bprefix, nmem, k, res);
+        else if (rs.K == 2) round_launch_k<256, 2>(rs, grid, st, members, bprefix, nmem, k, res);
+        else round_launch_k<256, 4>(rs, grid, st, members, bprefix, nmem, k, res);
     } else {
-        if (rs.K == 1) round_launch_k<64, 1>(rs, grid, st, members, bprefix, nmem, k);
-        else round_launch_k<64, 2>(rs, grid, st, members, bprefix, nmem, k);
+        if (rs.K == 1) round_launch_k<64, 1>(rs, grid, st, members, bprefix, nmem, k, res);
+        else round_launch_k<64, 2>(rs, grid, st, members, bprefix, nmem, k, res);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const uint32_t mgrid = (uint32_t)((mwords + 255) / 256 < 8192 ? (mwords + 255) / 256 : 8192);
     hipLaunchKernelGGL(kpz_batch_merge_kernel, dim3(mgrid), dim3(256), 0, st, members, sprefix,
-                       nmem, k);
+                       nmem, k, res);
     return hipGetLastError();
 }
 
@@ -1309,11 +1333,13 @@ kpz_status batch_sweep_on(kpz_batch *b, int32_t n_mcs, hipStream_t st)
     if (n_mcs <= 0) return KPZ_OK;
     const uint32_t *bp = (const uint32_t *)(b->ws + b->lay.off_bprefix);
     const unsigned long long *sp = (const unsigned long long *)(b->ws + b->lay.off_sprefix);
-    for (int32_t k = 0; k < n_mcs; ++k) {
-        const hipError_t e = round_launch(b->rs, b->per_round, b->merge_words, st, batch_members(b),
-                                          bp, sp, (uint32_t)b->n, (uint32_t)k);
-        if (e != hipSuccess) return batch_fail(b, e, "kpz_batch_sweep launch");
-    }
+    for (int32_t k = 0; k < n_mcs; ++k)
+        for (uint32_t r = 0; r < b->lay.moves; ++r) {
+            const hipError_t e = round_launch(b->rs, b->per_round, b->merge_words, st,
+                                              batch_members(b), bp, sp, (uint32_t)b->n,
+                                              (uint32_t)k, r);
+            if (e != hipSuccess) return batch_fail(b, e, "kpz_batch_sweep launch");
+        }
     hipLaunchKernelGGL(kpz_batch_advance_kernel, dim3((b->n + 255) / 256), dim3(256), 0, st,
                        batch_members(b), (uint32_t)b->n, (uint32_t)n_mcs);
     const hipError_t e = hipGetLastError();
@@ -1487,6 +1513,8 @@ SweepArgs pool_args(const kpz_pool *p, const PoolJob &j)
     a.seed_lo = (uint32_t)j.prm.seed;
     a.seed_hi = (uint32_t)(j.prm.seed >> 32);
     a.t = (uint32_t)j.t;
+    a.res = 0;
+    a.nsteps = 16;
     a.slot_mask = BATCH_SLOTS - 1;
     a.P = threshold(j.prm.p);
     a.Q = threshold(j.prm.q);
@@ -1604,6 +1632,8 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     a.Q = s->Q;
     a.slot_mask = NSLOTS - 1;
     a.acc = !(s->P == (1ull << 32) && s->Q == 0);
+    const uint32_t moves = moves_of(&s->prm);
+    a.nsteps = 16u / moves;
     // threads per block: four waves when the block has at least 256 quads
     // (fewer registers per lane, more waves to hide LDS and HBM latency);
     // KPZ_THREADS_PER_BLOCK=64 selects one wave per block.  The launch shape
@@ -1618,12 +1648,15 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     const uint32_t mgrid = (uint32_t)((nstraddle + 255) / 256 < 8192 ? (nstraddle + 255) / 256 : 8192);
     for (int32_t m = 0; m < n_mcs; ++m) {
         a.t = (uint32_t)(s->t + m);
-        hipError_t e = a.acc ? launch_sweep<true>(a, tpb, K, nblocks, shmem, s->stream)
-                             : launch_sweep<false>(a, tpb, K, nblocks, shmem, s->stream);
-        if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep launch");
-        hipLaunchKernelGGL(kpz_merge_kernel, dim3(mgrid), dim3(256), 0, s->stream, a);
-        e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep merge launch");
+        for (uint32_t r = 0; r < moves; ++r) {
+            a.res = r;
+            hipError_t e = a.acc ? launch_sweep<true>(a, tpb, K, nblocks, shmem, s->stream)
+                                 : launch_sweep<false>(a, tpb, K, nblocks, shmem, s->stream);
+            if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep launch");
+            hipLaunchKernelGGL(kpz_merge_kernel, dim3(mgrid), dim3(256), 0, s->stream, a);
+            e = hipGetLastError();
+            if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep merge launch");
+        }
     }
     s->t += n_mcs;
     return KPZ_OK;
@@ -1798,6 +1831,8 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
         a.seed_lo = (uint32_t)p.seed;
         a.seed_hi = (uint32_t)(p.seed >> 32);
         a.t = 0;
+        a.res = 0;
+        a.nsteps = 16u / lay.moves;
         a.slot_mask = BATCH_SLOTS - 1;
         a.P = threshold(p.p);
         a.Q = threshold(p.q);
@@ -2024,6 +2059,7 @@ kpz_status kpz_pool_submit(kpz_pool *p, const kpz_params *job, int64_t n_mcs, in
     if ((job->block_x && job->block_x != (int32_t)p->Bx) ||
         (job->block_y && job->block_y != (int32_t)p->By))
         return KPZ_EINVAL;
+    if (moves_of(job) != 1) return KPZ_EINVAL;
     uint32_t rbx, rby;
     kpz_status st = resolve(&q, &rbx, &rby);
     if (st != KPZ_OK) return st;
@@ -2114,7 +2150,7 @@ kpz_status kpz_pool_step(kpz_pool *p, int32_t quantum, int32_t *n_active)
     for (uint32_t k = 0; k < rounds[0]; ++k) {
         while (m > 0 && rounds[m - 1] <= k) --m;
         e = round_launch(p->rs, bprefix[m], sprefix[m], p->stream, d_members, d_bprefix, d_sprefix,
-                         (uint32_t)m, k);
+                         (uint32_t)m, k, 0u);
         if (e != hipSuccess) return pool_fail(p, e, "kpz_pool_step launch");
     }
     for (size_t k = 0; k < n; ++k) p->jobs[order[k]].t += rounds[k];

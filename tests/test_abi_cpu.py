@@ -51,6 +51,7 @@ def test_workspace_bytes_valid(kpz, L, block):
     dict(L=64, block=(48, 16)), dict(L=64, block=(8, 16)), dict(L=64, block=(128, 64)),
     dict(L=2048, block=(2048, 16)), dict(L=1024, block=(512, 256)),
     dict(L=64, tile=(8, 8)), dict(L=96, block=(64, 32)),
+    dict(L=64, moves=3), dict(L=64, moves=32), dict(L=64, moves=-1),
 ])
 def test_invalid_params_rejected(kpz, kw):
     p = kpz.make_params(**kw)
@@ -79,3 +80,15 @@ def test_init_validates_before_device_work(kpz):
     assert L.kpz_sweep(None, 1) == kpz.KPZ_EINVAL
     assert L.kpz_roughness(None, None, None, None) == kpz.KPZ_EINVAL
     L.kpz_destroy(None)
+
+
+@pytest.mark.parametrize("moves", [0, 1, 2, 4, 8, 16])
+def test_origin_moves_accepted(kpz, moves):
+    assert kpz.workspace_bytes(kpz.make_params(256, 1.0, 0.0, 1, (64, 64), moves=moves)) > 0
+
+
+def test_batch_members_must_share_moves(kpz):
+    ms = [kpz.make_params(256, 1.0, 0.0, 1, (64, 64), moves=1),
+          kpz.make_params(256, 1.0, 0.0, 2, (64, 64), moves=2)]
+    with pytest.raises(kpz.KPZError):
+        kpz.batch_sizes(ms)

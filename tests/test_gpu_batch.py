@@ -71,3 +71,39 @@ def test_batch_mixed_sizes_sweep_single_block_members(gpu):
         sim = gpu.Sim(m.L, m.p, m.q, m.seed, (256, 256))
         sim.sweep(2)
         assert np.array_equal(ens.member_words(r), sim.words_host()), r
+
+
+def test_batch_run_every_mcs_long_schedule(gpu):
+    """A one-member graph run with a sample after each of 300 MCS (more than
+    one sample block) equals the single-lattice run sampled MCS by MCS, and
+    a second run continues from where the first stopped."""
+    p = gpu.make_params(64, 1.0, 0.25, 5, (64, 64))
+    ens = gpu.Ensemble([p])
+    S1a, S2a, W2a = ens.run(list(range(1, 301)))
+    S1b, S2b, W2b = ens.run([305, 310])
+    sim = gpu.Sim(64, 1.0, 0.25, 5, (64, 64))
+    for k in range(300):
+        sim.sweep(1)
+        m = sim.roughness()
+        assert (int(S1a[k, 0]), int(S2a[k, 0]), float(W2a[k, 0])) == (m.S1, m.S2, m.W2), k
+    for k, T in enumerate([305, 310]):
+        sim.sweep(T - sim.state()[0])
+        m = sim.roughness()
+        assert (int(S1b[k, 0]), int(S2b[k, 0]), float(W2b[k, 0])) == (m.S1, m.S2, m.W2), T
+    assert np.array_equal(ens.member_words(0), sim.words_host())
+
+
+def test_batch_members_with_origin_moves_equal_single_runs(gpu):
+    """A batch whose members move the origin four times per MCS equals the
+    single-lattice runs with the same setting."""
+    members = [gpu.make_params(L, 1.0, q, 40 + r, (64, 64), moves=4)
+               for r, (L, q) in enumerate([(128, 0.0), (256, 0.25), (64, 0.5)])]
+    ens = gpu.Ensemble(members)
+    ens.sweep(3)
+    S1, S2, W2 = ens.roughness()
+    for r, m in enumerate(members):
+        sim = gpu.Sim(m.L, m.p, m.q, m.seed, (64, 64), moves=4)
+        sim.sweep(3)
+        assert np.array_equal(ens.member_words(r), sim.words_host()), r
+        mm = sim.roughness()
+        assert (int(S1[r]), int(S2[r]), float(W2[r])) == (mm.S1, mm.S2, mm.W2), r

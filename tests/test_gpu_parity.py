@@ -101,6 +101,29 @@ def test_sweep_matches_oracle(gpu, oracle_lib, L, block, p, q, seed, n):
         assert sim.state() == (t + 1, int(st.net[0]))
 
 
+MOVES_CASES = [
+    # (L, block, p, q, seed, n_mcs, moves): origin moved `moves` times per MCS
+    (64, (32, 16), 1.0, 0.0, 21, 4, 2),
+    (128, (64, 64), 1.0, 0.25, 22, 3, 4),
+    (256, (256, 64), 0.7, 0.3, 23, 2, 16),    # one step per residency
+    (64, (64, 16), 1.0, 0.0, 24, 3, 8),       # single block along x
+    (256, (128, 128), 1.0, 0.0, 25, 2, 16),
+]
+
+
+@pytest.mark.parametrize("L,block,p,q,seed,n,moves", MOVES_CASES)
+def test_sweep_moves_matches_oracle(gpu, oracle_lib, L, block, p, q, seed, n, moves):
+    _log(f"sweep moves={moves} L={L} block={block} p={p} q={q} seed={seed} n={n}")
+    sim = gpu.Sim(L, p, q, seed, block, moves=moves)
+    st = oracle_lib.SlopeState(L)
+    for t in range(n):
+        sim.sweep(1)
+        st.run_dd(1, p, q, seed, block=block, tile=(4, 4), moves=moves)
+        assert np.array_equal(sim.words_host(), oracle_lib.pack(st.sx, st.sy)), t
+        assert_moments(oracle_lib, st, sim.roughness(), L)
+        assert sim.state() == (t + 1, int(st.net[0]))
+
+
 def test_l64_full_run_every_mcs(gpu, oracle_lib):
     """The L = 64, p = 1, q = 0, seed 1 workload: 1000 MCS, moments after
     every MCS, words compared every 50 MCS."""

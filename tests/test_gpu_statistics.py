@@ -90,6 +90,32 @@ def test_gpu_dd_agrees_with_rs(oracle_lib, rs_reference, block):
     assert ok, (rel, _beta(dd), _beta(rs_reference))
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("moves", [4, 16])
+def test_gpu_dd_origin_moves_agree_with_rs(oracle_lib, rs_reference, moves):
+    """Block residency below one MCS (the origin moved 4 or 16 times per
+    MCS) keeps the agreement with random-sequential dynamics; the printed
+    amplitude difference is the fidelity figure for that residency."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1204_5072_amd as kpz
+    L, block = 256, (64, 64)
+    dd = np.zeros((64, len(TIMES)))
+    sims = [kpz.Sim(L, 1.0, 0.0, 95_000 + s, block, moves=moves) for s in range(64)]
+    t = 0
+    for k, T in enumerate(TIMES):
+        for sim in sims:
+            sim.sweep(T - t)
+        for i, sim in enumerate(sims):
+            dd[i, k] = sim.roughness().W2
+        t = T
+    ok, rel = _agrees(dd, rs_reference)
+    print("relative W^2 difference, moves", moves, np.round(rel, 3), "beta", _beta(dd),
+          _beta(rs_reference), flush=True)
+    assert ok, (rel, _beta(dd), _beta(rs_reference))
+
+
 def test_checkerboard_like_cells_fail(oracle_lib):
     """Negative control on the CPU: 1x1 cells (2x2 tiles) bias W^2(t)."""
     L = 64

@@ -341,3 +341,97 @@ def test_block_runner_equals_full_run(oracle_lib, p, q):
             assert np.array_equal(bsx, st.sx[np.ix_(rows, cols)])
             assert np.array_equal(bsy, st.sy[np.ix_(rows, cols)])
     assert total == int(st.net[0] - before.net[0])
+
+
+# ------------------------------------- origin moves within an MCS (tau < 1)
+
+@pytest.mark.parametrize("block,tile,moves", [((4, 2), (2, 2), 4), ((4, 2), (2, 2), 2),
+                                              ((2, 2), (2, 2), 4)])
+def test_dd_moves_matches_exact_law(oracle_lib, chain4, block, tile, moves):
+    """With the origin moved `moves` times per MCS, the oracle's law of W^2
+    after two MCS equals the exact law of that schedule (independent uniform
+    origin per residency, S/moves single-hit steps each)."""
+    p, q, t = 1.0, 0.0, 2
+    pi_t = chain4.distribution(chain4.dd_mcs(p, q, block, tile, moves), t)
+    n = 3000
+    counts = np.zeros(chain4.n)
+    for i in range(n):
+        st = oracle_lib.SlopeState(4).run_dd(t, p, q, 15000 + i, block=block, tile=tile,
+                                             moves=moves)
+        counts[chain4.index[exact_small.state_from_slopes(st.sx, st.sy)]] += 1
+    keys = np.round(chain4.w2, 12)
+    uniq = np.unique(keys)
+    obs = np.array([counts[keys == k].sum() for k in uniq])
+    exp = np.array([pi_t[keys == k].sum() for k in uniq]) * n
+    big = exp >= 5
+    o2 = np.append(obs[big], obs[~big].sum())
+    e2 = np.append(exp[big], exp[~big].sum())
+    keep = e2 > 0
+    chi2 = (((o2[keep] - e2[keep]) ** 2) / e2[keep]).sum()
+    dof = keep.sum() - 1
+    assert chi2 < dof + 4.5 * np.sqrt(2 * dof) + 10, (chi2, dof)
+
+
+def test_exact_moves_changes_the_law(chain4):
+    """With dead borders the residency is part of the dynamics: one origin
+    per MCS and several give clearly different laws at t = 2 (so the test
+    above tells them apart).  A single periodic block with one tile is RS
+    whatever the residency."""
+    for block, moves in (((2, 2), 4), ((4, 2), 2)):
+        a = chain4.distribution(chain4.dd_mcs(1.0, 0.0, block, (2, 2), 1), 2)
+        b = chain4.distribution(chain4.dd_mcs(1.0, 0.0, block, (2, 2), moves), 2)
+        assert np.abs(a - b).sum() > 0.3, block
+    a = chain4.dd_mcs(1.0, 0.0, (4, 4), (4, 4), 4)
+    assert np.allclose(a, chain4.rs_mcs(1.0, 0.0))
+
+
+@pytest.mark.parametrize("moves", [2, 16])
+def test_dd_moves_attempts_never_neighbours(oracle_lib, moves):
+    oracle_lib.SlopeState(32).run_dd(3, 0.5, 0.5, 23, block=(16, 8), check=True, moves=moves)
+
+
+def test_dd_moves_conjugation_and_invariants(oracle_lib):
+    L = 32
+    a = oracle_lib.SlopeState(L).run_rs(2, 0.9, 0.1, 99)
+    b = _negated(a)
+    a.run_dd(5, 1.0, 0.25, 8, block=(16, 8), moves=4)
+    b.run_dd(5, 0.25, 1.0, 8, block=(16, 8), moves=4)
+    assert np.array_equal(b.sx, -a.sx) and np.array_equal(b.sy, -a.sy)
+    assert b.h00[0] == -a.h00[0] and b.net[0] == -a.net[0]
+    oracle_lib.check_invariants(a.sx, a.sy)
+
+
+def test_dd_moves_one_is_the_default_schedule(oracle_lib):
+    a = oracle_lib.SlopeState(32).run_dd(4, 1.0, 0.3, 6, block=(16, 16))
+    b = oracle_lib.SlopeState(32).run_dd(4, 1.0, 0.3, 6, block=(16, 16), moves=1)
+    c = oracle_lib.SlopeState(32).run_dd(4, 1.0, 0.3, 6, block=(16, 16), moves=2)
+    assert np.array_equal(a.sx, b.sx) and np.array_equal(a.sy, b.sy)
+    assert not (np.array_equal(a.sx, c.sx) and np.array_equal(a.sy, c.sy))
+
+
+@pytest.mark.parametrize("moves", [2, 8])
+def test_block_runner_residencies_equal_full_run(oracle_lib, moves):
+    """Residency by residency, blocks on their own copies (each residency's
+    blocks from its own origin) reproduce the whole-lattice MCS."""
+    L, B, seed, p, q = 64, (32, 16), 3, 1.0, 0.4
+    st = oracle_lib.SlopeState(L).run_dd(1, p, q, seed, block=B, moves=moves)
+    t = st.t
+    cur = st.copy()
+    net_before = int(cur.net[0])
+    st.run_dd(1, p, q, seed, block=B, moves=moves)
+    total = 0
+    for res in range(moves):
+        origin = oracle_lib.dd_origin(seed, t, B, res)
+        nxt = cur.copy()
+        for by in range(L // B[1]):
+            for bx in range(L // B[0]):
+                rows, cols = oracle_lib.block_region(B, origin, bx, by, L)
+                bsx = np.ascontiguousarray(cur.sx[np.ix_(rows, cols)])
+                bsy = np.ascontiguousarray(cur.sy[np.ix_(rows, cols)])
+                total += oracle_lib.dd_block_mcs(L, p, q, seed, B, t, bx, by, bsx, bsy,
+                                                 moves=moves, res=res)
+                nxt.sx[np.ix_(rows, cols)] = bsx
+                nxt.sy[np.ix_(rows, cols)] = bsy
+        cur = nxt
+    assert np.array_equal(cur.sx, st.sx) and np.array_equal(cur.sy, st.sy)
+    assert total == int(st.net[0]) - net_before
