@@ -77,8 +77,15 @@ def lib():
         L.or_dd_origin.argtypes = [c.c_uint64, c.c_uint32, c.c_int, c.c_int, c.c_int,
                                    c.POINTER(c.c_int), c.POINTER(c.c_int)]
         L.or_dd_origin.restype = None
+        L.or_dd1d_run.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64, c.c_int,
+                                  c.c_uint32, c.c_int, i8p, i64p, i64p, c.c_int]
+        L.or_dd1d_block_mcs.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64, c.c_int,
+                                        c.c_uint32, c.c_int, i8p, i64p]
+        L.or_dd1d_origin.argtypes = [c.c_uint64, c.c_uint32, c.c_int]
+        L.or_flat1d.argtypes = [c.c_int, i8p]
         for f in ("or_flat", "or_rs_heights_run", "or_rs_slopes_run", "or_dd_run", "or_rs1d_run",
-                  "or_dd_block_mcs"):
+                  "or_dd_block_mcs", "or_dd1d_run", "or_dd1d_block_mcs", "or_dd1d_origin",
+                  "or_flat1d"):
             getattr(L, f).restype = c.c_int
         _lib = L
     return _lib
@@ -104,6 +111,7 @@ def draw(seed: int, tag: int, t: int, idx: int, sub: int) -> np.ndarray:
 
 
 TAG_ORIGIN, TAG_SET, TAG_SITE, TAG_ACC1, TAG_ACC2, TAG_RS, TAG_RS1D = 1, 2, 3, 4, 5, 6, 7
+TAG_ORIGIN1D, TAG_SET1D, TAG_SITE1D, TAG_ACC1D, TAG_ACC1D2 = 8, 9, 10, 11, 12
 
 
 # ------------------------------------------------------------------ state
@@ -197,6 +205,72 @@ def block_region(block, origin, bx: int, by: int, L: int):
 def rs1d_run(s: np.ndarray, h0: np.ndarray, net: np.ndarray, t0: int, n_mcs: int,
              p: float, q: float, seed: int) -> None:
     _check(lib().or_rs1d_run(s.shape[0], p, q, seed, t0, n_mcs, s, h0, net), "rs1d_run")
+
+
+class RingState:
+    """The 1+1-d rooftop ring: bonds s[i] = h(i+1) - h(i) in {-1, +1}
+    (int8, length L), anchor h0 = h(0), net flips, next MCS t."""
+
+    def __init__(self, L: int):
+        self.L = L
+        self.s = np.zeros(L, np.int8)
+        self.h0 = np.zeros(1, np.int64)
+        self.net = np.zeros(1, np.int64)
+        self.t = 0
+        _check(lib().or_flat1d(L, self.s), "flat1d")
+
+    def copy(self) -> "RingState":
+        o = RingState.__new__(RingState)
+        o.L, o.t = self.L, self.t
+        o.s, o.h0, o.net = self.s.copy(), self.h0.copy(), self.net.copy()
+        return o
+
+    def run_rs(self, n_mcs: int, p: float, q: float, seed: int) -> "RingState":
+        rs1d_run(self.s, self.h0, self.net, self.t, n_mcs, p, q, seed)
+        self.t += n_mcs
+        return self
+
+    def run_dd(self, n_mcs: int, p: float, q: float, seed: int, block: int,
+               check: bool = False) -> "RingState":
+        _check(lib().or_dd1d_run(self.L, p, q, seed, block, self.t, n_mcs, self.s, self.h0,
+                                 self.net, int(check)), "dd1d_run")
+        self.t += n_mcs
+        return self
+
+    def heights(self) -> np.ndarray:
+        h = np.zeros(self.L, np.int64)
+        h[1:] = np.cumsum(self.s[:-1].astype(np.int64))
+        return h + int(self.h0[0])
+
+    def moments(self):
+        """Exact (S1, S2) = (sum h, sum h^2) as Python ints."""
+        h = self.heights()
+        return int(h.sum()), int(sum(int(v) * int(v) for v in h))
+
+
+def pack1d(s: np.ndarray) -> np.ndarray:
+    """Bond i -> bit i mod 32 of word i / 32 (1 = +1)."""
+    bits = (np.asarray(s) > 0).astype(np.uint64).reshape(-1, 32)
+    return (bits << np.arange(32, dtype=np.uint64)).sum(axis=1).astype(np.uint32)
+
+
+def unpack1d(words: np.ndarray) -> np.ndarray:
+    w = np.asarray(words, np.uint32).astype(np.uint64)
+    bits = (w[:, None] >> np.arange(32, dtype=np.uint64)) & 1
+    return (2 * bits.reshape(-1).astype(np.int8) - 1).astype(np.int8)
+
+
+def dd1d_origin(seed: int, t: int, block: int) -> int:
+    return int(lib().or_dd1d_origin(seed, t, block))
+
+
+def dd1d_block_mcs(L: int, p: float, q: float, seed: int, block: int, t: int, b: int,
+                   bs: np.ndarray) -> int:
+    """One MCS of block b of the 1+1-d schedule on its own bonds ``bs``
+    (length block, modified in place); returns the net number of flips."""
+    net = np.zeros(1, np.int64)
+    _check(lib().or_dd1d_block_mcs(L, p, q, seed, block, t, b, bs, net), "dd1d_block_mcs")
+    return int(net[0])
 
 
 # ------------------------------------------------------------ observables

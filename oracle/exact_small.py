@@ -268,3 +268,74 @@ class SmallChain:
         nmin = (self.kind == 1).sum(axis=1)
         nmax = (self.kind == -1).sum(axis=1)
         return float(pi @ (2.0 * (p * nmin - q * nmax))) / self.N
+
+
+class RingChain:
+    """Exact law of the 1+1-d rooftop ring of L bonds with zero tilt (the
+    reduction of the octahedron model to one dimension, Sec. 2.1): states
+    are the bond sequences s in {-1, +1}^L with sum 0; site i touches bonds
+    i-1 and i and is a minimum iff (s[i-1], s[i]) = (-1, +1)."""
+
+    def __init__(self, L: int = 8):
+        import itertools
+        self.L = L
+        self.states = [c for c in itertools.product((-1, 1), repeat=L) if sum(c) == 0]
+        self.index = {c: i for i, c in enumerate(self.states)}
+        self.n = len(self.states)
+        self.w2 = np.zeros(self.n)
+        for i, c in enumerate(self.states):
+            h = np.concatenate([[0], np.cumsum(c[:-1])]).astype(np.int64)
+            self.w2[i] = float(Fraction(int(L * (h * h).sum() - h.sum() ** 2), L * L))
+        flat = tuple(1 if i % 2 == 0 else -1 for i in range(L))
+        self.flat = self.index[flat]
+
+    def site_operator(self, i: int, p: float, q: float) -> np.ndarray:
+        L = self.L
+        A = np.zeros((self.n, self.n))
+        for a, c in enumerate(self.states):
+            l, r = c[(i - 1) % L], c[i]
+            pr = p if (l, r) == (-1, 1) else (q if (l, r) == (1, -1) else 0.0)
+            A[a, a] += 1.0 - pr
+            if pr:
+                d = list(c)
+                d[(i - 1) % L], d[i] = -l, -r
+                A[a, self.index[tuple(d)]] += pr
+        return A
+
+    def rs_mcs(self, p: float, q: float) -> np.ndarray:
+        T1 = sum(self.site_operator(i, p, q) for i in range(self.L)) / self.L
+        return np.linalg.matrix_power(T1, self.L)
+
+    def dd_mcs(self, p: float, q: float, block: int) -> np.ndarray:
+        """One MCS of the decomposed ring: uniform origin, then 4 single-hit
+        steps; in each step every block draws a uniform set (cell of 2
+        sites in each 4-site tile) and every tile a uniform site of its
+        cell; site 0 of each block is dead when there are several blocks."""
+        L, B = self.L, block
+        nb = L // B
+        ops = {i: self.site_operator(i, p, q) for i in range(L)}
+        I = np.eye(self.n)
+        total = np.zeros((self.n, self.n))
+        for o in range(B):
+            step = I.copy()
+            for b in range(nb):
+                bstep = np.zeros((self.n, self.n))
+                for st in range(2):
+                    M = I.copy()
+                    for m in range(B // 4):
+                        cell = np.zeros((self.n, self.n))
+                        for r in range(2):
+                            lx = 4 * m + 2 * st + r
+                            cell += I if (nb > 1 and lx == 0) else ops[(o + b * B + lx) % L]
+                        M = M @ (cell / 2.0)
+                    bstep += M / 2.0
+                step = step @ bstep
+            total += np.linalg.matrix_power(step, 4)
+        return total / B
+
+    def distribution(self, T: np.ndarray, t: int) -> np.ndarray:
+        pi = np.zeros(self.n)
+        pi[self.flat] = 1.0
+        for _ in range(t):
+            pi = pi @ T
+        return pi

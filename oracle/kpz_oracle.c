@@ -27,7 +27,10 @@
  *                      dead-border blocks with a random origin every MCS
  *                      (device layer), single-hit double tiling inside each
  *                      block (work-group layer)
- *   or_rs1d_run        the 1+1-d rooftop (ASEP) reduction (Sec. 2.1)
+ *   or_rs1d_run        the 1+1-d rooftop (ASEP) reduction (Sec. 2.1),
+ *                      random-sequential
+ *   or_dd1d_run        the same ring under the decomposition of Sec. 3 / 3.1
+ *                      reduced to one dimension
  * One Monte Carlo step (MCS) is N = L*L update attempts (Sec. 2.2).
  *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
@@ -48,6 +51,11 @@
 #define OR_TAG_ACC2   5u
 #define OR_TAG_RS     6u
 #define OR_TAG_RS1D   7u
+#define OR_TAG_ORIGIN1D 8u
+#define OR_TAG_SET1D    9u
+#define OR_TAG_SITE1D  10u
+#define OR_TAG_ACC1D   11u
+#define OR_TAG_ACC1D2  12u
 
 #define OR_OK       0
 #define OR_EINVAL  -1
@@ -458,4 +466,155 @@ void or_dd_origin(uint64_t seed, uint32_t t, int res, int Bx, int By, int *ox, i
     or_draw(seed, OR_TAG_ORIGIN, t, (uint64_t)res, 0, w);
     *ox = (int)(((uint64_t)w[0] * (uint64_t)Bx) >> 32);
     *oy = (int)(((uint64_t)w[1] * (uint64_t)By) >> 32);
+}
+
+/* ------------------------------------ 1+1-d decomposed schedule */
+
+/*
+ * The rooftop ring (bonds s[i] = h(i+1) - h(i), site i touches bonds i-1
+ * and i) under the two-layer decomposition of Sec. 3 / 3.1 reduced to one
+ * dimension:
+ *
+ * Device layer.  Origin o = floor(w0 * B / 2^32) of draw (ORIGIN1D, t, 0, 0),
+ * once per MCS; block b covers sites (o + b B + lx) mod L, 0 <= lx < B.  With
+ * more than one block, site lx = 0 is the dead border: every update of a
+ * block then reads and writes only the block's own bonds.
+ *
+ * Work-group layer.  Tiles of 4 sites, bisected into two cells of 2 sites
+ * (set 0: sites 0, 1; set 1: sites 2, 3 of the tile); S = 4 single-hit
+ * steps per MCS.  In step k block b uses set bit k of w0 of draw
+ * (SET1D, t, b, 0) and tile m attempts site 4 m + 2 set + r.  Attempts of
+ * one step are at least three sites apart.
+ *
+ * Draws.  Tile m of block b is tile mm = m mod 8 of block word wl = m / 8
+ * (a packed word holds 32 sites = 8 tiles); with nt = B/4 tiles per block,
+ * n4 = ceil(nt/32) and n2 = ceil(nt/16):
+ *   r = bit 8k + mm of word (wl mod 4) of draw (SITE1D, t, b n4 + wl/4, 0);
+ *   u = A << 24 | (C & 0xFFFFFF) with A = byte (mm mod 4) of word
+ *       2 (wl mod 2) + mm/4 of draw (ACC1D, t, b n2 + wl/2, k) and
+ *       C = w0 of draw (ACC1D2, t, b nt + m, k) (needed only on a tie of A).
+ */
+static int dd1d_validate(int L, int B)
+{
+    return L > 0 && !(L & 1) && B >= 4 && B % 4 == 0 && L % B == 0;
+}
+
+static int dd1d_attempt(int L, int8_t *s, int i, uint64_t P, uint64_t Q, uint64_t seed,
+                        uint32_t t, int k, uint64_t acc_idx, int acc_word, int acc_shift,
+                        uint64_t tie_idx, int64_t *h0, int64_t *net)
+{
+    const int im = (i + L - 1) % L;
+    int kind = SITE_NONE;
+    if (s[im] == -1 && s[i] == 1) kind = SITE_MIN;
+    if (s[im] == 1 && s[i] == -1) kind = SITE_MAX;
+    if (kind == SITE_NONE) return 0;
+    const uint64_t thr = kind == SITE_MIN ? P : Q;
+    if (thr == 0) return 0;
+    if (thr < ((uint64_t)1 << 32)) {
+        uint32_t wa[4], wc[4];
+        or_draw(seed, OR_TAG_ACC1D, t, acc_idx, (uint32_t)k, wa);
+        const uint32_t A = (wa[acc_word] >> acc_shift) & 0xFFu;
+        or_draw(seed, OR_TAG_ACC1D2, t, tie_idx, (uint32_t)k, wc);
+        const uint32_t u = (A << 24) | (wc[0] & 0xFFFFFFu);
+        if ((uint64_t)u >= thr) return 0;
+    }
+    s[im] = (int8_t)-s[im];
+    s[i] = (int8_t)-s[i];
+    const int dh = kind == SITE_MIN ? 2 : -2;
+    *net += dh / 2;
+    if (i == 0) *h0 += dh;
+    return 1;
+}
+
+int or_dd1d_run(int L, double p, double q, uint64_t seed, int B, uint32_t t0, int n_mcs,
+                int8_t *s, int64_t *h0, int64_t *net, int check)
+{
+    if (!dd1d_validate(L, B) || n_mcs < 0) return OR_EINVAL;
+    const int nb = L / B, nt = B / 4;
+    const uint64_t n4 = (uint64_t)(nt + 31) / 32, n2 = (uint64_t)(nt + 15) / 16;
+    const uint64_t P = threshold(p), Q = threshold(q);
+    int64_t *stamp = check ? (int64_t *)malloc(sizeof(int64_t) * (size_t)L) : NULL;
+    if (check && !stamp) return OR_ENOMEM;
+    if (check)
+        for (int i = 0; i < L; ++i) stamp[i] = -1;
+    int64_t step_id = 0;
+    int status = OR_OK;
+    uint32_t w[4];
+    for (int mc = 0; mc < n_mcs && status == OR_OK; ++mc) {
+        const uint32_t t = t0 + (uint32_t)mc;
+        or_draw(seed, OR_TAG_ORIGIN1D, t, 0, 0, w);
+        const int o = (int)(((uint64_t)w[0] * (uint64_t)B) >> 32);
+        for (int k = 0; k < 4 && status == OR_OK; ++k, ++step_id) {
+            for (int b = 0; b < nb; ++b) {
+                or_draw(seed, OR_TAG_SET1D, t, (uint64_t)b, 0, w);
+                const int set = (int)((w[0] >> k) & 1u);
+                for (int m = 0; m < nt; ++m) {
+                    const int wl = m / 8, mm = m % 8;
+                    or_draw(seed, OR_TAG_SITE1D, t, (uint64_t)b * n4 + (uint64_t)(wl / 4), 0, w);
+                    const int r = (int)((w[wl % 4] >> (8 * k + mm)) & 1u);
+                    const int lx = 4 * m + 2 * set + r;
+                    if (nb > 1 && lx == 0) continue;
+                    const int i = (int)(((int64_t)o + (int64_t)b * B + lx) % L);
+                    if (check) {
+                        const int nbr[3] = { i, (i + 1) % L, (i + L - 1) % L };
+                        for (int e = 0; e < 3; ++e)
+                            if (stamp[nbr[e]] == step_id) status = OR_ECHECK;
+                        stamp[i] = step_id;
+                    }
+                    dd1d_attempt(L, s, i, P, Q, seed, t, k, (uint64_t)b * n2 + (uint64_t)(wl / 2),
+                                 2 * (wl % 2) + mm / 4, 8 * (mm % 4),
+                                 (uint64_t)b * (uint64_t)nt + (uint64_t)m, h0, net);
+                }
+            }
+        }
+    }
+    free(stamp);
+    return status;
+}
+
+/* One MCS t of block b of the 1+1-d schedule on its own copy bs[lx] of the
+ * block's bonds (global bond (o + b B + lx) mod L); needs two or more
+ * blocks, so that the dead border keeps every update inside the block. */
+int or_dd1d_block_mcs(int L, double p, double q, uint64_t seed, int B, uint32_t t, int b,
+                      int8_t *bs, int64_t *net)
+{
+    if (!dd1d_validate(L, B)) return OR_EINVAL;
+    const int nb = L / B, nt = B / 4;
+    if (nb < 2 || b < 0 || b >= nb) return OR_EINVAL;
+    const uint64_t n4 = (uint64_t)(nt + 31) / 32, n2 = (uint64_t)(nt + 15) / 16;
+    const uint64_t P = threshold(p), Q = threshold(q);
+    uint32_t w[4];
+    int64_t h0_unused = 0;
+    for (int k = 0; k < 4; ++k) {
+        or_draw(seed, OR_TAG_SET1D, t, (uint64_t)b, 0, w);
+        const int set = (int)((w[0] >> k) & 1u);
+        for (int m = 0; m < nt; ++m) {
+            const int wl = m / 8, mm = m % 8;
+            or_draw(seed, OR_TAG_SITE1D, t, (uint64_t)b * n4 + (uint64_t)(wl / 4), 0, w);
+            const int r = (int)((w[wl % 4] >> (8 * k + mm)) & 1u);
+            const int lx = 4 * m + 2 * set + r;
+            if (lx == 0) continue;
+            /* block-local ring of B bonds; lx >= 1 never wraps */
+            dd1d_attempt(B, bs, lx, P, Q, seed, t, k, (uint64_t)b * n2 + (uint64_t)(wl / 2),
+                         2 * (wl % 2) + mm / 4, 8 * (mm % 4),
+                         (uint64_t)b * (uint64_t)nt + (uint64_t)m, &h0_unused, net);
+        }
+    }
+    return OR_OK;
+}
+
+/* Origin of MCS t of the 1+1-d schedule. */
+int or_dd1d_origin(uint64_t seed, uint32_t t, int B)
+{
+    uint32_t w[4];
+    or_draw(seed, OR_TAG_ORIGIN1D, t, 0, 0, w);
+    return (int)(((uint64_t)w[0] * (uint64_t)B) >> 32);
+}
+
+/* Flat rooftop: s[i] = +1 for even i, -1 for odd i (h(i) = i mod 2). */
+int or_flat1d(int L, int8_t *s)
+{
+    if (L <= 0 || (L & 1)) return OR_EINVAL;
+    for (int i = 0; i < L; ++i) s[i] = (i & 1) ? -1 : 1;
+    return OR_OK;
 }
