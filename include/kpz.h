@@ -152,7 +152,9 @@ void kpz_destroy(kpz_sim *sim);
 /* Static text for a status code. */
 const char *kpz_status_str(kpz_status status);
 
-/* Text of the last error recorded in the handle ("" if none). */
+/* Text of the last error recorded in the handle ("" if none).  With
+ * sim = NULL: the text of the last failed kpz_init, kpz_batch_init or
+ * kpz_pool_init on the calling thread. */
 const char *kpz_last_error(const kpz_sim *sim);
 
 /* ------------------------------------------------------------------------
@@ -213,7 +215,8 @@ kpz_status kpz_batch_get_t(const kpz_batch *batch, int64_t *t);
 /* Frees the batch handle (not the caller's buffers).  NULL is ignored. */
 void kpz_batch_destroy(kpz_batch *batch);
 
-/* Text of the last error recorded in the batch handle ("" if none). */
+/* Text of the last error recorded in the batch handle ("" if none); NULL:
+ * as kpz_last_error(NULL). */
 const char *kpz_batch_last_error(const kpz_batch *batch);
 
 /* ------------------------------------------------------------------------
@@ -268,6 +271,9 @@ kpz_status kpz_pool_poll(kpz_pool *pool, int32_t max_results, int64_t *job_ids, 
 kpz_status kpz_pool_stats(const kpz_pool *pool, int32_t *n_active, size_t *largest_free);
 
 void kpz_pool_destroy(kpz_pool *pool);
+
+/* Text of the last error recorded in the pool handle; NULL: as
+ * kpz_last_error(NULL). */
 const char *kpz_pool_last_error(const kpz_pool *pool);
 
 #ifdef __cplusplus

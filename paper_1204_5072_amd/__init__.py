@@ -164,7 +164,7 @@ class Sim:
                             ctypes.c_void_p(self.workspace.data_ptr()), ws,
                             ctypes.c_void_p(self.stream.cuda_stream))
         if st != KPZ_OK:
-            raise KPZError(st, "kpz_init")
+            raise KPZError(st, "kpz_init", lib().kpz_last_error(None).decode())
 
     def _check(self, st: int, what: str) -> None:
         if st != KPZ_OK:
@@ -255,7 +255,7 @@ class Ensemble:
                                   ctypes.c_void_p(self.workspace.data_ptr()), sb,
                                   ctypes.c_void_p(self.stream.cuda_stream))
         if st != KPZ_OK:
-            raise KPZError(st, "kpz_batch_init")
+            raise KPZError(st, "kpz_batch_init", lib().kpz_batch_last_error(None).decode())
 
     def _check(self, st, what):
         if st != KPZ_OK:

@@ -50,20 +50,29 @@ def _time(fn, reps: int) -> float:
 
 
 def tune_lattice(L: int, p: float = 1.0, q: float = 0.0, mcs: int = 2,
-                 candidates: Optional[Sequence[Tuple[int, int]]] = None) -> Dict:
+                 candidates: Optional[Sequence[Tuple[int, int]]] = None,
+                 verbose: bool = False) -> Dict:
     """Fastest block shape for one lattice of size L; returns
     {"block": (bx, by), "ms_per_mcs": {shape: ms}}."""
     shapes = valid_shapes(L, candidates or CANDIDATES)
     if not shapes:
         raise ValueError(f"no valid block shape for L={L}")
-    timings = {}
+    timings, failed = {}, {}
     for shape in shapes:
-        sim = Sim(L, p, q, 12345, shape)
+        try:
+            sim = Sim(L, p, q, 12345, shape)
+        except KPZError as e:          # recorded, not fatal: other shapes may run
+            failed[shape] = str(e)
+            continue
         timings[shape] = _time(lambda: sim.sweep(mcs), 1) / mcs
         sim.close()
         del sim
+        if verbose:
+            print(f"autotune: {shape[0]}x{shape[1]} {timings[shape]:.3f} ms/MCS", flush=True)
+    if not timings:
+        raise RuntimeError(f"no block shape ran for L={L}: {failed}")
     best = min(timings, key=timings.get)
-    return {"block": best, "ms_per_mcs": timings}
+    return {"block": best, "ms_per_mcs": timings, "failed": failed}
 
 
 def tune_ensemble(members, mcs: int = 2,
@@ -95,11 +104,13 @@ def main(argv=None) -> None:
     ap.add_argument("--q", type=float, default=0.0)
     ap.add_argument("--mcs", type=int, default=5)
     args = ap.parse_args(argv)
-    res = tune_lattice(args.L, args.p, args.q, args.mcs)
+    res = tune_lattice(args.L, args.p, args.q, args.mcs, verbose=True)
     rows = {f"{s[0]}x{s[1]}": {"ms_per_mcs": ms, "attempts_per_s": args.L * args.L / ms * 1e3}
             for s, ms in sorted(res["ms_per_mcs"].items(), key=lambda kv: kv[1])}
     print(json.dumps({"L": args.L, "p": args.p, "q": args.q, "best": list(res["block"]),
-                      "shapes": rows}), flush=True)
+                      "shapes": rows,
+                      "failed": {f"{s[0]}x{s[1]}": m for s, m in res["failed"].items()}}),
+          flush=True)
 
 
 if __name__ == "__main__":

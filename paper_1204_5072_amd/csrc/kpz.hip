@@ -1524,6 +1524,26 @@ SweepArgs pool_args(const kpz_pool *p, const PoolJob &j)
 
 }  // namespace
 
+namespace {
+
+// A non-sticky error left pending on this thread by another library's HIP
+// call (a query that returned "not ready", a failed allocation that was
+// retried) would be reported by the hipGetLastError after our own launches;
+// entry points that launch clear it first.  Errors of a faulted context are
+// sticky and still surface.
+void clear_pending_error() { (void)hipGetLastError(); }
+
+// Text of the last failed kpz_init / kpz_batch_init / kpz_pool_init on this
+// thread (those return no handle to hold it).
+thread_local char g_init_err[256];
+
+void set_init_error(hipError_t e, const char *what)
+{
+    snprintf(g_init_err, sizeof g_init_err, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *kpz_status_str(kpz_status s)
@@ -1539,7 +1559,7 @@ const char *kpz_status_str(kpz_status s)
     return "unknown status";
 }
 
-const char *kpz_last_error(const kpz_sim *s) { return s ? s->err : ""; }
+const char *kpz_last_error(const kpz_sim *s) { return s ? s->err : g_init_err; }
 
 kpz_status kpz_workspace_bytes(const kpz_params *p, size_t *bytes)
 {
@@ -1554,6 +1574,7 @@ kpz_status kpz_workspace_bytes(const kpz_params *p, size_t *bytes)
 kpz_status kpz_init(kpz_sim **out, const kpz_params *p, uint32_t *d_words, size_t words_bytes,
                     void *d_ws, size_t ws_bytes, void *stream)
 {
+    clear_pending_error();
     if (!out) return KPZ_EINVAL;
     *out = nullptr;
     uint32_t bx, by;
@@ -1594,7 +1615,7 @@ kpz_status kpz_init(kpz_sim **out, const kpz_params *p, uint32_t *d_words, size_
         e = hipGetLastError();
     }
     if (e != hipSuccess) {
-        hip_fail(s, e, "kpz_init launch");
+        set_init_error(e, "kpz_init launch");
         delete s;
         return KPZ_EHIP;
     }
@@ -1604,6 +1625,7 @@ kpz_status kpz_init(kpz_sim **out, const kpz_params *p, uint32_t *d_words, size_
 
 kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
 {
+    clear_pending_error();
     if (!s || n_mcs < 0) return KPZ_EINVAL;
     if (n_mcs == 0) return KPZ_OK;
     if (s->t + n_mcs > 0xFFFFFFFFll) return KPZ_ERANGE;
@@ -1664,6 +1686,7 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
 
 kpz_status kpz_roughness(kpz_sim *s, int64_t *S1o, int64_t *S2o, double *W2o)
 {
+    clear_pending_error();
     if (!s) return KPZ_EINVAL;
     const uint32_t L = (uint32_t)s->prm.L, W = L / 16;
     const uint32_t rgrid = (L + 3) / 4 < 4096 ? (L + 3) / 4 : 4096;
@@ -1705,6 +1728,7 @@ kpz_status kpz_roughness(kpz_sim *s, int64_t *S1o, int64_t *S2o, double *W2o)
 kpz_status kpz_height_moments(kpz_sim *s, int64_t sums[8], double *W2, double *skewness,
                               double *kurtosis)
 {
+    clear_pending_error();
     if (!s) return KPZ_EINVAL;
     const uint32_t L = (uint32_t)s->prm.L, W = L / 16;
     long long *rows6 = ws_rowA(s);   // 6 int64 per row
@@ -1783,6 +1807,7 @@ kpz_status kpz_batch_sizes(const kpz_params *members, int32_t n, size_t *words_b
 kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n, uint32_t *d_words,
                           size_t words_bytes, void *d_ws, size_t ws_bytes, void *stream)
 {
+    clear_pending_error();
     if (!out) return KPZ_EINVAL;
     *out = nullptr;
     BatchLayout lay;
@@ -1882,7 +1907,7 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
     }
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
-        batch_fail(b, e, "kpz_batch_init");
+        set_init_error(e, "kpz_batch_init");
         delete b;
         return KPZ_EHIP;
     }
@@ -1899,6 +1924,7 @@ kpz_status kpz_batch_word_offset(const kpz_batch *b, int32_t r, size_t *off)
 
 kpz_status kpz_batch_sweep(kpz_batch *b, int32_t n_mcs)
 {
+    clear_pending_error();
     if (!b || n_mcs < 0) return KPZ_EINVAL;
     if (b->t + n_mcs > 0xFFFFFFFFll) return KPZ_ERANGE;
     const kpz_status st = batch_sweep_on(b, n_mcs, b->stream);
@@ -1908,6 +1934,7 @@ kpz_status kpz_batch_sweep(kpz_batch *b, int32_t n_mcs)
 
 kpz_status kpz_batch_roughness(kpz_batch *b, int64_t *S1, int64_t *S2, double *W2)
 {
+    clear_pending_error();
     if (!b) return KPZ_EINVAL;
     kpz_status st = batch_moments_on(b, 0, b->stream);
     if (st != KPZ_OK) return st;
@@ -1929,6 +1956,7 @@ kpz_status kpz_batch_roughness(kpz_batch *b, int64_t *S1, int64_t *S2, double *W
 kpz_status kpz_batch_run(kpz_batch *b, const int32_t *times, int32_t n_times, int64_t *S1,
                          int64_t *S2, double *W2)
 {
+    clear_pending_error();
     if (!b || !times || n_times < 1 || n_times > KPZ_BATCH_MAX_SAMPLES) return KPZ_EINVAL;
     int64_t prev = b->t;
     for (int32_t k = 0; k < n_times; ++k) {
@@ -1996,7 +2024,7 @@ kpz_status kpz_batch_get_t(const kpz_batch *b, int64_t *t)
 
 void kpz_batch_destroy(kpz_batch *b) { delete b; }
 
-const char *kpz_batch_last_error(const kpz_batch *b) { return b ? b->err : ""; }
+const char *kpz_batch_last_error(const kpz_batch *b) { return b ? b->err : g_init_err; }
 
 
 kpz_status kpz_pool_job_bytes(const kpz_params *job, int32_t bx, int32_t by, size_t *bytes)
@@ -2052,6 +2080,7 @@ kpz_status kpz_pool_init(kpz_pool **out, void *d_arena, size_t arena_bytes, int3
 
 kpz_status kpz_pool_submit(kpz_pool *p, const kpz_params *job, int64_t n_mcs, int64_t *id)
 {
+    clear_pending_error();
     if (!p || !job || n_mcs < 1 || n_mcs > 0xFFFFFFFFll) return KPZ_EINVAL;
     kpz_params q = *job;
     q.block_x = (int32_t)p->Bx;
@@ -2107,6 +2136,7 @@ kpz_status kpz_pool_submit(kpz_pool *p, const kpz_params *job, int64_t n_mcs, in
 
 kpz_status kpz_pool_step(kpz_pool *p, int32_t quantum, int32_t *n_active)
 {
+    clear_pending_error();
     if (!p || quantum < 1 || quantum > p->max_quantum) return KPZ_EINVAL;
     const size_t n = p->jobs.size();
     if (n == 0) {
@@ -2244,6 +2274,6 @@ kpz_status kpz_pool_stats(const kpz_pool *p, int32_t *n_active, size_t *largest_
 
 void kpz_pool_destroy(kpz_pool *p) { delete p; }
 
-const char *kpz_pool_last_error(const kpz_pool *p) { return p ? p->err : ""; }
+const char *kpz_pool_last_error(const kpz_pool *p) { return p ? p->err : g_init_err; }
 
 }  // extern "C"
