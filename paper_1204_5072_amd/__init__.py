@@ -54,11 +54,19 @@ _lib = None
 
 
 def lib() -> ctypes.CDLL:
-    """Loads libkpz.so; raises if it has not been built."""
+    """Loads libkpz.so; raises if it has not been built.
+
+    torch is imported first: it loads its own HIP runtime, and libkpz.so
+    then binds to that same runtime (same soname) instead of loading a
+    second one from the system ROCm.  Two HIP runtimes in one process do
+    not share devices, streams or allocations (the second one finds no
+    device), and the device buffers and streams passed to the library come
+    from torch."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        import torch  # noqa: F401  (binds the process to torch's HIP runtime)
         L = ctypes.CDLL(LIB_PATH)
         vp, c = ctypes.c_void_p, ctypes
         L.kpz_workspace_bytes.argtypes = [c.POINTER(kpz_params), c.POINTER(c.c_size_t)]

@@ -92,3 +92,13 @@ def test_batch_members_must_share_moves(kpz):
           kpz.make_params(256, 1.0, 0.0, 2, (64, 64), moves=2)]
     with pytest.raises(kpz.KPZError):
         kpz.batch_sizes(ms)
+
+
+def test_library_shares_torch_hip_runtime(kpz):
+    """libkpz.so binds to the HIP runtime torch loaded: one libamdhip64 in
+    the process (a second runtime would see no device)."""
+    import os
+    kpz.lib()
+    maps = open(f"/proc/{os.getpid()}/maps").read()
+    hip = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
+    assert len(hip) == 1, hip
