@@ -2,8 +2,9 @@
 """Throughput of the KPZ octahedron sweep on one MI355X.
 
 Workload (default): L = 65536 periodic lattice (2^32 sites, 1 GiB of packed
-slopes), p = 1, q = 0, flat start, Philox seed 1, 256 x 256 dead-border
-blocks with 4 x 4 double tiles; W^2 is sampled every 10 MCS.  One "step" =
+slopes), p = 1, q = 0, flat start, Philox seed 1, 1024 x 64 dead-border
+blocks (the autotuner's choice for this L) with 4 x 4 double tiles; W^2 is
+sampled every 10 MCS.  One "step" =
 10 MCS followed by one exact W^2 sample (the full hot path: init once, then
 sweep + roughness).  Value = site-update attempts per second over the timed
 steps, with the lattice already resident in HBM.
@@ -223,6 +224,26 @@ def serving_leg(args):
     }
 
 
+def measured_traffic(block):
+    """HBM bytes per MCS (sweep + merge) of this block shape from the
+    committed hardware-counter summary, or None when the library source has
+    changed since the counters were taken (or the shape was not measured)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "kpz_sweep_L65536_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_1204_5072_amd", "csrc", "kpz.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"source_sha256 = ([0-9a-f]{64})", text)
+    if not m or m.group(1) != sha:
+        return None
+    m = re.search(r"traffic_bytes_per_mcs\[%dx%d\] = (\d+)" % tuple(block), text)
+    return float(m.group(1)) if m else None
+
+
 def copy_probe(mib: int) -> None:
     """A plain copy of known size (mib MiB read, mib MiB written per call):
     hardware byte counters read on it give the scale between the counters'
@@ -244,7 +265,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--L", type=int, default=65536)
-    ap.add_argument("--block", type=int, nargs=2, default=[256, 256])
+    ap.add_argument("--block", type=int, nargs=2, default=[1024, 64],
+                    help="dead-border block shape (default: the autotuner's choice at L = 2^16)")
     ap.add_argument("--mcs-per-step", type=int, default=10)
     ap.add_argument("--p", type=float, default=1.0)
     ap.add_argument("--q", type=float, default=0.0)
@@ -319,6 +341,7 @@ def main():
     sweep_s = sweep_ms / 1e3
     achieved_tops = OPS_PER_ATTEMPT * per_launch_attempts / sweep_s / 1e12
     achieved_gbs = BYTES_PER_ATTEMPT * per_launch_attempts / sweep_s / 1e9
+    traffic = measured_traffic(block) if (L == 65536 and args.moves == 1) else None
     line = {
         "metric": "site-update attempts/s at L=2^16",
         "value": value,
@@ -345,7 +368,9 @@ def main():
             "peak": VALU_PEAK_TOPS,
             "unit": "Tops/s",
             "frac": achieved_tops / VALU_PEAK_TOPS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per MCS (sweep + merge; rocprofv3 FETCH_SIZE and "
+                            "WRITE_SIZE scaled by a 1 GiB copy probe)",
             # one MCS = the sweep launch plus the straddling-word merge launch,
             # bracketed together by the events (the sum of the two kernels'
             # average durations in a kernel trace)
