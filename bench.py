@@ -195,6 +195,40 @@ def latency_leg(args):
     }
 
 
+def ring_leg(args):
+    """The 1+1-d ring (the rooftop reduction) at L = 2^30 sites (128 MiB of
+    packed bonds), p = 1, q = 0, seed 1, default blocks: attempts/s over 20
+    MCS timed with HIP events on the ring's stream, and its HBM roofline at
+    0.25 B per attempt (each bond bit read and written once per MCS)."""
+    import torch
+    import paper_1204_5072_amd as kpz
+    L, n = 1 << 30, 20
+    r = kpz.Ring(L, 1.0, 0.0, 1)
+    r.sweep(2)
+    r.roughness()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(r.stream)
+    r.sweep(n)
+    e1.record(r.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n
+    m = r.roughness()
+    block = int(r.params.block) or 16384
+    r.close()
+    gbs = 0.25 * L / (ms * 1e-3) / 1e9
+    return {
+        "metric": "site-update attempts/s, 1+1-d ring L=2^30",
+        "value": L / (ms * 1e-3),
+        "unit": "attempts/s",
+        "ms_per_mcs": ms,
+        "block": block,
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "bytes_per_attempt": 0.25},
+        "w2_t22": m.W2,
+    }
+
+
 def serving_leg(args):
     """Serving: Poisson stream of jobs (2000 at 50 jobs/s by default), L =
     2^k with k uniform on 8..13, p = 1, q uniform on [0, 0.5], MCS log-uniform
@@ -282,6 +316,7 @@ def main():
     ap.add_argument("--ens-seq-members", type=int, default=32)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--no-ring", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-hbm-gib", type=float, default=16.0)
@@ -392,6 +427,9 @@ def main():
     if not args.no_latency:
         print("bench: latency leg", file=sys.stderr, flush=True)
         line["latency"] = latency_leg(args)
+    if not args.no_ring:
+        print("bench: ring leg", file=sys.stderr, flush=True)
+        line["ring"] = ring_leg(args)
     if not args.no_serve:
         print("bench: serving leg", file=sys.stderr, flush=True)
         line["serving"] = serving_leg(args)

@@ -276,6 +276,56 @@ void kpz_pool_destroy(kpz_pool *pool);
  * kpz_last_error(NULL). */
 const char *kpz_pool_last_error(const kpz_pool *pool);
 
+/* ------------------------------------------------------------------------
+ * The 1+1-dimensional ring (rooftop / ASEP reduction of the model, Sec.
+ * 2.1) under the same decomposition reduced to one dimension (Sec. 3 and
+ * 3.1): dead-border blocks of B sites whose origin moves every MCS, tiles
+ * of 4 sites (two cells of 2 sites), 4 single-hit steps per MCS.
+ *
+ * Layout: L / 32 uint32 words; bond i, s_i = h(i+1) - h(i), is bit i mod 32
+ * of word i / 32 (1 = +1).  Flat start h(i) = i mod 2 (words 0x55555555).
+ * Memory, streams and errors as for kpz_sim.
+ */
+typedef struct kpz_ring kpz_ring;
+
+/* L: a multiple of 2048, 2048 <= L <= 2^32.  block: 2048, 4096, 8192 or
+ * 16384 sites dividing L, 0 = the largest of these dividing L; a single
+ * block (block = L) has no dead border.  p, q, seed as in kpz_params;
+ * flags must be 0.  Results are reproducible for identical parameters. */
+typedef struct {
+    int64_t L;
+    double p;
+    double q;
+    uint64_t seed;
+    int32_t block;
+    uint32_t flags;
+} kpz_ring_params;
+
+/* Device workspace bytes for these parameters (KPZ_EINVAL if invalid). */
+kpz_status kpz_ring_workspace_bytes(const kpz_ring_params *params, size_t *ws_bytes);
+
+/* Creates a handle and enqueues the flat start into d_words (at least L/8
+ * bytes) and the workspace counters; t = 0. */
+kpz_status kpz_ring_init(kpz_ring **out, const kpz_ring_params *params, uint32_t *d_words,
+                         size_t words_bytes, void *d_workspace, size_t workspace_bytes,
+                         void *stream);
+
+/* Enqueues n_mcs MCS (each: one sweep launch, one straddling-word merge). */
+kpz_status kpz_ring_sweep(kpz_ring *ring, int32_t n_mcs);
+
+/* Exact S1 = sum h, S2 = sum h^2 and W^2 = S2/L - (S1/L)^2 (computed from
+ * 128-bit integers); synchronises the stream.  KPZ_ERANGE if S1 or S2 does
+ * not fit int64 (W^2 is still set); KPZ_ESTATE if words and flip counters
+ * disagree. */
+kpz_status kpz_ring_roughness(kpz_ring *ring, int64_t *S1, int64_t *S2, double *W2);
+
+/* MCS counter and net number of flips (deposits - desorptions); syncs. */
+kpz_status kpz_ring_get_state(kpz_ring *ring, int64_t *t, int64_t *net);
+
+void kpz_ring_destroy(kpz_ring *ring);
+
+const char *kpz_ring_last_error(const kpz_ring *ring);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,14 +22,15 @@ LIB_PATH = os.path.join(PKG, "libkpz.so")
 KPZ_OK, KPZ_EINVAL, KPZ_ESIZE, KPZ_EHIP, KPZ_ESTATE, KPZ_ERANGE = 0, -1, -2, -3, -4, -5
 
 EXPORTED = ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness", "kpz_height_moments",
-            "kpz_get_state",
-            "kpz_set_state", "kpz_destroy", "kpz_status_str", "kpz_last_error",
+            "kpz_get_state", "kpz_set_state", "kpz_destroy", "kpz_status_str", "kpz_last_error",
             "kpz_batch_sizes", "kpz_batch_init", "kpz_batch_word_offset", "kpz_batch_sweep",
             "kpz_batch_roughness", "kpz_batch_run", "kpz_batch_get_t", "kpz_batch_destroy",
             "kpz_batch_last_error",
             "kpz_pool_job_bytes", "kpz_pool_control_bytes", "kpz_pool_init", "kpz_pool_submit",
             "kpz_pool_step", "kpz_pool_poll", "kpz_pool_stats", "kpz_pool_destroy",
-            "kpz_pool_last_error")
+            "kpz_pool_last_error",
+            "kpz_ring_workspace_bytes", "kpz_ring_init", "kpz_ring_sweep", "kpz_ring_roughness",
+            "kpz_ring_get_state", "kpz_ring_destroy", "kpz_ring_last_error")
 BATCH_MAX_SAMPLES = 1024
 
 
@@ -48,6 +49,11 @@ class kpz_params(ctypes.Structure):
                 ("block_y", ctypes.c_int32), ("tile_x", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("moves", ctypes.c_int32),
                 ("flags", ctypes.c_uint32)]
+
+
+class kpz_ring_params(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int64), ("p", ctypes.c_double), ("q", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("block", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
 _lib = None
@@ -111,12 +117,23 @@ def lib() -> ctypes.CDLL:
         L.kpz_pool_destroy.restype = None
         L.kpz_pool_last_error.argtypes = [vp]
         L.kpz_pool_last_error.restype = c.c_char_p
+        RP = c.POINTER(kpz_ring_params)
+        L.kpz_ring_workspace_bytes.argtypes = [RP, szp]
+        L.kpz_ring_init.argtypes = [c.POINTER(vp), RP, vp, c.c_size_t, vp, c.c_size_t, vp]
+        L.kpz_ring_sweep.argtypes = [vp, c.c_int32]
+        L.kpz_ring_roughness.argtypes = [vp, i64p, i64p, f64p]
+        L.kpz_ring_get_state.argtypes = [vp, i64p, i64p]
+        L.kpz_ring_destroy.argtypes = [vp]
+        L.kpz_ring_destroy.restype = None
+        L.kpz_ring_last_error.argtypes = [vp]
+        L.kpz_ring_last_error.restype = c.c_char_p
         for f in ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness",
                   "kpz_get_state", "kpz_set_state", "kpz_batch_sizes", "kpz_batch_init",
                   "kpz_batch_word_offset", "kpz_batch_sweep", "kpz_batch_roughness",
                   "kpz_batch_run", "kpz_batch_get_t", "kpz_pool_job_bytes",
                   "kpz_pool_control_bytes", "kpz_pool_init", "kpz_pool_submit", "kpz_pool_step",
-                  "kpz_pool_poll", "kpz_pool_stats"):
+                  "kpz_pool_poll", "kpz_pool_stats", "kpz_ring_workspace_bytes", "kpz_ring_init",
+                  "kpz_ring_sweep", "kpz_ring_roughness", "kpz_ring_get_state"):
             getattr(L, f).restype = c.c_int
         _lib = L
     return _lib
@@ -397,6 +414,69 @@ class Pool:
     def close(self) -> None:
         if self._h:
             lib().kpz_pool_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ring:
+    """The 1+1-d rooftop ring of L sites on one GPU (the reduction of the
+    model to one dimension).  ``words`` is a torch int32 tensor of L/32
+    packed bond words (bit layout in include/kpz.h)."""
+
+    def __init__(self, L: int, p: float = 1.0, q: float = 0.0, seed: int = 1, block: int = 0,
+                 device="cuda", stream=None):
+        import torch
+        self.params = kpz_ring_params(int(L), float(p), float(q), int(seed), int(block), 0)
+        self.L = int(L)
+        n = ctypes.c_size_t()
+        st = lib().kpz_ring_workspace_bytes(ctypes.byref(self.params), ctypes.byref(n))
+        if st != KPZ_OK:
+            raise KPZError(st, "kpz_ring_workspace_bytes")
+        self.device = torch.device(device)
+        self.words = torch.empty(self.L // 32, dtype=torch.int32, device=self.device)
+        self.workspace = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = ctypes.c_void_p()
+        st = lib().kpz_ring_init(ctypes.byref(self._h), ctypes.byref(self.params),
+                                 ctypes.c_void_p(self.words.data_ptr()), self.words.numel() * 4,
+                                 ctypes.c_void_p(self.workspace.data_ptr()), n.value,
+                                 ctypes.c_void_p(self.stream.cuda_stream))
+        if st != KPZ_OK:
+            raise KPZError(st, "kpz_ring_init", lib().kpz_last_error(None).decode())
+
+    def _check(self, st: int, what: str) -> None:
+        if st != KPZ_OK:
+            raise KPZError(st, what, lib().kpz_ring_last_error(self._h).decode())
+
+    def sweep(self, n_mcs: int = 1) -> "Ring":
+        self._check(lib().kpz_ring_sweep(self._h, int(n_mcs)), "kpz_ring_sweep")
+        return self
+
+    def roughness(self) -> Moments:
+        S1, S2, W2 = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        self._check(lib().kpz_ring_roughness(self._h, ctypes.byref(S1), ctypes.byref(S2),
+                                             ctypes.byref(W2)), "kpz_ring_roughness")
+        return Moments(S1.value, S2.value, W2.value)
+
+    def state(self) -> Tuple[int, int]:
+        t, net = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().kpz_ring_get_state(self._h, ctypes.byref(t), ctypes.byref(net)),
+                    "kpz_ring_get_state")
+        return t.value, net.value
+
+    def words_host(self):
+        """Copy of the packed bonds, numpy uint32 of shape (L/32,)."""
+        self.stream.synchronize()
+        return self.words.cpu().numpy().view("uint32")
+
+    def close(self) -> None:
+        if self._h:
+            lib().kpz_ring_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

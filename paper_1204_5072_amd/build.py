@@ -7,7 +7,7 @@ import subprocess
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = os.path.join(PKG, "csrc", "kpz.hip")
+SRCS = [os.path.join(PKG, "csrc", "kpz.hip"), os.path.join(PKG, "csrc", "kpz_ring.hip")]
 HDR = os.path.join(ROOT, "include", "kpz.h")
 LIB = os.path.join(PKG, "libkpz.so")
 
@@ -25,7 +25,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, SRC]
+    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, *SRCS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -52,38 +52,21 @@
 #include <vector>
 
 #include "kpz.h"
+#include "kpz_device.h"
 
 namespace {
+
+using kpzdev::byte_eq;
+using kpzdev::byte_lt;
+using kpzdev::philox;
+using kpzdev::U4;
 
 constexpr uint32_t TAG_ORIGIN = 1, TAG_SET = 2, TAG_SITE = 3, TAG_ACC1 = 4, TAG_ACC2 = 5;
 constexpr int NSLOTS = 1024;          // flip-counter slots in the workspace
 constexpr int WS_HEADER = 256;        // results area at the start of the workspace
 constexpr int TILE = 4;               // tile edge (sites)
 
-// ------------------------------------------------------------------ Philox
-
-struct U4 {
-    uint32_t x, y, z, w;
-};
-
-__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                     uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return U4{c0, c1, c2, c3};
-}
+// ------------------------------------------------------------ bit helpers
 
 __device__ __forceinline__ uint32_t rotr(uint32_t x, uint32_t s)
 {
@@ -169,25 +152,8 @@ __device__ __forceinline__ bool quad_bottom_row(uint32_t tid, int i, const Sweep
     else return tid + (uint32_t)TPB * i < a.ntx;
 }
 
-// Byte-wise helpers for the acceptance test of four tiles at once.
-__device__ __forceinline__ uint32_t byte_lt(uint32_t A, uint32_t c)
-{
-    // 0x80 in every byte of A that is below c (c in [1, 255]): 9-bit
-    // differences (a | 0x100) - c in 16-bit lanes have bit 8 clear iff a < c
-    const uint32_t cc = c * 0x00010001u;
-    const uint32_t even = ((A & 0x00FF00FFu) | 0x01000100u) - cc;
-    const uint32_t odd = (((A >> 8) & 0x00FF00FFu) | 0x01000100u) - cc;
-    const uint32_t ge = ((even >> 1) & 0x00800080u) | ((odd << 7) & 0x80008000u);
-    return ~ge & 0x80808080u;
-}
-
-__device__ __forceinline__ uint32_t byte_eq(uint32_t A, uint32_t c)
-{
-    // 0x80 in every byte of A equal to c
-    const uint32_t z = A ^ (c * 0x01010101u);
-    return ~(((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z) & 0x80808080u;
-}
-
+// Byte-wise helpers for the acceptance test of four tiles at once (byte_lt
+// and byte_eq are in kpz_device.h).
 __device__ __forceinline__ uint32_t bytes_nonzero(uint32_t F)
 {
     // F has at most one bit per byte, at position 0, 2, 4 or 6

@@ -1,0 +1,125 @@
+"""GPU parity of the 1+1-d ring path (the rooftop reduction, Sec. 2.1,
+under the decomposition of Sec. 3 / 3.1 reduced to one dimension) against
+the oracle's ring schedule: every packed word, S1, S2 and the flip count
+after every MCS, bit for bit; large rings on sampled blocks; growth
+exponents at scale."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1204_5072_amd as kpz
+    kpz.lib()
+    return kpz
+
+
+def test_ring_init(gpu):
+    for L in (2048, 6144, 1 << 20):
+        r = gpu.Ring(L)
+        w = r.words_host()
+        assert w.shape == (L // 32,) and np.all(w == 0x55555555)
+        m = r.roughness()
+        assert (m.S1, m.S2, m.W2) == (L // 2, L // 2, 0.25)
+        assert r.state() == (0, 0)
+
+
+RING_CASES = [
+    # (L, block, p, q, seed, n_mcs)
+    (2048, 2048, 1.0, 0.0, 1, 8),        # one periodic block, K = 1
+    (4096, 2048, 1.0, 0.0, 2, 8),        # two blocks, dead borders
+    (8192, 4096, 0.7, 0.3, 3, 6),        # K = 2, generic thresholds
+    (16384, 8192, 0.5, 0.5, 4, 6),       # K = 4, EW
+    (65536, 16384, 1.0, 0.25, 5, 4),     # K = 8
+    (6144, 2048, 1.0, 0.0, 6, 6),        # three blocks (L not a power of two)
+    (10240, 2048, 0.3, 0.9, 7, 6),
+    (16384, 16384, 1.0, 0.0, 8, 6),      # one periodic block, K = 8
+    (8192, 2048, 1.0, 0.999999, 9, 4),   # threshold just below 2^32: tie draws
+    (4096, 2048, 0.0, 0.0, 10, 3),       # frozen
+    (4096, 2048, 0.0, 1.0, 11, 4),       # desorption only
+    (8192, 8192, 0.001, 0.002, 12, 3),   # thresholds below 2^24: ties at A = 0
+]
+
+
+@pytest.mark.parametrize("L,B,p,q,seed,n", RING_CASES)
+def test_ring_sweep_matches_oracle(gpu, oracle_lib, L, B, p, q, seed, n):
+    _log(f"ring L={L} block={B} p={p} q={q} seed={seed} n={n}")
+    r = gpu.Ring(L, p, q, seed, B)
+    st = oracle_lib.RingState(L)
+    for t in range(n):
+        r.sweep(1)
+        st.run_dd(1, p, q, seed, B)
+        w = r.words_host()
+        ref = oracle_lib.pack1d(st.s)
+        if not np.array_equal(w, ref):
+            bad = np.flatnonzero(w != ref)
+            pytest.fail(f"words differ after MCS {t}: {len(bad)} words, first at {bad[0]}")
+        m = r.roughness()
+        S1, S2 = st.moments()
+        assert (m.S1, m.S2) == (S1, S2), t
+        exact = (L * S2 - S1 * S1) / (L * L)
+        assert math.isclose(m.W2, exact, rel_tol=1e-15)
+        assert r.state() == (t + 1, int(st.net[0]))
+
+
+def test_ring_multi_mcs_call(gpu):
+    a = gpu.Ring(8192, 1.0, 0.25, 3, 2048).sweep(7)
+    b = gpu.Ring(8192, 1.0, 0.25, 3, 2048)
+    for _ in range(7):
+        b.sweep(1)
+    assert np.array_equal(a.words_host(), b.words_host()) and a.state() == b.state()
+
+
+def test_ring_large_sampled_blocks(gpu, oracle_lib):
+    """L = 2^26 in 8192-site blocks: after MCS 0 and 1 from the flat start,
+    sampled blocks (including the one that wraps around) equal the oracle's
+    block runner on the same input; the moments are consistent."""
+    L, B, seed, p, q = 1 << 26, 8192, 5, 1.0, 0.3
+    r = gpu.Ring(L, p, q, seed, B)
+    nb = L // B
+    for t in range(2):
+        before = oracle_lib.unpack1d(r.words_host())
+        r.sweep(1)
+        after = oracle_lib.unpack1d(r.words_host())
+        o = oracle_lib.dd1d_origin(seed, t, B)
+        for b in (0, 1, nb // 2, nb - 1):
+            idx = (o + b * B + np.arange(B)) % L
+            bs = np.ascontiguousarray(before[idx])
+            oracle_lib.dd1d_block_mcs(L, p, q, seed, B, t, b, bs)
+            assert np.array_equal(bs, after[idx]), (t, b)
+    m = r.roughness()
+    h = np.zeros(L, np.int64)
+    h[1:] = np.cumsum(after[:-1].astype(np.int64))
+    R1 = int(h.sum())
+    assert (m.S1 - R1) % L == 0
+
+
+def test_ring_kpz_growth_exponent(gpu):
+    """beta = 1/3 for the 1+1-d KPZ class (p = 1, q = 0) and 1/4 for EW
+    (p = q), fitted on t = 256 .. 4096 on a ring of 2^22 sites."""
+    out = {}
+    for name, (p, q) in {"kpz": (1.0, 0.0), "ew": (0.5, 0.5)}.items():
+        r = gpu.Ring(1 << 22, p, q, 77)
+        times, w2 = [256, 512, 1024, 2048, 4096], []
+        t = 0
+        for T in times:
+            r.sweep(T - t)
+            t = T
+            w2.append(r.roughness().W2)
+        out[name] = np.polyfit(np.log(times), np.log(w2), 1)[0] / 2
+    print("ring beta", out, flush=True)
+    assert 0.30 <= out["kpz"] <= 0.35, out
+    assert 0.22 <= out["ew"] <= 0.27, out
