@@ -214,7 +214,7 @@ def ring_leg(args):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / n
     m = r.roughness()
-    block = int(r.params.block) or 16384
+    block = int(r.params.block) or 128
     r.close()
     gbs = 0.25 * L / (ms * 1e-3) / 1e9
     return {

@@ -288,10 +288,14 @@ const char *kpz_pool_last_error(const kpz_pool *pool);
  */
 typedef struct kpz_ring kpz_ring;
 
-/* L: a multiple of 2048, 2048 <= L <= 2^32.  block: 2048, 4096, 8192 or
- * 16384 sites dividing L, 0 = the largest of these dividing L; a single
- * block (block = L) has no dead border.  p, q, seed as in kpz_params;
- * flags must be 0.  Results are reproducible for identical parameters. */
+/* L: a multiple of 128, 128 <= L <= 2^32.  block: the dead-border block
+ * of the device layer, 128, 256, 512 or 1024 sites dividing L; 0 = 128.
+ * Every block draws one cell set per step for all its tiles, which
+ * correlates the updates across the block; in one dimension blocks of
+ * thousands of sites visibly change the growth (amplitude and effective
+ * exponent), small blocks do not.  A single block (block = L) has no dead
+ * border.  p, q, seed as in kpz_params; flags must be 0.  Results are
+ * reproducible for identical parameters. */
 typedef struct {
     int64_t L;
     double p;

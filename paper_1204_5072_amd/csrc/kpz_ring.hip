@@ -28,10 +28,10 @@
 //
 // Kernels
 //   kpz_ring_init_kernel      flat start h(i) = i mod 2: words 0x55555555
-//   kpz_ring_sweep_kernel<K>  one MCS: one wave per block of B = 2048 K sites,
-//                             K consecutive block words per lane in registers
-//                             (no LDS: the left neighbour bond of a word's
-//                             bit 0 comes from the previous lane by a shuffle)
+//   kpz_ring_sweep_kernel<K>  one MCS: every lane one dead-border block of
+//                             B = 32 K sites in K registers (no LDS); a wave
+//                             takes 64 consecutive blocks, and neighbouring
+//                             lanes join their shared words by a shuffle
 //   kpz_ring_merge_kernel     the words two blocks share (origin not a
 //                             multiple of 32) from both blocks' parts
 //   kpz_ring_chunks_kernel    per chunk of 8192 bonds: (sum of bonds, sum of
@@ -63,11 +63,11 @@ constexpr int CHUNK_WORDS = 256;       // words per chunk of the moment pass (on
 
 struct RingArgs {
     uint32_t *words;
-    uint32_t *side;                // [2][nb]: block's part of its first / after-last word
+    uint32_t *side;                // [2][nwaves]: a wave's part of its first / after-last word
     unsigned long long *slots;
     uint64_t L;
     uint32_t W;                    // words
-    uint32_t B, nb;                // block size (sites), blocks
+    uint32_t B, nb, nwaves;        // block size (sites), blocks, waves (64 blocks each)
     uint32_t seed_lo, seed_hi;
     uint32_t t;
     uint64_t P, Q;
@@ -141,54 +141,53 @@ __device__ __forceinline__ uint32_t nibbles_nonzero(uint32_t m)
     return x;
 }
 
+// One MCS of the ring.  Every lane is one dead-border block of B = 32 K
+// sites held in K registers: blocks are independent within the MCS (site 0
+// of a block is dead, so no update touches another block's bonds), and a
+// wave handles 64 consecutive blocks.  The words two neighbouring lanes'
+// blocks share are assembled with a shuffle; the two at the ends of the
+// wave's range go through the side buffer and the merge launch.
 template <int K, bool ACC>
 __global__ __launch_bounds__(64) void kpz_ring_sweep_kernel(const RingArgs a)
 {
     const uint32_t lane = threadIdx.x;
-    const uint32_t b = blockIdx.x;
+    const uint32_t w = blockIdx.x;                  // wave (range of 64 blocks)
+    const uint32_t b = w * 64u + lane;              // this lane's block
+    const bool live = b < a.nb;
+    const uint32_t last = min(63u, a.nb - 1u - w * 64u);   // last live lane of the wave
     const uint32_t o = ring_origin(a);
+    const uint32_t sh = o & 31u;
+    // block b starts at site o + b B; its words are gw0 + j, j = 0..K
     const uint64_t g0 = ((uint64_t)o + (uint64_t)b * a.B) % a.L;
-    const uint32_t sh = (uint32_t)(g0 & 31u);
     const uint32_t gw0 = (uint32_t)(g0 >> 5);
-    const uint32_t nbw = a.B / 32;          // block words = 64 K
 
-    // ---- load: lane holds block words lane K .. lane K + K - 1
     uint32_t c[K];
-    {
-        uint32_t raw[K];
+    if (live) {
+        uint32_t raw[K + 1];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            uint32_t gw = gw0 + lane * K + j;
+        for (int j = 0; j <= K; ++j) {
+            uint32_t gw = gw0 + j;
             if (gw >= a.W) gw -= a.W;
             raw[j] = a.words[gw];
         }
-        // word after this lane's last: the next lane's first raw word; lane 63
-        // loads it (the word after the block's end)
-        uint32_t nxt = __shfl(raw[0], (lane + 1) & 63u, 64);
-        if (lane == 63 && sh) {
-            uint32_t gw = gw0 + nbw;
-            if (gw >= a.W) gw -= a.W;
-            nxt = a.words[gw];
-        }
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const uint32_t hi = j + 1 < K ? raw[j + 1] : nxt;
-            c[j] = __builtin_amdgcn_alignbit(hi, raw[j], sh);
-        }
+        for (int j = 0; j < K; ++j) c[j] = __builtin_amdgcn_alignbit(raw[j + 1], raw[j], sh);
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) c[j] = 0u;
     }
 
-    // ---- site draws of this MCS: block word wl uses word wl mod 4 of call wl / 4
-    const uint64_t q0 = (uint64_t)b * (a.B / 128);
+    // site draws: block word wl uses word wl mod 4 of call (b K/4 + wl/4)
     uint32_t sw[K];
 #pragma unroll
     for (int j = 0; j < K; j += 4) {
-        const uint32_t wl = lane * K + j;
-        const uint64_t qi = q0 + wl / 4;
+        const uint64_t qi = (uint64_t)b * (K / 4) + j / 4;
         const U4 s4 = philox((uint32_t)qi, (uint32_t)(qi >> 32), a.t, TAG_SITE1D << 24, a.seed_lo,
                              a.seed_hi);
-        const uint32_t sv[4] = {s4.x, s4.y, s4.z, s4.w};
-#pragma unroll
-        for (int jj = 0; jj < 4 && j + jj < K; ++jj) sw[j + jj] = sv[(wl + jj) & 3u];
+        sw[j] = s4.x;
+        sw[j + 1] = s4.y;
+        sw[j + 2] = s4.z;
+        sw[j + 3] = s4.w;
     }
     const uint32_t setw = philox(b, 0u, a.t, TAG_SET1D << 24, a.seed_lo, a.seed_hi).x;
 
@@ -198,90 +197,95 @@ __global__ __launch_bounds__(64) void kpz_ring_sweep_kernel(const RingArgs a)
     ac.tQ = (uint32_t)(a.Q >> 24);
     ac.lowP = (uint32_t)(a.P & 0xFFFFFFu);
     ac.lowQ = (uint32_t)(a.Q & 0xFFFFFFu);
-    const bool dead0 = a.nb > 1 && lane == 0;
+    const bool single = a.nb == 1;     // one periodic block: site 0 is live
     int net = 0;
 
+    if (live) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t set = (setw >> k) & 1u;
-        uint32_t F[K];
-        // left neighbour bond of each word's bit 0: bit 31 of the previous
-        // word (the previous lane's last word for j = 0)
-        const uint32_t prev_last = __shfl(c[K - 1], (lane + 63) & 63u, 64);
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t set = (setw >> k) & 1u;
+            uint32_t F[K];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const uint32_t prev = j ? c[j - 1] : prev_last;
-            const uint32_t l = (c[j] << 1) | (prev >> 31);
-            const uint32_t mn = ~l & c[j];
-            const uint32_t R = spread8(sw[j] >> (8 * k));
-            uint32_t sel = ((0x11111111u & ~R) | (R << 1)) << (2 * set);
-            if (j == 0 && dead0) sel &= ~1u;
-            if (ACC) {
-                const uint32_t mx = l & ~c[j];
-                const uint32_t wl = lane * K + j;
-                const uint64_t ai = (uint64_t)b * (a.B / 64) + wl / 2;
-                const U4 aw = philox((uint32_t)ai, (uint32_t)(ai >> 32), a.t, (TAG_ACC1D << 24) | k,
-                                     a.seed_lo, a.seed_hi);
-                const uint32_t A0 = (wl & 1u) ? aw.z : aw.x;
-                const uint32_t A1 = (wl & 1u) ? aw.w : aw.y;
-                uint32_t accP, accQ;
-                const uint64_t tile0 = (uint64_t)b * (a.B / 4) + 8ull * wl;
-                ring_accept(A0, A1, ac, nibbles_nonzero(sel & mn), nibbles_nonzero(sel & mx),
-                            tile0, k, a, accP, accQ);
-                const uint32_t fmin = sel & mn & accP, fmax = sel & mx & accQ;
-                net += __builtin_popcount(fmin) - __builtin_popcount(fmax);
-                F[j] = fmin | fmax;
-            } else {
-                F[j] = sel & mn;
-                net += __builtin_popcount(F[j]);
+            for (int j = 0; j < K; ++j) {
+                // left neighbour bond of bit 0: bit 31 of the previous word (for
+                // j = 0 the block's last bond when the block is the whole ring;
+                // otherwise site 0 is dead and the value is not used)
+                const uint32_t prev = j ? c[j - 1] : (single ? c[K - 1] : 0u);
+                const uint32_t l = (c[j] << 1) | (prev >> 31);
+                const uint32_t mn = ~l & c[j];
+                const uint32_t R = spread8(sw[j] >> (8 * k));
+                uint32_t sel = ((0x11111111u & ~R) | (R << 1)) << (2 * set);
+                if (j == 0 && !single) sel &= ~1u;
+                if (ACC) {
+                    const uint32_t mx = l & ~c[j];
+                    const uint64_t ai = (uint64_t)b * (K / 2) + j / 2;
+                    const U4 aw = philox((uint32_t)ai, (uint32_t)(ai >> 32), a.t,
+                                         (TAG_ACC1D << 24) | k, a.seed_lo, a.seed_hi);
+                    const uint32_t A0 = (j & 1) ? aw.z : aw.x;
+                    const uint32_t A1 = (j & 1) ? aw.w : aw.y;
+                    uint32_t accP, accQ;
+                    const uint64_t tile0 = (uint64_t)b * (a.B / 4) + 8ull * j;
+                    ring_accept(A0, A1, ac, nibbles_nonzero(sel & mn), nibbles_nonzero(sel & mx),
+                                tile0, k, a, accP, accQ);
+                    const uint32_t fmin = sel & mn & accP, fmax = sel & mx & accQ;
+                    net += __builtin_popcount(fmin) - __builtin_popcount(fmax);
+                    F[j] = fmin | fmax;
+                } else {
+                    F[j] = sel & mn;
+                    net += __builtin_popcount(F[j]);
+                }
             }
-        }
-        // apply: a flip at site i negates bonds i - 1 and i; chosen sites are
-        // at least three apart, so the masks never overlap
-        const uint32_t carry = __shfl(F[0] & 1u, (lane + 1) & 63u, 64);
+            // apply: a flip at site i negates bonds i - 1 and i; chosen sites
+            // are at least three apart, so the masks never overlap
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            c[j] ^= F[j] | (F[j] >> 1);
-            const uint32_t in = j + 1 < K ? (F[j + 1] & 1u) : carry;
-            c[j] ^= in << 31;
+            for (int j = 0; j < K; ++j) {
+                c[j] ^= F[j] | (F[j] >> 1);
+                const uint32_t in = j + 1 < K ? (F[j + 1] & 1u) : (single ? (F[0] & 1u) : 0u);
+                c[j] ^= in << 31;
+            }
         }
     }
 
-    // ---- store: global word gw0 + i (i = 1 .. nbw - 1) = high part of block
-    // word i - 1 and low part of block word i; the block's parts of words
-    // gw0 and gw0 + nbw go to the side buffer
-    const uint32_t prev_last = __shfl(c[K - 1], (lane + 63) & 63u, 64);
+    // store: global word gw0 + j of block b (j >= 1) = high part of block
+    // word j - 1 and low part of block word j; word gw0 is shared with the
+    // previous block (its last word's high part comes from lane - 1)
+    const uint32_t prev_last = __shfl(c[K - 1], (lane + 63u) & 63u, 64);
+    if (live) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const uint32_t i = lane * K + j;
-        const uint32_t prev = j ? c[j - 1] : prev_last;
-        uint32_t gw = gw0 + i;
-        if (gw >= a.W) gw -= a.W;
-        if (sh == 0) {
-            a.words[gw] = c[j];
-        } else if (i > 0) {
-            a.words[gw] = __builtin_amdgcn_alignbit(c[j], prev, 32u - sh);
-        } else {
-            a.side[b] = c[0] << sh;
+        for (int j = 0; j < K; ++j) {
+            uint32_t gw = gw0 + j;
+            if (gw >= a.W) gw -= a.W;
+            if (sh == 0) {
+                a.words[gw] = c[j];
+            } else if (j > 0) {
+                a.words[gw] = __builtin_amdgcn_alignbit(c[j], c[j - 1], 32u - sh);
+            } else if (lane > 0) {
+                a.words[gw] = __builtin_amdgcn_alignbit(c[0], prev_last, 32u - sh);
+            } else {
+                a.side[w] = c[0] << sh;
+            }
         }
+        if (sh && lane == last) a.side[a.nwaves + w] = c[K - 1] >> (32u - sh);
     }
-    if (sh && lane == 63) a.side[a.nb + b] = c[K - 1] >> (32u - sh);
 
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) net += __shfl_xor(net, off, 64);
     if (lane == 0 && net != 0)
-        atomicAdd(a.slots + (b & (RING_SLOTS - 1)), (unsigned long long)(long long)net);
+        atomicAdd(a.slots + (w & (RING_SLOTS - 1)), (unsigned long long)(long long)net);
 }
 
+// The word at the start of each wave's range: the previous wave's last
+// block's high part and this wave's first block's low part.
 __global__ void kpz_ring_merge_kernel(const RingArgs a)
 {
     const uint32_t o = ring_origin(a);
     const uint32_t sh = o & 31u;
     if (sh == 0) return;
-    for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < a.nb; b += gridDim.x * blockDim.x) {
-        uint32_t gw = (uint32_t)((((uint64_t)o + (uint64_t)b * a.B) % a.L) >> 5);
-        const uint32_t left = a.side[a.nb + (b == 0 ? a.nb - 1 : b - 1)];
-        a.words[gw] = left | a.side[b];
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < a.nwaves;
+         w += gridDim.x * blockDim.x) {
+        const uint32_t gw = (uint32_t)((((uint64_t)o + (uint64_t)w * 64u * a.B) % a.L) >> 5);
+        const uint32_t left = a.side[a.nwaves + (w == 0 ? a.nwaves - 1 : w - 1)];
+        a.words[gw] = left | a.side[w];
     }
 }
 
@@ -466,15 +470,11 @@ kpz_status ring_resolve(const kpz_ring_params *p, uint32_t *B)
 {
     if (!p) return KPZ_EINVAL;
     const int64_t L = p->L;
-    if (L < 2048 || L > (1ll << 32) || L % 2048) return KPZ_EINVAL;
+    if (L < 128 || L > (1ll << 32) || L % 128) return KPZ_EINVAL;
     if (!(p->p >= 0.0 && p->p <= 1.0 && p->q >= 0.0 && p->q <= 1.0)) return KPZ_EINVAL;
     if (p->flags != 0) return KPZ_EINVAL;
-    int64_t b = p->block;
-    if (b == 0) {
-        b = 16384;
-        while (L % b) b >>= 1;
-    }
-    if (b != 2048 && b != 4096 && b != 8192 && b != 16384) return KPZ_EINVAL;
+    const int64_t b = p->block ? p->block : 128;
+    if (b != 128 && b != 256 && b != 512 && b != 1024) return KPZ_EINVAL;
     if (L % b) return KPZ_EINVAL;
     *B = (uint32_t)b;
     return KPZ_OK;
@@ -482,10 +482,10 @@ kpz_status ring_resolve(const kpz_ring_params *p, uint32_t *B)
 
 size_t ring_ws_needed(int64_t L, uint32_t B)
 {
-    const uint64_t W = (uint64_t)L / 32, nb = (uint64_t)L / B;
+    const uint64_t W = (uint64_t)L / 32, nwaves = ((uint64_t)L / B + 63) / 64;
     const uint64_t nchunks = (W + CHUNK_WORDS - 1) / CHUNK_WORDS;
     return (size_t)RING_HEADER + sizeof(long long) * RING_SLOTS + 3 * sizeof(long long) * nchunks +
-           2 * sizeof(uint32_t) * nb;
+           2 * sizeof(uint32_t) * nwaves;
 }
 
 long long *ring_res(kpz_ring *r) { return (long long *)r->ws; }
@@ -566,27 +566,28 @@ kpz_status kpz_ring_sweep(kpz_ring *r, int32_t n_mcs)
     a.W = (uint32_t)(a.L / 32);
     a.B = r->B;
     a.nb = (uint32_t)(a.L / r->B);
+    a.nwaves = (a.nb + 63) / 64;
     a.seed_lo = (uint32_t)r->prm.seed;
     a.seed_hi = (uint32_t)(r->prm.seed >> 32);
     a.P = r->P;
     a.Q = r->Q;
     a.acc = !(r->P == (1ull << 32) && r->Q == 0);
-    const uint32_t K = r->B / 2048;
-    const uint32_t mgrid = (a.nb + 255) / 256 < 4096 ? (a.nb + 255) / 256 : 4096;
+    const uint32_t K = r->B / 32;
+    const uint32_t mgrid = (a.nwaves + 255) / 256 < 4096 ? (a.nwaves + 255) / 256 : 4096;
     for (int32_t m = 0; m < n_mcs; ++m) {
         a.t = (uint32_t)(r->t + m);
 #define RING_LAUNCH(KK)                                                                      \
     if (a.acc)                                                                               \
-        hipLaunchKernelGGL((kpz_ring_sweep_kernel<KK, true>), dim3(a.nb), dim3(64), 0,       \
+        hipLaunchKernelGGL((kpz_ring_sweep_kernel<KK, true>), dim3(a.nwaves), dim3(64), 0,   \
                            r->stream, a);                                                    \
     else                                                                                     \
-        hipLaunchKernelGGL((kpz_ring_sweep_kernel<KK, false>), dim3(a.nb), dim3(64), 0,      \
+        hipLaunchKernelGGL((kpz_ring_sweep_kernel<KK, false>), dim3(a.nwaves), dim3(64), 0,  \
                            r->stream, a);
         switch (K) {
-        case 1: RING_LAUNCH(1) break;
-        case 2: RING_LAUNCH(2) break;
         case 4: RING_LAUNCH(4) break;
-        default: RING_LAUNCH(8) break;
+        case 8: RING_LAUNCH(8) break;
+        case 16: RING_LAUNCH(16) break;
+        default: RING_LAUNCH(32) break;
         }
 #undef RING_LAUNCH
         hipLaunchKernelGGL(kpz_ring_merge_kernel, dim3(mgrid), dim3(256), 0, r->stream, a);

@@ -104,14 +104,15 @@ def test_library_shares_torch_hip_runtime(kpz):
     assert len(hip) == 1, hip
 
 
-@pytest.mark.parametrize("L,block,ok", [(2048, 0, True), (6144, 0, True), (1 << 20, 0, True),
-                                        (1 << 20, 4096, True), (1 << 32, 16384, True),
-                                        (1000, 0, False), (2048, 4096, False), (8192, 1024, False),
-                                        (6144, 4096, False), ((1 << 32) + 2048, 0, False)])
+@pytest.mark.parametrize("L,block,ok", [(128, 0, True), (6144, 0, True), (1 << 20, 0, True),
+                                        (1 << 20, 1024, True), (1 << 32, 512, True),
+                                        (1000, 0, False), (2048, 4096, False), (8192, 64, False),
+                                        (384, 256, False), ((1 << 32) + 128, 0, False),
+                                        (2048, 2048, False)])
 def test_ring_params_validation(kpz, L, block, ok):
     p = kpz.kpz_ring_params(L, 1.0, 0.0, 1, block, 0)
     n = ctypes.c_size_t()
     st = kpz.lib().kpz_ring_workspace_bytes(ctypes.byref(p), ctypes.byref(n))
     assert (st == kpz.KPZ_OK) == ok, st
     if ok:
-        assert n.value >= 256 + 8 * 1024 + 24 * (L // 8192)
+        assert n.value >= 256 + 8 * 1024 + 24 * (L // 8192) + 8 * (L // (64 * (block or 128)))

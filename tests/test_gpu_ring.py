@@ -39,18 +39,18 @@ def test_ring_init(gpu):
 
 RING_CASES = [
     # (L, block, p, q, seed, n_mcs)
-    (2048, 2048, 1.0, 0.0, 1, 8),        # one periodic block, K = 1
-    (4096, 2048, 1.0, 0.0, 2, 8),        # two blocks, dead borders
-    (8192, 4096, 0.7, 0.3, 3, 6),        # K = 2, generic thresholds
-    (16384, 8192, 0.5, 0.5, 4, 6),       # K = 4, EW
-    (65536, 16384, 1.0, 0.25, 5, 4),     # K = 8
-    (6144, 2048, 1.0, 0.0, 6, 6),        # three blocks (L not a power of two)
-    (10240, 2048, 0.3, 0.9, 7, 6),
-    (16384, 16384, 1.0, 0.0, 8, 6),      # one periodic block, K = 8
-    (8192, 2048, 1.0, 0.999999, 9, 4),   # threshold just below 2^32: tie draws
-    (4096, 2048, 0.0, 0.0, 10, 3),       # frozen
-    (4096, 2048, 0.0, 1.0, 11, 4),       # desorption only
-    (8192, 8192, 0.001, 0.002, 12, 3),   # thresholds below 2^24: ties at A = 0
+    (128, 128, 1.0, 0.0, 1, 8),          # one periodic block, one live lane
+    (1024, 1024, 0.7, 0.3, 2, 6),        # one periodic block of 32 words
+    (256, 128, 1.0, 0.0, 3, 8),          # two blocks, dead borders
+    (8576, 128, 1.0, 0.25, 4, 6),        # 67 blocks: a second, partial wave
+    (16384, 256, 0.5, 0.5, 5, 6),        # EW
+    (65536, 512, 1.0, 0.25, 6, 4),
+    (3072, 1024, 0.3, 0.9, 7, 6),        # L not a power of two
+    (8192, 128, 1.0, 0.999999, 8, 4),    # threshold just below 2^32: tie draws
+    (4096, 128, 0.0, 0.0, 9, 3),         # frozen
+    (4096, 128, 0.0, 1.0, 10, 4),        # desorption only
+    (4096, 512, 0.001, 0.002, 11, 3),    # thresholds below 2^24: ties at A = 0
+    (1 << 20, 128, 1.0, 0.0, 12, 2),     # 8192 blocks, 128 waves
 ]
 
 
@@ -76,18 +76,19 @@ def test_ring_sweep_matches_oracle(gpu, oracle_lib, L, B, p, q, seed, n):
 
 
 def test_ring_multi_mcs_call(gpu):
-    a = gpu.Ring(8192, 1.0, 0.25, 3, 2048).sweep(7)
-    b = gpu.Ring(8192, 1.0, 0.25, 3, 2048)
+    a = gpu.Ring(8192, 1.0, 0.25, 3, 256).sweep(7)
+    b = gpu.Ring(8192, 1.0, 0.25, 3, 256)
     for _ in range(7):
         b.sweep(1)
     assert np.array_equal(a.words_host(), b.words_host()) and a.state() == b.state()
 
 
 def test_ring_large_sampled_blocks(gpu, oracle_lib):
-    """L = 2^26 in 8192-site blocks: after MCS 0 and 1 from the flat start,
-    sampled blocks (including the one that wraps around) equal the oracle's
-    block runner on the same input; the moments are consistent."""
-    L, B, seed, p, q = 1 << 26, 8192, 5, 1.0, 0.3
+    """L = 2^26 in 128-site blocks: after MCS 0 and 1 from the flat start,
+    sampled blocks (including the one that wraps around and those at the
+    ends of a wave's range) equal the oracle's block runner on the same
+    input; the moments are consistent."""
+    L, B, seed, p, q = 1 << 26, 128, 5, 1.0, 0.3
     r = gpu.Ring(L, p, q, seed, B)
     nb = L // B
     for t in range(2):
@@ -95,7 +96,7 @@ def test_ring_large_sampled_blocks(gpu, oracle_lib):
         r.sweep(1)
         after = oracle_lib.unpack1d(r.words_host())
         o = oracle_lib.dd1d_origin(seed, t, B)
-        for b in (0, 1, nb // 2, nb - 1):
+        for b in (0, 1, 63, 64, nb // 2, nb - 1):
             idx = (o + b * B + np.arange(B)) % L
             bs = np.ascontiguousarray(before[idx])
             oracle_lib.dd1d_block_mcs(L, p, q, seed, B, t, b, bs)
@@ -109,7 +110,8 @@ def test_ring_large_sampled_blocks(gpu, oracle_lib):
 
 def test_ring_kpz_growth_exponent(gpu):
     """beta = 1/3 for the 1+1-d KPZ class (p = 1, q = 0) and 1/4 for EW
-    (p = q), fitted on t = 256 .. 4096 on a ring of 2^22 sites."""
+    (p = q), fitted on t = 256 .. 4096 on a ring of 2^22 sites in the
+    default 128-site blocks."""
     out = {}
     for name, (p, q) in {"kpz": (1.0, 0.0), "ew": (0.5, 0.5)}.items():
         r = gpu.Ring(1 << 22, p, q, 77)
