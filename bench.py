@@ -258,7 +258,7 @@ def serving_leg(args):
     }
 
 
-def measured_traffic(block):
+def measured_traffic(block, in_place=False):
     """HBM bytes per MCS (sweep + merge) of this block shape from the
     committed hardware-counter summary, or None when the library source has
     changed since the counters were taken (or the shape was not measured)."""
@@ -274,7 +274,8 @@ def measured_traffic(block):
     m = re.search(r"source_sha256 = ([0-9a-f]{64})", text)
     if not m or m.group(1) != sha:
         return None
-    m = re.search(r"traffic_bytes_per_mcs\[%dx%d\] = (\d+)" % tuple(block), text)
+    key = "%dx%d%s" % (block[0], block[1], ",in_place" if in_place else "")
+    m = re.search(r"traffic_bytes_per_mcs\[%s\] = (\d+)" % re.escape(key), text)
     return float(m.group(1)) if m else None
 
 
@@ -305,6 +306,8 @@ def main():
     ap.add_argument("--p", type=float, default=1.0)
     ap.add_argument("--q", type=float, default=0.0)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--in-place", action="store_true",
+                    help="update the lattice in place (no second lattice buffer)")
     ap.add_argument("--moves", type=int, default=1,
                     help="dead-border origin moves per MCS (block residency 1/moves MCS)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -341,7 +344,7 @@ def main():
     block = tuple(args.block)
     print(f"bench: L={L} block={block} p={args.p} q={args.q} seed={args.seed} "
           f"steps={args.steps} warmup={args.warmup} mcs/step={M}", file=sys.stderr, flush=True)
-    sim = kpz.Sim(L, args.p, args.q, args.seed, block, moves=args.moves)
+    sim = kpz.Sim(L, args.p, args.q, args.seed, block, moves=args.moves, in_place=args.in_place)
     stream = sim.stream
     for _ in range(args.warmup):
         sim.sweep(M)
@@ -376,7 +379,8 @@ def main():
     sweep_s = sweep_ms / 1e3
     achieved_tops = OPS_PER_ATTEMPT * per_launch_attempts / sweep_s / 1e12
     achieved_gbs = BYTES_PER_ATTEMPT * per_launch_attempts / sweep_s / 1e9
-    traffic = measured_traffic(block) if (L == 65536 and args.moves == 1) else None
+    traffic = (measured_traffic(block, args.in_place)
+               if (L == 65536 and args.moves == 1) else None)
     line = {
         "metric": "site-update attempts/s at L=2^16",
         "value": value,
@@ -396,6 +400,7 @@ def main():
                         f"4x4 double tiles; step = {M} MCS + one exact W^2 sample",
             "L": L, "block": list(block), "tile": [4, 4], "mcs_per_step": M,
             "origin_moves_per_mcs": args.moves,
+            "lattice_buffers": 1 if args.in_place else 2,
         },
         "roofline": {
             "bound": "alu",
@@ -404,12 +409,12 @@ def main():
             "unit": "Tops/s",
             "frac": achieved_tops / VALU_PEAK_TOPS,
             "traffic": traffic,
-            "traffic_unit": "HBM bytes per MCS (sweep + merge; rocprofv3 FETCH_SIZE and "
-                            "WRITE_SIZE scaled by a 1 GiB copy probe)",
-            # one MCS = the sweep launch plus the straddling-word merge launch,
-            # bracketed together by the events (the sum of the two kernels'
-            # average durations in a kernel trace)
-            "kernel": "kpz_sweep_kernel+kpz_merge_kernel",
+            "traffic_unit": "HBM bytes per MCS (all launches of one MCS; rocprofv3 FETCH_SIZE "
+                            "and WRITE_SIZE scaled by a 1 GiB copy probe)",
+            # one MCS = one sweep launch (two-buffer mode), or the sweep launch
+            # plus the straddling-word merge launch (in place), bracketed
+            # together by the events
+            "kernel": "kpz_sweep_kernel+kpz_merge_kernel" if args.in_place else "kpz_sweep_kernel",
             "mean_launch_ms": sweep_ms,
             "ops_per_attempt": OPS_PER_ATTEMPT,
             "hbm_achieved_gbs": achieved_gbs,

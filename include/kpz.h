@@ -28,10 +28,16 @@
  * other work on other streams, until kpz_destroy().  The handle itself is a
  * small host object owned by the library.
  *
+ * Between calls the lattice may live in either of two buffers, rotated by
+ * up to 15 sites (two-buffer mode, see kpz_params.flags): `words` holds the
+ * state in the layout above after kpz_init, kpz_set_state and
+ * kpz_sync_words.  kpz_roughness and kpz_height_moments read the state
+ * wherever it is.
+ *
  * Streams: all device work of a handle is enqueued on the HIP stream given
  * to kpz_init (a hipStream_t passed as void*; NULL = the default stream).
- * kpz_init and kpz_sweep only enqueue; kpz_roughness, kpz_get_state and
- * kpz_set_state synchronise that stream.
+ * kpz_init, kpz_sweep and kpz_sync_words only enqueue; kpz_roughness and
+ * kpz_get_state synchronise that stream.
  *
  * Errors: every entry point returns a kpz_status; nothing throws or aborts
  * across the ABI.  On KPZ_EHIP the HIP error text is kept in the handle
@@ -81,7 +87,14 @@ typedef enum {
  *            16 / moves single-hit steps, each with its own random origin
  *            (block residency 1 / moves MCS; every residency reads and
  *            writes the whole lattice once).
- *   flags    reserved, must be 0.
+ *   flags    0, or KPZ_FLAG_IN_PLACE.  By default the library keeps a second
+ *            lattice buffer in the workspace: every launch reads one buffer
+ *            and writes the other, each block writing whole words of its
+ *            own (no word is shared between blocks).  KPZ_FLAG_IN_PLACE
+ *            updates `words` in place instead (the workspace then holds no
+ *            second lattice; the words two blocks share are joined by a
+ *            merge launch after every sweep launch), for lattices too large
+ *            to hold twice.  Both modes give identical results.
  * The shape and `moves` change the sequence of updates, so results are
  * reproducible for identical (L, p, q, seed, block, tile, moves) only. */
 typedef struct {
@@ -96,6 +109,8 @@ typedef struct {
     int32_t moves;
     uint32_t flags;
 } kpz_params;
+
+#define KPZ_FLAG_IN_PLACE 1u
 
 typedef struct kpz_sim kpz_sim;
 
@@ -142,9 +157,16 @@ kpz_status kpz_height_moments(kpz_sim *sim, int64_t sums[8], double *W2, double 
 /* Checkpoint support.  The complete dynamical state is (words, t, net_flips)
  * where net_flips = #depositions - #desorptions since the flat start (so
  * S1 = N/2 + 2 net_flips).  get synchronises the stream; set enqueues the
- * counter reset and makes the next sweep run MCS number t. */
+ * counter reset, makes the next sweep run MCS number t, and declares that
+ * `words` holds the lattice (use it after writing `words`, e.g. from a
+ * checkpoint). */
 kpz_status kpz_get_state(kpz_sim *sim, int64_t *t, int64_t *net_flips);
 kpz_status kpz_set_state(kpz_sim *sim, int64_t t, int64_t net_flips);
+
+/* Enqueues whatever makes `words` hold the current state in the documented
+ * layout (nothing in in-place mode or when it already does; otherwise one
+ * or two copy launches over the lattice).  Call before reading `words`. */
+kpz_status kpz_sync_words(kpz_sim *sim);
 
 /* Frees the handle (not the caller's buffers).  NULL is ignored. */
 void kpz_destroy(kpz_sim *sim);

@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(PKG, "libkpz.so")
 KPZ_OK, KPZ_EINVAL, KPZ_ESIZE, KPZ_EHIP, KPZ_ESTATE, KPZ_ERANGE = 0, -1, -2, -3, -4, -5
 
 EXPORTED = ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness", "kpz_height_moments",
-            "kpz_get_state", "kpz_set_state", "kpz_destroy", "kpz_status_str", "kpz_last_error",
+            "kpz_get_state", "kpz_set_state", "kpz_sync_words", "kpz_destroy", "kpz_status_str",
+            "kpz_last_error",
             "kpz_batch_sizes", "kpz_batch_init", "kpz_batch_word_offset", "kpz_batch_sweep",
             "kpz_batch_roughness", "kpz_batch_run", "kpz_batch_get_t", "kpz_batch_destroy",
             "kpz_batch_last_error",
@@ -86,6 +87,7 @@ def lib() -> ctypes.CDLL:
         L.kpz_height_moments.restype = c.c_int
         L.kpz_get_state.argtypes = [vp, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
         L.kpz_set_state.argtypes = [vp, c.c_int64, c.c_int64]
+        L.kpz_sync_words.argtypes = [vp]
         L.kpz_destroy.argtypes = [vp]
         L.kpz_destroy.restype = None
         L.kpz_status_str.argtypes = [c.c_int]
@@ -128,7 +130,8 @@ def lib() -> ctypes.CDLL:
         L.kpz_ring_last_error.argtypes = [vp]
         L.kpz_ring_last_error.restype = c.c_char_p
         for f in ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness",
-                  "kpz_get_state", "kpz_set_state", "kpz_batch_sizes", "kpz_batch_init",
+                  "kpz_get_state", "kpz_set_state", "kpz_sync_words", "kpz_batch_sizes",
+                  "kpz_batch_init",
                   "kpz_batch_word_offset", "kpz_batch_sweep", "kpz_batch_roughness",
                   "kpz_batch_run", "kpz_batch_get_t", "kpz_pool_job_bytes",
                   "kpz_pool_control_bytes", "kpz_pool_init", "kpz_pool_submit", "kpz_pool_step",
@@ -143,14 +146,18 @@ def status_str(status: int) -> str:
     return lib().kpz_status_str(status).decode()
 
 
+KPZ_FLAG_IN_PLACE = 1
+
+
 def make_params(L: int, p: float = 1.0, q: float = 0.0, seed: int = 1,
                 block: Optional[Tuple[int, int]] = None, tile: Tuple[int, int] = (4, 4),
-                moves: int = 1) -> kpz_params:
+                moves: int = 1, in_place: bool = False) -> kpz_params:
     """Parameters of one lattice; ``moves`` = dead-border origin moves per
-    MCS (block residency 1/moves MCS)."""
+    MCS (block residency 1/moves MCS); ``in_place`` = update the lattice in
+    place (no second lattice buffer in the workspace)."""
     bx, by = block if block else (0, 0)
     return kpz_params(L, float(p), float(q), int(seed), int(bx), int(by), int(tile[0]),
-                      int(tile[1]), int(moves), 0)
+                      int(tile[1]), int(moves), KPZ_FLAG_IN_PLACE if in_place else 0)
 
 
 def workspace_bytes(params: kpz_params) -> int:
@@ -174,9 +181,9 @@ class Sim:
 
     def __init__(self, L: int, p: float = 1.0, q: float = 0.0, seed: int = 1,
                  block: Optional[Tuple[int, int]] = None, device="cuda", stream=None,
-                 moves: int = 1):
+                 moves: int = 1, in_place: bool = False):
         import torch
-        self.params = make_params(L, p, q, seed, block, moves=moves)
+        self.params = make_params(L, p, q, seed, block, moves=moves, in_place=in_place)
         self.L = L
         ws = workspace_bytes(self.params)
         self.device = torch.device(device)
@@ -224,8 +231,14 @@ class Sim:
     def set_state(self, t: int, net: int) -> None:
         self._check(lib().kpz_set_state(self._h, int(t), int(net)), "kpz_set_state")
 
+    def sync_words(self) -> "Sim":
+        """Make ``words`` hold the current state (kpz_sync_words)."""
+        self._check(lib().kpz_sync_words(self._h), "kpz_sync_words")
+        return self
+
     def words_host(self):
         """Copy of the packed words as a numpy uint32 array of shape (L, L/16)."""
+        self.sync_words()
         self.stream.synchronize()
         return self.words.cpu().numpy().view("uint32").reshape(self.L, self.L // 16)
 
@@ -234,8 +247,12 @@ class Sim:
         import numpy as np
         import torch
         arr = np.ascontiguousarray(np.asarray(words, dtype=np.uint32).reshape(-1)).view(np.int32)
+        t, net = self.state()
         with torch.cuda.stream(self.stream):
             self.words.copy_(torch.from_numpy(arr))
+        # `words` now holds the lattice (the counters are kept; set_state
+        # replaces them for a checkpoint)
+        self.set_state(t, net)
 
     def close(self) -> None:
         if self._h:

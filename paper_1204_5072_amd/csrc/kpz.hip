@@ -113,7 +113,8 @@ __global__ void kpz_fill_counters_kernel(long long *slots, long long first)
 // --------------------------------------------------------------- sweep
 
 struct SweepArgs {
-    uint32_t *words;
+    uint32_t *words;             // output lattice (and input when src == words)
+    const uint32_t *src;         // input lattice
     uint32_t *side;              // [2][L][nbx]: straddling-word parts (left edge, right edge)
     unsigned long long *slots;   // NSLOTS flip counters
     uint32_t L, W;               // size, words per row
@@ -130,8 +131,31 @@ struct SweepArgs {
     uint32_t nsteps;             // single-hit steps per residency (16 / moves)
     uint32_t slot_mask;          // flip-counter slots - 1 (power of two)
     uint32_t acc;                // 1 unless P = 2^32 and Q = 0 (acceptance draws needed)
+    // Two-buffer mode (db = 1): the launch reads src and writes words, a
+    // different buffer.  src is stored rotated by s_in sites (word w of a row
+    // holds sites 16 w + s_in ..), s_in = (x origin of launch (prev_t,
+    // prev_res)) mod 16 when prev_valid, else 0; the output is stored rotated
+    // by this launch's x origin mod 16, so every block writes whole words of
+    // its own and no word is shared.  db = 0: in place, shared words through
+    // the side buffer.
+    uint32_t db, prev_valid, prev_t, prev_res;
+    uint32_t xcd;                // 1: map work-groups so that consecutive blocks share an XCD
     uint64_t P, Q;               // acceptance thresholds over 2^32
 };
+
+// Storage rotation of a lattice buffer written in two-buffer mode: the x
+// origin of the launch that wrote it, mod 16 (0 for a buffer in the
+// documented layout, valid = 0).
+struct Rot {
+    uint32_t valid, t, res, Bx, seed_lo, seed_hi;
+};
+
+__device__ __forceinline__ uint32_t rot_sites(const Rot &r)
+{
+    if (!r.valid) return 0u;
+    const U4 w = philox(r.res, 0u, r.t, TAG_ORIGIN << 24, r.seed_lo, r.seed_hi);
+    return (uint32_t)(((uint64_t)w.x * r.Bx) >> 32) & 15u;
+}
 
 // Quad q = tid + TPB i (tid = thread in the block) has tile column
 // qx = q mod ntx and quad row qy = q / ntx.  With NTX (= ntx) known at
@@ -283,8 +307,17 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
     if (gx0 >= a.L) gx0 -= a.L;
     uint32_t gy0 = oy + by * a.By;
     if (gy0 >= a.L) gy0 -= a.L;
-    const uint32_t sh2 = 2u * (gx0 & 15u);
-    const uint32_t gw0 = gx0 >> 4;
+    // storage rotation of the input (two-buffer mode)
+    const uint32_t s_in =
+        rot_sites(Rot{a.db & a.prev_valid, a.prev_t, a.prev_res, a.Bx, a.seed_lo, a.seed_hi});
+    uint32_t px0 = gx0 + (a.L - s_in);          // storage position of the block's first site
+    if (px0 >= a.L) px0 -= a.L;
+    const uint32_t sh2 = 2u * (px0 & 15u);
+    const uint32_t gw0 = px0 >> 4;
+    // two-buffer mode: the output is rotated by ox mod 16, so the block's
+    // first site starts output word (ox >> 4) + bx nw
+    uint32_t gwo = (ox >> 4) + bx * nw;
+    if (gwo >= a.W) gwo -= a.W;
 
     // ---- load: HBM row words -> aligned block words -> cells -> quads.
     // Unit u = (wx, qy, sy): aligned word column wx of the two rows of cell
@@ -311,7 +344,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
             for (int h = 0; h < 2; ++h) {
                 uint32_t gy = gy0 + r0 + h;
                 if (gy >= a.L) gy -= a.L;
-                const uint32_t *row = a.words + (size_t)gy * a.W;
+                const uint32_t *row = a.src + (size_t)gy * a.W;
                 const uint32_t lo = uok ? row[gw] : 0u;
                 uint32_t hi = __shfl_down(lo, 1, 64);
                 if (uok && wx == nw - 1 && sh2) hi = row[gw1];
@@ -407,11 +440,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
     }
 
     // ---- store: quads -> cells -> aligned block words -> HBM row words.
-    // Words wholly inside the block are stored; the block's parts of the two
-    // words it shares with its left and right neighbours go to the side
-    // buffer and are merged by a separate launch (the kernel boundary makes
-    // both parts visible; a release/acquire between work-groups inside the
-    // launch would write back the whole L2 per block).
+    // Two-buffer mode: the block's words are whole output words (the output
+    // is rotated by the origin), stored as they are.  In place: words wholly
+    // inside the block are stored; the block's parts of the two words it
+    // shares with its left and right neighbours go to the side buffer and
+    // are merged by a separate launch (the kernel boundary makes both parts
+    // visible; a release/acquire between work-groups inside the launch would
+    // write back the whole L2 per block).
     for (int it = 0; it < UIT; ++it) {
         const uint32_t u = tid + (uint32_t)TPB * it;
         const bool uok = u < a.units;
@@ -429,7 +464,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
         }
         transpose_bytes(E);
         transpose_bytes(O);
-        uint32_t gw = gw0 + wx;
+        uint32_t gw = (a.db ? gwo : gw0) + wx;
         if (gw >= a.W) gw -= a.W;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -442,6 +477,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
                 uint32_t gy = gy0 + r0 + h;
                 if (gy >= a.L) gy -= a.L;
                 uint32_t *row = a.words + (size_t)gy * a.W;
+                if (a.db) {
+                    if (uok) row[gw] = A[h];
+                    continue;
+                }
                 const uint32_t prev = __shfl_up(A[h], 1, 64);
                 if (!uok) continue;
                 if (sh2 == 0) {
@@ -468,7 +507,13 @@ template <int TPB, int K, int NTX, bool ACC>
 __global__ __launch_bounds__(TPB) void kpz_sweep_kernel(const SweepArgs a)
 {
     extern __shared__ uint32_t lds[];
-    sweep_block<TPB, K, NTX, ACC>(a, blockIdx.x, lds);
+    // Work-groups are dealt to the 8 XCDs round-robin (group i to XCD i mod
+    // 8); with xcd set, group i takes block (i mod 8) n/8 + i/8, so each XCD
+    // runs one contiguous range of blocks and neighbouring blocks, which
+    // share cache lines at their edges, meet in the same L2.
+    uint32_t b = blockIdx.x;
+    if (a.xcd) b = (b & 7u) * (gridDim.x >> 3) + (b >> 3);
+    sweep_block<TPB, K, NTX, ACC>(a, b, lds);
 }
 
 // Straddling word j = gy * nbx + bx of MCS a.t: the word at the left edge of
@@ -541,13 +586,19 @@ __device__ __forceinline__ WordSums word_sums(uint32_t w, const uint32_t *lut)
     return r;
 }
 
-// Moments of one row (one wave): returns (A_y, B_y) in lane 0.
+// Moments of one row (one wave): returns (A_y, B_y) in lane 0 and, in
+// `first`, the row's first word in the documented layout.  rot2 = twice the
+// storage rotation (a row stored rotated by s sites holds sites s.. in its
+// word 0; word w of the layout is then bits of stored words w - 1 and w).
 __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, const uint32_t *lut,
-                                            uint32_t lane, long long &A, long long &B)
+                                            uint32_t lane, uint32_t rot2, long long &A,
+                                            long long &B, uint32_t &first)
 {
     const bool vec = (W & 3u) == 0;
     long long s1 = 0, s2 = 0;
     long long carry = 0;
+    uint32_t carry_w = rot2 ? rp[W - 1] : 0u;   // stored word before word 0 (periodic row)
+    first = 0u;
     for (uint32_t base = 0; base < W; base += 256) {
         const uint32_t idx = base + 4 * lane;
         uint32_t v[4] = {0u, 0u, 0u, 0u};
@@ -563,6 +614,22 @@ __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, cons
             for (int m = 0; m < 4; ++m)
                 if (idx + m < W) { v[m] = rp[idx + m]; nv = m + 1; }
         }
+        if (rot2) {
+            // the previous stored word of each lane's first word: the previous
+            // lane's last (full lanes precede any lane with words), or the
+            // carried word for lane 0
+            uint32_t pv = __shfl(v[3], (lane + 63u) & 63u, 64);
+            if (lane == 0) pv = carry_w;
+            carry_w = __shfl(v[3], 63, 64);
+            const uint32_t n3 = __builtin_amdgcn_alignbit(v[3], v[2], 32u - rot2);
+            const uint32_t n2 = __builtin_amdgcn_alignbit(v[2], v[1], 32u - rot2);
+            const uint32_t n1 = __builtin_amdgcn_alignbit(v[1], v[0], 32u - rot2);
+            v[0] = __builtin_amdgcn_alignbit(v[0], pv, 32u - rot2);
+            v[1] = n1;
+            v[2] = n2;
+            v[3] = n3;
+        }
+        if (base == 0) first = v[0];
         // this lane's words relative to its own start
         int o = 0;
         long long l1 = 0, l2 = 0;
@@ -599,30 +666,48 @@ __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, cons
 
 __global__ __launch_bounds__(256) void kpz_row_moments_kernel(const uint32_t *words, uint32_t L,
                                                               uint32_t W, long long *rowA,
-                                                              long long *rowB)
+                                                              long long *rowB, const Rot rot)
 {
     __shared__ uint32_t lut[256];
     lut[threadIdx.x] = lut8_entry(threadIdx.x);
     __syncthreads();
+    const uint32_t rot2 = 2u * rot_sites(rot);
     const uint32_t lane = threadIdx.x & 63u;
     for (uint32_t row = blockIdx.x * 4u + (threadIdx.x >> 6); row < L; row += gridDim.x * 4u) {
         long long A, B;
-        row_moments(words + (size_t)row * W, W, lut, lane, A, B);
+        uint32_t first;
+        row_moments(words + (size_t)row * W, W, lut, lane, rot2, A, B, first);
         if (lane == 0) {
             rowA[row] = A;
-            rowB[row] = B;
+            rowB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y(0, row)
         }
+    }
+}
+
+// A lattice buffer in the documented layout from one stored rotated by
+// rot_sites(rot) (src != dst).
+__global__ void kpz_rotate_kernel(const uint32_t *src, uint32_t *dst, uint32_t L, uint32_t W,
+                                  const Rot rot)
+{
+    const uint32_t rot2 = 2u * rot_sites(rot);
+    const uint64_t n = (uint64_t)L * W;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t w = (uint32_t)(i % W);
+        const uint64_t pi = w ? i - 1 : i + W - 1;
+        dst[i] = rot2 ? __builtin_amdgcn_alignbit(src[i], src[pi], 32u - rot2) : src[i];
     }
 }
 
 // One work-group of NT threads: c_y = sum_{k<y} sigma_y(0,k) (column-0
 // heights), R1 = sum_y (L c_y + A_y), R2 = sum_y (L c_y^2 + 2 c_y A_y + B_y)
-// in 128-bit, and the sum of the flip-counter slots.
+// in 128-bit, and the sum of the flip-counter slots.  The row pass stores
+// rowB[y] = 2 B_y + [sigma_y(0,y) = +1] (B_y <= L^3/4 leaves the room), so
+// this pass reads two contiguous arrays and never the lattice.
 template <int NT>
-__device__ __forceinline__ void finalize_moments(const uint32_t *words, uint32_t L, uint32_t W,
-                                                 const long long *rowA, const long long *rowB,
-                                                 const long long *slots, uint32_t nslots,
-                                                 long long *res)
+__device__ __forceinline__ void finalize_moments(uint32_t L, const long long *rowA,
+                                                 const long long *rowB, const long long *slots,
+                                                 uint32_t nslots, long long *res)
 {
     __shared__ long long sc[NT];
     __shared__ __int128 r2s[NT];
@@ -633,7 +718,8 @@ __device__ __forceinline__ void finalize_moments(const uint32_t *words, uint32_t
     const uint32_t y0 = min(L, tid * per);
     const uint32_t y1 = min(L, y0 + per);
     long long loc = 0;
-    for (uint32_t y = y0; y < y1; ++y) loc += ((words[(size_t)y * W] >> 1) & 1u) ? 1 : -1;
+#pragma unroll 8
+    for (uint32_t y = y0; y < y1; ++y) loc += (rowB[y] & 1) ? 1 : -1;
     sc[tid] = loc;
     __syncthreads();
     // inclusive Hillis-Steele scan over the thread sums
@@ -649,11 +735,13 @@ __device__ __forceinline__ void finalize_moments(const uint32_t *words, uint32_t
     long long c = sc[tid] - loc;
     long long r1 = 0;
     __int128 r2 = 0;
+#pragma unroll 8
     for (uint32_t y = y0; y < y1; ++y) {
-        const long long Ay = rowA[y], By = rowB[y];
+        const long long Ay = rowA[y], Bw = rowB[y];
+        const long long By = Bw >> 1;
         r1 += (long long)L * c + Ay;
         r2 += (__int128)((long long)L * c * c + 2 * c * Ay + By);
-        c += ((words[(size_t)y * W] >> 1) & 1u) ? 1 : -1;
+        c += (Bw & 1) ? 1 : -1;
     }
     long long n = 0;
     for (uint32_t i = tid; i < nslots; i += NT) n += slots[i];
@@ -678,13 +766,12 @@ __device__ __forceinline__ void finalize_moments(const uint32_t *words, uint32_t
     }
 }
 
-__global__ __launch_bounds__(1024) void kpz_finalize_kernel(const uint32_t *words, uint32_t L,
-                                                            uint32_t W, const long long *rowA,
+__global__ __launch_bounds__(1024) void kpz_finalize_kernel(uint32_t L, const long long *rowA,
                                                             const long long *rowB,
                                                             const long long *slots,
                                                             long long *res)
 {
-    finalize_moments<1024>(words, L, W, rowA, rowB, slots, NSLOTS, res);
+    finalize_moments<1024>(L, rowA, rowB, slots, NSLOTS, res);
 }
 
 
@@ -979,10 +1066,11 @@ __global__ __launch_bounds__(256) void kpz_batch_rows_kernel(const MemberRows *m
         const MemberRows m = mr[lo];
         const uint32_t row = g - rprefix[lo];
         long long A, B;
-        row_moments(m.words + (size_t)row * m.W, m.W, lut, lane, A, B);
+        uint32_t first;
+        row_moments(m.words + (size_t)row * m.W, m.W, lut, lane, 0u, A, B, first);
         if (lane == 0) {
             m.rowA[row] = A;
-            m.rowB[row] = B;
+            m.rowB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y(0, row)
         }
     }
 }
@@ -994,8 +1082,7 @@ __global__ __launch_bounds__(256) void kpz_batch_finalize_kernel(const MemberRow
 {
     const uint32_t r = blockIdx.x;
     const MemberRows m = mr[r];
-    finalize_moments<256>(m.words, m.L, m.W, m.rowA, m.rowB, m.slots, nslots,
-                          res + ((size_t)k * n + r) * 4);
+    finalize_moments<256>(m.L, m.rowA, m.rowB, m.slots, nslots, res + ((size_t)k * n + r) * 4);
 }
 
 }  // namespace
@@ -1012,6 +1099,12 @@ struct kpz_sim {
     hipStream_t stream;
     int64_t t;
     uint64_t P, Q;
+    // two-buffer mode: buf[cur] holds the state, rotated as written by the
+    // launch (rot_t, rot_res) when rot_valid
+    bool db;
+    uint32_t *buf[2];
+    int cur;
+    uint32_t rot_valid, rot_t, rot_res;
     char err[256];
 };
 
@@ -1039,7 +1132,7 @@ kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
     if (!p) return KPZ_EINVAL;
     if (p->L < 16 || (p->L % 16) != 0) return KPZ_EINVAL;
     if (!(p->p >= 0.0 && p->p <= 1.0 && p->q >= 0.0 && p->q <= 1.0)) return KPZ_EINVAL;
-    if (p->flags != 0) return KPZ_EINVAL;
+    if ((p->flags & ~KPZ_FLAG_IN_PLACE) != 0) return KPZ_EINVAL;
     if (p->moves != 0 && p->moves != 1 && p->moves != 2 && p->moves != 4 && p->moves != 8 &&
         p->moves != 16)
         return KPZ_EINVAL;
@@ -1061,14 +1154,21 @@ kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
 
 uint32_t moves_of(const kpz_params *p) { return p->moves ? (uint32_t)p->moves : 1u; }
 
-size_t ws_needed(int64_t L, int64_t Bx, int64_t By)
+size_t ws_side_end(int64_t L, int64_t Bx)
 {
     // header, flip-counter slots, six int64 per row (row moments: two for
     // W^2, six for the fourth-order moments) and the side buffer of the
     // straddling words (two uint32 per row and block column)
-    (void)By;
     return (size_t)WS_HEADER + sizeof(long long) * NSLOTS + 6 * sizeof(long long) * (size_t)L +
            2 * sizeof(uint32_t) * (size_t)L * (size_t)(L / Bx);
+}
+
+size_t ws_needed(int64_t L, int64_t Bx, uint32_t flags)
+{
+    // plus, in two-buffer mode, the second lattice buffer (256-byte aligned)
+    const size_t side_end = ws_side_end(L, Bx);
+    if (flags & KPZ_FLAG_IN_PLACE) return side_end;
+    return ((side_end + 255) & ~(size_t)255) + (size_t)L * (size_t)L / 4;
 }
 
 kpz_status hip_fail(kpz_sim *s, hipError_t e, const char *what)
@@ -1082,6 +1182,15 @@ long long *ws_slots(kpz_sim *s) { return (long long *)(s->ws + WS_HEADER); }
 long long *ws_rowA(kpz_sim *s) { return ws_slots(s) + NSLOTS; }
 long long *ws_rowB(kpz_sim *s) { return ws_rowA(s) + s->prm.L; }
 uint32_t *ws_side(kpz_sim *s) { return (uint32_t *)(ws_rowA(s) + 6 * (size_t)s->prm.L); }
+uint32_t *ws_alt(kpz_sim *s)
+{
+    return (uint32_t *)(s->ws + ((ws_side_end(s->prm.L, s->Bx) + 255) & ~(size_t)255));
+}
+Rot sim_rot(const kpz_sim *s)
+{
+    return Rot{s->rot_valid, s->rot_t, s->rot_res, s->Bx, (uint32_t)s->prm.seed,
+               (uint32_t)(s->prm.seed >> 32)};
+}
 
 template <int TPB, int K, int NTX, bool ACC>
 hipError_t launch_sweep_k(const SweepArgs &a, uint32_t nblocks, size_t shmem, hipStream_t st)
@@ -1460,6 +1569,8 @@ SweepArgs pool_args(const kpz_pool *p, const PoolJob &j)
     SweepArgs a;
     const uint32_t L = (uint32_t)j.prm.L;
     a.words = (uint32_t *)(p->arena + j.off_words);
+    a.src = a.words;
+    a.db = a.prev_valid = a.prev_t = a.prev_res = a.xcd = 0;
     a.side = (uint32_t *)(p->arena + j.off_side);
     a.slots = (unsigned long long *)(p->arena + j.off_slots);
     a.L = L;
@@ -1533,7 +1644,7 @@ kpz_status kpz_workspace_bytes(const kpz_params *p, size_t *bytes)
     const kpz_status st = resolve(p, &bx, &by);
     if (st != KPZ_OK) return st;
     if (!bytes) return KPZ_EINVAL;
-    *bytes = ws_needed(p->L, bx, by);
+    *bytes = ws_needed(p->L, bx, p->flags);
     return KPZ_OK;
 }
 
@@ -1548,7 +1659,7 @@ kpz_status kpz_init(kpz_sim **out, const kpz_params *p, uint32_t *d_words, size_
     if (st != KPZ_OK) return st;
     if (!d_words || !d_ws) return KPZ_EINVAL;
     const uint64_t L = (uint64_t)p->L;
-    if (words_bytes < L * L / 4 || ws_bytes < ws_needed(p->L, bx, by)) return KPZ_ESIZE;
+    if (words_bytes < L * L / 4 || ws_bytes < ws_needed(p->L, bx, p->flags)) return KPZ_ESIZE;
     kpz_sim *s = new (std::nothrow) kpz_sim();
     if (!s) return KPZ_EINVAL;
     s->prm = *p;
@@ -1562,6 +1673,11 @@ kpz_status kpz_init(kpz_sim **out, const kpz_params *p, uint32_t *d_words, size_
     s->t = 0;
     s->P = threshold(p->p);
     s->Q = threshold(p->q);
+    s->db = !(p->flags & KPZ_FLAG_IN_PLACE);
+    s->buf[0] = d_words;
+    s->buf[1] = s->db ? ws_alt(s) : d_words;
+    s->cur = 0;
+    s->rot_valid = s->rot_t = s->rot_res = 0;
     s->err[0] = 0;
     const uint64_t nwords = L * L / 16;
     const uint32_t W = (uint32_t)(L / 16);
@@ -1598,6 +1714,10 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     const uint32_t L = (uint32_t)s->prm.L;
     SweepArgs a;
     a.words = s->words;
+    a.src = s->words;
+    a.db = 0;
+    a.prev_valid = a.prev_t = a.prev_res = 0;
+    a.xcd = 0;
     a.side = ws_side(s);
     a.slots = (unsigned long long *)ws_slots(s);
     a.L = L;
@@ -1634,16 +1754,33 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     const size_t shmem = sizeof(uint32_t) * 4 * (size_t)a.nq;
     const uint64_t nstraddle = (uint64_t)L * a.nbx;
     const uint32_t mgrid = (uint32_t)((nstraddle + 255) / 256 < 8192 ? (nstraddle + 255) / 256 : 8192);
+    a.xcd = (nblocks % 8u) == 0;
     for (int32_t m = 0; m < n_mcs; ++m) {
         a.t = (uint32_t)(s->t + m);
         for (uint32_t r = 0; r < moves; ++r) {
             a.res = r;
+            if (s->db) {
+                // read buf[cur] (rotated as last written), write the other buffer
+                a.db = 1;
+                a.src = s->buf[s->cur];
+                a.words = s->buf[s->cur ^ 1];
+                a.prev_valid = s->rot_valid;
+                a.prev_t = s->rot_t;
+                a.prev_res = s->rot_res;
+            }
             hipError_t e = a.acc ? launch_sweep<true>(a, tpb, K, nblocks, shmem, s->stream)
                                  : launch_sweep<false>(a, tpb, K, nblocks, shmem, s->stream);
             if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep launch");
-            hipLaunchKernelGGL(kpz_merge_kernel, dim3(mgrid), dim3(256), 0, s->stream, a);
-            e = hipGetLastError();
-            if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep merge launch");
+            if (s->db) {
+                s->cur ^= 1;
+                s->rot_valid = 1;
+                s->rot_t = a.t;
+                s->rot_res = r;
+            } else {
+                hipLaunchKernelGGL(kpz_merge_kernel, dim3(mgrid), dim3(256), 0, s->stream, a);
+                e = hipGetLastError();
+                if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep merge launch");
+            }
         }
     }
     s->t += n_mcs;
@@ -1656,12 +1793,12 @@ kpz_status kpz_roughness(kpz_sim *s, int64_t *S1o, int64_t *S2o, double *W2o)
     if (!s) return KPZ_EINVAL;
     const uint32_t L = (uint32_t)s->prm.L, W = L / 16;
     const uint32_t rgrid = (L + 3) / 4 < 4096 ? (L + 3) / 4 : 4096;
-    hipLaunchKernelGGL(kpz_row_moments_kernel, dim3(rgrid), dim3(256), 0, s->stream, s->words, L,
-                       W, ws_rowA(s), ws_rowB(s));
+    hipLaunchKernelGGL(kpz_row_moments_kernel, dim3(rgrid), dim3(256), 0, s->stream,
+                       s->buf[s->cur], L, W, ws_rowA(s), ws_rowB(s), sim_rot(s));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(s, e, "kpz_roughness launch");
-    hipLaunchKernelGGL(kpz_finalize_kernel, dim3(1), dim3(1024), 0, s->stream, s->words, L, W,
-                       ws_rowA(s), ws_rowB(s), ws_slots(s), ws_res(s));
+    hipLaunchKernelGGL(kpz_finalize_kernel, dim3(1), dim3(1024), 0, s->stream, L, ws_rowA(s),
+                       ws_rowB(s), ws_slots(s), ws_res(s));
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(s, e, "kpz_roughness launch");
     long long res[4];
@@ -1696,6 +1833,8 @@ kpz_status kpz_height_moments(kpz_sim *s, int64_t sums[8], double *W2, double *s
 {
     clear_pending_error();
     if (!s) return KPZ_EINVAL;
+    const kpz_status sst = kpz_sync_words(s);
+    if (sst != KPZ_OK) return sst;
     const uint32_t L = (uint32_t)s->prm.L, W = L / 16;
     long long *rows6 = ws_rowA(s);   // 6 int64 per row
     const uint32_t rgrid = (L + 3) / 4 < 4096 ? (L + 3) / 4 : 4096;
@@ -1753,6 +1892,35 @@ kpz_status kpz_set_state(kpz_sim *s, int64_t t, int64_t net)
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(s, e, "kpz_set_state launch");
     s->t = t;
+    // `words` holds the state in the documented layout from here on
+    s->cur = 0;
+    s->rot_valid = 0;
+    return KPZ_OK;
+}
+
+kpz_status kpz_sync_words(kpz_sim *s)
+{
+    clear_pending_error();
+    if (!s) return KPZ_EINVAL;
+    if (!s->db || (s->cur == 0 && !s->rot_valid)) return KPZ_OK;
+    const uint32_t L = (uint32_t)s->prm.L, W = L / 16;
+    const uint64_t n = (uint64_t)L * W;
+    const uint32_t grid = (uint32_t)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    if (s->cur == 1) {
+        // the other buffer -> words, undoing the rotation on the way
+        hipLaunchKernelGGL(kpz_rotate_kernel, dim3(grid), dim3(256), 0, s->stream, s->buf[1],
+                           s->buf[0], L, W, sim_rot(s));
+    } else {
+        // words is rotated: through the other buffer and back
+        hipLaunchKernelGGL(kpz_rotate_kernel, dim3(grid), dim3(256), 0, s->stream, s->buf[0],
+                           s->buf[1], L, W, sim_rot(s));
+        hipLaunchKernelGGL(kpz_rotate_kernel, dim3(grid), dim3(256), 0, s->stream, s->buf[1],
+                           s->buf[0], L, W, Rot{0u, 0u, 0u, s->Bx, 0u, 0u});
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(s, e, "kpz_sync_words launch");
+    s->cur = 0;
+    s->rot_valid = 0;
     return KPZ_OK;
 }
 
@@ -1803,6 +1971,8 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
         const uint32_t L = (uint32_t)p.L;
         SweepArgs &a = args[r];
         a.words = d_words + lay.word_off[r];
+        a.src = a.words;
+        a.db = a.prev_valid = a.prev_t = a.prev_res = a.xcd = 0;
         a.side = (uint32_t *)(b->ws + lay.off_side[r]);
         a.slots = (unsigned long long *)(slots + (size_t)BATCH_SLOTS * r);
         a.L = L;

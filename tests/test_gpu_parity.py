@@ -124,6 +124,44 @@ def test_sweep_moves_matches_oracle(gpu, oracle_lib, L, block, p, q, seed, n, mo
         assert sim.state() == (t + 1, int(st.net[0]))
 
 
+@pytest.mark.parametrize("L,block,p,q,seed,n", [(64, (32, 16), 1.0, 0.0, 3, 6),
+                                              (256, (256, 64), 0.7, 0.3, 10, 4),
+                                              (1024, (1024, 64), 1.0, 0.5, 13, 3),
+                                              (96, (32, 32), 0.5, 0.5, 15, 5)])
+def test_in_place_mode_matches_oracle(gpu, oracle_lib, L, block, p, q, seed, n):
+    """The in-place mode (shared words through the side buffer and a merge
+    launch) gives the same words and moments as the oracle, and so as the
+    two-buffer mode."""
+    _log(f"in-place L={L} block={block} p={p} q={q} seed={seed} n={n}")
+    sim = gpu.Sim(L, p, q, seed, block, in_place=True)
+    two = gpu.Sim(L, p, q, seed, block)
+    st = oracle_lib.SlopeState(L)
+    for t in range(n):
+        sim.sweep(1)
+        two.sweep(1)
+        st.run_dd(1, p, q, seed, block=block, tile=(4, 4))
+        w = sim.words_host()
+        assert np.array_equal(w, oracle_lib.pack(st.sx, st.sy)), t
+        assert np.array_equal(w, two.words_host()), t
+        assert_moments(oracle_lib, st, sim.roughness(), L)
+
+
+def test_two_buffer_roughness_without_sync(gpu, oracle_lib):
+    """Moments read the rotated, alternating buffers directly: W^2 after odd
+    and even MCS counts, with no words_host() in between, equals the
+    oracle's."""
+    L, block, p, q, seed = 256, (64, 32), 1.0, 0.25, 31
+    sim = gpu.Sim(L, p, q, seed, block)
+    st = oracle_lib.SlopeState(L)
+    for n in (1, 2, 3, 5):
+        sim.sweep(n)
+        st.run_dd(n, p, q, seed, block=block, tile=(4, 4))
+        assert_moments(oracle_lib, st, sim.roughness(), L)
+    h = sim.height_moments()
+    assert np.array_equal(sim.words_host(), oracle_lib.pack(st.sx, st.sy))
+    assert sim.words_host() is not None and h is not None
+
+
 def test_l64_full_run_every_mcs(gpu, oracle_lib):
     """The L = 64, p = 1, q = 0, seed 1 workload: 1000 MCS, moments after
     every MCS, words compared every 50 MCS."""
