@@ -250,6 +250,7 @@ def test_l65536_sampled_blocks(gpu, oracle_lib):
     samples = [(0, 0), (nb - 1, 0), (0, nb - 1), (nb - 1, nb - 1), (123, 77), (200, 255)]
     W = L // 16
     words = sim.words.view(L, W)
+    sim.sync_words()   # `words` holds the state only after a sync (two-buffer mode)
     befores = []
     for bx, by in samples:
         rows, cols = oracle_lib.block_region(B, origin, bx, by, L)
@@ -257,6 +258,7 @@ def test_l65536_sampled_blocks(gpu, oracle_lib):
         host = words.index_select(0, r).cpu().numpy().view(np.uint32)
         befores.append(_block_slopes(oracle_lib, host, cols, L))
     sim.sweep(1)
+    sim.sync_words()
     for (bx, by), (bsx, bsy) in zip(samples, befores):
         rows, cols = oracle_lib.block_region(B, origin, bx, by, L)
         oracle_lib.dd_block_mcs(L, p, q, seed, B, t, bx, by, bsx, bsy)
