@@ -213,6 +213,14 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
                           uint32_t *d_words, size_t words_bytes, void *d_workspace,
                           size_t workspace_bytes, void *stream);
 
+/* Enqueues whatever makes every member's lattice in the words buffer hold
+ * its current state in the documented layout.  Members with L <= 65536 are
+ * swept in two-buffer mode (the second buffers are in the workspace; the
+ * lattice may sit in either, rotated by up to 15 sites, between calls);
+ * if any member is larger or has KPZ_FLAG_IN_PLACE, all are swept in place.
+ * Call before reading the words buffer. */
+kpz_status kpz_batch_sync_words(kpz_batch *batch);
+
 /* Offset (in uint32 words) of member r's lattice inside the words buffer. */
 kpz_status kpz_batch_word_offset(const kpz_batch *batch, int32_t member, size_t *offset_words);
 

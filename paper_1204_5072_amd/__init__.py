@@ -26,7 +26,7 @@ EXPORTED = ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness", "kp
             "kpz_last_error",
             "kpz_batch_sizes", "kpz_batch_init", "kpz_batch_word_offset", "kpz_batch_sweep",
             "kpz_batch_roughness", "kpz_batch_run", "kpz_batch_get_t", "kpz_batch_destroy",
-            "kpz_batch_last_error",
+            "kpz_batch_last_error", "kpz_batch_sync_words",
             "kpz_pool_job_bytes", "kpz_pool_control_bytes", "kpz_pool_init", "kpz_pool_submit",
             "kpz_pool_step", "kpz_pool_poll", "kpz_pool_stats", "kpz_pool_destroy",
             "kpz_pool_last_error",
@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
         L.kpz_batch_roughness.argtypes = [vp, i64p, i64p, f64p]
         L.kpz_batch_run.argtypes = [vp, c.POINTER(c.c_int32), c.c_int32, i64p, i64p, f64p]
         L.kpz_batch_get_t.argtypes = [vp, i64p]
+        L.kpz_batch_sync_words.argtypes = [vp]
         L.kpz_batch_destroy.argtypes = [vp]
         L.kpz_batch_destroy.restype = None
         L.kpz_batch_last_error.argtypes = [vp]
@@ -133,7 +134,7 @@ def lib() -> ctypes.CDLL:
                   "kpz_get_state", "kpz_set_state", "kpz_sync_words", "kpz_batch_sizes",
                   "kpz_batch_init",
                   "kpz_batch_word_offset", "kpz_batch_sweep", "kpz_batch_roughness",
-                  "kpz_batch_run", "kpz_batch_get_t", "kpz_pool_job_bytes",
+                  "kpz_batch_run", "kpz_batch_get_t", "kpz_batch_sync_words", "kpz_pool_job_bytes",
                   "kpz_pool_control_bytes", "kpz_pool_init", "kpz_pool_submit", "kpz_pool_step",
                   "kpz_pool_poll", "kpz_pool_stats", "kpz_ring_workspace_bytes", "kpz_ring_init",
                   "kpz_ring_sweep", "kpz_ring_roughness", "kpz_ring_get_state"):
@@ -343,6 +344,7 @@ class Ensemble:
         self._check(lib().kpz_batch_word_offset(self._h, int(r), ctypes.byref(off)),
                     "kpz_batch_word_offset")
         L = self.members[r].L
+        self._check(lib().kpz_batch_sync_words(self._h), "kpz_batch_sync_words")
         self.stream.synchronize()
         w = self.words[off.value: off.value + L * L // 16]
         return w.cpu().numpy().view("uint32").reshape(L, L // 16)

@@ -140,6 +140,11 @@ struct SweepArgs {
     // the side buffer.
     uint32_t db, prev_valid, prev_t, prev_res;
     uint32_t xcd;                // 1: map work-groups so that consecutive blocks share an XCD
+    // ensemble members in two-buffer mode: buffer 0 is `words`, buffer 1 is
+    // `alt`; at the start of a call the state is in buffer cur0, rotated as
+    // written by launch (prev_t, prev_res) when prev_valid
+    uint32_t *alt;
+    uint32_t cur0;
     uint64_t P, Q;               // acceptance thresholds over 2^32
 };
 
@@ -973,16 +978,60 @@ __global__ __launch_bounds__(256) void kpz_mom4_finalize_kernel(const uint32_t *
 //
 // Many independent lattices ("members", each with its own L, p, q and seed,
 // one common block shape) advance together: one launch runs one MCS of
-// every member (all their blocks in one grid), one more merges their
-// straddling words.  Rounds are separated by kernel boundaries, which make
-// each round's words visible to the next at no extra cost.
+// every member (all their blocks in one grid); in-place members need one
+// more launch that merges their straddling words, two-buffer members none.
+// Rounds are separated by kernel boundaries, which make each round's words
+// visible to the next at no extra cost.
 
+// Moment pass inputs of one member.  With `state` set (ensembles) the
+// current buffer and its rotation come from the member's sweep arguments;
+// otherwise `words` is the current buffer and `rot` its rotation (pool jobs,
+// filled by the host).
 struct MemberRows {
     const uint32_t *words;
     long long *rowA, *rowB;
     const long long *slots;
     uint32_t L, W;
+    const SweepArgs *state;
+    Rot rot;
 };
+
+__device__ __forceinline__ const uint32_t *member_current(const MemberRows &m, Rot &rot)
+{
+    if (!m.state) {
+        rot = m.rot;
+        return m.words;
+    }
+    const SweepArgs &a = *m.state;
+    if (!a.db) {
+        rot = Rot{0u, 0u, 0u, a.Bx, 0u, 0u};
+        return a.words;
+    }
+    rot = Rot{a.prev_valid, a.prev_t, a.prev_res, a.Bx, a.seed_lo, a.seed_hi};
+    return a.cur0 ? a.alt : a.words;
+}
+
+// The arguments of launch (k, res) of a call for a member whose state at the
+// call's start is in `a` (two-buffer mode: which buffer to read and write,
+// and how the input is rotated).
+__device__ __forceinline__ void member_launch_args(SweepArgs &a, uint32_t k, uint32_t res)
+{
+    if (a.db) {
+        const uint32_t moves = 16u / a.nsteps;
+        const uint32_t n = k * moves + res;            // launches before this one
+        const uint32_t cur = a.cur0 ^ (n & 1u);
+        uint32_t *b0 = a.words, *b1 = a.alt;
+        a.src = cur ? b1 : b0;
+        a.words = cur ? b0 : b1;
+        if (n > 0) {
+            a.prev_valid = 1u;
+            a.prev_t = a.t + (n - 1) / moves;
+            a.prev_res = (n - 1) % moves;
+        }
+    }
+    a.t += k;
+    a.res = res;
+}
 
 // One round of the ensemble: every block of members [0, nmem) runs MCS
 // t_r + k (t_r = the member's t at the start of the call).  Block g of the
@@ -995,7 +1044,10 @@ __global__ __launch_bounds__(TPB) void kpz_batch_round_kernel(const SweepArgs *m
                                                               uint32_t res)
 {
     extern __shared__ uint32_t lds[];
-    const uint32_t g = blockIdx.x;
+    // XCD-aware order (the grid is padded to a multiple of 8): group i takes
+    // block (i mod 8) n/8 + i/8 of the concatenated members
+    const uint32_t g = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    if (g >= bprefix[nmem]) return;
     uint32_t lo = 0, hi = nmem;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
@@ -1004,8 +1056,7 @@ __global__ __launch_bounds__(TPB) void kpz_batch_round_kernel(const SweepArgs *m
     }
     const uint32_t r = __builtin_amdgcn_readfirstlane(lo);
     SweepArgs a = members[r];
-    a.t += k;
-    a.res = res;
+    member_launch_args(a, k, res);
     const uint32_t b = g - bprefix[r];
     if (a.acc) sweep_block<TPB, K, NTX, true>(a, b, lds);
     else sweep_block<TPB, K, NTX, false>(a, b, lds);
@@ -1026,6 +1077,7 @@ __global__ void kpz_batch_merge_kernel(const SweepArgs *members, const unsigned 
             else hi = mid;
         }
         SweepArgs a = members[lo];
+        if (a.db) continue;                       // two-buffer members share no words
         a.t += k;
         a.res = res;
         const uint32_t ox = origin_x(a);
@@ -1042,8 +1094,58 @@ __global__ void kpz_zero_kernel(uint32_t *p, uint64_t n)
 
 __global__ void kpz_batch_advance_kernel(SweepArgs *members, uint32_t n, uint32_t dt)
 {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        members[i].t += dt;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        SweepArgs &a = members[i];
+        if (a.db && dt) {
+            const uint32_t moves = 16u / a.nsteps;
+            a.cur0 ^= (dt * moves) & 1u;
+            a.prev_valid = 1u;
+            a.prev_t = a.t + dt - 1u;
+            a.prev_res = moves - 1u;
+        }
+        a.t += dt;
+    }
+}
+
+// Ensemble members' `words` in the documented layout: one work-group per
+// row (rows numbered over the members as in the moment pass) copies the
+// current buffer's row through LDS, undoing the rotation; then
+// kpz_batch_settle_kernel marks every member as held in buffer 0.
+__global__ __launch_bounds__(256) void kpz_batch_sync_kernel(const MemberRows *mr,
+                                                             const uint32_t *rprefix, uint32_t n)
+{
+    extern __shared__ uint32_t rowbuf[];
+    const uint32_t total = rprefix[n];
+    for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
+        uint32_t lo = 0, hi = n;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (rprefix[mid] <= g) lo = mid;
+            else hi = mid;
+        }
+        const MemberRows m = mr[lo];
+        const uint32_t row = g - rprefix[lo];
+        Rot rot;
+        const uint32_t *cur = member_current(m, rot);
+        const uint32_t rot2 = 2u * rot_sites(rot);
+        const uint32_t *src = cur + (size_t)row * m.W;
+        for (uint32_t w = threadIdx.x; w < m.W; w += blockDim.x) rowbuf[w] = src[w];
+        __syncthreads();
+        uint32_t *dst = (m.state ? m.state->words : (uint32_t *)m.words) + (size_t)row * m.W;
+        for (uint32_t w = threadIdx.x; w < m.W; w += blockDim.x) {
+            const uint32_t pv = rowbuf[w ? w - 1 : m.W - 1];
+            dst[w] = rot2 ? __builtin_amdgcn_alignbit(rowbuf[w], pv, 32u - rot2) : rowbuf[w];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void kpz_batch_settle_kernel(SweepArgs *members, uint32_t n)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        members[i].cur0 = 0u;
+        members[i].prev_valid = 0u;
+    }
 }
 
 // Row moments of all members: rows numbered consecutively over the members
@@ -1065,9 +1167,11 @@ __global__ __launch_bounds__(256) void kpz_batch_rows_kernel(const MemberRows *m
         }
         const MemberRows m = mr[lo];
         const uint32_t row = g - rprefix[lo];
+        Rot rot;
+        const uint32_t *cur = member_current(m, rot);
         long long A, B;
         uint32_t first;
-        row_moments(m.words + (size_t)row * m.W, m.W, lut, lane, 0u, A, B, first);
+        row_moments(cur + (size_t)row * m.W, m.W, lut, lane, 2u * rot_sites(rot), A, B, first);
         if (lane == 0) {
             m.rowA[row] = A;
             m.rowB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y(0, row)
@@ -1251,6 +1355,9 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct BatchLayout {
     uint32_t Bx, By;
     uint32_t moves;                 // origin moves per MCS, common to all members
+    bool db;                        // two-buffer members (every L <= 65536)
+    uint32_t maxW;                  // longest row (words)
+    std::vector<size_t> off_alt;    // second lattice buffer of each member (two-buffer mode)
     std::vector<size_t> word_off;   // per member, in words
     size_t words_bytes;
     size_t off_members, off_bprefix, off_sprefix, off_rprefix, off_rows, off_res, off_slots;
@@ -1289,6 +1396,12 @@ kpz_status batch_layout(const kpz_params *m, int32_t n, BatchLayout *lay)
         w += align256((size_t)m[r].L * m[r].L / 4) / 4;
     }
     lay->words_bytes = 4 * w;
+    lay->db = true;
+    lay->maxW = 0;
+    for (int32_t r = 0; r < n; ++r) {
+        if (m[r].L > 65536 || (m[r].flags & KPZ_FLAG_IN_PLACE)) lay->db = false;
+        lay->maxW = std::max(lay->maxW, (uint32_t)(m[r].L / 16));
+    }
     size_t o = 0;
     lay->off_members = o;  o = align256(o + sizeof(SweepArgs) * (size_t)n);
     lay->off_bprefix = o;  o = align256(o + 4 * ((size_t)n + 1));
@@ -1306,6 +1419,12 @@ kpz_status batch_layout(const kpz_params *m, int32_t n, BatchLayout *lay)
         lay->off_rowB[r] = o; o = align256(o + 8 * L);
         lay->off_side[r] = o; o = align256(o + 4 * 2 * L * (L / lay->Bx));
     }
+    lay->off_alt.assign(n, 0);
+    if (lay->db)
+        for (int32_t r = 0; r < n; ++r) {
+            const size_t L = (size_t)m[r].L;
+            lay->off_alt[r] = o; o = align256(o + L * L / 4);
+        }
     lay->ws_bytes = o;
     return KPZ_OK;
 }
@@ -1353,11 +1472,12 @@ void round_launch_k(const RoundShape &rs, uint32_t grid, hipStream_t st, const S
 // One round (residency res of MCS k of the call) of members [0, nmem) plus
 // the merge of their straddling words.  grid = bprefix[nmem], mwords =
 // sprefix[nmem].
-hipError_t round_launch(const RoundShape &rs, uint32_t grid, uint64_t mwords, hipStream_t st,
+hipError_t round_launch(const RoundShape &rs, uint32_t nblocks, uint64_t mwords, hipStream_t st,
                         const SweepArgs *members, const uint32_t *bprefix,
                         const unsigned long long *sprefix, uint32_t nmem, uint32_t k,
-                        uint32_t res)
+                        uint32_t res, bool merge)
 {
+    const uint32_t grid = (nblocks + 7u) & ~7u;   // the kernel's XCD map needs a multiple of 8
     if (rs.tpb == 256) {
         if (rs.K == 1) round_launch_k<256, 1>(rs, grid, st, members, bprefix, nmem, k, res);
         else if (rs.K == 2) round_launch_k<256, 2>(rs, grid, st, members, bprefix, nmem, k, res);
@@ -1367,7 +1487,7 @@ hipError_t round_launch(const RoundShape &rs, uint32_t grid, uint64_t mwords, hi
         else round_launch_k<64, 2>(rs, grid, st, members, bprefix, nmem, k, res);
     }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !merge) return e;
     const uint32_t mgrid = (uint32_t)((mwords + 255) / 256 < 8192 ? (mwords + 255) / 256 : 8192);
     hipLaunchKernelGGL(kpz_batch_merge_kernel, dim3(mgrid), dim3(256), 0, st, members, sprefix,
                        nmem, k, res);
@@ -1412,7 +1532,7 @@ kpz_status batch_sweep_on(kpz_batch *b, int32_t n_mcs, hipStream_t st)
         for (uint32_t r = 0; r < b->lay.moves; ++r) {
             const hipError_t e = round_launch(b->rs, b->per_round, b->merge_words, st,
                                               batch_members(b), bp, sp, (uint32_t)b->n,
-                                              (uint32_t)k, r);
+                                              (uint32_t)k, r, !b->lay.db);
             if (e != hipSuccess) return batch_fail(b, e, "kpz_batch_sweep launch");
         }
     hipLaunchKernelGGL(kpz_batch_advance_kernel, dim3((b->n + 255) / 256), dim3(256), 0, st,
@@ -1473,7 +1593,10 @@ struct PoolJob {
     kpz_params prm;
     int64_t t, n_mcs;
     size_t off, bytes;        // arena extent
-    size_t off_words, off_slots, off_rowA, off_rowB, off_side;
+    size_t off_words, off_slots, off_rowA, off_rowB, off_alt;
+    // two-buffer state: the lattice is in buffer cur (0 = words, 1 = alt),
+    // rotated as written by launch (rot_t, rot_res) when rot_valid
+    uint32_t cur, rot_valid, rot_t, rot_res;
 };
 
 struct PoolResult {
@@ -1482,10 +1605,13 @@ struct PoolResult {
     kpz_status st;
 };
 
+// a job: its lattice twice (two-buffer mode), flip counters, row moments
 size_t pool_job_bytes_raw(int64_t L, uint32_t Bx, uint32_t By)
 {
-    return align256((size_t)L * L / 4) + align256(sizeof(long long) * BATCH_SLOTS) +
-           2 * align256(8 * (size_t)L) + align256(4 * 2 * (size_t)L * (size_t)(L / Bx));
+    (void)Bx;
+    (void)By;
+    return 2 * align256((size_t)L * L / 4) + align256(sizeof(long long) * BATCH_SLOTS) +
+           2 * align256(8 * (size_t)L);
 }
 
 struct PoolCtl {
@@ -1570,8 +1696,14 @@ SweepArgs pool_args(const kpz_pool *p, const PoolJob &j)
     const uint32_t L = (uint32_t)j.prm.L;
     a.words = (uint32_t *)(p->arena + j.off_words);
     a.src = a.words;
-    a.db = a.prev_valid = a.prev_t = a.prev_res = a.xcd = 0;
-    a.side = (uint32_t *)(p->arena + j.off_side);
+    a.db = 1;
+    a.alt = (uint32_t *)(p->arena + j.off_alt);
+    a.cur0 = j.cur;
+    a.prev_valid = j.rot_valid;
+    a.prev_t = j.rot_t;
+    a.prev_res = j.rot_res;
+    a.xcd = 0;
+    a.side = nullptr;
     a.slots = (unsigned long long *)(p->arena + j.off_slots);
     a.L = L;
     a.W = L / 16;
@@ -1972,7 +2104,10 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
         SweepArgs &a = args[r];
         a.words = d_words + lay.word_off[r];
         a.src = a.words;
-        a.db = a.prev_valid = a.prev_t = a.prev_res = a.xcd = 0;
+        a.db = lay.db ? 1u : 0u;
+        a.prev_valid = a.prev_t = a.prev_res = a.xcd = 0;
+        a.alt = lay.db ? (uint32_t *)(b->ws + lay.off_alt[r]) : nullptr;
+        a.cur0 = 0;
         a.side = (uint32_t *)(b->ws + lay.off_side[r]);
         a.slots = (unsigned long long *)(slots + (size_t)BATCH_SLOTS * r);
         a.L = L;
@@ -2004,6 +2139,8 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
         rows[r].slots = slots + (size_t)BATCH_SLOTS * r;
         rows[r].L = L;
         rows[r].W = L / 16;
+        rows[r].state = (const SweepArgs *)(b->ws + lay.off_members) + r;
+        rows[r].rot = Rot{0u, 0u, 0u, lay.Bx, 0u, 0u};
         bprefix[r + 1] = bprefix[r] + a.nbx * a.nby;
         sprefix[r + 1] = sprefix[r] + (unsigned long long)L * a.nbx;
         rprefix[r + 1] = rprefix[r] + L;
@@ -2055,6 +2192,22 @@ kpz_status kpz_batch_word_offset(const kpz_batch *b, int32_t r, size_t *off)
 {
     if (!b || !off || r < 0 || r >= b->n) return KPZ_EINVAL;
     *off = b->lay.word_off[r];
+    return KPZ_OK;
+}
+
+kpz_status kpz_batch_sync_words(kpz_batch *b)
+{
+    clear_pending_error();
+    if (!b) return KPZ_EINVAL;
+    if (!b->lay.db) return KPZ_OK;
+    const uint32_t grid = b->total_rows < 8192 ? b->total_rows : 8192;
+    hipLaunchKernelGGL(kpz_batch_sync_kernel, dim3(grid), dim3(256), sizeof(uint32_t) * b->lay.maxW,
+                       b->stream, (const MemberRows *)(b->ws + b->lay.off_rows),
+                       (const uint32_t *)(b->ws + b->lay.off_rprefix), (uint32_t)b->n);
+    hipLaunchKernelGGL(kpz_batch_settle_kernel, dim3((b->n + 255) / 256), dim3(256), 0, b->stream,
+                       batch_members(b), (uint32_t)b->n);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return batch_fail(b, e, "kpz_batch_sync_words launch");
     return KPZ_OK;
 }
 
@@ -2246,7 +2399,8 @@ kpz_status kpz_pool_submit(kpz_pool *p, const kpz_params *job, int64_t n_mcs, in
     j.off_slots = o; o += align256(sizeof(long long) * BATCH_SLOTS);
     j.off_rowA = o;  o += align256(8 * L);
     j.off_rowB = o;  o += align256(8 * L);
-    j.off_side = o;
+    j.off_alt = o;
+    j.cur = j.rot_valid = j.rot_t = j.rot_res = 0;
     const uint32_t W = (uint32_t)(L / 16);
     uint32_t *words = (uint32_t *)(p->arena + j.off_words);
     if (W % 4 == 0) {
@@ -2316,10 +2470,18 @@ kpz_status kpz_pool_step(kpz_pool *p, int32_t quantum, int32_t *n_active)
     for (uint32_t k = 0; k < rounds[0]; ++k) {
         while (m > 0 && rounds[m - 1] <= k) --m;
         e = round_launch(p->rs, bprefix[m], sprefix[m], p->stream, d_members, d_bprefix, d_sprefix,
-                         (uint32_t)m, k, 0u);
+                         (uint32_t)m, k, 0u, false);
         if (e != hipSuccess) return pool_fail(p, e, "kpz_pool_step launch");
     }
-    for (size_t k = 0; k < n; ++k) p->jobs[order[k]].t += rounds[k];
+    for (size_t k = 0; k < n; ++k) {
+        PoolJob &j = p->jobs[order[k]];
+        // two-buffer state after rounds[k] launches
+        j.cur ^= rounds[k] & 1u;
+        j.rot_valid = 1;
+        j.rot_t = (uint32_t)(j.t + rounds[k] - 1);
+        j.rot_res = 0;
+        j.t += rounds[k];
+    }
     // sample and release the jobs that reached their n_mcs
     std::vector<size_t> fin;
     for (size_t i = 0; i < n; ++i)
@@ -2329,7 +2491,10 @@ kpz_status kpz_pool_step(kpz_pool *p, int32_t quantum, int32_t *n_active)
         std::vector<uint32_t> rprefix(fin.size() + 1, 0);
         for (size_t f = 0; f < fin.size(); ++f) {
             const PoolJob &j = p->jobs[fin[f]];
-            rows[f].words = (const uint32_t *)(p->arena + j.off_words);
+            rows[f].words = (const uint32_t *)(p->arena + (j.cur ? j.off_alt : j.off_words));
+            rows[f].state = nullptr;
+            rows[f].rot = Rot{j.rot_valid, j.rot_t, j.rot_res, p->Bx, (uint32_t)j.prm.seed,
+                              (uint32_t)(j.prm.seed >> 32)};
             rows[f].rowA = (long long *)(p->arena + j.off_rowA);
             rows[f].rowB = (long long *)(p->arena + j.off_rowB);
             rows[f].slots = (const long long *)(p->arena + j.off_slots);

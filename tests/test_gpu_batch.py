@@ -107,3 +107,25 @@ def test_batch_members_with_origin_moves_equal_single_runs(gpu):
         assert np.array_equal(ens.member_words(r), sim.words_host()), r
         mm = sim.roughness()
         assert (int(S1[r]), int(S2[r]), float(W2[r])) == (mm.S1, mm.S2, mm.W2), r
+
+
+def test_batch_in_place_equals_two_buffer(gpu):
+    """A batch swept in place (one member flagged in place) and the same
+    batch in two-buffer mode give identical lattices and moments."""
+    Ls, qs = [256, 512, 256], [0.0, 0.25, 0.5]
+    two = gpu.Ensemble(_mix(gpu, Ls, qs, (256, 64)))
+    inp_members = _mix(gpu, Ls, qs, (256, 64))
+    inp_members[1].flags = gpu.KPZ_FLAG_IN_PLACE
+    inp = gpu.Ensemble(inp_members)
+    for n in (1, 2, 3):
+        two.sweep(n)
+        inp.sweep(n)
+        a, b = two.roughness(), inp.roughness()
+        assert [list(x) for x in a] == [list(x) for x in b], n
+    for r in range(len(Ls)):
+        assert np.array_equal(two.member_words(r), inp.member_words(r)), r
+    # syncing twice, and sweeping on after a sync, stay consistent
+    two.sweep(1)
+    inp.sweep(1)
+    for r in range(len(Ls)):
+        assert np.array_equal(two.member_words(r), inp.member_words(r)), r
