@@ -83,9 +83,13 @@ def lib():
                                         c.c_uint32, c.c_int, i8p, i64p]
         L.or_dd1d_origin.argtypes = [c.c_uint64, c.c_uint32, c.c_int]
         L.or_flat1d.argtypes = [c.c_int, i8p]
+        L.or_dt_run.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
+                                c.c_int, c.c_int, c.c_int, c.c_int,
+                                c.c_uint32, c.c_int, i8p, i8p, i64p, i64p, c.c_int]
+        L.or_dt_perm.argtypes = [c.c_uint64, c.c_uint32, c.POINTER(c.c_int * 4)]
         for f in ("or_flat", "or_rs_heights_run", "or_rs_slopes_run", "or_dd_run", "or_rs1d_run",
                   "or_dd_block_mcs", "or_dd1d_run", "or_dd1d_block_mcs", "or_dd1d_origin",
-                  "or_flat1d"):
+                  "or_flat1d", "or_dt_run", "or_dt_perm"):
             getattr(L, f).restype = c.c_int
         _lib = L
     return _lib
@@ -112,6 +116,7 @@ def draw(seed: int, tag: int, t: int, idx: int, sub: int) -> np.ndarray:
 
 TAG_ORIGIN, TAG_SET, TAG_SITE, TAG_ACC1, TAG_ACC2, TAG_RS, TAG_RS1D = 1, 2, 3, 4, 5, 6, 7
 TAG_ORIGIN1D, TAG_SET1D, TAG_SITE1D, TAG_ACC1D, TAG_ACC1D2 = 8, 9, 10, 11, 12
+TAG_DTORDER = 13
 
 
 # ------------------------------------------------------------------ state
@@ -150,6 +155,16 @@ class SlopeState:
         self.t += n_mcs
         return self
 
+    def run_dt(self, n_mcs: int, p: float, q: float, seed: int, block, tile=(4, 4),
+               check: bool = False) -> "SlopeState":
+        """n_mcs MCS with double tiling at the device layer too (the four
+        block sets in a random order per MCS, no dead border)."""
+        rc = lib().or_dt_run(self.L, p, q, seed, block[0], block[1], tile[0], tile[1], self.t,
+                             n_mcs, self.sx, self.sy, self.h00, self.net, int(check))
+        _check(rc, "dt_run")
+        self.t += n_mcs
+        return self
+
     def run_rs(self, n_mcs: int, p: float, q: float, seed: int) -> "SlopeState":
         rc = lib().or_rs_slopes_run(self.L, p, q, seed, self.t, n_mcs, self.sx, self.sy,
                                     self.h00, self.net)
@@ -163,6 +178,13 @@ class SlopeState:
 
     def moments(self):
         return moments(self.heights())
+
+
+def dt_perm(seed: int, t: int):
+    """Order of the four block sets in MCS t (double tiling at the device layer)."""
+    arr = (ctypes.c_int * 4)()
+    lib().or_dt_perm(seed, t, ctypes.byref(arr))
+    return list(arr)
 
 
 def flat_heights(L: int) -> np.ndarray:

@@ -236,6 +236,60 @@ class SmallChain:
                 total += np.linalg.matrix_power(step, S // moves)
         return np.linalg.matrix_power(total / (Bx * By), moves)
 
+    def dt_mcs(self, p: float, q: float, block, tile) -> np.ndarray:
+        """One MCS with double tiling at the device layer: uniform origin,
+        the four block sets (bx mod 2, by mod 2) in a uniformly random order,
+        each block of the active set making S single-hit steps with no dead
+        sites (blocks of one set share no slope, so their operators
+        commute)."""
+        import itertools
+        L = self.L
+        Bx, By = block
+        Tx, Ty = tile
+        nbx, nby = L // Bx, L // By
+        assert nbx % 2 == 0 and nby % 2 == 0
+        ntx, nty = Bx // Tx, By // Ty
+        cx, cy = Tx // 2, Ty // 2
+        S = Tx * Ty
+        ops = {s: self.site_operator(s, p, q) for s in range(self.N)}
+        I = np.eye(self.n)
+        total = np.zeros((self.n, self.n))
+        for oy in range(By):
+            for ox in range(Bx):
+                block_ops = {}
+                for by in range(nby):
+                    for bx in range(nbx):
+                        bstep = np.zeros((self.n, self.n))
+                        for st in range(4):
+                            ssx, ssy = st & 1, st >> 1
+                            M = I.copy()
+                            for ty in range(nty):
+                                for tx in range(ntx):
+                                    cell = np.zeros((self.n, self.n))
+                                    for ry in range(cy):
+                                        for rx in range(cx):
+                                            lx = tx * Tx + ssx * cx + rx
+                                            ly = ty * Ty + ssy * cy + ry
+                                            gx = (ox + bx * Bx + lx) % L
+                                            gy = (oy + by * By + ly) % L
+                                            cell += ops[gy * L + gx]
+                                    M = M @ (cell / (cx * cy))
+                            bstep += M / 4.0
+                        block_ops[(bx, by)] = np.linalg.matrix_power(bstep, S)
+                phase = {}
+                for c in range(4):
+                    M = I.copy()
+                    for (bx, by), op in block_ops.items():
+                        if (bx & 1) + 2 * (by & 1) == c:
+                            M = M @ op
+                    phase[c] = M
+                for perm in itertools.permutations(range(4)):
+                    M = I.copy()
+                    for c in perm:
+                        M = M @ phase[c]
+                    total += M / 24.0
+        return total / (Bx * By)
+
     def expected_w2(self, T: np.ndarray, times) -> dict:
         pi = np.zeros(self.n)
         pi[self.flat] = 1.0

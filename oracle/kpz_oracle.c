@@ -618,3 +618,133 @@ int or_flat1d(int L, int8_t *s)
     for (int i = 0; i < L; ++i) s[i] = (i & 1) ? -1 : 1;
     return OR_OK;
 }
+
+/* ------------------------------- double tiling at both layers (2+1-d) */
+
+/*
+ * The device layer as double tiling instead of dead borders (Sec. 3: the
+ * blocks are bisected in both directions into 2^2 sets of non-interacting
+ * blocks, the sets updated in turn in a sequence randomized every MCS; the
+ * paper uses this for its KMC code and notes that KPZ inherited the
+ * work-group scheme from it):
+ *
+ * MCS t: origin (ox, oy) from (ORIGIN, t, 0, 0) as for dead borders, so the
+ * block boundaries move every MCS; block (bx, by) covers the same sites as
+ * there, with nbx, nby even.  The four block sets c = (bx mod 2) + 2 (by
+ * mod 2) run in the order perm[floor(w0 * 24 / 2^32)] of draw
+ * (DTORDER, t, 0, 0), perm = the 24 orderings of (0, 1, 2, 3) in
+ * lexicographic order.  In its phase every block of the set makes its 16
+ * single-hit steps with the same set, site and acceptance draws as under
+ * dead borders, and no site is dead: an update at the block's left column
+ * or bottom row flips a slope stored at a site of the (idle) block to the
+ * left or below.  Blocks of one set share no slope, so a phase is the same
+ * whether its blocks run in parallel or one after the other.
+ */
+#define OR_TAG_DTORDER 13u
+
+static void dt_perm(uint32_t w0, int perm[4])
+{
+    int idx = (int)(((uint64_t)w0 * 24u) >> 32);
+    int pool[4] = { 0, 1, 2, 3 };
+    int n = 4;
+    for (int i = 0; i < 4; ++i) {
+        int f = 1;
+        for (int k = 2; k < n; ++k) f *= k;          /* (n-1)! */
+        const int pick = idx / f;
+        idx %= f;
+        perm[i] = pool[pick];
+        for (int k = pick; k < n - 1; ++k) pool[k] = pool[k + 1];
+        --n;
+    }
+}
+
+int or_dt_perm(uint64_t seed, uint32_t t, int perm[4])
+{
+    uint32_t w[4];
+    or_draw(seed, OR_TAG_DTORDER, t, 0, 0, w);
+    dt_perm(w[0], perm);
+    return OR_OK;
+}
+
+int or_dt_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, int Ty,
+              uint32_t t0, int n_mcs, int8_t *sx, int8_t *sy, int64_t *h00, int64_t *net,
+              int check)
+{
+    if (!dd_validate(L, Bx, By, Tx, Ty, 1) || n_mcs < 0) return OR_EINVAL;
+    const int nbx = L / Bx, nby = L / By;
+    if (nbx < 2 || nby < 2 || (nbx & 1) || (nby & 1)) return OR_EINVAL;
+    const int ntx = Bx / Tx, nty = By / Ty;
+    const int H = nty >= 4 ? nty / 4 : 1;
+    const uint64_t nq = (uint64_t)ntx * (uint64_t)H;
+    const int cx = Tx / 2, cy = Ty / 2;
+    const int S = Tx * Ty;
+    const int has_site_draw = (cx * cy == 4);
+    const uint64_t P = threshold(p), Q = threshold(q);
+    const uint64_t FULL = (uint64_t)1 << 32;
+    int64_t *stamp = check ? (int64_t *)malloc(sizeof(int64_t) * (size_t)L * (size_t)L) : NULL;
+    if (check && !stamp) return OR_ENOMEM;
+    if (check)
+        for (size_t i = 0; i < (size_t)L * (size_t)L; ++i) stamp[i] = -1;
+    int64_t step_id = 0;
+    int status = OR_OK;
+    uint32_t w[4];
+    for (int m = 0; m < n_mcs && status == OR_OK; ++m) {
+        const uint32_t t = t0 + (uint32_t)m;
+        or_draw(seed, OR_TAG_ORIGIN, t, 0, 0, w);
+        const int ox = (int)(((uint64_t)w[0] * (uint64_t)Bx) >> 32);
+        const int oy = (int)(((uint64_t)w[1] * (uint64_t)By) >> 32);
+        int perm[4];
+        or_dt_perm(seed, t, perm);
+        for (int ph = 0; ph < 4 && status == OR_OK; ++ph) {
+            const int csx = perm[ph] & 1, csy = perm[ph] >> 1;
+            for (int k = 0; k < S && status == OR_OK; ++k, ++step_id) {
+                for (int by = csy; by < nby; by += 2)
+                    for (int bx = csx; bx < nbx; bx += 2) {
+                        const int b = by * nbx + bx;
+                        or_draw(seed, OR_TAG_SET, t, (uint64_t)b, 0, w);
+                        const int s = (int)((w[0] >> (2 * k)) & 3u);
+                        const int ssx = s & 1, ssy = s >> 1;
+                        for (int ty = 0; ty < nty; ++ty)
+                            for (int tx = 0; tx < ntx; ++tx) {
+                                const int j = ty / H;
+                                const uint64_t G = (uint64_t)b * nq + (uint64_t)(ty % H) * ntx + tx;
+                                int r = 0;
+                                if (has_site_draw) {
+                                    or_draw(seed, OR_TAG_SITE, t, G, 0, w);
+                                    r = (int)((w[k >> 2] >> (8 * j + 2 * (k & 3))) & 3u);
+                                }
+                                const int lx = tx * Tx + ssx * cx + (has_site_draw ? (r & 1) : 0);
+                                const int ly = ty * Ty + ssy * cy + (has_site_draw ? (r >> 1) : 0);
+                                const int gx = (ox + bx * Bx + lx) % L;
+                                const int gy = (oy + by * By + ly) % L;
+                                if (check) {
+                                    const int nx[5] = { gx, (gx + 1) % L, (gx + L - 1) % L, gx, gx };
+                                    const int ny[5] = { gy, gy, gy, (gy + 1) % L, (gy + L - 1) % L };
+                                    for (int e = 0; e < 5; ++e)
+                                        if (stamp[(size_t)ny[e] * L + nx[e]] == step_id) status = OR_ECHECK;
+                                    stamp[(size_t)gy * L + gx] = step_id;
+                                }
+                                const int kind = classify(L, sx, sy, gx, gy);
+                                if (kind == SITE_NONE) continue;
+                                const uint64_t thr = kind == SITE_MIN ? P : Q;
+                                if (thr == 0) continue;
+                                if (thr < FULL) {
+                                    uint32_t wa[4], wb[4];
+                                    or_draw(seed, OR_TAG_ACC1, t, G, (uint32_t)(k >> 2), wa);
+                                    or_draw(seed, OR_TAG_ACC2, t, G, (uint32_t)k, wb);
+                                    const uint32_t A = (wa[k & 3] >> (8 * j)) & 0xFFu;
+                                    const uint32_t u = (A << 24) | (wb[j] & 0xFFFFFFu);
+                                    if ((uint64_t)u >= thr) continue;
+                                }
+                                flip(L, sx, sy, gx, gy);
+                                const int dh = kind == SITE_MIN ? 2 : -2;
+                                *net += dh / 2;
+                                if (gx == 0 && gy == 0) *h00 += dh;
+                            }
+                    }
+            }
+        }
+    }
+    free(stamp);
+    return status;
+}
