@@ -306,6 +306,8 @@ def main():
     ap.add_argument("--p", type=float, default=1.0)
     ap.add_argument("--q", type=float, default=0.0)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--device-dt", action="store_true",
+                    help="double tiling at the device layer instead of dead borders")
     ap.add_argument("--in-place", action="store_true",
                     help="update the lattice in place (no second lattice buffer)")
     ap.add_argument("--moves", type=int, default=1,
@@ -344,7 +346,8 @@ def main():
     block = tuple(args.block)
     print(f"bench: L={L} block={block} p={args.p} q={args.q} seed={args.seed} "
           f"steps={args.steps} warmup={args.warmup} mcs/step={M}", file=sys.stderr, flush=True)
-    sim = kpz.Sim(L, args.p, args.q, args.seed, block, moves=args.moves, in_place=args.in_place)
+    sim = kpz.Sim(L, args.p, args.q, args.seed, block, moves=args.moves, in_place=args.in_place,
+                  device_dt=args.device_dt)
     stream = sim.stream
     for _ in range(args.warmup):
         sim.sweep(M)
@@ -380,7 +383,7 @@ def main():
     achieved_tops = OPS_PER_ATTEMPT * per_launch_attempts / sweep_s / 1e12
     achieved_gbs = BYTES_PER_ATTEMPT * per_launch_attempts / sweep_s / 1e9
     traffic = (measured_traffic(block, args.in_place)
-               if (L == 65536 and args.moves == 1) else None)
+               if (L == 65536 and args.moves == 1 and not args.device_dt) else None)
     line = {
         "metric": "site-update attempts/s at L=2^16",
         "value": value,
@@ -400,7 +403,8 @@ def main():
                         f"4x4 double tiles; step = {M} MCS + one exact W^2 sample",
             "L": L, "block": list(block), "tile": [4, 4], "mcs_per_step": M,
             "origin_moves_per_mcs": args.moves,
-            "lattice_buffers": 1 if args.in_place else 2,
+            "lattice_buffers": 1 if (args.in_place or args.device_dt) else 2,
+            "device_layer": "double tiling" if args.device_dt else "dead border",
         },
         "roofline": {
             "bound": "alu",
@@ -414,7 +418,8 @@ def main():
             # one MCS = one sweep launch (two-buffer mode), or the sweep launch
             # plus the straddling-word merge launch (in place), bracketed
             # together by the events
-            "kernel": "kpz_sweep_kernel+kpz_merge_kernel" if args.in_place else "kpz_sweep_kernel",
+            "kernel": ("kpz_dt_sweep_kernel x4 phases" if args.device_dt else
+                       "kpz_sweep_kernel+kpz_merge_kernel" if args.in_place else "kpz_sweep_kernel"),
             "mean_launch_ms": sweep_ms,
             "ops_per_attempt": OPS_PER_ATTEMPT,
             "hbm_achieved_gbs": achieved_gbs,

@@ -95,6 +95,15 @@ typedef enum {
  *            second lattice; the words two blocks share are joined by a
  *            merge launch after every sweep launch), for lattices too large
  *            to hold twice.  Both modes give identical results.
+ *            KPZ_FLAG_DEVICE_DT replaces the dead borders of the device
+ *            layer by double tiling (Sec. 3): the blocks form four sets of
+ *            non-adjacent blocks (bx mod 2, by mod 2; L / block_x and
+ *            L / block_y must be even), run in a random order every MCS,
+ *            one launch per set, each block with all its sites live.  A
+ *            different schedule (different results), updated in place by a
+ *            plain one-byte-per-site kernel; needs (block_y + 1) *
+ *            (block_x + 4) <= 65536 and moves <= 1; not for batches or
+ *            pools.
  * The shape and `moves` change the sequence of updates, so results are
  * reproducible for identical (L, p, q, seed, block, tile, moves) only. */
 typedef struct {
@@ -111,6 +120,7 @@ typedef struct {
 } kpz_params;
 
 #define KPZ_FLAG_IN_PLACE 1u
+#define KPZ_FLAG_DEVICE_DT 2u
 
 typedef struct kpz_sim kpz_sim;
 

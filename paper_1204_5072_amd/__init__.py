@@ -148,17 +148,20 @@ def status_str(status: int) -> str:
 
 
 KPZ_FLAG_IN_PLACE = 1
+KPZ_FLAG_DEVICE_DT = 2
 
 
 def make_params(L: int, p: float = 1.0, q: float = 0.0, seed: int = 1,
                 block: Optional[Tuple[int, int]] = None, tile: Tuple[int, int] = (4, 4),
-                moves: int = 1, in_place: bool = False) -> kpz_params:
+                moves: int = 1, in_place: bool = False, device_dt: bool = False) -> kpz_params:
     """Parameters of one lattice; ``moves`` = dead-border origin moves per
     MCS (block residency 1/moves MCS); ``in_place`` = update the lattice in
-    place (no second lattice buffer in the workspace)."""
+    place (no second lattice buffer in the workspace); ``device_dt`` =
+    double tiling instead of dead borders at the device layer."""
     bx, by = block if block else (0, 0)
+    flags = (KPZ_FLAG_IN_PLACE if in_place else 0) | (KPZ_FLAG_DEVICE_DT if device_dt else 0)
     return kpz_params(L, float(p), float(q), int(seed), int(bx), int(by), int(tile[0]),
-                      int(tile[1]), int(moves), KPZ_FLAG_IN_PLACE if in_place else 0)
+                      int(tile[1]), int(moves), flags)
 
 
 def workspace_bytes(params: kpz_params) -> int:
@@ -182,9 +185,10 @@ class Sim:
 
     def __init__(self, L: int, p: float = 1.0, q: float = 0.0, seed: int = 1,
                  block: Optional[Tuple[int, int]] = None, device="cuda", stream=None,
-                 moves: int = 1, in_place: bool = False):
+                 moves: int = 1, in_place: bool = False, device_dt: bool = False):
         import torch
-        self.params = make_params(L, p, q, seed, block, moves=moves, in_place=in_place)
+        self.params = make_params(L, p, q, seed, block, moves=moves, in_place=in_place,
+                                  device_dt=device_dt)
         self.L = L
         ws = workspace_bytes(self.params)
         self.device = torch.device(device)

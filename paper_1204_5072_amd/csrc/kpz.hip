@@ -550,6 +550,208 @@ __global__ void kpz_merge_kernel(const SweepArgs a)
         merge_one(a, ox, j);
 }
 
+// ------------------------------------ double tiling at the device layer
+//
+// Alternative device layer (Sec. 3): the blocks (same frames as above, nbx
+// and nby even) form four sets (bx mod 2, by mod 2) of non-adjacent
+// blocks; an MCS runs the sets in the order perm[(DTORDER, t).w0 * 24 >>
+// 32] (the 24 orderings of 0..3 in lexicographic order), one launch per
+// set.  A block of the active set makes its 16 single-hit steps with the
+// same draws as under dead borders but has no dead sites: an update at its
+// left column or bottom row flips a slope stored in the idle block to the
+// left or below.  Blocks of one set touch disjoint words (for Bx >= 16), so
+// every launch updates the lattice in place with no merge.
+//
+// This kernel keeps one byte per site in LDS (bit 0 sigma_x, bit 1
+// sigma_y) with a halo column (lx = -1) and row (ly = -1): rows of Bx + 4
+// bytes, site lx at byte 4 + lx.  One thread per quad group G (the four
+// tiles (tx, qy + j H) that share a site draw) updates its tiles one after
+// the other; it is the plain counterpart of the SWAR kernel above.
+
+constexpr uint32_t TAG_DTORDER = 13;
+
+struct DtArgs {
+    uint32_t *words;
+    unsigned long long *slots;
+    uint32_t L, W, Bx, By, nbx, nby, ntx, H, nq, nw;
+    uint32_t seed_lo, seed_hi, t, slot_mask, acc;
+    uint64_t P, Q;
+};
+
+__device__ __forceinline__ uint32_t dt_active_set(const DtArgs &a, uint32_t phase)
+{
+    uint32_t idx = (uint32_t)(((uint64_t)philox(0u, 0u, a.t, TAG_DTORDER << 24, a.seed_lo,
+                                                a.seed_hi).x * 24u) >> 32);
+    uint32_t pool = 0x3210u;             // remaining set codes, one per nibble
+    uint32_t n = 4, c = 0;
+    const uint32_t fact[4] = {1u, 1u, 2u, 6u};
+    for (uint32_t i = 0; i <= phase; ++i) {
+        const uint32_t f = fact[n - 1];
+        const uint32_t pick = idx / f;
+        idx %= f;
+        c = (pool >> (4 * pick)) & 15u;
+        // remove nibble `pick`
+        const uint32_t lowmask = (1u << (4 * pick)) - 1u;
+        pool = (pool & lowmask) | ((pool >> 4) & ~lowmask);
+        --n;
+    }
+    return c;
+}
+
+// 8 site bits (4 sites x 2 bits) -> 4 bytes
+__device__ __forceinline__ uint32_t spread_sites(uint32_t x)
+{
+    return (x & 3u) | ((x & 0xCu) << 6) | ((x & 0x30u) << 12) | ((x & 0xC0u) << 18);
+}
+
+__device__ __forceinline__ uint32_t gather_sites(uint32_t v)
+{
+    return (v & 3u) | ((v >> 6) & 0xCu) | ((v >> 12) & 0x30u) | ((v >> 18) & 0xC0u);
+}
+
+template <int TPB>
+__global__ __launch_bounds__(TPB) void kpz_dt_sweep_kernel(const DtArgs a, uint32_t phase)
+{
+    extern __shared__ uint32_t dtl[];
+    uint8_t *site = (uint8_t *)dtl;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t SB = a.Bx + 4;                       // LDS row bytes
+    // active block of this work-group (XCD-aware order when the grid allows)
+    uint32_t g = blockIdx.x;
+    if ((gridDim.x & 7u) == 0) g = (g & 7u) * (gridDim.x >> 3) + (g >> 3);
+    const uint32_t c = dt_active_set(a, phase);
+    const uint32_t hx = a.nbx >> 1;
+    const uint32_t bx = 2 * (g % hx) + (c & 1u), by = 2 * (g / hx) + (c >> 1);
+    const uint32_t b = by * a.nbx + bx;
+    const U4 wo = philox(0u, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
+    const uint32_t ox = (uint32_t)(((uint64_t)wo.x * a.Bx) >> 32);
+    const uint32_t oy = (uint32_t)(((uint64_t)wo.y * a.By) >> 32);
+    const uint32_t x0 = (ox + bx * a.Bx) % a.L, y0 = (oy + by * a.By) % a.L;
+    const uint32_t xs = (x0 + a.L - 1) % a.L;           // halo column
+    const uint32_t shs = 2u * (xs & 15u), gws = xs >> 4;
+    const uint32_t nr = a.nw + 1;                       // range words per row (Bx + 1 sites)
+
+    // ---- load rows ly = -1 .. By-1, sites xs .. xs + Bx, into LDS bytes
+    // (range word k = sites xs + 16 k .. + 15; byte 3 + 16 k .. of the row)
+    const uint32_t nunits = (a.By + 1) * nr;
+    for (uint32_t u = tid; u < nunits; u += TPB) {
+        const uint32_t r = u / nr, k = u % nr;
+        uint32_t gy = y0 + a.L - 1 + r;
+        gy %= a.L;
+        const uint32_t *row = a.words + (size_t)gy * a.W;
+        uint32_t gw = gws + k;
+        if (gw >= a.W) gw -= a.W;
+        const uint32_t gw1 = gw + 1 == a.W ? 0u : gw + 1;
+        const uint32_t v = __builtin_amdgcn_alignbit(row[gw1], row[gw], shs);
+        uint8_t *dst = site + r * SB + 3 + 16 * k;
+        const uint32_t nsites = k + 1 < nr ? 16u : (a.Bx + 1) - 16 * k;
+        for (uint32_t i = 0; i < nsites; ++i) dst[i] = (uint8_t)((v >> (2 * i)) & 3u);
+    }
+    __syncthreads();
+
+    // ---- 16 single-hit steps; this thread's quads q = tid + TPB i (i < 4:
+    // nq <= 1024) with their site words for the MCS and acceptance words
+    // for the current group of four steps
+    constexpr int QM = 4;
+    const uint32_t setw = philox(b, 0u, a.t, TAG_SET << 24, a.seed_lo, a.seed_hi).x;
+    const bool fullP = a.P >= (1ull << 32);
+    uint32_t sw[QM][4], aw[QM][4];
+#pragma unroll
+    for (int i = 0; i < QM; ++i) {
+        const uint64_t G = (uint64_t)b * a.nq + tid + (uint32_t)TPB * i;
+        const U4 w = philox((uint32_t)G, (uint32_t)(G >> 32), a.t, TAG_SITE << 24, a.seed_lo,
+                            a.seed_hi);
+        sw[i][0] = w.x; sw[i][1] = w.y; sw[i][2] = w.z; sw[i][3] = w.w;
+        aw[i][0] = aw[i][1] = aw[i][2] = aw[i][3] = 0u;
+    }
+    int net = 0;
+    for (uint32_t k = 0; k < 16; ++k) {
+        const uint32_t s = (setw >> (2 * k)) & 3u;
+        const uint32_t sx = s & 1u, sy = s >> 1;
+#pragma unroll
+        for (int i = 0; i < QM; ++i) {
+            const uint32_t q = tid + (uint32_t)TPB * i;
+            if (q >= a.nq) continue;
+            const uint32_t tx = q % a.ntx, qy = q / a.ntx;
+            const uint64_t G = (uint64_t)b * a.nq + q;
+            if (a.acc && (k & 3) == 0) {
+                const U4 w = philox((uint32_t)G, (uint32_t)(G >> 32), a.t,
+                                    (TAG_ACC1 << 24) | (k >> 2), a.seed_lo, a.seed_hi);
+                aw[i][0] = w.x; aw[i][1] = w.y; aw[i][2] = w.z; aw[i][3] = w.w;
+            }
+            const uint32_t kq = k >> 2, kr = k & 3;
+            const uint32_t swk = kq == 0 ? sw[i][0] : kq == 1 ? sw[i][1] : kq == 2 ? sw[i][2] : sw[i][3];
+            const uint32_t awk = kr == 0 ? aw[i][0] : kr == 1 ? aw[i][1] : kr == 2 ? aw[i][2] : aw[i][3];
+            for (uint32_t j = 0; j < 4; ++j) {
+                const uint32_t ty = qy + j * a.H;
+                if (ty * 4 >= a.By) break;
+                const uint32_t r = (swk >> (8 * j + 2 * (k & 3))) & 3u;
+                const uint32_t lx = 4 * tx + 2 * sx + (r & 1u), ly = 4 * ty + 2 * sy + (r >> 1);
+                uint8_t *own = site + (ly + 1) * SB + 4 + lx;
+                uint8_t *lft = own - 1;
+                uint8_t *dwn = own - SB;
+                const uint32_t o = *own, l = *lft, d = *dwn;
+                // minimum: own (+1, +1), incoming sigma_x(x-1), sigma_y(y-1) = -1
+                const bool mn = o == 3u && !(l & 1u) && !(d & 2u);
+                const bool mx = o == 0u && (l & 1u) && (d & 2u);
+                if (!mn && !mx) continue;
+                bool acc = mn ? fullP : false;
+                const uint64_t thr = mn ? a.P : a.Q;
+                if (!acc && thr) {
+                    const uint32_t A = (awk >> (8 * j)) & 0xFFu;
+                    const uint32_t tA = (uint32_t)(thr >> 24);
+                    if (A < tA) {
+                        acc = true;
+                    } else if (A == tA && (thr & 0xFFFFFFu)) {
+                        const U4 w2 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t,
+                                             (TAG_ACC2 << 24) | k, a.seed_lo, a.seed_hi);
+                        const uint32_t bw = j == 0 ? w2.x : j == 1 ? w2.y : j == 2 ? w2.z : w2.w;
+                        acc = (bw & 0xFFFFFFu) < (uint32_t)(thr & 0xFFFFFFu);
+                    }
+                }
+                if (!acc) continue;
+                *own = (uint8_t)(o ^ 3u);
+                *lft = (uint8_t)(l ^ 1u);
+                *dwn = (uint8_t)(d ^ 2u);
+                net += mn ? 1 : -1;
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- store: global words gws .. gws + nr of rows -1 .. By-1; bits of
+    // the range [xs, xs + Bx] come from LDS, the others keep their value
+    // (no other work-group of this launch touches these words)
+    const uint32_t ng = nr + 1;                         // global words per row touched
+    const uint32_t nstore = (a.By + 1) * ng;
+    for (uint32_t u = tid; u < nstore; u += TPB) {
+        const uint32_t r = u / ng, m = u % ng;          // global word gws + m
+        uint32_t gy = y0 + a.L - 1 + r;
+        gy %= a.L;
+        uint32_t gw = gws + m;
+        if (gw >= a.W) gw -= a.W;
+        uint32_t *row = a.words + (size_t)gy * a.W;
+        // sites of this global word: xs - shs/2 + 16 m + i, i = 0..15; range
+        // index e = 16 m + i - shs/2 in [0, Bx]
+        const int base = (int)(16 * m) - (int)(shs >> 1);
+        uint32_t val = 0u, mask = 0u;
+        for (int i = 0; i < 16; ++i) {
+            const int e = base + i;
+            if (e < 0 || e > (int)a.Bx) continue;
+            val |= (uint32_t)site[r * SB + 3 + e] << (2 * i);
+            mask |= 3u << (2 * i);
+        }
+        if (mask == 0u) continue;
+        row[gw] = mask == 0xFFFFFFFFu ? val : ((row[gw] & ~mask) | val);
+    }
+
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) net += __shfl_xor(net, off, 64);
+    if ((tid & 63u) == 0 && net != 0)
+        atomicAdd(a.slots + ((b * (TPB / 64) + tid / 64) & a.slot_mask),
+                  (unsigned long long)(long long)net);
+}
+
 // ------------------------------------------------------------ roughness
 
 // Per row y: with P(x) = sum_{l<x} sigma_x(l,y) (height relative to the row
@@ -1206,6 +1408,7 @@ struct kpz_sim {
     // two-buffer mode: buf[cur] holds the state, rotated as written by the
     // launch (rot_t, rot_res) when rot_valid
     bool db;
+    bool dt;                       // double tiling at the device layer
     uint32_t *buf[2];
     int cur;
     uint32_t rot_valid, rot_t, rot_res;
@@ -1236,7 +1439,7 @@ kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
     if (!p) return KPZ_EINVAL;
     if (p->L < 16 || (p->L % 16) != 0) return KPZ_EINVAL;
     if (!(p->p >= 0.0 && p->p <= 1.0 && p->q >= 0.0 && p->q <= 1.0)) return KPZ_EINVAL;
-    if ((p->flags & ~KPZ_FLAG_IN_PLACE) != 0) return KPZ_EINVAL;
+    if ((p->flags & ~(KPZ_FLAG_IN_PLACE | KPZ_FLAG_DEVICE_DT)) != 0) return KPZ_EINVAL;
     if (p->moves != 0 && p->moves != 1 && p->moves != 2 && p->moves != 4 && p->moves != 8 &&
         p->moves != 16)
         return KPZ_EINVAL;
@@ -1251,6 +1454,14 @@ kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
     if (!is_pow2(bx) || !is_pow2(by)) return KPZ_EINVAL;
     if (bx < 16 || by < 16 || bx > 1024 || bx * by > 65536) return KPZ_EINVAL;
     if (L % bx || L % by) return KPZ_EINVAL;
+    if (p->flags & KPZ_FLAG_DEVICE_DT) {
+        // four block sets need an even number of blocks along both axes; the
+        // plain kernel keeps the block and its halo in LDS
+        const int64_t nbx = L / bx, nby = L / by;
+        if (nbx < 2 || nby < 2 || (nbx & 1) || (nby & 1)) return KPZ_EINVAL;
+        if (p->moves > 1) return KPZ_EINVAL;
+        if ((by + 1) * (bx + 4) > 65536) return KPZ_EINVAL;
+    }
     *Bx = (uint32_t)bx;
     *By = (uint32_t)by;
     return KPZ_OK;
@@ -1271,7 +1482,7 @@ size_t ws_needed(int64_t L, int64_t Bx, uint32_t flags)
 {
     // plus, in two-buffer mode, the second lattice buffer (256-byte aligned)
     const size_t side_end = ws_side_end(L, Bx);
-    if (flags & KPZ_FLAG_IN_PLACE) return side_end;
+    if (flags & (KPZ_FLAG_IN_PLACE | KPZ_FLAG_DEVICE_DT)) return side_end;
     return ((side_end + 255) & ~(size_t)255) + (size_t)L * (size_t)L / 4;
 }
 
@@ -1399,6 +1610,7 @@ kpz_status batch_layout(const kpz_params *m, int32_t n, BatchLayout *lay)
     lay->db = true;
     lay->maxW = 0;
     for (int32_t r = 0; r < n; ++r) {
+        if (m[r].flags & KPZ_FLAG_DEVICE_DT) return KPZ_EINVAL;   // dead borders only
         if (m[r].L > 65536 || (m[r].flags & KPZ_FLAG_IN_PLACE)) lay->db = false;
         lay->maxW = std::max(lay->maxW, (uint32_t)(m[r].L / 16));
     }
@@ -1805,7 +2017,8 @@ kpz_status kpz_init(kpz_sim **out, const kpz_params *p, uint32_t *d_words, size_
     s->t = 0;
     s->P = threshold(p->p);
     s->Q = threshold(p->q);
-    s->db = !(p->flags & KPZ_FLAG_IN_PLACE);
+    s->db = !(p->flags & (KPZ_FLAG_IN_PLACE | KPZ_FLAG_DEVICE_DT));
+    s->dt = (p->flags & KPZ_FLAG_DEVICE_DT) != 0;
     s->buf[0] = d_words;
     s->buf[1] = s->db ? ws_alt(s) : d_words;
     s->cur = 0;
@@ -1887,6 +2100,45 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     const uint64_t nstraddle = (uint64_t)L * a.nbx;
     const uint32_t mgrid = (uint32_t)((nstraddle + 255) / 256 < 8192 ? (nstraddle + 255) / 256 : 8192);
     a.xcd = (nblocks % 8u) == 0;
+    if (s->dt) {
+        DtArgs d;
+        d.words = s->words;
+        d.slots = (unsigned long long *)ws_slots(s);
+        d.L = L;
+        d.W = L / 16;
+        d.Bx = s->Bx;
+        d.By = s->By;
+        d.nbx = L / s->Bx;
+        d.nby = L / s->By;
+        d.ntx = s->Bx / TILE;
+        d.H = a.H;
+        d.nq = a.nq;
+        d.nw = s->Bx / 16;
+        d.seed_lo = a.seed_lo;
+        d.seed_hi = a.seed_hi;
+        d.slot_mask = NSLOTS - 1;
+        d.acc = a.acc;
+        d.P = s->P;
+        d.Q = s->Q;
+        const uint32_t grid = d.nbx * d.nby / 4;
+        const size_t lds = (((size_t)(d.By + 1) * (d.Bx + 4)) + 3) & ~(size_t)3;
+        const bool wide = d.nq > 64;
+        for (int32_t m = 0; m < n_mcs; ++m) {
+            d.t = (uint32_t)(s->t + m);
+            for (uint32_t ph = 0; ph < 4; ++ph) {
+                if (wide)
+                    hipLaunchKernelGGL(kpz_dt_sweep_kernel<256>, dim3(grid), dim3(256), lds, s->stream,
+                                       d, ph);
+                else
+                    hipLaunchKernelGGL(kpz_dt_sweep_kernel<64>, dim3(grid), dim3(64), lds, s->stream,
+                                       d, ph);
+                const hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep launch");
+            }
+        }
+        s->t += n_mcs;
+        return KPZ_OK;
+    }
     for (int32_t m = 0; m < n_mcs; ++m) {
         a.t = (uint32_t)(s->t + m);
         for (uint32_t r = 0; r < moves; ++r) {

@@ -116,3 +116,20 @@ def test_ring_params_validation(kpz, L, block, ok):
     assert (st == kpz.KPZ_OK) == ok, st
     if ok:
         assert n.value >= 256 + 8 * 1024 + 24 * (L // 8192) + 8 * (L // (64 * (block or 128)))
+
+
+@pytest.mark.parametrize("L,block,ok", [(64, (16, 16), True), (256, (128, 128), True),
+                                        (48, (16, 16), False), (64, (64, 16), False),
+                                        (512, (256, 256), False)])
+def test_device_dt_params(kpz, L, block, ok):
+    p = kpz.make_params(L, 1.0, 0.0, 1, block, device_dt=True)
+    if ok:
+        assert kpz.workspace_bytes(p) > 0
+    else:
+        with pytest.raises(kpz.KPZError):
+            kpz.workspace_bytes(p)
+
+
+def test_device_dt_not_for_batches(kpz):
+    with pytest.raises(kpz.KPZError):
+        kpz.batch_sizes([kpz.make_params(64, 1.0, 0.0, 1, (16, 16), device_dt=True)])

@@ -162,6 +162,35 @@ def test_two_buffer_roughness_without_sync(gpu, oracle_lib):
     assert sim.words_host() is not None and h is not None
 
 
+DT_CASES = [
+    # (L, block, p, q, seed, n_mcs): double tiling at the device layer
+    (64, (16, 16), 1.0, 0.0, 41, 5),
+    (128, (32, 16), 1.0, 0.25, 42, 4),
+    (256, (64, 64), 0.7, 0.3, 43, 3),
+    (256, (128, 128), 1.0, 0.0, 44, 3),      # 1024 quads: four per thread
+    (96, (16, 16), 0.5, 0.5, 45, 4),         # 6 x 6 blocks, L not a power of two
+    (512, (128, 64), 1.0, 0.999999, 46, 2),  # tie draws
+    (64, (32, 16), 0.0, 1.0, 47, 3),         # desorption only
+]
+
+
+@pytest.mark.parametrize("L,block,p,q,seed,n", DT_CASES)
+def test_device_dt_matches_oracle(gpu, oracle_lib, L, block, p, q, seed, n):
+    _log(f"device DT L={L} block={block} p={p} q={q} seed={seed} n={n}")
+    sim = gpu.Sim(L, p, q, seed, block, device_dt=True)
+    st = oracle_lib.SlopeState(L)
+    for t in range(n):
+        sim.sweep(1)
+        st.run_dt(1, p, q, seed, block)
+        w = sim.words_host()
+        ref = oracle_lib.pack(st.sx, st.sy)
+        if not np.array_equal(w, ref):
+            bad = np.argwhere(w != ref)
+            pytest.fail(f"words differ after MCS {t}: {len(bad)} words, first at {bad[0]}")
+        assert_moments(oracle_lib, st, sim.roughness(), L)
+        assert sim.state() == (t + 1, int(st.net[0]))
+
+
 def test_l64_full_run_every_mcs(gpu, oracle_lib):
     """The L = 64, p = 1, q = 0, seed 1 workload: 1000 MCS, moments after
     every MCS, words compared every 50 MCS."""
