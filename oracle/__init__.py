@@ -30,6 +30,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "kpz_oracle.c")
+SRC_KMC = os.path.join(HERE, "kmc_oracle.c")
 LIB = os.path.join(HERE, "_build", "libkpz_oracle.so")
 
 OR_OK, OR_EINVAL, OR_ENOMEM, OR_ECHECK = 0, -1, -2, -3
@@ -37,11 +38,13 @@ OR_OK, OR_EINVAL, OR_ENOMEM, OR_ECHECK = 0, -1, -2, -3
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc into ``oracle/_build``."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    stale = not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(SRC),
+                                                                    os.path.getmtime(SRC_KMC))
+    if force or stale:
         os.makedirs(os.path.dirname(LIB), exist_ok=True)
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared",
-                               "-fPIC", "-o", tmp, SRC])
+                               "-fPIC", "-o", tmp, SRC, SRC_KMC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
