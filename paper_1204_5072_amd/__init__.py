@@ -31,7 +31,9 @@ EXPORTED = ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness", "kp
             "kpz_pool_step", "kpz_pool_poll", "kpz_pool_stats", "kpz_pool_destroy",
             "kpz_pool_last_error",
             "kpz_ring_workspace_bytes", "kpz_ring_init", "kpz_ring_sweep", "kpz_ring_roughness",
-            "kpz_ring_get_state", "kpz_ring_destroy", "kpz_ring_last_error")
+            "kpz_ring_get_state", "kpz_ring_destroy", "kpz_ring_last_error",
+            "kmc_workspace_bytes", "kmc_init", "kmc_sweep", "kmc_counts", "kmc_get_state",
+            "kmc_set_state", "kmc_destroy", "kmc_last_error")
 BATCH_MAX_SAMPLES = 1024
 
 
@@ -54,6 +56,11 @@ class kpz_params(ctypes.Structure):
 
 class kpz_ring_params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int64), ("p", ctypes.c_double), ("q", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("block", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class kmc_params(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int64), ("c", ctypes.c_double), ("eps", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("block", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
@@ -130,6 +137,17 @@ def lib() -> ctypes.CDLL:
         L.kpz_ring_destroy.restype = None
         L.kpz_ring_last_error.argtypes = [vp]
         L.kpz_ring_last_error.restype = c.c_char_p
+        KP = c.POINTER(kmc_params)
+        L.kmc_workspace_bytes.argtypes = [KP, szp]
+        L.kmc_init.argtypes = [c.POINTER(vp), KP, vp, c.c_size_t, vp, c.c_size_t, vp]
+        L.kmc_sweep.argtypes = [vp, c.c_int32]
+        L.kmc_counts.argtypes = [vp, i64p, i64p]
+        L.kmc_get_state.argtypes = [vp, i64p, i64p]
+        L.kmc_set_state.argtypes = [vp, c.c_int64, c.c_int64]
+        L.kmc_destroy.argtypes = [vp]
+        L.kmc_destroy.restype = None
+        L.kmc_last_error.argtypes = [vp]
+        L.kmc_last_error.restype = c.c_char_p
         for f in ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness",
                   "kpz_get_state", "kpz_set_state", "kpz_sync_words", "kpz_batch_sizes",
                   "kpz_batch_init",
@@ -137,7 +155,9 @@ def lib() -> ctypes.CDLL:
                   "kpz_batch_run", "kpz_batch_get_t", "kpz_batch_sync_words", "kpz_pool_job_bytes",
                   "kpz_pool_control_bytes", "kpz_pool_init", "kpz_pool_submit", "kpz_pool_step",
                   "kpz_pool_poll", "kpz_pool_stats", "kpz_ring_workspace_bytes", "kpz_ring_init",
-                  "kpz_ring_sweep", "kpz_ring_roughness", "kpz_ring_get_state"):
+                  "kpz_ring_sweep", "kpz_ring_roughness", "kpz_ring_get_state",
+                  "kmc_workspace_bytes", "kmc_init", "kmc_sweep", "kmc_counts", "kmc_get_state",
+                  "kmc_set_state"):
             getattr(L, f).restype = c.c_int
         _lib = L
     return _lib
@@ -500,6 +520,85 @@ class Ring:
     def close(self) -> None:
         if self._h:
             lib().kpz_ring_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Kmc:
+    """The 3-d KMC binary alloy (fcc sub-lattice of an L^3 cubic grid) on one
+    GPU.  ``occ`` is a torch uint8 tensor of L^3/2 bytes, one per fcc site
+    (layout in include/kmc.h); ``eps`` is the coupling of the Metropolis
+    rule and ``c`` the initial B concentration."""
+
+    def __init__(self, L: int, c: float = 0.325, eps: float = 1.5, seed: int = 1, block: int = 0,
+                 device="cuda", stream=None):
+        import torch
+        self.params = kmc_params(int(L), float(c), float(eps), int(seed), int(block), 0)
+        self.L = int(L)
+        n = ctypes.c_size_t()
+        st = lib().kmc_workspace_bytes(ctypes.byref(self.params), ctypes.byref(n))
+        if st != KPZ_OK:
+            raise KPZError(st, "kmc_workspace_bytes")
+        self.device = torch.device(device)
+        self.occ = torch.empty(self.L ** 3 // 2, dtype=torch.uint8, device=self.device)
+        self.workspace = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = ctypes.c_void_p()
+        st = lib().kmc_init(ctypes.byref(self._h), ctypes.byref(self.params),
+                            ctypes.c_void_p(self.occ.data_ptr()), self.occ.numel(),
+                            ctypes.c_void_p(self.workspace.data_ptr()), n.value,
+                            ctypes.c_void_p(self.stream.cuda_stream))
+        if st != KPZ_OK:
+            raise KPZError(st, "kmc_init")
+
+    def _check(self, st: int, what: str) -> None:
+        if st != KPZ_OK:
+            raise KPZError(st, what, lib().kmc_last_error(self._h).decode())
+
+    def sweep(self, n_mcs: int = 1) -> "Kmc":
+        self._check(lib().kmc_sweep(self._h, int(n_mcs)), "kmc_sweep")
+        return self
+
+    def counts(self) -> Tuple[int, int]:
+        """(number of B, number of B-B bonds)."""
+        nb, bonds = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().kmc_counts(self._h, ctypes.byref(nb), ctypes.byref(bonds)),
+                    "kmc_counts")
+        return nb.value, bonds.value
+
+    def state(self) -> Tuple[int, int]:
+        """(MCS counter, accepted jumps)."""
+        t, m = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().kmc_get_state(self._h, ctypes.byref(t), ctypes.byref(m)),
+                    "kmc_get_state")
+        return t.value, m.value
+
+    def occ_host(self):
+        """Copy of the sites, numpy uint8 of shape (L^3/2,) in fcc order."""
+        self.stream.synchronize()
+        return self.occ.cpu().numpy()
+
+    def load(self, occ_fcc, t: int = 0, moves: int = 0) -> "Kmc":
+        """Replaces the state by ``occ_fcc`` (L^3/2 bytes, fcc order)."""
+        import numpy as np
+        import torch
+        a = np.ascontiguousarray(occ_fcc, dtype=np.uint8).reshape(-1)
+        if a.size != self.occ.numel():
+            raise ValueError("occupation array has the wrong size")
+        self.stream.synchronize()
+        self.occ.copy_(torch.from_numpy(a).to(self.device))
+        torch.cuda.synchronize(self.device)
+        self._check(lib().kmc_set_state(self._h, int(t), int(moves)), "kmc_set_state")
+        return self
+
+    def close(self) -> None:
+        if self._h:
+            lib().kmc_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

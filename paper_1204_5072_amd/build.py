@@ -7,7 +7,8 @@ import subprocess
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRCS = [os.path.join(PKG, "csrc", "kpz.hip"), os.path.join(PKG, "csrc", "kpz_ring.hip")]
+SRCS = [os.path.join(PKG, "csrc", "kpz.hip"), os.path.join(PKG, "csrc", "kpz_ring.hip"),
+        os.path.join(PKG, "csrc", "kmc.hip")]
 HDR = os.path.join(ROOT, "include", "kpz.h")
 LIB = os.path.join(PKG, "libkpz.so")
 

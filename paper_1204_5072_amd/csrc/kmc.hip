@@ -1,0 +1,443 @@
+// kmc.hip -- kinetic lattice Monte Carlo of a binary alloy on gfx950
+// (Sec. 2.2 "Kinetic Monte Carlo", eqs. fcc and metropolis; Sec. 3
+// "Implementation of KMC").
+//
+// Kernels:
+//   kmc_init_kernel     the homogeneous random mixture, one Philox draw per site
+//   kmc_phase_kernel    one block set of one MCS: each work-group copies its
+//                       block plus a two-position halo into LDS (one byte per
+//                       cubic position), makes the 256 single-hit steps of its
+//                       64 tiles in one wave, and writes the block plus a
+//                       one-position halo back
+//   kmc_count_kernel    number of B and of B-B bonds (64-bit atomics)
+//   kmc_fill_kernel     clears counters without hipMemsetAsync
+//
+// Schedule (both layers doubly tiled; the paper's own GPU scheme): blocks of
+// B^3 positions form eight sets by the parities of their block coordinates;
+// the sets run one launch each, in an order drawn per MCS; the block grid is
+// shifted by a random origin per MCS.  Blocks of one set lie a block apart,
+// so what one block reads (two positions beyond its faces) and writes (one
+// beyond) never meets another block of the launch.  Inside a block, tiles of
+// 8^3 positions are bisected into eight 4^3 cells; step k of 256 picks one
+// cell set for the whole block, and every tile makes one attempt at a random
+// fcc site of its cell: concurrent attempts are at least five positions
+// apart along some axis, more than the three an attempt can reach.
+//
+// Random numbers (Philox4x32-10, counter (idx lo, idx hi, t, tag << 24 | sub),
+// key = seed):
+//   origin of MCS t          (18, t, idx 0, sub 0): floor(w_i B / 2^32), i = x, y, z
+//   order of the block sets  (19, t, 0, 0): ordering number floor(w0 40320 / 2^32)
+//                            of 0..7 in lexicographic order
+//   cell set of step k       (20, t, block b, k / 10): bits 3 (k mod 10) .. +2 of w0
+//   attempt of step k        (21, t, tile G = b (B/8)^3 + g, k / 2): words
+//                            2 (k & 1), 2 (k & 1) + 1 as (wa, wb): site r = wa >> 27
+//                            of the cell's 32 fcc sites (x fastest), neighbour
+//                            floor((wa mod 2^27) 12 / 2^27), uniform u = wb
+//   initial state            (16, 0, site s, 0): B iff w0 < floor(c 2^32)
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <new>
+#include <stdio.h>
+#include <string.h>
+
+#include "kmc.h"
+#include "kpz_device.h"
+
+namespace {
+
+using kpzdev::philox;
+using kpzdev::U4;
+
+constexpr uint32_t TAG_INIT = 16, TAG_ORIGIN = 18, TAG_ORDER = 19, TAG_SET = 20, TAG_STEP = 21;
+constexpr int STEPS = 256;          // fcc sites per 8^3 tile: single-hit steps per block turn
+
+struct PhaseArgs {
+    uint8_t *occ;
+    unsigned long long *moves;
+    unsigned long long T[13];       // T[d] = floor(exp(-d eps) 2^32), T[0] = 2^32
+    uint32_t L, nbh;                // lattice edge (power of two); blocks per axis / 2
+    uint32_t seed_lo, seed_hi, t, phase;
+    uint32_t xcd;                   // 1: XCD-aware work-group -> block map
+};
+
+// Ordering number idx (0 <= idx < 8!) of the permutations of 0..7 in
+// lexicographic order -> element at position `phase`.
+__device__ __forceinline__ uint32_t order_at(uint32_t idx, uint32_t phase)
+{
+    uint32_t pool = 0x76543210u;    // remaining elements, one nibble each
+    uint32_t f = 5040;              // 7!
+    uint32_t v = 0;
+    for (uint32_t i = 0; i < 8; ++i) {
+        const uint32_t pick = idx / f;
+        idx -= pick * f;
+        v = (pool >> (4 * pick)) & 15u;
+        // drop nibble `pick`
+        const uint32_t lo = pool & ((1u << (4 * pick)) - 1u);
+        const uint32_t hi = pick < 7 ? (pool >> (4 * pick + 4)) << (4 * pick) : 0u;
+        pool = lo | hi;
+        if (i == phase) break;
+        f = i < 7 ? f / (7 - i) : 1;
+    }
+    return v;
+}
+
+// Neighbour offset number nb (0..11) as a linear offset in an S-wide cube.
+template <int S>
+__device__ __forceinline__ int nb_offset(uint32_t nb)
+{
+    const uint32_t grp = nb >> 2;
+    const int u1 = grp == 2 ? S : 1;
+    const int u2 = grp == 0 ? S : S * S;
+    return ((nb & 2) ? -u1 : u1) + ((nb & 1) ? -u2 : u2);
+}
+
+// Number of B among the twelve neighbours of LDS position a.
+template <int S>
+__device__ __forceinline__ uint32_t nb_sum(const uint8_t *lds, int a)
+{
+    const uint8_t *p = lds + (a - (S * S + S));
+    constexpr int Z = S * S + S;
+    return (uint32_t)p[Z + 1 + S] + p[Z + 1 - S] + p[Z - 1 + S] + p[Z - 1 - S] +
+           p[Z + 1 + S * S] + p[Z + 1 - S * S] + p[Z - 1 + S * S] + p[Z - 1 - S * S] +
+           p[Z + S + S * S] + p[Z + S - S * S] + p[Z - S + S * S] + p[Z - S - S * S];
+}
+
+template <int B, int NTHREADS>
+__global__ __launch_bounds__(NTHREADS) void kmc_phase_kernel(PhaseArgs a)
+{
+    constexpr int S = B + 4;                // LDS cube edge: block + halo 2 on each side
+    constexpr int NT = B / 8;               // tiles per block edge
+    constexpr int TPB = NT * NT * NT;       // tiles (attempting lanes) per block, <= 64
+    constexpr int H = S / 2;                // fcc sites per LDS row
+    constexpr int SO = B + 2;               // written-back edge: block + halo 1
+    constexpr int HO = SO / 2;
+    static_assert(TPB <= 64, "all attempting lanes must sit in wave 0");
+    __shared__ uint8_t lds[S * S * S];
+    __shared__ unsigned long long Ts[13];
+
+    const uint32_t L = a.L, Lm = L - 1, half = L >> 1;
+    // per-MCS draws (uniform over the launch)
+    const U4 wo = philox(0u, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
+    const uint32_t ox = (uint32_t)(((uint64_t)wo.x * B) >> 32);
+    const uint32_t oy = (uint32_t)(((uint64_t)wo.y * B) >> 32);
+    const uint32_t oz = (uint32_t)(((uint64_t)wo.z * B) >> 32);
+    const uint32_t ordw = philox(0u, 0u, a.t, TAG_ORDER << 24, a.seed_lo, a.seed_hi).x;
+    const uint32_t c = order_at((uint32_t)(((uint64_t)ordw * 40320u) >> 32), a.phase);
+
+    // work-group -> block of set c
+    const uint32_t nset = a.nbh * a.nbh * a.nbh;
+    uint32_t j = blockIdx.x;
+    if (a.xcd) j = (j & 7u) * (nset >> 3) + (j >> 3);
+    const uint32_t jx = j % a.nbh, jy = (j / a.nbh) % a.nbh, jz = j / (a.nbh * a.nbh);
+    const uint32_t nb = 2 * a.nbh;
+    const uint32_t bx = 2 * jx + (c & 1u), by = 2 * jy + ((c >> 1) & 1u), bz = 2 * jz + (c >> 2);
+    const uint32_t b = (bz * nb + by) * nb + bx;
+    const uint32_t X0 = ox + bx * B, Y0 = oy + by * B, Z0 = oz + bz * B;   // < 2L
+
+    if (threadIdx.x < 13) Ts[threadIdx.x] = a.T[threadIdx.x];
+    // load block + halo 2 (fcc positions only)
+    for (uint32_t e = threadIdx.x; e < (uint32_t)(S * S * H); e += NTHREADS) {
+        const uint32_t row = e / H, k = e - row * H;
+        const uint32_t ly = row % S, lz = row / S;
+        const uint32_t gy = (Y0 + L - 2 + ly) & Lm, gz = (Z0 + L - 2 + lz) & Lm;
+        const uint32_t lxo = (X0 + gy + gz) & 1u;
+        const uint32_t gx = (X0 + L - 2 + lxo + 2 * k) & Lm;
+        const uint64_t gi = ((uint64_t)gz * L + gy) * half + (gx >> 1);
+        lds[(lz * S + ly) * S + lxo + 2 * k] = a.occ[gi];
+    }
+    __syncthreads();
+
+    uint32_t mv = 0;
+    if (threadIdx.x < TPB) {
+        const uint32_t g = threadIdx.x;
+        const uint32_t tx = g % NT, ty = (g / NT) % NT, tz = g / (NT * NT);
+        const uint64_t G = (uint64_t)b * TPB + g;
+        const uint32_t par0 = (ox + oy + oz) & 1u;
+        uint32_t sw = 0;
+        U4 w = {0, 0, 0, 0};
+        for (int k = 0; k < STEPS; ++k) {
+            if (k % 10 == 0)
+                sw = philox(b, 0u, a.t, (TAG_SET << 24) | (uint32_t)(k / 10), a.seed_lo,
+                            a.seed_hi).x;
+            if ((k & 1) == 0)
+                w = philox((uint32_t)G, (uint32_t)(G >> 32), a.t, (TAG_STEP << 24) | (uint32_t)(k >> 1),
+                           a.seed_lo, a.seed_hi);
+            const uint32_t s = (sw >> (3 * (k % 10))) & 7u;
+            const uint32_t wa = (k & 1) ? w.z : w.x, wb = (k & 1) ? w.w : w.y;
+            const uint32_t r = wa >> 27;
+            const uint32_t nbr = ((wa & 0x7FFFFFFu) * 12u) >> 27;
+            const uint32_t rw = r >> 1, ly = rw & 3u, lz = rw >> 2;
+            const uint32_t lx = ((par0 + ly + lz) & 1u) + 2 * (r & 1u);
+            const int ai = (int)(((8 * tz + 4 * (s >> 2) + lz + 2) * S + (8 * ty + 4 * ((s >> 1) & 1u) + ly + 2)) * S +
+                                 (8 * tx + 4 * (s & 1u) + lx + 2));
+            const int af = ai + nb_offset<S>(nbr);
+            const uint32_t oi = lds[ai], of = lds[af];
+            const int si = (int)nb_sum<S>(lds, ai), sf = (int)nb_sum<S>(lds, af);
+            int d = oi ? (si - sf + 1) : (sf - si + 1);
+            d = d < 0 ? 0 : (d > 12 ? 12 : d);
+            const bool acc = (oi != of) && (d == 0 || (unsigned long long)wb < Ts[d]);
+            if (acc) {
+                lds[ai] = (uint8_t)of;
+                lds[af] = (uint8_t)oi;
+                ++mv;
+            }
+            // the next step's reads by other lanes of this wave must see
+            // these writes: LDS work of one wave completes in order
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    __syncthreads();
+
+    // write back block + halo 1 (the halo may have received jumps)
+    for (uint32_t e = threadIdx.x; e < (uint32_t)(SO * SO * HO); e += NTHREADS) {
+        const uint32_t row = e / HO, k = e - row * HO;
+        const uint32_t ly = row % SO, lz = row / SO;
+        const uint32_t gy = (Y0 + L - 1 + ly) & Lm, gz = (Z0 + L - 1 + lz) & Lm;
+        const uint32_t lxo = (X0 + 1 + gy + gz) & 1u;
+        const uint32_t gx = (X0 + L - 1 + lxo + 2 * k) & Lm;
+        const uint64_t gi = ((uint64_t)gz * L + gy) * half + (gx >> 1);
+        a.occ[gi] = lds[((lz + 1) * S + ly + 1) * S + 1 + lxo + 2 * k];
+    }
+
+    // accepted jumps: wave 0 holds them all
+    if (threadIdx.x < 64) {
+        for (int off = 32; off > 0; off >>= 1) mv += __shfl_xor(mv, off, 64);
+        if (threadIdx.x == 0 && mv) atomicAdd(a.moves, (unsigned long long)mv);
+    }
+}
+
+__global__ void kmc_init_kernel(uint8_t *occ, uint64_t n, unsigned long long C, uint32_t seed_lo,
+                                uint32_t seed_hi)
+{
+    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+         s += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t w0 = philox((uint32_t)s, (uint32_t)(s >> 32), 0u, TAG_INIT << 24, seed_lo,
+                                   seed_hi).x;
+        occ[s] = (unsigned long long)w0 < C ? 1 : 0;
+    }
+}
+
+__global__ void kmc_fill_kernel(unsigned long long *p, uint32_t n, unsigned long long v)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// res[0] += number of B, res[1] += B-B bonds (each counted once, through the
+// six neighbours with a positive first nonzero offset among (x, y, z) ordered
+// as (+1,+1,0) (+1,-1,0) (+1,0,+1) (+1,0,-1) (0,+1,+1) (0,+1,-1)).
+__global__ void kmc_count_kernel(const uint8_t *occ, uint32_t L, unsigned long long *res)
+{
+    const uint32_t Lm = L - 1, half = L >> 1;
+    const uint64_t n = (uint64_t)L * L * half;
+    unsigned long long nb = 0, bonds = 0;
+    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+         s += (uint64_t)gridDim.x * blockDim.x) {
+        if (!occ[s]) continue;
+        const uint64_t row = s / half;
+        const uint32_t k = (uint32_t)(s - row * half);
+        const uint32_t y = (uint32_t)(row & Lm), z = (uint32_t)(row / L);
+        const uint32_t x = 2 * k + ((y + z) & 1u);
+        const int D[6][3] = {{1, 1, 0}, {1, -1, 0}, {1, 0, 1}, {1, 0, -1}, {0, 1, 1}, {0, 1, -1}};
+        uint32_t m = 0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const uint32_t xx = (x + L + D[q][0]) & Lm, yy = (y + L + D[q][1]) & Lm,
+                           zz = (z + L + D[q][2]) & Lm;
+            m += occ[((uint64_t)zz * L + yy) * half + (xx >> 1)];
+        }
+        ++nb;
+        bonds += m;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        nb += __shfl_xor(nb, off, 64);
+        bonds += __shfl_xor(bonds, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (nb) atomicAdd(&res[0], nb);
+        if (bonds) atomicAdd(&res[1], bonds);
+    }
+}
+
+}  // namespace
+
+// ================================================================ host
+
+struct kmc_sim {
+    kmc_params prm;
+    int32_t B;
+    uint8_t *occ;
+    unsigned long long *ws;         // [0] accepted jumps, [1] n_b, [2] bonds
+    hipStream_t stream;
+    int64_t t;
+    unsigned long long T[13];
+    char err[256];
+};
+
+namespace {
+
+constexpr size_t KMC_WS = 256;
+
+kpz_status kmc_resolve(const kmc_params *p, int32_t *B)
+{
+    if (!p) return KPZ_EINVAL;
+    const int64_t L = p->L;
+    if (L < 16 || L > 2048 || (L & (L - 1))) return KPZ_EINVAL;
+    if (!(p->c >= 0.0 && p->c <= 1.0) || !(p->eps >= 0.0) || !isfinite(p->eps)) return KPZ_EINVAL;
+    if (p->flags != 0) return KPZ_EINVAL;
+    int32_t b = p->block;
+    if (b == 0) b = L >= 64 ? 32 : (L >= 32 ? 16 : 8);
+    if (b != 8 && b != 16 && b != 32) return KPZ_EINVAL;
+    if (L / b < 2) return KPZ_EINVAL;
+    *B = b;
+    return KPZ_OK;
+}
+
+kpz_status kmc_fail(kmc_sim *s, hipError_t e, const char *what)
+{
+    if (s) snprintf(s->err, sizeof s->err, "%s: %s", what, hipGetErrorString(e));
+    return KPZ_EHIP;
+}
+
+unsigned long long prob_threshold(double prob)
+{
+    if (prob >= 1.0) return 1ull << 32;
+    if (prob <= 0.0) return 0;
+    return (unsigned long long)(prob * 4294967296.0);
+}
+
+}  // namespace
+
+extern "C" {
+
+kpz_status kmc_workspace_bytes(const kmc_params *p, size_t *bytes)
+{
+    int32_t B;
+    const kpz_status st = kmc_resolve(p, &B);
+    if (st != KPZ_OK) return st;
+    if (!bytes) return KPZ_EINVAL;
+    *bytes = KMC_WS;
+    return KPZ_OK;
+}
+
+kpz_status kmc_init(kmc_sim **out, const kmc_params *p, uint8_t *d_occ, size_t occ_bytes,
+                    void *d_ws, size_t ws_bytes, void *stream)
+{
+    if (!out) return KPZ_EINVAL;
+    *out = nullptr;
+    int32_t B;
+    const kpz_status st = kmc_resolve(p, &B);
+    if (st != KPZ_OK) return st;
+    if (!d_occ || !d_ws) return KPZ_EINVAL;
+    const uint64_t n = (uint64_t)p->L * p->L * p->L / 2;
+    if (occ_bytes < n || ws_bytes < KMC_WS) return KPZ_ESIZE;
+    kmc_sim *s = new (std::nothrow) kmc_sim();
+    if (!s) return KPZ_EINVAL;
+    s->prm = *p;
+    s->B = B;
+    s->occ = d_occ;
+    s->ws = (unsigned long long *)d_ws;
+    s->stream = (hipStream_t)stream;
+    s->t = 0;
+    s->err[0] = 0;
+    s->T[0] = 1ull << 32;
+    for (int d = 1; d <= 12; ++d) s->T[d] = prob_threshold(exp(-(double)d * p->eps));
+    const unsigned long long C = prob_threshold(p->c);
+    const uint32_t grid = (uint32_t)((n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384);
+    hipLaunchKernelGGL(kmc_init_kernel, dim3(grid), dim3(256), 0, s->stream, d_occ, n, C,
+                       (uint32_t)p->seed, (uint32_t)(p->seed >> 32));
+    hipLaunchKernelGGL(kmc_fill_kernel, dim3(1), dim3(64), 0, s->stream, s->ws, 3u, 0ull);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        kmc_fail(s, e, "kmc_init launch");
+        delete s;
+        return KPZ_EHIP;
+    }
+    *out = s;
+    return KPZ_OK;
+}
+
+kpz_status kmc_sweep(kmc_sim *s, int32_t n_mcs)
+{
+    if (!s || n_mcs < 0) return KPZ_EINVAL;
+    if (n_mcs == 0) return KPZ_OK;
+    if (s->t + n_mcs > 0xFFFFFFFFll) return KPZ_ERANGE;
+    PhaseArgs a;
+    a.occ = s->occ;
+    a.moves = s->ws;
+    memcpy(a.T, s->T, sizeof a.T);
+    a.L = (uint32_t)s->prm.L;
+    a.nbh = a.L / (2u * (uint32_t)s->B);
+    a.seed_lo = (uint32_t)s->prm.seed;
+    a.seed_hi = (uint32_t)(s->prm.seed >> 32);
+    const uint32_t nset = a.nbh * a.nbh * a.nbh;
+    a.xcd = (nset % 8 == 0) ? 1u : 0u;
+    for (int32_t m = 0; m < n_mcs; ++m) {
+        a.t = (uint32_t)(s->t + m);
+        for (uint32_t ph = 0; ph < 8; ++ph) {
+            a.phase = ph;
+            switch (s->B) {
+            case 8: hipLaunchKernelGGL((kmc_phase_kernel<8, 64>), dim3(nset), dim3(64), 0, s->stream, a); break;
+            case 16: hipLaunchKernelGGL((kmc_phase_kernel<16, 64>), dim3(nset), dim3(64), 0, s->stream, a); break;
+            default: hipLaunchKernelGGL((kmc_phase_kernel<32, 256>), dim3(nset), dim3(256), 0, s->stream, a); break;
+            }
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return kmc_fail(s, e, "kmc_sweep launch");
+    }
+    s->t += n_mcs;
+    return KPZ_OK;
+}
+
+kpz_status kmc_counts(kmc_sim *s, int64_t *n_b, int64_t *bonds)
+{
+    if (!s) return KPZ_EINVAL;
+    const uint32_t L = (uint32_t)s->prm.L;
+    const uint64_t n = (uint64_t)L * L * L / 2;
+    const uint32_t grid = (uint32_t)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+    hipLaunchKernelGGL(kmc_fill_kernel, dim3(1), dim3(64), 0, s->stream, s->ws + 1, 2u, 0ull);
+    hipLaunchKernelGGL(kmc_count_kernel, dim3(grid), dim3(256), 0, s->stream,
+                       (const uint8_t *)s->occ, L, s->ws + 1);
+    hipError_t e = hipGetLastError();
+    unsigned long long r[2] = {0, 0};
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r, s->ws + 1, sizeof r, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return kmc_fail(s, e, "kmc_counts");
+    if (n_b) *n_b = (int64_t)r[0];
+    if (bonds) *bonds = (int64_t)r[1];
+    return KPZ_OK;
+}
+
+kpz_status kmc_get_state(kmc_sim *s, int64_t *t, int64_t *moves)
+{
+    if (!s) return KPZ_EINVAL;
+    unsigned long long m = 0;
+    hipError_t e = hipMemcpyAsync(&m, s->ws, sizeof m, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return kmc_fail(s, e, "kmc_get_state");
+    if (t) *t = s->t;
+    if (moves) *moves = (int64_t)m;
+    return KPZ_OK;
+}
+
+kpz_status kmc_set_state(kmc_sim *s, int64_t t, int64_t moves)
+{
+    if (!s || t < 0 || t > 0xFFFFFFFFll || moves < 0) return KPZ_EINVAL;
+    hipLaunchKernelGGL(kmc_fill_kernel, dim3(1), dim3(64), 0, s->stream, s->ws, 1u,
+                       (unsigned long long)moves);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return kmc_fail(s, e, "kmc_set_state");
+    s->t = t;
+    return KPZ_OK;
+}
+
+void kmc_destroy(kmc_sim *s) { delete s; }
+
+const char *kmc_last_error(const kmc_sim *s) { return s ? s->err : ""; }
+
+}  // extern "C"

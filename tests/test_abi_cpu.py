@@ -1,5 +1,6 @@
 """Host-only checks of the C ABI: the library loads, exports every function
-include/kpz.h declares, and validates its arguments before touching a GPU."""
+include/kpz.h and include/kmc.h declare, and validates its arguments before
+touching a GPU."""
 import ctypes
 import os
 import re
@@ -20,9 +21,15 @@ def kpz():
 
 
 def header_functions():
-    text = open(os.path.join(ROOT, "include", "kpz.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(kpz_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for h in sorted(os.listdir(inc)):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(inc, h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b((?:kpz|kmc)_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_exports_every_declared_function(kpz):
@@ -133,3 +140,39 @@ def test_device_dt_params(kpz, L, block, ok):
 def test_device_dt_not_for_batches(kpz):
     with pytest.raises(kpz.KPZError):
         kpz.batch_sizes([kpz.make_params(64, 1.0, 0.0, 1, (16, 16), device_dt=True)])
+
+
+@pytest.mark.parametrize("L,block,ok", [(16, 0, True), (16, 8, True), (32, 16, True),
+                                        (512, 32, True), (2048, 0, True), (16, 16, False),
+                                        (24, 8, False), (512, 64, False), (512, 4, False),
+                                        (4096, 32, False), (8, 0, False)])
+def test_kmc_params_validation(kpz, L, block, ok):
+    p = kpz.kmc_params(L, 0.325, 1.5, 1, block, 0)
+    n = ctypes.c_size_t()
+    st = kpz.lib().kmc_workspace_bytes(ctypes.byref(p), ctypes.byref(n))
+    assert (st == kpz.KPZ_OK) == ok, st
+    if ok:
+        assert n.value >= 24
+
+
+@pytest.mark.parametrize("c,eps,flags", [(-0.1, 1.0, 0), (1.5, 1.0, 0), (0.3, -1.0, 0),
+                                         (0.3, float("inf"), 0), (0.3, float("nan"), 0),
+                                         (0.3, 1.0, 1)])
+def test_kmc_bad_physics_rejected(kpz, c, eps, flags):
+    p = kpz.kmc_params(64, c, eps, 1, 0, flags)
+    n = ctypes.c_size_t()
+    assert kpz.lib().kmc_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == kpz.KPZ_EINVAL
+
+
+def test_kmc_init_checks_buffers_first(kpz):
+    p = kpz.kmc_params(64, 0.3, 1.0, 1, 0, 0)
+    h = ctypes.c_void_p()
+    lib = kpz.lib()
+    assert lib.kmc_init(ctypes.byref(h), ctypes.byref(p), None, 0, None, 0, None) == kpz.KPZ_EINVAL
+    buf = ctypes.create_string_buffer(64)
+    # too small: rejected before any device work
+    assert lib.kmc_init(ctypes.byref(h), ctypes.byref(p), ctypes.cast(buf, ctypes.c_void_p),
+                        64, ctypes.cast(buf, ctypes.c_void_p), 64, None) == kpz.KPZ_ESIZE
+    assert not h.value
+    assert lib.kmc_sweep(None, 1) == kpz.KPZ_EINVAL
+    assert lib.kmc_counts(None, None, None) == kpz.KPZ_EINVAL
