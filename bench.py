@@ -229,6 +229,54 @@ def ring_leg(args):
     }
 
 
+def kmc_leg(args):
+    """The paper's KMC quench benchmark configuration: fcc lattice of
+    512^3/2 sites, c = 0.325, eps = 1.5, 32^3 device-layer blocks: attempts/s
+    over 20 MCS timed with HIP events on the simulation's stream, plus the
+    oracle's random-sequential dynamics on a 128^3/2 sample for scale."""
+    import time
+    import torch
+    import paper_1204_5072_amd as kpz
+    L, n = 512, 20
+    sim = kpz.Kmc(L, c=0.325, eps=1.5, seed=1, block=32)
+    nb0, bonds0 = sim.counts()
+    sim.sweep(2)
+    torch.cuda.synchronize()
+    t0, m0 = sim.state()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.sweep(n)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n
+    t1, m1 = sim.state()
+    nb1, bonds1 = sim.counts()
+    sim.close()
+    N = L ** 3 // 2
+    out = {
+        "metric": "update attempts/s, KMC binary alloy fcc 512^3/2, c=0.325, eps=1.5",
+        "value": N / (ms * 1e-3),
+        "unit": "attempts/s",
+        "ms_per_mcs": ms,
+        "launches_per_mcs": 8,
+        "block": 32,
+        "accepted_per_attempt": (m1 - m0) / (N * n),
+        "bonds_initial": bonds0,
+        "bonds_final": bonds1,
+        "n_b": nb1,
+        "t_final": t1,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import kmc as okmc
+        occ = okmc.init(128, 0.325, 1)
+        t = time.perf_counter()
+        okmc.rs_run(occ, 1.5, 1, 0, 2)
+        dt = time.perf_counter() - t
+        out["cpu_oracle_rs"] = {"value": 2 * 128 ** 3 // 2 / dt, "unit": "attempts/s", "cores": 1,
+                                "kind": "oracle", "sample": "random-sequential, 128^3/2 sites, 2 MCS"}
+    return out
+
+
 def serving_leg(args):
     """Serving: Poisson stream of jobs (2000 at 50 jobs/s by default), L =
     2^k with k uniform on 8..13, p = 1, q uniform on [0, 0.5], MCS log-uniform
@@ -322,6 +370,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-ring", action="store_true")
+    ap.add_argument("--no-kmc", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-hbm-gib", type=float, default=16.0)
@@ -440,6 +489,9 @@ def main():
     if not args.no_ring:
         print("bench: ring leg", file=sys.stderr, flush=True)
         line["ring"] = ring_leg(args)
+    if not args.no_kmc:
+        print("bench: kmc leg", file=sys.stderr, flush=True)
+        line["kmc"] = kmc_leg(args)
     if not args.no_serve:
         print("bench: serving leg", file=sys.stderr, flush=True)
         line["serving"] = serving_leg(args)

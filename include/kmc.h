@@ -69,8 +69,11 @@ typedef struct kmc_sim kmc_sim;
 kpz_status kmc_workspace_bytes(const kmc_params *params, size_t *ws_bytes);
 
 /* Creates a handle and enqueues the initial random mixture into d_occ (at
- * least L^3/2 bytes): site s is B iff the first word of the draw (tag 16,
- * t = 0, index s) is below floor(c 2^32).  t = 0, accepted jumps = 0. */
+ * least L^3/2 bytes, 4-byte aligned): site s is B iff the first word of the
+ * draw (tag 16, t = 0, index s) is below floor(c 2^32).  t = 0, accepted
+ * jumps = 0.  d_workspace: kmc_workspace_bytes() bytes, 8-byte aligned.
+ * KPZ_EINVAL for a NULL or misaligned buffer, KPZ_ESIZE if one is too
+ * small; nothing is enqueued then. */
 kpz_status kmc_init(kmc_sim **out, const kmc_params *params, uint8_t *d_occ, size_t occ_bytes,
                     void *d_workspace, size_t workspace_bytes, void *stream);
 

@@ -82,25 +82,89 @@ __device__ __forceinline__ uint32_t order_at(uint32_t idx, uint32_t phase)
     return v;
 }
 
-// Neighbour offset number nb (0..11) as a linear offset in an S-wide cube.
-template <int S>
-__device__ __forceinline__ int nb_offset(uint32_t nb)
+// Philox4x32-10 as kpzdev::philox, with each round's two three-way XORs as
+// single v_bitop3_b32 instructions (the step loop is issue-bound).
+__device__ __forceinline__ U4 philox_x3(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1)
 {
-    const uint32_t grp = nb >> 2;
-    const int u1 = grp == 2 ? S : 1;
-    const int u2 = grp == 0 ? S : S * S;
-    return ((nb & 2) ? -u1 : u1) + ((nb & 1) ? -u2 : u2);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
 }
 
-// Number of B among the twelve neighbours of LDS position a.
-template <int S>
-__device__ __forceinline__ uint32_t nb_sum(const uint8_t *lds, int a)
+// Components + 1 of the twelve neighbour offsets (numbering of kmc.h), two
+// bits per neighbour: field nb at bits 2 nb .. 2 nb + 1.
+constexpr uint32_t pack2(const int (&v)[12])
 {
-    const uint8_t *p = lds + (a - (S * S + S));
+    uint32_t r = 0;
+    for (int k = 0; k < 12; ++k) r |= (uint32_t)v[k] << (2 * k);
+    return r;
+}
+constexpr int NBX1[12] = {2, 2, 0, 0, 2, 2, 0, 0, 1, 1, 1, 1};
+constexpr int NBY1[12] = {2, 0, 2, 0, 1, 1, 1, 1, 2, 2, 0, 0};
+constexpr int NBZ1[12] = {1, 1, 1, 1, 2, 0, 2, 0, 2, 0, 2, 0};
+constexpr uint32_t CXP = pack2(NBX1), CYP = pack2(NBY1), CZP = pack2(NBZ1);
+
+// Number of B among the twelve neighbours of LDS position p + S^2 + S (the
+// base p is the position minus S^2 + S, so that every offset is positive
+// and folds into the LDS instruction).
+template <int S>
+__device__ __forceinline__ uint32_t sum12(const uint8_t *p)
+{
     constexpr int Z = S * S + S;
     return (uint32_t)p[Z + 1 + S] + p[Z + 1 - S] + p[Z - 1 + S] + p[Z - 1 - S] +
            p[Z + 1 + S * S] + p[Z + 1 - S * S] + p[Z - 1 + S * S] + p[Z - 1 - S * S] +
            p[Z + S + S * S] + p[Z + S - S * S] + p[Z - S + S * S] + p[Z - S - S * S];
+}
+
+// One attempt of a tile lane: site r = wa >> 27 of the cell whose corner is
+// LDS position `corner` (x fastest over the cell's 32 fcc sites, row r / 2:
+// y = (r / 2) mod 4, z = r / 8; x = the fcc parity bit + 2 (r mod 2)),
+// neighbour floor((wa mod 2^27) 12 / 2^27), uniform u = wb; T[d] is the
+// acceptance threshold for n_b - n_e = d (T[0] = 2^32).  Branch-free: the
+// 26 reads are issued together and both positions are always rewritten
+// (with their own values when rejected).  Returns 1 if a B jumped.  The
+// write is seen by the next step's reads of other lanes: LDS work of one
+// wave completes in issue order, and the fences keep the compiler from
+// moving memory operations across.
+template <int S>
+__device__ __forceinline__ uint32_t attempt(uint8_t *lds, int corner, uint32_t par0, uint32_t wa,
+                                            uint32_t wb, const unsigned long long *T)
+{
+    constexpr int Z = S * S + S;
+    const uint32_t x4 = wa >> 28;                        // y + 4 z of the row
+    const uint32_t ly = x4 & 3u, lz = wa >> 30;
+    const uint32_t lx = ((par0 ^ x4 ^ lz) & 1u) | ((wa >> 26) & 2u);
+    const int ai = corner + (int)(lx + ly * S + lz * (S * S));
+    const uint32_t m = wa & 0x7FFFFFFu;
+    const uint32_t sh = ((m + (m << 1)) >> 25) << 1;     // 2 floor(12 m / 2^27)
+    const uint32_t X = (CXP >> sh) & 3u, Y = (CYP >> sh) & 3u, Zc = (CZP >> sh) & 3u;
+    const int af = ai + (int)(X + Y * S + Zc * (S * S)) - (1 + S + S * S);
+    // bases below 2^16: the constant offsets fold into the instructions
+    uint8_t *pi = lds + ((uint32_t)(ai - Z) & 0xFFFFu);
+    uint8_t *pf = lds + ((uint32_t)(af - Z) & 0xFFFFu);
+    const uint32_t oi = pi[Z], of = pf[Z];
+    const int si = (int)sum12<S>(pi), sf = (int)sum12<S>(pf);
+    int d = oi ? (si - sf + 1) : (sf - si + 1);       // n_b - n_e when oi != of
+    d = d < 0 ? 0 : (d > 12 ? 12 : d);
+    const uint32_t acc = (uint32_t)(oi != of) & (uint32_t)((unsigned long long)wb < T[d]);
+    pi[Z] = (uint8_t)(acc ? of : oi);
+    pf[Z] = (uint8_t)(acc ? oi : of);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return acc;
 }
 
 template <int B, int NTHREADS>
@@ -115,6 +179,7 @@ __global__ __launch_bounds__(NTHREADS) void kmc_phase_kernel(PhaseArgs a)
     static_assert(TPB <= 64, "all attempting lanes must sit in wave 0");
     __shared__ uint8_t lds[S * S * S];
     __shared__ unsigned long long Ts[13];
+    __shared__ uint32_t celltab[STEPS / 2];   // cell corners of steps 2j, 2j + 1
 
     const uint32_t L = a.L, Lm = L - 1, half = L >> 1;
     // per-MCS draws (uniform over the launch)
@@ -136,71 +201,175 @@ __global__ __launch_bounds__(NTHREADS) void kmc_phase_kernel(PhaseArgs a)
     const uint32_t X0 = ox + bx * B, Y0 = oy + by * B, Z0 = oz + bz * B;   // < 2L
 
     if (threadIdx.x < 13) Ts[threadIdx.x] = a.T[threadIdx.x];
+    if (TPB == 64 && threadIdx.x < STEPS / 2) {
+        // steps 2j and 2j + 1 share their cell-set draw (k / 10)
+        const uint32_t k0 = 2 * threadIdx.x;
+        const uint32_t sw =
+            philox(b, 0u, a.t, (TAG_SET << 24) | (k0 / 10), a.seed_lo, a.seed_hi).x;
+        uint32_t v = 0;
+        for (uint32_t h = 0; h < 2; ++h) {
+            const uint32_t sc = (sw >> (3 * ((k0 + h) % 10))) & 7u;
+            v |= (4u * ((sc & 1u) + ((sc >> 1) & 1u) * S + (sc >> 2) * S * S)) << (16 * h);
+        }
+        celltab[threadIdx.x] = v;
+    }
     // load block + halo 2 (fcc positions only)
-    for (uint32_t e = threadIdx.x; e < (uint32_t)(S * S * H); e += NTHREADS) {
-        const uint32_t row = e / H, k = e - row * H;
-        const uint32_t ly = row % S, lz = row / S;
-        const uint32_t gy = (Y0 + L - 2 + ly) & Lm, gz = (Z0 + L - 2 + lz) & Lm;
-        const uint32_t lxo = (X0 + gy + gz) & 1u;
-        const uint32_t gx = (X0 + L - 2 + lxo + 2 * k) & Lm;
-        const uint64_t gi = ((uint64_t)gz * L + gy) * half + (gx >> 1);
-        lds[(lz * S + ly) * S + lxo + 2 * k] = a.occ[gi];
+    constexpr int NIT = (S * S + NTHREADS - 1) / NTHREADS;   // LDS rows per thread
+    const uint32_t WL = L >> 3, WLm = WL - 1;                 // words per compact row
+    uint32_t keep0[NIT], keep4[NIT], keep5[NIT];              // edge words, for the write-back
+    if constexpr (TPB == 64) {
+        // LDS rows of 36 positions (18 sites), row tid + NTHREADS it: the
+        // row's 18 compact bytes lie in 6 aligned global words; realign them
+        // and spread each pair of sites over one LDS dword.  Straight-line
+        // over all rows (the last row repeated where the count runs out) so
+        // that every load is in flight at once.
+        const uint32_t *occw = (const uint32_t *)a.occ;
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const uint32_t row = min(threadIdx.x + it * NTHREADS, (uint32_t)(S * S - 1));
+            const uint32_t ly = row % S, lz = row / S;
+            const uint32_t gy = (Y0 + L - 2 + ly) & Lm, gz = (Z0 + L - 2 + lz) & Lm;
+            const uint32_t lxo = (X0 + gy + gz) & 1u;
+            const uint32_t k0 = ((X0 + L - 2 + lxo) & Lm) >> 1;
+            const uint32_t q = k0 >> 2, o = k0 & 3u;
+            const uint32_t *rw = occw + ((uint64_t)gz * L + gy) * WL;
+            uint32_t w[6], r[5];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) w[i] = rw[(q + i) & WLm];
+            keep0[it] = w[0];
+            keep4[it] = w[4];
+            keep5[it] = w[5];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) r[i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], o);
+            const uint32_t se = lxo ? 0x010C000Cu : 0x0C010C00u;
+            const uint32_t so = se + (lxo ? 0x02000200u : 0x00020002u);
+            uint32_t *dst = (uint32_t *)(lds + (lz * S + ly) * S);
+#pragma unroll
+            for (int j = 0; j < H / 2; ++j)
+                dst[j] = __builtin_amdgcn_perm(0u, r[j >> 1], (j & 1) ? so : se);
+        }
+    } else {
+        for (uint32_t e = threadIdx.x; e < (uint32_t)(S * S * H); e += NTHREADS) {
+            const uint32_t row = e / H, k = e - row * H;
+            const uint32_t ly = row % S, lz = row / S;
+            const uint32_t gy = (Y0 + L - 2 + ly) & Lm, gz = (Z0 + L - 2 + lz) & Lm;
+            const uint32_t lxo = (X0 + gy + gz) & 1u;
+            const uint32_t gx = (X0 + L - 2 + lxo + 2 * k) & Lm;
+            const uint64_t gi = ((uint64_t)gz * L + gy) * half + (gx >> 1);
+            lds[(lz * S + ly) * S + lxo + 2 * k] = a.occ[gi];
+        }
     }
     __syncthreads();
 
     uint32_t mv = 0;
-    if (threadIdx.x < TPB) {
-        const uint32_t g = threadIdx.x;
-        const uint32_t tx = g % NT, ty = (g / NT) % NT, tz = g / (NT * NT);
-        const uint64_t G = (uint64_t)b * TPB + g;
-        const uint32_t par0 = (ox + oy + oz) & 1u;
-        uint32_t sw = 0;
-        U4 w = {0, 0, 0, 0};
-        for (int k = 0; k < STEPS; ++k) {
-            if (k % 10 == 0)
-                sw = philox(b, 0u, a.t, (TAG_SET << 24) | (uint32_t)(k / 10), a.seed_lo,
-                            a.seed_hi).x;
-            if ((k & 1) == 0)
-                w = philox((uint32_t)G, (uint32_t)(G >> 32), a.t, (TAG_STEP << 24) | (uint32_t)(k >> 1),
-                           a.seed_lo, a.seed_hi);
-            const uint32_t s = (sw >> (3 * (k % 10))) & 7u;
-            const uint32_t wa = (k & 1) ? w.z : w.x, wb = (k & 1) ? w.w : w.y;
-            const uint32_t r = wa >> 27;
-            const uint32_t nbr = ((wa & 0x7FFFFFFu) * 12u) >> 27;
-            const uint32_t rw = r >> 1, ly = rw & 3u, lz = rw >> 2;
-            const uint32_t lx = ((par0 + ly + lz) & 1u) + 2 * (r & 1u);
-            const int ai = (int)(((8 * tz + 4 * (s >> 2) + lz + 2) * S + (8 * ty + 4 * ((s >> 1) & 1u) + ly + 2)) * S +
-                                 (8 * tx + 4 * (s & 1u) + lx + 2));
-            const int af = ai + nb_offset<S>(nbr);
-            const uint32_t oi = lds[ai], of = lds[af];
-            const int si = (int)nb_sum<S>(lds, ai), sf = (int)nb_sum<S>(lds, af);
-            int d = oi ? (si - sf + 1) : (sf - si + 1);
-            d = d < 0 ? 0 : (d > 12 ? 12 : d);
-            const bool acc = (oi != of) && (d == 0 || (unsigned long long)wb < Ts[d]);
-            if (acc) {
-                lds[ai] = (uint8_t)of;
-                lds[af] = (uint8_t)oi;
-                ++mv;
+    const uint32_t par0 = (ox + oy + oz) & 1u;
+    if constexpr (TPB == 64) {
+        // 32^3 blocks: wave 0 makes every attempt of the block, one lane per
+        // tile; the other waves only load and store.
+        if (threadIdx.x < 64) {
+            const uint32_t g = threadIdx.x;
+            const uint32_t tx = g % NT, ty = (g / NT) % NT, tz = g / (NT * NT);
+            const uint64_t G = (uint64_t)b * TPB + g;
+            const int tbase = (int)(((8 * tz + 2) * S + (8 * ty + 2)) * S + 8 * tx + 2);
+            U4 w = philox_x3((uint32_t)G, (uint32_t)(G >> 32), a.t, TAG_STEP << 24, a.seed_lo,
+                             a.seed_hi);
+            for (uint32_t kk = 0; kk < STEPS / 2; ++kk) {
+                // draws of the next pair of steps, independent of the lattice:
+                // their arithmetic fills the LDS latency of this pair
+                const U4 wn = philox_x3((uint32_t)G, (uint32_t)(G >> 32), a.t,
+                                        (TAG_STEP << 24) | (kk + 1), a.seed_lo, a.seed_hi);
+                const uint32_t cw = celltab[kk];
+                mv += attempt<S>(lds, tbase + (int)(cw & 0xFFFFu), par0, w.x, w.y, Ts);
+                mv += attempt<S>(lds, tbase + (int)(cw >> 16), par0, w.z, w.w, Ts);
+                w = wn;
             }
-            // the next step's reads by other lanes of this wave must see
-            // these writes: LDS work of one wave completes in order
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    } else {
+        // smaller blocks (small lattices): TPB lanes of wave 0
+        if (threadIdx.x < TPB) {
+            const uint32_t g = threadIdx.x;
+            const uint32_t tx = g % NT, ty = (g / NT) % NT, tz = g / (NT * NT);
+            const uint64_t G = (uint64_t)b * TPB + g;
+            const int tbase = (int)(((8 * tz + 2) * S + (8 * ty + 2)) * S + 8 * tx + 2);
+            uint32_t sw = 0;
+            U4 w = philox_x3((uint32_t)G, (uint32_t)(G >> 32), a.t, TAG_STEP << 24, a.seed_lo,
+                             a.seed_hi);
+            for (uint32_t kk = 0; kk < STEPS / 2; ++kk) {
+                const U4 wn = philox_x3((uint32_t)G, (uint32_t)(G >> 32), a.t,
+                                        (TAG_STEP << 24) | (kk + 1), a.seed_lo, a.seed_hi);
+#pragma unroll
+                for (uint32_t h = 0; h < 2; ++h) {
+                    const uint32_t k = 2 * kk + h;
+                    if (k % 10 == 0)
+                        sw = philox(b, 0u, a.t, (TAG_SET << 24) | (k / 10), a.seed_lo,
+                                    a.seed_hi).x;
+                    const uint32_t sc = (sw >> (3 * (k % 10))) & 7u;
+                    const int cell =
+                        4 * (int)((sc & 1u) + ((sc >> 1) & 1u) * S + (sc >> 2) * S * S);
+                    mv += attempt<S>(lds, tbase + cell, par0, h ? w.z : w.x, h ? w.w : w.y, Ts);
+                }
+                w = wn;
+            }
         }
     }
     __syncthreads();
 
     // write back block + halo 1 (the halo may have received jumps)
-    for (uint32_t e = threadIdx.x; e < (uint32_t)(SO * SO * HO); e += NTHREADS) {
-        const uint32_t row = e / HO, k = e - row * HO;
-        const uint32_t ly = row % SO, lz = row / SO;
-        const uint32_t gy = (Y0 + L - 1 + ly) & Lm, gz = (Z0 + L - 1 + lz) & Lm;
-        const uint32_t lxo = (X0 + 1 + gy + gz) & 1u;
-        const uint32_t gx = (X0 + L - 1 + lxo + 2 * k) & Lm;
-        const uint64_t gi = ((uint64_t)gz * L + gy) * half + (gx >> 1);
-        a.occ[gi] = lds[((lz + 1) * S + ly + 1) * S + 1 + lxo + 2 * k];
+    if constexpr (TPB == 64) {
+        // rows -1..B in y and z, each by the thread that loaded it: the row's
+        // whole loaded segment (x = -2..B+1) goes back in the same 6 aligned
+        // words; the bytes of the edge words outside the segment get the
+        // values loaded before.  No other work-group of the launch writes any
+        // byte of these words, nor reads one our block changes: blocks of one
+        // set are 32 positions apart and the words reach at most 8 positions
+        // beyond the segment.
+        uint32_t *occw = (uint32_t *)a.occ;
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const uint32_t row = threadIdx.x + it * NTHREADS;
+            const uint32_t ly = row % S, lz = row / S;
+            if (row >= (uint32_t)(S * S) || ly < 1 || ly > S - 2 || lz < 1 || lz > S - 2) continue;
+            const uint32_t gy = (Y0 + L - 2 + ly) & Lm, gz = (Z0 + L - 2 + lz) & Lm;
+            const uint32_t lxo = (X0 + gy + gz) & 1u;
+            const uint32_t k0 = ((X0 + L - 2 + lxo) & Lm) >> 1;
+            const uint32_t q = k0 >> 2, o = k0 & 3u;
+            uint32_t *rw = occw + ((uint64_t)gz * L + gy) * WL;
+            const uint32_t *src = (const uint32_t *)(lds + (lz * S + ly) * S);
+            uint32_t dd[H / 2 + 1], seg[6];
+#pragma unroll
+            for (int j = 0; j < H / 2; ++j) dd[j] = src[j];
+            dd[H / 2] = 0;
+            const uint32_t sel = lxo ? 0x07050301u : 0x06040200u;
+#pragma unroll
+            for (int m = 0; m < 5; ++m) seg[m] = __builtin_amdgcn_perm(dd[2 * m + 1], dd[2 * m], sel);
+            seg[5] = 0;
+            // window word i holds segment bytes 4 i - o .. 4 i - o + 3
+            const uint32_t sh = (4u - o) & 3u;
+            uint32_t out[6];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                const uint32_t lo = o ? (i ? seg[i - 1] : 0u) : seg[i];
+                out[i] = __builtin_amdgcn_alignbyte(seg[i], lo, sh);
+            }
+            const uint32_t m0 = 0xFFFFFFFFu << (8 * o);
+            rw[q & WLm] = (out[0] & m0) | (keep0[it] & ~m0);
+#pragma unroll
+            for (int i = 1; i < 4; ++i) rw[(q + i) & WLm] = out[i];
+            // bytes of words 4 and 5 inside the segment: below o + 2 and o - 2
+            const uint32_t m4 = o < 2 ? (1u << (8 * (o + 2))) - 1u : 0xFFFFFFFFu;
+            rw[(q + 4) & WLm] = (out[4] & m4) | (keep4[it] & ~m4);
+            if (o == 3) rw[(q + 5) & WLm] = (out[5] & 0xFFu) | (keep5[it] & ~0xFFu);
+        }
+    } else {
+        for (uint32_t e = threadIdx.x; e < (uint32_t)(SO * SO * HO); e += NTHREADS) {
+            const uint32_t row = e / HO, k = e - row * HO;
+            const uint32_t ly = row % SO, lz = row / SO;
+            const uint32_t gy = (Y0 + L - 1 + ly) & Lm, gz = (Z0 + L - 1 + lz) & Lm;
+            const uint32_t lxo = (X0 + 1 + gy + gz) & 1u;
+            const uint32_t gx = (X0 + L - 1 + lxo + 2 * k) & Lm;
+            const uint64_t gi = ((uint64_t)gz * L + gy) * half + (gx >> 1);
+            a.occ[gi] = lds[((lz + 1) * S + ly + 1) * S + 1 + lxo + 2 * k];
+        }
     }
 
     // accepted jumps: wave 0 holds them all
@@ -332,7 +501,7 @@ kpz_status kmc_init(kmc_sim **out, const kmc_params *p, uint8_t *d_occ, size_t o
     int32_t B;
     const kpz_status st = kmc_resolve(p, &B);
     if (st != KPZ_OK) return st;
-    if (!d_occ || !d_ws) return KPZ_EINVAL;
+    if (!d_occ || !d_ws || ((uintptr_t)d_occ & 3u) || ((uintptr_t)d_ws & 7u)) return KPZ_EINVAL;
     const uint64_t n = (uint64_t)p->L * p->L * p->L / 2;
     if (occ_bytes < n || ws_bytes < KMC_WS) return KPZ_ESIZE;
     kmc_sim *s = new (std::nothrow) kmc_sim();
