@@ -33,20 +33,20 @@ def lib():
         u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
         u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
         i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
-        L.kmc_thresholds.argtypes = [c.c_double, u64p]
-        L.kmc_thresholds.restype = None
-        L.kmc_init.argtypes = [c.c_int, c.c_double, c.c_uint64, u8p]
-        L.kmc_rs_run.argtypes = [c.c_int, c.c_double, c.c_uint64, c.c_uint32, c.c_int, u8p,
+        L.or_kmc_thresholds.argtypes = [c.c_double, u64p]
+        L.or_kmc_thresholds.restype = None
+        L.or_kmc_init.argtypes = [c.c_int, c.c_double, c.c_uint64, u8p]
+        L.or_kmc_rs_run.argtypes = [c.c_int, c.c_double, c.c_uint64, c.c_uint32, c.c_int, u8p,
                                  c.POINTER(c.c_int64)]
-        L.kmc_counts.argtypes = [c.c_int, u8p, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
-        L.kmc_counts.restype = None
-        L.kmc_attempt.argtypes = [c.c_int, c.c_double, u8p, c.c_int, c.c_int, c.c_int, c.c_int,
+        L.or_kmc_counts.argtypes = [c.c_int, u8p, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
+        L.or_kmc_counts.restype = None
+        L.or_kmc_attempt.argtypes = [c.c_int, c.c_double, u8p, c.c_int, c.c_int, c.c_int, c.c_int,
                                   c.c_uint32]
-        L.kmc_order.argtypes = [c.c_uint64, c.c_uint32, i32p]
-        L.kmc_order.restype = None
-        L.kmc_origin.argtypes = [c.c_uint64, c.c_uint32, c.c_int, i32p]
-        L.kmc_origin.restype = None
-        L.kmc_dt_run.argtypes = [c.c_int, c.c_double, c.c_uint64, c.c_int, c.c_uint32, c.c_int,
+        L.or_kmc_order.argtypes = [c.c_uint64, c.c_uint32, i32p]
+        L.or_kmc_order.restype = None
+        L.or_kmc_origin.argtypes = [c.c_uint64, c.c_uint32, c.c_int, i32p]
+        L.or_kmc_origin.restype = None
+        L.or_kmc_dt_run.argtypes = [c.c_int, c.c_double, c.c_uint64, c.c_int, c.c_uint32, c.c_int,
                                  u8p, c.POINTER(c.c_int64), c.c_int, c.c_void_p]
         _ready = True
     return L
@@ -55,22 +55,22 @@ def lib():
 def thresholds(eps: float) -> np.ndarray:
     """T[d] = floor(exp(-d eps) 2^32), d = 0..12 (eq. ``metropolis`` as integers)."""
     T = np.zeros(13, np.uint64)
-    lib().kmc_thresholds(float(eps), T)
+    lib().or_kmc_thresholds(float(eps), T)
     return T
 
 
 def init(L: int, c: float, seed: int) -> np.ndarray:
     """Homogeneous random mixture: each fcc site is B with probability c."""
     occ = np.zeros((L, L, L), np.uint8)
-    _check(lib().kmc_init(L, float(c), seed, occ), "kmc_init")
+    _check(lib().or_kmc_init(L, float(c), seed, occ), "or_kmc_init")
     return occ
 
 
 def rs_run(occ: np.ndarray, eps: float, seed: int, t0: int, n_mcs: int) -> int:
     """Random-sequential dynamics in place; returns the accepted jumps."""
     mv = ctypes.c_int64(0)
-    _check(lib().kmc_rs_run(occ.shape[0], float(eps), seed, t0, n_mcs, occ, ctypes.byref(mv)),
-           "kmc_rs_run")
+    _check(lib().or_kmc_rs_run(occ.shape[0], float(eps), seed, t0, n_mcs, occ, ctypes.byref(mv)),
+           "or_kmc_rs_run")
     return mv.value
 
 
@@ -84,33 +84,33 @@ def dt_run(occ: np.ndarray, eps: float, seed: int, block: int, t0: int, n_mcs: i
         assert counts.dtype == np.int32 and counts.flags.c_contiguous
         assert counts.size == occ.size // 2
         ptr = counts.ctypes.data
-    _check(lib().kmc_dt_run(occ.shape[0], float(eps), seed, block, t0, n_mcs, occ,
-                            ctypes.byref(mv), int(check), ptr), "kmc_dt_run")
+    _check(lib().or_kmc_dt_run(occ.shape[0], float(eps), seed, block, t0, n_mcs, occ,
+                            ctypes.byref(mv), int(check), ptr), "or_kmc_dt_run")
     return mv.value
 
 
 def attempt(occ: np.ndarray, eps: float, x: int, y: int, z: int, nb: int, u: int) -> int:
-    rc = lib().kmc_attempt(occ.shape[0], float(eps), occ, x, y, z, nb, u)
-    _check(min(rc, 0), "kmc_attempt")
+    rc = lib().or_kmc_attempt(occ.shape[0], float(eps), occ, x, y, z, nb, u)
+    _check(min(rc, 0), "or_kmc_attempt")
     return rc
 
 
 def counts(occ: np.ndarray):
     """(number of B, number of B-B nearest-neighbour bonds)."""
     nB, bonds = ctypes.c_int64(0), ctypes.c_int64(0)
-    lib().kmc_counts(occ.shape[0], occ, ctypes.byref(nB), ctypes.byref(bonds))
+    lib().or_kmc_counts(occ.shape[0], occ, ctypes.byref(nB), ctypes.byref(bonds))
     return nB.value, bonds.value
 
 
 def order(seed: int, t: int) -> list:
     p = np.zeros(8, np.int32)
-    lib().kmc_order(seed, t, p)
+    lib().or_kmc_order(seed, t, p)
     return [int(v) for v in p]
 
 
 def origin(seed: int, t: int, block: int) -> tuple:
     o = np.zeros(3, np.int32)
-    lib().kmc_origin(seed, t, block, o)
+    lib().or_kmc_origin(seed, t, block, o)
     return tuple(int(v) for v in o)
 
 

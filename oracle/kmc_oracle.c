@@ -65,7 +65,7 @@ static inline size_t pos(int L, int x, int y, int z)
 }
 
 /* Thresholds T[d] = floor(exp(-d eps) 2^32) for d = 0..12 (T[0] = 2^32). */
-void kmc_thresholds(double eps, uint64_t T[13])
+void or_kmc_thresholds(double eps, uint64_t T[13])
 {
     T[0] = (uint64_t)1 << 32;
     for (int d = 1; d <= 12; ++d) {
@@ -85,7 +85,7 @@ static void site_pos(int L, uint64_t s, int *x, int *y, int *z)
     *x = (int)(2 * k + (uint64_t)((*y + *z) & 1));
 }
 
-int kmc_init(int L, double c, uint64_t seed, uint8_t *occ)
+int or_kmc_init(int L, double c, uint64_t seed, uint8_t *occ)
 {
     if (L < 4 || (L & 1)) return KMC_EINVAL;
     const uint64_t C = c >= 1.0 ? ((uint64_t)1 << 32) : (c <= 0.0 ? 0 : (uint64_t)(c * 4294967296.0));
@@ -137,12 +137,12 @@ static int attempt(int L, uint8_t *occ, const uint64_t T[13], int x, int y, int 
 
 /* Random-sequential dynamics: MCS t0 .. t0 + n_mcs - 1.  *moves counts the
  * accepted jumps. */
-int kmc_rs_run(int L, double eps, uint64_t seed, uint32_t t0, int n_mcs, uint8_t *occ,
+int or_kmc_rs_run(int L, double eps, uint64_t seed, uint32_t t0, int n_mcs, uint8_t *occ,
                int64_t *moves)
 {
     if (L < 4 || (L & 1) || n_mcs < 0) return KMC_EINVAL;
     uint64_t T[13];
-    kmc_thresholds(eps, T);
+    or_kmc_thresholds(eps, T);
     const uint64_t N = (uint64_t)L * L * L / 2;
     uint32_t w[4];
     for (int m = 0; m < n_mcs; ++m) {
@@ -160,7 +160,7 @@ int kmc_rs_run(int L, double eps, uint64_t seed, uint32_t t0, int n_mcs, uint8_t
 }
 
 /* Number of B sites and of B-B nearest-neighbour bonds. */
-void kmc_counts(int L, const uint8_t *occ, int64_t *nB, int64_t *bonds)
+void or_kmc_counts(int L, const uint8_t *occ, int64_t *nB, int64_t *bonds)
 {
     int64_t b = 0, e = 0;
     for (int z = 0; z < L; ++z)
@@ -176,13 +176,13 @@ void kmc_counts(int L, const uint8_t *occ, int64_t *nB, int64_t *bonds)
 
 /* One attempt (exported for the tests): site (x, y, z) must be an fcc
  * position; returns 1 if a B jumped, 0 if not, KMC_EINVAL on bad input. */
-int kmc_attempt(int L, double eps, uint8_t *occ, int x, int y, int z, int nb, uint32_t u)
+int or_kmc_attempt(int L, double eps, uint8_t *occ, int x, int y, int z, int nb, uint32_t u)
 {
     if (L < 4 || (L & 1) || x < 0 || y < 0 || z < 0 || x >= L || y >= L || z >= L ||
         ((x ^ y ^ z) & 1) || nb < 0 || nb > 11)
         return KMC_EINVAL;
     uint64_t T[13];
-    kmc_thresholds(eps, T);
+    or_kmc_thresholds(eps, T);
     return attempt(L, occ, T, x, y, z, nb, u);
 }
 
@@ -218,7 +218,7 @@ int kmc_attempt(int L, double eps, uint8_t *occ, int x, int y, int z, int nb, ui
  * position away from its site); counts, if not NULL, receives per fcc site
  * (fcc index) the number of attempts made at it.
  */
-static void kmc_perm8(uint32_t w0, int perm[8])
+static void or_kmc_perm8(uint32_t w0, int perm[8])
 {
     uint64_t idx = ((uint64_t)w0 * 40320u) >> 32;
     int pool[8] = { 0, 1, 2, 3, 4, 5, 6, 7 };
@@ -235,31 +235,31 @@ static void kmc_perm8(uint32_t w0, int perm[8])
 }
 
 /* Order of the eight block sets in MCS t. */
-void kmc_order(uint64_t seed, uint32_t t, int32_t perm[8])
+void or_kmc_order(uint64_t seed, uint32_t t, int32_t perm[8])
 {
     uint32_t w[4];
     int p[8];
     or_draw(seed, KMC_TAG_ORDER, t, 0, 0, w);
-    kmc_perm8(w[0], p);
+    or_kmc_perm8(w[0], p);
     for (int i = 0; i < 8; ++i) perm[i] = p[i];
 }
 
 /* Block-grid shift of MCS t. */
-void kmc_origin(uint64_t seed, uint32_t t, int B, int32_t o[3])
+void or_kmc_origin(uint64_t seed, uint32_t t, int B, int32_t o[3])
 {
     uint32_t w[4];
     or_draw(seed, KMC_TAG_ORIGIN, t, 0, 0, w);
     for (int i = 0; i < 3; ++i) o[i] = (int32_t)(((uint64_t)w[i] * (uint64_t)B) >> 32);
 }
 
-int kmc_dt_run(int L, double eps, uint64_t seed, int B, uint32_t t0, int n_mcs, uint8_t *occ,
+int or_kmc_dt_run(int L, double eps, uint64_t seed, int B, uint32_t t0, int n_mcs, uint8_t *occ,
                int64_t *moves, int check, int32_t *counts)
 {
     if (L < 16 || (L & 1) || B < 8 || (B & 7) || L % B || ((L / B) & 1) || n_mcs < 0)
         return KMC_EINVAL;
     const int nb = L / B, nt = B / 8, tpb = nt * nt * nt;
     uint64_t T[13];
-    kmc_thresholds(eps, T);
+    or_kmc_thresholds(eps, T);
     int64_t *stamp = check ? (int64_t *)malloc(sizeof(int64_t) * (size_t)L * L * L) : NULL;
     if (check && !stamp) return KMC_ENOMEM;
     if (check)
@@ -270,8 +270,8 @@ int kmc_dt_run(int L, double eps, uint64_t seed, int B, uint32_t t0, int n_mcs, 
     for (int m = 0; m < n_mcs && status == KMC_OK; ++m) {
         const uint32_t t = t0 + (uint32_t)m;
         int32_t o[3], perm[8];
-        kmc_origin(seed, t, B, o);
-        kmc_order(seed, t, perm);
+        or_kmc_origin(seed, t, B, o);
+        or_kmc_order(seed, t, perm);
         for (int ph = 0; ph < 8 && status == KMC_OK; ++ph) {
             const int c = perm[ph];
             for (int k = 0; k < 256 && status == KMC_OK; ++k, ++step_id) {
