@@ -1,7 +1,7 @@
 /*
  * kmc.h -- C ABI of the gfx950 kinetic lattice Monte Carlo of a binary alloy
  * (Kelling, Odor, Nagy, Schulz, Heinig, Sec. 2.2 "Kinetic Monte Carlo" and
- * Sec. 3 "Implementation of KMC").  Part of libkpz.so.
+ * Sec. 3.2 "Implementation of KMC").  Part of libkpz.so.
  *
  * Model:
  *   - Sites: the fcc lattice stored as the sub-lattice of an L x L x L
@@ -24,7 +24,7 @@
  *     B^3 positions in eight sets (block parities), updated set after set in
  *     an order drawn per MCS, the block grid shifted by a random origin per
  *     MCS; inside a block, tiles of 8^3 positions bisected into eight cells
- *     of 4^3, 256 single-hit steps per block (Sec. 3, "Implementation of
+ *     of 4^3, 256 single-hit steps per block (Sec. 3.2, "Implementation of
  *     KMC").  All random numbers are Philox4x32-10 draws keyed by the seed;
  *     results are reproducible and independent of the device.
  *

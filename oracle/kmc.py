@@ -2,7 +2,7 @@
 
 Wraps ``kmc_oracle.c`` (Sec. 2.2 "Kinetic Monte Carlo": fcc sub-lattice of
 a simple cubic grid, eq. ``fcc``; Metropolis exchange, eq. ``metropolis``
-with Gamma = 1; Sec. 3 "Implementation of KMC": double tiling at both
+with Gamma = 1; Sec. 3.2 "Implementation of KMC": double tiling at both
 layers, both species active).  Only ``tests/``, ``__graft_entry__.smoke()``
 and the ``cpu_baseline`` leg of ``bench.py`` may use it.
 

@@ -3,7 +3,7 @@
  *
  * Plain CPU oracle for the paper's second workload, the kinetic lattice
  * Monte Carlo model of a binary alloy (Kelling, Odor, Nagy, Schulz, Heinig,
- * Sec. 2.2 "Kinetic Monte Carlo" and Sec. 3 "Implementation of KMC"):
+ * Sec. 2.2 "Kinetic Monte Carlo" and Sec. 3.2 "Implementation of KMC"):
  *
  * Lattice.  An fcc lattice stored as the sub-lattice of an L x L x L simple
  * cubic grid (L even, periodic): position (x, y, z) is a site iff
@@ -189,7 +189,7 @@ int or_kmc_attempt(int L, double eps, uint8_t *occ, int x, int y, int z, int nb,
 /* ------------------------------------------ decomposed schedule (Sec. 3) */
 
 /*
- * Double tiling at both layers, as in the paper's GPU KMC code (Sec. 3,
+ * Double tiling at both layers, as in the paper's GPU KMC code (Sec. 3.2,
  * "Implementation of KMC"):
  *
  * Device layer.  Blocks of B x B x B cubic positions (B a multiple of 8,

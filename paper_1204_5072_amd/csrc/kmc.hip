@@ -1,5 +1,5 @@
 // kmc.hip -- kinetic lattice Monte Carlo of a binary alloy on gfx950
-// (Sec. 2.2 "Kinetic Monte Carlo", eqs. fcc and metropolis; Sec. 3
+// (Sec. 2.2 "Kinetic Monte Carlo", eqs. fcc and metropolis; Sec. 3.2
 // "Implementation of KMC").
 //
 // Kernels:

@@ -1,5 +1,5 @@
 """GPU parity of the KMC binary alloy (Sec. 2.2 "Kinetic Monte Carlo";
-Sec. 3 "Implementation of KMC") against the oracle's doubly tiled schedule:
+Sec. 3.2 "Implementation of KMC") against the oracle's doubly tiled schedule:
 every site byte, the accepted-jump count and the B / bond counts after each
 call, bit for bit, from small lattices with one block per set up to the
 512^3 / 2 quench benchmark (c = 0.325, eps = 1.5)."""

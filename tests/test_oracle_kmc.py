@@ -1,5 +1,5 @@
 """Pins of the KMC binary-alloy oracle (Sec. 2.2 "Kinetic Monte Carlo",
-eqs. ``fcc`` and ``metropolis``; Sec. 3 "Implementation of KMC").
+eqs. ``fcc`` and ``metropolis``; Sec. 3.2 "Implementation of KMC").
 
 What fixes the oracle here, independently of its own code:
 
