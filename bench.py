@@ -217,16 +217,54 @@ def ring_leg(args):
     block = int(r.params.block) or 128
     r.close()
     gbs = 0.25 * L / (ms * 1e-3) / 1e9
+    valu = ring_valu_per_mcs()
+    if valu is None:
+        roof = {"bound": "alu", "achieved": None, "peak": VALU_ISSUE_PEAK / 1e9,
+                "unit": "G wave-instr/s", "frac": None,
+                "note": "VALU count not measured for this source"}
+    else:
+        rate = valu / (ms * 1e-3)
+        roof = {"bound": "alu", "achieved": rate / 1e9, "peak": VALU_ISSUE_PEAK / 1e9,
+                "unit": "G wave-instr/s", "frac": rate / VALU_ISSUE_PEAK,
+                "valu_wave_instr_per_mcs": valu}
+    roof.update({"hbm_achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                 "bytes_per_attempt": 0.25})
     return {
         "metric": "site-update attempts/s, 1+1-d ring L=2^30",
         "value": L / (ms * 1e-3),
         "unit": "attempts/s",
         "ms_per_mcs": ms,
         "block": block,
-        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "bytes_per_attempt": 0.25},
+        "roofline": roof,
         "w2_t22": m.W2,
     }
+
+
+# VALU issue limit: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every
+# 4 cycles at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def ring_valu_per_mcs():
+    """VALU wave instructions per ring MCS (sweep + merge launch) from the
+    committed counter summary, or None when kpz_ring.hip or the device
+    helpers changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "kpz_ring_L2p30_kernel_trace.md")
+    csrc = os.path.join(ROOT, "paper_1204_5072_amd", "csrc")
+    try:
+        text = open(path).read()
+        h = hashlib.sha256()
+        for f in ("kpz_ring.hip", "kpz_device.h"):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    except OSError:
+        return None
+    m = re.search(r"source_sha256 = ([0-9a-f]{64})", text)
+    if not m or m.group(1) != h.hexdigest():
+        return None
+    m = re.search(r"valu_wave_instr_per_mcs = (\d+)", text)
+    return float(m.group(1)) if m else None
 
 
 def kmc_leg(args):
@@ -308,15 +346,19 @@ def serving_leg(args):
 
 def measured_traffic(block, in_place=False):
     """HBM bytes per MCS (sweep + merge) of this block shape from the
-    committed hardware-counter summary, or None when the library source has
-    changed since the counters were taken (or the shape was not measured)."""
+    committed hardware-counter summary, or None when the sweep's source
+    (kpz.hip and the device helpers it includes) has changed since the
+    counters were taken, or the shape was not measured."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "kpz_sweep_L65536_hbm_counters.md")
-    src = os.path.join(ROOT, "paper_1204_5072_amd", "csrc", "kpz.hip")
+    csrc = os.path.join(ROOT, "paper_1204_5072_amd", "csrc")
     try:
         text = open(path).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for f in ("kpz.hip", "kpz_device.h"):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+        sha = h.hexdigest()
     except OSError:
         return None
     m = re.search(r"source_sha256 = ([0-9a-f]{64})", text)
