@@ -482,14 +482,15 @@ void or_dd_origin(uint64_t seed, uint32_t t, int res, int Bx, int By, int *ox, i
  *
  * Work-group layer.  Tiles of 4 sites, bisected into two cells of 2 sites
  * (set 0: sites 0, 1; set 1: sites 2, 3 of the tile); S = 4 single-hit
- * steps per MCS.  In step k block b uses set bit k of w0 of draw
- * (SET1D, t, b, 0) and tile m attempts site 4 m + 2 set + r.  Attempts of
- * one step are at least three sites apart.
+ * steps per MCS.  In step k block b uses set bit 4 (b mod 8) + k of word
+ * (b mod 32) / 8 of draw (SET1D, t, b / 32, 0) (one draw serves 32 blocks)
+ * and tile m attempts site 4 m + 2 set + r.  Attempts of one step are at
+ * least three sites apart.
  *
  * Draws.  Tile m of block b is tile mm = m mod 8 of block word wl = m / 8
  * (a packed word holds 32 sites = 8 tiles); with nt = B/4 tiles per block,
  * n4 = ceil(nt/32) and n2 = ceil(nt/16):
- *   r = bit 8k + mm of word (wl mod 4) of draw (SITE1D, t, b n4 + wl/4, 0);
+ *   r = bit 4 mm + k of word (wl mod 4) of draw (SITE1D, t, b n4 + wl/4, 0);
  *   u = A << 24 | (C & 0xFFFFFF) with A = byte (mm mod 4) of word
  *       2 (wl mod 2) + mm/4 of draw (ACC1D, t, b n2 + wl/2, k) and
  *       C = w0 of draw (ACC1D2, t, b nt + m, k) (needed only on a tie of A).
@@ -546,12 +547,12 @@ int or_dd1d_run(int L, double p, double q, uint64_t seed, int B, uint32_t t0, in
         const int o = (int)(((uint64_t)w[0] * (uint64_t)B) >> 32);
         for (int k = 0; k < 4 && status == OR_OK; ++k, ++step_id) {
             for (int b = 0; b < nb; ++b) {
-                or_draw(seed, OR_TAG_SET1D, t, (uint64_t)b, 0, w);
-                const int set = (int)((w[0] >> k) & 1u);
+                or_draw(seed, OR_TAG_SET1D, t, (uint64_t)(b / 32), 0, w);
+                const int set = (int)((w[(b % 32) / 8] >> (4 * (b % 8) + k)) & 1u);
                 for (int m = 0; m < nt; ++m) {
                     const int wl = m / 8, mm = m % 8;
                     or_draw(seed, OR_TAG_SITE1D, t, (uint64_t)b * n4 + (uint64_t)(wl / 4), 0, w);
-                    const int r = (int)((w[wl % 4] >> (8 * k + mm)) & 1u);
+                    const int r = (int)((w[wl % 4] >> (4 * mm + k)) & 1u);
                     const int lx = 4 * m + 2 * set + r;
                     if (nb > 1 && lx == 0) continue;
                     const int i = (int)(((int64_t)o + (int64_t)b * B + lx) % L);
@@ -586,12 +587,12 @@ int or_dd1d_block_mcs(int L, double p, double q, uint64_t seed, int B, uint32_t 
     uint32_t w[4];
     int64_t h0_unused = 0;
     for (int k = 0; k < 4; ++k) {
-        or_draw(seed, OR_TAG_SET1D, t, (uint64_t)b, 0, w);
-        const int set = (int)((w[0] >> k) & 1u);
+        or_draw(seed, OR_TAG_SET1D, t, (uint64_t)(b / 32), 0, w);
+        const int set = (int)((w[(b % 32) / 8] >> (4 * (b % 8) + k)) & 1u);
         for (int m = 0; m < nt; ++m) {
             const int wl = m / 8, mm = m % 8;
             or_draw(seed, OR_TAG_SITE1D, t, (uint64_t)b * n4 + (uint64_t)(wl / 4), 0, w);
-            const int r = (int)((w[wl % 4] >> (8 * k + mm)) & 1u);
+            const int r = (int)((w[wl % 4] >> (4 * mm + k)) & 1u);
             const int lx = 4 * m + 2 * set + r;
             if (lx == 0) continue;
             /* block-local ring of B bonds; lx >= 1 never wraps */

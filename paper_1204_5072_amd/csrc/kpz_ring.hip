@@ -18,10 +18,12 @@
 //   origin    o = w0 * B >> 32 of (ORIGIN1D, t, 0, 0); block b covers sites
 //             (o + b B + lx) mod L; lx = 0 is dead when there are >1 blocks
 //   tiles     4 sites = two cells of 2 sites (set 0: sites 0,1; set 1: 2,3)
-//   4 steps   step k: block set = bit k of w0 of (SET1D, t, b, 0); tile m
+//   4 steps   step k: block set = bit 4 (b mod 8) + k of word (b mod 32) / 8
+//             of (SET1D, t, b / 32, 0), one draw per 32 blocks; tile m
 //             attempts site 4m + 2 set + r
 //   sites     tile m = tile mm (= m mod 8) of block word wl (= m / 8):
-//             r = bit 8k + mm of word wl mod 4 of (SITE1D, t, b B/128 + wl/4, 0)
+//             r = bit 4 mm + k of word wl mod 4 of (SITE1D, t, b B/128 + wl/4, 0),
+//             so that the draw bits of step k sit on the tiles' nibbles
 //   accept    u = A << 24 | (C & 0xFFFFFF): A = byte mm mod 4 of word
 //             2 (wl mod 2) + mm / 4 of (ACC1D, t, b B/64 + wl/2, k);
 //             C = w0 of (ACC1D2, t, b B/4 + m, k), drawn only on a tie of A
@@ -189,7 +191,16 @@ __global__ __launch_bounds__(64) void kpz_ring_sweep_kernel(const RingArgs a)
         sw[j + 2] = s4.z;
         sw[j + 3] = s4.w;
     }
-    const uint32_t setw = philox(b, 0u, a.t, TAG_SET1D << 24, a.seed_lo, a.seed_hi).x;
+    // set bits: one draw per 32 blocks; the wave's two draws are uniform
+    // (scalar unit), each lane picks its block's 4 bits
+    const U4 st0 = philox(2u * w, 0u, a.t, TAG_SET1D << 24, a.seed_lo, a.seed_hi);
+    const U4 st1 = philox(2u * w + 1u, 0u, a.t, TAG_SET1D << 24, a.seed_lo, a.seed_hi);
+    const bool hi32 = lane >= 32u;
+    const uint32_t q8 = (lane >> 3) & 3u;
+    const uint32_t sx = hi32 ? st1.x : st0.x, sy = hi32 ? st1.y : st0.y;
+    const uint32_t sz = hi32 ? st1.z : st0.z, sww = hi32 ? st1.w : st0.w;
+    const uint32_t sword = q8 == 0 ? sx : (q8 == 1 ? sy : (q8 == 2 ? sz : sww));
+    const uint32_t setw = sword >> (4u * (lane & 7u));
 
     RingAcc ac;
     ac.fullP = a.P >= (1ull << 32);
@@ -213,7 +224,7 @@ __global__ __launch_bounds__(64) void kpz_ring_sweep_kernel(const RingArgs a)
                 const uint32_t prev = j ? c[j - 1] : (single ? c[K - 1] : 0u);
                 const uint32_t l = (c[j] << 1) | (prev >> 31);
                 const uint32_t mn = ~l & c[j];
-                const uint32_t R = spread8(sw[j] >> (8 * k));
+                const uint32_t R = (sw[j] >> k) & 0x11111111u;
                 uint32_t sel = ((0x11111111u & ~R) | (R << 1)) << (2 * set);
                 if (j == 0 && !single) sel &= ~1u;
                 if (ACC) {
