@@ -51,6 +51,9 @@ using kpzdev::U4;
 
 constexpr uint32_t TAG_INIT = 16, TAG_ORIGIN = 18, TAG_ORDER = 19, TAG_SET = 20, TAG_STEP = 21;
 constexpr int STEPS = 256;          // fcc sites per 8^3 tile: single-hit steps per block turn
+constexpr uint32_t MOVE_SLOTS = 64;  // accepted-jump counters (workspace words 0..63)
+constexpr uint32_t COUNT_OFF = 64;   // B and bond counts (workspace words 64, 65)
+constexpr uint32_t COUNT_BLOCKS = 1024;
 
 struct PhaseArgs {
     uint8_t *occ;
@@ -375,7 +378,10 @@ __global__ __launch_bounds__(NTHREADS) void kmc_phase_kernel(PhaseArgs a)
     // accepted jumps: wave 0 holds them all
     if (threadIdx.x < 64) {
         for (int off = 32; off > 0; off >>= 1) mv += __shfl_xor(mv, off, 64);
-        if (threadIdx.x == 0 && mv) atomicAdd(a.moves, (unsigned long long)mv);
+        // spread over MOVE_SLOTS counters: same-address atomics from every
+        // work-group of a launch would serialise in L2
+        if (threadIdx.x == 0 && mv)
+            atomicAdd(a.moves + (blockIdx.x & (MOVE_SLOTS - 1)), (unsigned long long)mv);
     }
 }
 
@@ -396,39 +402,64 @@ __global__ void kmc_fill_kernel(unsigned long long *p, uint32_t n, unsigned long
     if (i < n) p[i] = v;
 }
 
-// res[0] += number of B, res[1] += B-B bonds (each counted once, through the
-// six neighbours with a positive first nonzero offset among (x, y, z) ordered
-// as (+1,+1,0) (+1,-1,0) (+1,0,+1) (+1,0,-1) (0,+1,+1) (0,+1,-1)).
-__global__ void kmc_count_kernel(const uint8_t *occ, uint32_t L, unsigned long long *res)
+// res[0] += number of B, res[1] += B-B bonds, each bond counted once through
+// the six neighbours (+1,+1,0) (+1,-1,0) (+1,0,+1) (+1,0,-1) (0,+1,+1)
+// (0,+1,-1).  A thread takes one compact word (4 sites x = 2(4w + j) + p of
+// row (y, z), p = (y + z) mod 2).  The x+1 neighbours lie in rows of the
+// other parity at compact index 4w + j + p: bytes p.. of words w, w + 1 of
+// those rows; the (0, +1, +-1) neighbours lie at index 4w + j of rows of the
+// same parity.  Sites are bytes 0/1, so a bond is a byte of (own & other)
+// and the byte sums never carry (at most 6 per byte).
+__device__ __forceinline__ uint32_t byte_sum(uint32_t v) { return (v * 0x01010101u) >> 24; }
+
+__global__ void kmc_count_kernel(const uint8_t *occ, uint32_t L, uint32_t log2L,
+                                 unsigned long long *res)
 {
-    const uint32_t Lm = L - 1, half = L >> 1;
-    const uint64_t n = (uint64_t)L * L * half;
+    const uint32_t *occw = (const uint32_t *)occ;
+    const uint32_t Lm = L - 1, WL = L >> 3, WLm = WL - 1;
+    const uint64_t n = (uint64_t)L * L * WL;            // words
     unsigned long long nb = 0, bonds = 0;
-    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
-         s += (uint64_t)gridDim.x * blockDim.x) {
-        if (!occ[s]) continue;
-        const uint64_t row = s / half;
-        const uint32_t k = (uint32_t)(s - row * half);
-        const uint32_t y = (uint32_t)(row & Lm), z = (uint32_t)(row / L);
-        const uint32_t x = 2 * k + ((y + z) & 1u);
-        const int D[6][3] = {{1, 1, 0}, {1, -1, 0}, {1, 0, 1}, {1, 0, -1}, {0, 1, 1}, {0, 1, -1}};
-        uint32_t m = 0;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            const uint32_t xx = (x + L + D[q][0]) & Lm, yy = (y + L + D[q][1]) & Lm,
-                           zz = (z + L + D[q][2]) & Lm;
-            m += occ[((uint64_t)zz * L + yy) * half + (xx >> 1)];
-        }
-        ++nb;
-        bonds += m;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        // L is a power of two: rows and planes by shifts
+        const uint32_t row = (uint32_t)(e >> (log2L - 3));
+        const uint32_t w = (uint32_t)e & WLm;
+        const uint32_t y = row & Lm, z = row >> log2L;
+        const uint32_t p = (y + z) & 1u;
+        const uint32_t own = occw[e];
+        const uint32_t yp = (y + 1) & Lm, ym = (y + Lm) & Lm, zp = (z + 1) & Lm, zm = (z + Lm) & Lm;
+        const uint32_t w1 = (w + 1) & WLm;
+        const uint64_t r1 = ((uint64_t)z * L + yp) * WL, r2 = ((uint64_t)z * L + ym) * WL;
+        const uint64_t r3 = ((uint64_t)zp * L + y) * WL, r4 = ((uint64_t)zm * L + y) * WL;
+        const uint64_t r5 = ((uint64_t)zp * L + yp) * WL, r6 = ((uint64_t)zm * L + yp) * WL;
+        const uint32_t a = __builtin_amdgcn_alignbyte(occw[r1 + w1], occw[r1 + w], p);
+        const uint32_t b = __builtin_amdgcn_alignbyte(occw[r2 + w1], occw[r2 + w], p);
+        const uint32_t c = __builtin_amdgcn_alignbyte(occw[r3 + w1], occw[r3 + w], p);
+        const uint32_t d = __builtin_amdgcn_alignbyte(occw[r4 + w1], occw[r4 + w], p);
+        const uint32_t f = occw[r5 + w], g = occw[r6 + w];
+        const uint32_t m = (own & a) + (own & b) + (own & c) + (own & d) + (own & f) + (own & g);
+        nb += byte_sum(own);
+        bonds += byte_sum(m);
     }
     for (int off = 32; off > 0; off >>= 1) {
         nb += __shfl_xor(nb, off, 64);
         bonds += __shfl_xor(bonds, off, 64);
     }
+    // one atomic pair per work-group (at most COUNT_BLOCKS of them)
+    __shared__ unsigned long long part[2][4];
     if ((threadIdx.x & 63) == 0) {
-        if (nb) atomicAdd(&res[0], nb);
-        if (bonds) atomicAdd(&res[1], bonds);
+        part[0][threadIdx.x >> 6] = nb;
+        part[1][threadIdx.x >> 6] = bonds;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0, b = 0;
+        for (uint32_t i = 0; i < blockDim.x / 64; ++i) {
+            a += part[0][i];
+            b += part[1][i];
+        }
+        if (a) atomicAdd(&res[0], a);
+        if (b) atomicAdd(&res[1], b);
     }
 }
 
@@ -440,7 +471,7 @@ struct kmc_sim {
     kmc_params prm;
     int32_t B;
     uint8_t *occ;
-    unsigned long long *ws;         // [0] accepted jumps, [1] n_b, [2] bonds
+    unsigned long long *ws;         // [0, 64) accepted-jump slots, [64] n_b, [65] bonds
     hipStream_t stream;
     int64_t t;
     unsigned long long T[13];
@@ -449,7 +480,7 @@ struct kmc_sim {
 
 namespace {
 
-constexpr size_t KMC_WS = 256;
+constexpr size_t KMC_WS = 8 * (COUNT_OFF + 2);
 
 kpz_status kmc_resolve(const kmc_params *p, int32_t *B)
 {
@@ -519,7 +550,8 @@ kpz_status kmc_init(kmc_sim **out, const kmc_params *p, uint8_t *d_occ, size_t o
     const uint32_t grid = (uint32_t)((n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384);
     hipLaunchKernelGGL(kmc_init_kernel, dim3(grid), dim3(256), 0, s->stream, d_occ, n, C,
                        (uint32_t)p->seed, (uint32_t)(p->seed >> 32));
-    hipLaunchKernelGGL(kmc_fill_kernel, dim3(1), dim3(64), 0, s->stream, s->ws, 3u, 0ull);
+    hipLaunchKernelGGL(kmc_fill_kernel, dim3(1), dim3(128), 0, s->stream, s->ws, COUNT_OFF + 2,
+                       0ull);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         kmc_fail(s, e, "kmc_init launch");
@@ -567,14 +599,16 @@ kpz_status kmc_counts(kmc_sim *s, int64_t *n_b, int64_t *bonds)
     if (!s) return KPZ_EINVAL;
     const uint32_t L = (uint32_t)s->prm.L;
     const uint64_t n = (uint64_t)L * L * L / 2;
-    const uint32_t grid = (uint32_t)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
-    hipLaunchKernelGGL(kmc_fill_kernel, dim3(1), dim3(64), 0, s->stream, s->ws + 1, 2u, 0ull);
+    const uint32_t grid = (uint32_t)((n / 4 + 255) / 256 < COUNT_BLOCKS ? (n / 4 + 255) / 256
+                                                                         : COUNT_BLOCKS);
+    hipLaunchKernelGGL(kmc_fill_kernel, dim3(1), dim3(64), 0, s->stream, s->ws + COUNT_OFF, 2u,
+                       0ull);
     hipLaunchKernelGGL(kmc_count_kernel, dim3(grid), dim3(256), 0, s->stream,
-                       (const uint8_t *)s->occ, L, s->ws + 1);
+                       (const uint8_t *)s->occ, L, (uint32_t)__builtin_ctz(L), s->ws + COUNT_OFF);
     hipError_t e = hipGetLastError();
     unsigned long long r[2] = {0, 0};
     if (e == hipSuccess)
-        e = hipMemcpyAsync(r, s->ws + 1, sizeof r, hipMemcpyDeviceToHost, s->stream);
+        e = hipMemcpyAsync(r, s->ws + COUNT_OFF, sizeof r, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return kmc_fail(s, e, "kmc_counts");
     if (n_b) *n_b = (int64_t)r[0];
@@ -585,10 +619,12 @@ kpz_status kmc_counts(kmc_sim *s, int64_t *n_b, int64_t *bonds)
 kpz_status kmc_get_state(kmc_sim *s, int64_t *t, int64_t *moves)
 {
     if (!s) return KPZ_EINVAL;
-    unsigned long long m = 0;
-    hipError_t e = hipMemcpyAsync(&m, s->ws, sizeof m, hipMemcpyDeviceToHost, s->stream);
+    unsigned long long slots[MOVE_SLOTS];
+    hipError_t e = hipMemcpyAsync(slots, s->ws, sizeof slots, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return kmc_fail(s, e, "kmc_get_state");
+    unsigned long long m = 0;
+    for (uint32_t i = 0; i < MOVE_SLOTS; ++i) m += slots[i];
     if (t) *t = s->t;
     if (moves) *moves = (int64_t)m;
     return KPZ_OK;
@@ -597,6 +633,7 @@ kpz_status kmc_get_state(kmc_sim *s, int64_t *t, int64_t *moves)
 kpz_status kmc_set_state(kmc_sim *s, int64_t t, int64_t moves)
 {
     if (!s || t < 0 || t > 0xFFFFFFFFll || moves < 0) return KPZ_EINVAL;
+    hipLaunchKernelGGL(kmc_fill_kernel, dim3(1), dim3(64), 0, s->stream, s->ws, MOVE_SLOTS, 0ull);
     hipLaunchKernelGGL(kmc_fill_kernel, dim3(1), dim3(64), 0, s->stream, s->ws, 1u,
                        (unsigned long long)moves);
     const hipError_t e = hipGetLastError();
