@@ -509,7 +509,7 @@ def main():
             # one MCS = one sweep launch (two-buffer mode), or the sweep launch
             # plus the straddling-word merge launch (in place), bracketed
             # together by the events
-            "kernel": ("kpz_dt_sweep_kernel x4 phases" if args.device_dt else
+            "kernel": ("kpz_dt_swar_kernel x4 phases" if args.device_dt else
                        "kpz_sweep_kernel+kpz_merge_kernel" if args.in_place else "kpz_sweep_kernel"),
             "mean_launch_ms": sweep_ms,
             "ops_per_attempt": OPS_PER_ATTEMPT,

@@ -100,10 +100,10 @@ typedef enum {
  *            non-adjacent blocks (bx mod 2, by mod 2; L / block_x and
  *            L / block_y must be even), run in a random order every MCS,
  *            one launch per set, each block with all its sites live.  A
- *            different schedule (different results), updated in place by a
- *            plain one-byte-per-site kernel; needs (block_y + 1) *
- *            (block_x + 4) <= 65536 and moves <= 1; not for batches or
- *            pools.
+ *            different schedule (different results), updated in place; a
+ *            block reads and writes the slopes of its left neighbour's
+ *            last column and its lower neighbour's top row (both idle in
+ *            that launch).  Needs moves <= 1; not for batches or pools.
  * The shape and `moves` change the sequence of updates, so results are
  * reproducible for identical (L, p, q, seed, block, tile, moves) only. */
 typedef struct {

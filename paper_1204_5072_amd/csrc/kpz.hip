@@ -204,15 +204,22 @@ struct AccCtx {
 // One single-hit attempt in each of the four tiles of a quad.  ca, la, da:
 // LDS indices of the quad's own cells (set s), the cells to the left (set
 // s^1) and the cells below (set s^2).
-template <int SX, int SY, bool ACC>
+//
+// DT (double tiling at the device layer): with splice set (a bottom-row quad
+// and sy = 0) the lower cell of byte 0 is the halo byte at LDS index hb (the
+// block below), not byte 3 of the block's top quad row.
+template <int SX, int SY, bool ACC, bool DT>
 __device__ __forceinline__ void quad_update(uint32_t *lds, uint32_t ca, uint32_t la, uint32_t da,
                                             uint32_t rot, uint32_t D, uint32_t dm, bool lok,
                                             uint32_t Aw, const AccCtx &ac, uint64_t G, uint32_t k,
-                                            const SweepArgs &a, int &net)
+                                            const SweepArgs &a, int &net, bool splice = false,
+                                            uint32_t hb = 0)
 {
     const uint32_t c = lds[ca];
     const uint32_t l = lds[la];
-    const uint32_t d = SY ? lds[da] : rotr(lds[da], rot);
+    const uint32_t top = SY ? 0u : lds[da];
+    uint32_t d = SY ? lds[da] : rotr(top, rot);
+    if (DT && !SY && splice) d = (d & ~0xFFu) | (lds[hb] & 0xFFu);
     // one-hot sigma_x position 2r of each tile's chosen site
     const uint32_t oh = __builtin_amdgcn_perm(0u, 0x40100401u, D) & ~dm;
     // neighbour slopes moved onto each site's own bit positions:
@@ -258,11 +265,21 @@ __device__ __forceinline__ void quad_update(uint32_t *lds, uint32_t ca, uint32_t
     const uint32_t md = (F & 0x05050505u) << 5;
     lds[ca] = c ^ mc;
     if (SX || lok) lds[la] = l ^ ml;
-    lds[da] = SY ? (d ^ md) : rotr(d ^ md, (32u - rot) & 31u);
+    if (SY) {
+        lds[da] = d ^ md;
+    } else if (DT && splice) {
+        // bytes 1..3 go back to the top quad row (bytes 0..2), byte 0 to the
+        // halo; the top row's byte 3 keeps its value
+        const uint32_t nd = d ^ md;
+        lds[da] = (rotr(nd, 8u) & 0x00FFFFFFu) | (top & 0xFF000000u);
+        lds[hb] = nd & 0xFFu;
+    } else {
+        lds[da] = rotr(d ^ md, (32u - rot) & 31u);
+    }
 }
 
 // All quads of this thread for one step with cell set (SX, SY).
-template <int TPB, int K, int NTX, int SX, int SY, bool ACC>
+template <int TPB, int K, int NTX, int SX, int SY, bool ACC, bool DT>
 __device__ __forceinline__ void step_quads(uint32_t *lds, uint32_t tid, uint32_t kr,
                                            const uint32_t (&sw)[K][4], const uint32_t (&aw)[K][4],
                                            const AccCtx &ac, uint64_t Gbase, uint32_t k,
@@ -285,17 +302,33 @@ __device__ __forceinline__ void step_quads(uint32_t *lds, uint32_t tid, uint32_t
         // row the top quad row, one byte down
         const uint32_t dq = SY ? q : (bottom ? q + (a.H - 1) * ntx : q - ntx);
         const uint32_t rot = bottom ? 24u : 0u;
-        const uint32_t dm = (ledge && a.nbx > 1 ? 0x11111111u : 0u) |
-                            (bottom && a.nby > 1 ? 0x00000005u : 0u);
-        const bool lok = !ledge || a.nbx == 1;
-        const uint32_t D = (sw[i][0] >> (2 * kr)) & 0x03030303u;
-        quad_update<SX, SY, ACC>(lds, pc + q, pl + lq, pd + dq, rot, D, dm, lok,
-                                 ACC ? aw[i][0] : 0u, ac, Gbase + q, k, a, net);
+        if constexpr (DT) {
+            // no dead sites: the left cells of the left edge are the halo
+            // column (hcol[sy][qy] after the four planes), the lower cells of
+            // the bottom row's first tile row the halo row (hrow[sx][tx])
+            const uint32_t la = ledge ? 4 * nq + SY * a.H + q / ntx : pl + lq;
+            const uint32_t hb = 4 * nq + 2 * a.H + SX * ntx + (q & (ntx - 1));
+            const uint32_t D = (sw[i][0] >> (2 * kr)) & 0x03030303u;
+            quad_update<SX, SY, ACC, true>(lds, pc + q, la, pd + dq, rot, D, 0u, true,
+                                           ACC ? aw[i][0] : 0u, ac, Gbase + q, k, a, net, bottom,
+                                           hb);
+        } else {
+            const uint32_t dm = (ledge && a.nbx > 1 ? 0x11111111u : 0u) |
+                                (bottom && a.nby > 1 ? 0x00000005u : 0u);
+            const bool lok = !ledge || a.nbx == 1;
+            const uint32_t D = (sw[i][0] >> (2 * kr)) & 0x03030303u;
+            quad_update<SX, SY, ACC, false>(lds, pc + q, pl + lq, pd + dq, rot, D, dm, lok,
+                                            ACC ? aw[i][0] : 0u, ac, Gbase + q, k, a, net);
+        }
     }
 }
 
-// One MCS of dead-border block b (device layer) with the block in LDS.
-template <int TPB, int K, int NTX, bool ACC>
+// One MCS of dead-border block b (device layer) with the block in LDS.  DT:
+// block b of a double-tiling set instead (no dead sites, in place): the
+// left neighbour's last column and the lower neighbour's top row are loaded
+// as halos after the four planes, and written back (read-modify-write of
+// the slopes this block may flip) after the block's own words.
+template <int TPB, int K, int NTX, bool ACC, bool DT = false>
 __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint32_t *lds)
 {
     const uint32_t tid = threadIdx.x;
@@ -367,6 +400,39 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
         }
     }
 
+    if constexpr (DT) {
+        // halo column: sigma_x(gx0 - 1, y) of the block's rows, at the bits of
+        // the sx = 1 cells' right-hand sites (2 + 4 ry) of tile j = byte j
+        const uint32_t xh = gx0 == 0 ? a.L - 1 : gx0 - 1;
+        const uint32_t hw = xh >> 4, hbit = 2u * (xh & 15u);
+        for (uint32_t e = tid; e < 2 * a.H; e += TPB) {
+            const uint32_t sy = e / a.H, qy = e - sy * a.H;
+            uint32_t v = 0;
+            for (uint32_t j = 0; j < 4; ++j)
+                for (uint32_t ry = 0; ry < 2; ++ry) {
+                    uint32_t gy = gy0 + 4 * (qy + j * a.H) + 2 * sy + ry;
+                    if (gy >= a.L) gy -= a.L;
+                    const uint32_t bit = (a.src[(size_t)gy * a.W + hw] >> hbit) & 1u;
+                    v |= bit << (8 * j + 2 + 4 * ry);
+                }
+            lds[4 * nq + e] = v;
+        }
+        // halo row: sigma_y(x, gy0 - 1) of the block's columns, at the bits of
+        // the sy = 1 cells' upper sites (5 + 2 rx)
+        const uint32_t yh = gy0 == 0 ? a.L - 1 : gy0 - 1;
+        const uint32_t *hrowp = a.src + (size_t)yh * a.W;
+        for (uint32_t e = tid; e < 2 * ntx; e += TPB) {
+            const uint32_t sx = e / ntx, tx = e - sx * ntx;
+            uint32_t v = 0;
+            for (uint32_t rx = 0; rx < 2; ++rx) {
+                uint32_t x = gx0 + 4 * tx + 2 * sx + rx;
+                if (x >= a.L) x -= a.L;
+                v |= ((hrowp[x >> 4] >> (2u * (x & 15u) + 1u)) & 1u) << (5 + 2 * rx);
+            }
+            lds[4 * nq + 2 * a.H + e] = v;
+        }
+    }
+
     // ---- site draws of this MCS for this thread's quads
     const uint64_t Gbase = (uint64_t)b * nq;
     uint32_t sw[K][4];
@@ -419,10 +485,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
             if (k >= k0 && k < k1) {
                 if (active) {
                     switch (s) {
-                    case 0: step_quads<TPB, K, NTX, 0, 0, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
-                    case 1: step_quads<TPB, K, NTX, 1, 0, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
-                    case 2: step_quads<TPB, K, NTX, 0, 1, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
-                    default: step_quads<TPB, K, NTX, 1, 1, ACC>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
+                    case 0: step_quads<TPB, K, NTX, 0, 0, ACC, DT>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
+                    case 1: step_quads<TPB, K, NTX, 1, 0, ACC, DT>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
+                    case 2: step_quads<TPB, K, NTX, 0, 1, ACC, DT>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
+                    default: step_quads<TPB, K, NTX, 1, 1, ACC, DT>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
                     }
                 }
                 __syncthreads();
@@ -490,6 +556,16 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
                 if (!uok) continue;
                 if (sh2 == 0) {
                     row[gw] = A[h];
+                } else if (DT) {
+                    // the neighbours sharing the end words are idle (blocks of
+                    // one set are not adjacent): merge in place
+                    const uint32_t lowm = (1u << sh2) - 1u;
+                    if (wx > 0) row[gw] = __builtin_amdgcn_alignbit(A[h], prev, 32u - sh2);
+                    else row[gw] = (row[gw] & lowm) | (A[h] << sh2);
+                    if (wx == nw - 1) {
+                        const uint32_t gwn = gw + 1 == a.W ? 0u : gw + 1;
+                        row[gwn] = (row[gwn] & ~lowm) | (A[h] >> (32u - sh2));
+                    }
                 } else {
                     if (wx > 0) row[gw] = __builtin_amdgcn_alignbit(A[h], prev, 32u - sh2);
                     else a.side[(size_t)gy * a.nbx + bx] = A[h] << sh2;
@@ -497,6 +573,45 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
                         a.side[((size_t)a.L + gy) * a.nbx + bx] = A[h] >> (32u - sh2);
                 }
             }
+        }
+    }
+
+    if constexpr (DT) {
+        // ---- halo write-back, after this block's own words (one of which
+        // may hold the halo column's bit)
+        __syncthreads();
+        const uint32_t xh = gx0 == 0 ? a.L - 1 : gx0 - 1;
+        const uint32_t hw = xh >> 4, hbit = 2u * (xh & 15u);
+        for (uint32_t e = tid; e < a.By; e += TPB) {
+            const uint32_t ty = e >> 2, sy = (e >> 1) & 1u, ry = e & 1u;
+            const uint32_t j = ty / a.H, qy = ty - j * a.H;
+            const uint32_t bit = (lds[4 * nq + sy * a.H + qy] >> (8 * j + 2 + 4 * ry)) & 1u;
+            uint32_t gy = gy0 + e;
+            if (gy >= a.L) gy -= a.L;
+            uint32_t *wp = a.words + (size_t)gy * a.W + hw;
+            const uint32_t w0 = *wp;
+            const uint32_t w1 = (w0 & ~(1u << hbit)) | (bit << hbit);
+            if (w1 != w0) *wp = w1;
+        }
+        const uint32_t yh = gy0 == 0 ? a.L - 1 : gy0 - 1;
+        uint32_t *hrowp = a.words + (size_t)yh * a.W;
+        const uint32_t nwr = nw + (sh2 ? 1u : 0u);      // words holding the block's columns
+        for (uint32_t m = tid; m < nwr; m += TPB) {
+            uint32_t gwm = gw0 + m;
+            if (gwm >= a.W) gwm -= a.W;
+            uint32_t val = 0, mask = 0;
+            for (uint32_t i = 0; i < 16; ++i) {
+                uint32_t e = 16 * gwm + i + (a.L - gx0);
+                if (e >= a.L) e -= a.L;
+                if (e >= a.Bx) continue;
+                const uint32_t tx = e >> 2, sx = (e >> 1) & 1u, rx = e & 1u;
+                const uint32_t bit = (lds[4 * nq + 2 * a.H + sx * ntx + tx] >> (5 + 2 * rx)) & 1u;
+                val |= bit << (2 * i + 1);
+                mask |= 1u << (2 * i + 1);
+            }
+            const uint32_t w0 = hrowp[gwm];
+            const uint32_t w1 = (w0 & ~mask) | val;
+            if (w1 != w0) hrowp[gwm] = w1;
         }
     }
 
@@ -560,28 +675,20 @@ __global__ void kpz_merge_kernel(const SweepArgs a)
 // same draws as under dead borders but has no dead sites: an update at its
 // left column or bottom row flips a slope stored in the idle block to the
 // left or below.  Blocks of one set touch disjoint words (for Bx >= 16), so
-// every launch updates the lattice in place with no merge.
-//
-// This kernel keeps one byte per site in LDS (bit 0 sigma_x, bit 1
-// sigma_y) with a halo column (lx = -1) and row (ly = -1): rows of Bx + 4
-// bytes, site lx at byte 4 + lx.  One thread per quad group G (the four
-// tiles (tx, qy + j H) that share a site draw) updates its tiles one after
-// the other; it is the plain counterpart of the SWAR kernel above.
+// every launch updates the lattice in place with no merge.  The block runs
+// in the SWAR kernel above (sweep_block with DT), the left and lower
+// neighbours' slopes as halos.
 
 constexpr uint32_t TAG_DTORDER = 13;
 
-struct DtArgs {
-    uint32_t *words;
-    unsigned long long *slots;
-    uint32_t L, W, Bx, By, nbx, nby, ntx, H, nq, nw;
-    uint32_t seed_lo, seed_hi, t, slot_mask, acc;
-    uint64_t P, Q;
-};
-
-__device__ __forceinline__ uint32_t dt_active_set(const DtArgs &a, uint32_t phase)
+// Block set (bx mod 2 + 2 (by mod 2)) of position `phase` in MCS t: the
+// ordering floor(w0 24 / 2^32) of (DTORDER, t), orderings of 0..3 numbered
+// lexicographically.
+__device__ __forceinline__ uint32_t dt_set(uint32_t t, uint32_t seed_lo, uint32_t seed_hi,
+                                           uint32_t phase)
 {
-    uint32_t idx = (uint32_t)(((uint64_t)philox(0u, 0u, a.t, TAG_DTORDER << 24, a.seed_lo,
-                                                a.seed_hi).x * 24u) >> 32);
+    uint32_t idx = (uint32_t)(((uint64_t)philox(0u, 0u, t, TAG_DTORDER << 24, seed_lo,
+                                                seed_hi).x * 24u) >> 32);
     uint32_t pool = 0x3210u;             // remaining set codes, one per nibble
     uint32_t n = 4, c = 0;
     const uint32_t fact[4] = {1u, 1u, 2u, 6u};
@@ -598,159 +705,21 @@ __device__ __forceinline__ uint32_t dt_active_set(const DtArgs &a, uint32_t phas
     return c;
 }
 
-// 8 site bits (4 sites x 2 bits) -> 4 bytes
-__device__ __forceinline__ uint32_t spread_sites(uint32_t x)
+// The same schedule with the SWAR block kernel: one launch per block set; the
+// blocks of set c are (2 i + (c & 1), 2 j + (c >> 1)).  LDS: the block's four
+// cell planes plus the halo column (2 H words) and row (2 ntx words).
+template <int TPB, int K, int NTX, bool ACC>
+__global__ __launch_bounds__(TPB) void kpz_dt_swar_kernel(const SweepArgs a, uint32_t phase)
 {
-    return (x & 3u) | ((x & 0xCu) << 6) | ((x & 0x30u) << 12) | ((x & 0xC0u) << 18);
-}
-
-__device__ __forceinline__ uint32_t gather_sites(uint32_t v)
-{
-    return (v & 3u) | ((v >> 6) & 0xCu) | ((v >> 12) & 0x30u) | ((v >> 18) & 0xC0u);
-}
-
-template <int TPB>
-__global__ __launch_bounds__(TPB) void kpz_dt_sweep_kernel(const DtArgs a, uint32_t phase)
-{
-    extern __shared__ uint32_t dtl[];
-    uint8_t *site = (uint8_t *)dtl;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t SB = a.Bx + 4;                       // LDS row bytes
-    // active block of this work-group (XCD-aware order when the grid allows)
+    extern __shared__ uint32_t lds[];
     uint32_t g = blockIdx.x;
     if ((gridDim.x & 7u) == 0) g = (g & 7u) * (gridDim.x >> 3) + (g >> 3);
-    const uint32_t c = dt_active_set(a, phase);
+    const uint32_t c = dt_set(a.t, a.seed_lo, a.seed_hi, phase);
     const uint32_t hx = a.nbx >> 1;
     const uint32_t bx = 2 * (g % hx) + (c & 1u), by = 2 * (g / hx) + (c >> 1);
-    const uint32_t b = by * a.nbx + bx;
-    const U4 wo = philox(0u, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
-    const uint32_t ox = (uint32_t)(((uint64_t)wo.x * a.Bx) >> 32);
-    const uint32_t oy = (uint32_t)(((uint64_t)wo.y * a.By) >> 32);
-    const uint32_t x0 = (ox + bx * a.Bx) % a.L, y0 = (oy + by * a.By) % a.L;
-    const uint32_t xs = (x0 + a.L - 1) % a.L;           // halo column
-    const uint32_t shs = 2u * (xs & 15u), gws = xs >> 4;
-    const uint32_t nr = a.nw + 1;                       // range words per row (Bx + 1 sites)
-
-    // ---- load rows ly = -1 .. By-1, sites xs .. xs + Bx, into LDS bytes
-    // (range word k = sites xs + 16 k .. + 15; byte 3 + 16 k .. of the row)
-    const uint32_t nunits = (a.By + 1) * nr;
-    for (uint32_t u = tid; u < nunits; u += TPB) {
-        const uint32_t r = u / nr, k = u % nr;
-        uint32_t gy = y0 + a.L - 1 + r;
-        gy %= a.L;
-        const uint32_t *row = a.words + (size_t)gy * a.W;
-        uint32_t gw = gws + k;
-        if (gw >= a.W) gw -= a.W;
-        const uint32_t gw1 = gw + 1 == a.W ? 0u : gw + 1;
-        const uint32_t v = __builtin_amdgcn_alignbit(row[gw1], row[gw], shs);
-        uint8_t *dst = site + r * SB + 3 + 16 * k;
-        const uint32_t nsites = k + 1 < nr ? 16u : (a.Bx + 1) - 16 * k;
-        for (uint32_t i = 0; i < nsites; ++i) dst[i] = (uint8_t)((v >> (2 * i)) & 3u);
-    }
-    __syncthreads();
-
-    // ---- 16 single-hit steps; this thread's quads q = tid + TPB i (i < 4:
-    // nq <= 1024) with their site words for the MCS and acceptance words
-    // for the current group of four steps
-    constexpr int QM = 4;
-    const uint32_t setw = philox(b, 0u, a.t, TAG_SET << 24, a.seed_lo, a.seed_hi).x;
-    const bool fullP = a.P >= (1ull << 32);
-    uint32_t sw[QM][4], aw[QM][4];
-#pragma unroll
-    for (int i = 0; i < QM; ++i) {
-        const uint64_t G = (uint64_t)b * a.nq + tid + (uint32_t)TPB * i;
-        const U4 w = philox((uint32_t)G, (uint32_t)(G >> 32), a.t, TAG_SITE << 24, a.seed_lo,
-                            a.seed_hi);
-        sw[i][0] = w.x; sw[i][1] = w.y; sw[i][2] = w.z; sw[i][3] = w.w;
-        aw[i][0] = aw[i][1] = aw[i][2] = aw[i][3] = 0u;
-    }
-    int net = 0;
-    for (uint32_t k = 0; k < 16; ++k) {
-        const uint32_t s = (setw >> (2 * k)) & 3u;
-        const uint32_t sx = s & 1u, sy = s >> 1;
-#pragma unroll
-        for (int i = 0; i < QM; ++i) {
-            const uint32_t q = tid + (uint32_t)TPB * i;
-            if (q >= a.nq) continue;
-            const uint32_t tx = q % a.ntx, qy = q / a.ntx;
-            const uint64_t G = (uint64_t)b * a.nq + q;
-            if (a.acc && (k & 3) == 0) {
-                const U4 w = philox((uint32_t)G, (uint32_t)(G >> 32), a.t,
-                                    (TAG_ACC1 << 24) | (k >> 2), a.seed_lo, a.seed_hi);
-                aw[i][0] = w.x; aw[i][1] = w.y; aw[i][2] = w.z; aw[i][3] = w.w;
-            }
-            const uint32_t kq = k >> 2, kr = k & 3;
-            const uint32_t swk = kq == 0 ? sw[i][0] : kq == 1 ? sw[i][1] : kq == 2 ? sw[i][2] : sw[i][3];
-            const uint32_t awk = kr == 0 ? aw[i][0] : kr == 1 ? aw[i][1] : kr == 2 ? aw[i][2] : aw[i][3];
-            for (uint32_t j = 0; j < 4; ++j) {
-                const uint32_t ty = qy + j * a.H;
-                if (ty * 4 >= a.By) break;
-                const uint32_t r = (swk >> (8 * j + 2 * (k & 3))) & 3u;
-                const uint32_t lx = 4 * tx + 2 * sx + (r & 1u), ly = 4 * ty + 2 * sy + (r >> 1);
-                uint8_t *own = site + (ly + 1) * SB + 4 + lx;
-                uint8_t *lft = own - 1;
-                uint8_t *dwn = own - SB;
-                const uint32_t o = *own, l = *lft, d = *dwn;
-                // minimum: own (+1, +1), incoming sigma_x(x-1), sigma_y(y-1) = -1
-                const bool mn = o == 3u && !(l & 1u) && !(d & 2u);
-                const bool mx = o == 0u && (l & 1u) && (d & 2u);
-                if (!mn && !mx) continue;
-                bool acc = mn ? fullP : false;
-                const uint64_t thr = mn ? a.P : a.Q;
-                if (!acc && thr) {
-                    const uint32_t A = (awk >> (8 * j)) & 0xFFu;
-                    const uint32_t tA = (uint32_t)(thr >> 24);
-                    if (A < tA) {
-                        acc = true;
-                    } else if (A == tA && (thr & 0xFFFFFFu)) {
-                        const U4 w2 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t,
-                                             (TAG_ACC2 << 24) | k, a.seed_lo, a.seed_hi);
-                        const uint32_t bw = j == 0 ? w2.x : j == 1 ? w2.y : j == 2 ? w2.z : w2.w;
-                        acc = (bw & 0xFFFFFFu) < (uint32_t)(thr & 0xFFFFFFu);
-                    }
-                }
-                if (!acc) continue;
-                *own = (uint8_t)(o ^ 3u);
-                *lft = (uint8_t)(l ^ 1u);
-                *dwn = (uint8_t)(d ^ 2u);
-                net += mn ? 1 : -1;
-            }
-        }
-        __syncthreads();
-    }
-
-    // ---- store: global words gws .. gws + nr of rows -1 .. By-1; bits of
-    // the range [xs, xs + Bx] come from LDS, the others keep their value
-    // (no other work-group of this launch touches these words)
-    const uint32_t ng = nr + 1;                         // global words per row touched
-    const uint32_t nstore = (a.By + 1) * ng;
-    for (uint32_t u = tid; u < nstore; u += TPB) {
-        const uint32_t r = u / ng, m = u % ng;          // global word gws + m
-        uint32_t gy = y0 + a.L - 1 + r;
-        gy %= a.L;
-        uint32_t gw = gws + m;
-        if (gw >= a.W) gw -= a.W;
-        uint32_t *row = a.words + (size_t)gy * a.W;
-        // sites of this global word: xs - shs/2 + 16 m + i, i = 0..15; range
-        // index e = 16 m + i - shs/2 in [0, Bx]
-        const int base = (int)(16 * m) - (int)(shs >> 1);
-        uint32_t val = 0u, mask = 0u;
-        for (int i = 0; i < 16; ++i) {
-            const int e = base + i;
-            if (e < 0 || e > (int)a.Bx) continue;
-            val |= (uint32_t)site[r * SB + 3 + e] << (2 * i);
-            mask |= 3u << (2 * i);
-        }
-        if (mask == 0u) continue;
-        row[gw] = mask == 0xFFFFFFFFu ? val : ((row[gw] & ~mask) | val);
-    }
-
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) net += __shfl_xor(net, off, 64);
-    if ((tid & 63u) == 0 && net != 0)
-        atomicAdd(a.slots + ((b * (TPB / 64) + tid / 64) & a.slot_mask),
-                  (unsigned long long)(long long)net);
+    sweep_block<TPB, K, NTX, ACC, true>(a, by * a.nbx + bx, lds);
 }
+
 
 // ------------------------------------------------------------ roughness
 
@@ -1455,12 +1424,10 @@ kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
     if (bx < 16 || by < 16 || bx > 1024 || bx * by > 65536) return KPZ_EINVAL;
     if (L % bx || L % by) return KPZ_EINVAL;
     if (p->flags & KPZ_FLAG_DEVICE_DT) {
-        // four block sets need an even number of blocks along both axes; the
-        // plain kernel keeps the block and its halo in LDS
+        // four block sets need an even number of blocks along both axes
         const int64_t nbx = L / bx, nby = L / by;
         if (nbx < 2 || nby < 2 || (nbx & 1) || (nby & 1)) return KPZ_EINVAL;
         if (p->moves > 1) return KPZ_EINVAL;
-        if ((by + 1) * (bx + 4) > 65536) return KPZ_EINVAL;
     }
     *Bx = (uint32_t)bx;
     *By = (uint32_t)by;
@@ -1525,6 +1492,49 @@ hipError_t launch_sweep_ntx(const SweepArgs &a, uint32_t nblocks, size_t shmem, 
     case 128: return launch_sweep_k<TPB, K, 128, ACC>(a, nblocks, shmem, st);
     case 256: return launch_sweep_k<TPB, K, 256, ACC>(a, nblocks, shmem, st);
     default: return launch_sweep_k<TPB, K, 0, ACC>(a, nblocks, shmem, st);
+    }
+}
+
+template <int TPB, int K, int NTX, bool ACC>
+hipError_t launch_dt_k(const SweepArgs &a, uint32_t phase, uint32_t nblocks, size_t shmem,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL((kpz_dt_swar_kernel<TPB, K, NTX, ACC>), dim3(nblocks), dim3(TPB), shmem, st,
+                       a, phase);
+    return hipGetLastError();
+}
+
+template <int TPB, int K, bool ACC>
+hipError_t launch_dt_ntx(const SweepArgs &a, uint32_t phase, uint32_t nblocks, size_t shmem,
+                         hipStream_t st)
+{
+    switch (a.ntx) {
+    case 64: return launch_dt_k<TPB, K, 64, ACC>(a, phase, nblocks, shmem, st);
+    case 128: return launch_dt_k<TPB, K, 128, ACC>(a, phase, nblocks, shmem, st);
+    case 256: return launch_dt_k<TPB, K, 256, ACC>(a, phase, nblocks, shmem, st);
+    default: return launch_dt_k<TPB, K, 0, ACC>(a, phase, nblocks, shmem, st);
+    }
+}
+
+template <bool ACC>
+hipError_t launch_dt(const SweepArgs &a, uint32_t phase, uint32_t tpb, uint32_t K,
+                     uint32_t nblocks, size_t shmem, hipStream_t st)
+{
+    if (tpb == 256) {
+        switch (K) {
+        case 1: return launch_dt_ntx<256, 1, ACC>(a, phase, nblocks, shmem, st);
+        case 2: return launch_dt_ntx<256, 2, ACC>(a, phase, nblocks, shmem, st);
+        case 4: return launch_dt_ntx<256, 4, ACC>(a, phase, nblocks, shmem, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (K) {
+    case 1: return launch_dt_ntx<64, 1, ACC>(a, phase, nblocks, shmem, st);
+    case 2: return launch_dt_ntx<64, 2, ACC>(a, phase, nblocks, shmem, st);
+    case 4: return launch_dt_ntx<64, 4, ACC>(a, phase, nblocks, shmem, st);
+    case 8: return launch_dt_ntx<64, 8, ACC>(a, phase, nblocks, shmem, st);
+    case 16: return launch_dt_ntx<64, 16, ACC>(a, phase, nblocks, shmem, st);
+    default: return hipErrorInvalidValue;
     }
 }
 
@@ -2101,38 +2111,16 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     const uint32_t mgrid = (uint32_t)((nstraddle + 255) / 256 < 8192 ? (nstraddle + 255) / 256 : 8192);
     a.xcd = (nblocks % 8u) == 0;
     if (s->dt) {
-        DtArgs d;
-        d.words = s->words;
-        d.slots = (unsigned long long *)ws_slots(s);
-        d.L = L;
-        d.W = L / 16;
-        d.Bx = s->Bx;
-        d.By = s->By;
-        d.nbx = L / s->Bx;
-        d.nby = L / s->By;
-        d.ntx = s->Bx / TILE;
-        d.H = a.H;
-        d.nq = a.nq;
-        d.nw = s->Bx / 16;
-        d.seed_lo = a.seed_lo;
-        d.seed_hi = a.seed_hi;
-        d.slot_mask = NSLOTS - 1;
-        d.acc = a.acc;
-        d.P = s->P;
-        d.Q = s->Q;
-        const uint32_t grid = d.nbx * d.nby / 4;
-        const size_t lds = (((size_t)(d.By + 1) * (d.Bx + 4)) + 3) & ~(size_t)3;
-        const bool wide = d.nq > 64;
+        // double tiling at the device layer: four launches per MCS, one per
+        // block set in the order drawn for the MCS, in place
+        const uint32_t grid = a.nbx * a.nby / 4;
+        const size_t dshmem = shmem + sizeof(uint32_t) * (2 * (size_t)a.H + 2 * (size_t)a.ntx);
+        a.res = 0;
         for (int32_t m = 0; m < n_mcs; ++m) {
-            d.t = (uint32_t)(s->t + m);
+            a.t = (uint32_t)(s->t + m);
             for (uint32_t ph = 0; ph < 4; ++ph) {
-                if (wide)
-                    hipLaunchKernelGGL(kpz_dt_sweep_kernel<256>, dim3(grid), dim3(256), lds, s->stream,
-                                       d, ph);
-                else
-                    hipLaunchKernelGGL(kpz_dt_sweep_kernel<64>, dim3(grid), dim3(64), lds, s->stream,
-                                       d, ph);
-                const hipError_t e = hipGetLastError();
+                const hipError_t e = a.acc ? launch_dt<true>(a, ph, tpb, K, grid, dshmem, s->stream)
+                                           : launch_dt<false>(a, ph, tpb, K, grid, dshmem, s->stream);
                 if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep launch");
             }
         }

@@ -126,8 +126,9 @@ def test_ring_params_validation(kpz, L, block, ok):
 
 
 @pytest.mark.parametrize("L,block,ok", [(64, (16, 16), True), (256, (128, 128), True),
+                                        (512, (256, 256), True), (65536, (1024, 64), True),
                                         (48, (16, 16), False), (64, (64, 16), False),
-                                        (512, (256, 256), False)])
+                                        (1024, (1024, 64), False)])
 def test_device_dt_params(kpz, L, block, ok):
     p = kpz.make_params(L, 1.0, 0.0, 1, block, device_dt=True)
     if ok:

@@ -171,6 +171,9 @@ DT_CASES = [
     (96, (16, 16), 0.5, 0.5, 45, 4),         # 6 x 6 blocks, L not a power of two
     (512, (128, 64), 1.0, 0.999999, 46, 2),  # tie draws
     (64, (32, 16), 0.0, 1.0, 47, 3),         # desorption only
+    (2048, (1024, 64), 1.0, 0.0, 48, 2),     # the benchmark's block shape
+    (1024, (512, 32), 1.0, 0.5, 49, 2),
+    (512, (256, 16), 0.9, 0.1, 50, 2),
 ]
 
 
