@@ -1667,11 +1667,22 @@ bool round_shape(uint32_t Bx, uint32_t By, RoundShape *rs)
     return (rs->tpb == 256 && rs->K <= 4) || (rs->tpb == 64 && rs->K <= 2);
 }
 
+// The ensemble's round kernel is specialised for the tile-column counts of
+// block widths 64 to 1024 (the autotuner's candidates); others run the
+// runtime-width kernel.
 template <int TPB, int K>
 void round_launch_k(const RoundShape &rs, uint32_t grid, hipStream_t st, const SweepArgs *members,
                     const uint32_t *bprefix, uint32_t nmem, uint32_t k, uint32_t res)
 {
     switch (rs.ntx) {
+    case 16:
+        hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 16>), dim3(grid), dim3(TPB), rs.shmem,
+                           st, members, bprefix, nmem, k, res);
+        break;
+    case 32:
+        hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 32>), dim3(grid), dim3(TPB), rs.shmem,
+                           st, members, bprefix, nmem, k, res);
+        break;
     case 64:
         hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 64>), dim3(grid), dim3(TPB), rs.shmem,
                            st, members, bprefix, nmem, k, res);
