@@ -153,6 +153,13 @@ def ensemble_leg(args):
                                       "members": m_seq, "mcs": seq_mcs},
         "speedup_vs_sequential": (attempts / elapsed) / (seq_attempts / seq_elapsed),
         "mean_w2_final_by_L": final,
+        # each member's lattice is read and written once per MCS (0.5 B per
+        # attempt); the round kernel is bound by VALU issue (counters in
+        # DESIGN), so the HBM view is context, not the bound
+        "roofline": {"bound": "alu", "hbm_achieved_gbs": 0.5 * attempts / elapsed / 1e9,
+                     "hbm_peak_gbs": HBM_PEAK_GBS,
+                     "hbm_frac": 0.5 * attempts / elapsed / 1e9 / HBM_PEAK_GBS,
+                     "bytes_per_attempt": 0.5},
     }
 
 
