@@ -762,21 +762,42 @@ __device__ __forceinline__ WordSums word_sums(uint32_t w, const uint32_t *lut)
     return r;
 }
 
-// Moments of one row (one wave): returns (A_y, B_y) in lane 0 and, in
-// `first`, the row's first word in the documented layout.  rot2 = twice the
-// storage rotation (a row stored rotated by s sites holds sites s.. in its
-// word 0; word w of the layout is then bits of stored words w - 1 and w).
+// Lanes per row (a power of two, for the width of the group shuffles): a
+// row of W words, W a power of two from 4 to 128, is taken by W / 4 lanes,
+// one 16-byte load each, so a wave holds 256 / W rows; every other row takes
+// a whole wave.
+__host__ __device__ __forceinline__ uint32_t row_lanes(uint32_t W)
+{
+    return (W >= 4u && W < 256u && (W & (W - 1u)) == 0) ? W / 4u : 64u;
+}
+
+// Wave tasks of the row-moment pass for an L x L lattice: L / R, R = 64 /
+// row_lanes(L / 16) rows per wave (R > 1 only for L a power of two from 64
+// to 2048, where R = 4096 / L divides L).
+__host__ __device__ __forceinline__ uint32_t row_tasks(uint32_t L)
+{
+    const uint32_t R = 64u / row_lanes(L / 16u);
+    return (L + R - 1u) / R;
+}
+
+// Moments of one row, taken by a group of G lanes (G = row_lanes(W), the
+// group's lanes gl = 0..G-1 aligned to G in the wave): returns (A_y, B_y) in
+// lane gl = 0 and, in `first`, the row's first word in the documented layout.
+// rot2 = twice the storage rotation (a row stored rotated by s sites holds
+// sites s.. in its word 0; word w of the layout is then bits of stored words
+// w - 1 and w).  Each lane's local sums stay below 2^20 and heights within a
+// row below L, so they are 32-bit; only the row totals are 64-bit.
 __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, const uint32_t *lut,
-                                            uint32_t lane, uint32_t rot2, long long &A,
+                                            uint32_t gl, uint32_t G, uint32_t rot2, long long &A,
                                             long long &B, uint32_t &first)
 {
     const bool vec = (W & 3u) == 0;
     long long s1 = 0, s2 = 0;
-    long long carry = 0;
+    int carry = 0;
     uint32_t carry_w = rot2 ? rp[W - 1] : 0u;   // stored word before word 0 (periodic row)
     first = 0u;
-    for (uint32_t base = 0; base < W; base += 256) {
-        const uint32_t idx = base + 4 * lane;
+    for (uint32_t base = 0; base < W; base += 4u * G) {
+        const uint32_t idx = base + 4 * gl;
         uint32_t v[4] = {0u, 0u, 0u, 0u};
         int nv = 0;
         if (vec) {
@@ -793,10 +814,10 @@ __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, cons
         if (rot2) {
             // the previous stored word of each lane's first word: the previous
             // lane's last (full lanes precede any lane with words), or the
-            // carried word for lane 0
-            uint32_t pv = __shfl(v[3], (lane + 63u) & 63u, 64);
-            if (lane == 0) pv = carry_w;
-            carry_w = __shfl(v[3], 63, 64);
+            // carried word for the group's lane 0
+            uint32_t pv = __shfl(v[3], (gl + G - 1u) & (G - 1u), G);
+            if (gl == 0) pv = carry_w;
+            carry_w = __shfl(v[3], G - 1u, G);
             const uint32_t n3 = __builtin_amdgcn_alignbit(v[3], v[2], 32u - rot2);
             const uint32_t n2 = __builtin_amdgcn_alignbit(v[2], v[1], 32u - rot2);
             const uint32_t n1 = __builtin_amdgcn_alignbit(v[1], v[0], 32u - rot2);
@@ -807,39 +828,36 @@ __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, cons
         }
         if (base == 0) first = v[0];
         // this lane's words relative to its own start
-        int o = 0;
-        long long l1 = 0, l2 = 0;
+        int o = 0, l1 = 0, l2 = 0;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             if (m < nv) {
                 const WordSums ws = word_sums(v[m], lut);
                 l1 += 16 * o + ws.s1;
-                l2 += (long long)(16 * o) * o + 2LL * o * ws.s1 + ws.s2;
+                l2 += 16 * o * o + 2 * o * ws.s1 + ws.s2;
                 o += ws.d;
             }
         }
-        // lane offsets within the chunk: exclusive scan of o
+        // lane offsets within the chunk: exclusive scan of o over the group
         int incl = o;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int t = __shfl_up(incl, off, 64);
-            if ((int)lane >= off) incl += t;
+        for (uint32_t off = 1; off < G; off <<= 1) {
+            const int t = __shfl_up(incl, off, G);
+            if (gl >= off) incl += t;
         }
-        const long long c = carry + incl - o;
-        const long long n = 16LL * nv;
-        s1 += n * c + l1;
-        s2 += n * c * c + 2 * c * l1 + l2;
-        carry += __shfl(incl, 63, 64);
+        const int c = carry + incl - o;
+        s1 += (long long)(16 * nv) * c + l1;
+        s2 += (long long)(16 * nv) * ((long long)c * c) + 2LL * c * l1 + l2;
+        carry += __shfl(incl, G - 1u, G);
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        s1 += __shfl_xor(s1, off, 64);
-        s2 += __shfl_xor(s2, off, 64);
+    for (uint32_t off = G >> 1; off > 0; off >>= 1) {
+        s1 += __shfl_xor(s1, off, G);
+        s2 += __shfl_xor(s2, off, G);
     }
     A = s1;
     B = s2;
 }
 
+// One wave per 64 / row_lanes(W) rows.
 __global__ __launch_bounds__(256) void kpz_row_moments_kernel(const uint32_t *words, uint32_t L,
                                                               uint32_t W, long long *rowA,
                                                               long long *rowB, const Rot rot)
@@ -849,13 +867,20 @@ __global__ __launch_bounds__(256) void kpz_row_moments_kernel(const uint32_t *wo
     __syncthreads();
     const uint32_t rot2 = 2u * rot_sites(rot);
     const uint32_t lane = threadIdx.x & 63u;
-    for (uint32_t row = blockIdx.x * 4u + (threadIdx.x >> 6); row < L; row += gridDim.x * 4u) {
-        long long A, B;
-        uint32_t first;
-        row_moments(words + (size_t)row * W, W, lut, lane, rot2, A, B, first);
-        if (lane == 0) {
-            rowA[row] = A;
-            rowB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y(0, row)
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t G = row_lanes(W), R = 64u / G;
+    const uint32_t gl = lane & (G - 1u);
+    const uint32_t tasks = (L + R - 1u) / R;
+    for (uint32_t task = blockIdx.x * 4u + wv; task < tasks; task += gridDim.x * 4u) {
+        const uint32_t row = task * R + lane / G;
+        if (row < L) {   // a whole lane group is in or out
+            long long A, B;
+            uint32_t first;
+            row_moments(words + (size_t)row * W, W, lut, gl, G, rot2, A, B, first);
+            if (gl == 0) {
+                rowA[row] = A;
+                rowB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y(0, row)
+            }
         }
     }
 }
@@ -1319,33 +1344,39 @@ __global__ void kpz_batch_settle_kernel(SweepArgs *members, uint32_t n)
     }
 }
 
-// Row moments of all members: rows numbered consecutively over the members
-// (rprefix = prefix sums of L), one wave per row.
+// Row moments of all members: wave tasks numbered consecutively over the
+// members (tprefix = prefix sums of L / R, R = 64 / row_lanes(W) rows per
+// task, one member per task).
 __global__ __launch_bounds__(256) void kpz_batch_rows_kernel(const MemberRows *mr,
-                                                             const uint32_t *rprefix, uint32_t n)
+                                                             const uint32_t *tprefix, uint32_t n)
 {
     __shared__ uint32_t lut[256];
     lut[threadIdx.x] = lut8_entry(threadIdx.x);
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t total = rprefix[n];
-    for (uint32_t g = blockIdx.x * 4u + (threadIdx.x >> 6); g < total; g += gridDim.x * 4u) {
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t total = tprefix[n];
+    for (uint32_t g = blockIdx.x * 4u + wv; g < total; g += gridDim.x * 4u) {
         uint32_t lo = 0, hi = n;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (rprefix[mid] <= g) lo = mid;
+            if (tprefix[mid] <= g) lo = mid;
             else hi = mid;
         }
         const MemberRows m = mr[lo];
-        const uint32_t row = g - rprefix[lo];
-        Rot rot;
-        const uint32_t *cur = member_current(m, rot);
-        long long A, B;
-        uint32_t first;
-        row_moments(cur + (size_t)row * m.W, m.W, lut, lane, 2u * rot_sites(rot), A, B, first);
-        if (lane == 0) {
-            m.rowA[row] = A;
-            m.rowB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y(0, row)
+        const uint32_t G = row_lanes(m.W), R = 64u / G;
+        const uint32_t row = (g - tprefix[lo]) * R + lane / G;
+        if (row < m.L) {   // a whole lane group is in or out
+            Rot rot;
+            const uint32_t *cur = member_current(m, rot);
+            long long A, B;
+            uint32_t first;
+            row_moments(cur + (size_t)row * m.W, m.W, lut, lane & (G - 1u), G,
+                        2u * rot_sites(rot), A, B, first);
+            if ((lane & (G - 1u)) == 0) {
+                m.rowA[row] = A;
+                m.rowB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y(0, row)
+            }
         }
     }
 }
@@ -1581,7 +1612,8 @@ struct BatchLayout {
     std::vector<size_t> off_alt;    // second lattice buffer of each member (two-buffer mode)
     std::vector<size_t> word_off;   // per member, in words
     size_t words_bytes;
-    size_t off_members, off_bprefix, off_sprefix, off_rprefix, off_rows, off_res, off_slots;
+    size_t off_members, off_bprefix, off_sprefix, off_rprefix, off_tprefix, off_rows, off_res,
+        off_slots;
     std::vector<size_t> off_rowA, off_rowB, off_side;
     size_t ws_bytes;
 };
@@ -1629,6 +1661,7 @@ kpz_status batch_layout(const kpz_params *m, int32_t n, BatchLayout *lay)
     lay->off_bprefix = o;  o = align256(o + 4 * ((size_t)n + 1));
     lay->off_sprefix = o;  o = align256(o + 8 * ((size_t)n + 1));
     lay->off_rprefix = o;  o = align256(o + 4 * ((size_t)n + 1));
+    lay->off_tprefix = o;  o = align256(o + 4 * ((size_t)n + 1));
     lay->off_rows = o;     o = align256(o + sizeof(MemberRows) * (size_t)n);
     lay->off_res = o;      o = align256(o + 4 * sizeof(long long) * (size_t)n * KPZ_BATCH_MAX_SAMPLES);
     lay->off_slots = o;    o = align256(o + sizeof(long long) * BATCH_SLOTS * (size_t)n);
@@ -1740,7 +1773,7 @@ struct kpz_batch {
     RoundShape rs;
     uint32_t per_round;
     uint64_t merge_words;
-    uint32_t total_rows;
+    uint32_t total_rows, total_row_tasks;
     char err[256];
 };
 
@@ -1778,9 +1811,10 @@ kpz_status batch_sweep_on(kpz_batch *b, int32_t n_mcs, hipStream_t st)
 kpz_status batch_moments_on(kpz_batch *b, uint32_t k, hipStream_t st)
 {
     const MemberRows *mr = (const MemberRows *)(b->ws + b->lay.off_rows);
-    const uint32_t rgrid = (b->total_rows + 3) / 4 < 8192 ? (b->total_rows + 3) / 4 : 8192;
+    const uint32_t nt = b->total_row_tasks;
+    const uint32_t rgrid = (nt + 3) / 4 < 8192 ? (nt + 3) / 4 : 8192;
     hipLaunchKernelGGL(kpz_batch_rows_kernel, dim3(rgrid), dim3(256), 0, st, mr,
-                       (const uint32_t *)(b->ws + b->lay.off_rprefix), (uint32_t)b->n);
+                       (const uint32_t *)(b->ws + b->lay.off_tprefix), (uint32_t)b->n);
     hipLaunchKernelGGL(kpz_batch_finalize_kernel, dim3(b->n), dim3(256), 0, st, mr,
                        (uint32_t)b->n, (uint32_t)BATCH_SLOTS, batch_res(b), k);
     const hipError_t e = hipGetLastError();
@@ -1848,7 +1882,7 @@ size_t pool_job_bytes_raw(int64_t L, uint32_t Bx, uint32_t By)
 }
 
 struct PoolCtl {
-    size_t off_members, off_bprefix, off_sprefix, off_rprefix, off_rows, off_res, bytes;
+    size_t off_members, off_bprefix, off_sprefix, off_tprefix, off_rows, off_res, bytes;
 };
 
 PoolCtl pool_ctl_layout(int32_t max_jobs)
@@ -1858,7 +1892,7 @@ PoolCtl pool_ctl_layout(int32_t max_jobs)
     c.off_members = o;  o = align256(o + sizeof(SweepArgs) * (size_t)max_jobs);
     c.off_bprefix = o;  o = align256(o + 4 * ((size_t)max_jobs + 1));
     c.off_sprefix = o;  o = align256(o + 8 * ((size_t)max_jobs + 1));
-    c.off_rprefix = o;  o = align256(o + 4 * ((size_t)max_jobs + 1));
+    c.off_tprefix = o;  o = align256(o + 4 * ((size_t)max_jobs + 1));
     c.off_rows = o;     o = align256(o + sizeof(MemberRows) * (size_t)max_jobs);
     c.off_res = o;      o = align256(o + 4 * sizeof(long long) * (size_t)max_jobs);
     c.bytes = o;
@@ -2175,7 +2209,8 @@ kpz_status kpz_roughness(kpz_sim *s, int64_t *S1o, int64_t *S2o, double *W2o)
     clear_pending_error();
     if (!s) return KPZ_EINVAL;
     const uint32_t L = (uint32_t)s->prm.L, W = L / 16;
-    const uint32_t rgrid = (L + 3) / 4 < 4096 ? (L + 3) / 4 : 4096;
+    const uint32_t nt = row_tasks(L);
+    const uint32_t rgrid = (nt + 3) / 4 < 4096 ? (nt + 3) / 4 : 4096;
     hipLaunchKernelGGL(kpz_row_moments_kernel, dim3(rgrid), dim3(256), 0, s->stream,
                        s->buf[s->cur], L, W, ws_rowA(s), ws_rowB(s), sim_rot(s));
     hipError_t e = hipGetLastError();
@@ -2346,7 +2381,7 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
 
     std::vector<SweepArgs> args(n);
     std::vector<MemberRows> rows(n);
-    std::vector<uint32_t> bprefix(n + 1, 0), rprefix(n + 1, 0);
+    std::vector<uint32_t> bprefix(n + 1, 0), rprefix(n + 1, 0), tprefix(n + 1, 0);
     std::vector<unsigned long long> sprefix(n + 1, 0);
     long long *slots = (long long *)(b->ws + lay.off_slots);
     for (int32_t r = 0; r < n; ++r) {
@@ -2395,10 +2430,12 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
         bprefix[r + 1] = bprefix[r] + a.nbx * a.nby;
         sprefix[r + 1] = sprefix[r] + (unsigned long long)L * a.nbx;
         rprefix[r + 1] = rprefix[r] + L;
+        tprefix[r + 1] = tprefix[r] + row_tasks(L);
     }
     b->per_round = bprefix[n];
     b->merge_words = sprefix[n];
     b->total_rows = rprefix[n];
+    b->total_row_tasks = tprefix[n];
     hipError_t e = hipSuccess;
     auto h2d = [&](size_t off, const void *src, size_t bytes) {
         if (e == hipSuccess)
@@ -2408,6 +2445,7 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
     h2d(lay.off_bprefix, bprefix.data(), 4 * (n + 1));
     h2d(lay.off_sprefix, sprefix.data(), 8 * (n + 1));
     h2d(lay.off_rprefix, rprefix.data(), 4 * (n + 1));
+    h2d(lay.off_tprefix, tprefix.data(), 4 * (n + 1));
     h2d(lay.off_rows, rows.data(), sizeof(MemberRows) * n);
     for (int32_t r = 0; r < n && e == hipSuccess; ++r) {
         const uint64_t L = (uint64_t)members[r].L;
@@ -2739,7 +2777,7 @@ kpz_status kpz_pool_step(kpz_pool *p, int32_t quantum, int32_t *n_active)
         if (p->jobs[i].t >= p->jobs[i].n_mcs) fin.push_back(i);
     if (!fin.empty()) {
         std::vector<MemberRows> rows(fin.size());
-        std::vector<uint32_t> rprefix(fin.size() + 1, 0);
+        std::vector<uint32_t> tprefix(fin.size() + 1, 0);
         for (size_t f = 0; f < fin.size(); ++f) {
             const PoolJob &j = p->jobs[fin[f]];
             rows[f].words = (const uint32_t *)(p->arena + (j.cur ? j.off_alt : j.off_words));
@@ -2751,16 +2789,16 @@ kpz_status kpz_pool_step(kpz_pool *p, int32_t quantum, int32_t *n_active)
             rows[f].slots = (const long long *)(p->arena + j.off_slots);
             rows[f].L = (uint32_t)j.prm.L;
             rows[f].W = (uint32_t)(j.prm.L / 16);
-            rprefix[f + 1] = rprefix[f] + (uint32_t)j.prm.L;
+            tprefix[f + 1] = tprefix[f] + row_tasks((uint32_t)j.prm.L);
         }
         h2d(p->ctl.off_rows, rows.data(), sizeof(MemberRows) * fin.size());
-        h2d(p->ctl.off_rprefix, rprefix.data(), 4 * (fin.size() + 1));
+        h2d(p->ctl.off_tprefix, tprefix.data(), 4 * (fin.size() + 1));
         if (e != hipSuccess) return pool_fail(p, e, "kpz_pool_step copy");
-        const uint32_t total_rows = rprefix[fin.size()];
-        const uint32_t rgrid = (total_rows + 3) / 4 < 8192 ? (total_rows + 3) / 4 : 8192;
+        const uint32_t nt = tprefix[fin.size()];
+        const uint32_t rgrid = (nt + 3) / 4 < 8192 ? (nt + 3) / 4 : 8192;
         const MemberRows *mr = (const MemberRows *)(p->arena + p->ctl.off_rows);
         hipLaunchKernelGGL(kpz_batch_rows_kernel, dim3(rgrid), dim3(256), 0, p->stream, mr,
-                           (const uint32_t *)(p->arena + p->ctl.off_rprefix), (uint32_t)fin.size());
+                           (const uint32_t *)(p->arena + p->ctl.off_tprefix), (uint32_t)fin.size());
         hipLaunchKernelGGL(kpz_batch_finalize_kernel, dim3((uint32_t)fin.size()), dim3(256), 0,
                            p->stream, mr, (uint32_t)fin.size(), (uint32_t)BATCH_SLOTS,
                            (long long *)(p->arena + p->ctl.off_res), 0u);
