@@ -780,58 +780,84 @@ __host__ __device__ __forceinline__ uint32_t row_tasks(uint32_t L)
     return (L + R - 1u) / R;
 }
 
+// Inclusive sum over the 64 lanes of a wave: shifts by 1, 2, 4 and 8 lanes
+// within each row of 16 lanes, then the last lane of row 0 added to row 1 and
+// of row 2 to row 3, then lane 31 added to rows 2 and 3 (DPP).
+__device__ __forceinline__ int wave_incl_sum(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return x;
+}
+
 // Moments of one row, taken by a group of G lanes (G = row_lanes(W), the
-// group's lanes gl = 0..G-1 aligned to G in the wave): returns (A_y, B_y) in
-// lane gl = 0 and, in `first`, the row's first word in the documented layout.
-// rot2 = twice the storage rotation (a row stored rotated by s sites holds
-// sites s.. in its word 0; word w of the layout is then bits of stored words
-// w - 1 and w).  Each lane's local sums stay below 2^20 and heights within a
-// row below L, so they are 32-bit; only the row totals are 64-bit.
+// group's lanes gl = 0..G-1 aligned to G in the wave), NV consecutive words
+// per lane and chunk (NV = 16 only for W % 1024 == 0, where G = 64 and every
+// lane is full): returns (A_y, B_y) in lane gl = 0 and, in `first`, the
+// row's first word in the documented layout.  rot2 = twice the storage
+// rotation (a row stored rotated by s sites holds sites s.. in its word 0;
+// word w of the layout is then bits of stored words w - 1 and w).  A lane's
+// local sums stay below 2^24 and heights within a row below L, so they are
+// 32-bit; only the row totals are 64-bit.
+template <int NV>
 __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, const uint32_t *lut,
                                             uint32_t gl, uint32_t G, uint32_t rot2, long long &A,
                                             long long &B, uint32_t &first)
 {
+    static_assert(NV == 4 || NV == 16, "four or sixteen words per lane");
     const bool vec = (W & 3u) == 0;
     long long s1 = 0, s2 = 0;
     int carry = 0;
     uint32_t carry_w = rot2 ? rp[W - 1] : 0u;   // stored word before word 0 (periodic row)
     first = 0u;
-    for (uint32_t base = 0; base < W; base += 4u * G) {
-        const uint32_t idx = base + 4 * gl;
-        uint32_t v[4] = {0u, 0u, 0u, 0u};
+    for (uint32_t base = 0; base < W; base += NV * G) {
+        const uint32_t idx = base + NV * gl;
+        uint32_t v[NV];
         int nv = 0;
-        if (vec) {
-            if (idx < W) {
-                const uint4 q = *(const uint4 *)(rp + idx);
-                v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-                nv = 4;
+        if (NV == 16) {
+#pragma unroll
+            for (int j = 0; j < NV / 4; ++j) {
+                const uint4 q = *(const uint4 *)(rp + idx + 4 * j);
+                v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
             }
+            nv = NV;
         } else {
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
-                if (idx + m < W) { v[m] = rp[idx + m]; nv = m + 1; }
+            for (int m = 0; m < NV; ++m) v[m] = 0u;
+            if (vec) {
+                if (idx < W) {
+                    const uint4 q = *(const uint4 *)(rp + idx);
+                    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+                    nv = 4;
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    if (idx + m < W) { v[m] = rp[idx + m]; nv = m + 1; }
+            }
         }
         if (rot2) {
             // the previous stored word of each lane's first word: the previous
             // lane's last (full lanes precede any lane with words), or the
             // carried word for the group's lane 0
-            uint32_t pv = __shfl(v[3], (gl + G - 1u) & (G - 1u), G);
+            uint32_t pv = __shfl(v[NV - 1], (gl + G - 1u) & (G - 1u), G);
             if (gl == 0) pv = carry_w;
-            carry_w = __shfl(v[3], G - 1u, G);
-            const uint32_t n3 = __builtin_amdgcn_alignbit(v[3], v[2], 32u - rot2);
-            const uint32_t n2 = __builtin_amdgcn_alignbit(v[2], v[1], 32u - rot2);
-            const uint32_t n1 = __builtin_amdgcn_alignbit(v[1], v[0], 32u - rot2);
+            carry_w = __shfl(v[NV - 1], G - 1u, G);
+#pragma unroll
+            for (int m = NV - 1; m > 0; --m)
+                v[m] = __builtin_amdgcn_alignbit(v[m], v[m - 1], 32u - rot2);
             v[0] = __builtin_amdgcn_alignbit(v[0], pv, 32u - rot2);
-            v[1] = n1;
-            v[2] = n2;
-            v[3] = n3;
         }
         if (base == 0) first = v[0];
         // this lane's words relative to its own start
         int o = 0, l1 = 0, l2 = 0;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            if (m < nv) {
+        for (int m = 0; m < NV; ++m) {
+            if (NV == 16 || m < nv) {
                 const WordSums ws = word_sums(v[m], lut);
                 l1 += 16 * o + ws.s1;
                 l2 += 16 * o * o + 2 * o * ws.s1 + ws.s2;
@@ -839,15 +865,22 @@ __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, cons
             }
         }
         // lane offsets within the chunk: exclusive scan of o over the group
-        int incl = o;
-        for (uint32_t off = 1; off < G; off <<= 1) {
-            const int t = __shfl_up(incl, off, G);
-            if (gl >= off) incl += t;
+        int incl, total;
+        if (G == 64u) {
+            incl = wave_incl_sum(o);
+            total = __builtin_amdgcn_readlane(incl, 63);
+        } else {
+            incl = o;
+            for (uint32_t off = 1; off < G; off <<= 1) {
+                const int t = __shfl_up(incl, off, G);
+                if (gl >= off) incl += t;
+            }
+            total = __shfl(incl, G - 1u, G);
         }
         const int c = carry + incl - o;
         s1 += (long long)(16 * nv) * c + l1;
         s2 += (long long)(16 * nv) * ((long long)c * c) + 2LL * c * l1 + l2;
-        carry += __shfl(incl, G - 1u, G);
+        carry += total;
     }
     for (uint32_t off = G >> 1; off > 0; off >>= 1) {
         s1 += __shfl_xor(s1, off, G);
@@ -876,7 +909,10 @@ __global__ __launch_bounds__(256) void kpz_row_moments_kernel(const uint32_t *wo
         if (row < L) {   // a whole lane group is in or out
             long long A, B;
             uint32_t first;
-            row_moments(words + (size_t)row * W, W, lut, gl, G, rot2, A, B, first);
+            if ((W & 1023u) == 0)
+                row_moments<16>(words + (size_t)row * W, W, lut, gl, G, rot2, A, B, first);
+            else
+                row_moments<4>(words + (size_t)row * W, W, lut, gl, G, rot2, A, B, first);
             if (gl == 0) {
                 rowA[row] = A;
                 rowB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y(0, row)
@@ -904,46 +940,66 @@ __global__ void kpz_rotate_kernel(const uint32_t *src, uint32_t *dst, uint32_t L
 // heights), R1 = sum_y (L c_y + A_y), R2 = sum_y (L c_y^2 + 2 c_y A_y + B_y)
 // in 128-bit, and the sum of the flip-counter slots.  The row pass stores
 // rowB[y] = 2 B_y + [sigma_y(0,y) = +1] (B_y <= L^3/4 leaves the room), so
-// this pass reads two contiguous arrays and never the lattice.
+// this pass reads two contiguous arrays and never the lattice.  Wave w takes
+// one contiguous range of rows [y0, y1), 64 consecutive rows per load
+// (coalesced), in one pass: with d_y = c_y - c_{y0} (from a ballot of the
+// sigma_y bits and a count of the set bits below each lane), a lane sums
+// r1 = sum (L d_y + A_y) and r2 = sum (L d_y^2 + 2 d_y A_y + B_y) over its n
+// rows; once c_{y0} = C is known from the waves' totals, its share of R1 is
+// r1 + n L C and of R2 is r2 + 2 C r1 + n L C^2.
 template <int NT>
 __device__ __forceinline__ void finalize_moments(uint32_t L, const long long *rowA,
                                                  const long long *rowB, const long long *slots,
                                                  uint32_t nslots, long long *res)
 {
-    __shared__ long long sc[NT];
+    constexpr uint32_t NWV = NT / 64;
+    __shared__ long long wsum[NWV];
     __shared__ __int128 r2s[NT];
     __shared__ long long r1s[NT];
     __shared__ long long ns[NT];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t per = (L + NT - 1) / NT;
-    const uint32_t y0 = min(L, tid * per);
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint32_t per = (L + NWV - 1) / NWV;
+    const uint32_t y0 = min(L, wv * per);
     const uint32_t y1 = min(L, y0 + per);
-    long long loc = 0;
-#pragma unroll 8
-    for (uint32_t y = y0; y < y1; ++y) loc += (rowB[y] & 1) ? 1 : -1;
-    sc[tid] = loc;
-    __syncthreads();
-    // inclusive Hillis-Steele scan over the thread sums
-    for (uint32_t off = 1; off < NT; off <<= 1) {
-        const long long v = tid >= off ? sc[tid - off] : 0;
-        __syncthreads();
-        sc[tid] += v;
-        __syncthreads();
-    }
-    // this thread's rows: with |c| <= L/2, |A_y| <= L^2/2 and B_y <= L^3/4
-    // every row's term fits int64 for L <= 2^20; the sum over rows is kept
-    // in 128-bit (additions only)
-    long long c = sc[tid] - loc;
-    long long r1 = 0;
+    // with |c| <= L/2, |A_y| <= L^2/2 and B_y <= L^3/4 every row's term fits
+    // int64 for L <= 2^20; sums over rows are kept in 128-bit
+    long long d = 0;   // sum of sigma_y(0, .) over the wave's rows before `base`
+    long long r1 = 0, nr = 0;
     __int128 r2 = 0;
-#pragma unroll 8
-    for (uint32_t y = y0; y < y1; ++y) {
-        const long long Ay = rowA[y], Bw = rowB[y];
-        const long long By = Bw >> 1;
-        r1 += (long long)L * c + Ay;
-        r2 += (__int128)((long long)L * c * c + 2 * c * Ay + By);
-        c += (Bw & 1) ? 1 : -1;
+    constexpr int U = 8;   // loads of U groups of 64 rows in flight
+    for (uint32_t base = y0; base < y1; base += 64u * U) {
+        long long Av[U], Bv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t y = base + 64u * u + lane;
+            const uint32_t yy = y < y1 ? y : base;   // in range: base < y1
+            Av[u] = rowA[yy];
+            Bv[u] = rowB[yy];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t y = base + 64u * u + lane;
+            const bool ok = y < y1;
+            const uint64_t upm = __ballot(ok && (Bv[u] & 1));
+            // the lanes below this one hold rows y - lane .. y - 1, all in range
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(upm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)upm, 0u));
+            const long long dy = d + 2 * (long long)below - (long long)lane;
+            if (ok) {
+                r1 += (long long)L * dy + Av[u];
+                r2 += (__int128)((long long)L * dy * dy + 2 * dy * Av[u] + (Bv[u] >> 1));
+                nr += 1;
+            }
+            d += 2 * (long long)__popcll(upm) - (long long)__popcll(__ballot(ok));
+        }
     }
+    if (lane == 0) wsum[wv] = d;
+    __syncthreads();
+    long long C = 0;   // c_{y0}
+    for (uint32_t w = 0; w < wv; ++w) C += wsum[w];
+    r2 += (__int128)(2 * C) * r1 + (__int128)((long long)L * nr) * ((__int128)C * C);
+    r1 += (long long)L * nr * C;
     long long n = 0;
     for (uint32_t i = tid; i < nslots; i += NT) n += slots[i];
     r1s[tid] = r1;
@@ -1371,8 +1427,11 @@ __global__ __launch_bounds__(256) void kpz_batch_rows_kernel(const MemberRows *m
             const uint32_t *cur = member_current(m, rot);
             long long A, B;
             uint32_t first;
-            row_moments(cur + (size_t)row * m.W, m.W, lut, lane & (G - 1u), G,
-                        2u * rot_sites(rot), A, B, first);
+            const uint32_t *rp = cur + (size_t)row * m.W;
+            if ((m.W & 1023u) == 0)
+                row_moments<16>(rp, m.W, lut, lane & (G - 1u), G, 2u * rot_sites(rot), A, B, first);
+            else
+                row_moments<4>(rp, m.W, lut, lane & (G - 1u), G, 2u * rot_sites(rot), A, B, first);
             if ((lane & (G - 1u)) == 0) {
                 m.rowA[row] = A;
                 m.rowB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y(0, row)
