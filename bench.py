@@ -154,8 +154,9 @@ def ensemble_leg(args):
         "speedup_vs_sequential": (attempts / elapsed) / (seq_attempts / seq_elapsed),
         "mean_w2_final_by_L": final,
         # each member's lattice is read and written once per MCS (0.5 B per
-        # attempt); the round kernel is bound by VALU issue (counters in
-        # DESIGN), so the HBM view is context, not the bound
+        # attempt); the round kernel is bound by VALU issue (its counters:
+        # profiles/kpz_batch_round_ens512_kernel_trace.md), so the HBM view
+        # is context, not the bound
         "roofline": {"bound": "alu", "hbm_achieved_gbs": 0.5 * attempts / elapsed / 1e9,
                      "hbm_peak_gbs": HBM_PEAK_GBS,
                      "hbm_frac": 0.5 * attempts / elapsed / 1e9 / HBM_PEAK_GBS,
@@ -351,11 +352,11 @@ def serving_leg(args):
     }
 
 
-def measured_traffic(block, in_place=False):
-    """HBM bytes per MCS (sweep + merge) of this block shape from the
-    committed hardware-counter summary, or None when the sweep's source
-    (kpz.hip and the device helpers it includes) has changed since the
-    counters were taken, or the shape was not measured."""
+def measured_traffic(block, in_place=False, device_dt=False):
+    """HBM bytes per MCS (every launch of one MCS) of this block shape and
+    mode from the committed hardware-counter summary, or None when the
+    sweep's source (kpz.hip and the device helpers it includes) has changed
+    since the counters were taken, or the shape was not measured."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "kpz_sweep_L65536_hbm_counters.md")
@@ -371,7 +372,8 @@ def measured_traffic(block, in_place=False):
     m = re.search(r"source_sha256 = ([0-9a-f]{64})", text)
     if not m or m.group(1) != sha:
         return None
-    key = "%dx%d%s" % (block[0], block[1], ",in_place" if in_place else "")
+    key = "%dx%d%s" % (block[0], block[1],
+                       ",device_dt" if device_dt else (",in_place" if in_place else ""))
     m = re.search(r"traffic_bytes_per_mcs\[%s\] = (\d+)" % re.escape(key), text)
     return float(m.group(1)) if m else None
 
@@ -480,8 +482,8 @@ def main():
     sweep_s = sweep_ms / 1e3
     achieved_tops = OPS_PER_ATTEMPT * per_launch_attempts / sweep_s / 1e12
     achieved_gbs = BYTES_PER_ATTEMPT * per_launch_attempts / sweep_s / 1e9
-    traffic = (measured_traffic(block, args.in_place)
-               if (L == 65536 and args.moves == 1 and not args.device_dt) else None)
+    traffic = (measured_traffic(block, args.in_place, args.device_dt)
+               if (L == 65536 and args.moves == 1) else None)
     line = {
         "metric": "site-update attempts/s at L=2^16",
         "value": value,
