@@ -253,23 +253,38 @@ def ring_leg(args):
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
+def code_sha256(names):
+    """sha256 of the code of the named sources under paper_1204_5072_amd/csrc:
+    comments (// to the line end, /* ... */) and blank lines removed, trailing
+    blanks stripped, lines joined by newlines.  Counters taken on one code
+    stay valid across comment edits; any change to the code invalidates
+    them."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in names:
+        text = open(os.path.join(ROOT, "paper_1204_5072_amd", "csrc", f)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for line in text.splitlines():
+            line = re.sub(r"//.*", "", line).rstrip()
+            if line:
+                h.update(line.encode() + b"\n")
+    return h.hexdigest()
+
+
 def ring_valu_per_mcs():
     """VALU wave instructions per ring MCS (sweep + merge launch) from the
     committed counter summary, or None when kpz_ring.hip or the device
     helpers changed since the counters were taken."""
-    import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "kpz_ring_L2p30_kernel_trace.md")
-    csrc = os.path.join(ROOT, "paper_1204_5072_amd", "csrc")
     try:
         text = open(path).read()
-        h = hashlib.sha256()
-        for f in ("kpz_ring.hip", "kpz_device.h"):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+        sha = code_sha256(("kpz_ring.hip", "kpz_device.h"))
     except OSError:
         return None
-    m = re.search(r"source_sha256 = ([0-9a-f]{64})", text)
-    if not m or m.group(1) != h.hexdigest():
+    m = re.search(r"code_sha256 = ([0-9a-f]{64})", text)
+    if not m or m.group(1) != sha:
         return None
     m = re.search(r"valu_wave_instr_per_mcs = (\d+)", text)
     return float(m.group(1)) if m else None
@@ -357,19 +372,14 @@ def measured_traffic(block, in_place=False, device_dt=False):
     mode from the committed hardware-counter summary, or None when the
     sweep's source (kpz.hip and the device helpers it includes) has changed
     since the counters were taken, or the shape was not measured."""
-    import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "kpz_sweep_L65536_hbm_counters.md")
-    csrc = os.path.join(ROOT, "paper_1204_5072_amd", "csrc")
     try:
         text = open(path).read()
-        h = hashlib.sha256()
-        for f in ("kpz.hip", "kpz_device.h"):
-            h.update(open(os.path.join(csrc, f), "rb").read())
-        sha = h.hexdigest()
+        sha = code_sha256(("kpz.hip", "kpz_device.h"))
     except OSError:
         return None
-    m = re.search(r"source_sha256 = ([0-9a-f]{64})", text)
+    m = re.search(r"code_sha256 = ([0-9a-f]{64})", text)
     if not m or m.group(1) != sha:
         return None
     key = "%dx%d%s" % (block[0], block[1],

@@ -14,8 +14,10 @@
 //   kpz_sweep_kernel<K,ACC> one MCS: one wave64 work-group per dead-border
 //                           block; block in LDS; 16 single-hit steps
 //   kpz_row_moments_kernel  per-row (sum, sum of squares) of the x-prefix
-//                           heights, one wave per row, HBM read stream
-//   kpz_finalize_kernel     column-0 prefix, 128-bit totals, flip counters
+//                           heights, a lane group per row (a wave for long
+//                           rows), HBM read stream
+//   kpz_finalize_kernel     column-0 prefix, 128-bit totals, flip counters,
+//                           one work-group, one pass over the row sums
 //
 // LDS layout of a block in the sweep.  Tiles are 4 x 4 sites, each split
 // into four 2 x 2 cells; cell set s = sx + 2 sy.  A cell is one byte: site
