@@ -34,15 +34,18 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     return U4{c0, c1, c2, c3};
 }
 
-// 0x80 in every byte of A that is below c (0 <= c <= 256): in 16-bit lanes
-// (a | 0x100) - c has bit 8 clear iff a < c.
+// 0x80 in every byte of A that is below c (1 <= c <= 256, c uniform), i.e.
+// at most t = c - 1.  With t = 128 t7 + t', a byte a = 128 a7 + a' is <= t
+// iff a7 < t7, or a7 = t7 and a' <= t'.  In every byte, (a | 0x80) - (t' + 1)
+// lies in 0..254 (no borrow between bytes) and has bit 7 clear iff a' <= t'.
+// One three-input logic op then takes a7, that bit and t7 (as a uniform mask):
+// result bit 7 = ~a7 & ~d7 | t7 & ~(a7 & d7); truth table 0x2B over (A, d, m).
 __device__ __forceinline__ uint32_t byte_lt(uint32_t A, uint32_t c)
 {
-    const uint32_t cc = c * 0x00010001u;
-    const uint32_t even = ((A & 0x00FF00FFu) | 0x01000100u) - cc;
-    const uint32_t odd = (((A >> 8) & 0x00FF00FFu) | 0x01000100u) - cc;
-    const uint32_t ge = ((even >> 1) & 0x00800080u) | ((odd << 7) & 0x80008000u);
-    return ~ge & 0x80808080u;
+    const uint32_t t = c - 1u;
+    const uint32_t d = (A | 0x80808080u) - ((t & 0x7Fu) + 1u) * 0x01010101u;
+    const uint32_t m = (t & 0x80u) ? 0xFFFFFFFFu : 0u;
+    return __builtin_amdgcn_bitop3_b32(A, d, m, 0x2B) & 0x80808080u;
 }
 
 // 0x80 in every byte of A equal to c (0 <= c <= 255).
