@@ -199,6 +199,8 @@ __device__ __forceinline__ uint32_t expand_bit7(uint32_t m7)
 
 struct AccCtx {
     bool fullP;          // P = 2^32: every minimum is accepted
+    bool ties;           // a threshold below 2^32 has nonzero low bits: A equal
+                         // to its top byte needs the second draw
     uint32_t tP, tQ;     // top bytes of P and Q
     uint32_t lowP, lowQ; // low 24 bits of P and Q
 };
@@ -233,29 +235,31 @@ __device__ __forceinline__ void quad_update(uint32_t *lds, uint32_t ca, uint32_t
     const uint32_t zmin = c & ~N;
     uint32_t F = zmin & (zmin >> 1) & oh;
     if (ACC) {
-        // maximum: own slopes (-1,-1), incoming slopes (+1,+1)
+        // maximum: own slopes (-1,-1), incoming slopes (+1,+1).  A byte (tile)
+        // holds a minimum flip in F or a maximum flip in Fx, never both, so
+        // the P test applies to F and the Q test to Fx byte by byte
         const uint32_t zmax = N & ~c;
         const uint32_t Fx = zmax & (zmax >> 1) & oh;
-        const uint32_t mn = bytes_nonzero(F), mx = bytes_nonzero(Fx);
-        const uint32_t accP = ac.fullP ? 0x80808080u : (ac.tP ? byte_lt(Aw, ac.tP) : 0u);
-        const uint32_t accQ = ac.tQ ? byte_lt(Aw, ac.tQ) : 0u;
-        uint32_t keep7 = (mn & accP) | (mx & accQ);
-        const uint32_t tieP = (!ac.fullP && ac.lowP) ? (mn & byte_eq(Aw, ac.tP)) : 0u;
-        const uint32_t tieQ = ac.lowQ ? (mx & byte_eq(Aw, ac.tQ)) : 0u;
-        if (__any((tieP | tieQ) != 0)) {
-            const U4 w2 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t,
-                                 (TAG_ACC2 << 24) | (16u * a.res + k),
-                                 a.seed_lo, a.seed_hi);
-            const uint32_t Bw[4] = {w2.x, w2.y, w2.z, w2.w};
+        // bit 7 of each byte: the tile's uniform A accepts
+        uint32_t accP = ac.fullP ? 0x80808080u : (ac.tP ? byte_lt(Aw, ac.tP) : 0u);
+        uint32_t accQ = ac.tQ ? byte_lt(Aw, ac.tQ) : 0u;
+        if (ac.ties) {
+            const uint32_t tieP = (!ac.fullP && ac.lowP) ? (bytes_nonzero(F) & byte_eq(Aw, ac.tP)) : 0u;
+            const uint32_t tieQ = ac.lowQ ? (bytes_nonzero(Fx) & byte_eq(Aw, ac.tQ)) : 0u;
+            if (__any((tieP | tieQ) != 0)) {
+                const U4 w2 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t,
+                                     (TAG_ACC2 << 24) | (16u * a.res + k),
+                                     a.seed_lo, a.seed_hi);
+                const uint32_t Bw[4] = {w2.x, w2.y, w2.z, w2.w};
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t b24 = Bw[j] & 0xFFFFFFu;
-                if (((tieP >> (8 * j + 7)) & 1u) && b24 < ac.lowP) keep7 |= 0x80u << (8 * j);
-                if (((tieQ >> (8 * j + 7)) & 1u) && b24 < ac.lowQ) keep7 |= 0x80u << (8 * j);
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t b24 = Bw[j] & 0xFFFFFFu;
+                    if (((tieP >> (8 * j + 7)) & 1u) && b24 < ac.lowP) accP |= 0x80u << (8 * j);
+                    if (((tieQ >> (8 * j + 7)) & 1u) && b24 < ac.lowQ) accQ |= 0x80u << (8 * j);
+                }
             }
         }
-        const uint32_t keep = expand_bit7(keep7);
-        const uint32_t fmin = F & keep, fmax = Fx & keep;
+        const uint32_t fmin = F & expand_bit7(accP), fmax = Fx & expand_bit7(accQ);
         net += __builtin_popcount(fmin) - __builtin_popcount(fmax);
         F = fmin | fmax;
     } else {
@@ -459,6 +463,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
     ac.tQ = (uint32_t)(a.Q >> 24);
     ac.lowP = (uint32_t)(a.P & 0xFFFFFFu);
     ac.lowQ = (uint32_t)(a.Q & 0xFFFFFFu);
+    ac.ties = (!ac.fullP && ac.lowP != 0) || ac.lowQ != 0;
     const bool active = K * TPB == (int)nq || tid < nq;
     int net = 0;
 
