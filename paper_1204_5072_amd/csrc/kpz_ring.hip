@@ -103,6 +103,7 @@ __device__ __forceinline__ uint32_t gather_bytes(uint32_t lo, uint32_t hi)
 
 struct RingAcc {
     bool fullP;
+    bool ties;           // a threshold below 2^32 has nonzero low bits
     uint32_t tP, tQ, lowP, lowQ;
 };
 
@@ -115,18 +116,20 @@ __device__ __forceinline__ void ring_accept(uint32_t A0, uint32_t A1, const Ring
 {
     uint32_t p8 = ac.fullP ? 0xFFu : (ac.tP ? gather_bytes(byte_lt(A0, ac.tP), byte_lt(A1, ac.tP)) : 0u);
     uint32_t q8 = ac.tQ ? gather_bytes(byte_lt(A0, ac.tQ), byte_lt(A1, ac.tQ)) : 0u;
-    const uint32_t tp8 = (!ac.fullP && ac.lowP) ? gather_bytes(byte_eq(A0, ac.tP), byte_eq(A1, ac.tP)) & mn_t : 0u;
-    const uint32_t tq8 = ac.lowQ ? gather_bytes(byte_eq(A0, ac.tQ), byte_eq(A1, ac.tQ)) & mx_t : 0u;
-    uint32_t ties = tp8 | tq8;
-    while (ties) {
-        const uint32_t mm = __builtin_ctz(ties);
-        ties &= ties - 1;
-        const uint64_t g = tile0 + mm;
-        const U4 c = philox((uint32_t)g, (uint32_t)(g >> 32), a.t, (TAG_ACC1D2 << 24) | k,
-                            a.seed_lo, a.seed_hi);
-        const uint32_t c24 = c.x & 0xFFFFFFu;
-        if (((tp8 >> mm) & 1u) && c24 < ac.lowP) p8 |= 1u << mm;
-        if (((tq8 >> mm) & 1u) && c24 < ac.lowQ) q8 |= 1u << mm;
+    if (ac.ties) {   // uniform: skipped when both thresholds are whole bytes
+        const uint32_t tp8 = (!ac.fullP && ac.lowP) ? gather_bytes(byte_eq(A0, ac.tP), byte_eq(A1, ac.tP)) & mn_t : 0u;
+        const uint32_t tq8 = ac.lowQ ? gather_bytes(byte_eq(A0, ac.tQ), byte_eq(A1, ac.tQ)) & mx_t : 0u;
+        uint32_t ties = tp8 | tq8;
+        while (ties) {
+            const uint32_t mm = __builtin_ctz(ties);
+            ties &= ties - 1;
+            const uint64_t g = tile0 + mm;
+            const U4 c = philox((uint32_t)g, (uint32_t)(g >> 32), a.t, (TAG_ACC1D2 << 24) | k,
+                                a.seed_lo, a.seed_hi);
+            const uint32_t c24 = c.x & 0xFFFFFFu;
+            if (((tp8 >> mm) & 1u) && c24 < ac.lowP) p8 |= 1u << mm;
+            if (((tq8 >> mm) & 1u) && c24 < ac.lowQ) q8 |= 1u << mm;
+        }
     }
     accP = spread8(p8) * 0xFu;
     accQ = spread8(q8) * 0xFu;
@@ -208,6 +211,7 @@ __global__ __launch_bounds__(64) void kpz_ring_sweep_kernel(const RingArgs a)
     ac.tQ = (uint32_t)(a.Q >> 24);
     ac.lowP = (uint32_t)(a.P & 0xFFFFFFu);
     ac.lowQ = (uint32_t)(a.Q & 0xFFFFFFu);
+    ac.ties = (!ac.fullP && ac.lowP != 0) || ac.lowQ != 0;
     const bool single = a.nb == 1;     // one periodic block: site 0 is live
     int net = 0;
 
