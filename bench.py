@@ -349,8 +349,9 @@ def serving_leg(args):
         print(f"bench: serving {done}/{total} done, {resident} resident", file=sys.stderr,
               flush=True)
 
+    kw = {"block": tuple(args.serve_block)} if args.serve_block else {}
     rep = serve.serve(jobs, hbm_bytes=int(args.serve_hbm_gib * (1 << 30)),
-                      quantum=args.serve_quantum, progress=progress)
+                      quantum=args.serve_quantum, progress=progress, **kw)
     return {
         "metric": "job latency p50/p99 (arrival -> result), serving",
         "p50_ms": rep.latency_p50_ms,
@@ -436,6 +437,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-hbm-gib", type=float, default=16.0)
     ap.add_argument("--serve-quantum", type=int, default=64)
+    ap.add_argument("--serve-block", type=int, nargs=2, default=None,
+                    help="common block shape of the job pool (default: the pool's own)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (3 times) "
                          "and exit: the known-size reference for HBM byte counters")

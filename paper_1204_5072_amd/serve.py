@@ -11,7 +11,7 @@ from typing import Dict, List, Optional
 
 import numpy as np
 
-from . import Pool, make_params
+from . import POOL_BLOCK, Pool, make_params
 
 
 @dataclass
@@ -60,7 +60,7 @@ class ServeReport:
         return self.attempts / self.seconds
 
 
-def serve(jobs: List[Job], hbm_bytes: int, quantum: int = 64, block=(256, 256),
+def serve(jobs: List[Job], hbm_bytes: int, quantum: int = 64, block=POOL_BLOCK,
           max_jobs: int = 1024, clock=time.perf_counter, progress=None,
           progress_every_s: float = 10.0) -> ServeReport:
     """Runs the jobs in real time: a job becomes visible at its arrival time,

@@ -17,8 +17,8 @@ def gpu():
     return kpz
 
 
-def alone(kpz, L, p, q, seed, n, block=(256, 256)):
-    sim = kpz.Sim(L, p, q, seed, block)
+def alone(kpz, L, p, q, seed, n, block=None):
+    sim = kpz.Sim(L, p, q, seed, block or kpz.POOL_BLOCK)
     sim.sweep(n)
     m = sim.roughness()
     sim.close()
