@@ -333,3 +333,20 @@ def test_height_moments_exact(gpu, oracle_lib, L, block, p, q, n):
     m2 = ref[1] / N - mu * mu
     assert math.isclose(w2, m2, rel_tol=1e-12)
     assert w2 == pytest.approx(sim.roughness().W2, rel=1e-12)
+
+
+def test_l16384_moments_and_words(gpu, oracle_lib):
+    """L = 16384 (rows of 1024 words: the row pass's sixteen-words-per-lane
+    path and its DPP scan), the benchmark's 1024 x 64 blocks, two-buffer
+    (rotated) storage, q > 0: words and exact moments after 2 MCS equal the
+    oracle's (about half a minute of oracle time)."""
+    L, B, p, q, seed, n = 16384, (1024, 64), 1.0, 0.25, 21, 2
+    _log(f"L={L} block={B} q={q}: GPU")
+    sim = gpu.Sim(L, p, q, seed, B)
+    sim.sweep(n)
+    m = sim.roughness()
+    w = sim.words_host()
+    _log(f"L={L}: oracle")
+    st = oracle_state(oracle_lib, L, n, p, q, seed, B)
+    assert np.array_equal(w, oracle_lib.pack(st.sx, st.sy))
+    assert_moments(oracle_lib, st, m, L)
