@@ -731,7 +731,7 @@ __global__ __launch_bounds__(TPB) void kpz_dt_swar_kernel(const SweepArgs a, uin
 // ------------------------------------------------------------ roughness
 
 // Per row y: with P(x) = sum_{l<x} sigma_x(l,y) (height relative to the row
-// start), A_y = sum_x P(x) and B_y = sum_x P(x)^2.  One wave per row.
+// start), A_y = sum_x P(x) and B_y = sum_x P(x)^2, a group of lanes per row.
 //
 // A word's 16 sigma_x bits are compacted into two bytes of 8 sites; a
 // 256-entry LDS table gives, for 8 sites with local prefix p_k (k = 0..7),
