@@ -1038,6 +1038,41 @@ __global__ __launch_bounds__(1024) void kpz_finalize_kernel(uint32_t L, const lo
     finalize_moments<1024>(L, rowA, rowB, slots, NSLOTS, res);
 }
 
+// Lattices of at most SMALL_ROWS rows: the row pass and the finalize in one
+// work-group, the row sums in LDS (one launch per sample instead of two).
+constexpr uint32_t SMALL_ROWS = 1024;
+
+__global__ __launch_bounds__(1024) void kpz_roughness_small_kernel(const uint32_t *words,
+                                                                   uint32_t L, uint32_t W,
+                                                                   const long long *slots,
+                                                                   long long *res, const Rot rot)
+{
+    __shared__ uint32_t lut[256];
+    __shared__ long long rA[SMALL_ROWS], rB[SMALL_ROWS];
+    if (threadIdx.x < 256) lut[threadIdx.x] = lut8_entry(threadIdx.x);
+    __syncthreads();
+    const uint32_t rot2 = 2u * rot_sites(rot);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t G = row_lanes(W), R = 64u / G;
+    const uint32_t gl = lane & (G - 1u);
+    const uint32_t tasks = (L + R - 1u) / R;
+    for (uint32_t task = wv; task < tasks; task += 16u) {
+        const uint32_t row = task * R + lane / G;
+        if (row < L) {   // a whole lane group is in or out
+            long long A, B;
+            uint32_t first;
+            row_moments<4>(words + (size_t)row * W, W, lut, gl, G, rot2, A, B, first);
+            if (gl == 0) {
+                rA[row] = A;
+                rB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y(0, row)
+            }
+        }
+    }
+    __syncthreads();
+    finalize_moments<1024>(L, rA, rB, slots, NSLOTS, res);
+}
+
 
 // ------------------------------------------------ height moments to order 4
 //
@@ -2275,16 +2310,24 @@ kpz_status kpz_roughness(kpz_sim *s, int64_t *S1o, int64_t *S2o, double *W2o)
     clear_pending_error();
     if (!s) return KPZ_EINVAL;
     const uint32_t L = (uint32_t)s->prm.L, W = L / 16;
-    const uint32_t nt = row_tasks(L);
-    const uint32_t rgrid = (nt + 3) / 4 < 4096 ? (nt + 3) / 4 : 4096;
-    hipLaunchKernelGGL(kpz_row_moments_kernel, dim3(rgrid), dim3(256), 0, s->stream,
-                       s->buf[s->cur], L, W, ws_rowA(s), ws_rowB(s), sim_rot(s));
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(s, e, "kpz_roughness launch");
-    hipLaunchKernelGGL(kpz_finalize_kernel, dim3(1), dim3(1024), 0, s->stream, L, ws_rowA(s),
-                       ws_rowB(s), ws_slots(s), ws_res(s));
-    e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(s, e, "kpz_roughness launch");
+    hipError_t e = hipSuccess;
+    if (L <= SMALL_ROWS) {
+        hipLaunchKernelGGL(kpz_roughness_small_kernel, dim3(1), dim3(1024), 0, s->stream,
+                           s->buf[s->cur], L, W, ws_slots(s), ws_res(s), sim_rot(s));
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(s, e, "kpz_roughness launch");
+    } else {
+        const uint32_t nt = row_tasks(L);
+        const uint32_t rgrid = (nt + 3) / 4 < 4096 ? (nt + 3) / 4 : 4096;
+        hipLaunchKernelGGL(kpz_row_moments_kernel, dim3(rgrid), dim3(256), 0, s->stream,
+                           s->buf[s->cur], L, W, ws_rowA(s), ws_rowB(s), sim_rot(s));
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(s, e, "kpz_roughness launch");
+        hipLaunchKernelGGL(kpz_finalize_kernel, dim3(1), dim3(1024), 0, s->stream, L, ws_rowA(s),
+                           ws_rowB(s), ws_slots(s), ws_res(s));
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(s, e, "kpz_roughness launch");
+    }
     long long res[4];
     e = hipMemcpyAsync(res, ws_res(s), sizeof res, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
