@@ -1042,16 +1042,12 @@ __global__ __launch_bounds__(1024) void kpz_finalize_kernel(uint32_t L, const lo
 // work-group, the row sums in LDS (one launch per sample instead of two).
 constexpr uint32_t SMALL_ROWS = 1024;
 
-__global__ __launch_bounds__(1024) void kpz_roughness_small_kernel(const uint32_t *words,
-                                                                   uint32_t L, uint32_t W,
-                                                                   const long long *slots,
-                                                                   long long *res, const Rot rot)
+// Row sums of a lattice of L <= SMALL_ROWS rows by the 16 waves of one
+// work-group of 1024 threads, into rA / rB (LDS); `lut` filled.
+__device__ __forceinline__ void small_rows(const uint32_t *words, uint32_t L, uint32_t W,
+                                           uint32_t rot2, const uint32_t *lut, long long *rA,
+                                           long long *rB)
 {
-    __shared__ uint32_t lut[256];
-    __shared__ long long rA[SMALL_ROWS], rB[SMALL_ROWS];
-    if (threadIdx.x < 256) lut[threadIdx.x] = lut8_entry(threadIdx.x);
-    __syncthreads();
-    const uint32_t rot2 = 2u * rot_sites(rot);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t G = row_lanes(W), R = 64u / G;
@@ -1069,6 +1065,18 @@ __global__ __launch_bounds__(1024) void kpz_roughness_small_kernel(const uint32_
             }
         }
     }
+}
+
+__global__ __launch_bounds__(1024) void kpz_roughness_small_kernel(const uint32_t *words,
+                                                                   uint32_t L, uint32_t W,
+                                                                   const long long *slots,
+                                                                   long long *res, const Rot rot)
+{
+    __shared__ uint32_t lut[256];
+    __shared__ long long rA[SMALL_ROWS], rB[SMALL_ROWS];
+    if (threadIdx.x < 256) lut[threadIdx.x] = lut8_entry(threadIdx.x);
+    __syncthreads();
+    small_rows(words, L, W, 2u * rot_sites(rot), lut, rA, rB);
     __syncthreads();
     finalize_moments<1024>(L, rA, rB, slots, NSLOTS, res);
 }
@@ -1480,6 +1488,26 @@ __global__ __launch_bounds__(256) void kpz_batch_rows_kernel(const MemberRows *m
             }
         }
     }
+}
+
+// Members of at most SMALL_ROWS rows: one work-group of 1024 threads per
+// member computes the row sums into LDS and finalizes them (one launch per
+// sample instead of two); results as for kpz_batch_finalize_kernel.
+__global__ __launch_bounds__(1024) void kpz_batch_moments_small_kernel(const MemberRows *mr,
+                                                                       uint32_t n, uint32_t nslots,
+                                                                       long long *res, uint32_t k)
+{
+    __shared__ uint32_t lut[256];
+    __shared__ long long rA[SMALL_ROWS], rB[SMALL_ROWS];
+    if (threadIdx.x < 256) lut[threadIdx.x] = lut8_entry(threadIdx.x);
+    __syncthreads();
+    const uint32_t r = blockIdx.x;
+    const MemberRows m = mr[r];
+    Rot rot;
+    const uint32_t *cur = member_current(m, rot);
+    small_rows(cur, m.L, m.W, 2u * rot_sites(rot), lut, rA, rB);
+    __syncthreads();
+    finalize_moments<1024>(m.L, rA, rB, m.slots, nslots, res + ((size_t)k * n + r) * 4);
 }
 
 // One work-group per member; results of sample `k` go to res[(k n + r) 4 ..].
@@ -1912,6 +1940,13 @@ kpz_status batch_sweep_on(kpz_batch *b, int32_t n_mcs, hipStream_t st)
 kpz_status batch_moments_on(kpz_batch *b, uint32_t k, hipStream_t st)
 {
     const MemberRows *mr = (const MemberRows *)(b->ws + b->lay.off_rows);
+    if (16u * b->lay.maxW <= SMALL_ROWS) {
+        hipLaunchKernelGGL(kpz_batch_moments_small_kernel, dim3(b->n), dim3(1024), 0, st, mr,
+                           (uint32_t)b->n, (uint32_t)BATCH_SLOTS, batch_res(b), k);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return batch_fail(b, e, "kpz_batch moments launch");
+        return KPZ_OK;
+    }
     const uint32_t nt = b->total_row_tasks;
     const uint32_t rgrid = (nt + 3) / 4 < 8192 ? (nt + 3) / 4 : 8192;
     hipLaunchKernelGGL(kpz_batch_rows_kernel, dim3(rgrid), dim3(256), 0, st, mr,
