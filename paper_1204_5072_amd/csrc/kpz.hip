@@ -745,8 +745,9 @@ __device__ __forceinline__ uint32_t lut8_entry(uint32_t byte)
         c += p * p;
         p += ((byte >> i) & 1u) ? 1 : -1;
     }
-    // d + 8 in bits 0..4, a + 28 in bits 5..10, c in bits 11..18
-    return (uint32_t)(p + 8) | ((uint32_t)(a + 28) << 5) | ((uint32_t)c << 11);
+    // two's complement d (-8..8) in bits 0..4 and a (-28..28) in bits 5..11,
+    // c (0..140) in bits 12..19: one signed or unsigned field extract each
+    return ((uint32_t)p & 31u) | (((uint32_t)a & 127u) << 5) | ((uint32_t)c << 12);
 }
 
 struct WordSums {
@@ -760,8 +761,8 @@ __device__ __forceinline__ WordSums word_sums(uint32_t w, const uint32_t *lut)
     x = (x | (x >> 2)) & 0x0F0F0F0Fu;
     x = (x | (x >> 4)) & 0x00FF00FFu;          // sites 0..7 in byte 0, 8..15 in byte 2
     const uint32_t e0 = lut[x & 0xFFu], e1 = lut[(x >> 16) & 0xFFu];
-    const int d0 = (int)(e0 & 31u) - 8, a0 = (int)((e0 >> 5) & 63u) - 28, c0 = (int)(e0 >> 11);
-    const int d1 = (int)(e1 & 31u) - 8, a1 = (int)((e1 >> 5) & 63u) - 28, c1 = (int)(e1 >> 11);
+    const int d0 = (int)(e0 << 27) >> 27, a0 = (int)(e0 << 20) >> 25, c0 = (int)(e0 >> 12);
+    const int d1 = (int)(e1 << 27) >> 27, a1 = (int)(e1 << 20) >> 25, c1 = (int)(e1 >> 12);
     WordSums r;
     r.d = d0 + d1;
     r.s1 = a0 + 8 * d0 + a1;
