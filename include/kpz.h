@@ -303,9 +303,12 @@ kpz_status kpz_pool_submit(kpz_pool *pool, const kpz_params *job, int64_t n_mcs,
 kpz_status kpz_pool_step(kpz_pool *pool, int32_t quantum, int32_t *n_active);
 
 /* Moves up to max_results finished jobs' results (FIFO) to the arrays;
- * *n_results = how many.  Any array may be NULL. */
+ * *n_results = how many.  status[k] is job k's own kpz_status (KPZ_OK, or
+ * e.g. KPZ_ESTATE if its words and flip counter disagreed; its moments are
+ * then not meaningful).  A failed job never hides the others: the call
+ * returns KPZ_OK whenever its arguments are valid.  Any array may be NULL. */
 kpz_status kpz_pool_poll(kpz_pool *pool, int32_t max_results, int64_t *job_ids, int64_t *S1,
-                         int64_t *S2, double *W2, int32_t *n_results);
+                         int64_t *S2, double *W2, int32_t *status, int32_t *n_results);
 
 /* Resident jobs and free arena bytes (largest free extent). */
 kpz_status kpz_pool_stats(const kpz_pool *pool, int32_t *n_active, size_t *largest_free);

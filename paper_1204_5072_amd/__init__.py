@@ -121,7 +121,7 @@ def lib() -> ctypes.CDLL:
                                     c.c_int32, vp]
         L.kpz_pool_submit.argtypes = [vp, P, c.c_int64, i64p]
         L.kpz_pool_step.argtypes = [vp, c.c_int32, i32p]
-        L.kpz_pool_poll.argtypes = [vp, c.c_int32, i64p, i64p, i64p, f64p, i32p]
+        L.kpz_pool_poll.argtypes = [vp, c.c_int32, i64p, i64p, i64p, f64p, i32p, i32p]
         L.kpz_pool_stats.argtypes = [vp, i32p, szp]
         L.kpz_pool_destroy.argtypes = [vp]
         L.kpz_pool_destroy.restype = None
@@ -403,6 +403,7 @@ class Pool:
         import torch
         self.block = tuple(block)
         self.max_quantum = max_quantum
+        self.failures = []
         self.device = torch.device(device)
         self.arena = torch.empty(int(hbm_bytes), dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -446,14 +447,25 @@ class Pool:
         return n.value
 
     def poll(self, max_results: int = 4096):
+        """Finished jobs as [(job id, Moments)], FIFO.  A job whose own
+        result failed (its kpz_status is not KPZ_OK) is not in the list: it
+        is appended to ``self.failures`` as (job id, status), so one bad job
+        never loses the others' results."""
         ids = (ctypes.c_int64 * max_results)()
         S1 = (ctypes.c_int64 * max_results)()
         S2 = (ctypes.c_int64 * max_results)()
         W2 = (ctypes.c_double * max_results)()
+        status = (ctypes.c_int32 * max_results)()
         n = ctypes.c_int32()
-        self._check(lib().kpz_pool_poll(self._h, max_results, ids, S1, S2, W2, ctypes.byref(n)),
-                    "kpz_pool_poll")
-        return [(ids[i], Moments(S1[i], S2[i], W2[i])) for i in range(n.value)]
+        self._check(lib().kpz_pool_poll(self._h, max_results, ids, S1, S2, W2, status,
+                                        ctypes.byref(n)), "kpz_pool_poll")
+        out = []
+        for i in range(n.value):
+            if status[i] == KPZ_OK:
+                out.append((ids[i], Moments(S1[i], S2[i], W2[i])))
+            else:
+                self.failures.append((ids[i], int(status[i])))
+        return out
 
     def stats(self):
         n, free = ctypes.c_int32(), ctypes.c_size_t()

@@ -2976,23 +2976,22 @@ kpz_status kpz_pool_step(kpz_pool *p, int32_t quantum, int32_t *n_active)
 }
 
 kpz_status kpz_pool_poll(kpz_pool *p, int32_t max_results, int64_t *ids, int64_t *S1, int64_t *S2,
-                         double *W2, int32_t *n_results)
+                         double *W2, int32_t *status, int32_t *n_results)
 {
     if (!p || max_results < 0) return KPZ_EINVAL;
     int32_t k = 0;
-    kpz_status worst = KPZ_OK;
     while (k < max_results && !p->done.empty()) {
         const PoolResult &r = p->done.front();
         if (ids) ids[k] = r.id;
         if (S1) S1[k] = r.S1;
         if (S2) S2[k] = r.S2;
         if (W2) W2[k] = r.W2;
-        if (r.st != KPZ_OK && worst == KPZ_OK) worst = r.st;
+        if (status) status[k] = (int32_t)r.st;
         p->done.pop_front();
         ++k;
     }
     if (n_results) *n_results = k;
-    return worst;
+    return KPZ_OK;
 }
 
 kpz_status kpz_pool_stats(const kpz_pool *p, int32_t *n_active, size_t *largest_free)

@@ -108,6 +108,10 @@ def serve(jobs: List[Job], hbm_bytes: int, quantum: int = 64, block=POOL_BLOCK,
             j = by_id.pop(jid)
             j.finished, j.result = now, mom
             done += 1
+        if pool.failures:
+            bad = list(pool.failures)
+            pool.close()
+            raise RuntimeError(f"serving: {len(bad)} job(s) failed (job id, kpz_status): {bad[:8]}")
     seconds = clock() - t0
     pool.close()
     lat = np.array([(j.finished - j.arrival) * 1e3 for j in jobs])
