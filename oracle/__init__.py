@@ -44,7 +44,7 @@ def build(force: bool = True) -> str:
         os.makedirs(os.path.dirname(LIB), exist_ok=True)
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared",
-                               "-fPIC", "-o", tmp, SRC, SRC_KMC, "-lm"])
+                               "-fPIC", "-fopenmp", "-o", tmp, SRC, SRC_KMC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -72,6 +72,9 @@ def lib():
         L.or_dd_run.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
                                 c.c_int, c.c_int, c.c_int, c.c_int, c.c_int,
                                 c.c_uint32, c.c_int, i8p, i8p, i64p, i64p, c.c_int]
+        L.or_dd_run_par.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
+                                    c.c_int, c.c_int, c.c_int, c.c_int, c.c_int,
+                                    c.c_uint32, c.c_int, i8p, i8p, i64p, i64p, c.c_int]
         L.or_rs1d_run.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
                                   c.c_uint32, c.c_int, i8p, i64p, i64p]
         L.or_dd_block_mcs.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
@@ -90,7 +93,8 @@ def lib():
                                 c.c_int, c.c_int, c.c_int, c.c_int,
                                 c.c_uint32, c.c_int, i8p, i8p, i64p, i64p, c.c_int]
         L.or_dt_perm.argtypes = [c.c_uint64, c.c_uint32, c.POINTER(c.c_int * 4)]
-        for f in ("or_flat", "or_rs_heights_run", "or_rs_slopes_run", "or_dd_run", "or_rs1d_run",
+        for f in ("or_flat", "or_rs_heights_run", "or_rs_slopes_run", "or_dd_run", "or_dd_run_par",
+                  "or_rs1d_run",
                   "or_dd_block_mcs", "or_dd1d_run", "or_dd1d_block_mcs", "or_dd1d_origin",
                   "or_flat1d", "or_dt_run", "or_dt_perm"):
             getattr(L, f).restype = c.c_int
@@ -147,13 +151,22 @@ class SlopeState:
 
     # dynamics
     def run_dd(self, n_mcs: int, p: float, q: float, seed: int, block=(None, None),
-               tile=(4, 4), check: bool = False, moves: int = 1) -> "SlopeState":
+               tile=(4, 4), check: bool = False, moves: int = 1,
+               threads: int = 0) -> "SlopeState":
         """n_mcs MCS of the decomposed schedule; ``moves`` = origin moves
-        per MCS (block residency 1/moves MCS)."""
+        per MCS (block residency 1/moves MCS).  ``threads`` > 0 runs the
+        blocks of each residency in parallel (or_dd_run_par, same result;
+        no neighbour check)."""
         bx = block[0] or self.L
         by = block[1] or self.L
-        rc = lib().or_dd_run(self.L, p, q, seed, bx, by, tile[0], tile[1], moves, self.t,
-                             n_mcs, self.sx, self.sy, self.h00, self.net, int(check))
+        if threads > 0:
+            assert not check, "the parallel runner has no neighbour check"
+            rc = lib().or_dd_run_par(self.L, p, q, seed, bx, by, tile[0], tile[1], moves,
+                                     self.t, n_mcs, self.sx, self.sy, self.h00, self.net,
+                                     int(threads))
+        else:
+            rc = lib().or_dd_run(self.L, p, q, seed, bx, by, tile[0], tile[1], moves, self.t,
+                                 n_mcs, self.sx, self.sy, self.h00, self.net, int(check))
         _check(rc, "dd_run")
         self.t += n_mcs
         return self

@@ -27,6 +27,7 @@
  *                      dead-border blocks with a random origin every MCS
  *                      (device layer), single-hit double tiling inside each
  *                      block (work-group layer)
+ *   or_dd_run_par      the same, blocks of a residency on several threads
  *   or_rs1d_run        the 1+1-d rooftop (ASEP) reduction (Sec. 2.1),
  *                      random-sequential
  *   or_dd1d_run        the same ring under the decomposition of Sec. 3 / 3.1
@@ -224,23 +225,26 @@ int or_rs_slopes_run(int L, double p, double q, uint64_t seed, uint32_t t0, int 
  * set-s_k cell.  Cells of one set are at least cx+1 (cy+1) sites apart, so
  * the attempts of a step never touch each other.
  *
- * Site inside a 2x2 cell: r in [0,4), rx = r & 1, ry = r >> 1.  Tiles are
- * numbered in groups of four: with H = nty/4 (or 1 if nty < 4), tile
- * (tx, ty) of block b is member j = ty / H of group
- * G = b*(ntx*H) + (ty mod H)*ntx + tx.  Step k of member j takes
- * r = bits 8j + 2(k mod 4) .. +1 of word k/4 of draw (SITE, t, G, 0).
- * 1x1 cells (2x2 tiles) draw no site bits.
+ * Draw numbering (this project's layout; the paper leaves the random
+ * streams open).  The tiles of one tile row ty of block b form the row
+ * group G = b*nty + ty (nty = By/Ty tile rows per block, at most 32 tiles
+ * per row); tile tx of the row owns bit pi(tx) = 8*(tx mod 4) + tx/4 of
+ * every 32-bit word drawn for the group.
+ *   Site in a 2x2 cell at step k: rx = bit pi(tx) of word 2*(k mod 2), ry =
+ *   bit pi(tx) of word 2*(k mod 2) + 1 of draw (SITE, t, G, k/2).  1x1
+ *   cells (2x2 tiles) draw no site.
+ *   Acceptance uniform at step k: u = sum_j b_j 2^(31-j), j = 0..31, b_j =
+ *   bit pi(tx) of word (k mod 4) of draw (ACC1, t, G, 4*(k/4) + j) for
+ *   j < 4, and of word (j mod 4) of draw (ACC2, t, G, 8*k + j/4 - 1) for
+ *   j >= 4.  The attempt is accepted iff u < P (at a minimum) or u < Q (at a
+ *   maximum), P = floor(p*2^32) (2^32 for p = 1), Q likewise.
  *
- * Acceptance uniform of member j of group G at step k:
- * u = A << 24 | (B & 0xFFFFFF), A = byte j of word (k mod 4) of
- * draw (ACC1, t, G, k/4), B = word j of draw (ACC2, t, G, k).
- *
- * Block residency (Sec. 3: the origin is moved "after some time").  With
+ * Block residency (Sec. 3: the origin is moved after some time).  With
  * `moves` = m > 1 the origin moves m times per MCS: residency i = 0..m-1
- * of MCS t has its own origin from draw (ORIGIN, t, i, 0) and runs steps
- * k = i S/m .. (i+1) S/m - 1 in the blocks of that origin, with the set,
- * site and acceptance draws above taken with sub-counters (SET: i; SITE: i;
- * ACC1: 4i + k/4; ACC2: 16i + k).  m = 1 is the schedule above.
+ * of MCS t has its own origin from draw (ORIGIN, t, i, 0) and set word
+ * from (SET, t, b, i), and runs steps k = i S/m .. (i+1) S/m - 1 in the
+ * blocks of that origin; site and acceptance draws are numbered by the
+ * step k within the MCS as above.  m = 1 is the schedule above.
  */
 static int dd_validate(int L, int Bx, int By, int Tx, int Ty, int moves)
 {
@@ -249,9 +253,62 @@ static int dd_validate(int L, int Bx, int By, int Tx, int Ty, int moves)
     if (Bx <= 0 || By <= 0 || L % Bx || L % By) return 0;
     if (!((Tx == 4 && Ty == 4) || (Tx == 2 && Ty == 2))) return 0;
     if (Bx % Tx || By % Ty) return 0;
-    int nty = By / Ty;
-    if (nty >= 4 && nty % 4) return 0;
+    if (Bx / Tx > 32) return 0;          /* at most 32 tiles per row group */
     return 1;
+}
+
+/* Bit of tile tx in every word drawn for its row group. */
+static int tile_bit(int tx) { return 8 * (tx & 3) + (tx >> 2); }
+
+/* Site (rx, ry) in the 2x2 cell of tile tx of row group G at step k. */
+static void cell_site(uint64_t seed, uint32_t t, uint64_t G, int k, int tx, int *rx, int *ry)
+{
+    uint32_t w[4];
+    or_draw(seed, OR_TAG_SITE, t, G, (uint32_t)(k >> 1), w);
+    const int bit = tile_bit(tx);
+    *rx = (int)((w[2 * (k & 1)] >> bit) & 1u);
+    *ry = (int)((w[2 * (k & 1) + 1] >> bit) & 1u);
+}
+
+/* The 32-bit acceptance uniform of tile tx of row group G at step k. */
+static uint32_t acc_uniform(uint64_t seed, uint32_t t, uint64_t G, int k, int tx)
+{
+    const int bit = tile_bit(tx);
+    uint32_t u = 0, w[4];
+    for (int j = 0; j < 32; ++j) {
+        uint32_t word;
+        if (j < 4) {
+            or_draw(seed, OR_TAG_ACC1, t, G, (uint32_t)(4 * (k >> 2) + j), w);
+            word = w[k & 3];
+        } else {
+            or_draw(seed, OR_TAG_ACC2, t, G, (uint32_t)(8 * k + (j >> 2) - 1), w);
+            word = w[j & 3];
+        }
+        u |= ((word >> bit) & 1u) << (31 - j);
+    }
+    return u;
+}
+
+/* Whether an attempt at a site of kind `kind` is accepted. */
+static int accepted(int kind, uint64_t P, uint64_t Q, uint64_t seed, uint32_t t, uint64_t G,
+                    int k, int tx)
+{
+    const uint64_t thr = kind == SITE_MIN ? P : Q;
+    if (thr == 0) return 0;
+    if (thr >= ((uint64_t)1 << 32)) return 1;
+    return (uint64_t)acc_uniform(seed, t, G, k, tx) < thr;
+}
+
+/* Block-local site (lx, ly) of tile (tx, ty) of row group G at step k with
+ * cell set s. */
+static void attempt_site(uint64_t seed, uint32_t t, uint64_t G, int k, int s, int tx, int ty,
+                         int Tx, int Ty, int *lx, int *ly)
+{
+    const int cx = Tx / 2, cy = Ty / 2;
+    int rx = 0, ry = 0;
+    if (cx * cy == 4) cell_site(seed, t, G, k, tx, &rx, &ry);
+    *lx = tx * Tx + (s & 1) * cx + rx;
+    *ly = ty * Ty + (s >> 1) * cy + ry;
 }
 
 int or_dd_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, int Ty,
@@ -261,21 +318,13 @@ int or_dd_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
     if (!dd_validate(L, Bx, By, Tx, Ty, moves) || n_mcs < 0) return OR_EINVAL;
     const int nbx = L / Bx, nby = L / By;
     const int ntx = Bx / Tx, nty = By / Ty;
-    const int H = nty >= 4 ? nty / 4 : 1;
-    const uint64_t nq = (uint64_t)ntx * (uint64_t)H;
-    const int cx = Tx / 2, cy = Ty / 2;
     const int S = Tx * Ty;
-    const int has_site_draw = (cx * cy == 4);
     const uint64_t P = threshold(p), Q = threshold(q);
-    const uint64_t FULL = (uint64_t)1 << 32;
     const int nblocks = nbx * nby;
-
-    /* per block: its set word; per group: its four site-draw words */
     uint32_t *setw = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)nblocks);
-    uint32_t *sitew = (uint32_t *)malloc(sizeof(uint32_t) * 4 * (size_t)nblocks * (size_t)nq);
     int64_t *stamp = check ? (int64_t *)malloc(sizeof(int64_t) * (size_t)L * (size_t)L) : NULL;
-    if (!setw || !sitew || (check && !stamp)) {
-        free(setw); free(sitew); free(stamp);
+    if (!setw || (check && !stamp)) {
+        free(setw); free(stamp);
         return OR_ENOMEM;
     }
     if (check)
@@ -294,11 +343,6 @@ int or_dd_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
         for (int b = 0; b < nblocks; ++b) {
             or_draw(seed, OR_TAG_SET, t, (uint64_t)b, (uint32_t)res, w);
             setw[b] = w[0];
-            if (has_site_draw)
-                for (uint64_t g = 0; g < nq; ++g) {
-                    or_draw(seed, OR_TAG_SITE, t, (uint64_t)b * nq + g, (uint32_t)res, w);
-                    memcpy(&sitew[4 * ((uint64_t)b * nq + g)], w, sizeof w);
-                }
         }
         /* all blocks make step k "at the same time"; blocks are independent,
            so visiting them one after the other gives the same result */
@@ -307,18 +351,11 @@ int or_dd_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
                 for (int bx = 0; bx < nbx; ++bx) {
                     const int b = by * nbx + bx;
                     const int s = (int)((setw[b] >> (2 * k)) & 3u);
-                    const int ssx = s & 1, ssy = s >> 1;
                     for (int ty = 0; ty < nty; ++ty)
                         for (int tx = 0; tx < ntx; ++tx) {
-                            const int j = ty / H;
-                            const uint64_t G = (uint64_t)b * nq + (uint64_t)(ty % H) * ntx + tx;
-                            int r = 0;
-                            if (has_site_draw)
-                                r = (int)((sitew[4 * G + (k >> 2)] >> (8 * j + 2 * (k & 3))) & 3u);
-                            const int rx = has_site_draw ? (r & 1) : 0;
-                            const int ry = has_site_draw ? (r >> 1) : 0;
-                            const int lx = tx * Tx + ssx * cx + rx;
-                            const int ly = ty * Ty + ssy * cy + ry;
+                            const uint64_t G = (uint64_t)b * (uint64_t)nty + (uint64_t)ty;
+                            int lx, ly;
+                            attempt_site(seed, t, G, k, s, tx, ty, Tx, Ty, &lx, &ly);
                             if ((nbx > 1 && lx == 0) || (nby > 1 && ly == 0)) continue;
                             const int gx = (ox + bx * Bx + lx) % L;
                             const int gy = (oy + by * By + ly) % L;
@@ -332,16 +369,7 @@ int or_dd_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
                             }
                             const int kind = classify(L, sx, sy, gx, gy);
                             if (kind == SITE_NONE) continue;
-                            const uint64_t thr = kind == SITE_MIN ? P : Q;
-                            if (thr == 0) continue;
-                            if (thr < FULL) {
-                                uint32_t wa[4], wb[4];
-                                or_draw(seed, OR_TAG_ACC1, t, G, (uint32_t)(4 * res + (k >> 2)), wa);
-                                or_draw(seed, OR_TAG_ACC2, t, G, (uint32_t)(16 * res + k), wb);
-                                const uint32_t A = (wa[k & 3] >> (8 * j)) & 0xFFu;
-                                const uint32_t u = (A << 24) | (wb[j] & 0xFFFFFFu);
-                                if ((uint64_t)u >= thr) continue;
-                            }
+                            if (!accepted(kind, P, Q, seed, t, G, k, tx)) continue;
                             flip(L, sx, sy, gx, gy);
                             const int dh = kind == SITE_MIN ? 2 : -2;
                             *net += dh / 2;
@@ -351,8 +379,67 @@ int or_dd_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
         }
       }
     }
-    free(setw); free(sitew); free(stamp);
+    free(setw); free(stamp);
     return status;
+}
+
+/*
+ * The same schedule visited block by block: within one residency the
+ * blocks never touch each other's slopes (dead borders; a block that spans
+ * a whole axis wraps onto itself), so a residency may run its blocks in any
+ * order, here in parallel over `threads` OpenMP threads, each block making
+ * all its steps before the next.  Equal to or_dd_run (tested); used to time
+ * the oracle on all host cores and to reach larger lattices in the tests.
+ */
+int or_dd_run_par(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, int Ty,
+                  int moves, uint32_t t0, int n_mcs, int8_t *sx, int8_t *sy, int64_t *h00,
+                  int64_t *net, int threads)
+{
+    if (!dd_validate(L, Bx, By, Tx, Ty, moves) || n_mcs < 0 || threads < 1) return OR_EINVAL;
+    const int nbx = L / Bx, nby = L / By;
+    const int ntx = Bx / Tx, nty = By / Ty;
+    const int S = Tx * Ty;
+    const uint64_t P = threshold(p), Q = threshold(q);
+    const int nblocks = nbx * nby;
+    const int per_res = S / moves;
+    for (int m = 0; m < n_mcs; ++m) {
+        const uint32_t t = t0 + (uint32_t)m;
+        for (int res = 0; res < moves; ++res) {
+            uint32_t w[4];
+            or_draw(seed, OR_TAG_ORIGIN, t, (uint64_t)res, 0, w);
+            const int ox = (int)(((uint64_t)w[0] * (uint64_t)Bx) >> 32);
+            const int oy = (int)(((uint64_t)w[1] * (uint64_t)By) >> 32);
+            int64_t dnet = 0, dh00 = 0;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(threads) reduction(+ : dnet, dh00)
+            for (int b = 0; b < nblocks; ++b) {
+                const int bx = b % nbx, by = b / nbx;
+                uint32_t ws[4];
+                or_draw(seed, OR_TAG_SET, t, (uint64_t)b, (uint32_t)res, ws);
+                for (int k = res * per_res; k < (res + 1) * per_res; ++k) {
+                    const int s = (int)((ws[0] >> (2 * k)) & 3u);
+                    for (int ty = 0; ty < nty; ++ty)
+                        for (int tx = 0; tx < ntx; ++tx) {
+                            const uint64_t G = (uint64_t)b * (uint64_t)nty + (uint64_t)ty;
+                            int lx, ly;
+                            attempt_site(seed, t, G, k, s, tx, ty, Tx, Ty, &lx, &ly);
+                            if ((nbx > 1 && lx == 0) || (nby > 1 && ly == 0)) continue;
+                            const int gx = (ox + bx * Bx + lx) % L;
+                            const int gy = (oy + by * By + ly) % L;
+                            const int kind = classify(L, sx, sy, gx, gy);
+                            if (kind == SITE_NONE) continue;
+                            if (!accepted(kind, P, Q, seed, t, G, k, tx)) continue;
+                            flip(L, sx, sy, gx, gy);
+                            const int dh = kind == SITE_MIN ? 2 : -2;
+                            dnet += dh / 2;
+                            if (gx == 0 && gy == 0) dh00 += dh;
+                        }
+                }
+            }
+            *net += dnet;
+            *h00 += dh00;
+        }
+    }
+    return OR_OK;
 }
 
 /* -------------------------------------------- 1+1-d rooftop reduction */
@@ -406,13 +493,8 @@ int or_dd_block_mcs(int L, double p, double q, uint64_t seed, int Bx, int By, in
     const int nbx = L / Bx, nby = L / By;
     if (nbx < 2 || nby < 2 || bx < 0 || by < 0 || bx >= nbx || by >= nby) return OR_EINVAL;
     const int ntx = Bx / Tx, nty = By / Ty;
-    const int H = nty >= 4 ? nty / 4 : 1;
-    const uint64_t nq = (uint64_t)ntx * (uint64_t)H;
-    const int cx = Tx / 2, cy = Ty / 2;
     const int S = Tx * Ty;
-    const int has_site_draw = (cx * cy == 4);
     const uint64_t P = threshold(p), Q = threshold(q);
-    const uint64_t FULL = (uint64_t)1 << 32;
     const int b = by * nbx + bx;
     const int per_res = S / moves;
     uint32_t w[4];
@@ -420,20 +502,11 @@ int or_dd_block_mcs(int L, double p, double q, uint64_t seed, int Bx, int By, in
     const uint32_t setw = w[0];
     for (int k = res * per_res; k < (res + 1) * per_res; ++k) {
         const int s = (int)((setw >> (2 * k)) & 3u);
-        const int ssx = s & 1, ssy = s >> 1;
         for (int ty = 0; ty < nty; ++ty)
             for (int tx = 0; tx < ntx; ++tx) {
-                const int j = ty / H;
-                const uint64_t G = (uint64_t)b * nq + (uint64_t)(ty % H) * ntx + tx;
-                int r = 0;
-                if (has_site_draw) {
-                    or_draw(seed, OR_TAG_SITE, t, G, (uint32_t)res, w);
-                    r = (int)((w[k >> 2] >> (8 * j + 2 * (k & 3))) & 3u);
-                }
-                const int rx = has_site_draw ? (r & 1) : 0;
-                const int ry = has_site_draw ? (r >> 1) : 0;
-                const int lx = tx * Tx + ssx * cx + rx;
-                const int ly = ty * Ty + ssy * cy + ry;
+                const uint64_t G = (uint64_t)b * (uint64_t)nty + (uint64_t)ty;
+                int lx, ly;
+                attempt_site(seed, t, G, k, s, tx, ty, Tx, Ty, &lx, &ly);
                 if (lx == 0 || ly == 0) continue;   /* dead border */
                 int8_t *a = &bsx[ly * Bx + lx], *bb = &bsy[ly * Bx + lx];
                 int8_t *c = &bsx[ly * Bx + lx - 1], *d = &bsy[(ly - 1) * Bx + lx];
@@ -441,16 +514,7 @@ int or_dd_block_mcs(int L, double p, double q, uint64_t seed, int Bx, int By, in
                 if (*a == 1 && *bb == 1 && *c == -1 && *d == -1) kind = SITE_MIN;
                 if (*a == -1 && *bb == -1 && *c == 1 && *d == 1) kind = SITE_MAX;
                 if (kind == SITE_NONE) continue;
-                const uint64_t thr = kind == SITE_MIN ? P : Q;
-                if (thr == 0) continue;
-                if (thr < FULL) {
-                    uint32_t wa[4], wb[4];
-                    or_draw(seed, OR_TAG_ACC1, t, G, (uint32_t)(4 * res + (k >> 2)), wa);
-                    or_draw(seed, OR_TAG_ACC2, t, G, (uint32_t)(16 * res + k), wb);
-                    const uint32_t A = (wa[k & 3] >> (8 * j)) & 0xFFu;
-                    const uint32_t u = (A << 24) | (wb[j] & 0xFFFFFFu);
-                    if ((uint64_t)u >= thr) continue;
-                }
+                if (!accepted(kind, P, Q, seed, t, G, k, tx)) continue;
                 *a = (int8_t)-*a; *bb = (int8_t)-*bb; *c = (int8_t)-*c; *d = (int8_t)-*d;
                 *net += kind == SITE_MIN ? 1 : -1;
             }
@@ -675,13 +739,8 @@ int or_dt_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
     const int nbx = L / Bx, nby = L / By;
     if (nbx < 2 || nby < 2 || (nbx & 1) || (nby & 1)) return OR_EINVAL;
     const int ntx = Bx / Tx, nty = By / Ty;
-    const int H = nty >= 4 ? nty / 4 : 1;
-    const uint64_t nq = (uint64_t)ntx * (uint64_t)H;
-    const int cx = Tx / 2, cy = Ty / 2;
     const int S = Tx * Ty;
-    const int has_site_draw = (cx * cy == 4);
     const uint64_t P = threshold(p), Q = threshold(q);
-    const uint64_t FULL = (uint64_t)1 << 32;
     int64_t *stamp = check ? (int64_t *)malloc(sizeof(int64_t) * (size_t)L * (size_t)L) : NULL;
     if (check && !stamp) return OR_ENOMEM;
     if (check)
@@ -704,18 +763,11 @@ int or_dt_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
                         const int b = by * nbx + bx;
                         or_draw(seed, OR_TAG_SET, t, (uint64_t)b, 0, w);
                         const int s = (int)((w[0] >> (2 * k)) & 3u);
-                        const int ssx = s & 1, ssy = s >> 1;
                         for (int ty = 0; ty < nty; ++ty)
                             for (int tx = 0; tx < ntx; ++tx) {
-                                const int j = ty / H;
-                                const uint64_t G = (uint64_t)b * nq + (uint64_t)(ty % H) * ntx + tx;
-                                int r = 0;
-                                if (has_site_draw) {
-                                    or_draw(seed, OR_TAG_SITE, t, G, 0, w);
-                                    r = (int)((w[k >> 2] >> (8 * j + 2 * (k & 3))) & 3u);
-                                }
-                                const int lx = tx * Tx + ssx * cx + (has_site_draw ? (r & 1) : 0);
-                                const int ly = ty * Ty + ssy * cy + (has_site_draw ? (r >> 1) : 0);
+                                const uint64_t G = (uint64_t)b * (uint64_t)nty + (uint64_t)ty;
+                                int lx, ly;
+                                attempt_site(seed, t, G, k, s, tx, ty, Tx, Ty, &lx, &ly);
                                 const int gx = (ox + bx * Bx + lx) % L;
                                 const int gy = (oy + by * By + ly) % L;
                                 if (check) {
@@ -727,16 +779,7 @@ int or_dt_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
                                 }
                                 const int kind = classify(L, sx, sy, gx, gy);
                                 if (kind == SITE_NONE) continue;
-                                const uint64_t thr = kind == SITE_MIN ? P : Q;
-                                if (thr == 0) continue;
-                                if (thr < FULL) {
-                                    uint32_t wa[4], wb[4];
-                                    or_draw(seed, OR_TAG_ACC1, t, G, (uint32_t)(k >> 2), wa);
-                                    or_draw(seed, OR_TAG_ACC2, t, G, (uint32_t)k, wb);
-                                    const uint32_t A = (wa[k & 3] >> (8 * j)) & 0xFFu;
-                                    const uint32_t u = (A << 24) | (wb[j] & 0xFFFFFFu);
-                                    if ((uint64_t)u >= thr) continue;
-                                }
+                                if (!accepted(kind, P, Q, seed, t, G, k, tx)) continue;
                                 flip(L, sx, sy, gx, gy);
                                 const int dh = kind == SITE_MIN ? 2 : -2;
                                 *net += dh / 2;
