@@ -226,10 +226,11 @@ int or_rs_slopes_run(int L, double p, double q, uint64_t seed, uint32_t t0, int 
  * the attempts of a step never touch each other.
  *
  * Draw numbering (this project's layout; the paper leaves the random
- * streams open).  The tiles of one tile row ty of block b form the row
- * group G = b*nty + ty (nty = By/Ty tile rows per block, at most 32 tiles
- * per row); tile tx of the row owns bit pi(tx) = 8*(tx mod 4) + tx/4 of
- * every 32-bit word drawn for the group.
+ * streams open).  Tile row ty of block b is cut into row groups of 32
+ * tiles, G = (b*nty + ty)*nqx + tx/32 (nty = By/Ty tile rows per block,
+ * nqx = ntx/32 groups per tile row, or one group of all ntx tiles when
+ * ntx <= 32); tile tx owns bit pi(tx) = 8*(tx mod 4) + (tx mod 32)/4 of
+ * every 32-bit word drawn for its group.
  *   Site in a 2x2 cell at step k: rx = bit pi(tx) of word 2*(k mod 2), ry =
  *   bit pi(tx) of word 2*(k mod 2) + 1 of draw (SITE, t, G, k/2).  1x1
  *   cells (2x2 tiles) draw no site.
@@ -253,12 +254,22 @@ static int dd_validate(int L, int Bx, int By, int Tx, int Ty, int moves)
     if (Bx <= 0 || By <= 0 || L % Bx || L % By) return 0;
     if (!((Tx == 4 && Ty == 4) || (Tx == 2 && Ty == 2))) return 0;
     if (Bx % Tx || By % Ty) return 0;
-    if (Bx / Tx > 32) return 0;          /* at most 32 tiles per row group */
+    /* a tile row is one row group of at most 32 tiles or whole groups of 32 */
+    if (Bx / Tx > 32 && (Bx / Tx) % 32) return 0;
     return 1;
 }
 
-/* Bit of tile tx in every word drawn for its row group. */
-static int tile_bit(int tx) { return 8 * (tx & 3) + (tx >> 2); }
+/* Bit of tile tx (tile tx mod 32 of its row group) in every word drawn
+ * for the group. */
+static int tile_bit(int tx) { return 8 * (tx & 3) + ((tx & 31) >> 2); }
+
+/* Row group of tile (tx, ty) of block b: tile row ty of the block cut into
+ * groups of 32 tiles (one group when the row has at most 32). */
+static uint64_t row_group(int b, int ty, int tx, int nty, int ntx)
+{
+    const uint64_t nqx = ntx > 32 ? (uint64_t)(ntx / 32) : 1u;
+    return ((uint64_t)b * (uint64_t)nty + (uint64_t)ty) * nqx + (uint64_t)(tx / 32);
+}
 
 /* Site (rx, ry) in the 2x2 cell of tile tx of row group G at step k. */
 static void cell_site(uint64_t seed, uint32_t t, uint64_t G, int k, int tx, int *rx, int *ry)
@@ -353,7 +364,7 @@ int or_dd_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
                     const int s = (int)((setw[b] >> (2 * k)) & 3u);
                     for (int ty = 0; ty < nty; ++ty)
                         for (int tx = 0; tx < ntx; ++tx) {
-                            const uint64_t G = (uint64_t)b * (uint64_t)nty + (uint64_t)ty;
+                            const uint64_t G = row_group(b, ty, tx, nty, ntx);
                             int lx, ly;
                             attempt_site(seed, t, G, k, s, tx, ty, Tx, Ty, &lx, &ly);
                             if ((nbx > 1 && lx == 0) || (nby > 1 && ly == 0)) continue;
@@ -419,7 +430,7 @@ int or_dd_run_par(int L, double p, double q, uint64_t seed, int Bx, int By, int 
                     const int s = (int)((ws[0] >> (2 * k)) & 3u);
                     for (int ty = 0; ty < nty; ++ty)
                         for (int tx = 0; tx < ntx; ++tx) {
-                            const uint64_t G = (uint64_t)b * (uint64_t)nty + (uint64_t)ty;
+                            const uint64_t G = row_group(b, ty, tx, nty, ntx);
                             int lx, ly;
                             attempt_site(seed, t, G, k, s, tx, ty, Tx, Ty, &lx, &ly);
                             if ((nbx > 1 && lx == 0) || (nby > 1 && ly == 0)) continue;
@@ -504,7 +515,7 @@ int or_dd_block_mcs(int L, double p, double q, uint64_t seed, int Bx, int By, in
         const int s = (int)((setw >> (2 * k)) & 3u);
         for (int ty = 0; ty < nty; ++ty)
             for (int tx = 0; tx < ntx; ++tx) {
-                const uint64_t G = (uint64_t)b * (uint64_t)nty + (uint64_t)ty;
+                const uint64_t G = row_group(b, ty, tx, nty, ntx);
                 int lx, ly;
                 attempt_site(seed, t, G, k, s, tx, ty, Tx, Ty, &lx, &ly);
                 if (lx == 0 || ly == 0) continue;   /* dead border */
@@ -765,7 +776,7 @@ int or_dt_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
                         const int s = (int)((w[0] >> (2 * k)) & 3u);
                         for (int ty = 0; ty < nty; ++ty)
                             for (int tx = 0; tx < ntx; ++tx) {
-                                const uint64_t G = (uint64_t)b * (uint64_t)nty + (uint64_t)ty;
+                                const uint64_t G = row_group(b, ty, tx, nty, ntx);
                                 int lx, ly;
                                 attempt_site(seed, t, G, k, s, tx, ty, Tx, Ty, &lx, &ly);
                                 const int gx = (ox + bx * Bx + lx) % L;

@@ -55,11 +55,10 @@
 
 #include "kpz.h"
 #include "kpz_device.h"
+#include "kpz_slice.h"
 
 namespace {
 
-using kpzdev::byte_eq;
-using kpzdev::byte_lt;
 using kpzdev::philox;
 using kpzdev::U4;
 
@@ -67,26 +66,7 @@ constexpr uint32_t TAG_ORIGIN = 1, TAG_SET = 2, TAG_SITE = 3, TAG_ACC1 = 4, TAG_
 constexpr int NSLOTS = 1024;          // flip-counter slots in the workspace
 constexpr int WS_HEADER = 256;        // results area at the start of the workspace
 constexpr int TILE = 4;               // tile edge (sites)
-
-// ------------------------------------------------------------ bit helpers
-
-__device__ __forceinline__ uint32_t rotr(uint32_t x, uint32_t s)
-{
-    return __builtin_amdgcn_alignbit(x, x, s);
-}
-
-// 4 x 4 byte transpose: out[m].byte[j] = in[j].byte[m].
-__device__ __forceinline__ void transpose_bytes(uint32_t v[4])
-{
-    const uint32_t t0 = __builtin_amdgcn_perm(v[1], v[0], 0x05010400u);
-    const uint32_t t1 = __builtin_amdgcn_perm(v[1], v[0], 0x07030602u);
-    const uint32_t t2 = __builtin_amdgcn_perm(v[3], v[2], 0x05010400u);
-    const uint32_t t3 = __builtin_amdgcn_perm(v[3], v[2], 0x07030602u);
-    v[0] = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
-    v[1] = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
-    v[2] = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
-    v[3] = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
-}
+constexpr uint32_t GROUP_SITES = 128; // sites of a row group (32 tiles, one bit each per plane word)
 
 // ---------------------------------------------------------------- init
 
@@ -118,15 +98,14 @@ struct SweepArgs {
     uint32_t *words;             // output lattice (and input when src == words)
     const uint32_t *src;         // input lattice
     uint32_t *side;              // [2][L][nbx]: straddling-word parts (left edge, right edge)
-    unsigned long long *slots;   // NSLOTS flip counters
+    unsigned long long *slots;   // flip counters
     uint32_t L, W;               // size, words per row
     uint32_t Bx, By;             // block shape
     uint32_t nbx, nby;           // blocks per direction
-    uint32_t ntx, log2ntx;       // tiles per block row
-    uint32_t H, log2H;           // quad rows per plane (nty / 4)
-    uint32_t nq;                 // quads per plane
-    uint32_t nw, log2nw;         // aligned words per block row (Bx / 16)
-    uint32_t units;              // load/store units per block (nq / 2)
+    uint32_t nw;                 // words per block row (Bx / 16)
+    uint32_t nqx;                // row groups per tile row (Bx / 128, at least 1)
+    uint32_t ntg, nwg;           // tiles and lattice words per row group
+    uint32_t nty, log2nty;       // tile rows per block (By / 4)
     uint32_t seed_lo, seed_hi;
     uint32_t t;
     uint32_t res;                // residency of MCS t (origin move), 0 .. moves - 1
@@ -164,186 +143,81 @@ __device__ __forceinline__ uint32_t rot_sites(const Rot &r)
     return (uint32_t)(((uint64_t)w.x * r.Bx) >> 32) & 15u;
 }
 
-// Quad q = tid + TPB i (tid = thread in the block) has tile column
-// qx = q mod ntx and quad row qy = q / ntx.  With NTX (= ntx) known at
-// compile time both tests below fold to constants or a single lane compare.
-template <int TPB, int NTX>
-__device__ __forceinline__ bool quad_left_edge(uint32_t tid, int i, const SweepArgs &a)
+// Index i + d of a periodic row of W words (i < W, d <= W).
+__device__ __forceinline__ uint32_t wrap_add(uint32_t i, uint32_t d, uint32_t W)
 {
-    if constexpr (NTX >= TPB) return (i % (NTX / TPB)) == 0 && tid == 0;
-    else if constexpr (NTX > 0) return (tid & (NTX - 1)) == 0;
-    else return ((tid + (uint32_t)TPB * i) & (a.ntx - 1)) == 0;
+    const uint32_t j = i + d;
+    return j >= W ? j - W : j;
 }
 
-template <int TPB, int NTX>
-__device__ __forceinline__ bool quad_bottom_row(uint32_t tid, int i, const SweepArgs &a)
+// The nwg (1, 2, 4 or 8) lattice words of a row group whose first site is
+// bit sh2 of storage word gw of row `row`, realigned so that A[i] holds the
+// group's sites 16 i .. 16 i + 15; A[i] = 0 for i >= nwg.  w0: storage word
+// gw itself.  VEC (W % 4 == 0): three 16-byte loads of the aligned words
+// around the group, the funnel shift chosen by gw mod 4 (uniform).
+template <int O>
+__device__ __forceinline__ void funnel8(const uint32_t (&v)[12], uint32_t sh2, uint32_t nwg,
+                                        uint32_t (&A)[8])
 {
-    if constexpr (NTX >= TPB) return i < NTX / TPB;
-    else if constexpr (NTX > 0) return i == 0 && tid < (uint32_t)NTX;
-    else return tid + (uint32_t)TPB * i < a.ntx;
-}
-
-// Byte-wise helpers for the acceptance test of four tiles at once (byte_lt
-// and byte_eq are in kpz_device.h).
-__device__ __forceinline__ uint32_t bytes_nonzero(uint32_t F)
-{
-    // F has at most one bit per byte, at position 0, 2, 4 or 6
-    return (F + 0x7F7F7F7Fu) & 0x80808080u;
-}
-
-__device__ __forceinline__ uint32_t expand_bit7(uint32_t m7)
-{
-    const uint32_t m = m7 >> 7;
-    return (m << 8) - m;
-}
-
-struct AccCtx {
-    bool fullP;          // P = 2^32: every minimum is accepted
-    bool ties;           // a threshold below 2^32 has nonzero low bits: A equal
-                         // to its top byte needs the second draw
-    uint32_t tP, tQ;     // top bytes of P and Q
-    uint32_t lowP, lowQ; // low 24 bits of P and Q
-};
-
-// One single-hit attempt in each of the four tiles of a quad.  ca, la, da:
-// LDS indices of the quad's own cells (set s), the cells to the left (set
-// s^1) and the cells below (set s^2).
-//
-// DT (double tiling at the device layer): with splice set (a bottom-row quad
-// and sy = 0) the lower cell of byte 0 is the halo byte at LDS index hb (the
-// block below), not byte 3 of the block's top quad row.
-template <int SX, int SY, bool ACC, bool DT>
-__device__ __forceinline__ void quad_update(uint32_t *lds, uint32_t ca, uint32_t la, uint32_t da,
-                                            uint32_t rot, uint32_t D, uint32_t dm, bool lok,
-                                            uint32_t Aw, const AccCtx &ac, uint64_t G, uint32_t k,
-                                            const SweepArgs &a, int &net, bool splice = false,
-                                            uint32_t hb = 0)
-{
-    const uint32_t c = lds[ca];
-    const uint32_t l = lds[la];
-    const uint32_t top = SY ? 0u : lds[da];
-    uint32_t d = SY ? lds[da] : rotr(top, rot);
-    if (DT && !SY && splice) d = (d & ~0xFFu) | (lds[hb] & 0xFFu);
-    // one-hot sigma_x position 2r of each tile's chosen site
-    const uint32_t oh = __builtin_amdgcn_perm(0u, 0x40100401u, D) & ~dm;
-    // neighbour slopes moved onto each site's own bit positions:
-    // sigma_x(x-1,y) at 2r, sigma_y(x,y-1) at 2r+1
-    const uint32_t X = ((c << 2) & 0x44444444u) | ((l >> 2) & 0x11111111u);
-    const uint32_t Y = ((c << 4) & 0xA0A0A0A0u) | ((d >> 4) & 0x0A0A0A0Au);
-    const uint32_t N = X | Y;
-    // minimum: own slopes (+1,+1), incoming slopes (-1,-1)
-    const uint32_t zmin = c & ~N;
-    uint32_t F = zmin & (zmin >> 1) & oh;
-    if (ACC) {
-        // maximum: own slopes (-1,-1), incoming slopes (+1,+1).  A byte (tile)
-        // holds a minimum flip in F or a maximum flip in Fx, never both, so
-        // the P test applies to F and the Q test to Fx byte by byte
-        const uint32_t zmax = N & ~c;
-        const uint32_t Fx = zmax & (zmax >> 1) & oh;
-        // bit 7 of each byte: the tile's uniform A accepts
-        uint32_t accP = ac.fullP ? 0x80808080u : (ac.tP ? byte_lt(Aw, ac.tP) : 0u);
-        uint32_t accQ = ac.tQ ? byte_lt(Aw, ac.tQ) : 0u;
-        if (ac.ties) {
-            const uint32_t tieP = (!ac.fullP && ac.lowP) ? (bytes_nonzero(F) & byte_eq(Aw, ac.tP)) : 0u;
-            const uint32_t tieQ = ac.lowQ ? (bytes_nonzero(Fx) & byte_eq(Aw, ac.tQ)) : 0u;
-            if (__any((tieP | tieQ) != 0)) {
-                const U4 w2 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t,
-                                     (TAG_ACC2 << 24) | (16u * a.res + k),
-                                     a.seed_lo, a.seed_hi);
-                const uint32_t Bw[4] = {w2.x, w2.y, w2.z, w2.w};
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t b24 = Bw[j] & 0xFFFFFFu;
-                    if (((tieP >> (8 * j + 7)) & 1u) && b24 < ac.lowP) accP |= 0x80u << (8 * j);
-                    if (((tieQ >> (8 * j + 7)) & 1u) && b24 < ac.lowQ) accQ |= 0x80u << (8 * j);
-                }
+    for (int i = 0; i < 8; ++i)
+        A[i] = (uint32_t)i < nwg ? __builtin_amdgcn_alignbit(v[O + i + 1], v[O + i], sh2) : 0u;
+}
+
+template <bool VEC>
+__device__ __forceinline__ void load_group(const uint32_t *row, uint32_t gw, uint32_t W,
+                                           uint32_t nwg, uint32_t sh2, uint32_t (&A)[8],
+                                           uint32_t &w0)
+{
+    if constexpr (VEC) {
+        const uint32_t o = __builtin_amdgcn_readfirstlane(gw & 3u);
+        const uint32_t g0 = gw - o;
+        uint32_t v[12];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            uint4 x = make_uint4(0u, 0u, 0u, 0u);
+            if (4u * m < o + nwg + 1u) {
+                uint32_t idx = g0 + 4u * m;
+                if (idx >= W) idx -= W;
+                if (idx >= W) idx -= W;
+                x = *(const uint4 *)(row + idx);
             }
+            v[4 * m] = x.x; v[4 * m + 1] = x.y; v[4 * m + 2] = x.z; v[4 * m + 3] = x.w;
         }
-        const uint32_t fmin = F & expand_bit7(accP), fmax = Fx & expand_bit7(accQ);
-        net += __builtin_popcount(fmin) - __builtin_popcount(fmax);
-        F = fmin | fmax;
+        switch (o) {
+        case 0: funnel8<0>(v, sh2, nwg, A); w0 = v[0]; break;
+        case 1: funnel8<1>(v, sh2, nwg, A); w0 = v[1]; break;
+        case 2: funnel8<2>(v, sh2, nwg, A); w0 = v[2]; break;
+        default: funnel8<3>(v, sh2, nwg, A); w0 = v[3]; break;
+        }
     } else {
-        net += __builtin_popcount(F);
-    }
-    // flip: own sigma_x, sigma_y; sigma_x of the left site; sigma_y of the lower site
-    const uint32_t mc = F | (F << 1) | ((F >> 2) & 0x11111111u) | ((F >> 3) & 0x0A0A0A0Au);
-    const uint32_t ml = (F & 0x11111111u) << 2;
-    const uint32_t md = (F & 0x05050505u) << 5;
-    lds[ca] = c ^ mc;
-    if (SX || lok) lds[la] = l ^ ml;
-    if (SY) {
-        lds[da] = d ^ md;
-    } else if (DT && splice) {
-        // bytes 1..3 go back to the top quad row (bytes 0..2), byte 0 to the
-        // halo; the top row's byte 3 keeps its value
-        const uint32_t nd = d ^ md;
-        lds[da] = (rotr(nd, 8u) & 0x00FFFFFFu) | (top & 0xFF000000u);
-        lds[hb] = nd & 0xFFu;
-    } else {
-        lds[da] = rotr(d ^ md, (32u - rot) & 31u);
-    }
-}
-
-// All quads of this thread for one step with cell set (SX, SY).
-template <int TPB, int K, int NTX, int SX, int SY, bool ACC, bool DT>
-__device__ __forceinline__ void step_quads(uint32_t *lds, uint32_t tid, uint32_t kr,
-                                           const uint32_t (&sw)[K][4], const uint32_t (&aw)[K][4],
-                                           const AccCtx &ac, uint64_t Gbase, uint32_t k,
-                                           const SweepArgs &a, int &net)
-{
-    constexpr uint32_t S = SX + 2 * SY;
-    const uint32_t ntx = NTX ? (uint32_t)NTX : a.ntx;
-    const uint32_t nq = NTX ? (uint32_t)NTX * a.H : a.nq;
-    const uint32_t pc = S * nq, pl = (S ^ 1u) * nq, pd = (S ^ 2u) * nq;
+        uint32_t v[9];
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const uint32_t q = tid + (uint32_t)TPB * i;
-        const bool ledge = SX ? false : quad_left_edge<TPB, NTX>(tid, i, a);
-        const bool bottom = SY ? false : quad_bottom_row<TPB, NTX>(tid, i, a);
-        // left quad (tile tx-1) for sx = 0: q-1, or the wrap-around quad of
-        // a single periodic block, or (dead left edge) the quad itself,
-        // which is then only read
-        const uint32_t lq = SX ? q : (ledge ? (a.nbx == 1 ? q + ntx - 1 : q) : q - 1);
-        // lower quad (tile ty-1) for sy = 0: q - ntx, or for the bottom quad
-        // row the top quad row, one byte down
-        const uint32_t dq = SY ? q : (bottom ? q + (a.H - 1) * ntx : q - ntx);
-        const uint32_t rot = bottom ? 24u : 0u;
-        if constexpr (DT) {
-            // no dead sites: the left cells of the left edge are the halo
-            // column (hcol[sy][qy] after the four planes), the lower cells of
-            // the bottom row's first tile row the halo row (hrow[sx][tx])
-            const uint32_t la = ledge ? 4 * nq + SY * a.H + q / ntx : pl + lq;
-            const uint32_t hb = 4 * nq + 2 * a.H + SX * ntx + (q & (ntx - 1));
-            const uint32_t D = (sw[i][0] >> (2 * kr)) & 0x03030303u;
-            quad_update<SX, SY, ACC, true>(lds, pc + q, la, pd + dq, rot, D, 0u, true,
-                                           ACC ? aw[i][0] : 0u, ac, Gbase + q, k, a, net, bottom,
-                                           hb);
-        } else {
-            const uint32_t dm = (ledge && a.nbx > 1 ? 0x11111111u : 0u) |
-                                (bottom && a.nby > 1 ? 0x00000005u : 0u);
-            const bool lok = !ledge || a.nbx == 1;
-            const uint32_t D = (sw[i][0] >> (2 * kr)) & 0x03030303u;
-            quad_update<SX, SY, ACC, false>(lds, pc + q, pl + lq, pd + dq, rot, D, dm, lok,
-                                            ACC ? aw[i][0] : 0u, ac, Gbase + q, k, a, net);
-        }
+        for (uint32_t i = 0; i < 9; ++i) v[i] = i <= nwg ? row[wrap_add(gw, i, W)] : 0u;
+#pragma unroll
+        for (uint32_t i = 0; i < 8; ++i)
+            A[i] = i < nwg ? __builtin_amdgcn_alignbit(v[i + 1], v[i], sh2) : 0u;
+        w0 = v[0];
     }
 }
 
-// One MCS of dead-border block b (device layer) with the block in LDS.  DT:
-// block b of a double-tiling set instead (no dead sites, in place): the
-// left neighbour's last column and the lower neighbour's top row are loaded
-// as halos after the four planes, and written back (read-modify-write of
-// the slopes this block may flip) after the block's own words.
-template <int TPB, int K, int NTX, bool ACC, bool DT = false>
-__device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint32_t *lds)
+// One MCS residency of dead-border block b (DT: block b of a double-tiling
+// set, no dead sites, halos from the idle neighbours) by the calling wave;
+// the bit-sliced step is in kpz_slice.h.
+//
+// Device layer: origin (ox, oy) of residency res of MCS t; block (bx, by)
+// covers sites ((ox + bx Bx + lx) mod L, (oy + by By + ly) mod L).
+// Work-group layer: steps k = res * nsteps .. + nsteps - 1 of the MCS's 16;
+// step k takes cell set bits 2k.. of (SET, t, b, res).w0 and, for row group
+// G = (b nty + ty) nqx + q, the tile's bit of words 2 (k mod 2), +1 of
+// (SITE, t, G, k / 2) as the site (rx, ry) in its cell.
+template <bool ACC, bool DT, bool VEC>
+__device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
 {
-    const uint32_t tid = threadIdx.x;
+    using namespace kpzslice;
+    const uint32_t lane = threadIdx.x & 63u;
     const uint32_t bx = b % a.nbx, by = b / a.nbx;
-    const uint32_t ntx = NTX ? (uint32_t)NTX : a.ntx;
-    const uint32_t nq = NTX ? (uint32_t)NTX * a.H : a.nq;
-    const uint32_t nw = ntx / 4;
 
-    // device layer: origin of this residency, then this block's frame
     const U4 wo = philox(a.res, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
     const uint32_t ox = (uint32_t)(((uint64_t)wo.x * a.Bx) >> 32);
     const uint32_t oy = (uint32_t)(((uint64_t)wo.y * a.By) >> 32);
@@ -351,296 +225,279 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
     if (gx0 >= a.L) gx0 -= a.L;
     uint32_t gy0 = oy + by * a.By;
     if (gy0 >= a.L) gy0 -= a.L;
-    // storage rotation of the input (two-buffer mode)
     const uint32_t s_in =
         rot_sites(Rot{a.db & a.prev_valid, a.prev_t, a.prev_res, a.Bx, a.seed_lo, a.seed_hi});
     uint32_t px0 = gx0 + (a.L - s_in);          // storage position of the block's first site
     if (px0 >= a.L) px0 -= a.L;
     const uint32_t sh2 = 2u * (px0 & 15u);
     const uint32_t gw0 = px0 >> 4;
-    // two-buffer mode: the output is rotated by ox mod 16, so the block's
-    // first site starts output word (ox >> 4) + bx nw
-    uint32_t gwo = (ox >> 4) + bx * nw;
-    if (gwo >= a.W) gwo -= a.W;
 
-    // ---- load: HBM row words -> aligned block words -> cells -> quads.
-    // Unit u = (wx, qy, sy): aligned word column wx of the two rows of cell
-    // row sy in the tile rows qy + j H, j = 0..3.  The nw units of one row
-    // group sit in consecutive lanes of one wave (nw divides 64), so the next
-    // word of a row comes from the next lane.
-    constexpr int UIT = (K * TPB / 2 + TPB - 1) / TPB;
-    for (int it = 0; it < UIT; ++it) {
-        const uint32_t u = tid + (uint32_t)TPB * it;
-        const bool uok = u < a.units;
-        const uint32_t wx = u & (nw - 1);
-        const uint32_t rest = u >> a.log2nw;
-        const uint32_t qy = rest & (a.H - 1);
-        const uint32_t sy = rest >> a.log2H;
-        uint32_t gw = gw0 + wx;
-        if (gw >= a.W) gw -= a.W;
-        const uint32_t gw1 = gw + 1 == a.W ? 0 : gw + 1;
-        uint32_t E[4], O[4];
+    const uint32_t q = lane >> a.log2nty, ty = lane & (a.nty - 1u);
+    const bool active = q < a.nqx;
+    const uint32_t qw = active ? q * a.nwg : 0u;
+    const uint32_t gwq = wrap_add(gw0, qw, a.W);   // storage word of the group's first site
+
+    // ---- load: four rows of the group, transposed into planes
+    uint32_t X[4][4], Y[4][4];
+    uint32_t w0r[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t r0 = 4 * (qy + j * a.H) + 2 * sy;
-            uint32_t A[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                uint32_t gy = gy0 + r0 + h;
-                if (gy >= a.L) gy -= a.L;
-                const uint32_t *row = a.src + (size_t)gy * a.W;
-                const uint32_t lo = uok ? row[gw] : 0u;
-                uint32_t hi = __shfl_down(lo, 1, 64);
-                if (uok && wx == nw - 1 && sh2) hi = row[gw1];
-                A[h] = __builtin_amdgcn_alignbit(hi, lo, sh2);
-            }
-            E[j] = (A[0] & 0x0F0F0F0Fu) | ((A[1] & 0x0F0F0F0Fu) << 4);
-            O[j] = ((A[0] >> 4) & 0x0F0F0F0Fu) | (A[1] & 0xF0F0F0F0u);
+    for (int r = 0; r < 4; ++r) {
+        uint32_t A[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+        w0r[r] = 0u;
+        if (active) {
+            const uint32_t gy = wrap_add(gy0, 4u * ty + r, a.L);
+            load_group<VEC>(a.src + (size_t)gy * a.W, gwq, a.W, a.nwg, sh2, A, w0r[r]);
         }
-        transpose_bytes(E);
-        transpose_bytes(O);
-        if (uok) {
-            const uint32_t q0 = qy * ntx + 4 * wx;
-            *(uint4 *)(lds + (2 * sy) * nq + q0) = make_uint4(E[0], E[1], E[2], E[3]);
-            *(uint4 *)(lds + (2 * sy + 1) * nq + q0) = make_uint4(O[0], O[1], O[2], O[3]);
+        transpose8(A);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            X[r][c] = A[2 * c];
+            Y[r][c] = A[2 * c + 1];
         }
     }
-
+    // DT halos: sigma_x of the column left of the block (lanes of group 0,
+    // bit r = row r of the tile row) and sigma_y of the row below it (lanes of
+    // tile row 0, as planes)
+    uint32_t hx = 0u, hy[4] = {0u, 0u, 0u, 0u};
     if constexpr (DT) {
-        // halo column: sigma_x(gx0 - 1, y) of the block's rows, at the bits of
-        // the sx = 1 cells' right-hand sites (2 + 4 ry) of tile j = byte j
-        const uint32_t xh = gx0 == 0 ? a.L - 1 : gx0 - 1;
-        const uint32_t hw = xh >> 4, hbit = 2u * (xh & 15u);
-        for (uint32_t e = tid; e < 2 * a.H; e += TPB) {
-            const uint32_t sy = e / a.H, qy = e - sy * a.H;
-            uint32_t v = 0;
-            for (uint32_t j = 0; j < 4; ++j)
-                for (uint32_t ry = 0; ry < 2; ++ry) {
-                    uint32_t gy = gy0 + 4 * (qy + j * a.H) + 2 * sy + ry;
-                    if (gy >= a.L) gy -= a.L;
-                    const uint32_t bit = (a.src[(size_t)gy * a.W + hw] >> hbit) & 1u;
-                    v |= bit << (8 * j + 2 + 4 * ry);
+        if (active && q == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                uint32_t wl = w0r[r];
+                if (sh2 == 0) {
+                    const uint32_t gy = wrap_add(gy0, 4u * ty + r, a.L);
+                    wl = a.src[(size_t)gy * a.W + (gw0 == 0 ? a.W - 1 : gw0 - 1)];
                 }
-            lds[4 * nq + e] = v;
-        }
-        // halo row: sigma_y(x, gy0 - 1) of the block's columns, at the bits of
-        // the sy = 1 cells' upper sites (5 + 2 rx)
-        const uint32_t yh = gy0 == 0 ? a.L - 1 : gy0 - 1;
-        const uint32_t *hrowp = a.src + (size_t)yh * a.W;
-        for (uint32_t e = tid; e < 2 * ntx; e += TPB) {
-            const uint32_t sx = e / ntx, tx = e - sx * ntx;
-            uint32_t v = 0;
-            for (uint32_t rx = 0; rx < 2; ++rx) {
-                uint32_t x = gx0 + 4 * tx + 2 * sx + rx;
-                if (x >= a.L) x -= a.L;
-                v |= ((hrowp[x >> 4] >> (2u * (x & 15u) + 1u)) & 1u) << (5 + 2 * rx);
+                const uint32_t bit = sh2 ? sh2 - 2u : 30u;
+                hx |= ((wl >> bit) & 1u) << r;
             }
-            lds[4 * nq + 2 * a.H + e] = v;
+        }
+        if (active && ty == 0) {
+            uint32_t A[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+            uint32_t wdummy;
+            const uint32_t gy = gy0 == 0 ? a.L - 1 : gy0 - 1;
+            load_group<VEC>(a.src + (size_t)gy * a.W, gwq, a.W, a.nwg, sh2, A, wdummy);
+            transpose8(A);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) hy[c] = A[2 * c + 1];
         }
     }
 
-    // ---- site draws of this MCS for this thread's quads
-    const uint64_t Gbase = (uint64_t)b * nq;
-    uint32_t sw[K][4];
-    uint32_t aw[K][4];
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const uint64_t G = Gbase + tid + (uint32_t)TPB * i;
-        const U4 s4 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t, (TAG_SITE << 24) | a.res,
-                             a.seed_lo, a.seed_hi);
-        sw[i][0] = s4.x;
-        sw[i][1] = s4.y;
-        sw[i][2] = s4.z;
-        sw[i][3] = s4.w;
-        aw[i][0] = aw[i][1] = aw[i][2] = aw[i][3] = 0u;
-    }
+    // ---- per-lane constants
+    LaneCtx c;
+    c.vm = active ? ((1u << (a.ntg >> 2)) - 1u) * 0x01010101u : 0u;
+    c.dxm = (!DT && q == 0 && a.nbx > 1) ? 1u : 0u;
+    c.dym = (!DT && ty == 0 && a.nby > 1) ? ~0u : 0u;
+    c.xn = (a.nqx > 1 || a.nbx == 1) ? 1u : 0u;
+    const uint32_t span = (a.nqx - 1u) * a.nty;
+    const uint32_t srcL = q > 0 ? lane - a.nty : (a.nbx == 1 ? lane + span : lane);
+    const uint32_t srcR = q + 1 < a.nqx ? lane + a.nty : (a.nbx == 1 ? lane - span : lane);
+    c.srcL4 = 4u * srcL;
+    c.srcR4 = 4u * srcR;
+    c.rmask = (q + 1 < a.nqx || a.nbx == 1) ? ~0u : 0u;
+    c.pb = 24u + (a.ntg >> 2) - 1u;
+    c.wrapy = a.nby == 1 ? 1u : 0u;
+    c.srcD4 = 4u * (ty > 0 ? lane - 1u : lane + a.nty - 1u);
+    c.srcU4 = 4u * (ty + 1 < a.nty ? lane + 1u : lane - (a.nty - 1u));
+    c.hxl = (DT && q == 0) ? ~0u : 0u;
+    c.hyl = (DT && ty == 0) ? ~0u : 0u;
+    c.uym = (DT && ty + 1 == a.nty) ? 0u : ~0u;
+
+    const uint64_t G = ((uint64_t)b * a.nty + ty) * a.nqx + (active ? q : 0u);
+    AccDraw d;
+    d.P = a.P;
+    d.Q = a.Q;
+    d.nlP = levels_of(a.P);
+    d.nlQ = levels_of(a.Q);
+    d.nl = d.nlP > d.nlQ ? d.nlP : d.nlQ;
+    d.seed_lo = a.seed_lo;
+    d.seed_hi = a.seed_hi;
+    d.t = a.t;
+    d.G = (uint32_t)G;
+
+    // ---- work-group layer: single-hit steps k0 .. k1 - 1
     const uint32_t setw = philox(b, 0u, a.t, (TAG_SET << 24) | a.res, a.seed_lo, a.seed_hi).x;
-    // steps of this residency: [k0, k1) of the MCS's 16
     const uint32_t k0 = a.res * a.nsteps, k1 = k0 + a.nsteps;
-    AccCtx ac;
-    ac.fullP = a.P >= (1ull << 32);
-    ac.tP = ac.fullP ? 256u : (uint32_t)(a.P >> 24);
-    ac.tQ = (uint32_t)(a.Q >> 24);
-    ac.lowP = (uint32_t)(a.P & 0xFFFFFFu);
-    ac.lowQ = (uint32_t)(a.Q & 0xFFFFFFu);
-    ac.ties = (!ac.fullP && ac.lowP != 0) || ac.lowQ != 0;
-    const bool active = K * TPB == (int)nq || tid < nq;
     int net = 0;
-
-    __syncthreads();
-
-    // ---- work-group layer: single-hit steps k = 4 kq + kr in [k0, k1)
-    // (all 16 when the origin moves once per MCS); the step range is the
-    // same for the whole block, so skipping steps never splits a barrier
-    for (int kq = 0; kq < 4; ++kq) {
-        if (ACC && 4u * kq + 3u >= k0 && 4u * kq < k1) {
+    U4 sw = {0u, 0u, 0u, 0u};
+    uint32_t l1[4][4] = {{0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}};
+    for (uint32_t kq = k0 >> 2; 4u * kq < k1; ++kq) {
+        if (ACC) {
 #pragma unroll
-            for (int i = 0; i < K; ++i) {
-                const uint64_t G = Gbase + tid + (uint32_t)TPB * i;
-                const U4 w1 = philox((uint32_t)G, (uint32_t)(G >> 32), a.t,
-                                     (TAG_ACC1 << 24) | (4u * a.res + (uint32_t)kq), a.seed_lo,
-                                     a.seed_hi);
-                aw[i][0] = w1.x;
-                aw[i][1] = w1.y;
-                aw[i][2] = w1.z;
-                aw[i][3] = w1.w;
+            for (uint32_t j = 0; j < 4; ++j) {
+                if (j < d.nl) {
+                    const U4 v = philox((uint32_t)G, (uint32_t)(G >> 32), a.t,
+                                        (TAG_ACC1 << 24) | (4u * kq + j), a.seed_lo, a.seed_hi);
+                    l1[j][0] = v.x; l1[j][1] = v.y; l1[j][2] = v.z; l1[j][3] = v.w;
+                }
             }
         }
+#pragma unroll
         for (uint32_t kr = 0; kr < 4; ++kr) {
             const uint32_t k = 4u * kq + kr;
-            const uint32_t s = (setw >> (2 * k)) & 3u;
-            if (k >= k0 && k < k1) {
-                if (active) {
-                    switch (s) {
-                    case 0: step_quads<TPB, K, NTX, 0, 0, ACC, DT>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
-                    case 1: step_quads<TPB, K, NTX, 1, 0, ACC, DT>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
-                    case 2: step_quads<TPB, K, NTX, 0, 1, ACC, DT>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
-                    default: step_quads<TPB, K, NTX, 1, 1, ACC, DT>(lds, tid, kr, sw, aw, ac, Gbase, k, a, net); break;
-                    }
-                }
-                __syncthreads();
+            if (k < k0 || k >= k1) continue;
+            if ((kr & 1u) == 0 || k == k0)
+                sw = philox((uint32_t)G, (uint32_t)(G >> 32), a.t, (TAG_SITE << 24) | (k >> 1),
+                            a.seed_lo, a.seed_hi);
+            const uint32_t RX = (kr & 1u) ? sw.z : sw.x;
+            const uint32_t RY = (kr & 1u) ? sw.w : sw.y;
+            const uint32_t lev[4] = {l1[0][kr], l1[1][kr], l1[2][kr], l1[3][kr]};
+            switch ((setw >> (2u * k)) & 3u) {
+            case 0: step<0, 0, ACC, DT, TAG_ACC2>(X, Y, RX, RY, c, lev, d, k, net, hx, hy); break;
+            case 1: step<1, 0, ACC, DT, TAG_ACC2>(X, Y, RX, RY, c, lev, d, k, net, hx, hy); break;
+            case 2: step<0, 1, ACC, DT, TAG_ACC2>(X, Y, RX, RY, c, lev, d, k, net, hx, hy); break;
+            default: step<1, 1, ACC, DT, TAG_ACC2>(X, Y, RX, RY, c, lev, d, k, net, hx, hy); break;
             }
-            if (ACC) {
-#pragma unroll
-                for (int i = 0; i < K; ++i) {
-                    aw[i][0] = aw[i][1];
-                    aw[i][1] = aw[i][2];
-                    aw[i][2] = aw[i][3];
-                }
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-            sw[i][0] = sw[i][1];
-            sw[i][1] = sw[i][2];
-            sw[i][2] = sw[i][3];
         }
     }
 
-    // ---- store: quads -> cells -> aligned block words -> HBM row words.
-    // Two-buffer mode: the block's words are whole output words (the output
-    // is rotated by the origin), stored as they are.  In place: words wholly
-    // inside the block are stored; the block's parts of the two words it
-    // shares with its left and right neighbours go to the side buffer and
-    // are merged by a separate launch (the kernel boundary makes both parts
-    // visible; a release/acquire between work-groups inside the launch would
-    // write back the whole L2 per block).
-    for (int it = 0; it < UIT; ++it) {
-        const uint32_t u = tid + (uint32_t)TPB * it;
-        const bool uok = u < a.units;
-        const uint32_t wx = u & (nw - 1);
-        const uint32_t rest = u >> a.log2nw;
-        const uint32_t qy = rest & (a.H - 1);
-        const uint32_t sy = rest >> a.log2H;
-        const uint32_t q0 = qy * ntx + 4 * wx;
-        uint32_t E[4] = {0u, 0u, 0u, 0u}, O[4] = {0u, 0u, 0u, 0u};
-        if (uok) {
-            const uint4 e = *(const uint4 *)(lds + (2 * sy) * nq + q0);
-            const uint4 o = *(const uint4 *)(lds + (2 * sy + 1) * nq + q0);
-            E[0] = e.x; E[1] = e.y; E[2] = e.z; E[3] = e.w;
-            O[0] = o.x; O[1] = o.y; O[2] = o.z; O[3] = o.w;
+    // ---- store.  Two-buffer mode: the group's words are whole output words
+    // (the output is rotated by the origin).  In place: words wholly inside
+    // the block are stored (the word a group shares with the group to its
+    // left is assembled from that group's last word); the block's parts of
+    // the two words it shares with its neighbours go to the side buffer and
+    // are merged by a separate launch.  DT: those two words are merged in
+    // place (the neighbours are idle), and the halos are written back.
+    uint32_t gwo = (ox >> 4) + bx * a.nw;
+    if (gwo >= a.W) gwo -= a.W;
+    const uint32_t gwoq = wrap_add(gwo, qw, a.W);
+    const bool ovec = VEC && (gwoq & 3u) == 0 && (a.nwg & 3u) == 0;
+    const uint32_t lowm = sh2 ? (1u << sh2) - 1u : 0u;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        uint32_t A[8];
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            A[2 * cc] = X[r][cc];
+            A[2 * cc + 1] = Y[r][cc];
         }
-        transpose_bytes(E);
-        transpose_bytes(O);
-        uint32_t gw = (a.db ? gwo : gw0) + wx;
-        if (gw >= a.W) gw -= a.W;
+        transpose8(A);
+        const uint32_t gy = wrap_add(gy0, 4u * ty + r, a.L);
+        uint32_t *row = a.words + (size_t)gy * a.W;
+        if (a.db) {
+            if (!active) continue;
+            if (ovec) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t r0 = 4 * (qy + j * a.H) + 2 * sy;
-            uint32_t A[2];
-            A[0] = (E[j] & 0x0F0F0F0Fu) | ((O[j] & 0x0F0F0F0Fu) << 4);
-            A[1] = ((E[j] >> 4) & 0x0F0F0F0Fu) | (O[j] & 0xF0F0F0F0u);
+                for (uint32_t m = 0; m < 2; ++m)
+                    if (4u * m < a.nwg)
+                        *(uint4 *)(row + wrap_add(gwoq, 4u * m, a.W)) =
+                            make_uint4(A[4 * m], A[4 * m + 1], A[4 * m + 2], A[4 * m + 3]);
+            } else {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                uint32_t gy = gy0 + r0 + h;
-                if (gy >= a.L) gy -= a.L;
-                uint32_t *row = a.words + (size_t)gy * a.W;
-                if (a.db) {
-                    if (uok) row[gw] = A[h];
-                    continue;
-                }
-                const uint32_t prev = __shfl_up(A[h], 1, 64);
-                if (!uok) continue;
-                if (sh2 == 0) {
-                    row[gw] = A[h];
-                } else if (DT) {
-                    // the neighbours sharing the end words are idle (blocks of
-                    // one set are not adjacent): merge in place
-                    const uint32_t lowm = (1u << sh2) - 1u;
-                    if (wx > 0) row[gw] = __builtin_amdgcn_alignbit(A[h], prev, 32u - sh2);
-                    else row[gw] = (row[gw] & lowm) | (A[h] << sh2);
-                    if (wx == nw - 1) {
-                        const uint32_t gwn = gw + 1 == a.W ? 0u : gw + 1;
-                        row[gwn] = (row[gwn] & ~lowm) | (A[h] >> (32u - sh2));
-                    }
-                } else {
-                    if (wx > 0) row[gw] = __builtin_amdgcn_alignbit(A[h], prev, 32u - sh2);
-                    else a.side[(size_t)gy * a.nbx + bx] = A[h] << sh2;
-                    if (wx == nw - 1)
-                        a.side[((size_t)a.L + gy) * a.nbx + bx] = A[h] >> (32u - sh2);
-                }
+                for (uint32_t i = 0; i < 8; ++i)
+                    if (i < a.nwg) row[wrap_add(gwoq, i, a.W)] = A[i];
+            }
+            continue;
+        }
+        // in place (and DT): every lane takes part in the exchange
+        uint32_t lastA = A[0];
+#pragma unroll
+        for (uint32_t i = 1; i < 8; ++i)
+            if (i + 1 == a.nwg) lastA = A[i];
+        const uint32_t prevLast = bperm(c.srcL4, lastA);
+        if (!active) continue;
+        if (sh2 == 0) {
+#pragma unroll
+            for (uint32_t i = 0; i < 8; ++i)
+                if (i < a.nwg) row[wrap_add(gwq, i, a.W)] = A[i];
+            if (DT && q == 0) {
+                // halo column in the previous word, bit 30
+                uint32_t *wp = row + (gw0 == 0 ? a.W - 1 : gw0 - 1);
+                const uint32_t w = *wp;
+                const uint32_t nwv = (w & ~(1u << 30)) | (((hx >> r) & 1u) << 30);
+                if (nwv != w) *wp = nwv;
+            }
+            continue;
+        }
+#pragma unroll
+        for (uint32_t i = 1; i < 8; ++i)
+            if (i < a.nwg)
+                row[wrap_add(gwq, i, a.W)] = __builtin_amdgcn_alignbit(A[i], A[i - 1], 32u - sh2);
+        if (q > 0) {
+            row[gwq] = __builtin_amdgcn_alignbit(A[0], prevLast, 32u - sh2);
+        } else if (DT) {
+            const uint32_t hb = sh2 - 2u;
+            const uint32_t w = row[gwq];
+            row[gwq] = (w & lowm & ~(1u << hb)) | (((hx >> r) & 1u) << hb) | (A[0] << sh2);
+        } else {
+            a.side[(size_t)gy * a.nbx + bx] = A[0] << sh2;
+        }
+        if (q + 1 == a.nqx) {
+            if (DT) {
+                uint32_t *wp = row + wrap_add(gwq, a.nwg, a.W);
+                *wp = (*wp & ~lowm) | (lastA >> (32u - sh2));
+            } else {
+                a.side[((size_t)a.L + gy) * a.nbx + bx] = lastA >> (32u - sh2);
             }
         }
     }
 
     if constexpr (DT) {
-        // ---- halo write-back, after this block's own words (one of which
-        // may hold the halo column's bit)
-        __syncthreads();
-        const uint32_t xh = gx0 == 0 ? a.L - 1 : gx0 - 1;
-        const uint32_t hw = xh >> 4, hbit = 2u * (xh & 15u);
-        for (uint32_t e = tid; e < a.By; e += TPB) {
-            const uint32_t ty = e >> 2, sy = (e >> 1) & 1u, ry = e & 1u;
-            const uint32_t j = ty / a.H, qy = ty - j * a.H;
-            const uint32_t bit = (lds[4 * nq + sy * a.H + qy] >> (8 * j + 2 + 4 * ry)) & 1u;
-            uint32_t gy = gy0 + e;
-            if (gy >= a.L) gy -= a.L;
-            uint32_t *wp = a.words + (size_t)gy * a.W + hw;
-            const uint32_t w0 = *wp;
-            const uint32_t w1 = (w0 & ~(1u << hbit)) | (bit << hbit);
-            if (w1 != w0) *wp = w1;
+        // halo row: the sigma_y bits of the block's columns in the row below
+        uint32_t B[8];
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            B[2 * cc] = 0u;
+            B[2 * cc + 1] = hy[cc];
         }
-        const uint32_t yh = gy0 == 0 ? a.L - 1 : gy0 - 1;
-        uint32_t *hrowp = a.words + (size_t)yh * a.W;
-        const uint32_t nwr = nw + (sh2 ? 1u : 0u);      // words holding the block's columns
-        for (uint32_t m = tid; m < nwr; m += TPB) {
-            uint32_t gwm = gw0 + m;
-            if (gwm >= a.W) gwm -= a.W;
-            uint32_t val = 0, mask = 0;
-            for (uint32_t i = 0; i < 16; ++i) {
-                uint32_t e = 16 * gwm + i + (a.L - gx0);
-                if (e >= a.L) e -= a.L;
-                if (e >= a.Bx) continue;
-                const uint32_t tx = e >> 2, sx = (e >> 1) & 1u, rx = e & 1u;
-                const uint32_t bit = (lds[4 * nq + 2 * a.H + sx * ntx + tx] >> (5 + 2 * rx)) & 1u;
-                val |= bit << (2 * i + 1);
-                mask |= 1u << (2 * i + 1);
+        transpose8(B);
+        uint32_t lastB = B[0];
+#pragma unroll
+        for (uint32_t i = 1; i < 8; ++i)
+            if (i + 1 == a.nwg) lastB = B[i];
+        const uint32_t prevLastB = bperm(c.srcL4, lastB);
+        if (active && ty == 0) {
+            const uint32_t gy = gy0 == 0 ? a.L - 1 : gy0 - 1;
+            uint32_t *row = a.words + (size_t)gy * a.W;
+            const uint32_t YM = 0xAAAAAAAAu;
+            if (sh2 == 0) {
+#pragma unroll
+                for (uint32_t i = 0; i < 8; ++i)
+                    if (i < a.nwg) {
+                        uint32_t *wp = row + wrap_add(gwq, i, a.W);
+                        *wp = (*wp & ~YM) | B[i];
+                    }
+            } else {
+#pragma unroll
+                for (uint32_t i = 1; i < 8; ++i)
+                    if (i < a.nwg) {
+                        uint32_t *wp = row + wrap_add(gwq, i, a.W);
+                        *wp = (*wp & ~YM) | __builtin_amdgcn_alignbit(B[i], B[i - 1], 32u - sh2);
+                    }
+                uint32_t *wp = row + gwq;
+                if (q > 0)
+                    *wp = (*wp & ~YM) | __builtin_amdgcn_alignbit(B[0], prevLastB, 32u - sh2);
+                else
+                    *wp = (*wp & ~(YM & ~lowm)) | (B[0] << sh2);
+                if (q + 1 == a.nqx) {
+                    uint32_t *we = row + wrap_add(gwq, a.nwg, a.W);
+                    *we = (*we & ~(YM & lowm)) | (lastB >> (32u - sh2));
+                }
             }
-            const uint32_t w0 = hrowp[gwm];
-            const uint32_t w1 = (w0 & ~mask) | val;
-            if (w1 != w0) hrowp[gwm] = w1;
         }
     }
 
-    // ---- flip counter of this block: wave sums, one atomic per wave
+    // ---- flip counter of this block: wave sum, one atomic per block
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) net += __shfl_xor(net, off, 64);
-    if ((tid & 63u) == 0 && net != 0)
-        atomicAdd(a.slots + ((b * (TPB / 64) + tid / 64) & a.slot_mask),
-                  (unsigned long long)(long long)net);
+    if (lane == 0 && net != 0)
+        atomicAdd(a.slots + (b & a.slot_mask), (unsigned long long)(long long)net);
 }
 
-template <int TPB, int K, int NTX, bool ACC>
-__global__ __launch_bounds__(TPB) void kpz_sweep_kernel(const SweepArgs a)
+// One MCS residency of every block: one wave per block, four waves per
+// work-group (one when the block count is not a multiple of four).
+// Work-groups are dealt to the 8 XCDs round-robin (group i to XCD i mod 8);
+// with xcd set, group i takes the blocks of virtual group (i mod 8) n/8 +
+// i/8, so each XCD runs one contiguous range of blocks and neighbouring
+// blocks, which share cache lines at their edges, meet in the same L2.
+template <bool ACC, bool VEC>
+__global__ __launch_bounds__(256) void kpz_sweep_kernel(const SweepArgs a, uint32_t nblocks)
 {
-    extern __shared__ uint32_t lds[];
-    // Work-groups are dealt to the 8 XCDs round-robin (group i to XCD i mod
-    // 8); with xcd set, group i takes block (i mod 8) n/8 + i/8, so each XCD
-    // runs one contiguous range of blocks and neighbouring blocks, which
-    // share cache lines at their edges, meet in the same L2.
-    uint32_t b = blockIdx.x;
-    if (a.xcd) b = (b & 7u) * (gridDim.x >> 3) + (b >> 3);
-    sweep_block<TPB, K, NTX, ACC>(a, b, lds);
+    uint32_t g = blockIdx.x;
+    if (a.xcd) g = (g & 7u) * (gridDim.x >> 3) + (g >> 3);
+    const uint32_t b = g * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (b >= nblocks) return;
+    sweep_block<ACC, false, VEC>(a, __builtin_amdgcn_readfirstlane(b));
 }
 
 // Straddling word j = gy * nbx + bx of MCS a.t: the word at the left edge of
@@ -682,9 +539,7 @@ __global__ void kpz_merge_kernel(const SweepArgs a)
 // same draws as under dead borders but has no dead sites: an update at its
 // left column or bottom row flips a slope stored in the idle block to the
 // left or below.  Blocks of one set touch disjoint words (for Bx >= 16), so
-// every launch updates the lattice in place with no merge.  The block runs
-// in the SWAR kernel above (sweep_block with DT), the left and lower
-// neighbours' slopes as halos.
+// every launch updates the lattice in place with no merge.
 
 constexpr uint32_t TAG_DTORDER = 13;
 
@@ -712,19 +567,20 @@ __device__ __forceinline__ uint32_t dt_set(uint32_t t, uint32_t seed_lo, uint32_
     return c;
 }
 
-// The same schedule with the SWAR block kernel: one launch per block set; the
-// blocks of set c are (2 i + (c & 1), 2 j + (c >> 1)).  LDS: the block's four
-// cell planes plus the halo column (2 H words) and row (2 ntx words).
-template <int TPB, int K, int NTX, bool ACC>
-__global__ __launch_bounds__(TPB) void kpz_dt_swar_kernel(const SweepArgs a, uint32_t phase)
+// One launch per block set; the blocks of set c are (2 i + (c & 1), 2 j +
+// (c >> 1)), one wave each.
+template <bool ACC, bool VEC>
+__global__ __launch_bounds__(256) void kpz_dt_kernel(const SweepArgs a, uint32_t phase,
+                                                     uint32_t nset)
 {
-    extern __shared__ uint32_t lds[];
     uint32_t g = blockIdx.x;
     if ((gridDim.x & 7u) == 0) g = (g & 7u) * (gridDim.x >> 3) + (g >> 3);
+    const uint32_t w = g * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (w >= nset) return;
     const uint32_t c = dt_set(a.t, a.seed_lo, a.seed_hi, phase);
     const uint32_t hx = a.nbx >> 1;
-    const uint32_t bx = 2 * (g % hx) + (c & 1u), by = 2 * (g / hx) + (c >> 1);
-    sweep_block<TPB, K, NTX, ACC, true>(a, by * a.nbx + bx, lds);
+    const uint32_t bx = 2 * (w % hx) + (c & 1u), by = 2 * (w / hx) + (c >> 1);
+    sweep_block<ACC, true, VEC>(a, __builtin_amdgcn_readfirstlane(by * a.nbx + bx));
 }
 
 
@@ -1337,19 +1193,19 @@ __device__ __forceinline__ void member_launch_args(SweepArgs &a, uint32_t k, uin
 }
 
 // One round of the ensemble: every block of members [0, nmem) runs MCS
-// t_r + k (t_r = the member's t at the start of the call).  Block g of the
-// grid is block g - bprefix[r] of member r (bprefix = prefix sums of the
-// members' block counts).
-template <int TPB, int K, int NTX>
-__global__ __launch_bounds__(TPB) void kpz_batch_round_kernel(const SweepArgs *members,
+// t_r + k (t_r = the member's t at the start of the call), one wave per
+// block.  Wave g of the grid is block g - bprefix[r] of member r (bprefix =
+// prefix sums of the members' block counts); each member has its own block
+// shape.
+__global__ __launch_bounds__(256) void kpz_batch_round_kernel(const SweepArgs *members,
                                                               const uint32_t *bprefix,
                                                               uint32_t nmem, uint32_t k,
                                                               uint32_t res)
 {
-    extern __shared__ uint32_t lds[];
-    // XCD-aware order (the grid is padded to a multiple of 8): group i takes
-    // block (i mod 8) n/8 + i/8 of the concatenated members
-    const uint32_t g = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    // XCD-aware order (the grid is padded to a multiple of 8 work-groups):
+    // group i takes the waves of virtual group (i mod 8) n/8 + i/8
+    const uint32_t wg = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    const uint32_t g = __builtin_amdgcn_readfirstlane(wg * 4u + (threadIdx.x >> 6));
     if (g >= bprefix[nmem]) return;
     uint32_t lo = 0, hi = nmem;
     while (hi - lo > 1) {
@@ -1361,8 +1217,13 @@ __global__ __launch_bounds__(TPB) void kpz_batch_round_kernel(const SweepArgs *m
     SweepArgs a = members[r];
     member_launch_args(a, k, res);
     const uint32_t b = g - bprefix[r];
-    if (a.acc) sweep_block<TPB, K, NTX, true>(a, b, lds);
-    else sweep_block<TPB, K, NTX, false>(a, b, lds);
+    if (a.W % 4 == 0) {
+        if (a.acc) sweep_block<true, false, true>(a, b);
+        else sweep_block<false, false, true>(a, b);
+    } else {
+        if (a.acc) sweep_block<true, false, false>(a, b);
+        else sweep_block<false, false, false>(a, b);
+    }
 }
 
 // Straddling words of members [0, nmem) after round (k, res); sprefix =
@@ -1576,13 +1437,19 @@ kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
     const int tx = p->tile_x ? p->tile_x : TILE, ty = p->tile_y ? p->tile_y : TILE;
     if (tx != TILE || ty != TILE) return KPZ_EINVAL;
     const int64_t L = p->L;
-    // default: the largest power of two <= 256 that divides L (L % 16 == 0)
-    int64_t dflt = 256;
-    while (L % dflt) dflt >>= 1;
-    const int64_t bx = p->block_x ? p->block_x : dflt;
-    const int64_t by = p->block_y ? p->block_y : dflt;
+    // default: Bx the largest power of two <= 128 dividing L, By the largest
+    // <= 256 (one wave of 64 tile rows per block where L allows)
+    int64_t dx = 128, dy = 256;
+    while (L % dx) dx >>= 1;
+    while (L % dy) dy >>= 1;
+    const int64_t bx = p->block_x ? p->block_x : dx;
+    const int64_t by = p->block_y ? p->block_y : dy;
     if (!is_pow2(bx) || !is_pow2(by)) return KPZ_EINVAL;
-    if (bx < 16 || by < 16 || bx > 1024 || bx * by > 65536) return KPZ_EINVAL;
+    // one wave per block: Bx >= 16 (whole words), row groups of 128 sites,
+    // at most 64 lanes of (row group, tile row)
+    if (bx < 16 || by < TILE || bx > 512) return KPZ_EINVAL;
+    const int64_t lanes = (bx > GROUP_SITES ? bx / GROUP_SITES : 1) * (by / TILE);
+    if (lanes > 64) return KPZ_EINVAL;
     if (L % bx || L % by) return KPZ_EINVAL;
     if (p->flags & KPZ_FLAG_DEVICE_DT) {
         // four block sets need an even number of blocks along both axes
@@ -1635,92 +1502,66 @@ Rot sim_rot(const kpz_sim *s)
                (uint32_t)(s->prm.seed >> 32)};
 }
 
-template <int TPB, int K, int NTX, bool ACC>
-hipError_t launch_sweep_k(const SweepArgs &a, uint32_t nblocks, size_t shmem, hipStream_t st)
+// Block shape fields of the sweep arguments (shape validated by resolve).
+void set_shape(SweepArgs &a, uint32_t L, uint32_t Bx, uint32_t By)
 {
-    hipLaunchKernelGGL((kpz_sweep_kernel<TPB, K, NTX, ACC>), dim3(nblocks), dim3(TPB), shmem, st, a);
+    a.L = L;
+    a.W = L / 16;
+    a.Bx = Bx;
+    a.By = By;
+    a.nbx = L / Bx;
+    a.nby = L / By;
+    a.nw = Bx / 16;
+    a.nqx = Bx > GROUP_SITES ? Bx / GROUP_SITES : 1u;
+    a.ntg = (Bx > GROUP_SITES ? GROUP_SITES : Bx) / TILE;
+    a.nwg = a.ntg / 4;
+    a.nty = By / TILE;
+    a.log2nty = (uint32_t)ilog2(a.nty);
+}
+
+// Waves (blocks) per work-group: four when the block count allows;
+// KPZ_WAVES_PER_GROUP=1 selects one.  The launch shape changes no result.
+uint32_t waves_per_group(uint32_t nblocks)
+{
+    if (const char *env = getenv("KPZ_WAVES_PER_GROUP"))
+        if (atoi(env) == 1) return 1u;
+    return nblocks % 4 == 0 ? 4u : 1u;
+}
+
+// One wave per block.
+template <bool ACC, bool VEC>
+hipError_t launch_sweep_v(const SweepArgs &a, uint32_t nblocks, hipStream_t st)
+{
+    const uint32_t wpg = waves_per_group(nblocks);
+    const uint32_t grid = nblocks / wpg;
+    SweepArgs b = a;
+    b.xcd = (grid % 8u) == 0 ? a.xcd : 0u;
+    hipLaunchKernelGGL((kpz_sweep_kernel<ACC, VEC>), dim3(grid), dim3(64 * wpg), 0, st, b,
+                       nblocks);
     return hipGetLastError();
 }
 
-// Shape-specialised kernels for the tile-column counts of the common block
-// widths (256, 512, 1024 sites); every other width runs the runtime-width
-// kernel (NTX = 0).
-template <int TPB, int K, bool ACC>
-hipError_t launch_sweep_ntx(const SweepArgs &a, uint32_t nblocks, size_t shmem, hipStream_t st)
+template <bool ACC>
+hipError_t launch_sweep(const SweepArgs &a, uint32_t nblocks, hipStream_t st)
 {
-    switch (a.ntx) {
-    case 64: return launch_sweep_k<TPB, K, 64, ACC>(a, nblocks, shmem, st);
-    case 128: return launch_sweep_k<TPB, K, 128, ACC>(a, nblocks, shmem, st);
-    case 256: return launch_sweep_k<TPB, K, 256, ACC>(a, nblocks, shmem, st);
-    default: return launch_sweep_k<TPB, K, 0, ACC>(a, nblocks, shmem, st);
-    }
+    return (a.W % 4 == 0) ? launch_sweep_v<ACC, true>(a, nblocks, st)
+                          : launch_sweep_v<ACC, false>(a, nblocks, st);
 }
 
-template <int TPB, int K, int NTX, bool ACC>
-hipError_t launch_dt_k(const SweepArgs &a, uint32_t phase, uint32_t nblocks, size_t shmem,
-                       hipStream_t st)
+template <bool ACC, bool VEC>
+hipError_t launch_dt_v(const SweepArgs &a, uint32_t phase, uint32_t nset, hipStream_t st)
 {
-    hipLaunchKernelGGL((kpz_dt_swar_kernel<TPB, K, NTX, ACC>), dim3(nblocks), dim3(TPB), shmem, st,
-                       a, phase);
+    const uint32_t wpg = waves_per_group(nset);
+    hipLaunchKernelGGL((kpz_dt_kernel<ACC, VEC>), dim3(nset / wpg), dim3(64 * wpg), 0, st, a,
+                       phase, nset);
     return hipGetLastError();
 }
 
-template <int TPB, int K, bool ACC>
-hipError_t launch_dt_ntx(const SweepArgs &a, uint32_t phase, uint32_t nblocks, size_t shmem,
-                         hipStream_t st)
-{
-    switch (a.ntx) {
-    case 64: return launch_dt_k<TPB, K, 64, ACC>(a, phase, nblocks, shmem, st);
-    case 128: return launch_dt_k<TPB, K, 128, ACC>(a, phase, nblocks, shmem, st);
-    case 256: return launch_dt_k<TPB, K, 256, ACC>(a, phase, nblocks, shmem, st);
-    default: return launch_dt_k<TPB, K, 0, ACC>(a, phase, nblocks, shmem, st);
-    }
-}
-
 template <bool ACC>
-hipError_t launch_dt(const SweepArgs &a, uint32_t phase, uint32_t tpb, uint32_t K,
-                     uint32_t nblocks, size_t shmem, hipStream_t st)
+hipError_t launch_dt(const SweepArgs &a, uint32_t phase, uint32_t nset, hipStream_t st)
 {
-    if (tpb == 256) {
-        switch (K) {
-        case 1: return launch_dt_ntx<256, 1, ACC>(a, phase, nblocks, shmem, st);
-        case 2: return launch_dt_ntx<256, 2, ACC>(a, phase, nblocks, shmem, st);
-        case 4: return launch_dt_ntx<256, 4, ACC>(a, phase, nblocks, shmem, st);
-        default: return hipErrorInvalidValue;
-        }
-    }
-    switch (K) {
-    case 1: return launch_dt_ntx<64, 1, ACC>(a, phase, nblocks, shmem, st);
-    case 2: return launch_dt_ntx<64, 2, ACC>(a, phase, nblocks, shmem, st);
-    case 4: return launch_dt_ntx<64, 4, ACC>(a, phase, nblocks, shmem, st);
-    case 8: return launch_dt_ntx<64, 8, ACC>(a, phase, nblocks, shmem, st);
-    case 16: return launch_dt_ntx<64, 16, ACC>(a, phase, nblocks, shmem, st);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-// tpb threads per block, K = nq / tpb quads per thread (K = 1 with idle
-// lanes for blocks of fewer than 64 quads).
-template <bool ACC>
-hipError_t launch_sweep(const SweepArgs &a, uint32_t tpb, uint32_t K, uint32_t nblocks,
-                        size_t shmem, hipStream_t st)
-{
-    if (tpb == 256) {
-        switch (K) {
-        case 1: return launch_sweep_ntx<256, 1, ACC>(a, nblocks, shmem, st);
-        case 2: return launch_sweep_ntx<256, 2, ACC>(a, nblocks, shmem, st);
-        case 4: return launch_sweep_ntx<256, 4, ACC>(a, nblocks, shmem, st);
-        default: return hipErrorInvalidValue;
-        }
-    }
-    switch (K) {
-    case 1: return launch_sweep_ntx<64, 1, ACC>(a, nblocks, shmem, st);
-    case 2: return launch_sweep_ntx<64, 2, ACC>(a, nblocks, shmem, st);
-    case 4: return launch_sweep_ntx<64, 4, ACC>(a, nblocks, shmem, st);
-    case 8: return launch_sweep_ntx<64, 8, ACC>(a, nblocks, shmem, st);
-    case 16: return launch_sweep_ntx<64, 16, ACC>(a, nblocks, shmem, st);
-    default: return hipErrorInvalidValue;
-    }
+    return (a.W % 4 == 0) ? launch_dt_v<ACC, true>(a, phase, nset, st)
+                          : launch_dt_v<ACC, false>(a, phase, nset, st);
 }
 
 }  // namespace
@@ -1735,7 +1576,7 @@ constexpr int BATCH_SLOTS = 64;   // flip-counter slots per member
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct BatchLayout {
-    uint32_t Bx, By;
+    std::vector<uint32_t> Bx, By;   // block shape of each member
     uint32_t moves;                 // origin moves per MCS, common to all members
     bool db;                        // two-buffer members (every L <= 65536)
     uint32_t maxW;                  // longest row (words)
@@ -1751,27 +1592,15 @@ struct BatchLayout {
 kpz_status batch_layout(const kpz_params *m, int32_t n, BatchLayout *lay)
 {
     if (!m || n < 1) return KPZ_EINVAL;
-    int64_t Lmin = INT64_MAX;
-    for (int32_t r = 0; r < n; ++r) Lmin = m[r].L < Lmin ? m[r].L : Lmin;
-    if (Lmin < 16 || Lmin % 16) return KPZ_EINVAL;
-    int64_t dflt = 256;
-    while (Lmin % dflt) dflt >>= 1;
-    int64_t bx = -1, by = -1;
     for (int32_t r = 0; r < n; ++r)
         if (moves_of(&m[r]) != moves_of(&m[0])) return KPZ_EINVAL;
     lay->moves = moves_of(&m[0]);
+    lay->Bx.resize(n);
+    lay->By.resize(n);
     for (int32_t r = 0; r < n; ++r) {
-        kpz_params q = m[r];
-        if (!q.block_x) q.block_x = (int32_t)dflt;
-        if (!q.block_y) q.block_y = (int32_t)dflt;
-        uint32_t rbx, rby;
-        const kpz_status st = resolve(&q, &rbx, &rby);
+        const kpz_status st = resolve(&m[r], &lay->Bx[r], &lay->By[r]);
         if (st != KPZ_OK) return st;
-        if (bx < 0) { bx = rbx; by = rby; }
-        if ((int64_t)rbx != bx || (int64_t)rby != by) return KPZ_EINVAL;
     }
-    lay->Bx = (uint32_t)bx;
-    lay->By = (uint32_t)by;
     lay->word_off.resize(n);
     size_t w = 0;
     for (int32_t r = 0; r < n; ++r) {
@@ -1802,7 +1631,7 @@ kpz_status batch_layout(const kpz_params *m, int32_t n, BatchLayout *lay)
         const size_t L = (size_t)m[r].L;
         lay->off_rowA[r] = o; o = align256(o + 8 * L);
         lay->off_rowB[r] = o; o = align256(o + 8 * L);
-        lay->off_side[r] = o; o = align256(o + 4 * 2 * L * (L / lay->Bx));
+        lay->off_side[r] = o; o = align256(o + 4 * 2 * L * (L / lay->Bx[r]));
     }
     lay->off_alt.assign(n, 0);
     if (lay->db)
@@ -1814,74 +1643,19 @@ kpz_status batch_layout(const kpz_params *m, int32_t n, BatchLayout *lay)
     return KPZ_OK;
 }
 
-// Kernel shape shared by every member of an ensemble or pool.
-struct RoundShape {
-    uint32_t tpb, K, ntx;
-    size_t shmem;
-};
-
-bool round_shape(uint32_t Bx, uint32_t By, RoundShape *rs)
-{
-    rs->ntx = Bx / TILE;
-    const uint32_t nq = rs->ntx * (By / 16);
-    rs->tpb = nq >= 256 ? 256u : 64u;
-    rs->K = nq <= rs->tpb ? 1u : nq / rs->tpb;
-    rs->shmem = sizeof(uint32_t) * 4 * (size_t)nq;
-    return (rs->tpb == 256 && rs->K <= 4) || (rs->tpb == 64 && rs->K <= 2);
-}
-
-// The ensemble's round kernel is specialised for the tile-column counts of
-// block widths 64 to 1024 (the autotuner's candidates); others run the
-// runtime-width kernel.
-template <int TPB, int K>
-void round_launch_k(const RoundShape &rs, uint32_t grid, hipStream_t st, const SweepArgs *members,
-                    const uint32_t *bprefix, uint32_t nmem, uint32_t k, uint32_t res)
-{
-    switch (rs.ntx) {
-    case 16:
-        hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 16>), dim3(grid), dim3(TPB), rs.shmem,
-                           st, members, bprefix, nmem, k, res);
-        break;
-    case 32:
-        hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 32>), dim3(grid), dim3(TPB), rs.shmem,
-                           st, members, bprefix, nmem, k, res);
-        break;
-    case 64:
-        hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 64>), dim3(grid), dim3(TPB), rs.shmem,
-                           st, members, bprefix, nmem, k, res);
-        break;
-    case 128:
-        hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 128>), dim3(grid), dim3(TPB), rs.shmem,
-                           st, members, bprefix, nmem, k, res);
-        break;
-    case 256:
-        hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 256>), dim3(grid), dim3(TPB), rs.shmem,
-                           st, members, bprefix, nmem, k, res);
-        break;
-    default:
-        hipLaunchKernelGGL((kpz_batch_round_kernel<TPB, K, 0>), dim3(grid), dim3(TPB), rs.shmem,
-                           st, members, bprefix, nmem, k, res);
-        break;
-    }
-}
-
 // One round (residency res of MCS k of the call) of members [0, nmem) plus
-// the merge of their straddling words.  grid = bprefix[nmem], mwords =
+// the merge of their straddling words.  nblocks = bprefix[nmem], mwords =
 // sprefix[nmem].
-hipError_t round_launch(const RoundShape &rs, uint32_t nblocks, uint64_t mwords, hipStream_t st,
+hipError_t round_launch(uint32_t nblocks, uint64_t mwords, hipStream_t st,
                         const SweepArgs *members, const uint32_t *bprefix,
                         const unsigned long long *sprefix, uint32_t nmem, uint32_t k,
                         uint32_t res, bool merge)
 {
-    const uint32_t grid = (nblocks + 7u) & ~7u;   // the kernel's XCD map needs a multiple of 8
-    if (rs.tpb == 256) {
-        if (rs.K == 1) round_launch_k<256, 1>(rs, grid, st, members, bprefix, nmem, k, res);
-        else if (rs.K == 2) round_launch_k<256, 2>(rs, grid, st, members, bprefix, nmem, k, res);
-        else round_launch_k<256, 4>(rs, grid, st, members, bprefix, nmem, k, res);
-    } else {
-        if (rs.K == 1) round_launch_k<64, 1>(rs, grid, st, members, bprefix, nmem, k, res);
-        else round_launch_k<64, 2>(rs, grid, st, members, bprefix, nmem, k, res);
-    }
+    // four waves (blocks) per work-group; the kernel's XCD map needs a
+    // multiple of 8 work-groups
+    const uint32_t grid = (((nblocks + 3u) / 4u) + 7u) & ~7u;
+    hipLaunchKernelGGL(kpz_batch_round_kernel, dim3(grid), dim3(256), 0, st, members, bprefix,
+                       nmem, k, res);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !merge) return e;
     const uint32_t mgrid = (uint32_t)((mwords + 255) / 256 < 8192 ? (mwords + 255) / 256 : 8192);
@@ -1900,7 +1674,6 @@ struct kpz_batch {
     uint8_t *ws;
     hipStream_t stream;
     int64_t t;
-    RoundShape rs;
     uint32_t per_round;
     uint64_t merge_words;
     uint32_t total_rows, total_row_tasks;
@@ -1926,7 +1699,7 @@ kpz_status batch_sweep_on(kpz_batch *b, int32_t n_mcs, hipStream_t st)
     const unsigned long long *sp = (const unsigned long long *)(b->ws + b->lay.off_sprefix);
     for (int32_t k = 0; k < n_mcs; ++k)
         for (uint32_t r = 0; r < b->lay.moves; ++r) {
-            const hipError_t e = round_launch(b->rs, b->per_round, b->merge_words, st,
+            const hipError_t e = round_launch(b->per_round, b->merge_words, st,
                                               batch_members(b), bp, sp, (uint32_t)b->n,
                                               (uint32_t)k, r, !b->lay.db);
             if (e != hipSuccess) return batch_fail(b, e, "kpz_batch_sweep launch");
@@ -2042,8 +1815,7 @@ struct kpz_pool {
     uint8_t *arena;
     size_t arena_bytes;
     int32_t max_jobs, max_quantum;
-    uint32_t Bx, By;
-    RoundShape rs;
+    uint32_t Bx, By;                      // block shape of every job; 0: each job's default
     hipStream_t stream;
     PoolCtl ctl;
     std::map<size_t, size_t> free_list;   // offset -> bytes (heap part of the arena)
@@ -2109,20 +1881,7 @@ SweepArgs pool_args(const kpz_pool *p, const PoolJob &j)
     a.xcd = 0;
     a.side = nullptr;
     a.slots = (unsigned long long *)(p->arena + j.off_slots);
-    a.L = L;
-    a.W = L / 16;
-    a.Bx = p->Bx;
-    a.By = p->By;
-    a.nbx = L / p->Bx;
-    a.nby = L / p->By;
-    a.ntx = p->Bx / TILE;
-    a.log2ntx = (uint32_t)ilog2(a.ntx);
-    a.H = p->By / 16;
-    a.log2H = (uint32_t)ilog2(a.H);
-    a.nq = a.ntx * a.H;
-    a.nw = p->Bx / 16;
-    a.log2nw = (uint32_t)ilog2(a.nw);
-    a.units = a.nw * a.H * 2;
+    set_shape(a, L, (uint32_t)j.prm.block_x, (uint32_t)j.prm.block_y);
     a.seed_lo = (uint32_t)j.prm.seed;
     a.seed_hi = (uint32_t)(j.prm.seed >> 32);
     a.t = (uint32_t)j.t;
@@ -2252,25 +2011,13 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     SweepArgs a;
     a.words = s->words;
     a.src = s->words;
+    a.alt = nullptr;
+    a.cur0 = 0;
     a.db = 0;
     a.prev_valid = a.prev_t = a.prev_res = 0;
-    a.xcd = 0;
     a.side = ws_side(s);
     a.slots = (unsigned long long *)ws_slots(s);
-    a.L = L;
-    a.W = L / 16;
-    a.Bx = s->Bx;
-    a.By = s->By;
-    a.nbx = L / s->Bx;
-    a.nby = L / s->By;
-    a.ntx = s->Bx / TILE;
-    a.log2ntx = (uint32_t)ilog2(a.ntx);
-    a.H = s->By / 16;
-    a.log2H = (uint32_t)ilog2(a.H);
-    a.nq = a.ntx * a.H;
-    a.nw = s->Bx / 16;
-    a.log2nw = (uint32_t)ilog2(a.nw);
-    a.units = a.nw * a.H * 2;
+    set_shape(a, L, s->Bx, s->By);
     a.seed_lo = (uint32_t)s->prm.seed;
     a.seed_hi = (uint32_t)(s->prm.seed >> 32);
     a.P = s->P;
@@ -2279,30 +2026,20 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     a.acc = !(s->P == (1ull << 32) && s->Q == 0);
     const uint32_t moves = moves_of(&s->prm);
     a.nsteps = 16u / moves;
-    // threads per block: four waves when the block has at least 256 quads
-    // (fewer registers per lane, more waves to hide LDS and HBM latency);
-    // KPZ_THREADS_PER_BLOCK=64 selects one wave per block.  The launch shape
-    // does not change any result.
-    uint32_t tpb = a.nq >= 256 ? 256u : 64u;
-    if (const char *env = getenv("KPZ_THREADS_PER_BLOCK"))
-        if (atoi(env) == 64) tpb = 64u;
-    const uint32_t K = a.nq <= tpb ? 1u : a.nq / tpb;
     const uint32_t nblocks = a.nbx * a.nby;
-    const size_t shmem = sizeof(uint32_t) * 4 * (size_t)a.nq;
     const uint64_t nstraddle = (uint64_t)L * a.nbx;
     const uint32_t mgrid = (uint32_t)((nstraddle + 255) / 256 < 8192 ? (nstraddle + 255) / 256 : 8192);
-    a.xcd = (nblocks % 8u) == 0;
+    a.xcd = 1;
     if (s->dt) {
         // double tiling at the device layer: four launches per MCS, one per
         // block set in the order drawn for the MCS, in place
-        const uint32_t grid = a.nbx * a.nby / 4;
-        const size_t dshmem = shmem + sizeof(uint32_t) * (2 * (size_t)a.H + 2 * (size_t)a.ntx);
+        const uint32_t nset = nblocks / 4;
         a.res = 0;
         for (int32_t m = 0; m < n_mcs; ++m) {
             a.t = (uint32_t)(s->t + m);
             for (uint32_t ph = 0; ph < 4; ++ph) {
-                const hipError_t e = a.acc ? launch_dt<true>(a, ph, tpb, K, grid, dshmem, s->stream)
-                                           : launch_dt<false>(a, ph, tpb, K, grid, dshmem, s->stream);
+                const hipError_t e = a.acc ? launch_dt<true>(a, ph, nset, s->stream)
+                                           : launch_dt<false>(a, ph, nset, s->stream);
                 if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep launch");
             }
         }
@@ -2322,8 +2059,8 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
                 a.prev_t = s->rot_t;
                 a.prev_res = s->rot_res;
             }
-            hipError_t e = a.acc ? launch_sweep<true>(a, tpb, K, nblocks, shmem, s->stream)
-                                 : launch_sweep<false>(a, tpb, K, nblocks, shmem, s->stream);
+            hipError_t e = a.acc ? launch_sweep<true>(a, nblocks, s->stream)
+                                 : launch_sweep<false>(a, nblocks, s->stream);
             if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep launch");
             if (s->db) {
                 s->cur ^= 1;
@@ -2522,7 +2259,6 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
     b->stream = (hipStream_t)stream;
     b->t = 0;
     b->err[0] = 0;
-    if (!round_shape(lay.Bx, lay.By, &b->rs)) { delete b; return KPZ_EINVAL; }
 
     std::vector<SweepArgs> args(n);
     std::vector<MemberRows> rows(n);
@@ -2541,20 +2277,7 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
         a.cur0 = 0;
         a.side = (uint32_t *)(b->ws + lay.off_side[r]);
         a.slots = (unsigned long long *)(slots + (size_t)BATCH_SLOTS * r);
-        a.L = L;
-        a.W = L / 16;
-        a.Bx = lay.Bx;
-        a.By = lay.By;
-        a.nbx = L / lay.Bx;
-        a.nby = L / lay.By;
-        a.ntx = lay.Bx / TILE;
-        a.log2ntx = (uint32_t)ilog2(a.ntx);
-        a.H = lay.By / 16;
-        a.log2H = (uint32_t)ilog2(a.H);
-        a.nq = a.ntx * a.H;
-        a.nw = lay.Bx / 16;
-        a.log2nw = (uint32_t)ilog2(a.nw);
-        a.units = a.nw * a.H * 2;
+        set_shape(a, L, lay.Bx[r], lay.By[r]);
         a.seed_lo = (uint32_t)p.seed;
         a.seed_hi = (uint32_t)(p.seed >> 32);
         a.t = 0;
@@ -2571,7 +2294,7 @@ kpz_status kpz_batch_init(kpz_batch **out, const kpz_params *members, int32_t n,
         rows[r].L = L;
         rows[r].W = L / 16;
         rows[r].state = (const SweepArgs *)(b->ws + lay.off_members) + r;
-        rows[r].rot = Rot{0u, 0u, 0u, lay.Bx, 0u, 0u};
+        rows[r].rot = Rot{0u, 0u, 0u, lay.Bx[r], 0u, 0u};
         bprefix[r + 1] = bprefix[r] + a.nbx * a.nby;
         sprefix[r + 1] = sprefix[r] + (unsigned long long)L * a.nbx;
         rprefix[r + 1] = rprefix[r] + L;
@@ -2776,8 +2499,18 @@ kpz_status kpz_pool_init(kpz_pool **out, void *d_arena, size_t arena_bytes, int3
     if (!out) return KPZ_EINVAL;
     *out = nullptr;
     if (!d_arena || ((uintptr_t)d_arena & 255) || max_jobs < 1 || max_quantum < 1) return KPZ_EINVAL;
-    if (!is_pow2(bx) || !is_pow2(by) || bx < 16 || by < 16 || bx > 1024 || (int64_t)bx * by > 65536)
-        return KPZ_EINVAL;
+    if ((bx == 0) != (by == 0)) return KPZ_EINVAL;
+    if (bx) {
+        // the shape rules of resolve() for a lattice the block fits
+        kpz_params t = {};
+        t.L = 1024;
+        while (t.L < bx || t.L < by) t.L *= 2;
+        t.p = 1.0;
+        t.block_x = bx;
+        t.block_y = by;
+        uint32_t rbx, rby;
+        if (resolve(&t, &rbx, &rby) != KPZ_OK) return KPZ_EINVAL;
+    }
     const PoolCtl ctl = pool_ctl_layout(max_jobs);
     if (arena_bytes < ctl.bytes) return KPZ_ESIZE;
     kpz_pool *p = new (std::nothrow) kpz_pool();
@@ -2792,10 +2525,6 @@ kpz_status kpz_pool_init(kpz_pool **out, void *d_arena, size_t arena_bytes, int3
     p->ctl = ctl;
     p->next_id = 0;
     p->err[0] = 0;
-    if (!round_shape(p->Bx, p->By, &p->rs)) {
-        delete p;
-        return KPZ_EINVAL;
-    }
     if (arena_bytes > ctl.bytes) p->free_list[ctl.bytes] = arena_bytes - ctl.bytes;
     *out = p;
     return KPZ_OK;
@@ -2806,16 +2535,20 @@ kpz_status kpz_pool_submit(kpz_pool *p, const kpz_params *job, int64_t n_mcs, in
     clear_pending_error();
     if (!p || !job || n_mcs < 1 || n_mcs > 0xFFFFFFFFll) return KPZ_EINVAL;
     kpz_params q = *job;
-    q.block_x = (int32_t)p->Bx;
-    q.block_y = (int32_t)p->By;
-    if ((job->block_x && job->block_x != (int32_t)p->Bx) ||
-        (job->block_y && job->block_y != (int32_t)p->By))
-        return KPZ_EINVAL;
+    if (p->Bx) {
+        if ((job->block_x && job->block_x != (int32_t)p->Bx) ||
+            (job->block_y && job->block_y != (int32_t)p->By))
+            return KPZ_EINVAL;
+        q.block_x = (int32_t)p->Bx;
+        q.block_y = (int32_t)p->By;
+    }
     if (moves_of(job) != 1) return KPZ_EINVAL;
     uint32_t rbx, rby;
     kpz_status st = resolve(&q, &rbx, &rby);
     if (st != KPZ_OK) return st;
-    const size_t bytes = pool_job_bytes_raw(q.L, p->Bx, p->By);
+    q.block_x = (int32_t)rbx;
+    q.block_y = (int32_t)rby;
+    const size_t bytes = pool_job_bytes_raw(q.L, rbx, rby);
     if (bytes > p->arena_bytes - p->ctl.bytes) return KPZ_EINVAL;
     if ((int32_t)p->jobs.size() >= p->max_jobs) return KPZ_ESIZE;
     size_t off;
@@ -2903,7 +2636,7 @@ kpz_status kpz_pool_step(kpz_pool *p, int32_t quantum, int32_t *n_active)
     size_t m = n;
     for (uint32_t k = 0; k < rounds[0]; ++k) {
         while (m > 0 && rounds[m - 1] <= k) --m;
-        e = round_launch(p->rs, bprefix[m], sprefix[m], p->stream, d_members, d_bprefix, d_sprefix,
+        e = round_launch(bprefix[m], sprefix[m], p->stream, d_members, d_bprefix, d_sprefix,
                          (uint32_t)m, k, 0u, false);
         if (e != hipSuccess) return pool_fail(p, e, "kpz_pool_step launch");
     }
@@ -2927,7 +2660,7 @@ kpz_status kpz_pool_step(kpz_pool *p, int32_t quantum, int32_t *n_active)
             const PoolJob &j = p->jobs[fin[f]];
             rows[f].words = (const uint32_t *)(p->arena + (j.cur ? j.off_alt : j.off_words));
             rows[f].state = nullptr;
-            rows[f].rot = Rot{j.rot_valid, j.rot_t, j.rot_res, p->Bx, (uint32_t)j.prm.seed,
+            rows[f].rot = Rot{j.rot_valid, j.rot_t, j.rot_res, (uint32_t)j.prm.block_x, (uint32_t)j.prm.seed,
                               (uint32_t)(j.prm.seed >> 32)};
             rows[f].rowA = (long long *)(p->arena + j.off_rowA);
             rows[f].rowB = (long long *)(p->arena + j.off_rowB);

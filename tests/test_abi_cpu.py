@@ -47,7 +47,8 @@ def test_status_strings(kpz):
 
 
 @pytest.mark.parametrize("L,block", [(16, None), (64, None), (4096, None), (65536, None),
-                                     (4096, (256, 64)), (48, (16, 16)), (768, (256, 256))])
+                                     (4096, (256, 64)), (48, (16, 16)), (768, (256, 128)),
+                                     (65536, (512, 64)), (65536, (128, 256)), (64, (64, 4))])
 def test_workspace_bytes_valid(kpz, L, block):
     n = kpz.workspace_bytes(kpz.make_params(L, 1.0, 0.0, 1, block))
     assert n >= 256 + 8 * 1024 + 16 * L
@@ -57,6 +58,7 @@ def test_workspace_bytes_valid(kpz, L, block):
     dict(L=8), dict(L=24), dict(L=0), dict(L=64, p=1.5), dict(L=64, q=-0.1),
     dict(L=64, block=(48, 16)), dict(L=64, block=(8, 16)), dict(L=64, block=(128, 64)),
     dict(L=2048, block=(2048, 16)), dict(L=1024, block=(512, 256)),
+    dict(L=1024, block=(256, 256)), dict(L=4096, block=(1024, 16)), dict(L=64, block=(16, 2)),
     dict(L=64, tile=(8, 8)), dict(L=96, block=(64, 32)),
     dict(L=64, moves=3), dict(L=64, moves=32), dict(L=64, moves=-1),
 ])
@@ -126,7 +128,8 @@ def test_ring_params_validation(kpz, L, block, ok):
 
 
 @pytest.mark.parametrize("L,block,ok", [(64, (16, 16), True), (256, (128, 128), True),
-                                        (512, (256, 256), True), (65536, (1024, 64), True),
+                                        (512, (128, 128), True), (65536, (512, 64), True),
+                                        (512, (256, 256), False),
                                         (48, (16, 16), False), (64, (64, 16), False),
                                         (1024, (1024, 64), False)])
 def test_device_dt_params(kpz, L, block, ok):

@@ -59,27 +59,32 @@ def test_init_and_t0_moments(gpu, oracle_lib):
 
 
 CASES = [
-    # (L, block, p, q, seed, n_mcs)
+    # (L, block, p, q, seed, n_mcs).  One wave per block: lane q*nty + ty holds
+    # row group q (32 tiles) of tile row ty.
     (16, (16, 16), 1.0, 0.0, 1, 6),          # one block, periodic in both directions, 4 lanes
     (32, (16, 16), 1.0, 0.0, 2, 6),          # dead borders, 16-wide blocks (one word per row)
     (64, (64, 64), 1.0, 0.0, 1, 8),          # one 64x64 block (the L = 64 workload shape)
     (64, (32, 16), 1.0, 0.0, 3, 8),
     (64, (16, 64), 1.0, 0.0, 4, 8),          # single block along y, dead border along x
     (64, (64, 16), 0.5, 0.5, 5, 8),          # single block along x
+    (64, (32, 4), 1.0, 0.0, 30, 8),          # one tile row per block
     (128, (64, 64), 1.0, 0.25, 6, 6),
-    (128, (128, 128), 1.0, 0.0, 7, 6),        # K = 4 quads per lane
-    (256, (256, 256), 1.0, 0.0, 8, 4),        # K = 16 (the large-lattice shape)
-    (256, (128, 128), 1.0, 0.0, 9, 4),
-    (256, (256, 64), 0.7, 0.3, 10, 4),        # K = 4, generic thresholds (ties resolved)
-    (256, (1024 // 4, 32), 0.3, 0.9, 11, 4),
-    (512, (512, 128), 1.0, 0.0, 12, 3),       # 512-wide blocks, K = 16
-    (1024, (1024, 64), 1.0, 0.5, 13, 2),      # 1024-wide blocks
+    (128, (128, 128), 1.0, 0.0, 7, 6),        # one periodic 32-tile group per lane, 32 lanes
+    (256, (128, 256), 1.0, 0.0, 8, 4),        # 64 tile rows: the large-lattice default shape
+    (256, (256, 128), 1.0, 0.0, 9, 4),        # two groups per tile row, periodic along x
+    (256, (256, 64), 0.7, 0.3, 10, 4),        # generic thresholds (ties resolved)
+    (256, (256, 32), 0.3, 0.9, 11, 4),
+    (512, (512, 64), 1.0, 0.0, 12, 3),        # four groups per tile row, one block along x
+    (1024, (512, 64), 1.0, 0.5, 13, 2),       # four groups, dead borders
+    (1024, (128, 256), 1.0, 0.0, 32, 4),      # the benchmark's shape and thresholds
+    (2048, (512, 64), 1.0, 0.0, 33, 2),
     (48, (16, 16), 1.0, 0.0, 14, 6),          # non-power-of-two L (ragged word count per row)
     (96, (32, 32), 0.5, 0.5, 15, 6),
     (192, (64, 64), 1.0, 0.0, 16, 4),
+    (320, (64, 64), 1.0, 0.3, 20, 3),         # 20 words per row: 16-byte loads, L not 2^k
     (64, (32, 32), 0.0, 0.0, 17, 3),          # frozen dynamics
     (64, (32, 32), 0.0, 1.0, 18, 5),          # desorption only
-    (256, (64, 64), 1.0, 0.999999, 19, 3),    # threshold just below 2^32: tie path
+    (256, (64, 64), 1.0, 0.999999, 19, 3),    # threshold just below 2^32: every level drawn
 ]
 
 
@@ -126,7 +131,8 @@ def test_sweep_moves_matches_oracle(gpu, oracle_lib, L, block, p, q, seed, n, mo
 
 @pytest.mark.parametrize("L,block,p,q,seed,n", [(64, (32, 16), 1.0, 0.0, 3, 6),
                                               (256, (256, 64), 0.7, 0.3, 10, 4),
-                                              (1024, (1024, 64), 1.0, 0.5, 13, 3),
+                                              (1024, (512, 64), 1.0, 0.5, 13, 3),
+                                              (1024, (128, 256), 1.0, 0.0, 32, 4),
                                               (96, (32, 32), 0.5, 0.5, 15, 5)])
 def test_in_place_mode_matches_oracle(gpu, oracle_lib, L, block, p, q, seed, n):
     """The in-place mode (shared words through the side buffer and a merge
@@ -167,11 +173,12 @@ DT_CASES = [
     (64, (16, 16), 1.0, 0.0, 41, 5),
     (128, (32, 16), 1.0, 0.25, 42, 4),
     (256, (64, 64), 0.7, 0.3, 43, 3),
-    (256, (128, 128), 1.0, 0.0, 44, 3),      # 1024 quads: four per thread
+    (256, (128, 128), 1.0, 0.0, 44, 3),
     (96, (16, 16), 0.5, 0.5, 45, 4),         # 6 x 6 blocks, L not a power of two
     (512, (128, 64), 1.0, 0.999999, 46, 2),  # tie draws
     (64, (32, 16), 0.0, 1.0, 47, 3),         # desorption only
-    (2048, (1024, 64), 1.0, 0.0, 48, 2),     # the benchmark's block shape
+    (2048, (512, 64), 1.0, 0.0, 48, 2),      # four groups per tile row
+    (2048, (128, 256), 1.0, 0.0, 51, 2),     # the benchmark's block shape
     (1024, (512, 32), 1.0, 0.5, 49, 2),
     (512, (256, 16), 0.9, 0.1, 50, 2),
 ]
@@ -236,7 +243,7 @@ def test_checkpoint_resume(gpu):
 
 
 def test_l4096_first_mcs(gpu, oracle_lib):
-    """L = 4096 (the 2^24-site workload), default 256 x 256 blocks: words after
+    """L = 4096 (the 2^24-site workload), default 128 x 256 blocks: words after
     MCS 1 and 2 for both (p, q) of that workload."""
     L = 4096
     for p, q in ((1.0, 0.0), (0.5, 0.5)):
@@ -245,7 +252,7 @@ def test_l4096_first_mcs(gpu, oracle_lib):
         st = oracle_lib.SlopeState(L)
         for t in range(2):
             sim.sweep(1)
-            st.run_dd(1, p, q, 1, block=(256, 256), tile=(4, 4))
+            st.run_dd(1, p, q, 1, block=(128, 256), tile=(4, 4))
             assert np.array_equal(sim.words_host(), oracle_lib.pack(st.sx, st.sy)), t
         assert_moments(oracle_lib, st, sim.roughness(), L)
 
@@ -268,18 +275,18 @@ def _unpack_rows(oracle_lib, rows_words, L):
 
 def test_l65536_sampled_blocks(gpu, oracle_lib):
     """The 2^32-site workload in the launch configuration the benchmark times
-    (256 x 256 blocks, 16 quads per lane): MCS 2 checked on sampled blocks,
-    including the ones that wrap around the lattice edges, against the
+    (128 x 256 blocks, p = 1, q = 0, two-buffer): MCS 2 checked on sampled
+    blocks, including the ones that wrap around the lattice edges, against the
     oracle's single-block runner; the moments must be consistent."""
     import torch
-    L, B, p, q, seed = 65536, (256, 256), 1.0, 0.0, 1
+    L, B, p, q, seed = 65536, (128, 256), 1.0, 0.0, 1
     _log("L=65536 sampled blocks")
     sim = gpu.Sim(L, p, q, seed, B)
     sim.sweep(2)
     t = 2
     origin = oracle_lib.dd_origin(seed, t, B)
-    nb = L // B[0]
-    samples = [(0, 0), (nb - 1, 0), (0, nb - 1), (nb - 1, nb - 1), (123, 77), (200, 255)]
+    nbx, nby = L // B[0], L // B[1]
+    samples = [(0, 0), (nbx - 1, 0), (0, nby - 1), (nbx - 1, nby - 1), (123, 77), (400, 200)]
     W = L // 16
     words = sim.words.view(L, W)
     sim.sync_words()   # `words` holds the state only after a sync (two-buffer mode)
@@ -303,13 +310,13 @@ def test_l65536_sampled_blocks(gpu, oracle_lib):
     assert m.W2 > 0.25
 
 
-@pytest.mark.parametrize("block,q", [((256, 256), 0.0), ((512, 128), 0.25), ((256, 64), 0.0)])
+@pytest.mark.parametrize("block,q", [((128, 256), 0.0), ((512, 64), 0.25), ((256, 64), 0.0)])
 def test_launch_shape_does_not_change_results(gpu, monkeypatch, block, q):
-    """One wave per block and four waves per block give identical lattices."""
+    """Four waves (blocks) per work-group and one give identical lattices."""
     L = 512
     runs = []
-    for tpb in ("256", "64"):
-        monkeypatch.setenv("KPZ_THREADS_PER_BLOCK", tpb)
+    for wpg in ("4", "1"):
+        monkeypatch.setenv("KPZ_WAVES_PER_GROUP", wpg)
         sim = gpu.Sim(L, 1.0, q, 5, block)
         sim.sweep(3)
         runs.append((sim.words_host().copy(), sim.roughness()))
@@ -318,7 +325,7 @@ def test_launch_shape_does_not_change_results(gpu, monkeypatch, block, q):
 
 
 @pytest.mark.parametrize("L,block,p,q,n", [(64, (64, 64), 1.0, 0.0, 20), (256, (64, 64), 1.0, 0.3, 6),
-                                           (192, (64, 64), 0.5, 0.5, 5), (1024, (256, 256), 1.0, 0.0, 3)])
+                                           (192, (64, 64), 0.5, 0.5, 5), (1024, (128, 256), 1.0, 0.0, 3)])
 def test_height_moments_exact(gpu, oracle_lib, L, block, p, q, n):
     """Fourth-order sums sum (h - h(0,0))^k equal the oracle's exact sums."""
     sim = gpu.Sim(L, p, q, 7, block)
@@ -337,10 +344,10 @@ def test_height_moments_exact(gpu, oracle_lib, L, block, p, q, n):
 
 def test_l16384_moments_and_words(gpu, oracle_lib):
     """L = 16384 (rows of 1024 words: the row pass's sixteen-words-per-lane
-    path and its DPP scan), the benchmark's 1024 x 64 blocks, two-buffer
-    (rotated) storage, q > 0: words and exact moments after 2 MCS equal the
-    oracle's (about half a minute of oracle time)."""
-    L, B, p, q, seed, n = 16384, (1024, 64), 1.0, 0.25, 21, 2
+    path and its DPP scan), 512 x 64 blocks (four row groups per tile row),
+    two-buffer (rotated) storage, q > 0: words and exact moments after 2 MCS
+    equal the oracle's (about half a minute of oracle time)."""
+    L, B, p, q, seed, n = 16384, (512, 64), 1.0, 0.25, 21, 2
     _log(f"L={L} block={B} q={q}: GPU")
     sim = gpu.Sim(L, p, q, seed, B)
     sim.sweep(n)
