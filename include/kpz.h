@@ -320,6 +320,21 @@ void kpz_pool_destroy(kpz_pool *pool);
 const char *kpz_pool_last_error(const kpz_pool *pool);
 
 /* ------------------------------------------------------------------------
+ * Calibration (for the roofline of the sweep, which is bound by vector ALU
+ * issue): enqueues n_groups work-groups of 256 threads, each thread running
+ * `iters` rounds of 24 independent 32-bit bitwise vector instructions (the
+ * sweep's mix: bit select, xor, three-input logic) written in assembly so
+ * the count is exact.  *ops_per_iter (may be NULL) = wave instructions per
+ * wave and iteration (192).  The measured rate
+ * n_groups * 4 * iters * ops_per_iter / time is the device's VALU issue
+ * ceiling for that mix.  d_out: n_groups * 256 uint32 (caller-owned device
+ * memory, written with a checksum).  KPZ_EINVAL for n_groups or iters < 1;
+ * KPZ_EHIP if the launch fails.
+ */
+kpz_status kpz_valu_probe(uint32_t *d_out, int32_t n_groups, int32_t iters,
+                          int32_t *ops_per_iter, void *stream);
+
+/* ------------------------------------------------------------------------
  * The 1+1-dimensional ring (rooftop / ASEP reduction of the model, Sec.
  * 2.1) under the same decomposition reduced to one dimension (Sec. 3 and
  * 3.1): dead-border blocks of B sites whose origin moves every MCS, tiles

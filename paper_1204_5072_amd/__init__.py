@@ -385,23 +385,23 @@ class Ensemble:
             pass
 
 
-# The job pool's default block shape: 128 x 64 serves a mix of L = 2^8 ..
-# 2^13 at 1.45e12 attempts/s on MI355X, 256 x 256 at 1.21e12 (more, smaller
-# work-groups balance the mixed grids better).
-POOL_BLOCK: Tuple[int, int] = (128, 64)
+# The job pool's block shape: None gives every job the library's default
+# shape for its own L (one full wave of 64 lanes per block from L = 256 up).
+POOL_BLOCK: Optional[Tuple[int, int]] = None
 
 
 class Pool:
     """Continuous-batching job pool over a device arena of ``hbm_bytes``
     (the HBM budget).  submit() returns a job id, or None when the job does
     not fit right now; step() advances every resident job; poll() returns
-    finished jobs' exact moments.  Every job runs with the pool's block
-    shape (L must be a multiple of both sides)."""
+    finished jobs' exact moments.  With ``block`` set every job runs that
+    block shape (L must be a multiple of both sides); with None each job runs
+    the default shape for its L."""
 
     def __init__(self, hbm_bytes: int, max_jobs: int = 1024, max_quantum: int = 256,
-                 block: Tuple[int, int] = POOL_BLOCK, device="cuda", stream=None):
+                 block: Optional[Tuple[int, int]] = POOL_BLOCK, device="cuda", stream=None):
         import torch
-        self.block = tuple(block)
+        self.block = tuple(block) if block else (0, 0)
         self.max_quantum = max_quantum
         self.failures = []
         self.device = torch.device(device)

@@ -14,12 +14,13 @@ from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 
 from . import Ensemble, KPZError, Sim, make_params, workspace_bytes
 
-# Candidate shapes (block_x, block_y): wide blocks keep the HBM rows
-# coalesced; areas from 64x64 to 256x256 keep the dead-border fraction
-# 1/Bx + 1/By at or below about 3 %.
+# Candidate shapes (block_x, block_y): one wave per block, so the full
+# shapes hold 64 lanes of (row group of 128 sites, tile row): 128 x 256,
+# 256 x 128, 512 x 64; the half and quarter shapes keep the dead-border
+# fraction 1/Bx + 1/By at or below about 3 %.
 CANDIDATES: Tuple[Tuple[int, int], ...] = (
-    (256, 256), (512, 128), (1024, 64), (256, 128), (512, 64), (128, 128), (1024, 32),
-    (256, 64), (128, 64), (64, 64),
+    (128, 256), (256, 128), (512, 64), (128, 128), (256, 64), (512, 32), (64, 256),
+    (128, 64), (64, 64),
 )
 
 
@@ -36,17 +37,21 @@ def valid_shapes(L: int, candidates: Iterable[Tuple[int, int]] = CANDIDATES) -> 
     return out
 
 
-def _time(fn, reps: int) -> float:
+def _time(fn, reps: int, trials: int = 3) -> float:
+    """Median over `trials` of the mean time of `reps` calls of fn (ms)."""
     import torch
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     fn()                      # warm-up (first launch of this kernel variant)
     torch.cuda.synchronize()
-    start.record()
-    for _ in range(reps):
-        fn()
-    stop.record()
-    torch.cuda.synchronize()
-    return start.elapsed_time(stop) / reps
+    out = []
+    for _ in range(trials):
+        start.record()
+        for _ in range(reps):
+            fn()
+        stop.record()
+        torch.cuda.synchronize()
+        out.append(start.elapsed_time(stop) / reps)
+    return sorted(out)[len(out) // 2]
 
 
 def tune_lattice(L: int, p: float = 1.0, q: float = 0.0, mcs: int = 2,
@@ -75,24 +80,30 @@ def tune_lattice(L: int, p: float = 1.0, q: float = 0.0, mcs: int = 2,
     return {"block": best, "ms_per_mcs": timings, "failed": failed}
 
 
-def tune_ensemble(members, mcs: int = 2,
+def tune_ensemble(members, mcs: int = 4,
                   candidates: Optional[Sequence[Tuple[int, int]]] = None) -> Dict:
-    """Fastest common block shape for an ensemble (list of kpz_params with
-    block 0); returns {"block": (bx, by), "ms_per_mcs": {shape: ms}}."""
-    Lmin = min(m.L for m in members)
-    shapes = [s for s in valid_shapes(Lmin, candidates or CANDIDATES)
-              if all(m.L % s[0] == 0 and m.L % s[1] == 0 for m in members)]
-    if not shapes:
-        raise ValueError("no common block shape for the ensemble")
-    timings = {}
-    for shape in shapes:
-        ms = [make_params(m.L, m.p, m.q, m.seed, shape) for m in members]
-        ens = Ensemble(ms)
-        timings[shape] = _time(lambda: ens.sweep(mcs), 1) / mcs
-        ens.close()
-        del ens
-    best = min(timings, key=timings.get)
-    return {"block": best, "ms_per_mcs": timings}
+    """Fastest block shape for each lattice size of an ensemble (list of
+    kpz_params with block 0): for every distinct L the members of that size
+    run as one ensemble with each candidate shape (median of three timings
+    of `mcs` MCS).  Returns {"blocks": {L: (bx, by)}, "ms_per_mcs": {L:
+    {shape: ms}}}; every member then runs the shape chosen for its L."""
+    by_L: Dict[int, list] = {}
+    for m in members:
+        by_L.setdefault(int(m.L), []).append(m)
+    blocks, timings = {}, {}
+    for L, group in sorted(by_L.items()):
+        shapes = valid_shapes(L, candidates or CANDIDATES)
+        if not shapes:
+            raise ValueError(f"no valid block shape for L={L}")
+        t = {}
+        for shape in shapes:
+            ens = Ensemble([make_params(m.L, m.p, m.q, m.seed, shape) for m in group])
+            t[shape] = _time(lambda: ens.sweep(mcs), 1) / mcs
+            ens.close()
+            del ens
+        blocks[L] = min(t, key=t.get)
+        timings[L] = t
+    return {"blocks": blocks, "ms_per_mcs": timings}
 
 
 def main(argv=None) -> None:

@@ -115,10 +115,10 @@ struct SweepArgs {
     // Two-buffer mode (db = 1): the launch reads src and writes words, a
     // different buffer.  src is stored rotated by s_in sites (word w of a row
     // holds sites 16 w + s_in ..), s_in = (x origin of launch (prev_t,
-    // prev_res)) mod 16 when prev_valid, else 0; the output is stored rotated
-    // by this launch's x origin mod 16, so every block writes whole words of
-    // its own and no word is shared.  db = 0: in place, shared words through
-    // the side buffer.
+    // prev_res)) mod 64 when prev_valid, else 0; the output is stored rotated
+    // by this launch's x origin mod 64, so every block writes whole words of
+    // its own (16-byte aligned for blocks of 64 sites or more) and no word is
+    // shared.  db = 0: in place, shared words through the side buffer.
     uint32_t db, prev_valid, prev_t, prev_res;
     uint32_t xcd;                // 1: map work-groups so that consecutive blocks share an XCD
     // ensemble members in two-buffer mode: buffer 0 is `words`, buffer 1 is
@@ -130,8 +130,10 @@ struct SweepArgs {
 };
 
 // Storage rotation of a lattice buffer written in two-buffer mode: the x
-// origin of the launch that wrote it, mod 16 (0 for a buffer in the
-// documented layout, valid = 0).
+// origin of the launch that wrote it, mod 64 (0 for a buffer in the
+// documented layout, valid = 0).  Word w of a row then holds sites 16 w + s
+// .. 16 w + s + 15 (mod L); with blocks at least 64 sites wide every block
+// starts on a 16-byte boundary of the output.
 struct Rot {
     uint32_t valid, t, res, Bx, seed_lo, seed_hi;
 };
@@ -140,7 +142,7 @@ __device__ __forceinline__ uint32_t rot_sites(const Rot &r)
 {
     if (!r.valid) return 0u;
     const U4 w = philox(r.res, 0u, r.t, TAG_ORIGIN << 24, r.seed_lo, r.seed_hi);
-    return (uint32_t)(((uint64_t)w.x * r.Bx) >> 32) & 15u;
+    return (uint32_t)(((uint64_t)w.x * r.Bx) >> 32) & 63u;
 }
 
 // Index i + d of a periodic row of W words (i < W, d <= W).
@@ -358,7 +360,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
     // the two words it shares with its neighbours go to the side buffer and
     // are merged by a separate launch.  DT: those two words are merged in
     // place (the neighbours are idle), and the halos are written back.
-    uint32_t gwo = (ox >> 4) + bx * a.nw;
+    // output word of the block's first site: storage position ox + bx Bx -
+    // (ox mod 64)
+    uint32_t gwo = 4u * (ox >> 6) + bx * a.nw;
     if (gwo >= a.W) gwo -= a.W;
     const uint32_t gwoq = wrap_add(gwo, qw, a.W);
     const bool ovec = VEC && (gwoq & 3u) == 0 && (a.nwg & 3u) == 0;
@@ -658,25 +662,25 @@ __device__ __forceinline__ int wave_incl_sum(int x)
     return x;
 }
 
-// Moments of one row, taken by a group of G lanes (G = row_lanes(W), the
-// group's lanes gl = 0..G-1 aligned to G in the wave), NV consecutive words
-// per lane and chunk (NV = 16 only for W % 1024 == 0, where G = 64 and every
-// lane is full): returns (A_y, B_y) in lane gl = 0 and, in `first`, the
-// row's first word in the documented layout.  rot2 = twice the storage
-// rotation (a row stored rotated by s sites holds sites s.. in its word 0;
-// word w of the layout is then bits of stored words w - 1 and w).  A lane's
-// local sums stay below 2^24 and heights within a row below L, so they are
+// Moments of one row in stored order, taken by a group of G lanes (G =
+// row_lanes(W), the group's lanes gl = 0..G-1 aligned to G in the wave), NV
+// consecutive words per lane and chunk (NV = 16 only for W % 1024 == 0, where
+// G = 64 and every lane is full): returns (A_y, B_y), the sums of the
+// heights relative to the row's first stored site and of their squares, in
+// lane gl = 0 and, in `first`, the row's first stored word.  A row stored
+// rotated by s sites starts at site s; the finalize pass takes column s as
+// the reference column and shifts the totals to h(0, 0).  A lane's local
+// sums stay below 2^24 and heights within a row below L, so they are
 // 32-bit; only the row totals are 64-bit.
 template <int NV>
 __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, const uint32_t *lut,
-                                            uint32_t gl, uint32_t G, uint32_t rot2, long long &A,
-                                            long long &B, uint32_t &first)
+                                            uint32_t gl, uint32_t G, long long &A, long long &B,
+                                            uint32_t &first)
 {
     static_assert(NV == 4 || NV == 16, "four or sixteen words per lane");
     const bool vec = (W & 3u) == 0;
     long long s1 = 0, s2 = 0;
     int carry = 0;
-    uint32_t carry_w = rot2 ? rp[W - 1] : 0u;   // stored word before word 0 (periodic row)
     first = 0u;
     for (uint32_t base = 0; base < W; base += NV * G) {
         const uint32_t idx = base + NV * gl;
@@ -703,18 +707,6 @@ __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, cons
                 for (int m = 0; m < 4; ++m)
                     if (idx + m < W) { v[m] = rp[idx + m]; nv = m + 1; }
             }
-        }
-        if (rot2) {
-            // the previous stored word of each lane's first word: the previous
-            // lane's last (full lanes precede any lane with words), or the
-            // carried word for the group's lane 0
-            uint32_t pv = __shfl(v[NV - 1], (gl + G - 1u) & (G - 1u), G);
-            if (gl == 0) pv = carry_w;
-            carry_w = __shfl(v[NV - 1], G - 1u, G);
-#pragma unroll
-            for (int m = NV - 1; m > 0; --m)
-                v[m] = __builtin_amdgcn_alignbit(v[m], v[m - 1], 32u - rot2);
-            v[0] = __builtin_amdgcn_alignbit(v[0], pv, 32u - rot2);
         }
         if (base == 0) first = v[0];
         // this lane's words relative to its own start
@@ -757,12 +749,11 @@ __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, cons
 // One wave per 64 / row_lanes(W) rows.
 __global__ __launch_bounds__(256) void kpz_row_moments_kernel(const uint32_t *words, uint32_t L,
                                                               uint32_t W, long long *rowA,
-                                                              long long *rowB, const Rot rot)
+                                                              long long *rowB)
 {
     __shared__ uint32_t lut[256];
     lut[threadIdx.x] = lut8_entry(threadIdx.x);
     __syncthreads();
-    const uint32_t rot2 = 2u * rot_sites(rot);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t G = row_lanes(W), R = 64u / G;
@@ -774,12 +765,12 @@ __global__ __launch_bounds__(256) void kpz_row_moments_kernel(const uint32_t *wo
             long long A, B;
             uint32_t first;
             if ((W & 1023u) == 0)
-                row_moments<16>(words + (size_t)row * W, W, lut, gl, G, rot2, A, B, first);
+                row_moments<16>(words + (size_t)row * W, W, lut, gl, G, A, B, first);
             else
-                row_moments<4>(words + (size_t)row * W, W, lut, gl, G, rot2, A, B, first);
+                row_moments<4>(words + (size_t)row * W, W, lut, gl, G, A, B, first);
             if (gl == 0) {
                 rowA[row] = A;
-                rowB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y(0, row)
+                rowB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y of the first stored site
             }
         }
     }
@@ -790,13 +781,18 @@ __global__ __launch_bounds__(256) void kpz_row_moments_kernel(const uint32_t *wo
 __global__ void kpz_rotate_kernel(const uint32_t *src, uint32_t *dst, uint32_t L, uint32_t W,
                                   const Rot rot)
 {
-    const uint32_t rot2 = 2u * rot_sites(rot);
+    const uint32_t s = rot_sites(rot);
+    const uint32_t sw = s >> 4, rot2 = 2u * (s & 15u);
     const uint64_t n = (uint64_t)L * W;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x) {
+        // layout word w: sites 16 w .. = stored positions 16 (w - sw) - s mod 16
         const uint32_t w = (uint32_t)(i % W);
-        const uint64_t pi = w ? i - 1 : i + W - 1;
-        dst[i] = rot2 ? __builtin_amdgcn_alignbit(src[i], src[pi], 32u - rot2) : src[i];
+        const uint64_t rowb = i - w;
+        const uint32_t w1 = w >= sw ? w - sw : w + W - sw;
+        const uint32_t w0 = w1 ? w1 - 1 : W - 1;
+        dst[i] = rot2 ? __builtin_amdgcn_alignbit(src[rowb + w1], src[rowb + w0], 32u - rot2)
+                      : src[rowb + w1];
     }
 }
 
@@ -814,7 +810,8 @@ __global__ void kpz_rotate_kernel(const uint32_t *src, uint32_t *dst, uint32_t L
 template <int NT>
 __device__ __forceinline__ void finalize_moments(uint32_t L, const long long *rowA,
                                                  const long long *rowB, const long long *slots,
-                                                 uint32_t nslots, long long *res)
+                                                 uint32_t nslots, long long *res,
+                                                 const uint32_t *row0, uint32_t s)
 {
     constexpr uint32_t NWV = NT / 64;
     __shared__ long long wsum[NWV];
@@ -879,8 +876,17 @@ __device__ __forceinline__ void finalize_moments(uint32_t L, const long long *ro
         __syncthreads();
     }
     if (tid == 0) {
-        const unsigned __int128 u2 = (unsigned __int128)r2s[0];
-        res[0] = r1s[0];
+        // rows stored rotated by s sites: the sums above are relative to
+        // h(s, 0); h(s, 0) - h(0, 0) = P0 = the slopes of sites 0 .. s - 1 of
+        // row 0, stored at positions L - s .. L - 1
+        long long P0 = 0;
+        for (uint32_t i = L - s; i < L; ++i)
+            P0 += 2 * (long long)((row0[i >> 4] >> (2u * (i & 15u))) & 1u) - 1;
+        const long long N = (long long)L * L;
+        const __int128 R1p = r1s[0];
+        const __int128 R2 = r2s[0] + 2 * (__int128)P0 * R1p + (__int128)N * P0 * P0;
+        const unsigned __int128 u2 = (unsigned __int128)R2;
+        res[0] = (long long)(R1p + (__int128)N * P0);
         res[1] = (long long)(uint64_t)u2;
         res[2] = (long long)(uint64_t)(u2 >> 64);
         res[3] = ns[0];
@@ -890,9 +896,10 @@ __device__ __forceinline__ void finalize_moments(uint32_t L, const long long *ro
 __global__ __launch_bounds__(1024) void kpz_finalize_kernel(uint32_t L, const long long *rowA,
                                                             const long long *rowB,
                                                             const long long *slots,
-                                                            long long *res)
+                                                            long long *res, const uint32_t *words,
+                                                            const Rot rot)
 {
-    finalize_moments<1024>(L, rowA, rowB, slots, NSLOTS, res);
+    finalize_moments<1024>(L, rowA, rowB, slots, NSLOTS, res, words, rot_sites(rot));
 }
 
 // Lattices of at most SMALL_ROWS rows: the row pass and the finalize in one
@@ -902,8 +909,7 @@ constexpr uint32_t SMALL_ROWS = 1024;
 // Row sums of a lattice of L <= SMALL_ROWS rows by the 16 waves of one
 // work-group of 1024 threads, into rA / rB (LDS); `lut` filled.
 __device__ __forceinline__ void small_rows(const uint32_t *words, uint32_t L, uint32_t W,
-                                           uint32_t rot2, const uint32_t *lut, long long *rA,
-                                           long long *rB)
+                                           const uint32_t *lut, long long *rA, long long *rB)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -915,10 +921,10 @@ __device__ __forceinline__ void small_rows(const uint32_t *words, uint32_t L, ui
         if (row < L) {   // a whole lane group is in or out
             long long A, B;
             uint32_t first;
-            row_moments<4>(words + (size_t)row * W, W, lut, gl, G, rot2, A, B, first);
+            row_moments<4>(words + (size_t)row * W, W, lut, gl, G, A, B, first);
             if (gl == 0) {
                 rA[row] = A;
-                rB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y(0, row)
+                rB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y of the first stored site
             }
         }
     }
@@ -933,9 +939,9 @@ __global__ __launch_bounds__(1024) void kpz_roughness_small_kernel(const uint32_
     __shared__ long long rA[SMALL_ROWS], rB[SMALL_ROWS];
     if (threadIdx.x < 256) lut[threadIdx.x] = lut8_entry(threadIdx.x);
     __syncthreads();
-    small_rows(words, L, W, 2u * rot_sites(rot), lut, rA, rB);
+    small_rows(words, L, W, lut, rA, rB);
     __syncthreads();
-    finalize_moments<1024>(L, rA, rB, slots, NSLOTS, res);
+    finalize_moments<1024>(L, rA, rB, slots, NSLOTS, res, words, rot_sites(rot));
 }
 
 
@@ -1133,6 +1139,56 @@ __global__ __launch_bounds__(256) void kpz_mom4_finalize_kernel(const uint32_t *
         }
 }
 
+// ------------------------------------------------------------ calibration
+//
+// VALU issue rate of the sweep's instruction mix, measured: each wave runs
+// `iters` rounds of VALU_PROBE_OPS independent 32-bit bitwise instructions
+// (v_bfi_b32, v_xor_b32, v_bitop3_b32 on eight registers, written in asm so
+// the count is exact), the only other work being the scalar loop counter.
+// Wave instructions per second = waves * iters * VALU_PROBE_OPS / time.
+
+constexpr uint32_t VALU_PROBE_OPS = 192;
+
+__global__ __launch_bounds__(256) void kpz_valu_probe_kernel(uint32_t *out, uint32_t iters)
+{
+    uint32_t a0 = threadIdx.x, a1 = a0 * 3u, a2 = a0 * 5u, a3 = a0 * 7u;
+    uint32_t a4 = a0 ^ 0x55u, a5 = a0 ^ 0xAAu, a6 = a0 + 11u, a7 = a0 + 13u;
+    const uint32_t m = 0x0F0F3355u ^ blockIdx.x;
+    for (uint32_t it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            asm volatile(
+                "v_bfi_b32 %0, %8, %0, %1\n\t"
+                "v_bfi_b32 %1, %8, %1, %2\n\t"
+                "v_bfi_b32 %2, %8, %2, %3\n\t"
+                "v_bfi_b32 %3, %8, %3, %4\n\t"
+                "v_bfi_b32 %4, %8, %4, %5\n\t"
+                "v_bfi_b32 %5, %8, %5, %6\n\t"
+                "v_bfi_b32 %6, %8, %6, %7\n\t"
+                "v_bfi_b32 %7, %8, %7, %0\n\t"
+                "v_xor_b32 %0, %0, %2\n\t"
+                "v_xor_b32 %1, %1, %3\n\t"
+                "v_xor_b32 %2, %2, %4\n\t"
+                "v_xor_b32 %3, %3, %5\n\t"
+                "v_xor_b32 %4, %4, %6\n\t"
+                "v_xor_b32 %5, %5, %7\n\t"
+                "v_xor_b32 %6, %6, %0\n\t"
+                "v_xor_b32 %7, %7, %1\n\t"
+                "v_bitop3_b32 %0, %0, %3, %8 bitop3:0x96\n\t"
+                "v_bitop3_b32 %1, %1, %4, %8 bitop3:0x96\n\t"
+                "v_bitop3_b32 %2, %2, %5, %8 bitop3:0x96\n\t"
+                "v_bitop3_b32 %3, %3, %6, %8 bitop3:0x96\n\t"
+                "v_bitop3_b32 %4, %4, %7, %8 bitop3:0x96\n\t"
+                "v_bitop3_b32 %5, %5, %0, %8 bitop3:0x96\n\t"
+                "v_bitop3_b32 %6, %6, %1, %8 bitop3:0x96\n\t"
+                "v_bitop3_b32 %7, %7, %2, %8 bitop3:0x96"
+                : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7)
+                : "v"(m));
+        }
+    }
+    out[blockIdx.x * blockDim.x + threadIdx.x] = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7;
+}
+
 // ------------------------------------------------------------ ensemble
 //
 // Many independent lattices ("members", each with its own L, p, q and seed,
@@ -1291,14 +1347,16 @@ __global__ __launch_bounds__(256) void kpz_batch_sync_kernel(const MemberRows *m
         const uint32_t row = g - rprefix[lo];
         Rot rot;
         const uint32_t *cur = member_current(m, rot);
-        const uint32_t rot2 = 2u * rot_sites(rot);
+        const uint32_t s = rot_sites(rot);
+        const uint32_t sw = s >> 4, rot2 = 2u * (s & 15u);
         const uint32_t *src = cur + (size_t)row * m.W;
         for (uint32_t w = threadIdx.x; w < m.W; w += blockDim.x) rowbuf[w] = src[w];
         __syncthreads();
         uint32_t *dst = (m.state ? m.state->words : (uint32_t *)m.words) + (size_t)row * m.W;
         for (uint32_t w = threadIdx.x; w < m.W; w += blockDim.x) {
-            const uint32_t pv = rowbuf[w ? w - 1 : m.W - 1];
-            dst[w] = rot2 ? __builtin_amdgcn_alignbit(rowbuf[w], pv, 32u - rot2) : rowbuf[w];
+            const uint32_t w1 = w >= sw ? w - sw : w + m.W - sw;
+            const uint32_t pv = rowbuf[w1 ? w1 - 1 : m.W - 1];
+            dst[w] = rot2 ? __builtin_amdgcn_alignbit(rowbuf[w1], pv, 32u - rot2) : rowbuf[w1];
         }
         __syncthreads();
     }
@@ -1341,12 +1399,12 @@ __global__ __launch_bounds__(256) void kpz_batch_rows_kernel(const MemberRows *m
             uint32_t first;
             const uint32_t *rp = cur + (size_t)row * m.W;
             if ((m.W & 1023u) == 0)
-                row_moments<16>(rp, m.W, lut, lane & (G - 1u), G, 2u * rot_sites(rot), A, B, first);
+                row_moments<16>(rp, m.W, lut, lane & (G - 1u), G, A, B, first);
             else
-                row_moments<4>(rp, m.W, lut, lane & (G - 1u), G, 2u * rot_sites(rot), A, B, first);
+                row_moments<4>(rp, m.W, lut, lane & (G - 1u), G, A, B, first);
             if ((lane & (G - 1u)) == 0) {
                 m.rowA[row] = A;
-                m.rowB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y(0, row)
+                m.rowB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y of the first stored site
             }
         }
     }
@@ -1367,9 +1425,10 @@ __global__ __launch_bounds__(1024) void kpz_batch_moments_small_kernel(const Mem
     const MemberRows m = mr[r];
     Rot rot;
     const uint32_t *cur = member_current(m, rot);
-    small_rows(cur, m.L, m.W, 2u * rot_sites(rot), lut, rA, rB);
+    small_rows(cur, m.L, m.W, lut, rA, rB);
     __syncthreads();
-    finalize_moments<1024>(m.L, rA, rB, m.slots, nslots, res + ((size_t)k * n + r) * 4);
+    finalize_moments<1024>(m.L, rA, rB, m.slots, nslots, res + ((size_t)k * n + r) * 4, cur,
+                           rot_sites(rot));
 }
 
 // One work-group per member; results of sample `k` go to res[(k n + r) 4 ..].
@@ -1379,7 +1438,10 @@ __global__ __launch_bounds__(256) void kpz_batch_finalize_kernel(const MemberRow
 {
     const uint32_t r = blockIdx.x;
     const MemberRows m = mr[r];
-    finalize_moments<256>(m.L, m.rowA, m.rowB, m.slots, nslots, res + ((size_t)k * n + r) * 4);
+    Rot rot;
+    const uint32_t *cur = member_current(m, rot);
+    finalize_moments<256>(m.L, m.rowA, m.rowB, m.slots, nslots, res + ((size_t)k * n + r) * 4, cur,
+                          rot_sites(rot));
 }
 
 }  // namespace
@@ -2093,11 +2155,11 @@ kpz_status kpz_roughness(kpz_sim *s, int64_t *S1o, int64_t *S2o, double *W2o)
         const uint32_t nt = row_tasks(L);
         const uint32_t rgrid = (nt + 3) / 4 < 4096 ? (nt + 3) / 4 : 4096;
         hipLaunchKernelGGL(kpz_row_moments_kernel, dim3(rgrid), dim3(256), 0, s->stream,
-                           s->buf[s->cur], L, W, ws_rowA(s), ws_rowB(s), sim_rot(s));
+                           s->buf[s->cur], L, W, ws_rowA(s), ws_rowB(s));
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(s, e, "kpz_roughness launch");
         hipLaunchKernelGGL(kpz_finalize_kernel, dim3(1), dim3(1024), 0, s->stream, L, ws_rowA(s),
-                           ws_rowB(s), ws_slots(s), ws_res(s));
+                           ws_rowB(s), ws_slots(s), ws_res(s), s->buf[s->cur], sim_rot(s));
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(s, e, "kpz_roughness launch");
     }
@@ -2742,5 +2804,16 @@ kpz_status kpz_pool_stats(const kpz_pool *p, int32_t *n_active, size_t *largest_
 void kpz_pool_destroy(kpz_pool *p) { delete p; }
 
 const char *kpz_pool_last_error(const kpz_pool *p) { return p ? p->err : g_init_err; }
+
+kpz_status kpz_valu_probe(uint32_t *d_out, int32_t n_groups, int32_t iters,
+                          int32_t *ops_per_iter, void *stream)
+{
+    clear_pending_error();
+    if (!d_out || n_groups < 1 || iters < 1) return KPZ_EINVAL;
+    if (ops_per_iter) *ops_per_iter = (int32_t)VALU_PROBE_OPS;
+    hipLaunchKernelGGL(kpz_valu_probe_kernel, dim3((uint32_t)n_groups), dim3(256), 0,
+                       (hipStream_t)stream, d_out, (uint32_t)iters);
+    return hipGetLastError() == hipSuccess ? KPZ_OK : KPZ_EHIP;
+}
 
 }  // extern "C"

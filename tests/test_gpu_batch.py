@@ -1,6 +1,7 @@
 """Ensemble (batched) path: every member of a multi-lattice launch
 is bit-identical to the single-lattice run with the same parameters and
-block shape (and so to the oracle), with uneven L and different p, q."""
+block shape (and so to the oracle), with uneven L, different p, q and each
+member's own block shape."""
 import numpy as np
 import pytest
 
@@ -21,7 +22,7 @@ def _mix(kpz, Ls, qs, block, seed0=1000):
     return [kpz.make_params(L, 1.0, q, seed0 + r, block) for r, (L, q) in enumerate(zip(Ls, qs))]
 
 
-@pytest.mark.parametrize("block", [(64, 64), (256, 256), (128, 64)])
+@pytest.mark.parametrize("block", [(64, 64), (128, 256), (256, 128), (128, 64)])
 def test_batch_members_equal_single_runs(gpu, oracle_lib, block):
     Ls = [256, 512, 256, 1024, 512, 256]
     qs = [0.0, 0.25, 0.5, 0.0, 0.5, 0.25]
@@ -46,9 +47,9 @@ def test_batch_run_graph_equals_stepwise(gpu):
     Ls = [256, 512, 256, 512]
     qs = [0.0, 0.25, 0.5, 0.0]
     times = [1, 2, 3, 5, 8, 13]
-    a = gpu.Ensemble(_mix(gpu, Ls, qs, (256, 256)))
+    a = gpu.Ensemble(_mix(gpu, Ls, qs, (128, 256)))
     S1a, S2a, W2a = a.run(times)
-    b = gpu.Ensemble(_mix(gpu, Ls, qs, (256, 256)))
+    b = gpu.Ensemble(_mix(gpu, Ls, qs, (128, 256)))
     t = 0
     for k, T in enumerate(times):
         b.sweep(T - t)
@@ -64,11 +65,11 @@ def test_batch_run_graph_equals_stepwise(gpu):
 
 def test_batch_mixed_sizes_sweep_single_block_members(gpu):
     """Members with L equal to the block size are one periodic block."""
-    members = _mix(gpu, [256, 2048, 256], [0.0, 0.0, 0.25], (256, 256))
+    members = _mix(gpu, [256, 2048, 256], [0.0, 0.0, 0.25], (256, 128))
     ens = gpu.Ensemble(members)
     ens.sweep(2)
     for r, m in enumerate(members):
-        sim = gpu.Sim(m.L, m.p, m.q, m.seed, (256, 256))
+        sim = gpu.Sim(m.L, m.p, m.q, m.seed, (256, 128))
         sim.sweep(2)
         assert np.array_equal(ens.member_words(r), sim.words_host()), r
 
@@ -129,3 +130,25 @@ def test_batch_in_place_equals_two_buffer(gpu):
     inp.sweep(1)
     for r in range(len(Ls)):
         assert np.array_equal(two.member_words(r), inp.member_words(r)), r
+
+
+def test_batch_members_with_own_block_shapes(gpu, oracle_lib):
+    """Each member runs its own block shape (the default for its L when 0)
+    in one launch; every member equals its single-lattice run, one equals
+    the oracle directly."""
+    shapes = [(128, 256), (512, 64), None, (64, 64), (256, 128), (32, 16)]
+    Ls = [256, 1024, 512, 128, 256, 64]
+    qs = [0.0, 0.25, 0.5, 0.0, 0.7, 0.25]
+    members = [gpu.make_params(L, 1.0, q, 60 + r, shp)
+               for r, (L, q, shp) in enumerate(zip(Ls, qs, shapes))]
+    ens = gpu.Ensemble(members)
+    ens.sweep(3)
+    S1, S2, W2 = ens.roughness()
+    for r, m in enumerate(members):
+        sim = gpu.Sim(m.L, m.p, m.q, m.seed, shapes[r])
+        sim.sweep(3)
+        assert np.array_equal(ens.member_words(r), sim.words_host()), r
+        mm = sim.roughness()
+        assert (int(S1[r]), int(S2[r]), float(W2[r])) == (mm.S1, mm.S2, mm.W2), r
+    st = oracle_lib.SlopeState(1024).run_dd(3, 1.0, 0.25, 61, block=(512, 64), tile=(4, 4))
+    assert np.array_equal(ens.member_words(1), oracle_lib.pack(st.sx, st.sy))
