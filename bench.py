@@ -2,19 +2,22 @@
 """Throughput of the KPZ octahedron sweep on one MI355X.
 
 Workload (default): L = 65536 periodic lattice (2^32 sites, 1 GiB of packed
-slopes), p = 1, q = 0, flat start, Philox seed 1, 1024 x 64 dead-border
-blocks (the autotuner's choice for this L) with 4 x 4 double tiles; W^2 is
-sampled every 10 MCS.  One "step" =
-10 MCS followed by one exact W^2 sample (the full hot path: init once, then
-sweep + roughness).  Value = site-update attempts per second over the timed
-steps, with the lattice already resident in HBM.
+slopes), p = 1, q = 0, flat start, Philox seed 1, 256 x 128 dead-border
+blocks (the fastest shape at this L) with 4 x 4 double tiles; W^2 is sampled
+every 10 MCS.  One "step" = 10 MCS followed by one exact W^2 sample (the
+full hot path: init once, then sweep + roughness).  Value = site-update
+attempts per second over the timed steps, with the lattice already resident
+in HBM.
 
 Prints one JSON line.  Besides the contract fields it carries
-  roofline      the integer-ALU roofline of one MCS (sweep plus straddling-
-                word merge; HIP events on the sweep's stream give its mean
-                time), plus its HBM view
-  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload
-                (single blocks of the same lattice, same draws)
+  roofline      the sweep launch (one MCS) against the vector-ALU issue
+                ceiling measured in the same run by kpz_valu_probe (the
+                kernel's VALU instruction count per launch comes from the
+                committed rocprofv3 counter summary of the same code), and
+                its HBM view at the algorithmic 0.5 B per attempt
+  cpu_baseline  the CPU oracle (the same decomposed schedule and draws) on a
+                smaller lattice with the same block shape, on all host cores
+                and on one
 """
 from __future__ import annotations
 
@@ -28,51 +31,81 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Peak rates of MI355X used for the roofline (public figures): HBM3E 8 TB/s;
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 32-bit integer VALU lane
-# operations per second (the fp32 vector peak of 157.3 TFLOP/s counts packed
-# FMAs as 4 flops per lane-cycle).
+# HBM3E peak of MI355X (public figure).
 HBM_PEAK_GBS = 8000.0
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Algorithmic cost of one attempt: the packed lattice (2 bits per site) is
-# read once and written once per MCS (0.5 B); the SWAR update of four tiles
-# at once takes 31 32-bit integer operations per step (site draw, one-hot,
-# dead mask, neighbour alignment, minimum test, flip masks, apply, count),
-# 7.75 per attempt, plus 1.25 for the Philox draws: 9 per attempt.
+# Algorithmic traffic of one attempt: the packed lattice (2 bits per site)
+# is read once and written once per MCS.
 BYTES_PER_ATTEMPT = 0.5
-OPS_PER_ATTEMPT = 9.0
 
 
-def cpu_baseline(L, block, p, q, seed, budget_s):
-    """Oracle on single blocks of MCS 0 of the same lattice: block after
-    block until the time budget is used; attempts/s = blocks * Bx*By / time."""
-    import numpy as np
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(block, p, q, seed, budget_s):
+    """The oracle's decomposed schedule (or_dd_run_par, the plain C runner
+    with the blocks of a residency spread over OpenMP threads) on an L = 2048
+    lattice with the benchmark's block shape, p, q and seed, from the flat
+    start, MCS after MCS until half the budget is used: once on all host
+    cores, once on one.  attempts/s = MCS * L^2 / time."""
     import oracle
     oracle.build(force=False)
-    Bx, By = block
-    ox, oy = oracle.dd_origin(seed, 0, block)
-    y, x = np.mgrid[0:By, 0:Bx]
-    n_done = 0
-    t0 = time.perf_counter()
-    nbx = L // Bx
-    b = 0
-    while True:
-        bx, by = b % nbx, b // nbx
-        # flat start: the block's slopes depend only on the parity of its corner
-        gx0, gy0 = (ox + bx * Bx) % L, (oy + by * By) % L
-        par = (x + y + gx0 + gy0) & 1
-        sx = np.where(par == 0, 1, -1).astype(np.int8)
-        sy = sx.copy()
-        oracle.dd_block_mcs(L, p, q, seed, block, 0, bx, by, sx, sy)
-        n_done += 1
-        b += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": n_done * Bx * By / dt, "unit": "attempts/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_done} dead-border blocks of {Bx}x{By} sites, MCS 0 of the L={L} "
-                      f"lattice (p={p}, q={q}, seed {seed}), plain single-threaded C oracle, "
-                      f"{dt:.1f} s on {platform.processor() or platform.machine()}"}
+    L = 2048
+    threads = os.cpu_count() or 1
+
+    def run(nthreads, budget):
+        st = oracle.SlopeState(L)
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            st.run_dd(1, p, q, seed, block=block, tile=(4, 4), threads=nthreads)
+            n += 1
+            if time.perf_counter() - t0 > budget:
+                break
+        return n, time.perf_counter() - t0
+
+    n_all, t_all = run(threads, budget_s / 2)
+    n_one, t_one = run(1, budget_s / 2)
+    return {"value": n_all * L * L / t_all, "unit": "attempts/s", "cores": threads,
+            "kind": "oracle",
+            "single_core": n_one * L * L / t_one,
+            "cpu_model": cpu_model(),
+            "sample": f"L={L} lattice, {block[0]}x{block[1]} dead-border blocks, p={p} q={q} "
+                      f"seed {seed}, flat start: {n_all} MCS on {threads} threads in {t_all:.1f} s "
+                      f"and {n_one} MCS on one thread in {t_one:.1f} s (plain C oracle, "
+                      f"or_dd_run_par), {cpu_model()}"}
+
+
+def valu_ceiling(reps: int = 3):
+    """Vector-ALU issue ceiling of this device for the sweep's instruction
+    mix: kpz_valu_probe (8192 waves, exactly counted bitwise instructions),
+    best of `reps` timings with HIP events; wave instructions per second."""
+    import ctypes
+    import torch
+    import paper_1204_5072_amd as kpz
+    groups, iters = 2048, 1000
+    out = torch.empty(groups * 256, dtype=torch.int32, device="cuda")
+    ops = ctypes.c_int32()
+    st = torch.cuda.current_stream()
+    best = None
+    for _ in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        rc = kpz.lib().kpz_valu_probe(ctypes.c_void_p(out.data_ptr()), groups, iters,
+                                      ctypes.byref(ops), ctypes.c_void_p(st.cuda_stream))
+        e1.record(st)
+        torch.cuda.synchronize()
+        if rc != 0:
+            return None
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    return groups * 4 * iters * ops.value / (best * 1e-3)
 
 
 def log_times(n=64, t_max=10_000):
@@ -103,13 +136,13 @@ def ensemble_leg(args):
     qs = rng.choice([0.0, 0.25, 0.5], size=n)
     base = [kpz.make_params(int(L), 1.0, float(q), 1000 + r) for r, (L, q) in enumerate(zip(Ls, qs))]
     if args.ens_block:
-        block = tuple(args.ens_block)
+        blocks = {int(L): tuple(args.ens_block) for L in set(Ls)}
         tuned = None
     else:
-        tuned = autotune.tune_ensemble(base, mcs=2)
-        block = tuned["block"]
-        print(f"bench: ensemble block {block} (tuned)", file=sys.stderr, flush=True)
-    members = [kpz.make_params(m.L, m.p, m.q, m.seed, block) for m in base]
+        tuned = autotune.tune_ensemble(base)
+        blocks = tuned["blocks"]
+        print(f"bench: ensemble blocks {blocks} (tuned per L)", file=sys.stderr, flush=True)
+    members = [kpz.make_params(m.L, m.p, m.q, m.seed, blocks[int(m.L)]) for m in base]
     times = log_times(64, args.ens_mcs)
     ens = kpz.Ensemble(members)
     torch.cuda.synchronize()
@@ -123,7 +156,7 @@ def ensemble_leg(args):
     # sequential plain launches: a subset of members, each on its own
     m_seq = min(args.ens_seq_members, n)
     seq_mcs = 5
-    sims = [kpz.Sim(m.L, m.p, m.q, m.seed, block) for m in members[:m_seq]]
+    sims = [kpz.Sim(m.L, m.p, m.q, m.seed, blocks[int(m.L)]) for m in members[:m_seq]]
     for sim in sims:
         sim.sweep(1)
     torch.cuda.synchronize()
@@ -146,17 +179,16 @@ def ensemble_leg(args):
         "members": n,
         "mcs": times[-1],
         "samples": len(times),
-        "block": list(block),
-        "autotune_ms_per_mcs": ({f"{k[0]}x{k[1]}": v for k, v in tuned["ms_per_mcs"].items()}
-                                if tuned else None),
+        "blocks_by_L": {str(L): list(b) for L, b in sorted(blocks.items())},
+        "autotune_ms_per_mcs": ({str(L): {f"{k[0]}x{k[1]}": v for k, v in t.items()}
+                                 for L, t in tuned["ms_per_mcs"].items()} if tuned else None),
         "sequential_plain_launches": {"value": seq_attempts / seq_elapsed, "unit": "attempts/s",
                                       "members": m_seq, "mcs": seq_mcs},
         "speedup_vs_sequential": (attempts / elapsed) / (seq_attempts / seq_elapsed),
         "mean_w2_final_by_L": final,
         # each member's lattice is read and written once per MCS (0.5 B per
-        # attempt); the round kernel is bound by VALU issue (its counters:
-        # profiles/kpz_batch_round_ens512_kernel_trace.md), so the HBM view
-        # is context, not the bound
+        # attempt); the members' lattices (about 180 MB) stay in the 256 MB
+        # last-level cache, so the HBM figure is nominal
         "roofline": {"bound": "alu", "hbm_achieved_gbs": 0.5 * attempts / elapsed / 1e9,
                      "hbm_peak_gbs": HBM_PEAK_GBS,
                      "hbm_frac": 0.5 * attempts / elapsed / 1e9 / HBM_PEAK_GBS,
@@ -203,7 +235,7 @@ def latency_leg(args):
     }
 
 
-def ring_leg(args):
+def ring_leg(args, ceiling):
     """The 1+1-d ring (the rooftop reduction) at L = 2^30 sites (128 MiB of
     packed bonds), p = 1, q = 0, seed 1, default blocks: attempts/s over 20
     MCS timed with HIP events on the ring's stream, and its HBM roofline at
@@ -226,14 +258,15 @@ def ring_leg(args):
     r.close()
     gbs = 0.25 * L / (ms * 1e-3) / 1e9
     valu = ring_valu_per_mcs()
-    if valu is None:
-        roof = {"bound": "alu", "achieved": None, "peak": VALU_ISSUE_PEAK / 1e9,
+    if valu is None or ceiling is None:
+        roof = {"bound": "alu", "achieved": None,
+                "peak": ceiling / 1e9 if ceiling else None,
                 "unit": "G wave-instr/s", "frac": None,
                 "note": "VALU count not measured for this source"}
     else:
         rate = valu / (ms * 1e-3)
-        roof = {"bound": "alu", "achieved": rate / 1e9, "peak": VALU_ISSUE_PEAK / 1e9,
-                "unit": "G wave-instr/s", "frac": rate / VALU_ISSUE_PEAK,
+        roof = {"bound": "alu", "achieved": rate / 1e9, "peak": ceiling / 1e9,
+                "unit": "G wave-instr/s", "frac": rate / ceiling,
                 "valu_wave_instr_per_mcs": valu}
     roof.update({"hbm_achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
                  "bytes_per_attempt": 0.25})
@@ -246,11 +279,6 @@ def ring_leg(args):
         "roofline": roof,
         "w2_t22": m.W2,
     }
-
-
-# VALU issue limit: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every
-# 4 cycles at 2.4 GHz
-VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def code_sha256(names):
@@ -368,25 +396,28 @@ def serving_leg(args):
     }
 
 
-def measured_traffic(block, in_place=False, device_dt=False):
-    """HBM bytes per MCS (every launch of one MCS) of this block shape and
-    mode from the committed hardware-counter summary, or None when the
-    sweep's source (kpz.hip and the device helpers it includes) has changed
-    since the counters were taken, or the shape was not measured."""
+def sweep_counters(block, in_place=False, device_dt=False):
+    """(HBM bytes per MCS, VALU wave instructions per MCS) of this block shape
+    and mode from the committed hardware-counter summary, each None when the
+    sweep's source (kpz.hip and the device headers it includes) has changed
+    since the counters were taken or the shape was not measured."""
     import re
     path = os.path.join(ROOT, "profiles", "kpz_sweep_L65536_hbm_counters.md")
     try:
         text = open(path).read()
-        sha = code_sha256(("kpz.hip", "kpz_device.h"))
+        sha = code_sha256(("kpz.hip", "kpz_slice.h", "kpz_device.h"))
     except OSError:
-        return None
+        return None, None
     m = re.search(r"code_sha256 = ([0-9a-f]{64})", text)
     if not m or m.group(1) != sha:
-        return None
+        return None, None
     key = "%dx%d%s" % (block[0], block[1],
                        ",device_dt" if device_dt else (",in_place" if in_place else ""))
-    m = re.search(r"traffic_bytes_per_mcs\[%s\] = (\d+)" % re.escape(key), text)
-    return float(m.group(1)) if m else None
+    out = []
+    for name in ("traffic_bytes_per_mcs", "valu_wave_instr_per_mcs"):
+        m = re.search(r"%s\[%s\] = (\d+)" % (name, re.escape(key)), text)
+        out.append(float(m.group(1)) if m else None)
+    return tuple(out)
 
 
 def copy_probe(mib: int) -> None:
@@ -410,7 +441,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--L", type=int, default=65536)
-    ap.add_argument("--block", type=int, nargs=2, default=[1024, 64],
+    ap.add_argument("--block", type=int, nargs=2, default=[256, 128],
                     help="dead-border block shape (default: the autotuner's choice at L = 2^16)")
     ap.add_argument("--mcs-per-step", type=int, default=10)
     ap.add_argument("--p", type=float, default=1.0)
@@ -422,7 +453,7 @@ def main():
                     help="update the lattice in place (no second lattice buffer)")
     ap.add_argument("--moves", type=int, default=1,
                     help="dead-border origin moves per MCS (block residency 1/moves MCS)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--ens-members", type=int, default=512)
@@ -493,10 +524,11 @@ def main():
     value = attempts / elapsed
     per_launch_attempts = float(L) * L
     sweep_s = sweep_ms / 1e3
-    achieved_tops = OPS_PER_ATTEMPT * per_launch_attempts / sweep_s / 1e12
     achieved_gbs = BYTES_PER_ATTEMPT * per_launch_attempts / sweep_s / 1e9
-    traffic = (measured_traffic(block, args.in_place, args.device_dt)
-               if (L == 65536 and args.moves == 1) else None)
+    traffic, valu = (sweep_counters(block, args.in_place, args.device_dt)
+                     if (L == 65536 and args.moves == 1) else (None, None))
+    ceiling = valu_ceiling()
+    valu_rate = valu / sweep_s if valu else None
     line = {
         "metric": "site-update attempts/s at L=2^16",
         "value": value,
@@ -520,23 +552,27 @@ def main():
             "device_layer": "double tiling" if args.device_dt else "dead border",
         },
         "roofline": {
+            # bound by vector-ALU issue: the kernel's VALU wave instructions per
+            # launch (rocprofv3 SQ_INSTS_VALU, committed summary of this code)
+            # over the mean launch time, against the issue rate kpz_valu_probe
+            # measures on this device for the same instruction mix
             "bound": "alu",
-            "achieved": achieved_tops,
-            "peak": VALU_PEAK_TOPS,
-            "unit": "Tops/s",
-            "frac": achieved_tops / VALU_PEAK_TOPS,
+            "achieved": valu_rate / 1e9 if valu_rate else None,
+            "peak": ceiling / 1e9 if ceiling else None,
+            "unit": "G wave-instr/s",
+            "frac": valu_rate / ceiling if (valu_rate and ceiling) else None,
             "traffic": traffic,
             "traffic_unit": "HBM bytes per MCS (all launches of one MCS; rocprofv3 FETCH_SIZE "
                             "and WRITE_SIZE scaled by a 1 GiB copy probe)",
             # one MCS = one sweep launch (two-buffer mode), or the sweep launch
             # plus the straddling-word merge launch (in place), bracketed
             # together by the events
-            "kernel": ("kpz_dt_swar_kernel x4 phases" if args.device_dt else
+            "kernel": ("kpz_dt_kernel x4 phases" if args.device_dt else
                        "kpz_sweep_kernel+kpz_merge_kernel" if args.in_place else "kpz_sweep_kernel"),
             "mean_launch_ms": sweep_ms,
-            "ops_per_attempt": OPS_PER_ATTEMPT,
-            "hbm_achieved_gbs": achieved_gbs,
-            "hbm_frac": achieved_gbs / HBM_PEAK_GBS,
+            "valu_wave_instr_per_launch": valu,
+            "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved_gbs / HBM_PEAK_GBS, "bytes_per_attempt": BYTES_PER_ATTEMPT},
         },
         "roughness_ms": rough_ms,
         "w2_last": w2[-1] if w2 else None,
@@ -552,7 +588,7 @@ def main():
         line["latency"] = latency_leg(args)
     if not args.no_ring:
         print("bench: ring leg", file=sys.stderr, flush=True)
-        line["ring"] = ring_leg(args)
+        line["ring"] = ring_leg(args, ceiling)
     if not args.no_kmc:
         print("bench: kmc leg", file=sys.stderr, flush=True)
         line["kmc"] = kmc_leg(args)
@@ -560,7 +596,7 @@ def main():
         print("bench: serving leg", file=sys.stderr, flush=True)
         line["serving"] = serving_leg(args)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(L, block, args.p, args.q, args.seed, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(block, args.p, args.q, args.seed, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

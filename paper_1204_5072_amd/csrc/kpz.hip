@@ -213,7 +213,7 @@ __device__ __forceinline__ void load_group(const uint32_t *row, uint32_t gw, uin
 // step k takes cell set bits 2k.. of (SET, t, b, res).w0 and, for row group
 // G = (b nty + ty) nqx + q, the tile's bit of words 2 (k mod 2), +1 of
 // (SITE, t, G, k / 2) as the site (rx, ry) in its cell.
-template <bool ACC, bool DT, bool VEC>
+template <bool ACC, bool DT, bool VEC, int XN = 2, int WY = 2>
 __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
 {
     using namespace kpzslice;
@@ -292,11 +292,14 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
     c.dym = (!DT && ty == 0 && a.nby > 1) ? ~0u : 0u;
     c.xn = (a.nqx > 1 || a.nbx == 1) ? 1u : 0u;
     const uint32_t span = (a.nqx - 1u) * a.nty;
-    const uint32_t srcL = q > 0 ? lane - a.nty : (a.nbx == 1 ? lane + span : lane);
-    const uint32_t srcR = q + 1 < a.nqx ? lane + a.nty : (a.nbx == 1 ? lane - span : lane);
+    // the groups of a tile row exchange with their neighbours cyclically:
+    // with several blocks along x, group 0's tile 0 is dead at its left
+    // column (its read is masked, its flip bit there is always 0)
+    const uint32_t srcL = q > 0 ? lane - a.nty : lane + span;
+    const uint32_t srcR = q + 1 < a.nqx ? lane + a.nty : lane - span;
     c.srcL4 = 4u * srcL;
     c.srcR4 = 4u * srcR;
-    c.rmask = (q + 1 < a.nqx || a.nbx == 1) ? ~0u : 0u;
+    c.rmask = q + 1 < a.nqx ? ~0u : 0u;
     c.pb = 24u + (a.ntg >> 2) - 1u;
     c.wrapy = a.nby == 1 ? 1u : 0u;
     c.srcD4 = 4u * (ty > 0 ? lane - 1u : lane + a.nty - 1u);
@@ -320,9 +323,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
     // ---- work-group layer: single-hit steps k0 .. k1 - 1
     const uint32_t setw = philox(b, 0u, a.t, (TAG_SET << 24) | a.res, a.seed_lo, a.seed_hi).x;
     const uint32_t k0 = a.res * a.nsteps, k1 = k0 + a.nsteps;
+    const bool xn = XN == 2 ? c.xn != 0u : XN == 1;
+    constexpr bool XBC = DT || XN != 0;        // the group boundary bond is kept (hl)
     int net = 0;
     U4 sw = {0u, 0u, 0u, 0u};
     uint32_t l1[4][4] = {{0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}};
+    uint32_t hl = 0u;
+    bool own = false;   // hl holds the bond (a run of sx = 0 steps is on)
     for (uint32_t kq = k0 >> 2; 4u * kq < k1; ++kq) {
         if (ACC) {
 #pragma unroll
@@ -344,14 +351,25 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
             const uint32_t RX = (kr & 1u) ? sw.z : sw.x;
             const uint32_t RY = (kr & 1u) ? sw.w : sw.y;
             const uint32_t lev[4] = {l1[0][kr], l1[1][kr], l1[2][kr], l1[3][kr]};
-            switch ((setw >> (2u * k)) & 3u) {
-            case 0: step<0, 0, ACC, DT, TAG_ACC2>(X, Y, RX, RY, c, lev, d, k, net, hx, hy); break;
-            case 1: step<1, 0, ACC, DT, TAG_ACC2>(X, Y, RX, RY, c, lev, d, k, net, hx, hy); break;
-            case 2: step<0, 1, ACC, DT, TAG_ACC2>(X, Y, RX, RY, c, lev, d, k, net, hx, hy); break;
-            default: step<1, 1, ACC, DT, TAG_ACC2>(X, Y, RX, RY, c, lev, d, k, net, hx, hy); break;
+            const uint32_t s = (setw >> (2u * k)) & 3u;
+            if (XBC && (xn || DT)) {
+                if ((s & 1u) == 0 && !own) {
+                    pull_bond(X, c, xn, DT, hx, hl);
+                    own = true;
+                } else if ((s & 1u) && own) {
+                    push_bond(X, c, xn, DT, hx, hl);
+                    own = false;
+                }
+            }
+            switch (s) {
+            case 0: step<0, 0, ACC, DT, XBC, WY, TAG_ACC2>(X, Y, RX, RY, c, lev, d, k, net, hl, hy); break;
+            case 1: step<1, 0, ACC, DT, XBC, WY, TAG_ACC2>(X, Y, RX, RY, c, lev, d, k, net, hl, hy); break;
+            case 2: step<0, 1, ACC, DT, XBC, WY, TAG_ACC2>(X, Y, RX, RY, c, lev, d, k, net, hl, hy); break;
+            default: step<1, 1, ACC, DT, XBC, WY, TAG_ACC2>(X, Y, RX, RY, c, lev, d, k, net, hl, hy); break;
             }
         }
     }
+    if (XBC && own) push_bond(X, c, xn, DT, hx, hl);
 
     // ---- store.  Two-buffer mode: the group's words are whole output words
     // (the output is rotated by the origin).  In place: words wholly inside
@@ -494,14 +512,17 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
 // with xcd set, group i takes the blocks of virtual group (i mod 8) n/8 +
 // i/8, so each XCD runs one contiguous range of blocks and neighbouring
 // blocks, which share cache lines at their edges, meet in the same L2.
-template <bool ACC, bool VEC>
+// XN: the row groups exchange tile 0's left neighbour (several groups per
+// tile row, or one block along x); WY: one block along y (the tile row
+// below tile row 0 wraps around).
+template <bool ACC, bool VEC, int XN, int WY>
 __global__ __launch_bounds__(256) void kpz_sweep_kernel(const SweepArgs a, uint32_t nblocks)
 {
     uint32_t g = blockIdx.x;
     if (a.xcd) g = (g & 7u) * (gridDim.x >> 3) + (g >> 3);
     const uint32_t b = g * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (b >= nblocks) return;
-    sweep_block<ACC, false, VEC>(a, __builtin_amdgcn_readfirstlane(b));
+    sweep_block<ACC, false, VEC, XN, WY>(a, __builtin_amdgcn_readfirstlane(b));
 }
 
 // Straddling word j = gy * nbx + bx of MCS a.t: the word at the left edge of
@@ -573,7 +594,7 @@ __device__ __forceinline__ uint32_t dt_set(uint32_t t, uint32_t seed_lo, uint32_
 
 // One launch per block set; the blocks of set c are (2 i + (c & 1), 2 j +
 // (c >> 1)), one wave each.
-template <bool ACC, bool VEC>
+template <bool ACC, bool VEC, int XN>
 __global__ __launch_bounds__(256) void kpz_dt_kernel(const SweepArgs a, uint32_t phase,
                                                      uint32_t nset)
 {
@@ -584,7 +605,7 @@ __global__ __launch_bounds__(256) void kpz_dt_kernel(const SweepArgs a, uint32_t
     const uint32_t c = dt_set(a.t, a.seed_lo, a.seed_hi, phase);
     const uint32_t hx = a.nbx >> 1;
     const uint32_t bx = 2 * (w % hx) + (c & 1u), by = 2 * (w / hx) + (c >> 1);
-    sweep_block<ACC, true, VEC>(a, __builtin_amdgcn_readfirstlane(by * a.nbx + bx));
+    sweep_block<ACC, true, VEC, XN, 0>(a, __builtin_amdgcn_readfirstlane(by * a.nbx + bx));
 }
 
 
@@ -1499,9 +1520,10 @@ kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
     const int tx = p->tile_x ? p->tile_x : TILE, ty = p->tile_y ? p->tile_y : TILE;
     if (tx != TILE || ty != TILE) return KPZ_EINVAL;
     const int64_t L = p->L;
-    // default: Bx the largest power of two <= 128 dividing L, By the largest
-    // <= 256 (one wave of 64 tile rows per block where L allows)
-    int64_t dx = 128, dy = 256;
+    // default: Bx the largest power of two <= 256 dividing L, By the largest
+    // <= 128 (one full wave per block where L allows: two row groups of 128
+    // sites in 32 tile rows; the fastest of the full shapes at L = 65536)
+    int64_t dx = 256, dy = 128;
     while (L % dx) dx >>= 1;
     while (L % dy) dy >>= 1;
     const int64_t bx = p->block_x ? p->block_x : dx;
@@ -1591,39 +1613,54 @@ uint32_t waves_per_group(uint32_t nblocks)
 }
 
 // One wave per block.
-template <bool ACC, bool VEC>
+template <bool ACC, bool VEC, int XN, int WY>
 hipError_t launch_sweep_v(const SweepArgs &a, uint32_t nblocks, hipStream_t st)
 {
     const uint32_t wpg = waves_per_group(nblocks);
     const uint32_t grid = nblocks / wpg;
     SweepArgs b = a;
     b.xcd = (grid % 8u) == 0 ? a.xcd : 0u;
-    hipLaunchKernelGGL((kpz_sweep_kernel<ACC, VEC>), dim3(grid), dim3(64 * wpg), 0, st, b,
-                       nblocks);
+    hipLaunchKernelGGL((kpz_sweep_kernel<ACC, VEC, XN, WY>), dim3(grid), dim3(64 * wpg), 0, st,
+                       b, nblocks);
     return hipGetLastError();
+}
+
+template <bool ACC, bool VEC>
+hipError_t launch_sweep_x(const SweepArgs &a, uint32_t nblocks, hipStream_t st)
+{
+    const bool xn = a.nqx > 1 || a.nbx == 1, wy = a.nby == 1;
+    if (xn) return wy ? launch_sweep_v<ACC, VEC, 1, 1>(a, nblocks, st)
+                      : launch_sweep_v<ACC, VEC, 1, 0>(a, nblocks, st);
+    return wy ? launch_sweep_v<ACC, VEC, 0, 1>(a, nblocks, st)
+              : launch_sweep_v<ACC, VEC, 0, 0>(a, nblocks, st);
 }
 
 template <bool ACC>
 hipError_t launch_sweep(const SweepArgs &a, uint32_t nblocks, hipStream_t st)
 {
-    return (a.W % 4 == 0) ? launch_sweep_v<ACC, true>(a, nblocks, st)
-                          : launch_sweep_v<ACC, false>(a, nblocks, st);
+    return (a.W % 4 == 0) ? launch_sweep_x<ACC, true>(a, nblocks, st)
+                          : launch_sweep_x<ACC, false>(a, nblocks, st);
 }
 
-template <bool ACC, bool VEC>
+template <bool ACC, bool VEC, int XN>
 hipError_t launch_dt_v(const SweepArgs &a, uint32_t phase, uint32_t nset, hipStream_t st)
 {
     const uint32_t wpg = waves_per_group(nset);
-    hipLaunchKernelGGL((kpz_dt_kernel<ACC, VEC>), dim3(nset / wpg), dim3(64 * wpg), 0, st, a,
-                       phase, nset);
+    hipLaunchKernelGGL((kpz_dt_kernel<ACC, VEC, XN>), dim3(nset / wpg), dim3(64 * wpg), 0, st,
+                       a, phase, nset);
     return hipGetLastError();
 }
 
 template <bool ACC>
 hipError_t launch_dt(const SweepArgs &a, uint32_t phase, uint32_t nset, hipStream_t st)
 {
-    return (a.W % 4 == 0) ? launch_dt_v<ACC, true>(a, phase, nset, st)
-                          : launch_dt_v<ACC, false>(a, phase, nset, st);
+    // double tiling needs at least two blocks along each axis: no wrap
+    const bool xn = a.nqx > 1;
+    if (a.W % 4 == 0)
+        return xn ? launch_dt_v<ACC, true, 1>(a, phase, nset, st)
+                  : launch_dt_v<ACC, true, 0>(a, phase, nset, st);
+    return xn ? launch_dt_v<ACC, false, 1>(a, phase, nset, st)
+              : launch_dt_v<ACC, false, 0>(a, phase, nset, st);
 }
 
 }  // namespace

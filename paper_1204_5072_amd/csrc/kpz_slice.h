@@ -106,11 +106,16 @@ struct LaneCtx {
     uint32_t dxm;     // 1: tile 0's left column is the dead border
     uint32_t dym;     // ~0: the tile row's bottom row is the dead border
     uint32_t xn;      // (uniform) tile 0's left neighbour is in another lane / wraps
-    uint32_t srcL4;   // ds_bpermute address of the lane holding the left group
-    uint32_t srcR4;   // ... the right group
-    uint32_t rmask;   // ~0 when the right group exists (flips come from it)
+                      // (read when the XN template argument is 2)
+    uint32_t srcL4;   // ds_bpermute address of the lane holding the left group (the
+                      // block's last group for group 0: its wrap, or unused when the
+                      // left column is the dead border)
+    uint32_t srcR4;   // ... the right group (group 0 for the last group: its wrap, or
+                      // a dead tile 0 that never flips)
+    uint32_t rmask;   // DT: ~0 when the right group is in the block
     uint32_t pb;      // bit of the group's last tile
     uint32_t wrapy;   // (uniform) one block along y: the tile row below wraps
+                      // (read when the step's WY template argument is 2)
     uint32_t srcD4;   // wrapy: lane holding the tile row below
     uint32_t srcU4;   // wrapy: lane holding the tile row above
     // double tiling at the device layer (no dead sites): halos of group 0 /
@@ -182,17 +187,55 @@ __device__ __forceinline__ uint32_t accept(uint32_t mn, uint32_t mx, const uint3
     return fP | fQ;
 }
 
+// The slope bond between the last tile of a row group and the first tile of
+// the next group (sigma_x at the group boundary, one bit per row) is written
+// by the left group's last tile in steps with sx = 1 and by the right group's
+// first tile in steps with sx = 0, and read likewise.  The left group keeps it
+// as bit pb of X[r][3]; the right group keeps a copy `hl` (bit r for row r)
+// that is authoritative during a run of sx = 0 steps: pull_bond copies it
+// from the left lane before such a run, push_bond copies it back after it,
+// one lane exchange per change of sx instead of two per step.  DT: group 0's
+// bond is the halo column hx of the idle block to the left.
+__device__ __forceinline__ void pull_bond(const uint32_t (&X)[4][4], const LaneCtx &c, bool xn,
+                                          bool dt, uint32_t hx, uint32_t &hl)
+{
+    uint32_t v = 0u;
+    if (xn) {
+        const uint32_t e = __builtin_amdgcn_ubfe(X[0][3], c.pb, 1u) |
+                           (__builtin_amdgcn_ubfe(X[1][3], c.pb, 1u) << 1) |
+                           (__builtin_amdgcn_ubfe(X[2][3], c.pb, 1u) << 2) |
+                           (__builtin_amdgcn_ubfe(X[3][3], c.pb, 1u) << 3);
+        v = bperm(c.srcL4, e);
+    }
+    hl = dt ? bsel(c.hxl, hx, v) : v;
+}
+
+__device__ __forceinline__ void push_bond(uint32_t (&X)[4][4], const LaneCtx &c, bool xn, bool dt,
+                                          uint32_t &hx, uint32_t hl)
+{
+    if (dt) hx = bsel(c.hxl, hl, hx);
+    if (!xn) return;
+    const uint32_t v = bperm(c.srcR4, hl);
+    // DT: the last group's right bond stays its own (idle block beyond)
+    const uint32_t m = (1u << c.pb) & (dt ? c.rmask : ~0u);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        X[r][3] = bsel(m, __builtin_amdgcn_alignbit(v, v, ((uint32_t)r - c.pb) & 31u), X[r][3]);
+}
+
 // One single-hit step with cell set (SX, SY) for the 32 tiles of this lane's
 // row group.  RX, RY: the site of every tile in its 2 x 2 cell (tile bit).
-// DT: halo column hx (bit r = sigma_x left of tile 0 in row r, lanes of
-// group 0) and halo row hy[c] (sigma_y below tile row 0, lanes of tile row 0).
-template <int SX, int SY, bool ACC, bool DT, uint32_t TAG_ACC2>
+// hl: the group's left boundary bond (see pull_bond; used when XB).  DT: halo
+// row hy[c] (sigma_y below tile row 0, lanes of tile row 0).  WY: 0 or 1 fix
+// the wrapped tile row below at compile time; 2 reads it from the context.
+template <int SX, int SY, bool ACC, bool DT, bool XB, int WY, uint32_t TAG_ACC2>
 __device__ __forceinline__ void step(uint32_t (&X)[4][4], uint32_t (&Y)[4][4], uint32_t RX,
                                      uint32_t RY, const LaneCtx &c, const uint32_t (&lev)[4],
-                                     const AccDraw &d, uint32_t k, int &net, uint32_t &hx,
+                                     const AccDraw &d, uint32_t k, int &net, uint32_t &hl,
                                      uint32_t (&hy)[4])
 {
     constexpr int R0 = 2 * SY, C0 = 2 * SX;
+    const bool wrapy = !DT && (WY == 2 ? c.wrapy != 0u : WY == 1);
     // sigma_x one column left of C0, rows R0 and R0 + 1
     uint32_t xm0, xm1;
     if (SX) {
@@ -201,16 +244,10 @@ __device__ __forceinline__ void step(uint32_t (&X)[4][4], uint32_t (&Y)[4][4], u
     } else {
         xm0 = prev_tile(X[R0][3]);
         xm1 = prev_tile(X[R0 + 1][3]);
-        if (c.xn || DT) {
-            uint32_t el = 0u;
-            if (c.xn) {
-                const uint32_t e = __builtin_amdgcn_ubfe(X[R0][3], c.pb, 1u) |
-                                   (__builtin_amdgcn_ubfe(X[R0 + 1][3], c.pb, 1u) << 1);
-                el = bperm(c.srcL4, e);
-            }
-            if (DT) el = bsel(c.hxl, hx >> R0, el);
-            xm0 = bsel(1u, el, xm0);
-            xm1 = bsel(1u, el >> 1, xm1);
+        if (XB) {
+            // tile 0: the bond to the group on the left
+            xm0 = bsel(1u, hl >> R0, xm0);
+            xm1 = bsel(1u, hl >> (R0 + 1), xm1);
         }
     }
     // sigma_y one row below R0, columns C0 and C0 + 1
@@ -218,7 +255,7 @@ __device__ __forceinline__ void step(uint32_t (&X)[4][4], uint32_t (&Y)[4][4], u
     if (SY) {
         yd0 = Y[1][C0];
         yd1 = Y[1][C0 + 1];
-    } else if (!DT && c.wrapy) {
+    } else if (wrapy) {
         yd0 = bperm(c.srcD4, Y[3][C0]);
         yd1 = bperm(c.srcD4, Y[3][C0 + 1]);
     } else {
@@ -270,15 +307,7 @@ __device__ __forceinline__ void step(uint32_t (&X)[4][4], uint32_t (&Y)[4][4], u
     } else {
         X[R0][3] ^= next_tile(F00);
         X[R0 + 1][3] ^= next_tile(F10);
-        if (c.xn || DT) {
-            const uint32_t f = (F00 & 1u) | ((F10 & 1u) << 1);
-            if (c.xn) {
-                const uint32_t fr = bperm(c.srcR4, f) & c.rmask;
-                X[R0][3] ^= (fr & 1u) << c.pb;
-                X[R0 + 1][3] ^= ((fr >> 1) & 1u) << c.pb;
-            }
-            if (DT) hx ^= (f & c.hxl) << R0;
-        }
+        if (XB) hl ^= ((F00 & 1u) | ((F10 & 1u) << 1)) << R0;
     }
     Y[R0][C0] ^= F00 ^ F10;
     Y[R0][C0 + 1] ^= F01 ^ F11;
@@ -287,7 +316,7 @@ __device__ __forceinline__ void step(uint32_t (&X)[4][4], uint32_t (&Y)[4][4], u
     if (SY) {
         Y[1][C0] ^= F00;
         Y[1][C0 + 1] ^= F01;
-    } else if (!DT && c.wrapy) {
+    } else if (wrapy) {
         Y[3][C0] ^= bperm(c.srcU4, F00);
         Y[3][C0 + 1] ^= bperm(c.srcU4, F01);
     } else {

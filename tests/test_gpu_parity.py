@@ -76,7 +76,8 @@ CASES = [
     (256, (256, 32), 0.3, 0.9, 11, 4),
     (512, (512, 64), 1.0, 0.0, 12, 3),        # four groups per tile row, one block along x
     (1024, (512, 64), 1.0, 0.5, 13, 2),       # four groups, dead borders
-    (1024, (128, 256), 1.0, 0.0, 32, 4),      # the benchmark's shape and thresholds
+    (1024, (128, 256), 1.0, 0.0, 32, 4),      # 64 tile rows, one group per tile row
+    (1024, (256, 128), 1.0, 0.0, 34, 4),      # the benchmark's shape and thresholds
     (2048, (512, 64), 1.0, 0.0, 33, 2),
     (48, (16, 16), 1.0, 0.0, 14, 6),          # non-power-of-two L (ragged word count per row)
     (96, (32, 32), 0.5, 0.5, 15, 6),
@@ -132,7 +133,7 @@ def test_sweep_moves_matches_oracle(gpu, oracle_lib, L, block, p, q, seed, n, mo
 @pytest.mark.parametrize("L,block,p,q,seed,n", [(64, (32, 16), 1.0, 0.0, 3, 6),
                                               (256, (256, 64), 0.7, 0.3, 10, 4),
                                               (1024, (512, 64), 1.0, 0.5, 13, 3),
-                                              (1024, (128, 256), 1.0, 0.0, 32, 4),
+                                              (1024, (256, 128), 1.0, 0.0, 34, 4),
                                               (96, (32, 32), 0.5, 0.5, 15, 5)])
 def test_in_place_mode_matches_oracle(gpu, oracle_lib, L, block, p, q, seed, n):
     """The in-place mode (shared words through the side buffer and a merge
@@ -178,7 +179,7 @@ DT_CASES = [
     (512, (128, 64), 1.0, 0.999999, 46, 2),  # tie draws
     (64, (32, 16), 0.0, 1.0, 47, 3),         # desorption only
     (2048, (512, 64), 1.0, 0.0, 48, 2),      # four groups per tile row
-    (2048, (128, 256), 1.0, 0.0, 51, 2),     # the benchmark's block shape
+    (2048, (256, 128), 1.0, 0.0, 51, 2),     # the benchmark's block shape
     (1024, (512, 32), 1.0, 0.5, 49, 2),
     (512, (256, 16), 0.9, 0.1, 50, 2),
 ]
@@ -243,7 +244,7 @@ def test_checkpoint_resume(gpu):
 
 
 def test_l4096_first_mcs(gpu, oracle_lib):
-    """L = 4096 (the 2^24-site workload), default 128 x 256 blocks: words after
+    """L = 4096 (the 2^24-site workload), default 256 x 128 blocks: words after
     MCS 1 and 2 for both (p, q) of that workload."""
     L = 4096
     for p, q in ((1.0, 0.0), (0.5, 0.5)):
@@ -252,7 +253,7 @@ def test_l4096_first_mcs(gpu, oracle_lib):
         st = oracle_lib.SlopeState(L)
         for t in range(2):
             sim.sweep(1)
-            st.run_dd(1, p, q, 1, block=(128, 256), tile=(4, 4))
+            st.run_dd(1, p, q, 1, block=(256, 128), tile=(4, 4))
             assert np.array_equal(sim.words_host(), oracle_lib.pack(st.sx, st.sy)), t
         assert_moments(oracle_lib, st, sim.roughness(), L)
 
@@ -275,18 +276,19 @@ def _unpack_rows(oracle_lib, rows_words, L):
 
 def test_l65536_sampled_blocks(gpu, oracle_lib):
     """The 2^32-site workload in the launch configuration the benchmark times
-    (128 x 256 blocks, p = 1, q = 0, two-buffer): MCS 2 checked on sampled
+    (256 x 128 blocks, p = 1, q = 0, two-buffer): MCS 2 checked on sampled
     blocks, including the ones that wrap around the lattice edges, against the
     oracle's single-block runner; the moments must be consistent."""
     import torch
-    L, B, p, q, seed = 65536, (128, 256), 1.0, 0.0, 1
+    L, B, p, q, seed = 65536, (256, 128), 1.0, 0.0, 1
     _log("L=65536 sampled blocks")
     sim = gpu.Sim(L, p, q, seed, B)
     sim.sweep(2)
     t = 2
     origin = oracle_lib.dd_origin(seed, t, B)
     nbx, nby = L // B[0], L // B[1]
-    samples = [(0, 0), (nbx - 1, 0), (0, nby - 1), (nbx - 1, nby - 1), (123, 77), (400, 200)]
+    samples = [(0, 0), (nbx - 1, 0), (0, nby - 1), (nbx - 1, nby - 1), (123, 77),
+               (nbx // 2 + 3, nby // 3)]
     W = L // 16
     words = sim.words.view(L, W)
     sim.sync_words()   # `words` holds the state only after a sync (two-buffer mode)
