@@ -75,6 +75,8 @@ def lib():
         L.or_dd_run_par.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
                                     c.c_int, c.c_int, c.c_int, c.c_int, c.c_int,
                                     c.c_uint32, c.c_int, i8p, i8p, i64p, i64p, c.c_int]
+        L.or_strat_run.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64, c.c_int,
+                                   c.c_int, c.c_uint32, c.c_int, i8p, i8p, i64p, i64p]
         L.or_rs1d_run.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
                                   c.c_uint32, c.c_int, i8p, i64p, i64p]
         L.or_dd_block_mcs.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
@@ -94,6 +96,7 @@ def lib():
                                 c.c_uint32, c.c_int, i8p, i8p, i64p, i64p, c.c_int]
         L.or_dt_perm.argtypes = [c.c_uint64, c.c_uint32, c.POINTER(c.c_int * 4)]
         for f in ("or_flat", "or_rs_heights_run", "or_rs_slopes_run", "or_dd_run", "or_dd_run_par",
+                  "or_strat_run",
                   "or_rs1d_run",
                   "or_dd_block_mcs", "or_dd1d_run", "or_dd1d_block_mcs", "or_dd1d_origin",
                   "or_flat1d", "or_dt_run", "or_dt_perm"):
@@ -178,6 +181,15 @@ class SlopeState:
         rc = lib().or_dt_run(self.L, p, q, seed, block[0], block[1], tile[0], tile[1], self.t,
                              n_mcs, self.sx, self.sy, self.h00, self.net, int(check))
         _check(rc, "dt_run")
+        self.t += n_mcs
+        return self
+
+    def run_strat(self, n_mcs: int, p: float, q: float, seed: int, tile=(4, 4)) -> "SlopeState":
+        """n_mcs MCS of the stratified random-sequential control: exactly
+        Tx*Ty attempts per tile per MCS in a random global order."""
+        rc = lib().or_strat_run(self.L, p, q, seed, tile[0], tile[1], self.t, n_mcs, self.sx,
+                                self.sy, self.h00, self.net)
+        _check(rc, "strat_run")
         self.t += n_mcs
         return self
 

@@ -28,6 +28,8 @@
  *                      (device layer), single-hit double tiling inside each
  *                      block (work-group layer)
  *   or_dd_run_par      the same, blocks of a residency on several threads
+ *   or_strat_run       a control for the schedule studies: random-sequential
+ *                      updates with exactly Tx*Ty attempts per tile per MCS
  *   or_rs1d_run        the 1+1-d rooftop (ASEP) reduction (Sec. 2.1),
  *                      random-sequential
  *   or_dd1d_run        the same ring under the decomposition of Sec. 3 / 3.1
@@ -57,6 +59,8 @@
 #define OR_TAG_SITE1D  10u
 #define OR_TAG_ACC1D   11u
 #define OR_TAG_ACC1D2  12u
+#define OR_TAG_STRAT   14u
+#define OR_TAG_STRAT2  15u
 
 #define OR_OK       0
 #define OR_EINVAL  -1
@@ -202,6 +206,60 @@ int or_rs_slopes_run(int L, double p, double q, uint64_t seed, uint32_t t0, int 
     return OR_OK;
 }
 
+/*
+ * Stratified random-sequential control (an experiment, not a schedule of
+ * the paper): per MCS every Tx x Ty tile of the fixed tiling receives
+ * exactly Tx*Ty attempts, at uniformly random sites of the tile, and all N
+ * attempts run one at a time in a uniformly random order.  It differs from
+ * random-sequential updates only in the exact per-tile attempt count, and
+ * from the decomposed schedule in having no cells, sets, single hits or
+ * dead borders, so it isolates the effect of the exact count on W^2(t).
+ * Order: Fisher-Yates over the attempt list (tile-major), position i
+ * drawing j = floor(w0 (i+1) / 2^32) from (STRAT, t, i, 0); attempt a (tile
+ * a / S) takes its site floor(w0 S / 2^32) in the tile and u = w1 from
+ * (STRAT2, t, a, 0).
+ */
+int or_strat_run(int L, double p, double q, uint64_t seed, int Tx, int Ty, uint32_t t0,
+                 int n_mcs, int8_t *sx, int8_t *sy, int64_t *h00, int64_t *net)
+{
+    if (L <= 0 || (L & 1) || n_mcs < 0 || Tx <= 0 || Ty <= 0 || L % Tx || L % Ty) return OR_EINVAL;
+    const uint64_t N = (uint64_t)L * (uint64_t)L;
+    const int S = Tx * Ty, ntx = L / Tx;
+    const uint64_t P = threshold(p), Q = threshold(q);
+    uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * N);
+    if (!order) return OR_ENOMEM;
+    uint32_t w[4];
+    for (int m = 0; m < n_mcs; ++m) {
+        const uint32_t t = t0 + (uint32_t)m;
+        for (uint64_t a = 0; a < N; ++a) order[a] = (uint32_t)a;
+        for (uint64_t i = N - 1; i > 0; --i) {
+            or_draw(seed, OR_TAG_STRAT, t, i, 0, w);
+            const uint64_t j = ((uint64_t)w[0] * (i + 1)) >> 32;
+            const uint32_t tmp = order[i];
+            order[i] = order[j];
+            order[j] = tmp;
+        }
+        for (uint64_t i = 0; i < N; ++i) {
+            const uint32_t a = order[i];
+            or_draw(seed, OR_TAG_STRAT2, t, a, 0, w);
+            const int tile = (int)(a / (uint32_t)S);
+            const int r = (int)(((uint64_t)w[0] * (uint64_t)S) >> 32);
+            const int x = (tile % ntx) * Tx + r % Tx, y = (tile / ntx) * Ty + r / Tx;
+            const int kind = classify(L, sx, sy, x, y);
+            int dh = 0;
+            if (kind == SITE_MIN && (uint64_t)w[1] < P) dh = 2;
+            if (kind == SITE_MAX && (uint64_t)w[1] < Q) dh = -2;
+            if (dh) {
+                flip(L, sx, sy, x, y);
+                *net += dh / 2;
+                if (x == 0 && y == 0) *h00 += dh;
+            }
+        }
+    }
+    free(order);
+    return OR_OK;
+}
+
 /* ---------------------------------------- decomposed (DB + DT) dynamics */
 
 /*
@@ -247,12 +305,19 @@ int or_rs_slopes_run(int L, double p, double q, uint64_t seed, uint32_t t0, int 
  * blocks of that origin; site and acceptance draws are numbered by the
  * step k within the MCS as above.  m = 1 is the schedule above.
  */
+/* Cell set of step k from the block's set draw w[0..3]: bits 2 (k mod 16)
+ * .. +1 of word k / 16 (word 0 for the 16 steps of 4 x 4 tiles). */
+static int step_set(const uint32_t w[4], int k)
+{
+    return (int)((w[k >> 4] >> (2 * (k & 15))) & 3u);
+}
+
 static int dd_validate(int L, int Bx, int By, int Tx, int Ty, int moves)
 {
     if (L <= 0 || (L & 1)) return 0;
     if (moves < 1 || (moves & (moves - 1)) || (Tx * Ty) % moves) return 0;
     if (Bx <= 0 || By <= 0 || L % Bx || L % By) return 0;
-    if (!((Tx == 4 && Ty == 4) || (Tx == 2 && Ty == 2))) return 0;
+    if (!((Tx == 4 && Ty == 4) || (Tx == 2 && Ty == 2) || (Tx == 8 && Ty == 8))) return 0;
     if (Bx % Tx || By % Ty) return 0;
     /* a tile row is one row group of at most 32 tiles or whole groups of 32 */
     if (Bx / Tx > 32 && (Bx / Tx) % 32) return 0;
@@ -271,14 +336,30 @@ static uint64_t row_group(int b, int ty, int tx, int nty, int ntx)
     return ((uint64_t)b * (uint64_t)nty + (uint64_t)ty) * nqx + (uint64_t)(tx / 32);
 }
 
-/* Site (rx, ry) in the 2x2 cell of tile tx of row group G at step k. */
-static void cell_site(uint64_t seed, uint32_t t, uint64_t G, int k, int tx, int *rx, int *ry)
+/* Bit i of the site draw of step k, tile tx of row group G, for cells of
+ * 2^a sites: word a*k + i of the group's site stream, i.e. word
+ * (a*k + i) mod 4 of draw (SITE, t, G, (a*k + i) / 4). */
+static int site_bit(uint64_t seed, uint32_t t, uint64_t G, int k, int a, int i, int tx)
 {
     uint32_t w[4];
-    or_draw(seed, OR_TAG_SITE, t, G, (uint32_t)(k >> 1), w);
-    const int bit = tile_bit(tx);
-    *rx = (int)((w[2 * (k & 1)] >> bit) & 1u);
-    *ry = (int)((w[2 * (k & 1) + 1] >> bit) & 1u);
+    const uint32_t n = (uint32_t)(a * k + i);
+    or_draw(seed, OR_TAG_SITE, t, G, n >> 2, w);
+    return (int)((w[n & 3u] >> tile_bit(tx)) & 1u);
+}
+
+/* Site (rx, ry) in the cell of tile tx of row group G at step k: for 2x2
+ * cells rx = bit 0, ry = bit 1; for 4x4 cells rx = bit 0 + 2 bit 1, ry =
+ * bit 2 + 2 bit 3 (the 4x4 cells of 8x8 tiles, an oracle-only variant). */
+static void cell_site(uint64_t seed, uint32_t t, uint64_t G, int k, int cx, int tx, int *rx,
+                      int *ry)
+{
+    if (cx == 2) {
+        *rx = site_bit(seed, t, G, k, 2, 0, tx);
+        *ry = site_bit(seed, t, G, k, 2, 1, tx);
+    } else {
+        *rx = site_bit(seed, t, G, k, 4, 0, tx) + 2 * site_bit(seed, t, G, k, 4, 1, tx);
+        *ry = site_bit(seed, t, G, k, 4, 2, tx) + 2 * site_bit(seed, t, G, k, 4, 3, tx);
+    }
 }
 
 /* The 32-bit acceptance uniform of tile tx of row group G at step k. */
@@ -317,7 +398,7 @@ static void attempt_site(uint64_t seed, uint32_t t, uint64_t G, int k, int s, in
 {
     const int cx = Tx / 2, cy = Ty / 2;
     int rx = 0, ry = 0;
-    if (cx * cy == 4) cell_site(seed, t, G, k, tx, &rx, &ry);
+    if (cx * cy > 1) cell_site(seed, t, G, k, cx, tx, &rx, &ry);
     *lx = tx * Tx + (s & 1) * cx + rx;
     *ly = ty * Ty + (s >> 1) * cy + ry;
 }
@@ -332,7 +413,7 @@ int or_dd_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
     const int S = Tx * Ty;
     const uint64_t P = threshold(p), Q = threshold(q);
     const int nblocks = nbx * nby;
-    uint32_t *setw = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)nblocks);
+    uint32_t *setw = (uint32_t *)malloc(sizeof(uint32_t) * 4 * (size_t)nblocks);
     int64_t *stamp = check ? (int64_t *)malloc(sizeof(int64_t) * (size_t)L * (size_t)L) : NULL;
     if (!setw || (check && !stamp)) {
         free(setw); free(stamp);
@@ -352,8 +433,7 @@ int or_dd_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
         const int ox = (int)(((uint64_t)w[0] * (uint64_t)Bx) >> 32);
         const int oy = (int)(((uint64_t)w[1] * (uint64_t)By) >> 32);
         for (int b = 0; b < nblocks; ++b) {
-            or_draw(seed, OR_TAG_SET, t, (uint64_t)b, (uint32_t)res, w);
-            setw[b] = w[0];
+            or_draw(seed, OR_TAG_SET, t, (uint64_t)b, (uint32_t)res, &setw[4 * b]);
         }
         /* all blocks make step k "at the same time"; blocks are independent,
            so visiting them one after the other gives the same result */
@@ -361,7 +441,7 @@ int or_dd_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
             for (int by = 0; by < nby; ++by)
                 for (int bx = 0; bx < nbx; ++bx) {
                     const int b = by * nbx + bx;
-                    const int s = (int)((setw[b] >> (2 * k)) & 3u);
+                    const int s = step_set(&setw[4 * b], k);
                     for (int ty = 0; ty < nty; ++ty)
                         for (int tx = 0; tx < ntx; ++tx) {
                             const uint64_t G = row_group(b, ty, tx, nty, ntx);
@@ -427,7 +507,7 @@ int or_dd_run_par(int L, double p, double q, uint64_t seed, int Bx, int By, int 
                 uint32_t ws[4];
                 or_draw(seed, OR_TAG_SET, t, (uint64_t)b, (uint32_t)res, ws);
                 for (int k = res * per_res; k < (res + 1) * per_res; ++k) {
-                    const int s = (int)((ws[0] >> (2 * k)) & 3u);
+                    const int s = step_set(ws, k);
                     for (int ty = 0; ty < nty; ++ty)
                         for (int tx = 0; tx < ntx; ++tx) {
                             const uint64_t G = row_group(b, ty, tx, nty, ntx);
@@ -510,9 +590,8 @@ int or_dd_block_mcs(int L, double p, double q, uint64_t seed, int Bx, int By, in
     const int per_res = S / moves;
     uint32_t w[4];
     or_draw(seed, OR_TAG_SET, t, (uint64_t)b, (uint32_t)res, w);
-    const uint32_t setw = w[0];
     for (int k = res * per_res; k < (res + 1) * per_res; ++k) {
-        const int s = (int)((setw >> (2 * k)) & 3u);
+        const int s = step_set(w, k);
         for (int ty = 0; ty < nty; ++ty)
             for (int tx = 0; tx < ntx; ++tx) {
                 const uint64_t G = row_group(b, ty, tx, nty, ntx);
@@ -773,7 +852,7 @@ int or_dt_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
                     for (int bx = csx; bx < nbx; bx += 2) {
                         const int b = by * nbx + bx;
                         or_draw(seed, OR_TAG_SET, t, (uint64_t)b, 0, w);
-                        const int s = (int)((w[0] >> (2 * k)) & 3u);
+                        const int s = step_set(w, k);
                         for (int ty = 0; ty < nty; ++ty)
                             for (int tx = 0; tx < ntx; ++tx) {
                                 const uint64_t G = row_group(b, ty, tx, nty, ntx);
