@@ -172,7 +172,8 @@ def test_dd_step_attempts_never_neighbours(oracle_lib, L, block, tile):
 
 def test_dd_invalid_shapes_rejected(oracle_lib):
     s = oracle_lib.SlopeState(32)
-    for block, tile in [((12, 32), (4, 4)), ((32, 32), (8, 8)), ((32, 24), (4, 4)), ((32, 32), (3, 3))]:
+    for block, tile in [((12, 32), (4, 4)), ((32, 32), (16, 16)), ((32, 24), (4, 4)), ((32, 32), (3, 3)),
+                        ((36, 32), (8, 8))]:
         with pytest.raises(RuntimeError):
             s.run_dd(1, 1.0, 0.0, 1, block=block, tile=tile)
 
