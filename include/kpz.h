@@ -154,6 +154,27 @@ kpz_status kpz_sweep(kpz_sim *sim, int32_t n_mcs);
  * surface for the recorded number of flips. */
 kpz_status kpz_roughness(kpz_sim *sim, int64_t *S1, int64_t *S2, double *W2);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): the exact
+ * moments of kpz_roughness for a lattice given by its words alone, with the
+ * row sums and results in a static scratch area of the library instead of a
+ * caller-owned workspace.  Nothing is allocated; the scratch area (about
+ * 1 MiB) exists once per device and is held until the process ends.
+ *   d_words  L*L/16 uint32 on the current device in the documented layout
+ *            (for a two-buffer kpz_sim call kpz_sync_words first)
+ *   L        16 <= L <= KPZ_NOALLOC_MAX_L, L % 16 == 0
+ *   net      deposits minus desorptions since the flat start (kpz_get_state)
+ *   stream   hipStream_t the work is enqueued on; synchronised before return
+ * Outputs as for kpz_roughness (any may be NULL).  KPZ_ESIZE if L exceeds
+ * KPZ_NOALLOC_MAX_L, KPZ_EINVAL for a NULL pointer or an invalid L (nothing
+ * enqueued), KPZ_ESTATE if words and net disagree, KPZ_EHIP on a HIP error;
+ * kpz_last_error(NULL) gives the text.  Calls on one device share its
+ * scratch area, which keeps the last call's contents: calls that overlap in
+ * time on the same device race (use one stream, or serialise them). */
+#define KPZ_NOALLOC_MAX_L 65536
+kpz_status kpz_roughness_noalloc(const uint32_t *d_words, int64_t L, int64_t net, int64_t *S1,
+                                 int64_t *S2, double *W2, void *stream);
+
 /* Height distribution to fourth order (the one-point functions of Sec.
  * 2.1): exact sums M_k = sum over sites of (h - h(0,0))^k, k = 1..4, as
  * 128-bit integers in sums[2k-2] (low 64 bits) and sums[2k-1] (high 64

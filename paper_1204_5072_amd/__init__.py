@@ -23,7 +23,7 @@ KPZ_OK, KPZ_EINVAL, KPZ_ESIZE, KPZ_EHIP, KPZ_ESTATE, KPZ_ERANGE = 0, -1, -2, -3,
 
 EXPORTED = ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness", "kpz_height_moments",
             "kpz_get_state", "kpz_set_state", "kpz_sync_words", "kpz_destroy", "kpz_status_str",
-            "kpz_last_error", "kpz_valu_probe",
+            "kpz_last_error", "kpz_valu_probe", "kpz_roughness_noalloc",
             "kpz_batch_sizes", "kpz_batch_init", "kpz_batch_word_offset", "kpz_batch_sweep",
             "kpz_batch_roughness", "kpz_batch_run", "kpz_batch_get_t", "kpz_batch_destroy",
             "kpz_batch_last_error", "kpz_batch_sync_words",
@@ -88,6 +88,8 @@ def lib() -> ctypes.CDLL:
                                c.c_size_t, vp]
         L.kpz_sweep.argtypes = [vp, c.c_int32]
         L.kpz_valu_probe.argtypes = [vp, c.c_int32, c.c_int32, c.POINTER(c.c_int32), vp]
+        L.kpz_roughness_noalloc.argtypes = [vp, c.c_int64, c.c_int64, c.POINTER(c.c_int64),
+                                            c.POINTER(c.c_int64), c.POINTER(c.c_double), vp]
         L.kpz_roughness.argtypes = [vp, c.POINTER(c.c_int64), c.POINTER(c.c_int64),
                                     c.POINTER(c.c_double)]
         L.kpz_height_moments.argtypes = [vp, c.POINTER(c.c_int64), c.POINTER(c.c_double),

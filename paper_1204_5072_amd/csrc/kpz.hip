@@ -50,6 +50,7 @@
 #include <algorithm>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -2015,6 +2016,55 @@ void set_init_error(hipError_t e, const char *what)
 
 }  // namespace
 
+// ------------------------------------------------ no-allocation roughness
+//
+// Scratch of kpz_roughness_noalloc: the results header (WS_HEADER bytes),
+// NSLOTS flip-counter slots (slot 0 = the caller's flip count, the rest 0)
+// and two int64 row sums per row for L up to KPZ_NOALLOC_MAX_L.  One copy per
+// device, held until the process ends.  In host code `scratch` names a
+// host-side stand-in, never a device address: the address on each device
+// comes from hipGetSymbolAddress, looked up once per device with that device
+// current, and only that pointer is passed to kernels.
+namespace {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES =
+    WS_HEADER + sizeof(long long) * NSLOTS + 2 * sizeof(long long) * KPZ_NOALLOC_MAX_L;
+
+__device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES];   // device address of `scratch` per device ordinal
+
+// The current device's scratch address (looked up on the first call on it).
+kpz_status scratch_on_current_device(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_init_error(e, "kpz_roughness_noalloc: hipGetDevice");
+        return KPZ_EHIP;
+    }
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        snprintf(g_init_err, sizeof g_init_err, "kpz_roughness_noalloc: device %d out of range", dev);
+        return KPZ_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_init_error(e, "kpz_roughness_noalloc: hipGetSymbolAddress(scratch)");
+            return KPZ_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return KPZ_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *kpz_status_str(kpz_status s)
@@ -2851,6 +2901,53 @@ kpz_status kpz_valu_probe(uint32_t *d_out, int32_t n_groups, int32_t iters,
     hipLaunchKernelGGL(kpz_valu_probe_kernel, dim3((uint32_t)n_groups), dim3(256), 0,
                        (hipStream_t)stream, d_out, (uint32_t)iters);
     return hipGetLastError() == hipSuccess ? KPZ_OK : KPZ_EHIP;
+}
+
+kpz_status kpz_roughness_noalloc(const uint32_t *d_words, int64_t L, int64_t net, int64_t *S1o,
+                                 int64_t *S2o, double *W2o, void *stream)
+{
+    clear_pending_error();
+    if (!d_words || L < 16 || (L % 16) != 0) return KPZ_EINVAL;
+    if (L > KPZ_NOALLOC_MAX_L) {
+        snprintf(g_init_err, sizeof g_init_err,
+                 "kpz_roughness_noalloc: L = %lld exceeds the scratch maximum %d",
+                 (long long)L, KPZ_NOALLOC_MAX_L);
+        return KPZ_ESIZE;
+    }
+    void *base = nullptr;
+    const kpz_status sst = scratch_on_current_device(&base);
+    if (sst != KPZ_OK) return sst;
+    hipStream_t st = (hipStream_t)stream;
+    long long *res = (long long *)base;
+    long long *slots = (long long *)((uint8_t *)base + WS_HEADER);
+    long long *rowA = slots + NSLOTS, *rowB = rowA + L;
+    const uint32_t Lu = (uint32_t)L, W = Lu / 16;
+    const Rot none = {0u, 0u, 0u, 16u, 0u, 0u};
+    // every slot is rewritten (slot 0 = net) before the moments read them;
+    // the header and row sums are written before they are read
+    hipLaunchKernelGGL(kpz_fill_counters_kernel, dim3(NSLOTS / 256), dim3(256), 0, st, slots,
+                       (long long)net);
+    if (Lu <= SMALL_ROWS) {
+        hipLaunchKernelGGL(kpz_roughness_small_kernel, dim3(1), dim3(1024), 0, st, d_words, Lu, W,
+                           (const long long *)slots, res, none);
+    } else {
+        const uint32_t nt = row_tasks(Lu);
+        const uint32_t rgrid = (nt + 3) / 4 < 4096 ? (nt + 3) / 4 : 4096;
+        hipLaunchKernelGGL(kpz_row_moments_kernel, dim3(rgrid), dim3(256), 0, st, d_words, Lu, W,
+                           rowA, rowB);
+        hipLaunchKernelGGL(kpz_finalize_kernel, dim3(1), dim3(1024), 0, st, Lu,
+                           (const long long *)rowA, (const long long *)rowB,
+                           (const long long *)slots, res, d_words, none);
+    }
+    hipError_t e = hipGetLastError();
+    long long h[4];
+    if (e == hipSuccess) e = hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        set_init_error(e, "kpz_roughness_noalloc");
+        return KPZ_EHIP;
+    }
+    return convert_moments(h, L, S1o, S2o, W2o, g_init_err, sizeof g_init_err);
 }
 
 }  // extern "C"
