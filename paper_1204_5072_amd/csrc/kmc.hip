@@ -47,6 +47,7 @@
 namespace {
 
 using kpzdev::philox;
+using kpzdev::philox_v;
 using kpzdev::U4;
 
 constexpr uint32_t TAG_INIT = 16, TAG_ORIGIN = 18, TAG_ORDER = 19, TAG_SET = 20, TAG_STEP = 21;
@@ -83,27 +84,6 @@ __device__ __forceinline__ uint32_t order_at(uint32_t idx, uint32_t phase)
         f = i < 7 ? f / (7 - i) : 1;
     }
     return v;
-}
-
-// Philox4x32-10 as kpzdev::philox, with each round's two three-way XORs as
-// single v_bitop3_b32 instructions (the step loop is issue-bound).
-__device__ __forceinline__ U4 philox_x3(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                        uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
-        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return U4{c0, c1, c2, c3};
 }
 
 // Components + 1 of the twelve neighbour offsets (numbering of kmc.h), two
@@ -274,12 +254,12 @@ __global__ __launch_bounds__(NTHREADS) void kmc_phase_kernel(PhaseArgs a)
             const uint32_t tx = g % NT, ty = (g / NT) % NT, tz = g / (NT * NT);
             const uint64_t G = (uint64_t)b * TPB + g;
             const int tbase = (int)(((8 * tz + 2) * S + (8 * ty + 2)) * S + 8 * tx + 2);
-            U4 w = philox_x3((uint32_t)G, (uint32_t)(G >> 32), a.t, TAG_STEP << 24, a.seed_lo,
+            U4 w = philox_v((uint32_t)G, (uint32_t)(G >> 32), a.t, TAG_STEP << 24, a.seed_lo,
                              a.seed_hi);
             for (uint32_t kk = 0; kk < STEPS / 2; ++kk) {
                 // draws of the next pair of steps, independent of the lattice:
                 // their arithmetic fills the LDS latency of this pair
-                const U4 wn = philox_x3((uint32_t)G, (uint32_t)(G >> 32), a.t,
+                const U4 wn = philox_v((uint32_t)G, (uint32_t)(G >> 32), a.t,
                                         (TAG_STEP << 24) | (kk + 1), a.seed_lo, a.seed_hi);
                 const uint32_t cw = celltab[kk];
                 mv += attempt<S>(lds, tbase + (int)(cw & 0xFFFFu), par0, w.x, w.y, Ts);
@@ -295,10 +275,10 @@ __global__ __launch_bounds__(NTHREADS) void kmc_phase_kernel(PhaseArgs a)
             const uint64_t G = (uint64_t)b * TPB + g;
             const int tbase = (int)(((8 * tz + 2) * S + (8 * ty + 2)) * S + 8 * tx + 2);
             uint32_t sw = 0;
-            U4 w = philox_x3((uint32_t)G, (uint32_t)(G >> 32), a.t, TAG_STEP << 24, a.seed_lo,
+            U4 w = philox_v((uint32_t)G, (uint32_t)(G >> 32), a.t, TAG_STEP << 24, a.seed_lo,
                              a.seed_hi);
             for (uint32_t kk = 0; kk < STEPS / 2; ++kk) {
-                const U4 wn = philox_x3((uint32_t)G, (uint32_t)(G >> 32), a.t,
+                const U4 wn = philox_v((uint32_t)G, (uint32_t)(G >> 32), a.t,
                                         (TAG_STEP << 24) | (kk + 1), a.seed_lo, a.seed_hi);
 #pragma unroll
                 for (uint32_t h = 0; h < 2; ++h) {

@@ -9,35 +9,33 @@
 // domain set chosen collectively per work-group and step, several domains
 // per work-item).
 //
-// Kernels
-//   kpz_init_kernel         flat start, HBM write stream
-//   kpz_sweep_kernel<K,ACC> one MCS: one wave64 work-group per dead-border
-//                           block; block in LDS; 16 single-hit steps
-//   kpz_row_moments_kernel  per-row (sum, sum of squares) of the x-prefix
-//                           heights, a lane group per row (a wave for long
-//                           rows), HBM read stream
-//   kpz_finalize_kernel     column-0 prefix, 128-bit totals, flip counters,
-//                           one work-group, one pass over the row sums
-//
-// LDS layout of a block in the sweep.  Tiles are 4 x 4 sites, each split
-// into four 2 x 2 cells; cell set s = sx + 2 sy.  A cell is one byte: site
-// (rx, ry) of the cell at bits 2(2 ry + rx) (sigma_x) and +1 (sigma_y).
-// Four tiles of one tile column, (tx, qy + j H) for j = 0..3 with
-// H = nty / 4, share one dword ("quad"), byte j; the LDS holds four planes
-// (one per cell set) of nq = ntx * H quads.  Every bitwise operation of the
-// update therefore serves four tiles at once (the paper's several domains
-// per work-item, realised as SIMD within a 32-bit register), and the 64
-// lanes of a wave read consecutive dwords (no bank conflicts).
+// Kernels (the hot path)
+//   kpz_init_kernel          flat start, HBM write stream
+//   kpz_sweep_kernel         one MCS: one wave64 per dead-border block, the
+//                            block held in registers as bit planes (the
+//                            step code is in kpz_slice.h); 16 single-hit
+//                            steps; two-buffer store rotated by the origin
+//   kpz_row_moments_kernel   per-row (sum, sum of squares) of the x-prefix
+//                            heights, a lane group per row (a wave for long
+//                            rows), HBM read stream
+//   kpz_finalize_kernel      column-0 prefix, 128-bit totals, flip counters,
+//                            one work-group, one pass over the row sums
+// and around it: the in-place merge, device-layer double tiling
+// (kpz_dt_kernel, one launch per block set), the batched ensemble and the
+// job pool (kpz_batch_round_kernel), block residency below one MCS.
 //
 // Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the seed,
-// counter (idx_lo, idx_hi, t, tag << 24 | sub):
-//   origin    (ORIGIN, t, 0, 0):  ox = w0*Bx >> 32, oy = w1*By >> 32
-//   sets      (SET, t, block, 0): step k uses bits 2k..2k+1 of w0
-//   sites     (SITE, t, G, 0):    G = block*nq + quad; tile j of the quad,
-//                                 step k: bits 8j + 2(k&3) of word k>>2
-//   accept    u = A << 24 | (B & 0xFFFFFF), A = byte j of word k&3 of
-//             (ACC1, t, G, k>>2), B = word j of (ACC2, t, G, k); B is
-//             generated only when A alone cannot decide u < threshold.
+// counter (idx_lo, idx_hi, t, tag << 24 | sub).  Tile row ty of block b is
+// cut into row groups of 32 tiles, G = (b nty + ty) nqx + tx / 32, and tile
+// tx owns bit pi(tx) = 8 (tx mod 4) + (tx mod 32) / 4 of every word drawn for
+// its group:
+//   origin  (ORIGIN, t, res): ox = w0 Bx >> 32, oy = w1 By >> 32
+//   sets    (SET, t, b, res): step k takes bits 2k..2k+1 of w0
+//   sites   (SITE, t, G, k/2): rx from word 2 (k mod 2), ry from the next
+//   accept  bit j (most significant first) of the 32-bit uniform: word
+//           k mod 4 of (ACC1, t, G, 4 (k/4) + j) for j < 4, word j mod 4 of
+//           (ACC2, t, G, 8k + j/4 - 1) beyond; the kernel compares bit by
+//           bit and draws the later words only while some tile is undecided.
 
 #include <hip/hip_runtime.h>
 
@@ -61,6 +59,7 @@
 namespace {
 
 using kpzdev::philox;
+using kpzdev::philox_v;
 using kpzdev::U4;
 
 constexpr uint32_t TAG_ORIGIN = 1, TAG_SET = 2, TAG_SITE = 3, TAG_ACC1 = 4, TAG_ACC2 = 5;
@@ -336,7 +335,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
 #pragma unroll
             for (uint32_t j = 0; j < 4; ++j) {
                 if (j < d.nl) {
-                    const U4 v = philox((uint32_t)G, (uint32_t)(G >> 32), a.t,
+                    const U4 v = philox_v((uint32_t)G, (uint32_t)(G >> 32), a.t,
                                         (TAG_ACC1 << 24) | (4u * kq + j), a.seed_lo, a.seed_hi);
                     l1[j][0] = v.x; l1[j][1] = v.y; l1[j][2] = v.z; l1[j][3] = v.w;
                 }
@@ -347,7 +346,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
             const uint32_t k = 4u * kq + kr;
             if (k < k0 || k >= k1) continue;
             if ((kr & 1u) == 0 || k == k0)
-                sw = philox((uint32_t)G, (uint32_t)(G >> 32), a.t, (TAG_SITE << 24) | (k >> 1),
+                sw = philox_v((uint32_t)G, (uint32_t)(G >> 32), a.t, (TAG_SITE << 24) | (k >> 1),
                             a.seed_lo, a.seed_hi);
             const uint32_t RX = (kr & 1u) ? sw.z : sw.x;
             const uint32_t RY = (kr & 1u) ? sw.w : sw.y;

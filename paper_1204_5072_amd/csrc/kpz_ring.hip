@@ -55,6 +55,7 @@ namespace {
 using kpzdev::byte_eq;
 using kpzdev::byte_lt;
 using kpzdev::philox;
+using kpzdev::philox_v;
 using kpzdev::U4;
 
 constexpr uint32_t TAG_ORIGIN1D = 8, TAG_SET1D = 9, TAG_SITE1D = 10, TAG_ACC1D = 11,
@@ -124,7 +125,7 @@ __device__ __forceinline__ void ring_accept(uint32_t A0, uint32_t A1, const Ring
             const uint32_t mm = __builtin_ctz(ties);
             ties &= ties - 1;
             const uint64_t g = tile0 + mm;
-            const U4 c = philox((uint32_t)g, (uint32_t)(g >> 32), a.t, (TAG_ACC1D2 << 24) | k,
+            const U4 c = philox_v((uint32_t)g, (uint32_t)(g >> 32), a.t, (TAG_ACC1D2 << 24) | k,
                                 a.seed_lo, a.seed_hi);
             const uint32_t c24 = c.x & 0xFFFFFFu;
             if (((tp8 >> mm) & 1u) && c24 < ac.lowP) p8 |= 1u << mm;
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(64) void kpz_ring_sweep_kernel(const RingArgs a)
 #pragma unroll
     for (int j = 0; j < K; j += 4) {
         const uint64_t qi = (uint64_t)b * (K / 4) + j / 4;
-        const U4 s4 = philox((uint32_t)qi, (uint32_t)(qi >> 32), a.t, TAG_SITE1D << 24, a.seed_lo,
+        const U4 s4 = philox_v((uint32_t)qi, (uint32_t)(qi >> 32), a.t, TAG_SITE1D << 24, a.seed_lo,
                              a.seed_hi);
         sw[j] = s4.x;
         sw[j + 1] = s4.y;
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(64) void kpz_ring_sweep_kernel(const RingArgs a)
                 if (ACC) {
                     const uint32_t mx = l & ~c[j];
                     const uint64_t ai = (uint64_t)b * (K / 2) + j / 2;
-                    const U4 aw = philox((uint32_t)ai, (uint32_t)(ai >> 32), a.t,
+                    const U4 aw = philox_v((uint32_t)ai, (uint32_t)(ai >> 32), a.t,
                                          (TAG_ACC1D << 24) | k, a.seed_lo, a.seed_hi);
                     const uint32_t A0 = (j & 1) ? aw.z : aw.x;
                     const uint32_t A1 = (j & 1) ? aw.w : aw.y;
