@@ -367,33 +367,44 @@ def kmc_leg(args):
 
 
 def serving_leg(args):
-    """Serving: Poisson stream of jobs (2000 at 50 jobs/s by default), L =
-    2^k with k uniform on 8..13, p = 1, q uniform on [0, 0.5], MCS log-uniform
-    on 10^2..10^4, admitted into a device job pool by HBM budget and run with
-    continuous batching; p50/p99 of arrival -> result latency."""
+    """Serving: a Poisson stream of jobs (2000 at 50 jobs/s by default), L =
+    64 round(2^U / 64) with U uniform on [8, 13], p = 1, q uniform on [0, 0.5],
+    MCS log-uniform on 10^2..10^4, admitted into a device job pool by HBM
+    budget and run with continuous batching; p50/p99 of arrival -> result
+    latency.  A second, shorter stream at a rate above the pool's capacity
+    (`--serve-sat-rate`) reports the saturated latencies beside it."""
     from paper_1204_5072_amd import serve
-    jobs = serve.poisson_jobs(n_jobs=args.serve_jobs, rate=args.serve_rate, seed=0)
-    def progress(done, total, resident):
-        print(f"bench: serving {done}/{total} done, {resident} resident", file=sys.stderr,
-              flush=True)
 
-    kw = {"block": tuple(args.serve_block)} if args.serve_block else {}
-    rep = serve.serve(jobs, hbm_bytes=int(args.serve_hbm_gib * (1 << 30)),
-                      quantum=args.serve_quantum, progress=progress, **kw)
-    return {
-        "metric": "job latency p50/p99 (arrival -> result), serving",
-        "p50_ms": rep.latency_p50_ms,
-        "p99_ms": rep.latency_p99_ms,
-        "max_ms": rep.latency_max_ms,
-        "throughput_attempts_per_s": rep.attempts_per_s,
-        "jobs": rep.jobs,
-        "seconds": rep.seconds,
-        "offered_attempts_per_s": rep.attempts / max(j.arrival for j in jobs),
-        "steps": rep.steps,
-        "max_resident_jobs": rep.max_resident,
-        "hbm_budget_gib": args.serve_hbm_gib,
-        "quantum_mcs": args.serve_quantum,
-    }
+    def run(n_jobs, rate):
+        jobs = serve.poisson_jobs(n_jobs=n_jobs, rate=rate, seed=0)
+
+        def progress(done, total, resident):
+            print(f"bench: serving {done}/{total} done, {resident} resident", file=sys.stderr,
+                  flush=True)
+
+        kw = {"block": tuple(args.serve_block)} if args.serve_block else {}
+        rep = serve.serve(jobs, hbm_bytes=int(args.serve_hbm_gib * (1 << 30)),
+                          quantum=args.serve_quantum, progress=progress, **kw)
+        return {
+            "p50_ms": rep.latency_p50_ms,
+            "p99_ms": rep.latency_p99_ms,
+            "max_ms": rep.latency_max_ms,
+            "throughput_attempts_per_s": rep.attempts_per_s,
+            "jobs": rep.jobs,
+            "rate_jobs_per_s": rate,
+            "seconds": rep.seconds,
+            "offered_attempts_per_s": rep.attempts / max(j.arrival for j in jobs),
+            "steps": rep.steps,
+            "max_resident_jobs": rep.max_resident,
+        }
+
+    out = {"metric": "job latency p50/p99 (arrival -> result), serving",
+           "sizes": "L = 64 round(2^U / 64), U ~ U(8, 13)",
+           "hbm_budget_gib": args.serve_hbm_gib, "quantum_mcs": args.serve_quantum}
+    out.update(run(args.serve_jobs, args.serve_rate))
+    if args.serve_sat_jobs > 0:
+        out["saturated"] = run(args.serve_sat_jobs, args.serve_sat_rate)
+    return out
 
 
 def sweep_counters(block, in_place=False, device_dt=False):
@@ -461,6 +472,8 @@ def main():
     ap.add_argument("--ens-block", type=int, nargs=2, default=None)
     ap.add_argument("--ens-seq-members", type=int, default=32)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-sat-jobs", type=int, default=400)
+    ap.add_argument("--serve-sat-rate", type=float, default=200.0)
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-ring", action="store_true")
     ap.add_argument("--no-kmc", action="store_true")

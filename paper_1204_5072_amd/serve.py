@@ -29,17 +29,27 @@ class Job:
 
 
 def poisson_jobs(n_jobs: int = 2000, rate: float = 50.0, seed: int = 0,
-                 log2L=(8, 13), log10_mcs=(2.0, 4.0), q_max: float = 0.5) -> List[Job]:
-    """Poisson arrivals; L = 2^k with k uniform on the integers of log2L
-    (log-uniform over powers of two); MCS = round(10^U), U uniform on
-    log10_mcs; p = 1, q uniform on [0, q_max]; seed = job number."""
+                 log2L=(8, 13), log10_mcs=(2.0, 4.0), q_max: float = 0.5,
+                 sizes: str = "multiple64") -> List[Job]:
+    """Poisson arrivals (exponential gaps, mean 1/rate); MCS = round(10^U), U
+    uniform on log10_mcs; p = 1, q uniform on [0, q_max]; seed = job number.
+    Lattice sizes, log-uniform between 2^log2L[0] and 2^log2L[1]:
+      "multiple64": L = 64 round(2^U / 64), U uniform on log2L (sizes that
+                    are not powers of two run with the largest power-of-two
+                    blocks dividing them);
+      "pow2":       L = 2^k, k uniform on the integers of log2L."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, size=n_jobs)
     arrivals = np.cumsum(gaps) - gaps[0]
-    ks = rng.integers(log2L[0], log2L[1] + 1, size=n_jobs)
+    if sizes == "pow2":
+        Ls = 2 ** rng.integers(log2L[0], log2L[1] + 1, size=n_jobs)
+    elif sizes == "multiple64":
+        Ls = 64 * np.maximum(1, np.round(2.0 ** rng.uniform(log2L[0], log2L[1], size=n_jobs) / 64))
+    else:
+        raise ValueError(f"unknown size distribution {sizes!r}")
     mcs = np.round(10.0 ** rng.uniform(log10_mcs[0], log10_mcs[1], size=n_jobs)).astype(int)
     qs = rng.uniform(0.0, q_max, size=n_jobs)
-    return [Job(float(arrivals[i]), int(2 ** ks[i]), 1.0, float(qs[i]), i, int(mcs[i]))
+    return [Job(float(arrivals[i]), int(Ls[i]), 1.0, float(qs[i]), i, int(mcs[i]))
             for i in range(n_jobs)]
 
 
