@@ -371,8 +371,8 @@ def serving_leg(args):
     64 round(2^U / 64) with U uniform on [8, 13], p = 1, q uniform on [0, 0.5],
     MCS log-uniform on 10^2..10^4, admitted into a device job pool by HBM
     budget and run with continuous batching; p50/p99 of arrival -> result
-    latency.  A second, shorter stream at a rate above the pool's capacity
-    (`--serve-sat-rate`) reports the saturated latencies beside it."""
+    latency.  Two shorter streams report the latencies at half that rate
+    (below the pool's capacity) and at a rate above it."""
     from paper_1204_5072_amd import serve
 
     def run(n_jobs, rate):
@@ -402,6 +402,8 @@ def serving_leg(args):
            "sizes": "L = 64 round(2^U / 64), U ~ U(8, 13)",
            "hbm_budget_gib": args.serve_hbm_gib, "quantum_mcs": args.serve_quantum}
     out.update(run(args.serve_jobs, args.serve_rate))
+    if args.serve_low_jobs > 0:
+        out["below_saturation"] = run(args.serve_low_jobs, args.serve_low_rate)
     if args.serve_sat_jobs > 0:
         out["saturated"] = run(args.serve_sat_jobs, args.serve_sat_rate)
     return out
@@ -452,8 +454,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--L", type=int, default=65536)
-    ap.add_argument("--block", type=int, nargs=2, default=[256, 128],
-                    help="dead-border block shape (default: the autotuner's choice at L = 2^16)")
+    ap.add_argument("--block", type=int, nargs=2, default=None,
+                    help="block shape (default 256 x 128, the fastest dead-border shape at "
+                         "L = 2^16; 512 x 64 with --device-dt, whose 128-byte block rows "
+                         "halve the cache lines a set's launch shares with idle blocks)")
     ap.add_argument("--mcs-per-step", type=int, default=10)
     ap.add_argument("--p", type=float, default=1.0)
     ap.add_argument("--q", type=float, default=0.0)
@@ -472,6 +476,8 @@ def main():
     ap.add_argument("--ens-block", type=int, nargs=2, default=None)
     ap.add_argument("--ens-seq-members", type=int, default=32)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-low-jobs", type=int, default=500)
+    ap.add_argument("--serve-low-rate", type=float, default=25.0)
     ap.add_argument("--serve-sat-jobs", type=int, default=400)
     ap.add_argument("--serve-sat-rate", type=float, default=200.0)
     ap.add_argument("--no-latency", action="store_true")
@@ -500,7 +506,7 @@ def main():
     import paper_1204_5072_amd as kpz
 
     L, M = args.L, args.mcs_per_step
-    block = tuple(args.block)
+    block = tuple(args.block) if args.block else ((512, 64) if args.device_dt else (256, 128))
     print(f"bench: L={L} block={block} p={args.p} q={args.q} seed={args.seed} "
           f"steps={args.steps} warmup={args.warmup} mcs/step={M}", file=sys.stderr, flush=True)
     sim = kpz.Sim(L, args.p, args.q, args.seed, block, moves=args.moves, in_place=args.in_place,

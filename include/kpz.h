@@ -71,12 +71,16 @@ typedef enum {
  *            (p = 1 -> 2^32) against 32-bit uniforms.
  *   seed     64-bit Philox4x32-10 key.
  *   block_x, block_y
- *            dead-border block shape of the device layer (Sec. 3): powers
- *            of two dividing L, 16 <= block_x <= 1024, 16 <= block_y,
- *            block_x * block_y <= 65536.  0 = library default (the
- *            largest power of two <= 256 dividing L, per direction).  A
- *            direction with a single block has no dead border (the block is
- *            periodic).
+ *            dead-border block shape of the device layer (Sec. 3), sites;
+ *            both divide L.  block_x: a multiple of 16 (whole words per
+ *            row), at most 128 or a multiple of 128, at most 512; block_y:
+ *            a multiple of 4 (whole tiles); (block_x / 128, at least 1) x
+ *            block_y / 4 <= 64 (one wave per block, one lane per row group
+ *            of 32 tiles and tile row).  0 = library default: for L a
+ *            multiple of 128 the largest power of two <= 256 (x) and <= 128
+ *            (y) dividing L; otherwise the valid shape dividing L with the
+ *            most sites, then the widest.  A direction with a single block
+ *            has no dead border (the block is periodic).
  *   tile_x, tile_y
  *            double-tiling tile shape of the work-group layer (Sec. 3.1);
  *            must be 4 x 4 (four 2 x 2 cells per tile, 16 single-hit steps
@@ -127,6 +131,12 @@ typedef struct kpz_sim kpz_sim;
 /* Bytes of device workspace a simulation with these parameters needs.
  * Returns KPZ_EINVAL for invalid parameters. */
 kpz_status kpz_workspace_bytes(const kpz_params *params, size_t *ws_bytes);
+
+/* The dead-border block shape (Sec. 3) a simulation with these parameters
+ * runs, after defaults: *block_x, *block_y in sites.  The shape is part of
+ * the dynamics (it fixes the decomposition), so a caller that replays a run
+ * elsewhere records it.  Host only; KPZ_EINVAL for invalid parameters. */
+kpz_status kpz_block_shape(const kpz_params *params, int32_t *block_x, int32_t *block_y);
 
 /* Creates a handle and enqueues the flat initial state (Sec. 2.1: heights
  * h(x,y) = (x + y) mod 2, i.e. even rows 0x33333333 and odd rows
@@ -215,9 +225,8 @@ const char *kpz_last_error(const kpz_sim *sim);
  *
  * Ensemble averages of W^2(t) need hundreds of independent realisations.  A
  * batch holds n members, each a full simulation as above with its own L, p,
- * q and seed; all members share one block shape (block_x, block_y, resolved
- * as for a single lattice from the smallest L when 0), the 4 x 4 tile and
- * `moves`.
+ * q, seed and block shape (block_x, block_y; 0 = the default for its L),
+ * and all share the 4 x 4 tile and `moves`.
  * Every member's results are bit-identical to a single-lattice run with the
  * same parameters and block shape.  Each MCS of a kpz_batch_sweep is one
  * launch over the blocks of all members plus one launch that merges their
@@ -292,9 +301,10 @@ const char *kpz_batch_last_error(const kpz_batch *batch);
  * than k MCS left in this step (plus the merge of their straddling words);
  * jobs submitted between steps join the next one, so new work overlaps
  * running work on the device.  A job's result is bit-identical whatever
- * else runs with it.  All jobs of a pool share the pool's block shape
- * (block_x, block_y must divide every L) and move the origin once per MCS
- * (moves 0 or 1).
+ * else runs with it.  With the pool's block_x, block_y set, every job runs
+ * that shape (it must divide the job's L); with both 0 each job runs its own
+ * block_x, block_y or, where those are 0, the default shape for its L.  Jobs
+ * move the origin once per MCS (moves 0 or 1).
  */
 typedef struct kpz_pool kpz_pool;
 

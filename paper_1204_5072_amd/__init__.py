@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(PKG, "libkpz.so")
 
 KPZ_OK, KPZ_EINVAL, KPZ_ESIZE, KPZ_EHIP, KPZ_ESTATE, KPZ_ERANGE = 0, -1, -2, -3, -4, -5
 
-EXPORTED = ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness", "kpz_height_moments",
+EXPORTED = ("kpz_workspace_bytes", "kpz_block_shape", "kpz_init", "kpz_sweep", "kpz_roughness", "kpz_height_moments",
             "kpz_get_state", "kpz_set_state", "kpz_sync_words", "kpz_destroy", "kpz_status_str",
             "kpz_last_error", "kpz_valu_probe", "kpz_roughness_noalloc",
             "kpz_batch_sizes", "kpz_batch_init", "kpz_batch_word_offset", "kpz_batch_sweep",
@@ -84,6 +84,8 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(LIB_PATH)
         vp, c = ctypes.c_void_p, ctypes
         L.kpz_workspace_bytes.argtypes = [c.POINTER(kpz_params), c.POINTER(c.c_size_t)]
+        L.kpz_block_shape.argtypes = [c.POINTER(kpz_params), c.POINTER(c.c_int32),
+                                      c.POINTER(c.c_int32)]
         L.kpz_init.argtypes = [c.POINTER(vp), c.POINTER(kpz_params), vp, c.c_size_t, vp,
                                c.c_size_t, vp]
         L.kpz_sweep.argtypes = [vp, c.c_int32]
@@ -193,6 +195,15 @@ def workspace_bytes(params: kpz_params) -> int:
     if st != KPZ_OK:
         raise KPZError(st, "kpz_workspace_bytes")
     return n.value
+
+
+def block_shape(params: kpz_params) -> Tuple[int, int]:
+    """The block shape (sites) these parameters run with, defaults resolved."""
+    bx, by = ctypes.c_int32(), ctypes.c_int32()
+    st = lib().kpz_block_shape(ctypes.byref(params), ctypes.byref(bx), ctypes.byref(by))
+    if st != KPZ_OK:
+        raise KPZError(st, "kpz_block_shape")
+    return bx.value, by.value
 
 
 @dataclass

@@ -50,6 +50,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "kpz.h"
@@ -105,7 +106,7 @@ struct SweepArgs {
     uint32_t nw;                 // words per block row (Bx / 16)
     uint32_t nqx;                // row groups per tile row (Bx / 128, at least 1)
     uint32_t ntg, nwg;           // tiles and lattice words per row group
-    uint32_t nty, log2nty;       // tile rows per block (By / 4)
+    uint32_t nty, mnty;          // tile rows per block (By / 4); ceil(2^16 / nty)
     uint32_t seed_lo, seed_hi;
     uint32_t t;
     uint32_t res;                // residency of MCS t (origin move), 0 .. moves - 1
@@ -152,24 +153,27 @@ __device__ __forceinline__ uint32_t wrap_add(uint32_t i, uint32_t d, uint32_t W)
     return j >= W ? j - W : j;
 }
 
-// The nwg (1, 2, 4 or 8) lattice words of a row group whose first site is
-// bit sh2 of storage word gw of row `row`, realigned so that A[i] holds the
-// group's sites 16 i .. 16 i + 15; A[i] = 0 for i >= nwg.  w0: storage word
-// gw itself.  VEC (W % 4 == 0): three 16-byte loads of the aligned words
-// around the group, the funnel shift chosen by gw mod 4 (uniform).
+// The nwg (1 .. 8) lattice words of a row group whose first site is bit sh2
+// of storage word gw of row `row`, realigned so that A[i] holds the group's
+// sites 16 i .. 16 i + 15; A[i] = 0 for i >= nwg.  R[i], i <= nwg: storage
+// word gw + i as loaded (the words the group shares with its neighbours are
+// R[0] and R[nwg]).  VEC (W % 4 == 0): three 16-byte loads of the aligned
+// words around the group, the funnel shift chosen by gw mod 4 (uniform).
 template <int O>
 __device__ __forceinline__ void funnel8(const uint32_t (&v)[12], uint32_t sh2, uint32_t nwg,
-                                        uint32_t (&A)[8])
+                                        uint32_t (&A)[8], uint32_t (&R)[9])
 {
 #pragma unroll
     for (int i = 0; i < 8; ++i)
         A[i] = (uint32_t)i < nwg ? __builtin_amdgcn_alignbit(v[O + i + 1], v[O + i], sh2) : 0u;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) R[i] = v[O + i];
 }
 
 template <bool VEC>
 __device__ __forceinline__ void load_group(const uint32_t *row, uint32_t gw, uint32_t W,
                                            uint32_t nwg, uint32_t sh2, uint32_t (&A)[8],
-                                           uint32_t &w0)
+                                           uint32_t (&R)[9])
 {
     if constexpr (VEC) {
         const uint32_t o = __builtin_amdgcn_readfirstlane(gw & 3u);
@@ -187,20 +191,28 @@ __device__ __forceinline__ void load_group(const uint32_t *row, uint32_t gw, uin
             v[4 * m] = x.x; v[4 * m + 1] = x.y; v[4 * m + 2] = x.z; v[4 * m + 3] = x.w;
         }
         switch (o) {
-        case 0: funnel8<0>(v, sh2, nwg, A); w0 = v[0]; break;
-        case 1: funnel8<1>(v, sh2, nwg, A); w0 = v[1]; break;
-        case 2: funnel8<2>(v, sh2, nwg, A); w0 = v[2]; break;
-        default: funnel8<3>(v, sh2, nwg, A); w0 = v[3]; break;
+        case 0: funnel8<0>(v, sh2, nwg, A, R); break;
+        case 1: funnel8<1>(v, sh2, nwg, A, R); break;
+        case 2: funnel8<2>(v, sh2, nwg, A, R); break;
+        default: funnel8<3>(v, sh2, nwg, A, R); break;
         }
     } else {
-        uint32_t v[9];
 #pragma unroll
-        for (uint32_t i = 0; i < 9; ++i) v[i] = i <= nwg ? row[wrap_add(gw, i, W)] : 0u;
+        for (uint32_t i = 0; i < 9; ++i) R[i] = i <= nwg ? row[wrap_add(gw, i, W)] : 0u;
 #pragma unroll
         for (uint32_t i = 0; i < 8; ++i)
-            A[i] = i < nwg ? __builtin_amdgcn_alignbit(v[i + 1], v[i], sh2) : 0u;
-        w0 = v[0];
+            A[i] = i < nwg ? __builtin_amdgcn_alignbit(R[i + 1], R[i], sh2) : 0u;
     }
+}
+
+// R[n] for a runtime n <= 8.
+__device__ __forceinline__ uint32_t pick9(const uint32_t (&R)[9], uint32_t n)
+{
+    uint32_t v = R[0];
+#pragma unroll
+    for (uint32_t i = 1; i < 9; ++i)
+        if (i == n) v = R[i];
+    return v;
 }
 
 // One MCS residency of dead-border block b (DT: block b of a double-tiling
@@ -234,21 +246,30 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
     const uint32_t sh2 = 2u * (px0 & 15u);
     const uint32_t gw0 = px0 >> 4;
 
-    const uint32_t q = lane >> a.log2nty, ty = lane & (a.nty - 1u);
+    // lane = q nty + ty: q = floor(lane / nty) = lane ceil(2^16 / nty) >> 16
+    // for lane < 64 and nty <= 64 (the error lane / 2^16 stays below 1 / nty)
+    const uint32_t q = __umul24(lane, a.mnty) >> 16, ty = lane - __umul24(q, a.nty);
     const bool active = q < a.nqx;
     const uint32_t qw = active ? q * a.nwg : 0u;
     const uint32_t gwq = wrap_add(gw0, qw, a.W);   // storage word of the group's first site
 
-    // ---- load: four rows of the group, transposed into planes
+    // ---- load: four rows of the group, transposed into planes.  DT keeps
+    // the words the block shares with its idle neighbours as loaded: their
+    // neighbours' bits do not change during the launch, so the store merges
+    // into these copies instead of reading the words again.
     uint32_t X[4][4], Y[4][4];
-    uint32_t w0r[4];
+    uint32_t w0r[4], wnr[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         uint32_t A[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
         w0r[r] = 0u;
+        wnr[r] = 0u;
         if (active) {
             const uint32_t gy = wrap_add(gy0, 4u * ty + r, a.L);
-            load_group<VEC>(a.src + (size_t)gy * a.W, gwq, a.W, a.nwg, sh2, A, w0r[r]);
+            uint32_t R[9];
+            load_group<VEC>(a.src + (size_t)gy * a.W, gwq, a.W, a.nwg, sh2, A, R);
+            w0r[r] = R[0];
+            if (DT) wnr[r] = pick9(R, a.nwg);
         }
         transpose8(A);
 #pragma unroll
@@ -258,9 +279,12 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
         }
     }
     // DT halos: sigma_x of the column left of the block (lanes of group 0,
-    // bit r = row r of the tile row) and sigma_y of the row below it (lanes of
-    // tile row 0, as planes)
+    // bit r = row r of the tile row; with sh2 = 0 it lies in the word before
+    // the block, kept in hw) and sigma_y of the row below it (lanes of tile
+    // row 0, as planes; its words as loaded in hr)
     uint32_t hx = 0u, hy[4] = {0u, 0u, 0u, 0u};
+    uint32_t hw[4] = {0u, 0u, 0u, 0u};
+    uint32_t hr[9] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
     if constexpr (DT) {
         if (active && q == 0) {
 #pragma unroll
@@ -269,6 +293,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
                 if (sh2 == 0) {
                     const uint32_t gy = wrap_add(gy0, 4u * ty + r, a.L);
                     wl = a.src[(size_t)gy * a.W + (gw0 == 0 ? a.W - 1 : gw0 - 1)];
+                    hw[r] = wl;
                 }
                 const uint32_t bit = sh2 ? sh2 - 2u : 30u;
                 hx |= ((wl >> bit) & 1u) << r;
@@ -276,9 +301,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
         }
         if (active && ty == 0) {
             uint32_t A[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-            uint32_t wdummy;
             const uint32_t gy = gy0 == 0 ? a.L - 1 : gy0 - 1;
-            load_group<VEC>(a.src + (size_t)gy * a.W, gwq, a.W, a.nwg, sh2, A, wdummy);
+            load_group<VEC>(a.src + (size_t)gy * a.W, gwq, a.W, a.nwg, sh2, A, hr);
             transpose8(A);
 #pragma unroll
             for (int c = 0; c < 4; ++c) hy[c] = A[2 * c + 1];
@@ -424,10 +448,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
                 if (i < a.nwg) row[wrap_add(gwq, i, a.W)] = A[i];
             if (DT && q == 0) {
                 // halo column in the previous word, bit 30
-                uint32_t *wp = row + (gw0 == 0 ? a.W - 1 : gw0 - 1);
-                const uint32_t w = *wp;
+                const uint32_t w = hw[r];
                 const uint32_t nwv = (w & ~(1u << 30)) | (((hx >> r) & 1u) << 30);
-                if (nwv != w) *wp = nwv;
+                if (nwv != w) row[gw0 == 0 ? a.W - 1 : gw0 - 1] = nwv;
             }
             continue;
         }
@@ -439,15 +462,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
             row[gwq] = __builtin_amdgcn_alignbit(A[0], prevLast, 32u - sh2);
         } else if (DT) {
             const uint32_t hb = sh2 - 2u;
-            const uint32_t w = row[gwq];
-            row[gwq] = (w & lowm & ~(1u << hb)) | (((hx >> r) & 1u) << hb) | (A[0] << sh2);
+            row[gwq] = (w0r[r] & lowm & ~(1u << hb)) | (((hx >> r) & 1u) << hb) | (A[0] << sh2);
         } else {
             a.side[(size_t)gy * a.nbx + bx] = A[0] << sh2;
         }
         if (q + 1 == a.nqx) {
             if (DT) {
-                uint32_t *wp = row + wrap_add(gwq, a.nwg, a.W);
-                *wp = (*wp & ~lowm) | (lastA >> (32u - sh2));
+                row[wrap_add(gwq, a.nwg, a.W)] = (wnr[r] & ~lowm) | (lastA >> (32u - sh2));
             } else {
                 a.side[((size_t)a.L + gy) * a.nbx + bx] = lastA >> (32u - sh2);
             }
@@ -475,26 +496,20 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
             if (sh2 == 0) {
 #pragma unroll
                 for (uint32_t i = 0; i < 8; ++i)
-                    if (i < a.nwg) {
-                        uint32_t *wp = row + wrap_add(gwq, i, a.W);
-                        *wp = (*wp & ~YM) | B[i];
-                    }
+                    if (i < a.nwg) row[wrap_add(gwq, i, a.W)] = (hr[i] & ~YM) | B[i];
             } else {
 #pragma unroll
                 for (uint32_t i = 1; i < 8; ++i)
-                    if (i < a.nwg) {
-                        uint32_t *wp = row + wrap_add(gwq, i, a.W);
-                        *wp = (*wp & ~YM) | __builtin_amdgcn_alignbit(B[i], B[i - 1], 32u - sh2);
-                    }
-                uint32_t *wp = row + gwq;
+                    if (i < a.nwg)
+                        row[wrap_add(gwq, i, a.W)] =
+                            (hr[i] & ~YM) | __builtin_amdgcn_alignbit(B[i], B[i - 1], 32u - sh2);
                 if (q > 0)
-                    *wp = (*wp & ~YM) | __builtin_amdgcn_alignbit(B[0], prevLastB, 32u - sh2);
+                    row[gwq] = (hr[0] & ~YM) | __builtin_amdgcn_alignbit(B[0], prevLastB, 32u - sh2);
                 else
-                    *wp = (*wp & ~(YM & ~lowm)) | (B[0] << sh2);
-                if (q + 1 == a.nqx) {
-                    uint32_t *we = row + wrap_add(gwq, a.nwg, a.W);
-                    *we = (*we & ~(YM & lowm)) | (lastB >> (32u - sh2));
-                }
+                    row[gwq] = (hr[0] & ~(YM & ~lowm)) | (B[0] << sh2);
+                if (q + 1 == a.nqx)
+                    row[wrap_add(gwq, a.nwg, a.W)] =
+                        (pick9(hr, a.nwg) & ~(YM & lowm)) | (lastB >> (32u - sh2));
             }
         }
     }
@@ -616,8 +631,16 @@ __global__ __launch_bounds__(256) void kpz_dt_kernel(const SweepArgs a, uint32_t
 //
 // A word's 16 sigma_x bits are compacted into two bytes of 8 sites; a
 // 256-entry LDS table gives, for 8 sites with local prefix p_k (k = 0..7),
-// d = p_8, a = sum p_k and c = sum p_k^2.  Each lane takes four consecutive
-// words (one 16-byte load); one wave scan per 256 words places the lanes.
+// d = p_8, a = sum p_k and c = sum p_k^2.  The table is held in LUT_COPIES
+// copies, entry e of copy j at index e LUT_COPIES + j, and lane l reads copy
+// l mod LUT_COPIES: the 64 lookups of a wave then never meet in one bank.
+constexpr uint32_t LUT_COPIES = 32;
+constexpr uint32_t LUT_WORDS = 256 * LUT_COPIES;
+
+// Entry layout: c (0..140) in bits 0..7 with bits 8..12 zero, so the sum of
+// up to 32 entries holds the sum of their c exactly in bits 0..12; d (-8..8)
+// in bits 13..17 and a (-28..28) in bits 18..24, two's complement, one
+// signed field extract each.
 __device__ __forceinline__ uint32_t lut8_entry(uint32_t byte)
 {
     int p = 0, a = 0, c = 0;
@@ -626,29 +649,61 @@ __device__ __forceinline__ uint32_t lut8_entry(uint32_t byte)
         c += p * p;
         p += ((byte >> i) & 1u) ? 1 : -1;
     }
-    // two's complement d (-8..8) in bits 0..4 and a (-28..28) in bits 5..11,
-    // c (0..140) in bits 12..19: one signed or unsigned field extract each
-    return ((uint32_t)p & 31u) | (((uint32_t)a & 127u) << 5) | ((uint32_t)c << 12);
+    return (uint32_t)c | (((uint32_t)p & 31u) << 13) | (((uint32_t)a & 127u) << 18);
 }
 
-struct WordSums {
-    int d, s1, s2;   // increment, sum of prefixes, sum of squared prefixes (16 sites)
+// Fills the replicated table (every thread of the work-group takes part;
+// the caller synchronises before the first lookup).
+__device__ __forceinline__ void fill_row_lut(uint32_t *lut)
+{
+    for (uint32_t i = threadIdx.x; i < 256u; i += blockDim.x) {
+        const uint32_t e = lut8_entry(i);
+        const uint4 v = make_uint4(e, e, e, e);
+#pragma unroll
+        for (uint32_t j = 0; j < LUT_COPIES / 4; ++j)
+            ((uint4 *)(lut + i * LUT_COPIES))[(j + i) & (LUT_COPIES / 4 - 1u)] = v;
+    }
+}
+
+// Running sums of a lane over consecutive words: o = height offset (relative
+// to the lane's first site), s1 = sum of heights, s2 = sum of squared heights
+// without the c terms, csum = sum of the table entries (its bits 0..12 are the
+// sum of the c terms; at most 32 entries between two calls of take_c).
+struct LaneSums {
+    int o, s1, s2;
+    uint32_t csum;
 };
 
-__device__ __forceinline__ WordSums word_sums(uint32_t w, const uint32_t *lut)
+// Eight sites with table entry e: heights o + p_k, k = 0..7.
+__device__ __forceinline__ void add_half(LaneSums &r, uint32_t e)
+{
+    const int d = __builtin_amdgcn_sbfe((int)e, 13, 5);
+    const int a = __builtin_amdgcn_sbfe((int)e, 18, 7);
+    const int t = 8 * r.o + a;                 // sum_k (o + p_k)
+    r.s1 += t;
+    r.s2 += __mul24(r.o, t + a);               // 8 o^2 + 2 o a; + c through csum
+    r.csum += e;
+    r.o += d;
+}
+
+__device__ __forceinline__ void add_word(LaneSums &r, uint32_t w, const uint32_t *lut,
+                                         uint32_t copy)
 {
     uint32_t x = w & 0x55555555u;              // sigma_x of site i at bit 2i
     x = (x | (x >> 1)) & 0x33333333u;
     x = (x | (x >> 2)) & 0x0F0F0F0Fu;
-    x = (x | (x >> 4)) & 0x00FF00FFu;          // sites 0..7 in byte 0, 8..15 in byte 2
-    const uint32_t e0 = lut[x & 0xFFu], e1 = lut[(x >> 16) & 0xFFu];
-    const int d0 = (int)(e0 << 27) >> 27, a0 = (int)(e0 << 20) >> 25, c0 = (int)(e0 >> 12);
-    const int d1 = (int)(e1 << 27) >> 27, a1 = (int)(e1 << 20) >> 25, c1 = (int)(e1 >> 12);
-    WordSums r;
-    r.d = d0 + d1;
-    r.s1 = a0 + 8 * d0 + a1;
-    r.s2 = c0 + 8 * d0 * d0 + 2 * d0 * a1 + c1;
-    return r;
+    x = x | (x >> 4);                          // sites 0..7 in bits 0..7, 8..15 in 16..23
+    const uint32_t e0 = lut[((x & 0xFFu) * LUT_COPIES) | copy];
+    const uint32_t e1 = lut[(((x >> 16) & 0xFFu) * LUT_COPIES) | copy];
+    add_half(r, e0);
+    add_half(r, e1);
+}
+
+// Moves the c terms accumulated in csum into s2.
+__device__ __forceinline__ void take_c(LaneSums &r)
+{
+    r.s2 += (int)(r.csum & 0x1FFFu);
+    r.csum = 0u;
 }
 
 // Lanes per row (a power of two, for the width of the group shuffles): a
@@ -693,54 +748,59 @@ __device__ __forceinline__ int wave_incl_sum(int x)
 // the reference column and shifts the totals to h(0, 0).  A lane's local
 // sums stay below 2^24 and heights within a row below L, so they are
 // 32-bit; only the row totals are 64-bit.
+// Words idx .. idx + NV - 1 of a row of W words (zero beyond W); *nv = how
+// many lie in the row.
+template <int NV>
+__device__ __forceinline__ void row_chunk(const uint32_t *rp, uint32_t W, uint32_t idx,
+                                          uint32_t (&v)[NV], int &nv)
+{
+    nv = 0;
+    if (NV == 16) {
+#pragma unroll
+        for (int j = 0; j < NV / 4; ++j) {
+            const uint4 q = *(const uint4 *)(rp + idx + 4 * j);
+            v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
+        }
+        nv = NV;
+    } else {
+#pragma unroll
+        for (int m = 0; m < NV; ++m) v[m] = 0u;
+        if ((W & 3u) == 0) {
+            if (idx < W) {
+                const uint4 q = *(const uint4 *)(rp + idx);
+                v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+                nv = 4;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                if (idx + m < W) { v[m] = rp[idx + m]; nv = m + 1; }
+        }
+    }
+}
+
 template <int NV>
 __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, const uint32_t *lut,
                                             uint32_t gl, uint32_t G, long long &A, long long &B,
                                             uint32_t &first)
 {
     static_assert(NV == 4 || NV == 16, "four or sixteen words per lane");
-    const bool vec = (W & 3u) == 0;
+    const uint32_t copy = threadIdx.x & (LUT_COPIES - 1u);   // work-groups of whole waves
     long long s1 = 0, s2 = 0;
     int carry = 0;
     first = 0u;
     for (uint32_t base = 0; base < W; base += NV * G) {
-        const uint32_t idx = base + NV * gl;
         uint32_t v[NV];
-        int nv = 0;
-        if (NV == 16) {
-#pragma unroll
-            for (int j = 0; j < NV / 4; ++j) {
-                const uint4 q = *(const uint4 *)(rp + idx + 4 * j);
-                v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
-            }
-            nv = NV;
-        } else {
-#pragma unroll
-            for (int m = 0; m < NV; ++m) v[m] = 0u;
-            if (vec) {
-                if (idx < W) {
-                    const uint4 q = *(const uint4 *)(rp + idx);
-                    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-                    nv = 4;
-                }
-            } else {
-#pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    if (idx + m < W) { v[m] = rp[idx + m]; nv = m + 1; }
-            }
-        }
+        int nv;
+        row_chunk<NV>(rp, W, base + NV * gl, v, nv);
         if (base == 0) first = v[0];
         // this lane's words relative to its own start
-        int o = 0, l1 = 0, l2 = 0;
+        LaneSums ls = {0, 0, 0, 0u};
 #pragma unroll
-        for (int m = 0; m < NV; ++m) {
-            if (NV == 16 || m < nv) {
-                const WordSums ws = word_sums(v[m], lut);
-                l1 += 16 * o + ws.s1;
-                l2 += 16 * o * o + 2 * o * ws.s1 + ws.s2;
-                o += ws.d;
-            }
-        }
+        for (int m = 0; m < NV; ++m)
+            if (NV == 16 || m < nv) add_word(ls, v[m], lut, copy);
+        take_c(ls);
+        const int o = ls.o, l1 = ls.s1, l2 = ls.s2;
         // lane offsets within the chunk: exclusive scan of o over the group
         int incl, total;
         if (G == 64u) {
@@ -772,8 +832,8 @@ __global__ __launch_bounds__(256) void kpz_row_moments_kernel(const uint32_t *wo
                                                               uint32_t W, long long *rowA,
                                                               long long *rowB)
 {
-    __shared__ uint32_t lut[256];
-    lut[threadIdx.x] = lut8_entry(threadIdx.x);
+    __shared__ uint32_t lut[LUT_WORDS];
+    fill_row_lut(lut);
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -956,9 +1016,9 @@ __global__ __launch_bounds__(1024) void kpz_roughness_small_kernel(const uint32_
                                                                    const long long *slots,
                                                                    long long *res, const Rot rot)
 {
-    __shared__ uint32_t lut[256];
+    __shared__ uint32_t lut[LUT_WORDS];
     __shared__ long long rA[SMALL_ROWS], rB[SMALL_ROWS];
-    if (threadIdx.x < 256) lut[threadIdx.x] = lut8_entry(threadIdx.x);
+    fill_row_lut(lut);
     __syncthreads();
     small_rows(words, L, W, lut, rA, rB);
     __syncthreads();
@@ -1397,8 +1457,8 @@ __global__ void kpz_batch_settle_kernel(SweepArgs *members, uint32_t n)
 __global__ __launch_bounds__(256) void kpz_batch_rows_kernel(const MemberRows *mr,
                                                              const uint32_t *tprefix, uint32_t n)
 {
-    __shared__ uint32_t lut[256];
-    lut[threadIdx.x] = lut8_entry(threadIdx.x);
+    __shared__ uint32_t lut[LUT_WORDS];
+    fill_row_lut(lut);
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1438,9 +1498,9 @@ __global__ __launch_bounds__(1024) void kpz_batch_moments_small_kernel(const Mem
                                                                        uint32_t n, uint32_t nslots,
                                                                        long long *res, uint32_t k)
 {
-    __shared__ uint32_t lut[256];
+    __shared__ uint32_t lut[LUT_WORDS];
     __shared__ long long rA[SMALL_ROWS], rB[SMALL_ROWS];
-    if (threadIdx.x < 256) lut[threadIdx.x] = lut8_entry(threadIdx.x);
+    fill_row_lut(lut);
     __syncthreads();
     const uint32_t r = blockIdx.x;
     const MemberRows m = mr[r];
@@ -1507,6 +1567,47 @@ uint64_t threshold(double prob)
     return (uint64_t)(prob * 4294967296.0);
 }
 
+// A block shape the sweep takes: whole words per row (Bx a multiple of 16),
+// whole tiles (By a multiple of 4), a row of at most 32 tiles or of whole row
+// groups of 32 tiles (Bx <= 128 or a multiple of 128, at most 512), and at
+// most 64 (row group, tile row) pairs, one per lane of the block's wave.
+bool block_ok(int64_t bx, int64_t by)
+{
+    if (bx < 16 || bx > 512 || bx % 16 || by < TILE || by % TILE) return false;
+    if (bx > (int64_t)GROUP_SITES && bx % GROUP_SITES) return false;
+    const int64_t lanes = (bx > (int64_t)GROUP_SITES ? bx / GROUP_SITES : 1) * (by / TILE);
+    return lanes <= 64;
+}
+
+// Default block shape for L.  L a multiple of 128: Bx the largest power of
+// two <= 256 dividing L, By the largest <= 128 (one full wave per block where
+// L allows: two row groups of 128 sites in 32 tile rows; the fastest of the
+// full shapes at L = 65536).  Other L (multiples of 16): the valid shape
+// dividing L with the most tiles per wave, then the widest.
+std::pair<int64_t, int64_t> default_block(int64_t L)
+{
+    if (L % 128 == 0) {
+        int64_t dx = 256, dy = 128;
+        while (L % dx) dx >>= 1;
+        while (L % dy) dy >>= 1;
+        return {dx, dy};
+    }
+    int64_t best_x = 16, best_y = TILE, best_area = 0;
+    for (int64_t bx = 16; bx <= 512 && bx <= L; bx += 16) {
+        if (L % bx) continue;
+        for (int64_t by = TILE; by <= L && by <= 64 * TILE; by += TILE) {
+            if (L % by || !block_ok(bx, by)) continue;
+            const int64_t area = bx * by;
+            if (area > best_area || (area == best_area && bx > best_x)) {
+                best_area = area;
+                best_x = bx;
+                best_y = by;
+            }
+        }
+    }
+    return {best_x, best_y};
+}
+
 // Resolves defaults and validates; fills block shape.
 kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
 {
@@ -1520,20 +1621,9 @@ kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
     const int tx = p->tile_x ? p->tile_x : TILE, ty = p->tile_y ? p->tile_y : TILE;
     if (tx != TILE || ty != TILE) return KPZ_EINVAL;
     const int64_t L = p->L;
-    // default: Bx the largest power of two <= 256 dividing L, By the largest
-    // <= 128 (one full wave per block where L allows: two row groups of 128
-    // sites in 32 tile rows; the fastest of the full shapes at L = 65536)
-    int64_t dx = 256, dy = 128;
-    while (L % dx) dx >>= 1;
-    while (L % dy) dy >>= 1;
-    const int64_t bx = p->block_x ? p->block_x : dx;
-    const int64_t by = p->block_y ? p->block_y : dy;
-    if (!is_pow2(bx) || !is_pow2(by)) return KPZ_EINVAL;
-    // one wave per block: Bx >= 16 (whole words), row groups of 128 sites,
-    // at most 64 lanes of (row group, tile row)
-    if (bx < 16 || by < TILE || bx > 512) return KPZ_EINVAL;
-    const int64_t lanes = (bx > GROUP_SITES ? bx / GROUP_SITES : 1) * (by / TILE);
-    if (lanes > 64) return KPZ_EINVAL;
+    const int64_t bx = p->block_x ? p->block_x : default_block(L).first;
+    const int64_t by = p->block_y ? p->block_y : default_block(L).second;
+    if (!block_ok(bx, by)) return KPZ_EINVAL;
     if (L % bx || L % by) return KPZ_EINVAL;
     if (p->flags & KPZ_FLAG_DEVICE_DT) {
         // four block sets need an even number of blocks along both axes
@@ -1600,7 +1690,7 @@ void set_shape(SweepArgs &a, uint32_t L, uint32_t Bx, uint32_t By)
     a.ntg = (Bx > GROUP_SITES ? GROUP_SITES : Bx) / TILE;
     a.nwg = a.ntg / 4;
     a.nty = By / TILE;
-    a.log2nty = (uint32_t)ilog2(a.nty);
+    a.mnty = (65536u + a.nty - 1u) / a.nty;
 }
 
 // Waves (blocks) per work-group: four when the block count allows;
@@ -2088,6 +2178,17 @@ kpz_status kpz_workspace_bytes(const kpz_params *p, size_t *bytes)
     if (st != KPZ_OK) return st;
     if (!bytes) return KPZ_EINVAL;
     *bytes = ws_needed(p->L, bx, p->flags);
+    return KPZ_OK;
+}
+
+kpz_status kpz_block_shape(const kpz_params *p, int32_t *block_x, int32_t *block_y)
+{
+    uint32_t bx, by;
+    const kpz_status st = resolve(p, &bx, &by);
+    if (st != KPZ_OK) return st;
+    if (!block_x || !block_y) return KPZ_EINVAL;
+    *block_x = (int32_t)bx;
+    *block_y = (int32_t)by;
     return KPZ_OK;
 }
 
@@ -2651,8 +2752,7 @@ kpz_status kpz_pool_init(kpz_pool **out, void *d_arena, size_t arena_bytes, int3
     if (bx) {
         // the shape rules of resolve() for a lattice the block fits
         kpz_params t = {};
-        t.L = 1024;
-        while (t.L < bx || t.L < by) t.L *= 2;
+        t.L = bx * by;   // a multiple of both sides and of 16
         t.p = 1.0;
         t.block_x = bx;
         t.block_y = by;

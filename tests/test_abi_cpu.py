@@ -48,10 +48,23 @@ def test_status_strings(kpz):
 
 @pytest.mark.parametrize("L,block", [(16, None), (64, None), (4096, None), (65536, None),
                                      (4096, (256, 64)), (48, (16, 16)), (768, (256, 128)),
-                                     (65536, (512, 64)), (65536, (128, 256)), (64, (64, 4))])
+                                     (65536, (512, 64)), (65536, (128, 256)), (64, (64, 4)),
+                                     (320, (80, 160)), (192, (96, 192)), (384, (384, 16)),
+                                     (960, (96, 240)), (48, (48, 48)), (96, (16, 12))])
 def test_workspace_bytes_valid(kpz, L, block):
     n = kpz.workspace_bytes(kpz.make_params(L, 1.0, 0.0, 1, block))
     assert n >= 256 + 8 * 1024 + 16 * L
+
+
+@pytest.mark.parametrize("L,shape", [
+    (64, (64, 64)), (4096, (256, 128)), (65536, (256, 128)), (2048, (256, 128)),
+    (128, (128, 128)), (1024 + 512, (256, 128)),
+    # not multiples of 128: the valid shape dividing L with the most sites, then the widest
+    (320, (80, 160)), (192, (96, 192)), (448, (112, 224)), (960, (96, 240)), (48, (48, 48)),
+    (576, (96, 192)), (16, (16, 16))])
+def test_default_block_shape(kpz, L, shape):
+    assert kpz.block_shape(kpz.make_params(L, 1.0, 0.0, 1)) == shape
+
 
 
 @pytest.mark.parametrize("kw", [
@@ -60,6 +73,8 @@ def test_workspace_bytes_valid(kpz, L, block):
     dict(L=2048, block=(2048, 16)), dict(L=1024, block=(512, 256)),
     dict(L=1024, block=(256, 256)), dict(L=4096, block=(1024, 16)), dict(L=64, block=(16, 2)),
     dict(L=64, tile=(8, 8)), dict(L=96, block=(64, 32)),
+    dict(L=320, block=(160, 64)), dict(L=96, block=(24, 48)), dict(L=64, block=(16, 6)),
+    dict(L=640, block=(640, 16)), dict(L=384, block=(96, 264)),
     dict(L=64, moves=3), dict(L=64, moves=32), dict(L=64, moves=-1),
 ])
 def test_invalid_params_rejected(kpz, kw):

@@ -136,9 +136,9 @@ def test_batch_members_with_own_block_shapes(gpu, oracle_lib):
     """Each member runs its own block shape (the default for its L when 0)
     in one launch; every member equals its single-lattice run, one equals
     the oracle directly."""
-    shapes = [(128, 256), (512, 64), None, (64, 64), (256, 128), (32, 16)]
-    Ls = [256, 1024, 512, 128, 256, 64]
-    qs = [0.0, 0.25, 0.5, 0.0, 0.7, 0.25]
+    shapes = [(128, 256), (512, 64), None, (64, 64), (256, 128), (32, 16), None, (48, 48)]
+    Ls = [256, 1024, 512, 128, 256, 64, 320, 96]
+    qs = [0.0, 0.25, 0.5, 0.0, 0.7, 0.25, 0.25, 0.0]
     members = [gpu.make_params(L, 1.0, q, 60 + r, shp)
                for r, (L, q, shp) in enumerate(zip(Ls, qs, shapes))]
     ens = gpu.Ensemble(members)

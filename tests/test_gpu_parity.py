@@ -86,6 +86,13 @@ CASES = [
     (64, (32, 32), 0.0, 0.0, 17, 3),          # frozen dynamics
     (64, (32, 32), 0.0, 1.0, 18, 5),          # desorption only
     (256, (64, 64), 1.0, 0.999999, 19, 3),    # threshold just below 2^32: every level drawn
+    # block shapes that are not powers of two (lattice sizes that are not)
+    (320, (80, 160), 1.0, 0.25, 60, 4),       # 5 words per row group, 40 lanes
+    (192, (96, 192), 1.0, 0.0, 61, 4),        # one block along y, 48 lanes
+    (448, (112, 224), 0.7, 0.3, 62, 3),       # 7 words per row group, 56 lanes
+    (384, (384, 16), 1.0, 0.0, 63, 4),        # three row groups per tile row
+    (96, (48, 48), 0.5, 0.5, 64, 4),
+    (960, (96, 240), 1.0, 0.0, 65, 2),        # 60 lanes
 ]
 
 
@@ -134,7 +141,8 @@ def test_sweep_moves_matches_oracle(gpu, oracle_lib, L, block, p, q, seed, n, mo
                                               (256, (256, 64), 0.7, 0.3, 10, 4),
                                               (1024, (512, 64), 1.0, 0.5, 13, 3),
                                               (1024, (256, 128), 1.0, 0.0, 34, 4),
-                                              (96, (32, 32), 0.5, 0.5, 15, 5)])
+                                              (96, (32, 32), 0.5, 0.5, 15, 5),
+                                              (320, (80, 160), 1.0, 0.0, 66, 4)])
 def test_in_place_mode_matches_oracle(gpu, oracle_lib, L, block, p, q, seed, n):
     """The in-place mode (shared words through the side buffer and a merge
     launch) gives the same words and moments as the oracle, and so as the
@@ -182,6 +190,8 @@ DT_CASES = [
     (2048, (256, 128), 1.0, 0.0, 51, 2),     # the benchmark's block shape
     (1024, (512, 32), 1.0, 0.5, 49, 2),
     (512, (256, 16), 0.9, 0.1, 50, 2),
+    (320, (80, 40), 1.0, 0.25, 52, 3),       # block shapes that are not powers of two
+    (768, (384, 64), 1.0, 0.0, 53, 2),       # three row groups per tile row
 ]
 
 
@@ -276,40 +286,57 @@ def _unpack_rows(oracle_lib, rows_words, L):
 
 def test_l65536_sampled_blocks(gpu, oracle_lib):
     """The 2^32-site workload in the launch configuration the benchmark times
-    (256 x 128 blocks, p = 1, q = 0, two-buffer): MCS 2 checked on sampled
-    blocks, including the ones that wrap around the lattice edges, against the
-    oracle's single-block runner; the moments must be consistent."""
+    (256 x 128 blocks, p = 1, q = 0, two-buffer): each of the first 10 MCS
+    checked on sampled blocks, including the ones that wrap around the lattice
+    edges, against the oracle's single-block runner started from the GPU's
+    state of that block; the moments must be consistent after every MCS."""
     import torch
     L, B, p, q, seed = 65536, (256, 128), 1.0, 0.0, 1
-    _log("L=65536 sampled blocks")
     sim = gpu.Sim(L, p, q, seed, B)
-    sim.sweep(2)
-    t = 2
-    origin = oracle_lib.dd_origin(seed, t, B)
     nbx, nby = L // B[0], L // B[1]
-    samples = [(0, 0), (nbx - 1, 0), (0, nby - 1), (nbx - 1, nby - 1), (123, 77),
-               (nbx // 2 + 3, nby // 3)]
     W = L // 16
     words = sim.words.view(L, W)
-    sim.sync_words()   # `words` holds the state only after a sync (two-buffer mode)
-    befores = []
-    for bx, by in samples:
-        rows, cols = oracle_lib.block_region(B, origin, bx, by, L)
+
+    def region(rows, cols):
         r = torch.as_tensor(rows, device=sim.words.device)
         host = words.index_select(0, r).cpu().numpy().view(np.uint32)
-        befores.append(_block_slopes(oracle_lib, host, cols, L))
-    sim.sweep(1)
-    sim.sync_words()
-    for (bx, by), (bsx, bsy) in zip(samples, befores):
-        rows, cols = oracle_lib.block_region(B, origin, bx, by, L)
-        oracle_lib.dd_block_mcs(L, p, q, seed, B, t, bx, by, bsx, bsy)
-        r = torch.as_tensor(rows, device=sim.words.device)
-        host = words.index_select(0, r).cpu().numpy().view(np.uint32)
-        gsx, gsy = _block_slopes(oracle_lib, host, cols, L)
-        assert np.array_equal(gsx, bsx), (bx, by)
-        assert np.array_equal(gsy, bsy), (bx, by)
-    m = sim.roughness()   # raises KPZ_ESTATE if words and flip count disagree
-    assert m.W2 > 0.25
+        return _block_slopes(oracle_lib, host, cols, L)
+
+    for t in range(10):
+        _log(f"L=65536 sampled blocks, MCS {t}")
+        origin = oracle_lib.dd_origin(seed, t, B)
+        samples = [(0, 0), (nbx - 1, 0), (0, nby - 1), (nbx - 1, nby - 1),
+                   ((37 * t + 123) % nbx, (11 * t + 77) % nby), (nbx // 2 + t, nby // 3)]
+        sim.sync_words()   # `words` holds the state only after a sync (two-buffer mode)
+        befores = [region(*oracle_lib.block_region(B, origin, bx, by, L)) for bx, by in samples]
+        sim.sweep(1)
+        sim.sync_words()
+        for (bx, by), (bsx, bsy) in zip(samples, befores):
+            rows, cols = oracle_lib.block_region(B, origin, bx, by, L)
+            oracle_lib.dd_block_mcs(L, p, q, seed, B, t, bx, by, bsx, bsy)
+            gsx, gsy = region(rows, cols)
+            assert np.array_equal(gsx, bsx), (t, bx, by)
+            assert np.array_equal(gsy, bsy), (t, bx, by)
+        m = sim.roughness()   # raises KPZ_ESTATE if words and flip count disagree
+        assert m.W2 > 0.25
+
+
+@pytest.mark.parametrize("p,q", [(1.0, 0.0), (0.5, 0.5)])
+def test_l4096_hundred_mcs(gpu, oracle_lib, p, q):
+    """The 2^24-site workload (L = 4096, seed 1, default 256 x 128 blocks):
+    every word and the exact moments after each of ten calls of 10 MCS,
+    against the oracle's block-parallel runner."""
+    import os
+    L, seed = 4096, 1
+    threads = min(16, os.cpu_count() or 1)
+    sim = gpu.Sim(L, p, q, seed)
+    st = oracle_lib.SlopeState(L)
+    for c in range(10):
+        _log(f"L=4096 p={p} q={q} MCS {10 * c}..{10 * c + 9}")
+        sim.sweep(10)
+        st.run_dd(10, p, q, seed, block=(256, 128), threads=threads)
+        assert np.array_equal(sim.words_host(), oracle_lib.pack(st.sx, st.sy)), c
+        assert_moments(oracle_lib, st, sim.roughness(), L)
 
 
 @pytest.mark.parametrize("block,q", [((128, 256), 0.0), ((512, 64), 0.25), ((256, 64), 0.0)])
