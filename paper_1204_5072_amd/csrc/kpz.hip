@@ -170,6 +170,57 @@ __device__ __forceinline__ void funnel8(const uint32_t (&v)[12], uint32_t sh2, u
     for (int i = 0; i < 9; ++i) R[i] = v[O + i];
 }
 
+// The raw words of a row group: VEC, the three aligned 16-byte units from
+// word gw - (gw mod 4) on (all three always loaded, so the loads of several
+// rows can be issued before the first wait; words beyond the group are
+// neighbours' and unused; W >= 4); otherwise the nwg + 1 words gw .. gw + nwg
+// (nwg + 1 <= W + 1, so one wrap suffices), zero beyond.
+template <bool VEC>
+struct GroupRaw {
+    uint32_t v[12];
+};
+
+template <bool VEC>
+__device__ __forceinline__ void load_raw(const uint32_t *row, uint32_t gw, uint32_t W,
+                                         uint32_t nwg, GroupRaw<VEC> &g)
+{
+    if constexpr (VEC) {
+        const uint32_t g0 = gw - (gw & 3u);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            uint32_t idx = g0 + 4u * m;
+            if (idx >= W) idx -= W;
+            if (idx >= W) idx -= W;
+            const uint4 x = *(const uint4 *)(row + idx);
+            g.v[4 * m] = x.x; g.v[4 * m + 1] = x.y; g.v[4 * m + 2] = x.z; g.v[4 * m + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (uint32_t i = 0; i < 9; ++i) g.v[i] = i <= nwg ? row[wrap_add(gw, i, W)] : 0u;
+#pragma unroll
+        for (uint32_t i = 9; i < 12; ++i) g.v[i] = 0u;
+    }
+}
+
+// Realigns loaded words (see load_raw) into A and R as load_group does.
+template <bool VEC>
+__device__ __forceinline__ void funnel_group(const GroupRaw<VEC> &g, uint32_t gw, uint32_t nwg,
+                                             uint32_t sh2, uint32_t (&A)[8], uint32_t (&R)[9])
+{
+    if constexpr (VEC) {
+        switch (__builtin_amdgcn_readfirstlane(gw & 3u)) {
+        case 0: funnel8<0>(g.v, sh2, nwg, A, R); break;
+        case 1: funnel8<1>(g.v, sh2, nwg, A, R); break;
+        case 2: funnel8<2>(g.v, sh2, nwg, A, R); break;
+        default: funnel8<3>(g.v, sh2, nwg, A, R); break;
+        }
+    } else {
+        funnel8<0>(g.v, sh2, nwg, A, R);
+    }
+}
+
+// load_raw and funnel_group of one row group, with the loads the group does
+// not need skipped.
 template <bool VEC>
 __device__ __forceinline__ void load_group(const uint32_t *row, uint32_t gw, uint32_t W,
                                            uint32_t nwg, uint32_t sh2, uint32_t (&A)[8],
@@ -249,8 +300,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
     // lane = q nty + ty: q = floor(lane / nty) = lane ceil(2^16 / nty) >> 16
     // for lane < 64 and nty <= 64 (the error lane / 2^16 stays below 1 / nty)
     const uint32_t q = __umul24(lane, a.mnty) >> 16, ty = lane - __umul24(q, a.nty);
+    // XN = 1: several row groups per tile row, so every group has 8 words
+    const uint32_t nwg = XN == 1 ? 8u : a.nwg;
     const bool active = q < a.nqx;
-    const uint32_t qw = active ? q * a.nwg : 0u;
+    const uint32_t qw = active ? q * nwg : 0u;
     const uint32_t gwq = wrap_add(gw0, qw, a.W);   // storage word of the group's first site
 
     // ---- load: four rows of the group, transposed into planes.  DT keeps
@@ -259,23 +312,46 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
     // into these copies instead of reading the words again.
     uint32_t X[4][4], Y[4][4];
     uint32_t w0r[4], wnr[4];
+    {
+        // the loads of HR rows at a time are issued before the first is used
+        // (all four in the dead-border sweep; one at a time with DT, whose
+        // halo copies leave no registers for more); idle lanes read the
+        // group 0 words of their tile row's rows
+        constexpr int HR = DT ? 1 : 4;
+        const uint32_t gwl = active ? gwq : gw0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        uint32_t A[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-        w0r[r] = 0u;
-        wnr[r] = 0u;
-        if (active) {
-            const uint32_t gy = wrap_add(gy0, 4u * ty + r, a.L);
-            uint32_t R[9];
-            load_group<VEC>(a.src + (size_t)gy * a.W, gwq, a.W, a.nwg, sh2, A, R);
-            w0r[r] = R[0];
-            if (DT) wnr[r] = pick9(R, a.nwg);
+        for (int r0 = 0; r0 < 4; r0 += HR) {
+        GroupRaw<VEC> g[HR];
+        if (HR > 1) {
+#pragma unroll
+            for (int h = 0; h < HR; ++h) {
+                const uint32_t gy = wrap_add(gy0, 4u * (active ? ty : 0u) + r0 + h, a.L);
+                load_raw<VEC>(a.src + (size_t)gy * a.W, gwl, a.W, nwg, g[h]);
+            }
         }
-        transpose8(A);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            X[r][c] = A[2 * c];
-            Y[r][c] = A[2 * c + 1];
+        for (int h = 0; h < HR; ++h) {
+            const int r = r0 + h;
+            uint32_t A[8], R[9];
+            if (HR > 1) {
+                funnel_group<VEC>(g[h], gwl, nwg, sh2, A, R);
+            } else {
+                const uint32_t gy = wrap_add(gy0, 4u * (active ? ty : 0u) + r, a.L);
+                load_group<VEC>(a.src + (size_t)gy * a.W, gwl, a.W, nwg, sh2, A, R);
+            }
+            w0r[r] = R[0];
+            wnr[r] = DT ? pick9(R, nwg) : 0u;
+            if (!active) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) A[i] = 0u;
+            }
+            transpose8(A);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                X[r][c] = A[2 * c];
+                Y[r][c] = A[2 * c + 1];
+            }
+        }
         }
     }
     // DT halos: sigma_x of the column left of the block (lanes of group 0,
@@ -302,7 +378,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
         if (active && ty == 0) {
             uint32_t A[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
             const uint32_t gy = gy0 == 0 ? a.L - 1 : gy0 - 1;
-            load_group<VEC>(a.src + (size_t)gy * a.W, gwq, a.W, a.nwg, sh2, A, hr);
+            load_group<VEC>(a.src + (size_t)gy * a.W, gwq, a.W, nwg, sh2, A, hr);
             transpose8(A);
 #pragma unroll
             for (int c = 0; c < 4; ++c) hy[c] = A[2 * c + 1];
@@ -407,7 +483,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
     uint32_t gwo = 4u * (ox >> 6) + bx * a.nw;
     if (gwo >= a.W) gwo -= a.W;
     const uint32_t gwoq = wrap_add(gwo, qw, a.W);
-    const bool ovec = VEC && (gwoq & 3u) == 0 && (a.nwg & 3u) == 0;
+    const bool ovec = VEC && (gwoq & 3u) == 0 && (nwg & 3u) == 0;
     const uint32_t lowm = sh2 ? (1u << sh2) - 1u : 0u;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -425,13 +501,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
             if (ovec) {
 #pragma unroll
                 for (uint32_t m = 0; m < 2; ++m)
-                    if (4u * m < a.nwg)
+                    if (4u * m < nwg)
                         *(uint4 *)(row + wrap_add(gwoq, 4u * m, a.W)) =
                             make_uint4(A[4 * m], A[4 * m + 1], A[4 * m + 2], A[4 * m + 3]);
             } else {
 #pragma unroll
                 for (uint32_t i = 0; i < 8; ++i)
-                    if (i < a.nwg) row[wrap_add(gwoq, i, a.W)] = A[i];
+                    if (i < nwg) row[wrap_add(gwoq, i, a.W)] = A[i];
             }
             continue;
         }
@@ -439,13 +515,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
         uint32_t lastA = A[0];
 #pragma unroll
         for (uint32_t i = 1; i < 8; ++i)
-            if (i + 1 == a.nwg) lastA = A[i];
+            if (i + 1 == nwg) lastA = A[i];
         const uint32_t prevLast = bperm(c.srcL4, lastA);
         if (!active) continue;
         if (sh2 == 0) {
 #pragma unroll
             for (uint32_t i = 0; i < 8; ++i)
-                if (i < a.nwg) row[wrap_add(gwq, i, a.W)] = A[i];
+                if (i < nwg) row[wrap_add(gwq, i, a.W)] = A[i];
             if (DT && q == 0) {
                 // halo column in the previous word, bit 30
                 const uint32_t w = hw[r];
@@ -456,7 +532,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
         }
 #pragma unroll
         for (uint32_t i = 1; i < 8; ++i)
-            if (i < a.nwg)
+            if (i < nwg)
                 row[wrap_add(gwq, i, a.W)] = __builtin_amdgcn_alignbit(A[i], A[i - 1], 32u - sh2);
         if (q > 0) {
             row[gwq] = __builtin_amdgcn_alignbit(A[0], prevLast, 32u - sh2);
@@ -468,7 +544,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
         }
         if (q + 1 == a.nqx) {
             if (DT) {
-                row[wrap_add(gwq, a.nwg, a.W)] = (wnr[r] & ~lowm) | (lastA >> (32u - sh2));
+                row[wrap_add(gwq, nwg, a.W)] = (wnr[r] & ~lowm) | (lastA >> (32u - sh2));
             } else {
                 a.side[((size_t)a.L + gy) * a.nbx + bx] = lastA >> (32u - sh2);
             }
@@ -487,7 +563,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
         uint32_t lastB = B[0];
 #pragma unroll
         for (uint32_t i = 1; i < 8; ++i)
-            if (i + 1 == a.nwg) lastB = B[i];
+            if (i + 1 == nwg) lastB = B[i];
         const uint32_t prevLastB = bperm(c.srcL4, lastB);
         if (active && ty == 0) {
             const uint32_t gy = gy0 == 0 ? a.L - 1 : gy0 - 1;
@@ -496,11 +572,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
             if (sh2 == 0) {
 #pragma unroll
                 for (uint32_t i = 0; i < 8; ++i)
-                    if (i < a.nwg) row[wrap_add(gwq, i, a.W)] = (hr[i] & ~YM) | B[i];
+                    if (i < nwg) row[wrap_add(gwq, i, a.W)] = (hr[i] & ~YM) | B[i];
             } else {
 #pragma unroll
                 for (uint32_t i = 1; i < 8; ++i)
-                    if (i < a.nwg)
+                    if (i < nwg)
                         row[wrap_add(gwq, i, a.W)] =
                             (hr[i] & ~YM) | __builtin_amdgcn_alignbit(B[i], B[i - 1], 32u - sh2);
                 if (q > 0)
@@ -508,8 +584,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
                 else
                     row[gwq] = (hr[0] & ~(YM & ~lowm)) | (B[0] << sh2);
                 if (q + 1 == a.nqx)
-                    row[wrap_add(gwq, a.nwg, a.W)] =
-                        (pick9(hr, a.nwg) & ~(YM & lowm)) | (lastB >> (32u - sh2));
+                    row[wrap_add(gwq, nwg, a.W)] =
+                        (pick9(hr, nwg) & ~(YM & lowm)) | (lastB >> (32u - sh2));
             }
         }
     }
@@ -527,9 +603,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
 // with xcd set, group i takes the blocks of virtual group (i mod 8) n/8 +
 // i/8, so each XCD runs one contiguous range of blocks and neighbouring
 // blocks, which share cache lines at their edges, meet in the same L2.
-// XN: the row groups exchange tile 0's left neighbour (several groups per
-// tile row, or one block along x); WY: one block along y (the tile row
-// below tile row 0 wraps around).
+// XN = 1: several row groups per tile row (8 words each), which exchange
+// tile 0's left neighbour; 0: one group per tile row and several blocks along
+// x; 2: decided at run time (one block along x, where tile 0's left
+// neighbour wraps around).  WY: one block along y (the tile row below tile
+// row 0 wraps around); 2 = at run time.
 template <bool ACC, bool VEC, int XN, int WY>
 __global__ __launch_bounds__(256) void kpz_sweep_kernel(const SweepArgs a, uint32_t nblocks)
 {
@@ -1718,9 +1796,12 @@ hipError_t launch_sweep_v(const SweepArgs &a, uint32_t nblocks, hipStream_t st)
 template <bool ACC, bool VEC>
 hipError_t launch_sweep_x(const SweepArgs &a, uint32_t nblocks, hipStream_t st)
 {
-    const bool xn = a.nqx > 1 || a.nbx == 1, wy = a.nby == 1;
-    if (xn) return wy ? launch_sweep_v<ACC, VEC, 1, 1>(a, nblocks, st)
-                      : launch_sweep_v<ACC, VEC, 1, 0>(a, nblocks, st);
+    // XN = 1 only with several row groups per tile row (8 words per group);
+    // a single block along x with one group takes the runtime form
+    const bool wy = a.nby == 1;
+    if (a.nqx > 1) return wy ? launch_sweep_v<ACC, VEC, 1, 1>(a, nblocks, st)
+                             : launch_sweep_v<ACC, VEC, 1, 0>(a, nblocks, st);
+    if (a.nbx == 1) return launch_sweep_v<ACC, VEC, 2, 2>(a, nblocks, st);
     return wy ? launch_sweep_v<ACC, VEC, 0, 1>(a, nblocks, st)
               : launch_sweep_v<ACC, VEC, 0, 0>(a, nblocks, st);
 }
