@@ -5,7 +5,9 @@ free parameter of the method: any valid shape gives a correct decomposed
 schedule, but the shape changes the sequence of updates, so the chosen shape
 is returned and must be recorded with the results (runs are reproducible for
 identical parameters and shape only).  The tuner times each candidate with
-HIP events on the device and keeps the fastest; the launch shape (threads per
+HIP events on the device and keeps the fastest, counting shapes within a few
+per cent of it as ties (the first in a fixed order wins, so that timing noise
+does not change the dynamics between runs); the launch shape (threads per
 block) is chosen by the library and does not affect results.
 """
 from __future__ import annotations
@@ -35,6 +37,20 @@ def valid_shapes(L: int, candidates: Iterable[Tuple[int, int]] = CANDIDATES) -> 
             continue
         out.append((bx, by))
     return out
+
+
+# Shapes whose times lie within this fraction of the fastest count as ties;
+# the first of them in CANDIDATES order is chosen, so that run-to-run timing
+# noise of a few per cent does not change the chosen shape (and with it the
+# dynamics) from one run to the next.
+TIE = 0.03
+
+
+def pick(timings: Dict[Tuple[int, int], float]) -> Tuple[int, int]:
+    """The first shape, in the order of `timings` (candidate order), whose
+    time is within TIE of the fastest."""
+    best = min(timings.values())
+    return next(s for s, t in timings.items() if t <= best * (1.0 + TIE))
 
 
 def _time(fn, reps: int, trials: int = 3) -> float:
@@ -76,8 +92,7 @@ def tune_lattice(L: int, p: float = 1.0, q: float = 0.0, mcs: int = 2,
             print(f"autotune: {shape[0]}x{shape[1]} {timings[shape]:.3f} ms/MCS", flush=True)
     if not timings:
         raise RuntimeError(f"no block shape ran for L={L}: {failed}")
-    best = min(timings, key=timings.get)
-    return {"block": best, "ms_per_mcs": timings, "failed": failed}
+    return {"block": pick(timings), "ms_per_mcs": timings, "failed": failed}
 
 
 def tune_ensemble(members, mcs: int = 4,
@@ -101,7 +116,7 @@ def tune_ensemble(members, mcs: int = 4,
             t[shape] = _time(lambda: ens.sweep(mcs), 1) / mcs
             ens.close()
             del ens
-        blocks[L] = min(t, key=t.get)
+        blocks[L] = pick(t)
         timings[L] = t
     return {"blocks": blocks, "ms_per_mcs": timings}
 

@@ -150,6 +150,22 @@ __device__ __forceinline__ uint32_t attempt(uint8_t *lds, int corner, uint32_t p
     return acc;
 }
 
+// Cell corners (LDS offsets within a tile) of steps 2j and 2j + 1 of block b,
+// in the low and high half-word; the two steps share their cell-set draw
+// (k / 10).
+template <int S>
+__device__ __forceinline__ uint32_t cell_pair(const PhaseArgs &a, uint32_t b, uint32_t j)
+{
+    const uint32_t k0 = 2 * j;
+    const uint32_t sw = philox(b, 0u, a.t, (TAG_SET << 24) | (k0 / 10), a.seed_lo, a.seed_hi).x;
+    uint32_t v = 0;
+    for (uint32_t h = 0; h < 2; ++h) {
+        const uint32_t sc = (sw >> (3 * ((k0 + h) % 10))) & 7u;
+        v |= (4u * ((sc & 1u) + ((sc >> 1) & 1u) * S + (sc >> 2) * S * S)) << (16 * h);
+    }
+    return v;
+}
+
 template <int B, int NTHREADS>
 __global__ __launch_bounds__(NTHREADS) void kmc_phase_kernel(PhaseArgs a)
 {
@@ -162,7 +178,6 @@ __global__ __launch_bounds__(NTHREADS) void kmc_phase_kernel(PhaseArgs a)
     static_assert(TPB <= 64, "all attempting lanes must sit in wave 0");
     __shared__ uint8_t lds[S * S * S];
     __shared__ unsigned long long Ts[13];
-    __shared__ uint32_t celltab[STEPS / 2];   // cell corners of steps 2j, 2j + 1
 
     const uint32_t L = a.L, Lm = L - 1, half = L >> 1;
     // per-MCS draws (uniform over the launch)
@@ -184,18 +199,6 @@ __global__ __launch_bounds__(NTHREADS) void kmc_phase_kernel(PhaseArgs a)
     const uint32_t X0 = ox + bx * B, Y0 = oy + by * B, Z0 = oz + bz * B;   // < 2L
 
     if (threadIdx.x < 13) Ts[threadIdx.x] = a.T[threadIdx.x];
-    if (TPB == 64 && threadIdx.x < STEPS / 2) {
-        // steps 2j and 2j + 1 share their cell-set draw (k / 10)
-        const uint32_t k0 = 2 * threadIdx.x;
-        const uint32_t sw =
-            philox(b, 0u, a.t, (TAG_SET << 24) | (k0 / 10), a.seed_lo, a.seed_hi).x;
-        uint32_t v = 0;
-        for (uint32_t h = 0; h < 2; ++h) {
-            const uint32_t sc = (sw >> (3 * ((k0 + h) % 10))) & 7u;
-            v |= (4u * ((sc & 1u) + ((sc >> 1) & 1u) * S + (sc >> 2) * S * S)) << (16 * h);
-        }
-        celltab[threadIdx.x] = v;
-    }
     // load block + halo 2 (fcc positions only)
     constexpr int NIT = (S * S + NTHREADS - 1) / NTHREADS;   // LDS rows per thread
     const uint32_t WL = L >> 3, WLm = WL - 1;                 // words per compact row
@@ -254,17 +257,26 @@ __global__ __launch_bounds__(NTHREADS) void kmc_phase_kernel(PhaseArgs a)
             const uint32_t tx = g % NT, ty = (g / NT) % NT, tz = g / (NT * NT);
             const uint64_t G = (uint64_t)b * TPB + g;
             const int tbase = (int)(((8 * tz + 2) * S + (8 * ty + 2)) * S + 8 * tx + 2);
+            // the 128 pairs of cell corners in two registers: lane l holds
+            // pairs l and 64 + l; each is read uniformly with v_readlane (no
+            // LDS read, whose wait would also wait for the last step's writes)
+            static_assert(STEPS == 256, "two 64-lane tables of step pairs");
+            const uint32_t ct[2] = {cell_pair<S>(a, b, g), cell_pair<S>(a, b, 64u + g)};
             U4 w = philox_v((uint32_t)G, (uint32_t)(G >> 32), a.t, TAG_STEP << 24, a.seed_lo,
                              a.seed_hi);
-            for (uint32_t kk = 0; kk < STEPS / 2; ++kk) {
-                // draws of the next pair of steps, independent of the lattice:
-                // their arithmetic fills the LDS latency of this pair
-                const U4 wn = philox_v((uint32_t)G, (uint32_t)(G >> 32), a.t,
-                                        (TAG_STEP << 24) | (kk + 1), a.seed_lo, a.seed_hi);
-                const uint32_t cw = celltab[kk];
-                mv += attempt<S>(lds, tbase + (int)(cw & 0xFFFFu), par0, w.x, w.y, Ts);
-                mv += attempt<S>(lds, tbase + (int)(cw >> 16), par0, w.z, w.w, Ts);
-                w = wn;
+#pragma unroll
+            for (uint32_t hv = 0; hv < 2; ++hv) {
+                for (uint32_t q = 0; q < 64; ++q) {
+                    const uint32_t kk = 64 * hv + q;
+                    // draws of the next pair of steps, independent of the
+                    // lattice: their arithmetic fills the LDS latency of this pair
+                    const U4 wn = philox_v((uint32_t)G, (uint32_t)(G >> 32), a.t,
+                                            (TAG_STEP << 24) | (kk + 1), a.seed_lo, a.seed_hi);
+                    const uint32_t cw = (uint32_t)__builtin_amdgcn_readlane((int)ct[hv], (int)q);
+                    mv += attempt<S>(lds, tbase + (int)(cw & 0xFFFFu), par0, w.x, w.y, Ts);
+                    mv += attempt<S>(lds, tbase + (int)(cw >> 16), par0, w.z, w.w, Ts);
+                    w = wn;
+                }
             }
         }
     } else {

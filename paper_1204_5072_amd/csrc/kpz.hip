@@ -423,7 +423,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
     // ---- work-group layer: single-hit steps k0 .. k1 - 1
     const uint32_t setw = philox(b, 0u, a.t, (TAG_SET << 24) | a.res, a.seed_lo, a.seed_hi).x;
     const uint32_t k0 = a.res * a.nsteps, k1 = k0 + a.nsteps;
-    const bool xn = XN == 2 ? c.xn != 0u : XN == 1;
+    const bool xn = XN == 2 ? c.xn != 0u : (XN == 1 || XN == 3);
     constexpr bool XBC = DT || XN != 0;        // the group boundary bond is kept (hl)
     int net = 0;
     U4 sw = {0u, 0u, 0u, 0u};
@@ -604,10 +604,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
 // i/8, so each XCD runs one contiguous range of blocks and neighbouring
 // blocks, which share cache lines at their edges, meet in the same L2.
 // XN = 1: several row groups per tile row (8 words each), which exchange
-// tile 0's left neighbour; 0: one group per tile row and several blocks along
-// x; 2: decided at run time (one block along x, where tile 0's left
-// neighbour wraps around).  WY: one block along y (the tile row below tile
-// row 0 wraps around); 2 = at run time.
+// tile 0's left neighbour; 3: one block along x and one row group per tile
+// row (tile 0's left neighbour wraps around to the same lane's group); 0: one
+// group per tile row and several blocks along x; 2: decided at run time.
+// WY: one block along y (the tile row below tile row 0 wraps around); 2 = at
+// run time.
 template <bool ACC, bool VEC, int XN, int WY>
 __global__ __launch_bounds__(256) void kpz_sweep_kernel(const SweepArgs a, uint32_t nblocks)
 {
@@ -709,9 +710,11 @@ __global__ __launch_bounds__(256) void kpz_dt_kernel(const SweepArgs a, uint32_t
 //
 // A word's 16 sigma_x bits are compacted into two bytes of 8 sites; a
 // 256-entry LDS table gives, for 8 sites with local prefix p_k (k = 0..7),
-// d = p_8, a = sum p_k and c = sum p_k^2.  The table is held in LUT_COPIES
-// copies, entry e of copy j at index e LUT_COPIES + j, and lane l reads copy
-// l mod LUT_COPIES: the 64 lookups of a wave then never meet in one bank.
+// d = p_8, a = sum p_k and c = sum p_k^2.  The large row passes hold the
+// table in LUT_COPIES copies, entry e of copy j at index e LUT_COPIES + j,
+// and lane l reads copy l mod LUT_COPIES: the 64 lookups of a wave then never
+// meet in one bank.  The one-work-group passes of small lattices, whose table
+// fill would outlast their few lookups, keep one copy (C = 1).
 constexpr uint32_t LUT_COPIES = 32;
 constexpr uint32_t LUT_WORDS = 256 * LUT_COPIES;
 
@@ -732,14 +735,19 @@ __device__ __forceinline__ uint32_t lut8_entry(uint32_t byte)
 
 // Fills the replicated table (every thread of the work-group takes part;
 // the caller synchronises before the first lookup).
+template <uint32_t C = LUT_COPIES>
 __device__ __forceinline__ void fill_row_lut(uint32_t *lut)
 {
     for (uint32_t i = threadIdx.x; i < 256u; i += blockDim.x) {
         const uint32_t e = lut8_entry(i);
-        const uint4 v = make_uint4(e, e, e, e);
+        if constexpr (C == 1) {
+            lut[i] = e;
+        } else {
+            const uint4 v = make_uint4(e, e, e, e);
 #pragma unroll
-        for (uint32_t j = 0; j < LUT_COPIES / 4; ++j)
-            ((uint4 *)(lut + i * LUT_COPIES))[(j + i) & (LUT_COPIES / 4 - 1u)] = v;
+            for (uint32_t j = 0; j < C / 4; ++j)
+                ((uint4 *)(lut + i * C))[(j + i) & (C / 4 - 1u)] = v;
+        }
     }
 }
 
@@ -764,6 +772,7 @@ __device__ __forceinline__ void add_half(LaneSums &r, uint32_t e)
     r.o += d;
 }
 
+template <uint32_t C>
 __device__ __forceinline__ void add_word(LaneSums &r, uint32_t w, const uint32_t *lut,
                                          uint32_t copy)
 {
@@ -771,8 +780,8 @@ __device__ __forceinline__ void add_word(LaneSums &r, uint32_t w, const uint32_t
     x = (x | (x >> 1)) & 0x33333333u;
     x = (x | (x >> 2)) & 0x0F0F0F0Fu;
     x = x | (x >> 4);                          // sites 0..7 in bits 0..7, 8..15 in 16..23
-    const uint32_t e0 = lut[((x & 0xFFu) * LUT_COPIES) | copy];
-    const uint32_t e1 = lut[(((x >> 16) & 0xFFu) * LUT_COPIES) | copy];
+    const uint32_t e0 = lut[((x & 0xFFu) * C) | copy];
+    const uint32_t e1 = lut[(((x >> 16) & 0xFFu) * C) | copy];
     add_half(r, e0);
     add_half(r, e1);
 }
@@ -857,13 +866,13 @@ __device__ __forceinline__ void row_chunk(const uint32_t *rp, uint32_t W, uint32
     }
 }
 
-template <int NV>
+template <int NV, uint32_t C = LUT_COPIES>
 __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, const uint32_t *lut,
                                             uint32_t gl, uint32_t G, long long &A, long long &B,
                                             uint32_t &first)
 {
     static_assert(NV == 4 || NV == 16, "four or sixteen words per lane");
-    const uint32_t copy = threadIdx.x & (LUT_COPIES - 1u);   // work-groups of whole waves
+    const uint32_t copy = threadIdx.x & (C - 1u);   // work-groups of whole waves
     long long s1 = 0, s2 = 0;
     int carry = 0;
     first = 0u;
@@ -876,7 +885,7 @@ __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, cons
         LaneSums ls = {0, 0, 0, 0u};
 #pragma unroll
         for (int m = 0; m < NV; ++m)
-            if (NV == 16 || m < nv) add_word(ls, v[m], lut, copy);
+            if (NV == 16 || m < nv) add_word<C>(ls, v[m], lut, copy);
         take_c(ls);
         const int o = ls.o, l1 = ls.s1, l2 = ls.s2;
         // lane offsets within the chunk: exclusive scan of o over the group
@@ -1080,7 +1089,7 @@ __device__ __forceinline__ void small_rows(const uint32_t *words, uint32_t L, ui
         if (row < L) {   // a whole lane group is in or out
             long long A, B;
             uint32_t first;
-            row_moments<4>(words + (size_t)row * W, W, lut, gl, G, A, B, first);
+            row_moments<4, 1>(words + (size_t)row * W, W, lut, gl, G, A, B, first);
             if (gl == 0) {
                 rA[row] = A;
                 rB[row] = (B << 1) | ((first >> 1) & 1u);   // + sigma_y of the first stored site
@@ -1094,9 +1103,9 @@ __global__ __launch_bounds__(1024) void kpz_roughness_small_kernel(const uint32_
                                                                    const long long *slots,
                                                                    long long *res, const Rot rot)
 {
-    __shared__ uint32_t lut[LUT_WORDS];
+    __shared__ uint32_t lut[256];
     __shared__ long long rA[SMALL_ROWS], rB[SMALL_ROWS];
-    fill_row_lut(lut);
+    fill_row_lut<1>(lut);
     __syncthreads();
     small_rows(words, L, W, lut, rA, rB);
     __syncthreads();
@@ -1576,9 +1585,9 @@ __global__ __launch_bounds__(1024) void kpz_batch_moments_small_kernel(const Mem
                                                                        uint32_t n, uint32_t nslots,
                                                                        long long *res, uint32_t k)
 {
-    __shared__ uint32_t lut[LUT_WORDS];
+    __shared__ uint32_t lut[256];
     __shared__ long long rA[SMALL_ROWS], rB[SMALL_ROWS];
-    fill_row_lut(lut);
+    fill_row_lut<1>(lut);
     __syncthreads();
     const uint32_t r = blockIdx.x;
     const MemberRows m = mr[r];
@@ -1797,11 +1806,12 @@ template <bool ACC, bool VEC>
 hipError_t launch_sweep_x(const SweepArgs &a, uint32_t nblocks, hipStream_t st)
 {
     // XN = 1 only with several row groups per tile row (8 words per group);
-    // a single block along x with one group takes the runtime form
+    // a single block along x with one group is XN = 3
     const bool wy = a.nby == 1;
     if (a.nqx > 1) return wy ? launch_sweep_v<ACC, VEC, 1, 1>(a, nblocks, st)
                              : launch_sweep_v<ACC, VEC, 1, 0>(a, nblocks, st);
-    if (a.nbx == 1) return launch_sweep_v<ACC, VEC, 2, 2>(a, nblocks, st);
+    if (a.nbx == 1) return wy ? launch_sweep_v<ACC, VEC, 3, 1>(a, nblocks, st)
+                              : launch_sweep_v<ACC, VEC, 3, 0>(a, nblocks, st);
     return wy ? launch_sweep_v<ACC, VEC, 0, 1>(a, nblocks, st)
               : launch_sweep_v<ACC, VEC, 0, 0>(a, nblocks, st);
 }

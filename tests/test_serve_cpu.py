@@ -1,5 +1,6 @@
-"""Host logic of the serving loop's job stream (no GPU): sizes, rates and
-the mean work per job of the two lattice-size distributions."""
+"""Host logic (no GPU): the serving loop's job stream (sizes, rates and the
+mean work per job of the two lattice-size distributions) and the
+autotuner's choice among near-tied block shapes."""
 import numpy as np
 import pytest
 
@@ -31,3 +32,11 @@ def test_pow2_sizes():
 def test_unknown_size_distribution():
     with pytest.raises(ValueError):
         serve.poisson_jobs(n_jobs=3, sizes="square")
+
+
+def test_autotune_pick_breaks_near_ties_by_candidate_order():
+    from paper_1204_5072_amd.autotune import pick
+    t = {(128, 256): 1.02, (256, 128): 1.00, (512, 64): 1.01}
+    assert pick(t) == (128, 256)                    # within 3 % of the fastest: first wins
+    t = {(128, 256): 1.10, (256, 128): 1.00, (512, 64): 1.01}
+    assert pick(t) == (256, 128)
