@@ -284,14 +284,12 @@ def _unpack_rows(oracle_lib, rows_words, L):
     return (2 * bx.astype(np.int8) - 1), (2 * by.astype(np.int8) - 1)
 
 
-def test_l65536_sampled_blocks(gpu, oracle_lib):
-    """The 2^32-site workload in the launch configuration the benchmark times
-    (256 x 128 blocks, p = 1, q = 0, two-buffer): each of the first 10 MCS
-    checked on sampled blocks, including the ones that wrap around the lattice
-    edges, against the oracle's single-block runner started from the GPU's
-    state of that block; the moments must be consistent after every MCS."""
+def _sampled_blocks(gpu, oracle_lib, L, B, p, q, seed, n_mcs):
+    """Each of the first n_mcs MCS checked on sampled blocks, including the
+    ones that wrap around the lattice edges, against the oracle's single-block
+    runner started from the GPU's state of that block; the moments must be
+    consistent after every MCS."""
     import torch
-    L, B, p, q, seed = 65536, (256, 128), 1.0, 0.0, 1
     sim = gpu.Sim(L, p, q, seed, B)
     nbx, nby = L // B[0], L // B[1]
     W = L // 16
@@ -302,8 +300,8 @@ def test_l65536_sampled_blocks(gpu, oracle_lib):
         host = words.index_select(0, r).cpu().numpy().view(np.uint32)
         return _block_slopes(oracle_lib, host, cols, L)
 
-    for t in range(10):
-        _log(f"L=65536 sampled blocks, MCS {t}")
+    for t in range(n_mcs):
+        _log(f"L={L} sampled blocks, MCS {t}")
         origin = oracle_lib.dd_origin(seed, t, B)
         samples = [(0, 0), (nbx - 1, 0), (0, nby - 1), (nbx - 1, nby - 1),
                    ((37 * t + 123) % nbx, (11 * t + 77) % nby), (nbx // 2 + t, nby // 3)]
@@ -319,6 +317,19 @@ def test_l65536_sampled_blocks(gpu, oracle_lib):
             assert np.array_equal(gsy, bsy), (t, bx, by)
         m = sim.roughness()   # raises KPZ_ESTATE if words and flip count disagree
         assert m.W2 > 0.25
+    sim.close()
+
+
+def test_l65536_sampled_blocks(gpu, oracle_lib):
+    """The 2^32-site workload in the launch configuration the benchmark times
+    (256 x 128 blocks, p = 1, q = 0, two-buffer): the first 10 MCS."""
+    _sampled_blocks(gpu, oracle_lib, 65536, (256, 128), 1.0, 0.0, 1, 10)
+
+
+def test_l131072_sampled_blocks(gpu, oracle_lib):
+    """The paper's largest lattice, L = 2^17 (4 GiB per lattice buffer), with
+    the default blocks and q = 1/4: the first 3 MCS."""
+    _sampled_blocks(gpu, oracle_lib, 131072, (256, 128), 1.0, 0.25, 7, 3)
 
 
 @pytest.mark.parametrize("p,q", [(1.0, 0.0), (0.5, 0.5)])
