@@ -68,6 +68,19 @@ constexpr int NSLOTS = 1024;          // flip-counter slots in the workspace
 constexpr int WS_HEADER = 256;        // results area at the start of the workspace
 constexpr int TILE = 4;               // tile edge (sites)
 constexpr uint32_t GROUP_SITES = 128; // sites of a row group (32 tiles, one bit each per plane word)
+// Staged sweep loads: a block row spans at most U = floor((nw + 7) / 4)
+// 16-byte units; R = floor(64 / U) rows per load instruction, so the nty
+// tile rows of one row offset take ceil(nty / R) <= STAGE_NC instructions
+// for every valid shape (at most 64 lanes: By = 4 nty, nw <= 8 nqx,
+// nty nqx <= 64), and a block takes By U <= STAGE_UNITS units of LDS.
+constexpr uint32_t STAGE_UNITS = 768;
+constexpr uint32_t STAGE_NC = 4;
+// global and LDS pointers of the global-to-LDS load
+typedef const __attribute__((address_space(1))) void *gptr_t;
+typedef __attribute__((address_space(3))) void *lptr_t;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt not waited for)
+constexpr int WAIT_VMCNT0 = 0x0F70;
 
 // ---------------------------------------------------------------- init
 
@@ -107,6 +120,10 @@ struct SweepArgs {
     uint32_t nqx;                // row groups per tile row (Bx / 128, at least 1)
     uint32_t ntg, nwg;           // tiles and lattice words per row group
     uint32_t nty, mnty;          // tile rows per block (By / 4); ceil(2^16 / nty)
+    // staged sweep loads: units per block row floor((nw + 7) / 4), ceil(2^16
+    // / su_u), rows per load instruction floor(64 / su_u), load instructions
+    // per row offset ceil(nty / su_r), units of LDS per block By su_u
+    uint32_t su_u, su_m, su_r, su_nc, su;
     uint32_t seed_lo, seed_hi;
     uint32_t t;
     uint32_t res;                // residency of MCS t (origin move), 0 .. moves - 1
@@ -276,8 +293,8 @@ __device__ __forceinline__ uint32_t pick9(const uint32_t (&R)[9], uint32_t n)
 // step k takes cell set bits 2k.. of (SET, t, b, res).w0 and, for row group
 // G = (b nty + ty) nqx + q, the tile's bit of words 2 (k mod 2), +1 of
 // (SITE, t, G, k / 2) as the site (rx, ry) in its cell.
-template <bool ACC, bool DT, bool VEC, int XN = 2, int WY = 2>
-__device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
+template <bool ACC, bool DT, bool VEC, int XN = 2, int WY = 2, bool STG = false>
+__device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint4 *stg = nullptr)
 {
     using namespace kpzslice;
     const uint32_t lane = threadIdx.x & 63u;
@@ -312,7 +329,80 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
     // into these copies instead of reading the words again.
     uint32_t X[4][4], Y[4][4];
     uint32_t w0r[4], wnr[4];
-    {
+    if constexpr (STG) {
+        // Staged load (VEC): the wave reads the block's By rows of su_u
+        // aligned 16-byte units (from the unit holding the block's first
+        // word), su_r rows per load instruction with consecutive lanes on
+        // consecutive units of a row, and keeps them in its LDS region with
+        // row 4 ty + r at position r nty + ty; every lane then takes its
+        // group's three units of each of its four rows (lanes of consecutive
+        // tile rows read units su_u apart: no bank conflicts for odd su_u).
+        const uint32_t U = a.su_u, R = a.su_r;
+        const uint32_t rs = __umul24(lane, a.su_m) >> 16, col = lane - __umul24(rs, U);
+        const uint32_t rsv = rs < R ? rs : 0xffffu;        // lanes past R U idle
+        const uint32_t xin = wrap_add(gw0 >> 2, col, a.W >> 2);
+        // each load goes straight to LDS (global_load_lds_dwordx4: lane i's
+        // 16 bytes at the wave-uniform destination + 16 i)
+#pragma unroll
+        for (uint32_t cc = 0; cc < STAGE_NC; ++cc) {
+            if (cc < a.su_nc) {
+                const uint32_t tyc = cc * R + rsv;
+#pragma unroll
+                for (uint32_t r = 0; r < 4; ++r) {
+                    if (tyc < a.nty) {
+                        uint32_t gy = gy0 + 4u * tyc + r;
+                        if (gy >= a.L) gy -= a.L;
+                        __builtin_amdgcn_global_load_lds(
+                            (const gptr_t)((const uint4 *)(a.src + (size_t)gy * a.W) + xin),
+                            (lptr_t)(stg + (r * a.nty + cc * R) * U), 16, 0, 0);
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // the group's first unit; with one group per tile row the third unit
+        // exists only when U > 2 (it is needed only then)
+        const uint32_t j0 = ((gw0 & 3u) + q * nwg) >> 2;
+        const bool third = XN == 1 || U > 2u;
+        // whole 16-byte reads, all twelve issued before the first is used (a
+        // volatile vector load is not cut into the words one funnel case
+        // uses): lanes of consecutive tile rows then meet no bank conflict
+        u32x4 v[4][3];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint4 *srow = stg + (r * a.nty + ty) * U + j0;
+#pragma unroll
+            for (uint32_t m = 0; m < 3; ++m) {
+                v[r][m] = u32x4{0u, 0u, 0u, 0u};
+                if (active && (m < 2 || third))
+                    v[r][m] = *(const volatile __attribute__((address_space(3))) u32x4 *)(srow + m);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            uint32_t A[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u}, R9[9];
+            if (active) {
+                GroupRaw<VEC> g;
+#pragma unroll
+                for (uint32_t m = 0; m < 3; ++m) {
+                    g.v[4 * m] = v[r][m].x; g.v[4 * m + 1] = v[r][m].y;
+                    g.v[4 * m + 2] = v[r][m].z; g.v[4 * m + 3] = v[r][m].w;
+                }
+                funnel_group<VEC>(g, gwq, nwg, sh2, A, R9);
+            }
+            w0r[r] = 0u;
+            wnr[r] = 0u;
+            transpose8(A);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                X[r][c] = A[2 * c];
+                Y[r][c] = A[2 * c + 1];
+            }
+        }
+    } else {
         // the loads of HR rows at a time are issued before the first is used
         // (all four in the dead-border sweep; one at a time with DT, whose
         // halo copies leave no registers for more); idle lanes read the
@@ -485,6 +575,54 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
     const uint32_t gwoq = wrap_add(gwo, qw, a.W);
     const bool ovec = VEC && (gwoq & 3u) == 0 && (nwg & 3u) == 0;
     const uint32_t lowm = sh2 ? (1u << sh2) - 1u : 0u;
+    if (STG && a.db && (a.nw & 3u) == 0) {
+        // Staged store (two-buffer mode, whole units per row): every lane
+        // puts its group's output units into the wave's LDS region (the
+        // layout of the staged load, nw / 4 of the su_u units of a row in
+        // use), then the wave writes the block's rows as it read them.
+        const uint32_t U = a.su_u, R = a.su_r;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            uint32_t A[8];
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                A[2 * cc] = X[r][cc];
+                A[2 * cc + 1] = Y[r][cc];
+            }
+            transpose8(A);
+            if (active) {
+                uint4 *srow = stg + (r * a.nty + ty) * U + ((q * nwg) >> 2);
+#pragma unroll
+                for (uint32_t m = 0; m < 2; ++m)
+                    if (4u * m < nwg)
+                        srow[m] = make_uint4(A[4 * m], A[4 * m + 1], A[4 * m + 2], A[4 * m + 3]);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t rs = __umul24(lane, a.su_m) >> 16, col = lane - __umul24(rs, U);
+        const uint32_t rsv = (rs < R && col + 1u < U) ? rs : 0xffffu;
+        const uint32_t xout = wrap_add(gwo >> 2, col, a.W >> 2);
+#pragma unroll
+        for (uint32_t cc = 0; cc < STAGE_NC; ++cc) {
+            if (cc < a.su_nc) {
+                const uint32_t tyc = cc * R + rsv;
+#pragma unroll
+                for (uint32_t r = 0; r < 4; ++r) {
+                    if (tyc < a.nty) {
+                        uint32_t gy = gy0 + 4u * tyc + r;
+                        if (gy >= a.L) gy -= a.L;
+                        ((uint4 *)(a.words + (size_t)gy * a.W))[xout] =
+                            stg[(r * a.nty + cc * R) * U + lane];
+                    }
+                }
+            }
+        }
+    } else
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         uint32_t A[8];
@@ -609,14 +747,18 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b)
 // group per tile row and several blocks along x; 2: decided at run time.
 // WY: one block along y (the tile row below tile row 0 wraps around); 2 = at
 // run time.
+// VEC: every wave stages its block's rows in its own a.su 16-byte units of
+// the dynamic LDS.
 template <bool ACC, bool VEC, int XN, int WY>
 __global__ __launch_bounds__(256) void kpz_sweep_kernel(const SweepArgs a, uint32_t nblocks)
 {
+    extern __shared__ uint4 kpz_stage[];
     uint32_t g = blockIdx.x;
     if (a.xcd) g = (g & 7u) * (gridDim.x >> 3) + (g >> 3);
     const uint32_t b = g * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (b >= nblocks) return;
-    sweep_block<ACC, false, VEC, XN, WY>(a, __builtin_amdgcn_readfirstlane(b));
+    sweep_block<ACC, false, VEC, XN, WY, VEC>(a, __builtin_amdgcn_readfirstlane(b),
+                                              kpz_stage + (threadIdx.x >> 6) * a.su);
 }
 
 // Straddling word j = gy * nbx + bx of MCS a.t: the word at the left edge of
@@ -1778,6 +1920,11 @@ void set_shape(SweepArgs &a, uint32_t L, uint32_t Bx, uint32_t By)
     a.nwg = a.ntg / 4;
     a.nty = By / TILE;
     a.mnty = (65536u + a.nty - 1u) / a.nty;
+    a.su_u = (a.nw + 7u) / 4u;
+    a.su_m = (65536u + a.su_u - 1u) / a.su_u;
+    a.su_r = 64u / a.su_u;
+    a.su_nc = (a.nty + a.su_r - 1u) / a.su_r;
+    a.su = a.By * a.su_u;
 }
 
 // Waves (blocks) per work-group: four when the block count allows;
@@ -1797,8 +1944,9 @@ hipError_t launch_sweep_v(const SweepArgs &a, uint32_t nblocks, hipStream_t st)
     const uint32_t grid = nblocks / wpg;
     SweepArgs b = a;
     b.xcd = (grid % 8u) == 0 ? a.xcd : 0u;
-    hipLaunchKernelGGL((kpz_sweep_kernel<ACC, VEC, XN, WY>), dim3(grid), dim3(64 * wpg), 0, st,
-                       b, nblocks);
+    if (VEC && (b.su > STAGE_UNITS || b.su_nc > STAGE_NC)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((kpz_sweep_kernel<ACC, VEC, XN, WY>), dim3(grid), dim3(64 * wpg),
+                       VEC ? (size_t)wpg * b.su * sizeof(uint4) : 0, st, b, nblocks);
     return hipGetLastError();
 }
 
