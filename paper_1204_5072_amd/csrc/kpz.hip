@@ -38,6 +38,7 @@
 //           bit and draws the later words only while some tile is undecided.
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <math.h>
 #include <stdint.h>
@@ -341,24 +342,31 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
         const uint32_t rs = __umul24(lane, a.su_m) >> 16, col = lane - __umul24(rs, U);
         const uint32_t rsv = rs < R ? rs : 0xffffu;        // lanes past R U idle
         const uint32_t xin = wrap_add(gw0 >> 2, col, a.W >> 2);
+        const char *base = (const char *)a.src + 16u * xin;    // the lane's unit in row 0
+        const uint32_t pitch = 4u * a.W;                       // bytes per row
         // each load goes straight to LDS (global_load_lds_dwordx4: lane i's
         // 16 bytes at the wave-uniform destination + 16 i)
+        // (the row index wraps only in blocks that cross the lattice's edge)
+        auto issue = [&](auto wrap) {
 #pragma unroll
-        for (uint32_t cc = 0; cc < STAGE_NC; ++cc) {
-            if (cc < a.su_nc) {
-                const uint32_t tyc = cc * R + rsv;
+            for (uint32_t cc = 0; cc < STAGE_NC; ++cc) {
+                if (cc < a.su_nc) {
+                    const uint32_t tyc = cc * R + rsv;
 #pragma unroll
-                for (uint32_t r = 0; r < 4; ++r) {
-                    if (tyc < a.nty) {
-                        uint32_t gy = gy0 + 4u * tyc + r;
-                        if (gy >= a.L) gy -= a.L;
-                        __builtin_amdgcn_global_load_lds(
-                            (const gptr_t)((const uint4 *)(a.src + (size_t)gy * a.W) + xin),
-                            (lptr_t)(stg + (r * a.nty + cc * R) * U), 16, 0, 0);
+                    for (uint32_t r = 0; r < 4; ++r) {
+                        if (tyc < a.nty) {
+                            uint32_t gy = gy0 + 4u * tyc + r;
+                            if (decltype(wrap)::value && gy >= a.L) gy -= a.L;
+                            __builtin_amdgcn_global_load_lds(
+                                (const gptr_t)(base + (uint64_t)gy * pitch),
+                                (lptr_t)(stg + (r * a.nty + cc * R) * U), 16, 0, 0);
+                        }
                     }
                 }
             }
-        }
+        };
+        if (gy0 + a.By > a.L) issue(std::true_type{});
+        else issue(std::false_type{});
         __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -607,21 +615,27 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
         const uint32_t rs = __umul24(lane, a.su_m) >> 16, col = lane - __umul24(rs, U);
         const uint32_t rsv = (rs < R && col + 1u < U) ? rs : 0xffffu;
         const uint32_t xout = wrap_add(gwo >> 2, col, a.W >> 2);
+        char *base = (char *)a.words + 16u * xout;             // the lane's unit in row 0
+        const uint32_t pitch = 4u * a.W;
+        auto put = [&](auto wrap) {
 #pragma unroll
-        for (uint32_t cc = 0; cc < STAGE_NC; ++cc) {
-            if (cc < a.su_nc) {
-                const uint32_t tyc = cc * R + rsv;
+            for (uint32_t cc = 0; cc < STAGE_NC; ++cc) {
+                if (cc < a.su_nc) {
+                    const uint32_t tyc = cc * R + rsv;
 #pragma unroll
-                for (uint32_t r = 0; r < 4; ++r) {
-                    if (tyc < a.nty) {
-                        uint32_t gy = gy0 + 4u * tyc + r;
-                        if (gy >= a.L) gy -= a.L;
-                        ((uint4 *)(a.words + (size_t)gy * a.W))[xout] =
-                            stg[(r * a.nty + cc * R) * U + lane];
+                    for (uint32_t r = 0; r < 4; ++r) {
+                        if (tyc < a.nty) {
+                            uint32_t gy = gy0 + 4u * tyc + r;
+                            if (decltype(wrap)::value && gy >= a.L) gy -= a.L;
+                            *(uint4 *)(base + (uint64_t)gy * pitch) =
+                                stg[(r * a.nty + cc * R) * U + lane];
+                        }
                     }
                 }
             }
-        }
+        };
+        if (gy0 + a.By > a.L) put(std::true_type{});
+        else put(std::false_type{});
     } else
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -755,10 +769,10 @@ __global__ __launch_bounds__(256) void kpz_sweep_kernel(const SweepArgs a, uint3
     extern __shared__ uint4 kpz_stage[];
     uint32_t g = blockIdx.x;
     if (a.xcd) g = (g & 7u) * (gridDim.x >> 3) + (g >> 3);
-    const uint32_t b = g * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t b = g * (blockDim.x >> 6) + wv;
     if (b >= nblocks) return;
-    sweep_block<ACC, false, VEC, XN, WY, VEC>(a, __builtin_amdgcn_readfirstlane(b),
-                                              kpz_stage + (threadIdx.x >> 6) * a.su);
+    sweep_block<ACC, false, VEC, XN, WY, VEC>(a, b, kpz_stage + wv * a.su);
 }
 
 // Straddling word j = gy * nbx + bx of MCS a.t: the word at the left edge of
