@@ -609,6 +609,10 @@ def main():
         "w2_last": w2[-1] if w2 else None,
         "t_final": sim.state()[0],
     }
+    # after the timed region: the final surface must satisfy the slope
+    # constraints everywhere (open plaquettes, row-0 and column-0 sums)
+    line["final_surface_check"] = dict(zip(("open_plaquettes", "row0_sum", "col0_sum"),
+                                           sim.check_invariants()))
     sim.close()
     del sim
     if not args.no_ensemble:

@@ -195,6 +195,18 @@ kpz_status kpz_roughness_noalloc(const uint32_t *d_words, int64_t L, int64_t net
 kpz_status kpz_height_moments(kpz_sim *sim, int64_t sums[8], double *W2, double *skewness,
                               double *kurtosis);
 
+/* Validity of the stored surface (Sec. 2.1: the slopes are the differences
+ * of a periodic height function): counts[0] = number of plaquettes whose
+ * four slopes do not sum to zero, sigma_x(x,y) + sigma_y(x+1,y) !=
+ * sigma_y(x,y) + sigma_x(x,y+1); counts[1] = sum of sigma_x along row 0;
+ * counts[2] = sum of sigma_y along column 0.  When every plaquette is closed
+ * all rows have the sum of row 0 and all columns that of column 0, so the
+ * three counts are zero exactly when every plaquette, row and column sums
+ * to zero.  One pass over the lattice (after kpz_sync_words); synchronises
+ * the stream.  Returns KPZ_ESTATE if any count is non-zero (the counts are
+ * still written), KPZ_EINVAL for a NULL argument. */
+kpz_status kpz_check_invariants(kpz_sim *sim, int64_t counts[3]);
+
 /* Checkpoint support.  The complete dynamical state is (words, t, net_flips)
  * where net_flips = #depositions - #desorptions since the flat start (so
  * S1 = N/2 + 2 net_flips).  get synchronises the stream; set enqueues the

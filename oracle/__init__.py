@@ -402,3 +402,18 @@ def check_invariants(sx: np.ndarray, sy: np.ndarray) -> None:
     assert not curl.any(), "plaquette circulation"
     assert not sx64.sum(axis=1).any(), "row sum of sigma_x"
     assert not sy64.sum(axis=0).any(), "column sum of sigma_y"
+
+
+def invariant_counts(sx: np.ndarray, sy: np.ndarray) -> tuple:
+    """(open plaquettes, sum of sigma_x along row 0, sum of sigma_y along
+    column 0) of a slope field, from the definitions of Sec. 2.1: a
+    plaquette is closed when the two paths from (x, y) to (x+1, y+1) have the
+    same height change.  All three are zero for a valid surface (with every
+    plaquette closed, every row and column carries the sums of row 0 and
+    column 0)."""
+    sx64 = sx.astype(np.int64)
+    sy64 = sy.astype(np.int64)
+    right_then_up = sx64 + np.roll(sy64, -1, axis=1)
+    up_then_right = sy64 + np.roll(sx64, -1, axis=0)
+    return (int(np.count_nonzero(right_then_up != up_then_right)), int(sx64[0, :].sum()),
+            int(sy64[:, 0].sum()))

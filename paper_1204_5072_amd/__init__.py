@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(PKG, "libkpz.so")
 KPZ_OK, KPZ_EINVAL, KPZ_ESIZE, KPZ_EHIP, KPZ_ESTATE, KPZ_ERANGE = 0, -1, -2, -3, -4, -5
 
 EXPORTED = ("kpz_workspace_bytes", "kpz_block_shape", "kpz_init", "kpz_sweep", "kpz_roughness", "kpz_height_moments",
-            "kpz_get_state", "kpz_set_state", "kpz_sync_words", "kpz_destroy", "kpz_status_str",
+            "kpz_get_state", "kpz_set_state", "kpz_sync_words", "kpz_check_invariants", "kpz_destroy", "kpz_status_str",
             "kpz_last_error", "kpz_valu_probe", "kpz_roughness_noalloc",
             "kpz_batch_sizes", "kpz_batch_init", "kpz_batch_word_offset", "kpz_batch_sweep",
             "kpz_batch_roughness", "kpz_batch_run", "kpz_batch_get_t", "kpz_batch_destroy",
@@ -100,6 +100,7 @@ def lib() -> ctypes.CDLL:
         L.kpz_get_state.argtypes = [vp, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
         L.kpz_set_state.argtypes = [vp, c.c_int64, c.c_int64]
         L.kpz_sync_words.argtypes = [vp]
+        L.kpz_check_invariants.argtypes = [vp, c.POINTER(c.c_int64)]
         L.kpz_destroy.argtypes = [vp]
         L.kpz_destroy.restype = None
         L.kpz_status_str.argtypes = [c.c_int]
@@ -154,7 +155,8 @@ def lib() -> ctypes.CDLL:
         L.kmc_last_error.argtypes = [vp]
         L.kmc_last_error.restype = c.c_char_p
         for f in ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness",
-                  "kpz_get_state", "kpz_set_state", "kpz_sync_words", "kpz_batch_sizes",
+                  "kpz_get_state", "kpz_set_state", "kpz_sync_words", "kpz_check_invariants",
+                  "kpz_batch_sizes",
                   "kpz_batch_init",
                   "kpz_batch_word_offset", "kpz_batch_sweep", "kpz_batch_roughness",
                   "kpz_batch_run", "kpz_batch_get_t", "kpz_batch_sync_words", "kpz_pool_job_bytes",
@@ -260,6 +262,16 @@ class Sim:
                                              ctypes.byref(ku)), "kpz_height_moments")
         M = [(sums[2 * k + 1] << 64) + (sums[2 * k] & ((1 << 64) - 1)) for k in range(4)]
         return M, (w2.value, sk.value, ku.value)
+
+    def check_invariants(self) -> Tuple[int, int, int]:
+        """(open plaquettes, row-0 slope sum, column-0 slope sum) of the
+        stored surface (kpz_check_invariants); all zero for a valid one.
+        Returns the counts whatever they are; raises only on other errors."""
+        counts = (ctypes.c_int64 * 3)()
+        st = lib().kpz_check_invariants(self._h, counts)
+        if st not in (KPZ_OK, KPZ_ESTATE):
+            self._check(st, "kpz_check_invariants")
+        return counts[0], counts[1], counts[2]
 
     def state(self) -> Tuple[int, int]:
         t, net = ctypes.c_int64(), ctypes.c_int64()

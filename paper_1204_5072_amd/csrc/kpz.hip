@@ -864,29 +864,35 @@ __global__ __launch_bounds__(256) void kpz_dt_kernel(const SweepArgs a, uint32_t
 // Per row y: with P(x) = sum_{l<x} sigma_x(l,y) (height relative to the row
 // start), A_y = sum_x P(x) and B_y = sum_x P(x)^2, a group of lanes per row.
 //
-// A word's 16 sigma_x bits are compacted into two bytes of 8 sites; a
-// 256-entry LDS table gives, for 8 sites with local prefix p_k (k = 0..7),
-// d = p_8, a = sum p_k and c = sum p_k^2.  The large row passes hold the
-// table in LUT_COPIES copies, entry e of copy j at index e LUT_COPIES + j,
-// and lane l reads copy l mod LUT_COPIES: the 64 lookups of a wave then never
-// meet in one bank.  The one-work-group passes of small lattices, whose table
-// fill would outlast their few lookups, keep one copy (C = 1).
+// A word's 16 sites are taken as two halves of 8; a 256-entry LDS table gives,
+// for 8 sites with local prefix p_k (k = 0..7), d = p_8, a = sum p_k and
+// c = sum p_k^2.  A half's table index is gathered from the word with two
+// masks and a shift: bit 2i of the index is sigma_x of site i and bit 2i+1
+// that of site i + 4 (i = 0..3), i.e. the index interleaves the half's first
+// and last four sites, and the table is filled in that order.  The large row
+// passes hold the table in LUT_COPIES copies, entry e of copy j at index
+// e LUT_COPIES + j, and lane l reads copy l mod LUT_COPIES: the 64 lookups of
+// a wave then never meet in one bank.  The one-work-group passes of small
+// lattices, whose table fill would outlast their few lookups, keep one copy
+// (C = 1).
 constexpr uint32_t LUT_COPIES = 32;
 constexpr uint32_t LUT_WORDS = 256 * LUT_COPIES;
+constexpr int LUT_ABIAS = 28;   // a + LUT_ABIAS >= 0
 
-// Entry layout: c (0..140) in bits 0..7 with bits 8..12 zero, so the sum of
-// up to 32 entries holds the sum of their c exactly in bits 0..12; d (-8..8)
-// in bits 13..17 and a (-28..28) in bits 18..24, two's complement, one
-// signed field extract each.
-__device__ __forceinline__ uint32_t lut8_entry(uint32_t byte)
+// Entry layout: c (0..140) in bits 0..7 with bits 8..12 zero and a + 28
+// (0..56) in bits 13..18 with bits 19..23 zero, so the plain sum of up to 32
+// entries holds the sums of c and of a + 28 exactly in bits 0..12 and
+// 13..23; d (-8..8) in bits 27..31, two's complement (one arithmetic shift).
+__device__ __forceinline__ uint32_t lut8_entry(uint32_t idx)
 {
     int p = 0, a = 0, c = 0;
-    for (int i = 0; i < 8; ++i) {
+    for (int k = 0; k < 8; ++k) {
         a += p;
         c += p * p;
-        p += ((byte >> i) & 1u) ? 1 : -1;
+        const uint32_t bit = k < 4 ? 2 * k : 2 * (k - 4) + 1;   // interleaved index
+        p += ((idx >> bit) & 1u) ? 1 : -1;
     }
-    return (uint32_t)c | (((uint32_t)p & 31u) << 13) | (((uint32_t)a & 127u) << 18);
+    return (uint32_t)c | ((uint32_t)(a + LUT_ABIAS) << 13) | ((uint32_t)p << 27);
 }
 
 // Fills the replicated table (every thread of the work-group takes part;
@@ -907,46 +913,64 @@ __device__ __forceinline__ void fill_row_lut(uint32_t *lut)
     }
 }
 
-// Running sums of a lane over consecutive words: o = height offset (relative
-// to the lane's first site), s1 = sum of heights, s2 = sum of squared heights
-// without the c terms, csum = sum of the table entries (its bits 0..12 are the
-// sum of the c terms; at most 32 entries between two calls of take_c).
+// Sums of a lane over the halves of consecutive words, the heights of a half
+// being o + p_k with o its offset from the lane's first site: T = sum o,
+// Q = sum o^2, R = sum o (a + 28), csum = sum of the table entries (at most
+// 32 halves between two calls of lane_totals).
 struct LaneSums {
-    int o, s1, s2;
+    int o, T, Q, R;
     uint32_t csum;
 };
 
-// Eight sites with table entry e: heights o + p_k, k = 0..7.
 __device__ __forceinline__ void add_half(LaneSums &r, uint32_t e)
 {
-    const int d = __builtin_amdgcn_sbfe((int)e, 13, 5);
-    const int a = __builtin_amdgcn_sbfe((int)e, 18, 7);
-    const int t = 8 * r.o + a;                 // sum_k (o + p_k)
-    r.s1 += t;
-    r.s2 += __mul24(r.o, t + a);               // 8 o^2 + 2 o a; + c through csum
+    const int ab = (int)__builtin_amdgcn_ubfe(e, 13, 6);
+    r.T += r.o;
+    r.Q = __mul24(r.o, r.o) + r.Q;
+    r.R = __mul24(r.o, ab) + r.R;
     r.csum += e;
-    r.o += d;
+    r.o += (int)e >> 27;
+}
+
+// Byte offsets into the table of the two halves of word w, for copy offset
+// `copy4x2` = 4 copy (0x10001): the interleaved index of each half times
+// 4 C, computed for both halves at once, the first in the low and the second
+// in the high 16 bits (the sites of the second half sit 16 bits above those
+// of the first, and every offset stays below 2^15).
+template <uint32_t C>
+__device__ __forceinline__ void lut_addrs(uint32_t w, uint32_t copy4x2, uint32_t &a0, uint32_t &a1)
+{
+    constexpr uint32_t S = C == 1 ? 2 : C == 32 ? 7 : 0;   // log2(4 C)
+    static_assert(S != 0, "one or 32 copies");
+    constexpr uint32_t M1 = (0x55u << S) * 0x10001u, M2 = (0xAAu << S) * 0x10001u;
+    // index bits 0,2,4,6 <- sites 0..3 (w bits 0,2,4,6); bits 1,3,5,7 <-
+    // sites 4..7 (w bits 8,10,12,14); likewise 16 bits up
+    const uint32_t P = ((w << S) & M1) | ((w >> (7 - S)) & M2) | copy4x2;
+    a0 = P & 0xFFFFu;
+    a1 = P >> 16;
 }
 
 template <uint32_t C>
 __device__ __forceinline__ void add_word(LaneSums &r, uint32_t w, const uint32_t *lut,
-                                         uint32_t copy)
+                                         uint32_t copy4x2)
 {
-    uint32_t x = w & 0x55555555u;              // sigma_x of site i at bit 2i
-    x = (x | (x >> 1)) & 0x33333333u;
-    x = (x | (x >> 2)) & 0x0F0F0F0Fu;
-    x = x | (x >> 4);                          // sites 0..7 in bits 0..7, 8..15 in 16..23
-    const uint32_t e0 = lut[((x & 0xFFu) * C) | copy];
-    const uint32_t e1 = lut[(((x >> 16) & 0xFFu) * C) | copy];
+    uint32_t a0, a1;
+    lut_addrs<C>(w, copy4x2, a0, a1);
+    const uint32_t e0 = *(const uint32_t *)((const char *)lut + a0);
+    const uint32_t e1 = *(const uint32_t *)((const char *)lut + a1);
     add_half(r, e0);
     add_half(r, e1);
 }
 
-// Moves the c terms accumulated in csum into s2.
-__device__ __forceinline__ void take_c(LaneSums &r)
+// (o, sum of heights, sum of squared heights) of the lane's nh halves,
+// heights relative to its first site: sum over halves of 8 o + a and of
+// 8 o^2 + 2 o a + c.
+__device__ __forceinline__ void lane_totals(const LaneSums &r, int nh, int &l1, int &l2)
 {
-    r.s2 += (int)(r.csum & 0x1FFFu);
-    r.csum = 0u;
+    const int sa = (int)((r.csum >> 13) & 0x7FFu) - LUT_ABIAS * nh;
+    const int sc = (int)(r.csum & 0x1FFFu);
+    l1 = 8 * r.T + sa;
+    l2 = 8 * r.Q + 2 * (r.R - LUT_ABIAS * r.T) + sc;
 }
 
 // Lanes per row (a power of two, for the width of the group shuffles): a
@@ -1028,7 +1052,7 @@ __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, cons
                                             uint32_t &first)
 {
     static_assert(NV == 4 || NV == 16, "four or sixteen words per lane");
-    const uint32_t copy = threadIdx.x & (C - 1u);   // work-groups of whole waves
+    const uint32_t copy4x2 = (threadIdx.x & (C - 1u)) * 0x40004u;   // work-groups of whole waves
     long long s1 = 0, s2 = 0;
     int carry = 0;
     first = 0u;
@@ -1038,12 +1062,13 @@ __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, cons
         row_chunk<NV>(rp, W, base + NV * gl, v, nv);
         if (base == 0) first = v[0];
         // this lane's words relative to its own start
-        LaneSums ls = {0, 0, 0, 0u};
+        LaneSums ls = {0, 0, 0, 0, 0u};
 #pragma unroll
         for (int m = 0; m < NV; ++m)
-            if (NV == 16 || m < nv) add_word<C>(ls, v[m], lut, copy);
-        take_c(ls);
-        const int o = ls.o, l1 = ls.s1, l2 = ls.s2;
+            if (NV == 16 || m < nv) add_word<C>(ls, v[m], lut, copy4x2);
+        int l1, l2;
+        lane_totals(ls, 2 * nv, l1, l2);
+        const int o = ls.o;
         // lane offsets within the chunk: exclusive scan of o over the group
         int incl, total;
         if (G == 64u) {
@@ -1461,6 +1486,79 @@ __global__ __launch_bounds__(256) void kpz_mom4_finalize_kernel(const uint32_t *
             res[2 * k] = (long long)(uint64_t)u;
             res[2 * k + 1] = (long long)(uint64_t)(u >> 64);
         }
+}
+
+// ------------------------------------------------------------ invariants
+//
+// The surface constraints of Sec. 2.1 on the stored slopes: around every
+// plaquette the four slopes sum to zero, sigma_x(x,y) + sigma_y(x+1,y) =
+// sigma_y(x,y) + sigma_x(x,y+1), and along the periodic row 0 (column 0)
+// the sigma_x (sigma_y) sum to zero.  With every plaquette closed, the
+// sigma_x sums of rows y and y+1 differ by the sum of sigma_y(x+1,y) -
+// sigma_y(x,y) over the periodic row, which is zero, so all rows (and
+// likewise all columns) share the sums of row 0 and column 0.
+//
+// In bits (a = sigma_x(x,y) > 0, b = sigma_y(x+1,y) > 0, c = sigma_x(x,y+1)
+// > 0, d = sigma_y(x,y) > 0) a plaquette is closed iff {a, b} = {c, d} as
+// multisets: a ^ b = c ^ d and a & b = c & d.  A thread takes U consecutive
+// words of a row (one 16-byte load for U = 4) and walks down R rows, keeping
+// the row above from one iteration to the next; the word to the right of its
+// last word gives sigma_y(x+1,y) of the last site.  out[0] counts open
+// plaquettes, out[1] the sigma_x = +1 bonds of row 0, out[2] the sigma_y = +1
+// bonds of column 0 (one atomic per wave each).
+template <int U>
+__global__ __launch_bounds__(256) void kpz_check_kernel(const uint32_t *words, uint32_t L,
+                                                        uint32_t W, uint32_t R,
+                                                        unsigned long long *out)
+{
+    const uint32_t ng = W / U;
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t chunk = gid / ng;
+    const uint32_t g = (uint32_t)(gid - chunk * ng);
+    uint32_t open = 0, row0 = 0, col0 = 0;
+    if (chunk * R < L) {
+        const uint32_t y0 = (uint32_t)chunk * R, y1 = min(L, y0 + R);
+        const uint32_t xn = (g + 1 == ng) ? 0u : (g + 1) * U;   // word right of the last
+        uint32_t cur[U], cn;
+        auto load = [&](uint32_t y, uint32_t (&v)[U], uint32_t &n) {
+            const uint32_t *rp = words + (size_t)y * W;
+            if constexpr (U == 4) {
+                const uint4 q = *(const uint4 *)(rp + g * 4u);
+                v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) v[u] = rp[g * U + u];
+            }
+            n = rp[xn];
+        };
+        load(y0, cur, cn);
+        for (uint32_t y = y0; y < y1; ++y) {
+            uint32_t up[U], un;
+            load(y + 1 == L ? 0u : y + 1, up, un);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t w = cur[u], wn = (u + 1 < U) ? cur[u + 1] : cn;
+                const uint32_t a = w, d = w >> 1, c = up[u];
+                const uint32_t b = __builtin_amdgcn_alignbit(wn, w, 3);   // sigma_y(x+1, y)
+                open += __popc(((a ^ b ^ c ^ d) | ((a & b) ^ (c & d))) & 0x55555555u);
+                if (y == 0) row0 += __popc(w & 0x55555555u);
+            }
+            if (g == 0) col0 += (cur[0] >> 1) & 1u;
+#pragma unroll
+            for (int u = 0; u < U; ++u) cur[u] = up[u];
+            cn = un;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        open += __shfl_xor(open, off);
+        row0 += __shfl_xor(row0, off);
+        col0 += __shfl_xor(col0, off);
+    }
+    if ((threadIdx.x & 63u) == 0) {
+        if (open) atomicAdd(out, (unsigned long long)open);
+        if (row0) atomicAdd(out + 1, (unsigned long long)row0);
+        if (col0) atomicAdd(out + 2, (unsigned long long)col0);
+    }
 }
 
 // ------------------------------------------------------------ calibration
@@ -2666,6 +2764,50 @@ kpz_status kpz_height_moments(kpz_sim *s, int64_t sums[8], double *W2, double *s
     if (W2) *W2 = (double)m2;
     if (skewness) *skewness = m2 > 0 ? (double)(m3 / powl(m2, 1.5L)) : 0.0;
     if (kurtosis) *kurtosis = m2 > 0 ? (double)(m4 / (m2 * m2) - 3) : 0.0;
+    return KPZ_OK;
+}
+
+// Header slots of the invariant counters (after the moments of
+// kpz_roughness and kpz_height_moments).
+constexpr int RES_CHECK = 16;
+constexpr uint32_t CHECK_ROWS = 64;   // rows a thread walks
+
+kpz_status kpz_check_invariants(kpz_sim *s, int64_t counts[3])
+{
+    clear_pending_error();
+    if (!s || !counts) return KPZ_EINVAL;
+    const kpz_status sst = kpz_sync_words(s);
+    if (sst != KPZ_OK) return sst;
+    const uint32_t L = (uint32_t)s->prm.L, W = L / 16;
+    unsigned long long *d = (unsigned long long *)(ws_res(s) + RES_CHECK);
+    hipLaunchKernelGGL(kpz_zero_kernel, dim3(1), dim3(64), 0, s->stream, (uint32_t *)d,
+                       (uint64_t)6);
+    const uint32_t R = L < CHECK_ROWS ? L : CHECK_ROWS;
+    const uint64_t chunks = (L + R - 1) / R;
+    if ((W & 3u) == 0) {
+        const uint64_t th = (uint64_t)(W / 4) * chunks;
+        hipLaunchKernelGGL(kpz_check_kernel<4>, dim3((uint32_t)((th + 255) / 256)), dim3(256), 0,
+                           s->stream, s->words, L, W, R, d);
+    } else {
+        const uint64_t th = (uint64_t)W * chunks;
+        hipLaunchKernelGGL(kpz_check_kernel<1>, dim3((uint32_t)((th + 255) / 256)), dim3(256), 0,
+                           s->stream, s->words, L, W, R, d);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(s, e, "kpz_check_invariants launch");
+    unsigned long long v[3];
+    e = hipMemcpyAsync(v, d, sizeof v, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "kpz_check_invariants copy");
+    counts[0] = (int64_t)v[0];
+    counts[1] = 2 * (int64_t)v[1] - (int64_t)L;
+    counts[2] = 2 * (int64_t)v[2] - (int64_t)L;
+    if (counts[0] || counts[1] || counts[2]) {
+        snprintf(s->err, sizeof s->err,
+                 "invalid surface: %lld open plaquettes, row-0 slope sum %lld, column-0 slope sum "
+                 "%lld", (long long)counts[0], (long long)counts[1], (long long)counts[2]);
+        return KPZ_ESTATE;
+    }
     return KPZ_OK;
 }
 

@@ -103,6 +103,7 @@ def test_init_validates_before_device_work(kpz):
                       1 << 20, None) == kpz.KPZ_EINVAL
     assert L.kpz_sweep(None, 1) == kpz.KPZ_EINVAL
     assert L.kpz_roughness(None, None, None, None) == kpz.KPZ_EINVAL
+    assert L.kpz_check_invariants(None, None) == kpz.KPZ_EINVAL
     L.kpz_destroy(None)
 
 

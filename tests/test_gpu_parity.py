@@ -317,6 +317,7 @@ def _sampled_blocks(gpu, oracle_lib, L, B, p, q, seed, n_mcs):
             assert np.array_equal(gsy, bsy), (t, bx, by)
         m = sim.roughness()   # raises KPZ_ESTATE if words and flip count disagree
         assert m.W2 > 0.25
+    assert sim.check_invariants() == (0, 0, 0)   # the whole surface, on the device
     sim.close()
 
 

@@ -146,3 +146,63 @@ def test_checker_rejects_values_other_than_plus_minus_one(oracle_lib):
     sy[2, 2] = 3
     with pytest.raises(AssertionError):
         oracle_lib.check_invariants(sx, sy)
+
+
+# ------------------------------------------------- the invariant counts
+
+def test_counts_zero_on_valid_surfaces(oracle_lib):
+    sx, sy = _valid_surface(oracle_lib, L=16, n=5)
+    assert oracle_lib.invariant_counts(sx, sy) == (0, 0, 0)
+    st = oracle_lib.SlopeState(32)
+    assert oracle_lib.invariant_counts(st.sx, st.sy) == (0, 0, 0)
+
+
+def test_counts_of_one_flipped_bond(oracle_lib):
+    """A flipped sigma_x bond borders exactly two plaquettes (the one above
+    it and the one below it), a flipped sigma_y bond the one to its left and
+    the one to its right; the row or column sum moves by 2 when the bond
+    lies in row 0 or column 0.  Bonds on the periodic edges included."""
+    L = 16
+    for (y, x) in [(3, 5), (0, 7), (L - 1, L - 1), (0, 0), (9, 15), (9, 16 % L)]:
+        sx, sy = _valid_surface(oracle_lib, L=L)
+        sx[y, x] = -sx[y, x]
+        open_, r0, c0 = oracle_lib.invariant_counts(sx, sy)
+        assert open_ == 2
+        assert r0 == (2 * sx[0, x] if y == 0 else 0)
+        assert c0 == 0
+        sx, sy = _valid_surface(oracle_lib, L=L)
+        sy[y, x] = -sy[y, x]
+        open_, r0, c0 = oracle_lib.invariant_counts(sx, sy)
+        assert open_ == 2
+        assert r0 == 0
+        assert c0 == (2 * sy[y, 0] if x == 0 else 0)
+
+
+def test_counts_of_a_tilted_plane(oracle_lib):
+    """A plane tilted along y closes every plaquette but sums to L along
+    every column."""
+    L = 8
+    x = np.arange(L)
+    sx = np.tile(np.where(x % 2 == 0, 1, -1), (L, 1)).astype(np.int8)
+    sy = np.ones((L, L), np.int8)
+    assert oracle_lib.invariant_counts(sx, sy) == (0, 0, L)
+    assert oracle_lib.invariant_counts(sy.T.copy(), sx.T.copy()) == (0, L, 0)
+
+
+def test_counts_agree_with_the_checker(oracle_lib):
+    """Random +-1 perturbations: the counts are all zero exactly when the
+    checker accepts the surface."""
+    rng = np.random.default_rng(7)
+    for trial in range(40):
+        sx, sy = _valid_surface(oracle_lib, L=8, n=2, seed=trial + 1)
+        for _ in range(int(rng.integers(0, 3))):
+            a = sx if rng.integers(2) else sy
+            i, j = rng.integers(8, size=2)
+            a[i, j] = -a[i, j]
+        zero = oracle_lib.invariant_counts(sx, sy) == (0, 0, 0)
+        try:
+            oracle_lib.check_invariants(sx, sy)
+            ok = True
+        except AssertionError:
+            ok = False
+        assert zero == ok
