@@ -69,7 +69,7 @@ typedef enum {
  *            desorption (maximum -> minimum), 0 <= p, q <= 1 (Sec. 2.1).
  *            They are applied as integer thresholds floor(p * 2^32)
  *            (p = 1 -> 2^32) against 32-bit uniforms.
- *   seed     64-bit Philox4x32-10 key.
+ *   seed     64-bit Philox4x32-7 key (seven rounds).
  *   block_x, block_y
  *            dead-border block shape of the device layer (Sec. 3), sites;
  *            both divide L.  block_x: a multiple of 16 (whole words per
@@ -86,7 +86,7 @@ typedef enum {
  *            must be 4 x 4 (four 2 x 2 cells per tile, 16 single-hit steps
  *            per MCS); 0 = default (4).
  *   moves    how often the dead-border origin moves per MCS (Sec. 3: the
- *            origin is moved randomly "after some time"): 1, 2, 4, 8 or 16;
+ *            origin moves to a new random place from time to time): 1, 2, 4, 8 or 16;
  *            0 = default (1).  Each MCS then runs `moves` residencies of
  *            16 / moves single-hit steps, each with its own random origin
  *            (block residency 1 / moves MCS; every residency reads and

@@ -63,6 +63,9 @@ def lib():
         u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
         c = ctypes
         L.or_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.or_philox4x32_r.argtypes = [u32p, u32p, ctypes.c_int, u32p]
+        L.or_tag_rounds.argtypes = [ctypes.c_uint32]
+        L.or_tag_rounds.restype = ctypes.c_int
         L.or_draw.argtypes = [c.c_uint64, c.c_uint32, c.c_uint32, c.c_uint64, c.c_uint32, u32p]
         L.or_flat.argtypes = [c.c_int, i8p, i8p]
         L.or_rs_heights_run.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
@@ -116,6 +119,20 @@ def philox(ctr, key) -> np.ndarray:
     out = np.zeros(4, np.uint32)
     lib().or_philox4x32_10(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), out)
     return out
+
+
+def philox_rounds(ctr, key, rounds: int) -> np.ndarray:
+    """Philox4x32 with the given number of rounds (philox() is rounds = 10)."""
+    out = np.zeros(4, np.uint32)
+    lib().or_philox4x32_r(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), int(rounds),
+                          out)
+    return out
+
+
+def tag_rounds(tag: int) -> int:
+    """Philox rounds of a draw tag: 7 for the 2+1-d lattice dynamics, 10
+    for the ring and KMC."""
+    return int(lib().or_tag_rounds(int(tag)))
 
 
 def draw(seed: int, tag: int, t: int, idx: int, sub: int) -> np.ndarray:

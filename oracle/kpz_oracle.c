@@ -69,11 +69,14 @@
 
 /* ---------------------------------------------------------------- Philox */
 
-void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+/* R rounds of Philox4x32 on counter ctr with key key, the key advanced by
+ * its Weyl increments before each round after the first.  R = 10 is the
+ * published default; the 2+1-d lattice dynamics draw with R = 7. */
+void or_philox4x32_r(const uint32_t ctr[4], const uint32_t key[2], int rounds, uint32_t out[4])
 {
     uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
     uint32_t k0 = key[0], k1 = key[1];
-    for (int round = 0; round < 10; ++round) {
+    for (int round = 0; round < rounds; ++round) {
         uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
         uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
         uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
@@ -89,11 +92,26 @@ void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    or_philox4x32_r(ctr, key, 10, out);
+}
+
+/* Rounds per tag: the draws of the 2+1-d lattice dynamics (its decomposed
+ * schedules, their random-sequential and stratified references: tags 1..6
+ * and 13..15) use Philox4x32-7, the smallest round count its authors found
+ * to pass the BigCrush battery; the ring (7..12) and KMC (16..) draws keep
+ * the ten-round default. */
+int or_tag_rounds(uint32_t tag)
+{
+    return ((tag >= 1u && tag <= 6u) || (tag >= 13u && tag <= 15u)) ? 7 : 10;
+}
+
 void or_draw(uint64_t seed, uint32_t tag, uint32_t t, uint64_t idx, uint32_t sub, uint32_t w[4])
 {
     uint32_t ctr[4] = { (uint32_t)idx, (uint32_t)(idx >> 32), t, (tag << 24) | (sub & 0xFFFFFFu) };
     uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
-    or_philox4x32_10(ctr, key, w);
+    or_philox4x32_r(ctr, key, or_tag_rounds(tag), w);
 }
 
 /* Acceptance threshold: an attempt with 32-bit uniform u is accepted iff

@@ -24,7 +24,7 @@
 // (kpz_dt_kernel, one launch per block set), the batched ensemble and the
 // job pool (kpz_batch_round_kernel), block residency below one MCS.
 //
-// Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the seed,
+// Random numbers: Philox4x32-7 (Salmon et al., SC'11) keyed by the seed,
 // counter (idx_lo, idx_hi, t, tag << 24 | sub).  Tile row ty of block b is
 // cut into row groups of 32 tiles, G = (b nty + ty) nqx + tx / 32, and tile
 // tx owns bit pi(tx) = 8 (tx mod 4) + (tx mod 32) / 4 of every word drawn for
@@ -62,6 +62,7 @@ namespace {
 
 using kpzdev::philox;
 using kpzdev::philox_v;
+using kpzdev::LATTICE_ROUNDS;
 using kpzdev::U4;
 
 constexpr uint32_t TAG_ORIGIN = 1, TAG_SET = 2, TAG_SITE = 3, TAG_ACC1 = 4, TAG_ACC2 = 5;
@@ -160,7 +161,7 @@ struct Rot {
 __device__ __forceinline__ uint32_t rot_sites(const Rot &r)
 {
     if (!r.valid) return 0u;
-    const U4 w = philox(r.res, 0u, r.t, TAG_ORIGIN << 24, r.seed_lo, r.seed_hi);
+    const U4 w = philox<LATTICE_ROUNDS>(r.res, 0u, r.t, TAG_ORIGIN << 24, r.seed_lo, r.seed_hi);
     return (uint32_t)(((uint64_t)w.x * r.Bx) >> 32) & 63u;
 }
 
@@ -301,7 +302,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t bx = b % a.nbx, by = b / a.nbx;
 
-    const U4 wo = philox(a.res, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
+    const U4 wo = philox<LATTICE_ROUNDS>(a.res, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
     const uint32_t ox = (uint32_t)(((uint64_t)wo.x * a.Bx) >> 32);
     const uint32_t oy = (uint32_t)(((uint64_t)wo.y * a.By) >> 32);
     uint32_t gx0 = ox + bx * a.Bx;
@@ -519,7 +520,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
     d.G = (uint32_t)G;
 
     // ---- work-group layer: single-hit steps k0 .. k1 - 1
-    const uint32_t setw = philox(b, 0u, a.t, (TAG_SET << 24) | a.res, a.seed_lo, a.seed_hi).x;
+    const uint32_t setw = philox<LATTICE_ROUNDS>(b, 0u, a.t, (TAG_SET << 24) | a.res, a.seed_lo, a.seed_hi).x;
     const uint32_t k0 = a.res * a.nsteps, k1 = k0 + a.nsteps;
     const bool xn = XN == 2 ? c.xn != 0u : (XN == 1 || XN == 3);
     constexpr bool XBC = DT || XN != 0;        // the group boundary bond is kept (hl)
@@ -533,7 +534,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
 #pragma unroll
             for (uint32_t j = 0; j < 4; ++j) {
                 if (j < d.nl) {
-                    const U4 v = philox_v((uint32_t)G, (uint32_t)(G >> 32), a.t,
+                    const U4 v = philox_v<LATTICE_ROUNDS>((uint32_t)G, (uint32_t)(G >> 32), a.t,
                                         (TAG_ACC1 << 24) | (4u * kq + j), a.seed_lo, a.seed_hi);
                     l1[j][0] = v.x; l1[j][1] = v.y; l1[j][2] = v.z; l1[j][3] = v.w;
                 }
@@ -544,7 +545,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
             const uint32_t k = 4u * kq + kr;
             if (k < k0 || k >= k1) continue;
             if ((kr & 1u) == 0 || k == k0)
-                sw = philox_v((uint32_t)G, (uint32_t)(G >> 32), a.t, (TAG_SITE << 24) | (k >> 1),
+                sw = philox_v<LATTICE_ROUNDS>((uint32_t)G, (uint32_t)(G >> 32), a.t, (TAG_SITE << 24) | (k >> 1),
                             a.seed_lo, a.seed_hi);
             const uint32_t RX = (kr & 1u) ? sw.z : sw.x;
             const uint32_t RY = (kr & 1u) ? sw.w : sw.y;
@@ -790,7 +791,7 @@ __device__ __forceinline__ void merge_one(const SweepArgs &a, uint32_t ox, uint6
 
 __device__ __forceinline__ uint32_t origin_x(const SweepArgs &a)
 {
-    const U4 wo = philox(a.res, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
+    const U4 wo = philox<LATTICE_ROUNDS>(a.res, 0u, a.t, TAG_ORIGIN << 24, a.seed_lo, a.seed_hi);
     return (uint32_t)(((uint64_t)wo.x * a.Bx) >> 32);
 }
 
@@ -824,7 +825,7 @@ constexpr uint32_t TAG_DTORDER = 13;
 __device__ __forceinline__ uint32_t dt_set(uint32_t t, uint32_t seed_lo, uint32_t seed_hi,
                                            uint32_t phase)
 {
-    uint32_t idx = (uint32_t)(((uint64_t)philox(0u, 0u, t, TAG_DTORDER << 24, seed_lo,
+    uint32_t idx = (uint32_t)(((uint64_t)philox<LATTICE_ROUNDS>(0u, 0u, t, TAG_DTORDER << 24, seed_lo,
                                                 seed_hi).x * 24u) >> 32);
     uint32_t pool = 0x3210u;             // remaining set codes, one per nibble
     uint32_t n = 4, c = 0;
@@ -1007,7 +1008,7 @@ __device__ __forceinline__ int wave_incl_sum(int x)
 
 // Moments of one row in stored order, taken by a group of G lanes (G =
 // row_lanes(W), the group's lanes gl = 0..G-1 aligned to G in the wave), NV
-// consecutive words per lane and chunk (NV = 16 only for W % 1024 == 0, where
+// consecutive words per lane and chunk (NV = 8 only for W % 512 == 0, where
 // G = 64 and every lane is full): returns (A_y, B_y), the sums of the
 // heights relative to the row's first stored site and of their squares, in
 // lane gl = 0 and, in `first`, the row's first stored word.  A row stored
@@ -1022,7 +1023,7 @@ __device__ __forceinline__ void row_chunk(const uint32_t *rp, uint32_t W, uint32
                                           uint32_t (&v)[NV], int &nv)
 {
     nv = 0;
-    if (NV == 16) {
+    if (NV == 8) {
 #pragma unroll
         for (int j = 0; j < NV / 4; ++j) {
             const uint4 q = *(const uint4 *)(rp + idx + 4 * j);
@@ -1051,7 +1052,7 @@ __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, cons
                                             uint32_t gl, uint32_t G, long long &A, long long &B,
                                             uint32_t &first)
 {
-    static_assert(NV == 4 || NV == 16, "four or sixteen words per lane");
+    static_assert(NV == 4 || NV == 8, "four or eight words per lane");
     const uint32_t copy4x2 = (threadIdx.x & (C - 1u)) * 0x40004u;   // work-groups of whole waves
     long long s1 = 0, s2 = 0;
     int carry = 0;
@@ -1065,7 +1066,7 @@ __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, cons
         LaneSums ls = {0, 0, 0, 0, 0u};
 #pragma unroll
         for (int m = 0; m < NV; ++m)
-            if (NV == 16 || m < nv) add_word<C>(ls, v[m], lut, copy4x2);
+            if (NV == 8 || m < nv) add_word<C>(ls, v[m], lut, copy4x2);
         int l1, l2;
         lane_totals(ls, 2 * nv, l1, l2);
         const int o = ls.o;
@@ -1095,10 +1096,12 @@ __device__ __forceinline__ void row_moments(const uint32_t *rp, uint32_t W, cons
     B = s2;
 }
 
-// One wave per 64 / row_lanes(W) rows.
-__global__ __launch_bounds__(256) void kpz_row_moments_kernel(const uint32_t *words, uint32_t L,
-                                                              uint32_t W, long long *rowA,
-                                                              long long *rowB)
+// One wave per 64 / row_lanes(W) rows; work-groups of ROW_WAVES waves share
+// one table, so that its LDS (32 KiB) admits eight waves per SIMD.
+constexpr uint32_t ROW_WAVES = 8;
+__global__ __launch_bounds__(64 * ROW_WAVES) __attribute__((amdgpu_waves_per_eu(8)))
+void kpz_row_moments_kernel(const uint32_t *words, uint32_t L, uint32_t W, long long *rowA,
+                            long long *rowB)
 {
     __shared__ uint32_t lut[LUT_WORDS];
     fill_row_lut(lut);
@@ -1108,13 +1111,14 @@ __global__ __launch_bounds__(256) void kpz_row_moments_kernel(const uint32_t *wo
     const uint32_t G = row_lanes(W), R = 64u / G;
     const uint32_t gl = lane & (G - 1u);
     const uint32_t tasks = (L + R - 1u) / R;
-    for (uint32_t task = blockIdx.x * 4u + wv; task < tasks; task += gridDim.x * 4u) {
+    for (uint32_t task = blockIdx.x * ROW_WAVES + wv; task < tasks;
+         task += gridDim.x * ROW_WAVES) {
         const uint32_t row = task * R + lane / G;
         if (row < L) {   // a whole lane group is in or out
             long long A, B;
             uint32_t first;
-            if ((W & 1023u) == 0)
-                row_moments<16>(words + (size_t)row * W, W, lut, gl, G, A, B, first);
+            if ((W & 511u) == 0)
+                row_moments<8>(words + (size_t)row * W, W, lut, gl, G, A, B, first);
             else
                 row_moments<4>(words + (size_t)row * W, W, lut, gl, G, A, B, first);
             if (gl == 0) {
@@ -1123,6 +1127,13 @@ __global__ __launch_bounds__(256) void kpz_row_moments_kernel(const uint32_t *wo
             }
         }
     }
+}
+
+// Work-groups of a row-moment launch over `tasks` wave tasks.
+__host__ __forceinline__ uint32_t row_grid(uint32_t tasks)
+{
+    const uint32_t g = (tasks + ROW_WAVES - 1u) / ROW_WAVES;
+    return g < 2048u ? g : 2048u;
 }
 
 // A lattice buffer in the documented layout from one stored rotated by
@@ -1820,8 +1831,8 @@ __global__ __launch_bounds__(256) void kpz_batch_rows_kernel(const MemberRows *m
             long long A, B;
             uint32_t first;
             const uint32_t *rp = cur + (size_t)row * m.W;
-            if ((m.W & 1023u) == 0)
-                row_moments<16>(rp, m.W, lut, lane & (G - 1u), G, A, B, first);
+            if ((m.W & 511u) == 0)
+                row_moments<8>(rp, m.W, lut, lane & (G - 1u), G, A, B, first);
             else
                 row_moments<4>(rp, m.W, lut, lane & (G - 1u), G, A, B, first);
             if ((lane & (G - 1u)) == 0) {
@@ -2690,9 +2701,8 @@ kpz_status kpz_roughness(kpz_sim *s, int64_t *S1o, int64_t *S2o, double *W2o)
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(s, e, "kpz_roughness launch");
     } else {
-        const uint32_t nt = row_tasks(L);
-        const uint32_t rgrid = (nt + 3) / 4 < 4096 ? (nt + 3) / 4 : 4096;
-        hipLaunchKernelGGL(kpz_row_moments_kernel, dim3(rgrid), dim3(256), 0, s->stream,
+        hipLaunchKernelGGL(kpz_row_moments_kernel, dim3(row_grid(row_tasks(L))),
+                           dim3(64 * ROW_WAVES), 0, s->stream,
                            s->buf[s->cur], L, W, ws_rowA(s), ws_rowB(s));
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(s, e, "kpz_roughness launch");
@@ -3425,9 +3435,8 @@ kpz_status kpz_roughness_noalloc(const uint32_t *d_words, int64_t L, int64_t net
         hipLaunchKernelGGL(kpz_roughness_small_kernel, dim3(1), dim3(1024), 0, st, d_words, Lu, W,
                            (const long long *)slots, res, none);
     } else {
-        const uint32_t nt = row_tasks(Lu);
-        const uint32_t rgrid = (nt + 3) / 4 < 4096 ? (nt + 3) / 4 : 4096;
-        hipLaunchKernelGGL(kpz_row_moments_kernel, dim3(rgrid), dim3(256), 0, st, d_words, Lu, W,
+        hipLaunchKernelGGL(kpz_row_moments_kernel, dim3(row_grid(row_tasks(Lu))),
+                           dim3(64 * ROW_WAVES), 0, st, d_words, Lu, W,
                            rowA, rowB);
         hipLaunchKernelGGL(kpz_finalize_kernel, dim3(1), dim3(1024), 0, st, Lu,
                            (const long long *)rowA, (const long long *)rowB,

@@ -1,5 +1,5 @@
 // kpz_device.h -- device helpers shared by the lattice and ring kernels:
-// the Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw,
+// the Philox4x32 counter-based generator (Salmon, Moraes, Dror, Shaw,
 // "Parallel random numbers: as easy as 1, 2, 3", SC'11) and byte-wise
 // comparisons used by the SWAR acceptance tests.
 #ifndef KPZ_DEVICE_H_
@@ -14,14 +14,21 @@ struct U4 {
     uint32_t x, y, z, w;
 };
 
-// Ten rounds of Philox4x32 on counter (c0, c1, c2, c3) with key (k0, k1).
+// Rounds of the 2+1-d lattice dynamics' draws: seven, the smallest count
+// for which the generator's authors found Philox4x32 to pass the BigCrush
+// battery (their default, ten, keeps a safety margin and is what the ring
+// and KMC draws use).
+constexpr int LATTICE_ROUNDS = 7;
+
+// R rounds of Philox4x32 on counter (c0, c1, c2, c3) with key (k0, k1).
 // Plain xors: with a wave-uniform counter the compiler keeps the whole call
 // on the scalar unit.
+template <int R = 10>
 __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                      uint32_t k0, uint32_t k1)
 {
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
+    for (int r = 0; r < R; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
         const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
@@ -39,11 +46,12 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 // The same generator for per-lane counters: each round's two three-input
 // xors as single v_bitop3_b32 instructions.  Vector-only, so a wave-uniform
 // counter belongs to philox() above.
+template <int R = 10>
 __device__ __forceinline__ U4 philox_v(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                        uint32_t k0, uint32_t k1)
 {
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
+    for (int r = 0; r < R; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
         const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);

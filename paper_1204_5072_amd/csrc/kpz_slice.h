@@ -169,7 +169,7 @@ __device__ __forceinline__ uint32_t accept(uint32_t mn, uint32_t mx, const uint3
     }
     for (uint32_t jb = 4; jb < d.nl; jb += 4) {
         if (!__any((eqP | eqQ) != 0u)) break;
-        const U4 w = philox_v(d.G, 0u, d.t, (TAG_ACC2 << 24) | (8u * k + jb / 4u - 1u), d.seed_lo,
+        const U4 w = philox_v<kpzdev::LATTICE_ROUNDS>(d.G, 0u, d.t, (TAG_ACC2 << 24) | (8u * k + jb / 4u - 1u), d.seed_lo,
                               d.seed_hi);
         const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll

@@ -1,9 +1,11 @@
-"""Pins for the oracle's Philox4x32-10 (Salmon et al., SC'11).
+"""Pins for the oracle's Philox4x32 (Salmon et al., SC'11).
 
-The oracle writes the generator out from its published definition; here it is
-compared with an independent implementation (rocRAND's host-callable engine,
-compiled from its public header), plus basic uniformity checks of the draws
-the schedule consumes.
+The oracle writes the generator out from its published definition, with a
+round count: ten (the published default) for the ring and KMC draws, seven
+for the 2+1-d lattice dynamics.  The ten-round generator is compared with an
+independent implementation (rocRAND's host-callable engine, compiled from its
+public header); the seven-round one is shown to be its first seven rounds.
+Basic uniformity checks of the draws the schedule consumes follow.
 """
 import os
 import shutil
@@ -60,7 +62,36 @@ def test_draw_counter_layout(oracle_lib):
     seed, tag, t, idx, sub = 0x1234_5678_9ABC_DEF0, 3, 77, 0x5_0000_0007, 0x00ABCD
     ctr = [idx & 0xFFFFFFFF, idx >> 32, t, (tag << 24) | sub]
     key = [seed & 0xFFFFFFFF, seed >> 32]
-    assert np.array_equal(oracle_lib.draw(seed, tag, t, idx, sub), oracle_lib.philox(ctr, key))
+    assert oracle_lib.tag_rounds(tag) == 7
+    assert np.array_equal(oracle_lib.draw(seed, tag, t, idx, sub),
+                          oracle_lib.philox_rounds(ctr, key, 7))
+    # the ring's and KMC's tags keep ten rounds
+    for tag in (7, 8, 10, 12, 16, 21):
+        ctr = [idx & 0xFFFFFFFF, idx >> 32, t, (tag << 24) | sub]
+        assert np.array_equal(oracle_lib.draw(seed, tag, t, idx, sub), oracle_lib.philox(ctr, key))
+    assert [oracle_lib.tag_rounds(g) for g in range(1, 22)] == \
+        [7] * 6 + [10] * 6 + [7] * 3 + [10] * 6
+
+
+def test_seven_rounds_are_the_first_seven_of_ten(oracle_lib, rocrand_ref):
+    """Philox4x32-7 is the ten-round generator (pinned to rocRAND above)
+    stopped after its seventh round: continuing a seven-round output for
+    three rounds with the key advanced by seven Weyl increments gives
+    rocRAND's ten-round output."""
+    rng = np.random.default_rng(777)
+    cases = []
+    for _ in range(64):
+        seed = int(rng.integers(0, 2**64, dtype=np.uint64))
+        c = [int(v) for v in rng.integers(0, 2**32, size=4, dtype=np.uint64)]
+        c[1] &= 2**30 - 1
+        cases.append((seed, c))
+    ref = rocrand_ref([f"{seed} {c[2] | (c[3] << 32)} {c[0] | (c[1] << 32)}" for seed, c in cases])
+    for (seed, c), r in zip(cases, ref):
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        mid = oracle_lib.philox_rounds(c, key, 7)
+        key7 = [(key[0] + 7 * 0x9E3779B9) & 0xFFFFFFFF, (key[1] + 7 * 0xBB67AE85) & 0xFFFFFFFF]
+        assert tuple(int(v) for v in oracle_lib.philox_rounds(mid, key7, 3)) == r
+        assert not np.array_equal(mid, np.asarray(r, np.uint32))
 
 
 def test_draw_uniformity(oracle_lib):
