@@ -96,7 +96,7 @@ def lib():
         L.or_flat1d.argtypes = [c.c_int, i8p]
         L.or_dt_run.argtypes = [c.c_int, c.c_double, c.c_double, c.c_uint64,
                                 c.c_int, c.c_int, c.c_int, c.c_int,
-                                c.c_uint32, c.c_int, i8p, i8p, i64p, i64p, c.c_int]
+                                c.c_uint32, c.c_int, i8p, i8p, i64p, i64p, c.c_int, c.c_int]
         L.or_dt_perm.argtypes = [c.c_uint64, c.c_uint32, c.POINTER(c.c_int * 4)]
         for f in ("or_flat", "or_rs_heights_run", "or_rs_slopes_run", "or_dd_run", "or_dd_run_par",
                   "or_strat_run",
@@ -192,11 +192,17 @@ class SlopeState:
         return self
 
     def run_dt(self, n_mcs: int, p: float, q: float, seed: int, block, tile=(4, 4),
-               check: bool = False) -> "SlopeState":
+               check: bool = False, ahead: int = 0) -> "SlopeState":
         """n_mcs MCS with double tiling at the device layer too (the four
-        block sets in a random order per MCS, no dead border)."""
+        block sets in a random order per MCS, no dead border).  ahead = 1: a
+        set whose successor in the order is its diagonal partner runs
+        together with it, the two interleaved step by step (Sec. 3.2,
+        blocks updated ahead of time); exactly the plain result.  ahead = 2
+        pairs x-neighbour sets the same way, which is not exact (a negative
+        control for the tests)."""
         rc = lib().or_dt_run(self.L, p, q, seed, block[0], block[1], tile[0], tile[1], self.t,
-                             n_mcs, self.sx, self.sy, self.h00, self.net, int(check))
+                             n_mcs, self.sx, self.sy, self.h00, self.net, int(check),
+                             int(ahead))   # 2: the x-neighbour control (not exact)
         _check(rc, "dt_run")
         self.t += n_mcs
         return self

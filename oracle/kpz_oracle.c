@@ -812,6 +812,16 @@ int or_flat1d(int L, int8_t *s)
  * or bottom row flips a slope stored at a site of the (idle) block to the
  * left or below.  Blocks of one set share no slope, so a phase is the same
  * whether its blocks run in parallel or one after the other.
+ *
+ * Blocks of the next set updated ahead of time (Sec. 3.2, the KMC code's
+ * way to fill the device; Sec. 4, the fraction f): with `ahead`, a phase
+ * whose next set is its diagonal partner (c ^ 3: both block coordinates of
+ * the other parity) takes that set too.  A block's update touches its own
+ * sites, the sigma_x column of the block to its left and the sigma_y row of
+ * the block below, so diagonal neighbours touch no common slope and the two
+ * sets commute.  This mode runs them interleaved, each step first over the
+ * partner's blocks and then over the current set's, an order unlike the
+ * plain one; the result must equal the plain run exactly.
  */
 #define OR_TAG_DTORDER 13u
 
@@ -841,7 +851,7 @@ int or_dt_perm(uint64_t seed, uint32_t t, int perm[4])
 
 int or_dt_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, int Ty,
               uint32_t t0, int n_mcs, int8_t *sx, int8_t *sy, int64_t *h00, int64_t *net,
-              int check)
+              int check, int ahead)
 {
     if (!dd_validate(L, Bx, By, Tx, Ty, 1) || n_mcs < 0) return OR_EINVAL;
     const int nbx = L / Bx, nby = L / By;
@@ -864,8 +874,19 @@ int or_dt_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
         int perm[4];
         or_dt_perm(seed, t, perm);
         for (int ph = 0; ph < 4 && status == OR_OK; ++ph) {
-            const int csx = perm[ph] & 1, csy = perm[ph] >> 1;
-            for (int k = 0; k < S && status == OR_OK; ++k, ++step_id) {
+            /* sets of this phase: the partner first when it is taken ahead */
+            int sets[2] = { perm[ph], -1 }, nsets = 1;
+            /* ahead = 2 pairs a set with its x neighbour set (c ^ 1) instead:
+             * not exact, the negative control of the tests */
+            const int partner = perm[ph] ^ (ahead == 2 ? 1 : 3);
+            if (ahead && ph + 1 < 4 && perm[ph + 1] == partner) {
+                sets[0] = perm[ph + 1];
+                sets[1] = perm[ph];
+                nsets = 2;
+            }
+            for (int k = 0; k < S && status == OR_OK; ++k, ++step_id)
+              for (int si = 0; si < nsets; ++si) {
+                const int csx = sets[si] & 1, csy = sets[si] >> 1;
                 for (int by = csy; by < nby; by += 2)
                     for (int bx = csx; bx < nbx; bx += 2) {
                         const int b = by * nbx + bx;
@@ -895,6 +916,7 @@ int or_dt_run(int L, double p, double q, uint64_t seed, int Bx, int By, int Tx, 
                             }
                     }
             }
+            if (nsets == 2) ++ph;   /* the partner's phase is done */
         }
     }
     free(stamp);

@@ -119,3 +119,28 @@ def test_dt_agrees_with_random_sequential(oracle_lib):
     print("DT vs RS", np.round(rel, 3), b_dt, b_rs)
     assert np.all(np.abs(rel) < 0.08), rel
     assert abs(b_dt - b_rs) < 0.03
+
+
+# Blocks of the next set updated ahead of time (Sec. 3.2; Sec. 4, the
+# fraction f of full use): a set and its diagonal partner touch no common
+# slope, so running them together, interleaved step by step with the
+# partner's blocks first, must give the plain schedule's lattice bit for bit.
+# Pairing x-neighbour sets the same way must not (the control shows the
+# comparison can fail).
+@pytest.mark.parametrize("L,block,tile,p,q", [(32, (8, 8), (4, 4), 1.0, 0.0),
+                                              (64, (16, 8), (4, 4), 0.6, 0.3),
+                                              (64, (32, 16), (4, 4), 1.0, 0.25),
+                                              (16, (8, 8), (4, 4), 0.8, 0.1),
+                                              (16, (4, 4), (2, 2), 1.0, 0.0),
+                                              (8, (2, 2), (2, 2), 0.7, 0.2)])
+def test_dt_ahead_equals_plain_schedule(oracle_lib, L, block, tile, p, q):
+    n = 24
+    merged = sum(any(b == a ^ 3 for a, b in zip(pm, pm[1:]))
+                 for pm in (oracle_lib.dt_perm(11, t) for t in range(n)))
+    assert merged >= n // 3          # the pairing occurs in about 2/3 of the MCS
+    plain = oracle_lib.SlopeState(L).run_dt(n, p, q, 11, block, tile)
+    ahead = oracle_lib.SlopeState(L).run_dt(n, p, q, 11, block, tile, check=True, ahead=1)
+    assert np.array_equal(plain.sx, ahead.sx) and np.array_equal(plain.sy, ahead.sy)
+    assert plain.h00[0] == ahead.h00[0] and plain.net[0] == ahead.net[0]
+    ctrl = oracle_lib.SlopeState(L).run_dt(n, p, q, 11, block, tile, ahead=2)
+    assert not (np.array_equal(plain.sx, ctrl.sx) and np.array_equal(plain.sy, ctrl.sy))
