@@ -474,6 +474,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--device-dt", action="store_true",
                     help="double tiling at the device layer instead of dead borders")
+    ap.add_argument("--dt-ahead", action="store_true",
+                    help="device-layer double tiling with a set and its diagonal partner "
+                         "sharing a launch where they follow each other (implies --device-dt)")
     ap.add_argument("--in-place", action="store_true",
                     help="update the lattice in place (no second lattice buffer)")
     ap.add_argument("--moves", type=int, default=1,
@@ -518,11 +521,12 @@ def main():
     import paper_1204_5072_amd as kpz
 
     L, M = args.L, args.mcs_per_step
+    args.device_dt = args.device_dt or args.dt_ahead
     block = tuple(args.block) if args.block else ((512, 64) if args.device_dt else (256, 128))
     print(f"bench: L={L} block={block} p={args.p} q={args.q} seed={args.seed} "
           f"steps={args.steps} warmup={args.warmup} mcs/step={M}", file=sys.stderr, flush=True)
     sim = kpz.Sim(L, args.p, args.q, args.seed, block, moves=args.moves, in_place=args.in_place,
-                  device_dt=args.device_dt)
+                  device_dt=args.device_dt or args.dt_ahead, dt_ahead=args.dt_ahead)
     stream = sim.stream
     for _ in range(args.warmup):
         sim.sweep(M)
@@ -557,7 +561,7 @@ def main():
     sweep_s = sweep_ms / 1e3
     achieved_gbs = BYTES_PER_ATTEMPT * per_launch_attempts / sweep_s / 1e9
     traffic, valu = (sweep_counters(block, args.in_place, args.device_dt)
-                     if (L == 65536 and args.moves == 1) else (None, None))
+                     if (L == 65536 and args.moves == 1 and not args.dt_ahead) else (None, None))
     ceiling = valu_ceiling()
     valu_rate = valu / sweep_s if valu else None
     line = {
@@ -598,7 +602,8 @@ def main():
             # one MCS = one sweep launch (two-buffer mode), or the sweep launch
             # plus the straddling-word merge launch (in place), bracketed
             # together by the events
-            "kernel": ("kpz_dt_kernel x4 phases" if args.device_dt else
+            "kernel": ("kpz_dt_kernel, 2-4 launches per MCS" if args.dt_ahead else
+                       "kpz_dt_kernel x4 phases" if args.device_dt else
                        "kpz_sweep_kernel+kpz_merge_kernel" if args.in_place else "kpz_sweep_kernel"),
             "mean_launch_ms": sweep_ms,
             "valu_wave_instr_per_launch": valu,

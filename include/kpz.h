@@ -108,6 +108,15 @@ typedef enum {
  *            block reads and writes the slopes of its left neighbour's
  *            last column and its lower neighbour's top row (both idle in
  *            that launch).  Needs moves <= 1; not for batches or pools.
+ *            KPZ_FLAG_DT_AHEAD (with KPZ_FLAG_DEVICE_DT) updates the next
+ *            set ahead of time (Sec. 3.2; Sec. 4, the fraction f of full
+ *            use): where the next set in the MCS's order is the diagonal
+ *            partner of the current one (both block coordinates of the
+ *            other parity), the two share one launch.  Diagonal blocks
+ *            touch no common slope, so the results are identical to the
+ *            plain double tiling; an MCS takes two to four launches (three
+ *            on average).  The words at block corners that two blocks of
+ *            such a launch share are written by atomic xor.
  * The shape and `moves` change the sequence of updates, so results are
  * reproducible for identical (L, p, q, seed, block, tile, moves) only. */
 typedef struct {
@@ -125,6 +134,7 @@ typedef struct {
 
 #define KPZ_FLAG_IN_PLACE 1u
 #define KPZ_FLAG_DEVICE_DT 2u
+#define KPZ_FLAG_DT_AHEAD 4u
 
 typedef struct kpz_sim kpz_sim;
 
@@ -223,6 +233,13 @@ kpz_status kpz_sync_words(kpz_sim *sim);
 
 /* Frees the handle (not the caller's buffers).  NULL is ignored. */
 void kpz_destroy(kpz_sim *sim);
+
+/* Order of the four block sets in MCS t under double tiling at the device
+ * layer (Sec. 3: the sets updated in a sequence randomized every MCS):
+ * perm[0..3] (host memory, four int32 written) receives the set codes
+ * bx mod 2 + 2 (by mod 2) in launch order, drawn from the lattice's seed.
+ * Pure host computation.  KPZ_EINVAL if perm is NULL. */
+kpz_status kpz_dt_order(uint64_t seed, uint32_t t, int32_t *perm);
 
 /* Static text for a status code. */
 const char *kpz_status_str(kpz_status status);

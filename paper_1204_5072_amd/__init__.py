@@ -23,7 +23,7 @@ KPZ_OK, KPZ_EINVAL, KPZ_ESIZE, KPZ_EHIP, KPZ_ESTATE, KPZ_ERANGE = 0, -1, -2, -3,
 
 EXPORTED = ("kpz_workspace_bytes", "kpz_block_shape", "kpz_init", "kpz_sweep", "kpz_roughness", "kpz_height_moments",
             "kpz_get_state", "kpz_set_state", "kpz_sync_words", "kpz_check_invariants", "kpz_destroy", "kpz_status_str",
-            "kpz_last_error", "kpz_valu_probe", "kpz_roughness_noalloc",
+            "kpz_last_error", "kpz_valu_probe", "kpz_roughness_noalloc", "kpz_dt_order",
             "kpz_batch_sizes", "kpz_batch_init", "kpz_batch_word_offset", "kpz_batch_sweep",
             "kpz_batch_roughness", "kpz_batch_run", "kpz_batch_get_t", "kpz_batch_destroy",
             "kpz_batch_last_error", "kpz_batch_sync_words",
@@ -98,6 +98,7 @@ def lib() -> ctypes.CDLL:
                                          c.POINTER(c.c_double), c.POINTER(c.c_double)]
         L.kpz_height_moments.restype = c.c_int
         L.kpz_get_state.argtypes = [vp, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
+        L.kpz_dt_order.argtypes = [c.c_uint64, c.c_uint32, c.POINTER(c.c_int32 * 4)]
         L.kpz_set_state.argtypes = [vp, c.c_int64, c.c_int64]
         L.kpz_sync_words.argtypes = [vp]
         L.kpz_check_invariants.argtypes = [vp, c.POINTER(c.c_int64)]
@@ -156,6 +157,7 @@ def lib() -> ctypes.CDLL:
         L.kmc_last_error.restype = c.c_char_p
         for f in ("kpz_workspace_bytes", "kpz_init", "kpz_sweep", "kpz_roughness",
                   "kpz_get_state", "kpz_set_state", "kpz_sync_words", "kpz_check_invariants",
+                  "kpz_dt_order",
                   "kpz_batch_sizes",
                   "kpz_batch_init",
                   "kpz_batch_word_offset", "kpz_batch_sweep", "kpz_batch_roughness",
@@ -176,19 +178,34 @@ def status_str(status: int) -> str:
 
 KPZ_FLAG_IN_PLACE = 1
 KPZ_FLAG_DEVICE_DT = 2
+KPZ_FLAG_DT_AHEAD = 4
 
 
 def make_params(L: int, p: float = 1.0, q: float = 0.0, seed: int = 1,
                 block: Optional[Tuple[int, int]] = None, tile: Tuple[int, int] = (4, 4),
-                moves: int = 1, in_place: bool = False, device_dt: bool = False) -> kpz_params:
+                moves: int = 1, in_place: bool = False, device_dt: bool = False,
+                dt_ahead: bool = False) -> kpz_params:
     """Parameters of one lattice; ``moves`` = dead-border origin moves per
     MCS (block residency 1/moves MCS); ``in_place`` = update the lattice in
     place (no second lattice buffer in the workspace); ``device_dt`` =
-    double tiling instead of dead borders at the device layer."""
+    double tiling instead of dead borders at the device layer;
+    ``dt_ahead`` = with it, a set and its diagonal partner share a launch
+    when they follow each other in the MCS's order."""
     bx, by = block if block else (0, 0)
-    flags = (KPZ_FLAG_IN_PLACE if in_place else 0) | (KPZ_FLAG_DEVICE_DT if device_dt else 0)
+    flags = ((KPZ_FLAG_IN_PLACE if in_place else 0) | (KPZ_FLAG_DEVICE_DT if device_dt else 0)
+             | (KPZ_FLAG_DT_AHEAD if dt_ahead else 0))
     return kpz_params(L, float(p), float(q), int(seed), int(bx), int(by), int(tile[0]),
                       int(tile[1]), int(moves), flags)
+
+
+def dt_order(seed: int, t: int):
+    """Order of the four block sets in MCS t under device-layer double
+    tiling (the library's host-side draw)."""
+    arr = (ctypes.c_int32 * 4)()
+    st = lib().kpz_dt_order(int(seed), int(t), ctypes.byref(arr))
+    if st != KPZ_OK:
+        raise KPZError(st, "kpz_dt_order", "")
+    return list(arr)
 
 
 def workspace_bytes(params: kpz_params) -> int:
@@ -221,10 +238,11 @@ class Sim:
 
     def __init__(self, L: int, p: float = 1.0, q: float = 0.0, seed: int = 1,
                  block: Optional[Tuple[int, int]] = None, device="cuda", stream=None,
-                 moves: int = 1, in_place: bool = False, device_dt: bool = False):
+                 moves: int = 1, in_place: bool = False, device_dt: bool = False,
+                 dt_ahead: bool = False):
         import torch
         self.params = make_params(L, p, q, seed, block, moves=moves, in_place=in_place,
-                                  device_dt=device_dt)
+                                  device_dt=device_dt, dt_ahead=dt_ahead)
         self.L = L
         ws = workspace_bytes(self.params)
         self.device = torch.device(device)

@@ -147,6 +147,13 @@ struct SweepArgs {
     uint32_t *alt;
     uint32_t cur0;
     uint64_t P, Q;               // acceptance thresholds over 2^32
+    // Device-layer double tiling: 1 when the launch runs a block set together
+    // with its diagonal partner set.  The four words at a block's corners in
+    // its top row and in the halo row below it are then shared with a
+    // diagonal block of the same launch (each changes only its own bits) and
+    // are written by atomic xor of the change; every other word stays one
+    // block's.
+    uint32_t ahead;
 };
 
 // Storage rotation of a lattice buffer written in two-buffer mode: the x
@@ -671,6 +678,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
             if (i + 1 == nwg) lastA = A[i];
         const uint32_t prevLast = bperm(c.srcL4, lastA);
         if (!active) continue;
+        // DT with the diagonal partner set in the launch: the block's top
+        // row shares its corner words with the partner blocks above-left
+        // and above-right
+        const bool corner = DT && a.ahead && r == 3 && ty + 1u == a.nty;
         if (sh2 == 0) {
 #pragma unroll
             for (uint32_t i = 0; i < 8; ++i)
@@ -679,7 +690,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
                 // halo column in the previous word, bit 30
                 const uint32_t w = hw[r];
                 const uint32_t nwv = (w & ~(1u << 30)) | (((hx >> r) & 1u) << 30);
-                if (nwv != w) row[gw0 == 0 ? a.W - 1 : gw0 - 1] = nwv;
+                uint32_t *hp = row + (gw0 == 0 ? a.W - 1 : gw0 - 1);
+                if (nwv != w) {
+                    if (corner) atomicXor(hp, nwv ^ w);
+                    else *hp = nwv;
+                }
             }
             continue;
         }
@@ -691,13 +706,19 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
             row[gwq] = __builtin_amdgcn_alignbit(A[0], prevLast, 32u - sh2);
         } else if (DT) {
             const uint32_t hb = sh2 - 2u;
-            row[gwq] = (w0r[r] & lowm & ~(1u << hb)) | (((hx >> r) & 1u) << hb) | (A[0] << sh2);
+            const uint32_t nwv =
+                (w0r[r] & lowm & ~(1u << hb)) | (((hx >> r) & 1u) << hb) | (A[0] << sh2);
+            if (corner) atomicXor(row + gwq, nwv ^ w0r[r]);
+            else row[gwq] = nwv;
         } else {
             a.side[(size_t)gy * a.nbx + bx] = A[0] << sh2;
         }
         if (q + 1 == a.nqx) {
             if (DT) {
-                row[wrap_add(gwq, nwg, a.W)] = (wnr[r] & ~lowm) | (lastA >> (32u - sh2));
+                const uint32_t nwv = (wnr[r] & ~lowm) | (lastA >> (32u - sh2));
+                uint32_t *ep = row + wrap_add(gwq, nwg, a.W);
+                if (corner) atomicXor(ep, nwv ^ wnr[r]);
+                else *ep = nwv;
             } else {
                 a.side[((size_t)a.L + gy) * a.nbx + bx] = lastA >> (32u - sh2);
             }
@@ -722,23 +743,39 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, uint32_t b, uint
             const uint32_t gy = gy0 == 0 ? a.L - 1 : gy0 - 1;
             uint32_t *row = a.words + (size_t)gy * a.W;
             const uint32_t YM = 0xAAAAAAAAu;
+            // with the diagonal partner set in the launch, the halo row's
+            // end words are shared with the partner blocks below-left and
+            // below-right (atomic xor of this block's change)
+            const bool corner = a.ahead != 0u;
             if (sh2 == 0) {
 #pragma unroll
                 for (uint32_t i = 0; i < 8; ++i)
-                    if (i < nwg) row[wrap_add(gwq, i, a.W)] = (hr[i] & ~YM) | B[i];
+                    if (i < nwg) {
+                        const uint32_t nwv = (hr[i] & ~YM) | B[i];
+                        uint32_t *wp = row + wrap_add(gwq, i, a.W);
+                        if (corner && q + 1 == a.nqx && i + 1 == nwg) atomicXor(wp, nwv ^ hr[i]);
+                        else *wp = nwv;
+                    }
             } else {
 #pragma unroll
                 for (uint32_t i = 1; i < 8; ++i)
                     if (i < nwg)
                         row[wrap_add(gwq, i, a.W)] =
                             (hr[i] & ~YM) | __builtin_amdgcn_alignbit(B[i], B[i - 1], 32u - sh2);
-                if (q > 0)
+                if (q > 0) {
                     row[gwq] = (hr[0] & ~YM) | __builtin_amdgcn_alignbit(B[0], prevLastB, 32u - sh2);
-                else
-                    row[gwq] = (hr[0] & ~(YM & ~lowm)) | (B[0] << sh2);
-                if (q + 1 == a.nqx)
-                    row[wrap_add(gwq, nwg, a.W)] =
-                        (pick9(hr, nwg) & ~(YM & lowm)) | (lastB >> (32u - sh2));
+                } else {
+                    const uint32_t nwv = (hr[0] & ~(YM & ~lowm)) | (B[0] << sh2);
+                    if (corner) atomicXor(row + gwq, nwv ^ hr[0]);
+                    else row[gwq] = nwv;
+                }
+                if (q + 1 == a.nqx) {
+                    const uint32_t lw = pick9(hr, nwg);
+                    const uint32_t nwv = (lw & ~(YM & lowm)) | (lastB >> (32u - sh2));
+                    uint32_t *ep = row + wrap_add(gwq, nwg, a.W);
+                    if (corner) atomicXor(ep, nwv ^ lw);
+                    else *ep = nwv;
+                }
             }
         }
     }
@@ -844,15 +881,22 @@ __device__ __forceinline__ uint32_t dt_set(uint32_t t, uint32_t seed_lo, uint32_
 }
 
 // One launch per block set; the blocks of set c are (2 i + (c & 1), 2 j +
-// (c >> 1)), one wave each.
+// (c >> 1)), one wave each.  a.ahead: the launch also runs the set of the
+// next phase, the diagonal partner (c ^ 3) of this one, in waves nset ..
+// 2 nset - 1 (Sec. 3.2, blocks updated ahead of time): the two sets touch
+// no common slope, so this equals running them one after the other.
 template <bool ACC, bool VEC, int XN>
 __global__ __launch_bounds__(256) void kpz_dt_kernel(const SweepArgs a, uint32_t phase,
                                                      uint32_t nset)
 {
     uint32_t g = blockIdx.x;
     if ((gridDim.x & 7u) == 0) g = (g & 7u) * (gridDim.x >> 3) + (g >> 3);
-    const uint32_t w = g * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (w >= nset) return;
+    uint32_t w = g * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (w >= (a.ahead ? 2u * nset : nset)) return;
+    if (w >= nset) {   // wave-uniform
+        w -= nset;
+        ++phase;
+    }
     const uint32_t c = dt_set(a.t, a.seed_lo, a.seed_hi, phase);
     const uint32_t hx = a.nbx >> 1;
     const uint32_t bx = 2 * (w % hx) + (c & 1u), by = 2 * (w / hx) + (c >> 1);
@@ -1895,6 +1939,7 @@ struct kpz_sim {
     // launch (rot_t, rot_res) when rot_valid
     bool db;
     bool dt;                       // double tiling at the device layer
+    bool dt_ahead;                 // ... with diagonal partner sets run together
     uint32_t *buf[2];
     int cur;
     uint32_t rot_valid, rot_t, rot_res;
@@ -1960,13 +2005,54 @@ std::pair<int64_t, int64_t> default_block(int64_t L)
     return {best_x, best_y};
 }
 
+// Philox4x32 with the lattice draws' round count, on the host: the order of
+// the block sets of an MCS is needed before its launches are issued.
+void philox_host(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+    for (int r = 0; r < kpzdev::LATTICE_ROUNDS; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[1] = (uint32_t)p1;
+        c[3] = (uint32_t)p0;
+        c[0] = n0;
+        c[2] = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// The four block sets of MCS t in launch order: ordering number
+// floor(w0 24 / 2^32) of draw (DTORDER, t), the 24 orderings of 0..3 in
+// lexicographic order (the device's dt_set for every phase at once).
+void dt_order_host(uint32_t t, uint64_t seed, uint32_t perm[4])
+{
+    uint32_t c[4] = {0u, 0u, t, TAG_DTORDER << 24};
+    philox_host(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    uint32_t idx = (uint32_t)(((uint64_t)c[0] * 24u) >> 32);
+    uint32_t pool[4] = {0u, 1u, 2u, 3u};
+    uint32_t n = 4;
+    const uint32_t fact[4] = {1u, 1u, 2u, 6u};
+    for (uint32_t i = 0; i < 4; ++i) {
+        const uint32_t f = fact[n - 1];
+        const uint32_t pick = idx / f;
+        idx %= f;
+        perm[i] = pool[pick];
+        for (uint32_t k = pick; k + 1 < n; ++k) pool[k] = pool[k + 1];
+        --n;
+    }
+}
+
 // Resolves defaults and validates; fills block shape.
 kpz_status resolve(const kpz_params *p, uint32_t *Bx, uint32_t *By)
 {
     if (!p) return KPZ_EINVAL;
     if (p->L < 16 || (p->L % 16) != 0) return KPZ_EINVAL;
     if (!(p->p >= 0.0 && p->p <= 1.0 && p->q >= 0.0 && p->q <= 1.0)) return KPZ_EINVAL;
-    if ((p->flags & ~(KPZ_FLAG_IN_PLACE | KPZ_FLAG_DEVICE_DT)) != 0) return KPZ_EINVAL;
+    if ((p->flags & ~(KPZ_FLAG_IN_PLACE | KPZ_FLAG_DEVICE_DT | KPZ_FLAG_DT_AHEAD)) != 0)
+        return KPZ_EINVAL;
+    if ((p->flags & KPZ_FLAG_DT_AHEAD) && !(p->flags & KPZ_FLAG_DEVICE_DT)) return KPZ_EINVAL;
     if (p->moves != 0 && p->moves != 1 && p->moves != 2 && p->moves != 4 && p->moves != 8 &&
         p->moves != 16)
         return KPZ_EINVAL;
@@ -2098,7 +2184,8 @@ template <bool ACC, bool VEC, int XN>
 hipError_t launch_dt_v(const SweepArgs &a, uint32_t phase, uint32_t nset, hipStream_t st)
 {
     const uint32_t wpg = waves_per_group(nset);
-    hipLaunchKernelGGL((kpz_dt_kernel<ACC, VEC, XN>), dim3(nset / wpg), dim3(64 * wpg), 0, st,
+    const uint32_t waves = a.ahead ? 2u * nset : nset;
+    hipLaunchKernelGGL((kpz_dt_kernel<ACC, VEC, XN>), dim3(waves / wpg), dim3(64 * wpg), 0, st,
                        a, phase, nset);
     return hipGetLastError();
 }
@@ -2518,6 +2605,15 @@ kpz_status scratch_on_current_device(void **out)
 
 extern "C" {
 
+kpz_status kpz_dt_order(uint64_t seed, uint32_t t, int32_t *perm)
+{
+    if (!perm) return KPZ_EINVAL;
+    uint32_t o[4];
+    dt_order_host(t, seed, o);
+    for (int i = 0; i < 4; ++i) perm[i] = (int32_t)o[i];
+    return KPZ_OK;
+}
+
 const char *kpz_status_str(kpz_status s)
 {
     switch (s) {
@@ -2581,6 +2677,7 @@ kpz_status kpz_init(kpz_sim **out, const kpz_params *p, uint32_t *d_words, size_
     s->Q = threshold(p->q);
     s->db = !(p->flags & (KPZ_FLAG_IN_PLACE | KPZ_FLAG_DEVICE_DT));
     s->dt = (p->flags & KPZ_FLAG_DEVICE_DT) != 0;
+    s->dt_ahead = (p->flags & KPZ_FLAG_DT_AHEAD) != 0;
     s->buf[0] = d_words;
     s->buf[1] = s->db ? ws_alt(s) : d_words;
     s->cur = 0;
@@ -2624,6 +2721,7 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     a.src = s->words;
     a.alt = nullptr;
     a.cur0 = 0;
+    a.ahead = 0;
     a.db = 0;
     a.prev_valid = a.prev_t = a.prev_res = 0;
     a.side = ws_side(s);
@@ -2644,14 +2742,20 @@ kpz_status kpz_sweep(kpz_sim *s, int32_t n_mcs)
     if (s->dt) {
         // double tiling at the device layer: four launches per MCS, one per
         // block set in the order drawn for the MCS, in place
+        // (with dt_ahead, a set whose successor in the order is its diagonal
+        // partner shares its launch with it: two to four launches per MCS)
         const uint32_t nset = nblocks / 4;
         a.res = 0;
         for (int32_t m = 0; m < n_mcs; ++m) {
             a.t = (uint32_t)(s->t + m);
+            uint32_t perm[4];
+            dt_order_host(a.t, s->prm.seed, perm);
             for (uint32_t ph = 0; ph < 4; ++ph) {
+                a.ahead = (s->dt_ahead && ph + 1 < 4 && perm[ph + 1] == (perm[ph] ^ 3u)) ? 1u : 0u;
                 const hipError_t e = a.acc ? launch_dt<true>(a, ph, nset, s->stream)
                                            : launch_dt<false>(a, ph, nset, s->stream);
                 if (e != hipSuccess) return hip_fail(s, e, "kpz_sweep launch");
+                ph += a.ahead;
             }
         }
         s->t += n_mcs;

@@ -196,3 +196,13 @@ def test_kmc_init_checks_buffers_first(kpz):
     assert not h.value
     assert lib.kmc_sweep(None, 1) == kpz.KPZ_EINVAL
     assert lib.kmc_counts(None, None, None) == kpz.KPZ_EINVAL
+
+
+def test_dt_order_matches_oracle(oracle_lib):
+    """The library's host-side order of the four block sets (it decides which
+    launches take a set together with its diagonal partner) equals the
+    oracle's draw for every MCS tried."""
+    import paper_1204_5072_amd as kpz
+    for seed in (1, 11, 2 ** 40 + 3):
+        for t in range(300):
+            assert kpz.dt_order(seed, t) == oracle_lib.dt_perm(seed, t)

@@ -398,3 +398,62 @@ def test_l16384_moments_and_words(gpu, oracle_lib):
     st = oracle_state(oracle_lib, L, n, p, q, seed, B)
     assert np.array_equal(w, oracle_lib.pack(st.sx, st.sy))
     assert_moments(oracle_lib, st, m, L)
+
+
+def _ahead_mcs(oracle_lib, seed, n):
+    """MCS among 0..n-1 whose set order puts a set right before its diagonal
+    partner (their launches are shared under KPZ_FLAG_DT_AHEAD)."""
+    out = []
+    for t in range(n):
+        pm = oracle_lib.dt_perm(seed, t)
+        if any(b == a ^ 3 for a, b in zip(pm, pm[1:])):
+            out.append(t)
+    return out
+
+
+@pytest.mark.parametrize("L,block,p,q,seed,n", DT_CASES)
+def test_device_dt_ahead_matches_oracle(gpu, oracle_lib, L, block, p, q, seed, n):
+    """Device-layer double tiling with the next set updated ahead of time
+    where it is the diagonal partner (Sec. 3.2): the same words and moments
+    as the oracle's plain schedule after every MCS."""
+    n = max(n, 6)
+    assert _ahead_mcs(oracle_lib, seed, n), "no shared launch in this case"
+    _log(f"device DT ahead L={L} block={block} p={p} q={q} seed={seed} n={n}")
+    sim = gpu.Sim(L, p, q, seed, block, device_dt=True, dt_ahead=True)
+    st = oracle_lib.SlopeState(L)
+    for t in range(n):
+        sim.sweep(1)
+        st.run_dt(1, p, q, seed, block)
+        w = sim.words_host()
+        ref = oracle_lib.pack(st.sx, st.sy)
+        if not np.array_equal(w, ref):
+            bad = np.argwhere(w != ref)
+            pytest.fail(f"words differ after MCS {t}: {len(bad)} words, first at {bad[0]}")
+        assert_moments(oracle_lib, st, sim.roughness(), L)
+        assert sim.state() == (t + 1, int(st.net[0]))
+
+
+@pytest.mark.parametrize("block", [(256, 128), (512, 64), (64, 64)])
+def test_device_dt_ahead_word_aligned_origin(gpu, oracle_lib, block):
+    """A shared launch in an MCS whose block origin falls on a word boundary
+    (the halo column then sits in a word of its own): the first such
+    (seed, MCS) pair is searched on the host, run there and compared."""
+    L, p, q = 1024, 1.0, 0.25
+    found = None
+    for seed in range(300, 400):
+        for t in range(4):
+            ox, _ = oracle_lib.dd_origin(seed, t, block)
+            if ox % 16 == 0 and t in _ahead_mcs(oracle_lib, seed, t + 1):
+                found = (seed, t)
+                break
+        if found:
+            break
+    assert found, "no word-aligned shared launch among the seeds tried"
+    seed, t_hit = found
+    _log(f"device DT ahead aligned origin block={block} seed={seed} t={t_hit}")
+    sim = gpu.Sim(L, p, q, seed, block, device_dt=True, dt_ahead=True)
+    st = oracle_lib.SlopeState(L)
+    sim.sweep(t_hit + 1)
+    st.run_dt(t_hit + 1, p, q, seed, block)
+    assert np.array_equal(sim.words_host(), oracle_lib.pack(st.sx, st.sy))
+    assert sim.state() == (t_hit + 1, int(st.net[0]))
