@@ -206,6 +206,49 @@ def ensemble_leg(args):
     }
 
 
+def growth_leg(args):
+    """The L = 4096 growth runs: p = 1, q = 0 (KPZ) and p = q = 1/2 (EW),
+    seeds 1..8 each, flat start, 10^4 MCS with W^2 at 64 log-spaced times,
+    all 16 realisations as one ensemble graph with the default block shape.
+    Reports the rate and, per (p, q), the seed-mean W^2 at the last time and
+    the slope of log W^2 against log t over the last decade (2 beta for KPZ,
+    about 0.48 in 2+1 d; EW grows like log t, so its slope falls)."""
+    import numpy as np
+    import torch
+    import paper_1204_5072_amd as kpz
+
+    L, n_seeds = 4096, 8
+    runs = [(1.0, 0.0), (0.5, 0.5)]
+    members = [kpz.make_params(L, p, q, seed) for p, q in runs for seed in range(1, n_seeds + 1)]
+    times = log_times(64, args.growth_mcs)
+    ens = kpz.Ensemble(members)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, W2 = ens.run(times)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ens.close()
+    W2 = np.asarray(W2, dtype=np.float64)
+    t = np.asarray(times, dtype=np.float64)
+    late = t >= t[-1] / 10
+    out = {}
+    for k, (p, q) in enumerate(runs):
+        w = W2[:, k * n_seeds:(k + 1) * n_seeds].mean(axis=1)
+        slope = float(np.polyfit(np.log(t[late]), np.log(w[late]), 1)[0])
+        out[f"p={p},q={q}"] = {"w2_final_mean": float(w[-1]), "slope_log_w2_last_decade": slope}
+    attempts = float(L) * L * len(members) * times[-1]
+    return {
+        "metric": "site-update attempts/s, L=4096 growth runs (KPZ and EW, 8 seeds each)",
+        "value": attempts / elapsed,
+        "unit": "attempts/s",
+        "seconds": elapsed,
+        "members": len(members),
+        "mcs": times[-1],
+        "samples": len(times),
+        "runs": out,
+    }
+
+
 def latency_leg(args):
     """The small workload: L = 64, p = 1, q = 0, seed 1, one 64 x 64 block
     (periodic, no dead border), 1000 MCS with the exact moments after every
@@ -496,6 +539,8 @@ def main():
     ap.add_argument("--serve-sat-jobs", type=int, default=400)
     ap.add_argument("--serve-sat-rate", type=float, default=200.0)
     ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--no-growth", action="store_true")
+    ap.add_argument("--growth-mcs", type=int, default=10_000)
     ap.add_argument("--no-ring", action="store_true")
     ap.add_argument("--no-kmc", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=2000)
@@ -623,6 +668,9 @@ def main():
     if not args.no_ensemble:
         print("bench: ensemble leg", file=sys.stderr, flush=True)
         line["ensemble"] = ensemble_leg(args)
+    if not args.no_growth:
+        print("bench: growth leg", file=sys.stderr, flush=True)
+        line["growth"] = growth_leg(args)
     if not args.no_latency:
         print("bench: latency leg", file=sys.stderr, flush=True)
         line["latency"] = latency_leg(args)
