@@ -457,3 +457,36 @@ def test_device_dt_ahead_word_aligned_origin(gpu, oracle_lib, block):
     st.run_dt(t_hit + 1, p, q, seed, block)
     assert np.array_equal(sim.words_host(), oracle_lib.pack(st.sx, st.sy))
     assert sim.state() == (t_hit + 1, int(st.net[0]))
+
+
+def test_l4096_ten_thousand_mcs_against_oracle_fixture(gpu):
+    """The 2^24-site workload over its full length: L = 4096, seed 1, default
+    256 x 128 blocks, p = 1, q = 0 and p = q = 1/2, 10^4 MCS.  The expected
+    states come from tests/golden/l4096_seed1.json, written by the CPU
+    oracle's block-parallel runner (make_l4096_seed1.py): the sha256 of every
+    packed word, the exact S1 and S2, and the net flip count at t = 1000 and
+    t = 10^4."""
+    import hashlib
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "l4096_seed1.json")
+    if not os.path.exists(path):
+        pytest.skip("fixture not written (run tests/golden/make_l4096_seed1.py)")
+    with open(path) as f:
+        g = json.load(f)
+    assert [(r["p"], r["q"]) for r in g["runs"]] == [(1.0, 0.0), (0.5, 0.5)]
+    L = g["L"]
+    for run in g["runs"]:
+        assert [c["t"] for c in run["checkpoints"]] == [1000, 10_000]
+        sim = gpu.Sim(L, run["p"], run["q"], g["seed"], tuple(g["block"]))
+        t = 0
+        for rec in run["checkpoints"]:
+            _log(f"L=4096 p={run['p']} q={run['q']} to t={rec['t']}")
+            sim.sweep(rec["t"] - t)
+            t = rec["t"]
+            words = sim.words_host().astype("<u4")
+            assert hashlib.sha256(words.tobytes()).hexdigest() == rec["words_sha256"], t
+            m = sim.roughness()
+            assert (m.S1, m.S2) == (int(rec["S1"]), int(rec["S2"])), t
+            assert sim.state() == (t, rec["net"])
+        sim.close()
