@@ -73,7 +73,7 @@ typedef enum {
  *   block_x, block_y
  *            dead-border block shape of the device layer (Sec. 3), sites;
  *            both divide L.  block_x: a multiple of 16 (whole words per
- *            row), at most 128 or a multiple of 128, at most 512; block_y:
+ *            row), at most 128 or a multiple of 128, at most 1024; block_y:
  *            a multiple of 4 (whole tiles); (block_x / 128, at least 1) x
  *            block_y / 4 <= 64 (one wave per block, one lane per row group
  *            of 32 tiles and tile row).  0 = library default: for L a

@@ -1966,11 +1966,11 @@ uint64_t threshold(double prob)
 
 // A block shape the sweep takes: whole words per row (Bx a multiple of 16),
 // whole tiles (By a multiple of 4), a row of at most 32 tiles or of whole row
-// groups of 32 tiles (Bx <= 128 or a multiple of 128, at most 512), and at
+// groups of 32 tiles (Bx <= 128 or a multiple of 128, at most 1024), and at
 // most 64 (row group, tile row) pairs, one per lane of the block's wave.
 bool block_ok(int64_t bx, int64_t by)
 {
-    if (bx < 16 || bx > 512 || bx % 16 || by < TILE || by % TILE) return false;
+    if (bx < 16 || bx > 1024 || bx % 16 || by < TILE || by % TILE) return false;
     if (bx > (int64_t)GROUP_SITES && bx % GROUP_SITES) return false;
     const int64_t lanes = (bx > (int64_t)GROUP_SITES ? bx / GROUP_SITES : 1) * (by / TILE);
     return lanes <= 64;

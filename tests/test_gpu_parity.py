@@ -79,6 +79,9 @@ CASES = [
     (1024, (128, 256), 1.0, 0.0, 32, 4),      # 64 tile rows, one group per tile row
     (1024, (256, 128), 1.0, 0.0, 34, 4),      # the benchmark's shape and thresholds
     (2048, (512, 64), 1.0, 0.0, 33, 2),
+    (1024, (1024, 32), 1.0, 0.0, 35, 3),      # eight groups per tile row, one block along x
+    (4096, (1024, 32), 1.0, 0.25, 36, 2),     # eight groups, dead borders
+    (2048, (1024, 16), 0.7, 0.3, 37, 2),
     (48, (16, 16), 1.0, 0.0, 14, 6),          # non-power-of-two L (ragged word count per row)
     (96, (32, 32), 0.5, 0.5, 15, 6),
     (192, (64, 64), 1.0, 0.0, 16, 4),
@@ -192,6 +195,8 @@ DT_CASES = [
     (512, (256, 16), 0.9, 0.1, 50, 2),
     (320, (80, 40), 1.0, 0.25, 52, 3),       # block shapes that are not powers of two
     (768, (384, 64), 1.0, 0.0, 53, 2),       # three row groups per tile row
+    (4096, (1024, 32), 1.0, 0.0, 54, 2),     # eight row groups per tile row
+    (2048, (1024, 16), 0.8, 0.2, 55, 2),
 ]
 
 
