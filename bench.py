@@ -2,7 +2,7 @@
 """Throughput of the KPZ octahedron sweep on one MI355X.
 
 Workload (default): L = 65536 periodic lattice (2^32 sites, 1 GiB of packed
-slopes), p = 1, q = 0, flat start, Philox seed 1, 256 x 128 dead-border
+slopes), p = 1, q = 0, flat start, Philox seed 1, 1024 x 32 dead-border
 blocks (the fastest shape at this L) with 4 x 4 double tiles; W^2 is sampled
 every 10 MCS.  One "step" = 10 MCS followed by one exact W^2 sample (the
 full hot path: init once, then sweep + roughness).  Value = site-update
@@ -508,9 +508,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--L", type=int, default=65536)
     ap.add_argument("--block", type=int, nargs=2, default=None,
-                    help="block shape (default 256 x 128, the fastest dead-border shape at "
-                         "L = 2^16; 512 x 64 with --device-dt, whose 128-byte block rows "
-                         "halve the cache lines a set's launch shares with idle blocks)")
+                    help="block shape (default 1024 x 32, the fastest shape at L = 2^16 for "
+                         "dead borders and for --device-dt, whose 256-byte block rows leave "
+                         "fewest cache lines shared with idle blocks)")
     ap.add_argument("--mcs-per-step", type=int, default=10)
     ap.add_argument("--p", type=float, default=1.0)
     ap.add_argument("--q", type=float, default=0.0)
@@ -567,7 +567,7 @@ def main():
 
     L, M = args.L, args.mcs_per_step
     args.device_dt = args.device_dt or args.dt_ahead
-    block = tuple(args.block) if args.block else ((512, 64) if args.device_dt else (256, 128))
+    block = tuple(args.block) if args.block else (1024, 32)
     print(f"bench: L={L} block={block} p={args.p} q={args.q} seed={args.seed} "
           f"steps={args.steps} warmup={args.warmup} mcs/step={M}", file=sys.stderr, flush=True)
     sim = kpz.Sim(L, args.p, args.q, args.seed, block, moves=args.moves, in_place=args.in_place,

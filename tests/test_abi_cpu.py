@@ -49,6 +49,7 @@ def test_status_strings(kpz):
 @pytest.mark.parametrize("L,block", [(16, None), (64, None), (4096, None), (65536, None),
                                      (4096, (256, 64)), (48, (16, 16)), (768, (256, 128)),
                                      (65536, (512, 64)), (65536, (128, 256)), (64, (64, 4)),
+                                     (65536, (1024, 32)), (4096, (1024, 16)),
                                      (320, (80, 160)), (192, (96, 192)), (384, (384, 16)),
                                      (960, (96, 240)), (48, (48, 48)), (96, (16, 12))])
 def test_workspace_bytes_valid(kpz, L, block):
@@ -71,10 +72,11 @@ def test_default_block_shape(kpz, L, shape):
     dict(L=8), dict(L=24), dict(L=0), dict(L=64, p=1.5), dict(L=64, q=-0.1),
     dict(L=64, block=(48, 16)), dict(L=64, block=(8, 16)), dict(L=64, block=(128, 64)),
     dict(L=2048, block=(2048, 16)), dict(L=1024, block=(512, 256)),
-    dict(L=1024, block=(256, 256)), dict(L=4096, block=(1024, 16)), dict(L=64, block=(16, 2)),
+    dict(L=1024, block=(256, 256)), dict(L=4096, block=(2048, 8)), dict(L=64, block=(16, 2)),
+    dict(L=4096, block=(1024, 128)),
     dict(L=64, tile=(8, 8)), dict(L=96, block=(64, 32)),
     dict(L=320, block=(160, 64)), dict(L=96, block=(24, 48)), dict(L=64, block=(16, 6)),
-    dict(L=640, block=(640, 16)), dict(L=384, block=(96, 264)),
+    dict(L=1280, block=(1280, 16)), dict(L=384, block=(96, 264)),
     dict(L=64, moves=3), dict(L=64, moves=32), dict(L=64, moves=-1),
 ])
 def test_invalid_params_rejected(kpz, kw):

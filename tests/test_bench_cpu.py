@@ -34,7 +34,7 @@ def bench_copy(tmp_path, monkeypatch):
 def test_summaries_carry_a_hash_and_figures():
     text = open(os.path.join(ROOT, "profiles", "kpz_sweep_L65536_hbm_counters.md")).read()
     assert re.search(r"code_sha256 = [0-9a-f]{64}", text)
-    for key in ("256x128", "256x128,in_place", "512x64,device_dt"):
+    for key in ("1024x32", "1024x32,in_place", "1024x32,device_dt"):
         m = re.search(r"traffic_bytes_per_mcs\[%s\] = (\d+)" % re.escape(key), text)
         assert m and int(m.group(1)) > 2 * 2 ** 30   # at least the algorithmic 2 GiB
         m = re.search(r"valu_wave_instr_per_mcs\[%s\] = (\d+)" % re.escape(key), text)
@@ -43,8 +43,8 @@ def test_summaries_carry_a_hash_and_figures():
 
 def test_matching_code_gives_the_figures(bench_copy):
     bench, _ = bench_copy
-    for block, kw in (((256, 128), {}), ((256, 128), {"in_place": True}),
-                      ((512, 64), {"device_dt": True})):
+    for block, kw in (((1024, 32), {}), ((1024, 32), {"in_place": True}),
+                      ((1024, 32), {"device_dt": True})):
         traffic, valu = bench.sweep_counters(block, **kw)
         assert traffic > 2 * 2 ** 30 and valu > 0
     assert bench.ring_valu_per_mcs() > 0
@@ -53,16 +53,16 @@ def test_matching_code_gives_the_figures(bench_copy):
 
 def test_comment_edits_keep_the_figures(bench_copy):
     bench, csrc = bench_copy
-    before = bench.sweep_counters((256, 128))
+    before = bench.sweep_counters((1024, 32))
     p = csrc / "kpz.hip"
     p.write_text("// an added line comment\n/* and a block\n   comment */\n\n" + p.read_text()
                  + "\n// end\n")
-    assert bench.sweep_counters((256, 128)) == before
+    assert bench.sweep_counters((1024, 32)) == before
 
 
 def test_code_edits_void_the_figures(bench_copy):
     bench, csrc = bench_copy
     p = csrc / "kpz_device.h"
     p.write_text(p.read_text().replace("0x9E3779B9u", "0x9E3779B8u"))
-    assert bench.sweep_counters((256, 128)) == (None, None)
+    assert bench.sweep_counters((1024, 32)) == (None, None)
     assert bench.ring_valu_per_mcs() is None

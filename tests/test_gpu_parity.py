@@ -81,7 +81,9 @@ CASES = [
     (2048, (512, 64), 1.0, 0.0, 33, 2),
     (1024, (1024, 32), 1.0, 0.0, 35, 3),      # eight groups per tile row, one block along x
     (4096, (1024, 32), 1.0, 0.25, 36, 2),     # eight groups, dead borders
+    (4096, (1024, 32), 1.0, 0.0, 38, 3),      # the benchmark's shape and thresholds
     (2048, (1024, 16), 0.7, 0.3, 37, 2),
+    (1280, (640, 32), 1.0, 0.25, 39, 2),      # five groups per tile row
     (48, (16, 16), 1.0, 0.0, 14, 6),          # non-power-of-two L (ragged word count per row)
     (96, (32, 32), 0.5, 0.5, 15, 6),
     (192, (64, 64), 1.0, 0.0, 16, 4),
@@ -328,8 +330,14 @@ def _sampled_blocks(gpu, oracle_lib, L, B, p, q, seed, n_mcs):
 
 def test_l65536_sampled_blocks(gpu, oracle_lib):
     """The 2^32-site workload in the launch configuration the benchmark times
-    (256 x 128 blocks, p = 1, q = 0, two-buffer): the first 10 MCS."""
-    _sampled_blocks(gpu, oracle_lib, 65536, (256, 128), 1.0, 0.0, 1, 10)
+    (1024 x 32 blocks, p = 1, q = 0, two-buffer): the first 10 MCS."""
+    _sampled_blocks(gpu, oracle_lib, 65536, (1024, 32), 1.0, 0.0, 1, 10)
+
+
+def test_l65536_sampled_blocks_256x128(gpu, oracle_lib):
+    """The same workload with 256 x 128 blocks (the library's default shape
+    at this L): the first 3 MCS."""
+    _sampled_blocks(gpu, oracle_lib, 65536, (256, 128), 1.0, 0.0, 1, 3)
 
 
 def test_l131072_sampled_blocks(gpu, oracle_lib):
