@@ -22,7 +22,7 @@ from . import Ensemble, KPZError, Sim, make_params, workspace_bytes
 # fraction 1/Bx + 1/By at or below about 3 %.
 CANDIDATES: Tuple[Tuple[int, int], ...] = (
     (128, 256), (256, 128), (512, 64), (128, 128), (256, 64), (512, 32), (64, 256),
-    (128, 64), (64, 64),
+    (128, 64), (64, 64), (1024, 32), (1024, 16),
 )
 
 
